@@ -1,0 +1,430 @@
+"""FP64 CPU oracle for batched free-space propagation with modulation.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package.  It shares no code
+with the GPU library in ``paper_2411_18591_amd``: it has its own FFT
+(``oracle.c``), its own transfer functions, element matrices and gradients.
+
+Every function states the passage of the TorchOptics paper (Filipovich &
+Lvovsky, arXiv 2411.18591) it follows.  Where the paper leaves a convention
+open, the reading taken is stated beside the code.
+
+Conventions
+-----------
+* Fields are complex128 arrays ``[..., ny, nx]`` (x fastest).
+* Grid coordinates (section "Computational Fourier optics": a uniformly
+  sampled grid that may be offset from the z axis):
+  ``x_n = (n - nx // 2) * dx + x0`` and likewise for y.
+* Zero padding: the padded grid is ``pad * ny`` by ``pad * nx``; the field
+  sits in a centred window and the same window is cropped.
+* Gradients follow the PyTorch convention ``g = dL/dRe(u) + i dL/dIm(u)``:
+  a linear map A has vector-Jacobian product ``A^H g``.
+
+Parity status of each function is recorded in its docstring; functions
+without an independent pin say "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC_PATH = os.path.join(_HERE, "oracle.c")
+
+ASM = 0
+FRESNEL = 1
+
+
+def build(force: bool = False) -> str:
+    """Compile ``oracle.c`` with gcc into ``liboracle.so`` (host code only)."""
+    if force or not os.path.exists(_LIB_PATH) or (
+        os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC_PATH)
+    ):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC_PATH, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        c_p = ctypes.c_void_p
+        c_l = ctypes.c_long
+        c_i = ctypes.c_int
+        c_d = ctypes.c_double
+        lib.orc_dft.argtypes = [c_p, c_p, c_l, c_i]
+        lib.orc_dft.restype = None
+        lib.orc_fft.argtypes = [c_p, c_l, c_i]
+        lib.orc_fft.restype = c_i
+        lib.orc_fft2.argtypes = [c_p, c_l, c_l, c_i]
+        lib.orc_fft2.restype = c_i
+        lib.orc_transfer.argtypes = [c_p, c_l, c_l, c_d, c_d, c_d, c_d, c_i]
+        lib.orc_transfer.restype = None
+        lib.orc_propagate.argtypes = [c_p, c_p, c_l, c_l, c_l, c_i, c_d, c_d, c_d, c_d, c_i, c_i]
+        lib.orc_propagate.restype = c_i
+        lib.orc_propagate_offset.argtypes = [c_p, c_p, c_l, c_l, c_i, c_l, c_l, c_d, c_d, c_d, c_d, c_i]
+        lib.orc_propagate_offset.restype = c_i
+        lib.orc_rs_direct.argtypes = [c_p, c_p, c_l, c_l, c_d, c_d, c_d, c_d]
+        lib.orc_rs_direct.restype = None
+        _lib = lib
+    return _lib
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+# ---------------------------------------------------------------------------
+# Discrete Fourier transforms (the O(MN log MN) step of section
+# "Computational Fourier optics")
+# ---------------------------------------------------------------------------
+
+def dft(x, sign: int = -1) -> np.ndarray:
+    """Naive O(n^2) DFT ``y[k] = sum_n x[n] exp(sign 2 pi i n k / n)``.
+
+    Pinned against closed-form transforms in the tests."""
+    x = _c128(x)
+    y = np.empty_like(x)
+    _load().orc_dft(_ptr(x), _ptr(y), x.size, sign)
+    return y
+
+
+def fft(x, sign: int = -1) -> np.ndarray:
+    """Radix-2 FFT (unnormalised) of a power-of-two length vector.
+
+    Pinned against :func:`dft` and against numpy.fft."""
+    x = _c128(x).copy()
+    if _load().orc_fft(_ptr(x), x.size, sign) != 0:
+        raise ValueError("length must be a power of two")
+    return x
+
+
+def fft2(a, sign: int = -1) -> np.ndarray:
+    """2-D radix-2 FFT of a ``[ny, nx]`` array (rows then columns)."""
+    a = _c128(a).copy()
+    ny, nx = a.shape
+    if _load().orc_fft2(_ptr(a), ny, nx, sign) != 0:
+        raise ValueError("extents must be powers of two")
+    return a
+
+
+# ---------------------------------------------------------------------------
+# Grid geometry
+# ---------------------------------------------------------------------------
+
+def coords(n: int, d: float, offset: float = 0.0) -> np.ndarray:
+    """Sample positions of a length-n axis with spacing d.
+
+    The paper states only that the grid has a size, a spacing and an optional
+    offset from the z axis; this oracle places sample ``n // 2`` on the axis
+    (integer centring), plus the offset."""
+    return (np.arange(n) - n // 2) * float(d) + float(offset)
+
+
+def fftfreq(n: int, d: float) -> np.ndarray:
+    """Spatial frequency (cycles/m) of each DFT bin, FFT order."""
+    k = np.arange(n)
+    k = np.where(k < n // 2, k, k - n)
+    return k / (n * float(d))
+
+
+# ---------------------------------------------------------------------------
+# Propagation: Eq. (field_propagation_tf) with Eq. (transfer_function)
+# ---------------------------------------------------------------------------
+
+def transfer(py: int, px: int, dy: float, dx: float, wavelength: float, z: float,
+             method: int = ASM) -> np.ndarray:
+    """Transfer function on the ``py x px`` padded grid, FFT order.
+
+    AS: ``exp(2 pi i z sqrt(1/lambda^2 - fx^2 - fy^2))`` with evanescent
+    components set to zero (the paper is silent on them; the boundary where
+    the root vanishes is kept).  Fresnel: ``exp(2 pi i (z/lambda -
+    lambda z (fx^2 + fy^2) / 2))``.  Phases in long double, reduced mod 1.
+
+    Pinned by the plane-wave eigenfunction test."""
+    H = np.empty((py, px), dtype=np.complex128)
+    _load().orc_transfer(_ptr(H), py, px, dy, dx, wavelength, z, method)
+    return H
+
+
+def propagate(u, dy: float, dx: float, wavelength: float, z: float, method: int = ASM,
+              pad: int = 2, adjoint: bool = False) -> np.ndarray:
+    """Propagate a batch of fields ``[..., ny, nx]`` over distance z.
+
+    ``crop(IDFT2(H * DFT2(zero_pad(u))))``, Eq. (field_propagation_tf); with
+    ``adjoint`` the transfer function is conjugated, which gives the Hermitian
+    adjoint of the operator.
+
+    Pinned by: explicit circular convolution, plane-wave eigenfunction, z=0
+    identity, adjoint identity, Parseval, pad-placement invariance, group
+    law, Gaussian-beam closed form, lens f-f Fourier identity, Dirichlet
+    aperture pattern, Rayleigh-Sommerfeld convergence."""
+    u = _c128(u)
+    shape = u.shape
+    ny, nx = shape[-2:]
+    batch = int(np.prod(shape[:-2])) if len(shape) > 2 else 1
+    out = np.empty_like(u)
+    rc = _load().orc_propagate(_ptr(u), _ptr(out), batch, ny, nx, pad, dy, dx, wavelength, z,
+                               method, 1 if adjoint else 0)
+    if rc != 0:
+        raise ValueError("unsupported propagation size")
+    return out
+
+
+def propagate_offset(u, dy, dx, wavelength, z, method, pad, oy, ox) -> np.ndarray:
+    """Propagation with the field at window offset (oy, ox) in the padded grid."""
+    u = _c128(u)
+    ny, nx = u.shape
+    out = np.empty_like(u)
+    if _load().orc_propagate_offset(_ptr(u), _ptr(out), ny, nx, pad, oy, ox, dy, dx, wavelength,
+                                    z, method) != 0:
+        raise ValueError("bad offset")
+    return out
+
+
+def rs_direct(u, dy: float, dx: float, wavelength: float, z: float) -> np.ndarray:
+    """Brute-force Rayleigh-Sommerfeld sum, Eq. (field_propagation) with the
+    impulse response of Eq. (impulse_response); O(N^4), tiny grids only."""
+    u = _c128(u)
+    ny, nx = u.shape
+    out = np.empty_like(u)
+    _load().orc_rs_direct(_ptr(u), _ptr(out), ny, nx, dy, dx, wavelength, z)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Modulation: Eq. (field_modulation) and the Jones product of the
+# "Polarization" section
+# ---------------------------------------------------------------------------
+
+def cis_cycles(c) -> np.ndarray:
+    """``exp(2 pi i c)`` with c reduced to [0, 1) first (exact in FP64)."""
+    c = np.asarray(c, dtype=np.float64)
+    fr = c - np.floor(c)
+    return np.exp(2j * np.pi * fr)
+
+
+def phase_mask(phi) -> np.ndarray:
+    """Modulation profile of a phase modulator: ``exp(i phi)``."""
+    return np.exp(1j * np.asarray(phi, dtype=np.float64))
+
+
+def lens_phase_cycles(ny, nx, dy, dx, wavelength, f, y0=0.0, x0=0.0) -> np.ndarray:
+    """Thin-lens phase in cycles, ``-r^2 / (2 lambda f)``.
+
+    The paper says only that a lens applies a quadratic phase; the sign is
+    fixed by the ``exp(+i k z)`` convention of Eq. (transfer_function) so
+    that f > 0 converges.  No pupil."""
+    y = coords(ny, dy, y0)[:, None]
+    x = coords(nx, dx, x0)[None, :]
+    return -(x * x + y * y) / (2.0 * wavelength * f)
+
+
+def lens(ny, nx, dy, dx, wavelength, f, y0=0.0, x0=0.0) -> np.ndarray:
+    """Thin-lens modulation profile ``exp(-i pi r^2 / (lambda f))``."""
+    return cis_cycles(lens_phase_cycles(ny, nx, dy, dx, wavelength, f, y0, x0))
+
+
+def modulate(u, m, conj: bool = False) -> np.ndarray:
+    """Eq. (field_modulation): ``u_out = M u_in`` (``conj(M) u`` if conj)."""
+    m = np.asarray(m)
+    return (np.conj(m) if conj else m) * _c128(u)
+
+
+def linear_polarizer(theta: float) -> np.ndarray:
+    """Jones matrix of a linear polarizer with its axis at angle theta from
+    x: the projector onto (cos theta, sin theta).  Pinned by the printed
+    powers of the polarizer listing."""
+    c, s = np.cos(theta), np.sin(theta)
+    return np.array([[c * c, c * s], [c * s, s * s]], dtype=np.complex128)
+
+
+def waveplate(theta: float, retardance: float) -> np.ndarray:
+    """Jones matrix of a waveplate with fast axis at theta and retardance
+    Gamma: ``R(theta) diag(1, exp(i Gamma)) R(-theta)`` (no global phase).
+    The paper lists "arbitrary waveplates" without a formula; this is the
+    textbook form."""
+    c, s = np.cos(theta), np.sin(theta)
+    R = np.array([[c, -s], [s, c]], dtype=np.complex128)
+    D = np.diag([1.0, np.exp(1j * retardance)])
+    return R @ D @ R.T
+
+
+def embed_jones(J2) -> np.ndarray:
+    """Embed a 2x2 transverse Jones matrix in 3x3, leaving E_z unchanged
+    (the paper's polarized fields carry a z component, its Jones matrices
+    are 2x2)."""
+    J = np.eye(3, dtype=np.complex128)
+    J[:2, :2] = J2
+    return J
+
+
+def jones_apply(E, J, conj_transpose: bool = False) -> np.ndarray:
+    """``E_out[c] = sum_d J[c, d] E_in[d]`` per pixel; E is ``[..., 3, ny, nx]``,
+    J is ``[3, 3]`` (uniform) or ``[3, 3, ny, nx]`` (spatially varying).
+    With conj_transpose, J^H is applied (the adjoint)."""
+    E = _c128(E)
+    J = np.asarray(J, dtype=np.complex128)
+    if conj_transpose:
+        J = np.conj(np.swapaxes(J, 0, 1))
+    if J.ndim == 2:
+        return np.einsum("cd,...dyx->...cyx", J, E)
+    return np.einsum("cdyx,...dyx->...cyx", J, E)
+
+
+def power(u, dy: float, dx: float) -> float:
+    """Total power ``sum |u|^2 dx dy`` (the integral of the paper's inner
+    product and loss, sampled)."""
+    u = np.asarray(u)
+    return float(np.sum(np.abs(u) ** 2) * dx * dy)
+
+
+def inner(u, v, dy: float, dx: float) -> complex:
+    """Inner product ``sum u conj(v) dx dy``, as in Eq. (loss_func)."""
+    return complex(np.sum(np.asarray(u) * np.conj(np.asarray(v))) * dx * dy)
+
+
+# ---------------------------------------------------------------------------
+# Gradients (section "Gradient-based optimization"), written as the chain
+# rule of the operators above.  Pinned against central finite differences of
+# this module's own forward functions.
+# ---------------------------------------------------------------------------
+
+def grad_phase(g_mod, u_mod, reduce_axes=None) -> np.ndarray:
+    """dL/dphi for ``u_mod = exp(i phi) u_in``, given the gradient g_mod of
+    the loss with respect to u_mod: ``Im(g_mod conj(u_mod))``, summed over
+    every axis except the last two (fields that share the mask)."""
+    t = np.imag(np.asarray(g_mod) * np.conj(np.asarray(u_mod)))
+    if reduce_axes is None:
+        reduce_axes = tuple(range(t.ndim - 2))
+    return t.sum(axis=reduce_axes) if reduce_axes else t
+
+
+def grad_lens_f(g_mod, u_mod, ny, nx, dy, dx, wavelength, f, y0=0.0, x0=0.0) -> float:
+    """dL/df for the thin lens: its phase is ``-pi r^2 / (lambda f)`` rad, so
+    ``d phase / df = pi r^2 / (lambda f^2)`` and
+    ``dL/df = sum (pi r^2/(lambda f^2)) Im(g_mod conj(u_mod))``."""
+    y = coords(ny, dy, y0)[:, None]
+    x = coords(nx, dx, x0)[None, :]
+    dpsi = np.pi * (x * x + y * y) / (wavelength * f * f)
+    t = np.imag(np.asarray(g_mod) * np.conj(np.asarray(u_mod)))
+    return float(np.sum(t * dpsi))
+
+
+def mse_intensity(u, target):
+    """``L = mean((|u|^2 - T)^2)`` over every element of u (T broadcast over
+    the batch) and its gradient ``g = (4/n)(|u|^2 - T) u``."""
+    u = _c128(u)
+    I = np.abs(u) ** 2
+    d = I - np.asarray(target, dtype=np.float64)
+    n = u.size
+    return float(np.sum(d * d) / n), (4.0 / n) * d * u
+
+
+def weighted_intensity(u, weight, dy, dx):
+    """``L = sum W |u|^2 dx dy`` (W broadcast) and its gradient
+    ``g = 2 W dx dy u``."""
+    u = _c128(u)
+    W = np.asarray(weight, dtype=np.float64)
+    return float(np.sum(W * np.abs(u) ** 2) * dx * dy), 2.0 * W * dx * dy * u
+
+
+# ---------------------------------------------------------------------------
+# Diffractive stack (phase masks separated by free space), forward and
+# backward, as in the paper's training example generalised to L layers:
+# u_l = P_z(exp(i phi_l) u_{l-1}).
+# ---------------------------------------------------------------------------
+
+def stack_forward(u0, phis, dy, dx, wavelength, z, method=ASM, pad=2):
+    """Returns the list ``[u_0, u_1, ..., u_L]`` of layer inputs/outputs."""
+    us = [_c128(u0)]
+    for phi in phis:
+        us.append(propagate(modulate(us[-1], phase_mask(phi)), dy, dx, wavelength, z, method, pad))
+    return us
+
+
+def stack_backward(us, phis, g_out, dy, dx, wavelength, z, method=ASM, pad=2):
+    """Backward pass of :func:`stack_forward` given dL/du_L.
+
+    Per layer, in reverse: ``g_mod = P^H g``, ``dL/dphi = Im(g_mod conj(M
+    u_prev))`` summed over the batch, ``g <- conj(M) g_mod``.  Returns
+    ``(dL/du_0, [dL/dphi_1..L])``."""
+    g = _c128(g_out)
+    grads = [None] * len(phis)
+    for l in range(len(phis) - 1, -1, -1):
+        m = phase_mask(phis[l])
+        g_mod = propagate(g, dy, dx, wavelength, z, method, pad, adjoint=True)
+        grads[l] = grad_phase(g_mod, modulate(us[l], m))
+        g = modulate(g_mod, m, conj=True)
+    return g, grads
+
+
+# ---------------------------------------------------------------------------
+# Spatial coherence (section "Spatial coherence")
+# ---------------------------------------------------------------------------
+
+def coherence_modulate(gamma, m, conj: bool = False) -> np.ndarray:
+    """``Gamma_out(r1, r2) = M(r1) conj(M(r2)) Gamma_in(r1, r2)``;
+    gamma is ``[ny, nx, ny, nx]``.  With conj, M is replaced by conj(M)."""
+    m = np.asarray(m, dtype=np.complex128)
+    if conj:
+        m = np.conj(m)
+    return m[:, :, None, None] * np.conj(m)[None, None, :, :] * _c128(gamma)
+
+
+def coherence_propagate(gamma, dy, dx, wavelength, z, method=ASM, pad=2,
+                        adjoint: bool = False) -> np.ndarray:
+    """Propagate a mutual coherence function ``[ny, nx, ny, nx]``.
+
+    The 4-D integral of the coherence section applies h_z along r1 and
+    conj(h_z) along r2, i.e. with the sampled operator P:
+    ``Gamma_z = P Gamma P^H`` (P along r1 for each r2, then conj(P) along r2
+    for each r1).  The adjoint (under Re tr(A^H B)) is ``P^H Gamma P``.
+    Pinned by the rank-one and sum-of-modes reductions."""
+    g = _c128(gamma)
+    ny, nx = g.shape[:2]
+    n2 = ny * nx
+    M = g.reshape(n2, n2)
+    # P along r1: each column (fixed r2) is an ny x nx field.
+    cols = np.ascontiguousarray(M.T).reshape(n2, ny, nx)
+    A = propagate(cols, dy, dx, wavelength, z, method, pad, adjoint=adjoint)
+    M1 = A.reshape(n2, n2).T  # back to [r1][r2]
+    # conj(P) along r2: each row (fixed r1) is an ny x nx field.
+    rows = np.ascontiguousarray(M1).reshape(n2, ny, nx)
+    B = np.conj(propagate(np.conj(rows), dy, dx, wavelength, z, method, pad, adjoint=adjoint))
+    return B.reshape(ny, nx, ny, nx)
+
+
+def coherence_intensity(gamma) -> np.ndarray:
+    """Time-averaged intensity ``Gamma(r, r)`` (real part)."""
+    g = np.asarray(gamma)
+    ny, nx = g.shape[:2]
+    n2 = ny * nx
+    return np.real(np.diagonal(g.reshape(n2, n2))).reshape(ny, nx)
+
+
+def coherence_grad_phase(G_mod, gamma_mod) -> np.ndarray:
+    """dL/dphi for ``Gamma_mod = exp(i phi(r1)) exp(-i phi(r2)) Gamma``, given
+    the gradient G_mod with respect to Gamma_mod:
+    ``sum_b Im(G[r,b] conj(Gm[r,b])) - sum_a Im(G[a,r] conj(Gm[a,r]))``."""
+    G = np.asarray(G_mod)
+    Gm = np.asarray(gamma_mod)
+    ny, nx = G.shape[:2]
+    n2 = ny * nx
+    t = np.imag(G.reshape(n2, n2) * np.conj(Gm.reshape(n2, n2)))
+    return (t.sum(axis=1) - t.sum(axis=0)).reshape(ny, nx)

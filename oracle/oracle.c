@@ -1,0 +1,288 @@
+/*
+ * FP64 CPU oracle for free-space propagation of sampled optical fields.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant
+ * generator with the GPU library.
+ *
+ * What it computes (TorchOptics paper, section "Computational Fourier
+ * optics"):
+ *   - the angular-spectrum (AS) propagation of Eq. (field_propagation_tf)
+ *     with the transfer function of Eq. (transfer_function), evaluated on a
+ *     zero-padded grid with the discrete Fourier transform;
+ *   - the Fresnel transfer-function variant of the same pipeline;
+ *   - the adjoint of that linear operator;
+ *   - a brute-force Rayleigh-Sommerfeld sum of Eq. (field_propagation) with
+ *     the impulse response of Eq. (impulse_response), used as a physics
+ *     cross-check.
+ *
+ * Everything is double precision; transfer-function and twiddle phases are
+ * evaluated in long double (x86-64 80-bit) and reduced modulo one cycle
+ * before the exponential.  The FFT is a plain iterative radix-2 transform
+ * with its own twiddle table (no recurrences); a naive O(n^2) DFT is provided
+ * as an independent check of it.
+ *
+ * Complex arrays are C99 double _Complex, which has the memory layout of
+ * numpy complex128 (interleaved re, im).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double _Complex cplx;
+
+#define ORC_ASM 0
+#define ORC_FRESNEL 1
+
+static const long double TWO_PI_L = 6.283185307179586476925286766559005768L;
+
+/* exp(2*pi*i*c) for a phase c given in cycles; c is first reduced to [0,1). */
+static cplx cis_cycles(long double c)
+{
+    long double fr = c - floorl(c);
+    long double a = TWO_PI_L * fr;
+    return (double)cosl(a) + I * (double)sinl(a);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Discrete Fourier transform                                              */
+/* ---------------------------------------------------------------------- */
+
+/* Naive DFT: y[k] = sum_n x[n] exp(sign * 2 pi i n k / n_len).  The product
+ * n*k is reduced modulo n_len in integers, so the angle is exact before the
+ * long-double sine/cosine. */
+void orc_dft(const cplx *x, cplx *y, long n, int sign)
+{
+    for (long k = 0; k < n; ++k) {
+        long double sr = 0.0L, si = 0.0L;
+        for (long j = 0; j < n; ++j) {
+            long m = (long)(((unsigned long)j * (unsigned long)k) % (unsigned long)n);
+            long double a = (long double)sign * TWO_PI_L * (long double)m / (long double)n;
+            long double c = cosl(a), s = sinl(a);
+            long double xr = creal(x[j]), xi = cimag(x[j]);
+            sr += xr * c - xi * s;
+            si += xr * s + xi * c;
+        }
+        y[k] = (double)sr + I * (double)si;
+    }
+}
+
+static int is_pow2(long n) { return n > 0 && (n & (n - 1)) == 0; }
+
+/* In-place iterative radix-2 FFT (decimation in time), unnormalised:
+ * x[k] <- sum_n x[n] exp(sign * 2 pi i n k / n).  Returns -1 if n is not a
+ * power of two. */
+int orc_fft(cplx *x, long n, int sign)
+{
+    if (!is_pow2(n)) return -1;
+    if (n == 1) return 0;
+    /* bit-reversal permutation */
+    for (long i = 1, j = 0; i < n; ++i) {
+        long bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) { cplx t = x[i]; x[i] = x[j]; x[j] = t; }
+    }
+    /* twiddles w[m] = exp(sign * 2 pi i m / n), m < n/2, each from its own
+     * long-double sine/cosine */
+    cplx *w = (cplx *)malloc(sizeof(cplx) * (size_t)(n / 2));
+    for (long m = 0; m < n / 2; ++m) {
+        long double a = (long double)sign * TWO_PI_L * (long double)m / (long double)n;
+        w[m] = (double)cosl(a) + I * (double)sinl(a);
+    }
+    for (long len = 2; len <= n; len <<= 1) {
+        long half = len >> 1, step = n / len;
+        for (long s = 0; s < n; s += len) {
+            for (long k = 0; k < half; ++k) {
+                cplx t = w[k * step] * x[s + k + half];
+                cplx u = x[s + k];
+                x[s + k] = u + t;
+                x[s + k + half] = u - t;
+            }
+        }
+    }
+    free(w);
+    return 0;
+}
+
+/* 2-D FFT of a row-major ny x nx array (x fastest): rows, then columns. */
+int orc_fft2(cplx *a, long ny, long nx, int sign)
+{
+    if (!is_pow2(ny) || !is_pow2(nx)) return -1;
+    for (long r = 0; r < ny; ++r) orc_fft(a + r * nx, nx, sign);
+    cplx *col = (cplx *)malloc(sizeof(cplx) * (size_t)ny);
+    for (long c = 0; c < nx; ++c) {
+        for (long r = 0; r < ny; ++r) col[r] = a[r * nx + c];
+        orc_fft(col, ny, sign);
+        for (long r = 0; r < ny; ++r) a[r * nx + c] = col[r];
+    }
+    free(col);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Transfer functions                                                      */
+/* ---------------------------------------------------------------------- */
+
+/* Spatial frequency of DFT bin k on a length-n grid of spacing d, in cycles
+ * per metre, with numpy's fftfreq ordering (bins n/2 .. n-1 are negative). */
+static long double freq_of_bin(long k, long n, double d)
+{
+    long ks = (k < n / 2) ? k : k - n;
+    return (long double)ks / ((long double)n * (long double)d);
+}
+
+/* Phase, in cycles, of the transfer function at spatial frequency (fx, fy).
+ *
+ * AS method, Eq. (transfer_function): H = exp(i z sqrt(k^2 - kx^2 - ky^2))
+ * with k = 2 pi / lambda and kx = 2 pi fx, i.e. a phase of
+ * z * sqrt(1/lambda^2 - fx^2 - fy^2) cycles.  The paper does not say what is
+ * done where the root is imaginary; this oracle zeroes those (evanescent)
+ * components, keeping the boundary where the root is exactly zero.
+ *
+ * Fresnel transfer function (the paraxial approximation the paper offers as
+ * an alternative): phase z/lambda - (lambda z / 2)(fx^2 + fy^2) cycles.
+ *
+ * Returns 0 and sets *valid = 0 for an evanescent AS component. */
+static long double tf_phase_cycles(long double fx, long double fy, double lam, double z,
+                                   int method, int *valid)
+{
+    long double L = (long double)lam, Z = (long double)z;
+    long double rho2 = fx * fx + fy * fy;
+    *valid = 1;
+    if (method == ORC_FRESNEL)
+        return Z / L - 0.5L * L * Z * rho2;
+    long double arg = 1.0L / (L * L) - rho2;
+    if (arg < 0.0L) { *valid = 0; return 0.0L; }
+    return Z * sqrtl(arg);
+}
+
+/* Transfer function on a py x px grid of DFT bins (row-major, FFT order). */
+void orc_transfer(cplx *H, long py, long px, double dy, double dx, double lam, double z,
+                  int method)
+{
+    for (long ky = 0; ky < py; ++ky) {
+        long double fy = freq_of_bin(ky, py, dy);
+        for (long kx = 0; kx < px; ++kx) {
+            long double fx = freq_of_bin(kx, px, dx);
+            int valid;
+            long double c = tf_phase_cycles(fx, fy, lam, z, method, &valid);
+            H[ky * px + kx] = valid ? cis_cycles(c) : 0.0;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Propagation                                                             */
+/* ---------------------------------------------------------------------- */
+
+/* One propagation of an ny x nx field through distance z (section
+ * "Computational Fourier optics", Eq. (field_propagation_tf)):
+ *   1. zero-pad to py = pad*ny by px = pad*nx, the field centred in a window
+ *      starting at ((py-ny)/2, (px-nx)/2) (integer division);
+ *   2. forward 2-D DFT;
+ *   3. multiply by the transfer function H (or by conj(H) when adjoint != 0,
+ *      which is the Hermitian adjoint of the whole operator because the
+ *      crop is the adjoint of the pad and the unnormalised DFT pair is
+ *      unitary up to the 1/(py*px) factor);
+ *   4. inverse 2-D DFT scaled by 1/(py*px);
+ *   5. crop the same window.
+ * H is passed in (from orc_transfer) so a batch shares one table. */
+static void propagate_one(const cplx *in, cplx *out, cplx *work, const cplx *H, long ny,
+                          long nx, long py, long px, int adjoint)
+{
+    long oy = (py - ny) / 2, ox = (px - nx) / 2;
+    memset(work, 0, sizeof(cplx) * (size_t)(py * px));
+    for (long r = 0; r < ny; ++r)
+        memcpy(work + (r + oy) * px + ox, in + r * nx, sizeof(cplx) * (size_t)nx);
+    orc_fft2(work, py, px, -1);
+    for (long i = 0; i < py * px; ++i) work[i] *= adjoint ? conj(H[i]) : H[i];
+    orc_fft2(work, py, px, +1);
+    double scale = 1.0 / ((double)py * (double)px);
+    for (long r = 0; r < ny; ++r)
+        for (long c = 0; c < nx; ++c) out[r * nx + c] = work[(r + oy) * px + c + ox] * scale;
+}
+
+/* Batched propagation of `batch` contiguous ny x nx fields.  Returns -1 for
+ * an unsupported size (padded extents must be powers of two, pad >= 1). */
+int orc_propagate(const cplx *in, cplx *out, long batch, long ny, long nx, int pad, double dy,
+                  double dx, double lam, double z, int method, int adjoint)
+{
+    if (pad < 1 || ny < 1 || nx < 1) return -1;
+    long py = pad * ny, px = pad * nx;
+    if (!is_pow2(py) || !is_pow2(px)) return -1;
+    cplx *H = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
+    orc_transfer(H, py, px, dy, dx, lam, z, method);
+#pragma omp parallel
+    {
+        cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
+#pragma omp for schedule(dynamic, 1)
+        for (long b = 0; b < batch; ++b)
+            propagate_one(in + b * ny * nx, out + b * ny * nx, work, H, ny, nx, py, px, adjoint);
+        free(work);
+    }
+    free(H);
+    return 0;
+}
+
+/* Same operator, but with the field placed at an arbitrary window offset
+ * (oy, ox) inside the padded grid.  Used only to test that the result does
+ * not depend on where the zero padding goes. */
+int orc_propagate_offset(const cplx *in, cplx *out, long ny, long nx, int pad, long oy, long ox,
+                         double dy, double dx, double lam, double z, int method)
+{
+    long py = pad * ny, px = pad * nx;
+    if (!is_pow2(py) || !is_pow2(px) || oy < 0 || ox < 0 || oy + ny > py || ox + nx > px)
+        return -1;
+    cplx *H = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
+    cplx *work = (cplx *)calloc((size_t)(py * px), sizeof(cplx));
+    orc_transfer(H, py, px, dy, dx, lam, z, method);
+    for (long r = 0; r < ny; ++r)
+        memcpy(work + (r + oy) * px + ox, in + r * nx, sizeof(cplx) * (size_t)nx);
+    orc_fft2(work, py, px, -1);
+    for (long i = 0; i < py * px; ++i) work[i] *= H[i];
+    orc_fft2(work, py, px, +1);
+    double scale = 1.0 / ((double)py * (double)px);
+    for (long r = 0; r < ny; ++r)
+        for (long c = 0; c < nx; ++c) out[r * nx + c] = work[(r + oy) * px + c + ox] * scale;
+    free(work);
+    free(H);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Rayleigh-Sommerfeld brute force                                         */
+/* ---------------------------------------------------------------------- */
+
+/* Direct Riemann sum of Eq. (field_propagation) with the impulse response of
+ * Eq. (impulse_response):
+ *   h = z / (i lambda d) * (1 + i / (k d)) * exp(i k d) / d,
+ *   d = sqrt((x - x')^2 + (y - y')^2 + z^2),  k = 2 pi / lambda,
+ * on the same grid for input and output (spacing dy, dx), weighted by the
+ * area element dx*dy.  O(N^4): for tiny grids only. */
+void orc_rs_direct(const cplx *in, cplx *out, long ny, long nx, double dy, double dx, double lam,
+                   double z)
+{
+    long double k = TWO_PI_L / (long double)lam;
+#pragma omp parallel for collapse(2)
+    for (long r = 0; r < ny; ++r) {
+        for (long c = 0; c < nx; ++c) {
+            cplx acc = 0.0;
+            for (long rp = 0; rp < ny; ++rp) {
+                for (long cp = 0; cp < nx; ++cp) {
+                    long double ddy = (long double)(r - rp) * dy;
+                    long double ddx = (long double)(c - cp) * dx;
+                    long double d = sqrtl(ddx * ddx + ddy * ddy + (long double)z * z);
+                    /* exp(i k d) with the phase k d / (2 pi) = d / lambda cycles */
+                    cplx e = cis_cycles(d / (long double)lam);
+                    cplx pre = (double)((long double)z / ((long double)lam * d * d)) / I;
+                    cplx corr = 1.0 + I * (double)(1.0L / (k * d));
+                    acc += pre * corr * e * in[rp * nx + cp];
+                }
+            }
+            out[r * nx + c] = acc * dx * dy;
+        }
+    }
+}
