@@ -1,0 +1,196 @@
+/*
+ * toprop — batched free-space propagation of sampled optical fields on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow the TorchOptics paper (Filipovich & Lvovsky,
+ * arXiv 2411.18591):
+ *   - modulation by an element, Eq. (field_modulation): u_out = M u_in, and
+ *     its Jones-matrix form for polarized fields (section "Polarization");
+ *   - propagation by the angular-spectrum method, Eq. (field_propagation_tf)
+ *     with the transfer function of Eq. (transfer_function), on a zero-padded
+ *     grid ("configurable zero-padding"), or by the Fresnel transfer
+ *     function (the paraxial alternative the same section mentions);
+ *   - gradients of both for gradient-based optimization (section
+ *     "Gradient-based optimization");
+ *   - propagation of a mutual coherence function (section "Spatial
+ *     coherence").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is DEVICE memory owned by the caller; the
+ *   library reads or writes it only during the call's stream work and keeps
+ *   no reference afterwards.  The library owns its workspace (scratch FFT
+ *   buffers, twiddle tables, reduction partials), allocated on first use per
+ *   device and grown as needed; to_release() frees it.
+ * Layout.  Complex arrays are interleaved (re, im) — complex64 (float2) for
+ *   TO_C64, complex128 (double2) for TO_C128 — row-major [field][comp][ny][nx]
+ *   with x fastest.  Real arrays (phase masks, targets, weights, gradients)
+ *   are float for TO_C64 and double for TO_C128, [ny][nx].
+ * Grid.  Sample (y, x) sits at ((y - ny/2) dy + y0, (x - nx/2) dx + x0)
+ *   (integer division), i.e. sample ny/2 is on the optical axis when the
+ *   offset is zero.
+ * Padding.  Propagation zero-pads the ny x nx field to the py x px grid of
+ *   the job (powers of two in [8, 8192]); the field may be ragged (e.g.
+ *   1000 x 1000 padded to 2048 x 2048).  The operator is the circular
+ *   convolution on the padded grid restricted to the field window, so the
+ *   window position inside the padded grid does not change the result.
+ * Transfer function (cycles, lambda = wavelength):
+ *   TO_ASM:     H = exp(2 pi i z sqrt(1/lambda^2 - fx^2 - fy^2)),
+ *               H = 0 where fx^2 + fy^2 > 1/lambda^2 (evanescent cut-off);
+ *   TO_FRESNEL: H = exp(2 pi i (z/lambda - lambda z (fx^2 + fy^2) / 2)),
+ *   with fx = k / (px dx), fy = k / (py dy) in FFT order (bins k >= px / 2
+ *   are negative).
+ *   The phase is evaluated in FP64 and reduced modulo one cycle before the
+ *   sine and cosine; c64 fields then use FP32 arithmetic.
+ * Gradients.  For a real loss L of a complex array u, the gradient array is
+ *   dL/dRe(u) + i dL/dIm(u); for a linear operator A the backward map is
+ *   A^H.  Parameter gradients are ACCUMULATED (+=) into caller buffers in a
+ *   fixed order (bitwise deterministic).
+ * Streams.  Every call only enqueues work on `stream` (a hipStream_t, NULL =
+ *   the null stream) and returns; results are valid once the stream is
+ *   synchronized.  No host synchronization happens inside a call except on
+ *   the first use of a device (table upload) or when the workspace grows.
+ * Errors.  Every entry point returns a to_status and never aborts.  All
+ *   arguments are validated on the host before anything is enqueued;
+ *   TO_E_INVAL for null pointers or out-of-range values, TO_E_UNSUPPORTED
+ *   for sizes outside the supported set, TO_E_NOMEM if the workspace cannot
+ *   be allocated, TO_E_HIP for a failing HIP call.  to_last_error() returns a
+ *   description of the calling thread's last failure.  NaN/Inf in the data
+ *   are propagated, not checked.
+ */
+#ifndef TOPROP_H
+#define TOPROP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TO_OK = 0,
+  TO_E_INVAL = -1,
+  TO_E_UNSUPPORTED = -2,
+  TO_E_NOMEM = -3,
+  TO_E_HIP = -4
+} to_status;
+
+typedef enum { TO_ASM = 0, TO_FRESNEL = 1 } to_method;
+typedef enum { TO_C64 = 0, TO_C128 = 1 } to_dtype;
+
+/* Element applied before the propagation (fused into its first pass).  Flags
+ * combine; the composite modulation is M(r) = P(r) C(r) T(r) J where
+ *   TO_EL_PHASE   P = exp(i phi(r)), phi = el_phase [ny][nx] (radians);
+ *   TO_EL_COMPLEX C = el_complex [ny][nx] (complex of the job's dtype);
+ *   TO_EL_LENS    T = exp(-i pi r^2 / (lambda el_f)), r measured from the
+ *                 optical axis (thin lens, no pupil);
+ *   TO_EL_JONES   J = el_jones, a uniform 3x3 complex matrix mixing the
+ *                 three components (needs ncomp == 3); a 2x2 Jones matrix is
+ *                 embedded with J[2][2] = 1.                                 */
+#define TO_EL_PHASE 1u
+#define TO_EL_COMPLEX 2u
+#define TO_EL_LENS 4u
+#define TO_EL_JONES 8u
+
+/* Epilogue of a forward propagation (fused into its last pass), computed per
+ * component from the intensity I = |u|^2 of the propagated field:
+ *   TO_EPI_MSE      loss += epi_scale * sum (I - T)^2 over fields, comps and
+ *                   pixels (T = epi_ref, broadcast over fields/comps);
+ *                   epi_grad = 4 epi_scale (I - T) u  (use epi_scale = 1/n
+ *                   for a mean);
+ *   TO_EPI_WEIGHTED loss += epi_scale * sum W I  (W = epi_ref);
+ *                   epi_grad = 2 epi_scale W u.
+ * epi_loss is one device double, accumulated.                                */
+typedef enum { TO_EPI_NONE = 0, TO_EPI_MSE = 1, TO_EPI_WEIGHTED = 2 } to_epilogue;
+
+/* One propagation job: `batch` fields of `ncomp` components, all on the same
+ * grid, through the same element and the same free-space distance.          */
+typedef struct to_job {
+  int32_t ny, nx;     /* field grid (rows, columns), >= 1                      */
+  int32_t py, px;     /* padded grid: powers of two in [8, 8192], py >= ny,
+                         px >= nx (py = 2 ny, px = 2 nx is "2x padding")      */
+  int32_t method;     /* to_method                                             */
+  int32_t ncomp;      /* components per field: 1 (scalar) or 3 (polarized)    */
+  double dy, dx;      /* sample spacing [m], > 0                               */
+  double wavelength;  /* [m], > 0                                              */
+  double z;           /* propagation distance [m], any sign (0 = identity)     */
+  double y0, x0;      /* grid offset from the optical axis [m]                 */
+  int64_t batch;      /* number of fields (0 = nothing to do)                  */
+  uint32_t el_flags;  /* TO_EL_* (0 = free space only)                         */
+  int32_t epi;        /* to_epilogue                                           */
+  const void* el_phase;   /* TO_EL_PHASE: real [ny][nx]                         */
+  const void* el_complex; /* TO_EL_COMPLEX: complex [ny][nx]                    */
+  double el_f;            /* TO_EL_LENS: focal length [m], != 0                 */
+  double el_jones[18];    /* TO_EL_JONES: row-major 3x3, (re, im) pairs          */
+  const void* epi_ref;    /* TO_EPI_*: real [ny][nx] target (MSE) or weight      */
+  double epi_scale;
+  void* epi_grad;         /* TO_EPI_*: complex, same layout as `out`             */
+  double* epi_loss;       /* TO_EPI_*: one device double, accumulated            */
+  const void* in;         /* complex [batch][ncomp][ny][nx]                      */
+  void* out;              /* complex [batch][ncomp][ny][nx]; may equal `in`      */
+} to_job;
+
+/* Gradient buffers of one job for to_propagate_backward.                    */
+typedef struct to_grad {
+  const void* grad_out;  /* dL/d(out), layout of job.out                         */
+  void* grad_in;         /* dL/d(in) (overwritten), layout of job.in, or NULL    */
+  const void* saved_in;  /* the job's forward input; required when grad_phase or
+                            grad_f is requested                                  */
+  void* grad_phase;      /* TO_EL_PHASE: real [ny][nx], += dL/dphi summed over
+                            fields and components, or NULL                       */
+  double* grad_f;        /* TO_EL_LENS: one device double, += dL/df, or NULL     */
+} to_grad;
+
+/* Forward propagation of every job (Eq. (field_propagation_tf) after the
+ * element of Eq. (field_modulation)): out = P_z (M in), with the optional
+ * loss epilogue.  Jobs run in order on `stream`; a job may read the output
+ * of an earlier one.                                                         */
+to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* stream);
+
+/* Modulation only (Eq. (field_modulation) / the Jones product):
+ * out = M in, or out = M^H in when adjoint != 0.  The propagation fields of
+ * the job (py, px, method, z) are ignored.   */
+to_status to_modulate(const to_job* jobs, int32_t njobs, to_dtype dtype, int32_t adjoint,
+                      void* stream);
+
+/* Backward pass of to_propagate for each job (section "Gradient-based
+ * optimization"): with g_mod = P_z^H grad_out,
+ *   grad_in     = M^H g_mod,
+ *   grad_phase += sum Im(g_mod conj(M saved_in)),
+ *   grad_f     += sum (pi r^2 / (lambda f^2)) Im(g_mod conj(M saved_in)).
+ * P_z^H is the same pipeline with conj(H).  The per-layer input is taken
+ * from `saved_in` (recomputation: no padded spectra are stored).  The
+ * job's epilogue fields are ignored.  grads[i] belongs to jobs[i].           */
+to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_t njobs,
+                                to_dtype dtype, void* stream);
+
+/* Propagation of a mutual coherence function (section "Spatial coherence"):
+ * job->in / job->out hold Gamma [ny][nx][ny][nx] (r1 = (y1, x1) major,
+ * r2 = (y2, x2) minor), job->batch must be 1 and ncomp 1.
+ *   adjoint == 0:  Gamma_out = P (M Gamma M^H) P^H
+ *                  (M = diag of the job's scalar element; P = P_z);
+ *   adjoint != 0:  Gamma_out = M^H (P^H Gamma P) M, the adjoint of the
+ *                  forward map under Re tr(A^H B).
+ * When adjoint != 0 and grad is not NULL, grad->saved_in is the forward
+ * input Gamma_in and grad->grad_phase (+=) receives dL/dphi of the phase
+ * element, with job->in holding dL/dGamma_out:
+ *   dL/dphi(r) = sum_b Im(G[r,b] conj(Gm[r,b])) - sum_a Im(G[a,r] conj(Gm[a,r])),
+ *   G = P^H (dL/dGamma_out) P, Gm = M Gamma_in M^H.
+ * Needs workspace for one extra copy of Gamma.                              */
+to_status to_coherence_propagate(const to_job* job, to_dtype dtype, int32_t adjoint,
+                                 const to_grad* grad, void* stream);
+
+/* Description of the calling thread's last non-TO_OK status ("" if none).   */
+const char* to_last_error(void);
+
+/* Frees the library's workspace on every device (waits for the device).     */
+to_status to_release(void);
+
+/* Library version, e.g. "toprop 0.1.0 gfx950".                              */
+const char* to_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOPROP_H */

@@ -71,9 +71,9 @@ def _load():
         lib.orc_fft2.restype = c_i
         lib.orc_transfer.argtypes = [c_p, c_l, c_l, c_d, c_d, c_d, c_d, c_i]
         lib.orc_transfer.restype = None
-        lib.orc_propagate.argtypes = [c_p, c_p, c_l, c_l, c_l, c_i, c_d, c_d, c_d, c_d, c_i, c_i]
+        lib.orc_propagate.argtypes = [c_p, c_p, c_l, c_l, c_l, c_l, c_l, c_d, c_d, c_d, c_d, c_i, c_i]
         lib.orc_propagate.restype = c_i
-        lib.orc_propagate_offset.argtypes = [c_p, c_p, c_l, c_l, c_i, c_l, c_l, c_d, c_d, c_d, c_d, c_i]
+        lib.orc_propagate_offset.argtypes = [c_p, c_p, c_l, c_l, c_l, c_l, c_l, c_l, c_d, c_d, c_d, c_d, c_i]
         lib.orc_propagate_offset.restype = c_i
         lib.orc_rs_direct.argtypes = [c_p, c_p, c_l, c_l, c_d, c_d, c_d, c_d]
         lib.orc_rs_direct.restype = None
@@ -162,13 +162,21 @@ def transfer(py: int, px: int, dy: float, dx: float, wavelength: float, z: float
     return H
 
 
+def padded_shape(ny: int, nx: int, pad: int = 2, padded=None):
+    """Padded grid: ``padded`` = (py, px) if given, else (pad*ny, pad*nx)."""
+    if padded is not None:
+        return int(padded[0]), int(padded[1])
+    return pad * ny, pad * nx
+
+
 def propagate(u, dy: float, dx: float, wavelength: float, z: float, method: int = ASM,
-              pad: int = 2, adjoint: bool = False) -> np.ndarray:
+              pad: int = 2, adjoint: bool = False, padded=None) -> np.ndarray:
     """Propagate a batch of fields ``[..., ny, nx]`` over distance z.
 
-    ``crop(IDFT2(H * DFT2(zero_pad(u))))``, Eq. (field_propagation_tf); with
-    ``adjoint`` the transfer function is conjugated, which gives the Hermitian
-    adjoint of the operator.
+    ``crop(IDFT2(H * DFT2(zero_pad(u))))``, Eq. (field_propagation_tf), on a
+    padded grid of ``pad`` times the field (or the explicit ``padded`` =
+    (py, px)); with ``adjoint`` the transfer function is conjugated, which
+    gives the Hermitian adjoint of the operator.
 
     Pinned by: explicit circular convolution, plane-wave eigenfunction, z=0
     identity, adjoint identity, Parseval, pad-placement invariance, group
@@ -179,7 +187,8 @@ def propagate(u, dy: float, dx: float, wavelength: float, z: float, method: int 
     ny, nx = shape[-2:]
     batch = int(np.prod(shape[:-2])) if len(shape) > 2 else 1
     out = np.empty_like(u)
-    rc = _load().orc_propagate(_ptr(u), _ptr(out), batch, ny, nx, pad, dy, dx, wavelength, z,
+    py, px = padded_shape(ny, nx, pad, padded)
+    rc = _load().orc_propagate(_ptr(u), _ptr(out), batch, ny, nx, py, px, dy, dx, wavelength, z,
                                method, 1 if adjoint else 0)
     if rc != 0:
         raise ValueError("unsupported propagation size")
@@ -191,8 +200,8 @@ def propagate_offset(u, dy, dx, wavelength, z, method, pad, oy, ox) -> np.ndarra
     u = _c128(u)
     ny, nx = u.shape
     out = np.empty_like(u)
-    if _load().orc_propagate_offset(_ptr(u), _ptr(out), ny, nx, pad, oy, ox, dy, dx, wavelength,
-                                    z, method) != 0:
+    if _load().orc_propagate_offset(_ptr(u), _ptr(out), ny, nx, pad * ny, pad * nx, oy, ox, dy, dx,
+                                    wavelength, z, method) != 0:
         raise ValueError("bad offset")
     return out
 

@@ -180,7 +180,7 @@ void orc_transfer(cplx *H, long py, long px, double dy, double dx, double lam, d
 
 /* One propagation of an ny x nx field through distance z (section
  * "Computational Fourier optics", Eq. (field_propagation_tf)):
- *   1. zero-pad to py = pad*ny by px = pad*nx, the field centred in a window
+ *   1. zero-pad to py x px (py >= ny, px >= nx), the field centred in a window
  *      starting at ((py-ny)/2, (px-nx)/2) (integer division);
  *   2. forward 2-D DFT;
  *   3. multiply by the transfer function H (or by conj(H) when adjoint != 0,
@@ -205,13 +205,13 @@ static void propagate_one(const cplx *in, cplx *out, cplx *work, const cplx *H, 
         for (long c = 0; c < nx; ++c) out[r * nx + c] = work[(r + oy) * px + c + ox] * scale;
 }
 
-/* Batched propagation of `batch` contiguous ny x nx fields.  Returns -1 for
- * an unsupported size (padded extents must be powers of two, pad >= 1). */
-int orc_propagate(const cplx *in, cplx *out, long batch, long ny, long nx, int pad, double dy,
-                  double dx, double lam, double z, int method, int adjoint)
+/* Batched propagation of `batch` contiguous ny x nx fields on a py x px
+ * padded grid.  Returns -1 for an unsupported size (padded extents must be
+ * powers of two no smaller than the field). */
+int orc_propagate(const cplx *in, cplx *out, long batch, long ny, long nx, long py, long px,
+                  double dy, double dx, double lam, double z, int method, int adjoint)
 {
-    if (pad < 1 || ny < 1 || nx < 1) return -1;
-    long py = pad * ny, px = pad * nx;
+    if (ny < 1 || nx < 1 || py < ny || px < nx) return -1;
     if (!is_pow2(py) || !is_pow2(px)) return -1;
     cplx *H = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
     orc_transfer(H, py, px, dy, dx, lam, z, method);
@@ -230,10 +230,9 @@ int orc_propagate(const cplx *in, cplx *out, long batch, long ny, long nx, int p
 /* Same operator, but with the field placed at an arbitrary window offset
  * (oy, ox) inside the padded grid.  Used only to test that the result does
  * not depend on where the zero padding goes. */
-int orc_propagate_offset(const cplx *in, cplx *out, long ny, long nx, int pad, long oy, long ox,
-                         double dy, double dx, double lam, double z, int method)
+int orc_propagate_offset(const cplx *in, cplx *out, long ny, long nx, long py, long px, long oy,
+                         long ox, double dy, double dx, double lam, double z, int method)
 {
-    long py = pad * ny, px = pad * nx;
     if (!is_pow2(py) || !is_pow2(px) || oy < 0 || ox < 0 || oy + ny > py || ox + nx > px)
         return -1;
     cplx *H = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));

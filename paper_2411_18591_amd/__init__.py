@@ -1,0 +1,342 @@
+"""MI355X-native batched free-space propagation (angular spectrum / Fresnel
+transfer function) with fused element modulation, after the TorchOptics
+paper (Filipovich & Lvovsky, arXiv 2411.18591).
+
+This module is a thin PyTorch binding of the C-ABI in ``include/toprop.h``:
+it marshals tensor pointers, shapes and physical parameters into ``to_job``
+records and calls ``libtoprop.so`` on the current HIP stream.  Every step of
+the computation runs in the library's HIP kernels; PyTorch only provides
+device memory and streams.
+
+Fields are complex64 (FP32 arithmetic, FP64 transfer-function phases) or
+complex128 tensors of shape ``[..., ny, nx]`` (scalar) or ``[..., 3, ny, nx]``
+(polarized, ``ncomp=3``), contiguous, on a GPU.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _capi
+from ._capi import ToError  # noqa: F401
+
+__all__ = [
+    "Optics", "propagate", "modulate", "propagate_backward", "coherence_propagate",
+    "propagate_ad", "linear_polarizer", "waveplate", "jones3", "version",
+]
+
+ASM = "asm"
+FRESNEL = "fresnel"
+_METHODS = {ASM: _capi.TO_ASM, FRESNEL: _capi.TO_FRESNEL}
+
+
+def version() -> str:
+    return _capi.lib().to_version().decode()
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex64:
+        return _capi.TO_C64
+    if t.dtype == torch.complex128:
+        return _capi.TO_C128
+    raise TypeError(f"fields must be complex64 or complex128, got {t.dtype}")
+
+
+def _real_dtype(t: torch.Tensor):
+    return torch.float32 if t.dtype == torch.complex64 else torch.float64
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _need(t: torch.Tensor, name: str, dtype, like: torch.Tensor, shape=None) -> torch.Tensor:
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != like.device:
+        raise ValueError(f"{name} must be on {like.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _stream(t: torch.Tensor) -> int:
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# Jones matrices of standard elements (section "Polarization")
+# ---------------------------------------------------------------------------
+
+def linear_polarizer(theta: float):
+    """2x2 Jones matrix of a linear polarizer whose axis is at angle theta
+    from x: the projector onto (cos theta, sin theta)."""
+    c, s = math.cos(theta), math.sin(theta)
+    return [[complex(c * c), complex(c * s)], [complex(c * s), complex(s * s)]]
+
+
+def waveplate(theta: float, retardance: float):
+    """2x2 Jones matrix of a waveplate (fast axis at theta, retardance
+    Gamma): R(theta) diag(1, exp(i Gamma)) R(-theta)."""
+    c, s = math.cos(theta), math.sin(theta)
+    e = complex(math.cos(retardance), math.sin(retardance))
+    # R diag(1, e) R^T with R = [[c, -s], [s, c]]
+    return [[c * c + e * s * s, c * s - e * c * s], [s * c - e * s * c, s * s + e * c * c]]
+
+
+def jones3(*mats2x2):
+    """Product of 2x2 Jones matrices (applied left to right: the first
+    argument acts first), embedded in 3x3 with J[2][2] = 1."""
+    J = [[1 + 0j, 0j], [0j, 1 + 0j]]
+    for M in mats2x2:
+        J = [[sum(M[r][k] * J[k][c] for k in range(2)) for c in range(2)] for r in range(2)]
+    return [[J[0][0], J[0][1], 0j], [J[1][0], J[1][1], 0j], [0j, 0j, 1 + 0j]]
+
+
+# ---------------------------------------------------------------------------
+# Job marshalling
+# ---------------------------------------------------------------------------
+
+def next_pow2(n: int) -> int:
+    p = 1
+    while p < n:
+        p *= 2
+    return p
+
+
+@dataclass
+class Optics:
+    """Geometry and free-space parameters of one propagation.
+
+    The padded grid is ``padded`` = (py, px) if given, else each extent is
+    ``pad`` times the field rounded up to a power of two."""
+    dy: float
+    dx: float
+    wavelength: float
+    z: float
+    method: str = ASM
+    pad: int = 2
+    y0: float = 0.0
+    x0: float = 0.0
+    padded: Optional[tuple] = None
+
+    def padded_shape(self, ny: int, nx: int):
+        if self.padded is not None:
+            return int(self.padded[0]), int(self.padded[1])
+        return next_pow2(self.pad * ny), next_pow2(self.pad * nx)
+
+
+def _field_dims(u: torch.Tensor, ncomp: int):
+    if u.dim() < 2 + (1 if ncomp == 3 else 0):
+        raise ValueError("field tensor has too few dimensions")
+    ny, nx = u.shape[-2], u.shape[-1]
+    lead = u.shape[:-3] if ncomp == 3 else u.shape[:-2]
+    if ncomp == 3 and u.shape[-3] != 3:
+        raise ValueError("polarized fields need a component axis of size 3")
+    batch = 1
+    for d in lead:
+        batch *= int(d)
+    return int(ny), int(nx), batch
+
+
+def make_job(u: torch.Tensor, opt: Optics, *, out: Optional[torch.Tensor] = None, ncomp: int = 1,
+             phase=None, cmask=None, lens_f=None, jones=None, epi: int = _capi.TO_EPI_NONE,
+             epi_ref=None, epi_scale: float = 1.0, epi_grad=None, epi_loss=None):
+    """Fill a to_job record for field tensor u (and the given element /
+    epilogue tensors).  Returns the record; the caller keeps the tensors
+    alive until the stream work is done."""
+    if not u.is_contiguous():
+        raise ValueError("field must be contiguous")
+    _dtype_code(u)
+    rdt = _real_dtype(u)
+    ny, nx, batch = _field_dims(u, ncomp)
+    j = _capi.Job()
+    j.ny, j.nx = ny, nx
+    j.py, j.px = opt.padded_shape(ny, nx)
+    if opt.method not in _METHODS:
+        raise ValueError(f"method must be one of {list(_METHODS)}")
+    j.method = _METHODS[opt.method]
+    j.dy, j.dx, j.wavelength, j.z = float(opt.dy), float(opt.dx), float(opt.wavelength), float(opt.z)
+    j.y0, j.x0 = float(opt.y0), float(opt.x0)
+    j.batch = batch
+    j.ncomp = ncomp
+    flags = 0
+    if phase is not None:
+        _need(phase, "phase", rdt, u, (ny, nx))
+        j.el_phase = _ptr(phase)
+        flags |= _capi.TO_EL_PHASE
+    if cmask is not None:
+        _need(cmask, "cmask", u.dtype, u, (ny, nx))
+        j.el_complex = _ptr(cmask)
+        flags |= _capi.TO_EL_COMPLEX
+    if lens_f is not None:
+        j.el_f = float(lens_f)
+        flags |= _capi.TO_EL_LENS
+    if jones is not None:
+        flat = []
+        for r in range(3):
+            for c in range(3):
+                v = complex(jones[r][c])
+                flat += [v.real, v.imag]
+        j.el_jones[:] = flat
+        flags |= _capi.TO_EL_JONES
+    j.el_flags = flags
+    j.epi = int(epi)
+    if epi != _capi.TO_EPI_NONE:
+        _need(epi_ref, "epi_ref", rdt, u, (ny, nx))
+        _need(epi_grad, "epi_grad", u.dtype, u, tuple(u.shape))
+        _need(epi_loss, "epi_loss", torch.float64, u)
+        j.epi_ref, j.epi_grad, j.epi_loss = _ptr(epi_ref), _ptr(epi_grad), _ptr(epi_loss)
+        j.epi_scale = float(epi_scale)
+    j.in_ = _ptr(u)
+    if out is not None:
+        _need(out, "out", u.dtype, u, tuple(u.shape))
+        j.out = _ptr(out)
+    return j
+
+
+# ---------------------------------------------------------------------------
+# Entry points
+# ---------------------------------------------------------------------------
+
+def propagate(u: torch.Tensor, opt: Optics, *, out: Optional[torch.Tensor] = None, ncomp: int = 1,
+              **element) -> torch.Tensor:
+    """out = P_z(M u): modulation by the element (phase=, cmask=, lens_f=,
+    jones=) fused into the first pass, then zero-padded propagation."""
+    if out is None:
+        out = torch.empty_like(u)
+    job = make_job(u, opt, out=out, ncomp=ncomp, **element)
+    _capi.propagate([job], _dtype_code(u), _stream(u))
+    return out
+
+
+def propagate_loss(u: torch.Tensor, opt: Optics, *, kind: str, ref: torch.Tensor, scale: float,
+                   out: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None,
+                   loss: Optional[torch.Tensor] = None, ncomp: int = 1, **element):
+    """Forward propagation with a fused intensity-loss epilogue ("mse" or
+    "weighted").  Returns (out, dL/d(out), loss) where loss is a float64
+    device scalar (accumulated into `loss` if given)."""
+    epi = {"mse": _capi.TO_EPI_MSE, "weighted": _capi.TO_EPI_WEIGHTED}[kind]
+    out = torch.empty_like(u) if out is None else out
+    grad = torch.empty_like(u) if grad is None else grad
+    loss = torch.zeros((), dtype=torch.float64, device=u.device) if loss is None else loss
+    job = make_job(u, opt, out=out, ncomp=ncomp, epi=epi, epi_ref=ref, epi_scale=scale,
+                   epi_grad=grad, epi_loss=loss, **element)
+    _capi.propagate([job], _dtype_code(u), _stream(u))
+    return out, grad, loss
+
+
+def modulate(u: torch.Tensor, *, dy: float, dx: float, wavelength: float, y0: float = 0.0,
+             x0: float = 0.0, adjoint: bool = False, out: Optional[torch.Tensor] = None,
+             ncomp: int = 1, **element) -> torch.Tensor:
+    """out = M u (or M^H u), Eq. (field_modulation) / the Jones product."""
+    if out is None:
+        out = torch.empty_like(u)
+    opt = Optics(dy=dy, dx=dx, wavelength=wavelength, z=0.0, pad=1, y0=y0, x0=x0, padded=(8, 8))
+    job = make_job(u, opt, out=out, ncomp=ncomp, **element)
+    _capi.modulate([job], _dtype_code(u), adjoint, _stream(u))
+    return out
+
+
+def propagate_backward(grad_out: torch.Tensor, opt: Optics, *, saved_in=None, want_grad_in=True,
+                       grad_in=None, grad_phase=None, grad_f=None, ncomp: int = 1, **element):
+    """Backward of :func:`propagate`: returns dL/d(in) (or None); element
+    gradients are accumulated into grad_phase / grad_f (device tensors)."""
+    job = make_job(grad_out, opt, ncomp=ncomp, **element)
+    job.in_ = None
+    g = _capi.Grad()
+    g.grad_out = _ptr(grad_out)
+    if want_grad_in:
+        grad_in = torch.empty_like(grad_out) if grad_in is None else grad_in
+        g.grad_in = _ptr(grad_in)
+    else:
+        grad_in = None
+    if saved_in is not None:
+        _need(saved_in, "saved_in", grad_out.dtype, grad_out, tuple(grad_out.shape))
+        g.saved_in = _ptr(saved_in)
+    if grad_phase is not None:
+        g.grad_phase = _ptr(_need(grad_phase, "grad_phase", _real_dtype(grad_out), grad_out,
+                                  grad_out.shape[-2:]))
+    if grad_f is not None:
+        g.grad_f = _ptr(_need(grad_f, "grad_f", torch.float64, grad_out))
+    _capi.propagate_backward([job], [g], _dtype_code(grad_out), _stream(grad_out))
+    return grad_in
+
+
+def coherence_propagate(gamma: torch.Tensor, opt: Optics, *, adjoint: bool = False,
+                        out: Optional[torch.Tensor] = None, saved_in=None, grad_phase=None,
+                        **element) -> torch.Tensor:
+    """Propagate a mutual coherence function [ny, nx, ny, nx] (section
+    "Spatial coherence"): P (M G M^H) P^H, or its adjoint."""
+    ny, nx = int(gamma.shape[0]), int(gamma.shape[1])
+    if gamma.dim() != 4 or tuple(gamma.shape) != (ny, nx, ny, nx):
+        raise ValueError("gamma must be [ny, nx, ny, nx]")
+    if out is None:
+        out = torch.empty_like(gamma)
+    job = make_job(gamma[0, 0], opt, ncomp=1, **element)  # grid and element only
+    job.batch = 1
+    job.in_ = _ptr(gamma)
+    job.out = _ptr(out)
+    g = None
+    if adjoint and (saved_in is not None or grad_phase is not None):
+        g = _capi.Grad()
+        g.saved_in = _ptr(saved_in)
+        g.grad_phase = _ptr(grad_phase)
+    _capi.coherence_propagate(job, _dtype_code(gamma), adjoint, g, _stream(gamma))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Autograd
+# ---------------------------------------------------------------------------
+
+class _Propagate(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u, phase, lens_f, opt, ncomp, jones, cmask):
+        ctx.opt, ctx.ncomp, ctx.jones, ctx.lens_f_value = opt, ncomp, jones, None
+        el = {}
+        if phase is not None:
+            el["phase"] = phase.detach().contiguous()
+        if lens_f is not None:
+            ctx.lens_f_value = float(lens_f)
+            el["lens_f"] = ctx.lens_f_value
+        if jones is not None:
+            el["jones"] = jones
+        if cmask is not None:
+            el["cmask"] = cmask.detach().contiguous()
+        ctx.el = el
+        u = u.detach().contiguous()
+        out = propagate(u, opt, ncomp=ncomp, **el)
+        ctx.save_for_backward(u)
+        ctx.has_phase = phase is not None
+        ctx.has_lens = lens_f is not None
+        ctx.lens_requires = lens_f is not None and isinstance(lens_f, torch.Tensor) and lens_f.requires_grad
+        ctx.phase_requires = phase is not None and phase.requires_grad
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        (u,) = ctx.saved_tensors
+        g = g.contiguous()
+        gp = torch.zeros_like(ctx.el["phase"]) if ctx.phase_requires else None
+        gf = torch.zeros((), dtype=torch.float64, device=g.device) if ctx.lens_requires else None
+        need_param = gp is not None or gf is not None
+        gin = propagate_backward(g, ctx.opt, saved_in=u if need_param else None,
+                                 want_grad_in=ctx.needs_input_grad[0], grad_phase=gp, grad_f=gf,
+                                 ncomp=ctx.ncomp, **ctx.el)
+        gf_out = None
+        if gf is not None:
+            gf_out = gf.to(torch.float64)
+        return gin, gp, gf_out, None, None, None, None
+
+
+def propagate_ad(u: torch.Tensor, opt: Optics, *, phase=None, lens_f=None, jones=None, cmask=None,
+                 ncomp: int = 1) -> torch.Tensor:
+    """Differentiable P_z(M u) with respect to u, the phase mask and the lens
+    focal length (pass lens_f as a 0-d float64 tensor with requires_grad)."""
+    return _Propagate.apply(u, phase, lens_f, opt, ncomp, jones, cmask)

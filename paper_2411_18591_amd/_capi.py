@@ -1,0 +1,157 @@
+"""ctypes view of the C-ABI declared in include/toprop.h.
+
+Argument marshalling only: every computation happens in libtoprop.so.  The
+library is loaded from this package directory; if it is missing the loader
+raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtoprop.so")
+
+TO_OK = 0
+TO_E_INVAL = -1
+TO_E_UNSUPPORTED = -2
+TO_E_NOMEM = -3
+TO_E_HIP = -4
+
+TO_ASM = 0
+TO_FRESNEL = 1
+TO_C64 = 0
+TO_C128 = 1
+
+TO_EL_PHASE = 1
+TO_EL_COMPLEX = 2
+TO_EL_LENS = 4
+TO_EL_JONES = 8
+
+TO_EPI_NONE = 0
+TO_EPI_MSE = 1
+TO_EPI_WEIGHTED = 2
+
+EXPORTED = (
+    "to_propagate",
+    "to_modulate",
+    "to_propagate_backward",
+    "to_coherence_propagate",
+    "to_last_error",
+    "to_release",
+    "to_version",
+)
+
+
+class Job(ctypes.Structure):
+    _fields_ = [
+        ("ny", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("py", ctypes.c_int32),
+        ("px", ctypes.c_int32),
+        ("method", ctypes.c_int32),
+        ("ncomp", ctypes.c_int32),
+        ("dy", ctypes.c_double),
+        ("dx", ctypes.c_double),
+        ("wavelength", ctypes.c_double),
+        ("z", ctypes.c_double),
+        ("y0", ctypes.c_double),
+        ("x0", ctypes.c_double),
+        ("batch", ctypes.c_int64),
+        ("el_flags", ctypes.c_uint32),
+        ("epi", ctypes.c_int32),
+        ("el_phase", ctypes.c_void_p),
+        ("el_complex", ctypes.c_void_p),
+        ("el_f", ctypes.c_double),
+        ("el_jones", ctypes.c_double * 18),
+        ("epi_ref", ctypes.c_void_p),
+        ("epi_scale", ctypes.c_double),
+        ("epi_grad", ctypes.c_void_p),
+        ("epi_loss", ctypes.c_void_p),
+        ("in_", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+    ]
+
+
+class Grad(ctypes.Structure):
+    _fields_ = [
+        ("grad_out", ctypes.c_void_p),
+        ("grad_in", ctypes.c_void_p),
+        ("saved_in", ctypes.c_void_p),
+        ("grad_phase", ctypes.c_void_p),
+        ("grad_f", ctypes.c_void_p),
+    ]
+
+
+class ToError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"toprop error {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libtoprop.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2411_18591_amd.build` "
+                "(hipcc, gfx950). There is no fallback implementation.")
+        L = ctypes.CDLL(LIB_PATH)
+        c_int = ctypes.c_int32
+        JP = ctypes.POINTER(Job)
+        GP = ctypes.POINTER(Grad)
+        L.to_propagate.argtypes = [JP, c_int, c_int, ctypes.c_void_p]
+        L.to_propagate.restype = c_int
+        L.to_modulate.argtypes = [JP, c_int, c_int, c_int, ctypes.c_void_p]
+        L.to_modulate.restype = c_int
+        L.to_propagate_backward.argtypes = [JP, GP, c_int, c_int, ctypes.c_void_p]
+        L.to_propagate_backward.restype = c_int
+        L.to_coherence_propagate.argtypes = [JP, c_int, c_int, GP, ctypes.c_void_p]
+        L.to_coherence_propagate.restype = c_int
+        L.to_last_error.argtypes = []
+        L.to_last_error.restype = ctypes.c_char_p
+        L.to_release.argtypes = []
+        L.to_release.restype = c_int
+        L.to_version.argtypes = []
+        L.to_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != TO_OK:
+        raise ToError(status, lib().to_last_error().decode())
+
+
+def jobs_array(jobs):
+    arr = (Job * len(jobs))(*jobs)
+    return arr
+
+
+def grads_array(grads):
+    return (Grad * len(grads))(*grads)
+
+
+def propagate(jobs, dtype: int, stream: int) -> None:
+    arr = jobs_array(jobs)
+    check(lib().to_propagate(arr, len(jobs), dtype, ctypes.c_void_p(stream)))
+
+
+def modulate(jobs, dtype: int, adjoint: bool, stream: int) -> None:
+    arr = jobs_array(jobs)
+    check(lib().to_modulate(arr, len(jobs), dtype, 1 if adjoint else 0, ctypes.c_void_p(stream)))
+
+
+def propagate_backward(jobs, grads, dtype: int, stream: int) -> None:
+    check(lib().to_propagate_backward(jobs_array(jobs), grads_array(grads), len(jobs), dtype,
+                                      ctypes.c_void_p(stream)))
+
+
+def coherence_propagate(job, dtype: int, adjoint: bool, grad, stream: int) -> None:
+    jp = ctypes.byref(job)
+    gp = ctypes.byref(grad) if grad is not None else None
+    check(lib().to_coherence_propagate(jp, dtype, 1 if adjoint else 0, gp, ctypes.c_void_p(stream)))

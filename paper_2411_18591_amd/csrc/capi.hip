@@ -1,0 +1,559 @@
+// C-ABI of the propagation library: argument validation, workspace and
+// table management, and the launch sequence of each entry point.  The
+// operations are documented in include/toprop.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/toprop.h"
+#include "launch.hpp"
+
+using namespace toprop;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+to_status fail(to_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+to_status hip_fail(hipError_t e, const char* what) {
+  return fail(TO_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+int ilog2i(int64_t n) {
+  int k = 0;
+  while ((int64_t(1) << k) < n) ++k;
+  return k;
+}
+
+// Twiddle table of length L: exp(-2 pi i m / L), m < L, each entry from its
+// own long-double sine and cosine (no recurrences).  All lengths 8..8192 are
+// packed in one buffer; length L starts at element L - 8 (sum of the
+// smaller power-of-two lengths from 8).
+constexpr int kTwTotal = 2 * kMaxLen - kMinLen;
+inline int tw_offset(int L) { return L - kMinLen; }
+
+template <typename T>
+std::vector<cx<T>> build_twiddles() {
+  std::vector<cx<T>> h(kTwTotal);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int L = kMinLen; L <= kMaxLen; L *= 2) {
+    for (int m = 0; m < L; ++m) {
+      long double a = -two_pi * (long double)m / (long double)L;
+      h[tw_offset(L) + m] = {(T)cosl(a), (T)sinl(a)};
+    }
+  }
+  return h;
+}
+
+struct DeviceCtx {
+  bool init = false;
+  cx<float>* tw32 = nullptr;
+  cx<double>* tw64 = nullptr;
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  double* partial = nullptr;
+  size_t partial_count = 0;
+};
+
+std::mutex g_mutex;
+std::vector<DeviceCtx> g_ctx;
+
+to_status get_ctx(DeviceCtx** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mutex);
+  if ((int)g_ctx.size() <= dev) g_ctx.resize(dev + 1);
+  DeviceCtx& c = g_ctx[dev];
+  if (!c.init) {
+    auto h32 = build_twiddles<float>();
+    auto h64 = build_twiddles<double>();
+    if ((e = hipMalloc(&c.tw32, sizeof(cx<float>) * kTwTotal)) != hipSuccess)
+      return fail(TO_E_NOMEM, "twiddle table allocation failed: %s", hipGetErrorString(e));
+    if ((e = hipMalloc(&c.tw64, sizeof(cx<double>) * kTwTotal)) != hipSuccess)
+      return fail(TO_E_NOMEM, "twiddle table allocation failed: %s", hipGetErrorString(e));
+    if ((e = hipMemcpy(c.tw32, h32.data(), sizeof(cx<float>) * kTwTotal, hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return hip_fail(e, "twiddle upload");
+    if ((e = hipMemcpy(c.tw64, h64.data(), sizeof(cx<double>) * kTwTotal, hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return hip_fail(e, "twiddle upload");
+    c.init = true;
+  }
+  *out = &c;
+  return TO_OK;
+}
+
+// Grow the scratch buffer to at least `bytes` (synchronizes the device when
+// it has to reallocate, since queued work may still use the old buffer).
+to_status ensure_scratch(DeviceCtx* c, size_t bytes) {
+  if (c->scratch_bytes >= bytes) return TO_OK;
+  hipError_t e;
+  if (c->scratch) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    hipFree(c->scratch);
+    c->scratch = nullptr;
+    c->scratch_bytes = 0;
+  }
+  if ((e = hipMalloc(&c->scratch, bytes)) != hipSuccess)
+    return fail(TO_E_NOMEM, "scratch allocation of %zu bytes failed: %s", bytes,
+                hipGetErrorString(e));
+  c->scratch_bytes = bytes;
+  return TO_OK;
+}
+
+to_status ensure_partial(DeviceCtx* c, size_t count) {
+  if (c->partial_count >= count) return TO_OK;
+  hipError_t e;
+  if (c->partial) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    hipFree(c->partial);
+    c->partial = nullptr;
+    c->partial_count = 0;
+  }
+  if ((e = hipMalloc(&c->partial, count * sizeof(double))) != hipSuccess)
+    return fail(TO_E_NOMEM, "partial-sum allocation failed: %s", hipGetErrorString(e));
+  c->partial_count = count;
+  return TO_OK;
+}
+
+size_t chunk_budget_bytes() {
+  static size_t budget = [] {
+    const char* s = getenv("TOPROP_CHUNK_MB");
+    long mb = s ? atol(s) : 128;
+    if (mb < 1) mb = 1;
+    return (size_t)mb << 20;
+  }();
+  return budget;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Host-side validation of one job.  `what` selects which pointers matter.
+enum Mode { MODE_FWD, MODE_BWD, MODE_MOD, MODE_COH };
+
+to_status validate(const to_job& j, int idx, to_dtype dt, Mode mode) {
+  if (dt != TO_C64 && dt != TO_C128) return fail(TO_E_INVAL, "dtype %d is not TO_C64/TO_C128", (int)dt);
+  if (j.ny < 1 || j.nx < 1) return fail(TO_E_INVAL, "job %d: grid %dx%d must be >= 1", idx, j.ny, j.nx);
+  if (mode != MODE_MOD) {
+    const int64_t ly = j.py, lx = j.px;
+    if (ly < j.ny || lx < j.nx)
+      return fail(TO_E_INVAL, "job %d: padded grid %lldx%lld smaller than the field %dx%d", idx,
+                  (long long)ly, (long long)lx, j.ny, j.nx);
+    if (!is_pow2(ly) || !is_pow2(lx) || ly < kMinLen || lx < kMinLen || ly > kMaxLen ||
+        lx > kMaxLen)
+      return fail(TO_E_UNSUPPORTED,
+                  "job %d: padded grid %lldx%lld must be powers of two in [%d, %d]", idx,
+                  (long long)ly, (long long)lx, kMinLen, kMaxLen);
+    if (j.method != TO_ASM && j.method != TO_FRESNEL)
+      return fail(TO_E_INVAL, "job %d: unknown method %d", idx, j.method);
+    if (!std::isfinite(j.z)) return fail(TO_E_INVAL, "job %d: z is not finite", idx);
+  }
+  if (!finite_pos(j.dy) || !finite_pos(j.dx))
+    return fail(TO_E_INVAL, "job %d: spacing must be finite and > 0", idx);
+  if (!finite_pos(j.wavelength)) return fail(TO_E_INVAL, "job %d: wavelength must be finite and > 0", idx);
+  if (!std::isfinite(j.y0) || !std::isfinite(j.x0)) return fail(TO_E_INVAL, "job %d: offset not finite", idx);
+  if (j.batch < 0) return fail(TO_E_INVAL, "job %d: batch %lld < 0", idx, (long long)j.batch);
+  if (j.ncomp != 1 && j.ncomp != 3) return fail(TO_E_INVAL, "job %d: ncomp must be 1 or 3", idx);
+  const uint32_t known = TO_EL_PHASE | TO_EL_COMPLEX | TO_EL_LENS | TO_EL_JONES;
+  if (j.el_flags & ~known) return fail(TO_E_INVAL, "job %d: unknown element flags 0x%x", idx, j.el_flags);
+  if ((j.el_flags & TO_EL_JONES) && j.ncomp != 3)
+    return fail(TO_E_INVAL, "job %d: a Jones element needs ncomp == 3", idx);
+  if ((j.el_flags & TO_EL_PHASE) && !j.el_phase) return fail(TO_E_INVAL, "job %d: el_phase is NULL", idx);
+  if ((j.el_flags & TO_EL_COMPLEX) && !j.el_complex)
+    return fail(TO_E_INVAL, "job %d: el_complex is NULL", idx);
+  if ((j.el_flags & TO_EL_LENS) && (!std::isfinite(j.el_f) || j.el_f == 0.0))
+    return fail(TO_E_INVAL, "job %d: lens focal length must be finite and non-zero", idx);
+  if (j.el_flags & TO_EL_JONES)
+    for (int k = 0; k < 18; ++k)
+      if (!std::isfinite(j.el_jones[k])) return fail(TO_E_INVAL, "job %d: Jones matrix not finite", idx);
+  if (j.batch > 0 && mode != MODE_BWD && (!j.in || !j.out))
+    return fail(TO_E_INVAL, "job %d: in/out is NULL", idx);
+  if (mode == MODE_FWD && j.batch > 0) {
+    if (j.epi != TO_EPI_NONE && j.epi != TO_EPI_MSE && j.epi != TO_EPI_WEIGHTED)
+      return fail(TO_E_INVAL, "job %d: unknown epilogue %d", idx, j.epi);
+    if (j.epi != TO_EPI_NONE && (!j.epi_ref || !j.epi_grad || !j.epi_loss))
+      return fail(TO_E_INVAL, "job %d: epilogue needs epi_ref, epi_grad and epi_loss", idx);
+    if (j.epi != TO_EPI_NONE && !std::isfinite(j.epi_scale))
+      return fail(TO_E_INVAL, "job %d: epi_scale not finite", idx);
+  }
+  const int64_t npix = (int64_t)j.ny * j.nx;
+  if (j.batch > 0 && npix * j.ncomp > (int64_t(1) << 40) / j.batch)
+    return fail(TO_E_UNSUPPORTED, "job %d: batch too large", idx);
+  return TO_OK;
+}
+
+TransferParams make_transfer(const to_job& j, bool conj) {
+  TransferParams p;
+  p.method = j.method;
+  p.conj = conj ? 1 : 0;
+  const double lam = j.wavelength, z = j.z;
+  p.lam2 = lam * lam;
+  p.q = z / lam;
+  // frac(z / lambda) without losing the fractional digits of a large ratio:
+  // q_hat = fl(z/lambda), remainder r = z - q_hat lambda is exact with fma.
+  const double qh = z / lam;
+  const double r = std::fma(-qh, lam, z);
+  p.q_frac = (qh - std::floor(qh)) + r / lam;
+  p.fres_a = 0.5 * lam * z;
+  p.inv_lxdx = 1.0 / ((double)j.px * j.dx);
+  p.inv_lydy = 1.0 / ((double)j.py * j.dy);
+  return p;
+}
+
+template <typename T>
+ElementParams<T> make_element(const to_job& j, uint32_t flags) {
+  ElementParams<T> e;
+  memset(&e, 0, sizeof(e));
+  e.flags = flags;
+  e.phase = (const T*)j.el_phase;
+  e.cmask = (const cx<T>*)j.el_complex;
+  e.lens_a = (flags & TO_EL_LENS) ? 1.0 / (2.0 * j.wavelength * j.el_f) : 0.0;
+  e.dy = j.dy;
+  e.dx = j.dx;
+  e.y0 = j.y0;
+  e.x0 = j.x0;
+  for (int k = 0; k < 9; ++k) e.jones[k] = {(T)j.el_jones[2 * k], (T)j.el_jones[2 * k + 1]};
+  return e;
+}
+
+template <typename T>
+const cx<T>* twiddles(DeviceCtx* c, int L);
+template <>
+const cx<float>* twiddles<float>(DeviceCtx* c, int L) { return c->tw32 + tw_offset(L); }
+template <>
+const cx<double>* twiddles<double>(DeviceCtx* c, int L) { return c->tw64 + tw_offset(L); }
+
+// Geometry shared by the forward and backward launch sequences.
+struct Geometry {
+  int lx, ly, tc, tc_shift;
+  bool half_x, half_y;
+  int nc_kernel;          // 3 when a Jones element couples the components
+  int64_t nfields;        // independent field groups seen by the row kernels
+  int64_t in_stride;      // elements between field groups
+  int64_t comp_stride;    // elements between components
+  int64_t s_stride;       // scratch elements per (field group, component)
+  int64_t chunk;          // field groups per chunk
+};
+
+template <typename T>
+to_status make_geometry(const to_job& j, bool jones, Geometry* g) {
+  g->lx = j.px;
+  g->ly = j.py;
+  g->tc = col_tile_width(g->ly, sizeof(T) == 8);
+  if (g->tc > g->lx) g->tc = g->lx;
+  if (g->tc <= 0 || g->lx % g->tc != 0)
+    return fail(TO_E_UNSUPPORTED, "no column configuration for %dx%d", g->ly, g->lx);
+  g->tc_shift = ilog2i(g->tc);
+  // Pruned first/last passes when the field fills at most half of the
+  // padded extent along that axis.
+  g->half_x = 2 * j.nx <= g->lx;
+  g->half_y = 2 * j.ny <= g->ly;
+  g->nc_kernel = jones ? 3 : 1;
+  const int64_t npix = (int64_t)j.ny * j.nx;
+  g->nfields = jones ? j.batch : j.batch * j.ncomp;
+  g->in_stride = jones ? 3 * npix : npix;
+  g->comp_stride = npix;
+  g->s_stride = (int64_t)g->lx * j.ny;
+  const size_t per = (size_t)g->s_stride * g->nc_kernel * sizeof(cx<T>);
+  int64_t ch = (int64_t)(chunk_budget_bytes() / per);
+  if (ch < 1) ch = 1;
+  if (ch > g->nfields) ch = g->nfields;
+  if (ch > 65535) ch = 65535;
+  g->chunk = ch;
+  return TO_OK;
+}
+
+template <typename T>
+to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s) {
+  if (j.batch == 0) return TO_OK;
+  Geometry g;
+  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
+  to_status st = make_geometry<T>(j, jones, &g);
+  if (st != TO_OK) return st;
+  st = ensure_scratch(c, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
+  if (st != TO_OK) return st;
+  if (j.epi != TO_EPI_NONE) {
+    st = ensure_partial(c, (size_t)g.chunk * j.ny);
+    if (st != TO_OK) return st;
+  }
+  cx<T>* scratch = (cx<T>*)c->scratch;
+  const TransferParams h = make_transfer(j, false);
+  const ElementParams<T> el = make_element<T>(j, j.el_flags);
+  hipError_t e;
+  for (int64_t f0 = 0; f0 < g.nfields; f0 += g.chunk) {
+    const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
+    RowFwdArgs<T> ra;
+    ra.in = (const cx<T>*)j.in + f0 * g.in_stride;
+    ra.scratch = scratch;
+    ra.in_stride = g.in_stride;
+    ra.comp_stride = g.comp_stride;
+    ra.s_stride = g.s_stride;
+    ra.ny = j.ny;
+    ra.nx = j.nx;
+    ra.tc_shift = g.tc_shift;
+    ra.nfields = nf;
+    ra.el = el;
+    ra.tw = twiddles<T>(c, g.lx);
+    if ((e = Launch<T>::row_fwd(g.lx, g.half_x, g.nc_kernel, j.ny, nf, ra, s)) != hipSuccess)
+      return hip_fail(e, "row_fwd launch");
+    ColArgs<T> ca;
+    ca.scratch = scratch;
+    ca.s_stride = g.s_stride;
+    ca.ny = j.ny;
+    ca.lx = g.lx;
+    ca.tcl = g.tc;
+    ca.nfields = nf * g.nc_kernel;
+    ca.h = h;
+    ca.tw = twiddles<T>(c, g.ly);
+    if ((e = Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, ca, s)) != hipSuccess)
+      return hip_fail(e, "col launch");
+    RowInvArgs<T> ia;
+    memset(&ia, 0, sizeof(ia));
+    ia.scratch = scratch;
+    ia.s_stride = g.s_stride;
+    ia.comp_stride = g.comp_stride;
+    ia.out = (cx<T>*)j.out + f0 * g.in_stride;
+    ia.out_stride = g.in_stride;
+    ia.ny = j.ny;
+    ia.nx = j.nx;
+    ia.tc_shift = g.tc_shift;
+    ia.nfields = nf;
+    ia.scale = (T)(1.0 / ((double)g.lx * (double)g.ly));
+    ia.tw = twiddles<T>(c, g.lx);
+    ia.epi = j.epi;
+    ia.epi_ref = (const T*)j.epi_ref;
+    ia.epi_scale = (T)j.epi_scale;
+    ia.epi_grad = j.epi_grad ? (cx<T>*)j.epi_grad + f0 * g.in_stride : nullptr;
+    ia.row_partial = c->partial;
+    ia.backward = 0;
+    ia.el = make_element<T>(j, 0);
+    if ((e = Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, nf, ia, s)) != hipSuccess)
+      return hip_fail(e, "row_inv launch");
+    if (j.epi != TO_EPI_NONE) {
+      if ((e = launch_reduce_add(c->partial, (int64_t)nf * j.ny, j.epi_scale, j.epi_loss, s)) !=
+          hipSuccess)
+        return hip_fail(e, "loss reduction launch");
+    }
+  }
+  return TO_OK;
+}
+
+template <typename T>
+to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStream_t s) {
+  if (j.batch == 0) return TO_OK;
+  Geometry g;
+  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
+  to_status st = make_geometry<T>(j, jones, &g);
+  if (st != TO_OK) return st;
+  st = ensure_scratch(c, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
+  if (st != TO_OK) return st;
+  const bool want_f = (j.el_flags & TO_EL_LENS) && gr.grad_f;
+  if (want_f) {
+    st = ensure_partial(c, (size_t)j.ny);
+    if (st != TO_OK) return st;
+  }
+  cx<T>* scratch = (cx<T>*)c->scratch;
+  const TransferParams h = make_transfer(j, true);
+  const ElementParams<T> el = make_element<T>(j, j.el_flags);
+  hipError_t e;
+  // The gradient rows carry no element: the first two passes treat every
+  // component as an independent field.
+  const int64_t flat_per_group = g.nc_kernel;
+  for (int64_t f0 = 0; f0 < g.nfields; f0 += g.chunk) {
+    const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
+    RowFwdArgs<T> ra;
+    memset(&ra, 0, sizeof(ra));
+    ra.in = (const cx<T>*)gr.grad_out + f0 * g.in_stride;
+    ra.scratch = scratch;
+    ra.in_stride = g.comp_stride;
+    ra.comp_stride = g.comp_stride;
+    ra.s_stride = g.s_stride;
+    ra.ny = j.ny;
+    ra.nx = j.nx;
+    ra.tc_shift = g.tc_shift;
+    ra.nfields = nf * (int)flat_per_group;
+    ra.el = make_element<T>(j, 0);
+    ra.tw = twiddles<T>(c, g.lx);
+    if ((e = Launch<T>::row_fwd(g.lx, g.half_x, 1, j.ny, nf * (int)flat_per_group, ra, s)) !=
+        hipSuccess)
+      return hip_fail(e, "row_fwd launch");
+    ColArgs<T> ca;
+    ca.scratch = scratch;
+    ca.s_stride = g.s_stride;
+    ca.ny = j.ny;
+    ca.lx = g.lx;
+    ca.tcl = g.tc;
+    ca.nfields = nf * g.nc_kernel;
+    ca.h = h;
+    ca.tw = twiddles<T>(c, g.ly);
+    if ((e = Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, ca, s)) != hipSuccess)
+      return hip_fail(e, "col launch");
+    RowInvArgs<T> ia;
+    memset(&ia, 0, sizeof(ia));
+    ia.scratch = scratch;
+    ia.s_stride = g.s_stride;
+    ia.comp_stride = g.comp_stride;
+    ia.out = gr.grad_in ? (cx<T>*)gr.grad_in + f0 * g.in_stride : nullptr;
+    ia.out_stride = g.in_stride;
+    ia.ny = j.ny;
+    ia.nx = j.nx;
+    ia.tc_shift = g.tc_shift;
+    ia.nfields = nf;
+    ia.scale = (T)(1.0 / ((double)g.lx * (double)g.ly));
+    ia.tw = twiddles<T>(c, g.lx);
+    ia.epi = TO_EPI_NONE;
+    ia.backward = 1;
+    ia.el = el;
+    ia.saved_in = gr.saved_in ? (const cx<T>*)gr.saved_in + f0 * g.in_stride : nullptr;
+    ia.grad_phase = (T*)gr.grad_phase;
+    ia.lens_f = j.el_f;
+    ia.lens_partial = want_f ? c->partial : nullptr;
+    if ((e = Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, 1, ia, s)) != hipSuccess)
+      return hip_fail(e, "row_inv launch");
+    if (want_f) {
+      if ((e = launch_reduce_add(c->partial, j.ny, 1.0, gr.grad_f, s)) != hipSuccess)
+        return hip_fail(e, "lens gradient reduction launch");
+    }
+  }
+  return TO_OK;
+}
+
+template <typename T>
+to_status run_modulate(const to_job& j, int adjoint, hipStream_t s) {
+  if (j.batch == 0) return TO_OK;
+  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
+  const int64_t npix = (int64_t)j.ny * j.nx;
+  const int nc = jones ? 3 : 1;
+  const int64_t nfields = jones ? j.batch : j.batch * j.ncomp;
+  if (nfields > INT32_MAX) return fail(TO_E_UNSUPPORTED, "too many fields");
+  const ElementParams<T> el = make_element<T>(j, j.el_flags);
+  hipError_t e = Launch<T>::modulate(nc, (const cx<T>*)j.in, (cx<T>*)j.out, nc * npix, npix, j.ny,
+                                     j.nx, (int)nfields, adjoint, el, s);
+  if (e != hipSuccess) return hip_fail(e, "modulate launch");
+  return TO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* stream) {
+  if (njobs < 0) return fail(TO_E_INVAL, "njobs < 0");
+  if (njobs > 0 && !jobs) return fail(TO_E_INVAL, "jobs is NULL");
+  for (int i = 0; i < njobs; ++i) {
+    to_status st = validate(jobs[i], i, dtype, MODE_FWD);
+    if (st != TO_OK) return st;
+  }
+  if (njobs == 0) return TO_OK;
+  DeviceCtx* c;
+  to_status st = get_ctx(&c);
+  if (st != TO_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < njobs; ++i) {
+    st = dtype == TO_C64 ? run_forward<float>(jobs[i], c, s) : run_forward<double>(jobs[i], c, s);
+    if (st != TO_OK) return st;
+  }
+  return TO_OK;
+}
+
+to_status to_modulate(const to_job* jobs, int32_t njobs, to_dtype dtype, int32_t adjoint,
+                      void* stream) {
+  if (njobs < 0) return fail(TO_E_INVAL, "njobs < 0");
+  if (njobs > 0 && !jobs) return fail(TO_E_INVAL, "jobs is NULL");
+  for (int i = 0; i < njobs; ++i) {
+    to_status st = validate(jobs[i], i, dtype, MODE_MOD);
+    if (st != TO_OK) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < njobs; ++i) {
+    to_status st = dtype == TO_C64 ? run_modulate<float>(jobs[i], adjoint, s)
+                                   : run_modulate<double>(jobs[i], adjoint, s);
+    if (st != TO_OK) return st;
+  }
+  return TO_OK;
+}
+
+to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_t njobs,
+                                to_dtype dtype, void* stream) {
+  if (njobs < 0) return fail(TO_E_INVAL, "njobs < 0");
+  if (njobs > 0 && (!jobs || !grads)) return fail(TO_E_INVAL, "jobs or grads is NULL");
+  for (int i = 0; i < njobs; ++i) {
+    to_status st = validate(jobs[i], i, dtype, MODE_BWD);
+    if (st != TO_OK) return st;
+    const to_grad& g = grads[i];
+    if (jobs[i].batch > 0) {
+      if (!g.grad_out) return fail(TO_E_INVAL, "job %d: grad_out is NULL", i);
+      const bool want_param = (g.grad_phase && (jobs[i].el_flags & TO_EL_PHASE)) ||
+                              (g.grad_f && (jobs[i].el_flags & TO_EL_LENS));
+      if (want_param && !g.saved_in)
+        return fail(TO_E_INVAL, "job %d: a parameter gradient needs saved_in", i);
+    }
+  }
+  if (njobs == 0) return TO_OK;
+  DeviceCtx* c;
+  to_status st = get_ctx(&c);
+  if (st != TO_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < njobs; ++i) {
+    st = dtype == TO_C64 ? run_backward<float>(jobs[i], grads[i], c, s)
+                         : run_backward<double>(jobs[i], grads[i], c, s);
+    if (st != TO_OK) return st;
+  }
+  return TO_OK;
+}
+
+to_status to_coherence_propagate(const to_job* job, to_dtype dtype, int32_t adjoint,
+                                 const to_grad* grad, void* stream) {
+  (void)adjoint;
+  (void)grad;
+  (void)stream;
+  if (!job) return fail(TO_E_INVAL, "job is NULL");
+  to_status st = validate(*job, 0, dtype, MODE_COH);
+  if (st != TO_OK) return st;
+  if (job->batch != 1 || job->ncomp != 1)
+    return fail(TO_E_INVAL, "coherence job needs batch == 1 and ncomp == 1");
+  return fail(TO_E_UNSUPPORTED, "coherence propagation is not available in this build");
+}
+
+const char* to_last_error(void) { return g_last_error.c_str(); }
+
+to_status to_release(void) {
+  std::lock_guard<std::mutex> lk(g_mutex);
+  int cur = 0;
+  hipGetDevice(&cur);
+  for (size_t d = 0; d < g_ctx.size(); ++d) {
+    DeviceCtx& c = g_ctx[d];
+    if (!c.init && !c.scratch && !c.partial) continue;
+    hipSetDevice((int)d);
+    hipDeviceSynchronize();
+    if (c.tw32) hipFree(c.tw32);
+    if (c.tw64) hipFree(c.tw64);
+    if (c.scratch) hipFree(c.scratch);
+    if (c.partial) hipFree(c.partial);
+    c = DeviceCtx();
+  }
+  hipSetDevice(cur);
+  return TO_OK;
+}
+
+const char* to_version(void) { return "toprop 0.1.0 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+"""CPU-side checks of the C-ABI: the library loads, exports every function
+the public header declares, its struct layout matches the ctypes binding,
+and argument validation rejects bad jobs before any device work (these calls
+never reach the GPU, so they run without one)."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "toprop.h")
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2411_18591_amd import _capi
+    return _capi
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:to_status|const char\*)\s+(to_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_function(capi):
+    lib = capi.lib()
+    names = declared_functions()
+    assert set(names) >= {"to_propagate", "to_modulate", "to_propagate_backward",
+                          "to_coherence_propagate", "to_last_error"}
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(capi.EXPORTED)
+    assert lib.to_version().decode().startswith("toprop")
+
+
+def test_struct_layout_matches_header(capi):
+    fields = [f for f, _ in capi.Job._fields_]
+    gfields = [f for f, _ in capi.Grad._fields_]
+    src = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){"]
+    src.append('printf("%zu %zu\\n", sizeof(to_job), sizeof(to_grad));')
+    for f in fields:
+        cf = "in" if f == "in_" else f
+        src.append(f'printf("%zu\\n", offsetof(to_job, {cf}));')
+    for f in gfields:
+        src.append(f'printf("%zu\\n", offsetof(to_grad, {f}));')
+    src.append("return 0;}")
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write("\n".join(src))
+        subprocess.check_call(["gcc", "-std=c11", "-o", exe, c])
+        out = subprocess.check_output([exe]).decode().split()
+    sizes = [int(x) for x in out]
+    assert sizes[0] == ctypes.sizeof(capi.Job)
+    assert sizes[1] == ctypes.sizeof(capi.Grad)
+    for f, off in zip(fields, sizes[2:2 + len(fields)]):
+        assert getattr(capi.Job, f).offset == off, f
+    for f, off in zip(gfields, sizes[2 + len(fields):]):
+        assert getattr(capi.Grad, f).offset == off, f
+
+
+def good_job(capi):
+    j = capi.Job()
+    j.ny, j.nx, j.py, j.px = 16, 16, 32, 32
+    j.method = capi.TO_ASM
+    j.ncomp = 1
+    j.dy = j.dx = 1e-5
+    j.wavelength = 7e-7
+    j.z = 0.1
+    j.batch = 1
+    j.in_ = 0x1000  # never dereferenced: validation fails first in every case below
+    j.out = 0x2000
+    return j
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda j: setattr(j, "ny", 0), "TO_E_INVAL"),
+    (lambda j: setattr(j, "py", 8), "TO_E_INVAL"),          # smaller than the field
+    (lambda j: setattr(j, "px", 48), "TO_E_UNSUPPORTED"),   # not a power of two
+    (lambda j: setattr(j, "px", 16384), "TO_E_UNSUPPORTED"),
+    (lambda j: setattr(j, "dx", 0.0), "TO_E_INVAL"),
+    (lambda j: setattr(j, "dy", float("nan")), "TO_E_INVAL"),
+    (lambda j: setattr(j, "wavelength", -1.0), "TO_E_INVAL"),
+    (lambda j: setattr(j, "z", float("inf")), "TO_E_INVAL"),
+    (lambda j: setattr(j, "method", 7), "TO_E_INVAL"),
+    (lambda j: setattr(j, "batch", -1), "TO_E_INVAL"),
+    (lambda j: setattr(j, "ncomp", 2), "TO_E_INVAL"),
+    (lambda j: setattr(j, "el_flags", 8), "TO_E_INVAL"),    # Jones with ncomp 1
+    (lambda j: setattr(j, "el_flags", 1), "TO_E_INVAL"),    # phase mask pointer NULL
+    (lambda j: setattr(j, "el_flags", 64), "TO_E_INVAL"),
+    (lambda j: (setattr(j, "el_flags", 4), setattr(j, "el_f", 0.0)), "TO_E_INVAL"),
+    (lambda j: setattr(j, "out", None), "TO_E_INVAL"),
+    (lambda j: setattr(j, "epi", 1), "TO_E_INVAL"),         # epilogue buffers NULL
+    (lambda j: setattr(j, "epi", 9), "TO_E_INVAL"),
+])
+def test_validation_rejects_bad_jobs(capi, mutate, status):
+    j = good_job(capi)
+    mutate(j)
+    arr = capi.jobs_array([j])
+    rc = capi.lib().to_propagate(arr, 1, capi.TO_C64, None)
+    assert rc == getattr(capi, status)
+    assert len(capi.lib().to_last_error()) > 0
+
+
+def test_validation_other_entry_points(capi):
+    lib = capi.lib()
+    assert lib.to_propagate(None, 1, capi.TO_C64, None) == capi.TO_E_INVAL
+    assert lib.to_propagate(None, -1, capi.TO_C64, None) == capi.TO_E_INVAL
+    assert lib.to_propagate(None, 0, capi.TO_C64, None) == capi.TO_OK
+    j = good_job(capi)
+    assert lib.to_propagate(capi.jobs_array([j]), 1, 5, None) == capi.TO_E_INVAL  # dtype
+    g = capi.Grad()
+    assert lib.to_propagate_backward(capi.jobs_array([j]), capi.grads_array([g]), 1,
+                                     capi.TO_C64, None) == capi.TO_E_INVAL  # grad_out NULL
+    g.grad_out = 0x3000
+    g.grad_phase = 0x4000
+    j.el_flags = capi.TO_EL_PHASE
+    j.el_phase = 0x5000
+    assert lib.to_propagate_backward(capi.jobs_array([j]), capi.grads_array([g]), 1,
+                                     capi.TO_C64, None) == capi.TO_E_INVAL  # saved_in NULL
+    assert lib.to_coherence_propagate(None, capi.TO_C64, 0, None, None) == capi.TO_E_INVAL
+    j2 = good_job(capi)
+    j2.batch = 2
+    assert lib.to_coherence_propagate(ctypes.byref(j2), capi.TO_C64, 0, None, None) == capi.TO_E_INVAL
+
+
+def test_missing_library_fails_loudly(capi, monkeypatch, tmp_path):
+    monkeypatch.setattr(capi, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(capi, "_lib", None)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        capi.lib()
