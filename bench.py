@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark: forward + backward ASM propagations per second through a
+diffractive network on one MI355X.
+
+Workload (one "step"): 64 complex64 fields of 1024 x 1024 (amplitude =
+seeded blurred noise, zero phase) pass through 5 trainable phase masks, each
+followed by angular-spectrum propagation over 10 cm (spacing 8 um, 700 nm,
+2x zero padding to 2048 x 2048); an MSE loss on the output intensity against
+a seeded target is fused into the last propagation; the backward pass runs
+the adjoint propagations and accumulates the 5 mask gradients.  That is
+64 x 5 forward + 64 x 5 adjoint = 640 propagations per step, every one of
+them in the library's HIP kernels (the Python side only enqueues calls).
+
+Prints one JSON line (see the keys below).  --gpus must be 1: this build
+runs on a single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+VALU_FP32_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, non-packed FP32
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--batch", type=int, default=64)
+    p.add_argument("--n", type=int, default=1024)
+    p.add_argument("--layers", type=int, default=5)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-fields", type=int, default=0,
+                   help="fields in the CPU oracle sample (0 = min(8, host cores))")
+    p.add_argument("--cpu-sample-layers", type=int, default=2,
+                   help="layers (of the workload's masks) in the CPU oracle sample")
+    p.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    return p.parse_args()
+
+
+def fft_flops(L: int) -> float:
+    """Conventional flop count of one complex FFT of length L."""
+    return 5.0 * L * math.log2(L)
+
+
+def kernel_model(name: str, wl, chunk_fields: int):
+    """Algorithmic bytes and flops of ONE launch of a propagation kernel for
+    this workload (c64, N x N field, P x P padded, `chunk_fields` fields per
+    launch).  Bytes are what the kernel must read and write in the 3-pass
+    decomposition (field in/out, the N x P intermediate in/out, masks and
+    gradients); flops count 5 L log2 L per length-L FFT plus 6 per complex
+    multiply."""
+    N, P = wl["n"], wl["padded"]
+    c = 8  # bytes per complex64
+    f = chunk_fields
+    if ".row_fwd_" in name:
+        by = f * (N * N * c + N * P * c) + (N * N * 4 if name.startswith("fwd") else 0)
+        fl = f * (N * fft_flops(P) + (6 * N * N if name.startswith("fwd") else 0))
+    elif ".col_" in name:
+        by = f * 2 * N * P * c
+        fl = f * P * (2 * fft_flops(P) + 6 * P)
+    elif ".row_inv_" in name:
+        if name.startswith("fwd"):
+            by = f * (N * P * c + N * N * c)
+        else:  # reads g rows + saved input, writes grad_in, mask in / grad out
+            by = f * (N * P * c + 2 * N * N * c) + 2 * N * N * 4
+        fl = f * N * fft_flops(P)
+    else:
+        return None
+    return by, fl
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        return 2
+    import numpy as np
+    import torch
+
+    import paper_2411_18591_amd as tp
+    from paper_2411_18591_amd import _capi
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl_def = workloads.DiffractiveNetWorkload(batch=args.batch, n=args.n, layers=args.layers)
+    B, N, L = wl_def.batch, wl_def.n, wl_def.layers
+    P = 2 * N
+    print(f"[bench] generating inputs: {B} x {N}^2 fields, {L} masks", file=sys.stderr, flush=True)
+    t0 = time.time()
+    u0_np = wl_def.fields()
+    masks_np = wl_def.masks()
+    target_np = wl_def.target()
+    print(f"[bench] inputs ready in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    u = [torch.from_numpy(u0_np).to(dev)] + [torch.empty((B, N, N), dtype=torch.complex64, device=dev)
+                                             for _ in range(L)]
+    masks = torch.from_numpy(masks_np).to(dev)
+    target = torch.from_numpy(target_np).to(dev)
+    gmask = torch.zeros_like(masks)
+    gbuf = [torch.empty((B, N, N), dtype=torch.complex64, device=dev) for _ in range(2)]
+    loss = torch.zeros((), dtype=torch.float64, device=dev)
+    opt = tp.Optics(dy=wl_def.d, dx=wl_def.d, wavelength=wl_def.wavelength, z=wl_def.z, pad=2)
+    n_total = B * N * N
+
+    def step():
+        gmask.zero_()
+        loss.zero_()
+        for l in range(L - 1):
+            tp.propagate(u[l], opt, out=u[l + 1], phase=masks[l])
+        tp.propagate_loss(u[L - 1], opt, kind="mse", ref=target, scale=1.0 / n_total,
+                          out=u[L], grad=gbuf[0], loss=loss, phase=masks[L - 1])
+        g_cur = 0
+        for l in range(L - 1, -1, -1):
+            nxt = 1 - g_cur
+            tp.propagate_backward(gbuf[g_cur], opt, saved_in=u[l], grad_phase=gmask[l],
+                                  phase=masks[l], want_grad_in=l > 0, grad_in=gbuf[nxt])
+            g_cur = nxt
+
+    print("[bench] warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] timed region", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if not args.no_profile:
+        _capi.profile_begin()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    t_wall = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    prof = _capi.profile_end() if not args.no_profile else {}
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    props = 2 * B * L
+    value = props / (ms_step / 1000.0)
+    print(f"[bench] {ms_step:.3f} ms/step, loss {float(loss.item()):.6e}", file=sys.stderr, flush=True)
+
+    # Algorithmic HBM bytes of one step (fields in/out of every propagation,
+    # the loss gradient, masks and mask gradients; no padded intermediates).
+    c = 8
+    fwd_bytes = L * B * N * N * 2 * c + B * N * N * c + N * N * 4 + L * N * N * 4
+    bwd_bytes = (L - 1) * B * N * N * 3 * c + B * N * N * 2 * c + L * N * N * 4 * 3
+    step_bytes = fwd_bytes + bwd_bytes
+    hbm_frac_step = step_bytes / (ms_step / 1000.0) / (HBM_PEAK_GBS * 1e9)
+
+    # Dominant kernel: largest total GPU time in the timed region.
+    wl = {"n": N, "padded": P}
+    chunk = max(1, min(B, (128 << 20) // (N * P * c)))
+    kern = []
+    for name, (cnt, ms) in prof.items():
+        m = kernel_model(name, wl, chunk)
+        kern.append((ms, name, cnt, m))
+    kern.sort(reverse=True)
+    roofline = None
+    kernels_out = {}
+    for ms, name, cnt, m in kern:
+        avg_us = 1000.0 * ms / cnt
+        entry = {"launches": cnt, "avg_us": round(avg_us, 2), "share": round(ms / sum(k[0] for k in kern), 4)}
+        if m:
+            by, fl = m
+            entry["GB_s"] = round(by / (avg_us * 1e-6) / 1e9, 1)
+            entry["TFLOP_s"] = round(fl / (avg_us * 1e-6) / 1e12, 2)
+        kernels_out[name] = entry
+    if kern and kern[0][3]:
+        ms, name, cnt, (by, fl) = kern[0]
+        avg_s = ms / cnt / 1000.0
+        gbs = by / avg_s / 1e9
+        tfs = fl / avg_s / 1e12
+        f_h = gbs / HBM_PEAK_GBS
+        f_a = tfs / VALU_FP32_PEAK_TFLOPS
+        if f_a >= f_h:
+            roofline = {"bound": "alu", "achieved": round(tfs, 3), "peak": VALU_FP32_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(f_a, 4), "traffic": None,
+                        "kernel": name, "avg_us": round(avg_s * 1e6, 2),
+                        "hbm_view": {"achieved_GB_s": round(gbs, 1), "frac": round(f_h, 4)}}
+        else:
+            roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(f_h, 4), "traffic": None,
+                        "kernel": name, "avg_us": round(avg_s * 1e6, 2),
+                        "alu_view": {"achieved_TFLOP_s": round(tfs, 3), "frac": round(f_a, 4)}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args, wl_def, u0_np, masks_np, target_np)
+
+    out = {
+        "metric": "fwd+bwd ASM propagations/s at 1024^2 c64; % of HBM roofline vs plain form",
+        "value": round(value, 1),
+        "unit": "propagations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic (seeded blurred-noise fields, uniform random phase masks, blurred target)",
+        "config": {
+            "workload": f"diffractive network: {B} x {N}^2 complex64 fields, {L} phase masks, "
+                        f"ASM z=10 cm, 8 um, 700 nm, padded to {P}^2, MSE loss, fwd+bwd to masks",
+            "global_batch": B, "grid": N, "padded": P, "layers": L,
+            "propagations_per_step": props,
+        },
+        "hbm_roofline_step": {"algorithmic_bytes": step_bytes, "frac": round(hbm_frac_step, 4)},
+        "roofline": roofline,
+        "kernels": kernels_out,
+        "wall_s": round(t_wall, 3),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def cpu_baseline(args, wl_def, u0_np, masks_np, target_np):
+    """The FP64 oracle timed on the host on a bounded sample of the same
+    workload: `k` fields through the same 5 layers, forward and backward."""
+    import numpy as np
+
+    import oracle
+    cores = os.cpu_count() or 1
+    k = args.cpu_sample_fields or min(8, cores)
+    k = min(k, wl_def.batch)
+    print(f"[bench] cpu baseline: oracle on {k} fields", file=sys.stderr, flush=True)
+    oracle.build()
+    u0 = u0_np[:k].astype(np.complex128)
+    nl = max(1, min(args.cpu_sample_layers, wl_def.layers))
+    phis = [m.astype(np.float64) for m in masks_np[:nl]]
+    T = target_np.astype(np.float64)
+    d, lam, z = wl_def.d, wl_def.wavelength, wl_def.z
+    t0 = time.perf_counter()
+    us = oracle.stack_forward(u0, phis, d, d, lam, z, oracle.ASM, 2)
+    _, g = oracle.mse_intensity(us[-1], T)
+    oracle.stack_backward(us, phis, g, d, d, lam, z, oracle.ASM, 2)
+    dt = time.perf_counter() - t0
+    props = 2 * k * nl
+    return {"value": round(props / dt, 3), "unit": "propagations/s", "cores": min(k, cores),
+            "kind": "oracle",
+            "sample": f"{k} of {wl_def.batch} fields through the first {nl} of {wl_def.layers} "
+                      f"layers, fwd+bwd with MSE loss ({props} FP64 propagations at the same "
+                      f"1024^2 -> 2048^2 shape, {dt:.1f} s; OpenMP over fields)"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

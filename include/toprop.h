@@ -189,6 +189,21 @@ to_status to_release(void);
 /* Library version, e.g. "toprop 0.1.0 gfx950".                              */
 const char* to_version(void);
 
+/* Kernel timing, for measurement only (not part of the computation).
+ * to_profile_begin() clears previous results and, until to_profile_end(),
+ * brackets every kernel the library launches with a pair of HIP events
+ * recorded on the launch's own stream.  to_profile_end() waits for those
+ * events and aggregates the elapsed GPU time per kernel name
+ * ("<phase>.<kernel>_<dtype>_L<transform length>").  to_profile_count() and
+ * to_profile_entry() read the aggregate: `name` receives at most name_len
+ * bytes including the terminator.  Not thread-safe with concurrent calls
+ * on other threads while enabled.                                            */
+to_status to_profile_begin(void);
+to_status to_profile_end(void);
+int32_t to_profile_count(void);
+to_status to_profile_entry(int32_t i, char* name, int32_t name_len, int64_t* launches,
+                           double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

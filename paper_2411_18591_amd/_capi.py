@@ -40,6 +40,10 @@ EXPORTED = (
     "to_last_error",
     "to_release",
     "to_version",
+    "to_profile_begin",
+    "to_profile_end",
+    "to_profile_count",
+    "to_profile_entry",
 )
 
 
@@ -118,6 +122,15 @@ def lib() -> ctypes.CDLL:
         L.to_release.restype = c_int
         L.to_version.argtypes = []
         L.to_version.restype = ctypes.c_char_p
+        L.to_profile_begin.argtypes = []
+        L.to_profile_begin.restype = c_int
+        L.to_profile_end.argtypes = []
+        L.to_profile_end.restype = c_int
+        L.to_profile_count.argtypes = []
+        L.to_profile_count.restype = c_int
+        L.to_profile_entry.argtypes = [c_int, ctypes.c_char_p, c_int, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double)]
+        L.to_profile_entry.restype = c_int
         _lib = L
     return _lib
 
@@ -155,3 +168,21 @@ def coherence_propagate(job, dtype: int, adjoint: bool, grad, stream: int) -> No
     jp = ctypes.byref(job)
     gp = ctypes.byref(grad) if grad is not None else None
     check(lib().to_coherence_propagate(jp, dtype, 1 if adjoint else 0, gp, ctypes.c_void_p(stream)))
+
+
+def profile_begin() -> None:
+    check(lib().to_profile_begin())
+
+
+def profile_end() -> dict:
+    """Stop kernel timing; returns {kernel name: (launches, total GPU ms)}."""
+    L = lib()
+    check(L.to_profile_end())
+    out = {}
+    buf = ctypes.create_string_buffer(128)
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    for i in range(L.to_profile_count()):
+        check(L.to_profile_entry(i, buf, 128, ctypes.byref(n), ctypes.byref(ms)))
+        out[buf.value.decode()] = (int(n.value), float(ms.value))
+    return out

@@ -144,6 +144,65 @@ size_t chunk_budget_bytes() {
   return budget;
 }
 
+// ---------------------------------------------------------------------------
+// Kernel timing (diagnostics): while enabled, every launch is bracketed by a
+// pair of HIP events recorded on its own stream; to_profile_end() waits for
+// them and aggregates the elapsed times per kernel name.
+// ---------------------------------------------------------------------------
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+struct ProfAgg {
+  std::string name;
+  int64_t launches;
+  double ms;
+};
+std::mutex g_prof_mutex;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_prof_pool;
+size_t g_prof_pool_used = 0;
+std::vector<ProfAgg> g_prof_agg;
+
+hipEvent_t prof_event() {
+  if (g_prof_pool_used == g_prof_pool.size()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    g_prof_pool.push_back(ev);
+  }
+  return g_prof_pool[g_prof_pool_used++];
+}
+
+int prof_start(const char* name, int L, bool dbl, hipStream_t s) {
+  if (!g_prof_on) return -1;
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
+  ProfRec r;
+  char buf[96];
+  snprintf(buf, sizeof(buf), "%s_%s_L%d", name, dbl ? "c128" : "c64", L);
+  r.name = buf;
+  r.a = prof_event();
+  r.b = prof_event();
+  if (!r.a || !r.b) return -1;
+  hipEventRecord(r.a, s);
+  g_prof_recs.push_back(r);
+  return (int)g_prof_recs.size() - 1;
+}
+
+void prof_stop(int tok, hipStream_t s) {
+  if (tok < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
+  hipEventRecord(g_prof_recs[tok].b, s);
+}
+
+template <typename F>
+hipError_t timed(const char* name, int L, bool dbl, hipStream_t s, F&& f) {
+  const int tok = prof_start(name, L, dbl, s);
+  hipError_t e = f();
+  prof_stop(tok, s);
+  return e;
+}
+
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 // Host-side validation of one job.  `what` selects which pointers matter.
@@ -312,8 +371,10 @@ to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s) {
     ra.nfields = nf;
     ra.el = el;
     ra.tw = twiddles<T>(c, g.lx);
-    if ((e = Launch<T>::row_fwd(g.lx, g.half_x, g.nc_kernel, j.ny, nf, ra, s)) != hipSuccess)
-      return hip_fail(e, "row_fwd launch");
+    const bool dbl = sizeof(T) == 8;
+    e = timed("fwd.row_fwd", g.lx, dbl, s,
+              [&] { return Launch<T>::row_fwd(g.lx, g.half_x, g.nc_kernel, j.ny, nf, ra, s); });
+    if (e != hipSuccess) return hip_fail(e, "row_fwd launch");
     ColArgs<T> ca;
     ca.scratch = scratch;
     ca.s_stride = g.s_stride;
@@ -323,8 +384,10 @@ to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s) {
     ca.nfields = nf * g.nc_kernel;
     ca.h = h;
     ca.tw = twiddles<T>(c, g.ly);
-    if ((e = Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, ca, s)) != hipSuccess)
-      return hip_fail(e, "col launch");
+    e = timed("fwd.col", g.ly, dbl, s, [&] {
+      return Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, ca, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "col launch");
     RowInvArgs<T> ia;
     memset(&ia, 0, sizeof(ia));
     ia.scratch = scratch;
@@ -345,12 +408,14 @@ to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s) {
     ia.row_partial = c->partial;
     ia.backward = 0;
     ia.el = make_element<T>(j, 0);
-    if ((e = Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, nf, ia, s)) != hipSuccess)
-      return hip_fail(e, "row_inv launch");
+    e = timed("fwd.row_inv", g.lx, dbl, s,
+              [&] { return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, nf, ia, s); });
+    if (e != hipSuccess) return hip_fail(e, "row_inv launch");
     if (j.epi != TO_EPI_NONE) {
-      if ((e = launch_reduce_add(c->partial, (int64_t)nf * j.ny, j.epi_scale, j.epi_loss, s)) !=
-          hipSuccess)
-        return hip_fail(e, "loss reduction launch");
+      e = timed("fwd.loss_reduce", 0, dbl, s, [&] {
+        return launch_reduce_add(c->partial, (int64_t)nf * j.ny, j.epi_scale, j.epi_loss, s);
+      });
+      if (e != hipSuccess) return hip_fail(e, "loss reduction launch");
     }
   }
   return TO_OK;
@@ -392,9 +457,11 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStre
     ra.nfields = nf * (int)flat_per_group;
     ra.el = make_element<T>(j, 0);
     ra.tw = twiddles<T>(c, g.lx);
-    if ((e = Launch<T>::row_fwd(g.lx, g.half_x, 1, j.ny, nf * (int)flat_per_group, ra, s)) !=
-        hipSuccess)
-      return hip_fail(e, "row_fwd launch");
+    const bool dbl = sizeof(T) == 8;
+    e = timed("bwd.row_fwd", g.lx, dbl, s, [&] {
+      return Launch<T>::row_fwd(g.lx, g.half_x, 1, j.ny, nf * (int)flat_per_group, ra, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "row_fwd launch");
     ColArgs<T> ca;
     ca.scratch = scratch;
     ca.s_stride = g.s_stride;
@@ -404,8 +471,10 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStre
     ca.nfields = nf * g.nc_kernel;
     ca.h = h;
     ca.tw = twiddles<T>(c, g.ly);
-    if ((e = Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, ca, s)) != hipSuccess)
-      return hip_fail(e, "col launch");
+    e = timed("bwd.col", g.ly, dbl, s, [&] {
+      return Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, ca, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "col launch");
     RowInvArgs<T> ia;
     memset(&ia, 0, sizeof(ia));
     ia.scratch = scratch;
@@ -426,11 +495,13 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStre
     ia.grad_phase = (T*)gr.grad_phase;
     ia.lens_f = j.el_f;
     ia.lens_partial = want_f ? c->partial : nullptr;
-    if ((e = Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, 1, ia, s)) != hipSuccess)
-      return hip_fail(e, "row_inv launch");
+    e = timed("bwd.row_inv", g.lx, dbl, s,
+              [&] { return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, 1, ia, s); });
+    if (e != hipSuccess) return hip_fail(e, "row_inv launch");
     if (want_f) {
-      if ((e = launch_reduce_add(c->partial, j.ny, 1.0, gr.grad_f, s)) != hipSuccess)
-        return hip_fail(e, "lens gradient reduction launch");
+      e = timed("bwd.lens_reduce", 0, dbl, s,
+                [&] { return launch_reduce_add(c->partial, j.ny, 1.0, gr.grad_f, s); });
+      if (e != hipSuccess) return hip_fail(e, "lens gradient reduction launch");
     }
   }
   return TO_OK;
@@ -555,5 +626,51 @@ to_status to_release(void) {
 }
 
 const char* to_version(void) { return "toprop 0.1.0 gfx950"; }
+
+to_status to_profile_begin(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
+  g_prof_recs.clear();
+  g_prof_agg.clear();
+  g_prof_pool_used = 0;
+  g_prof_on = true;
+  return TO_OK;
+}
+
+to_status to_profile_end(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
+  g_prof_on = false;
+  g_prof_agg.clear();
+  for (const ProfRec& r : g_prof_recs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, r.a, r.b)) != hipSuccess)
+      return hip_fail(e, "hipEventElapsedTime");
+    size_t k = 0;
+    while (k < g_prof_agg.size() && g_prof_agg[k].name != r.name) ++k;
+    if (k == g_prof_agg.size()) g_prof_agg.push_back({r.name, 0, 0.0});
+    g_prof_agg[k].launches += 1;
+    g_prof_agg[k].ms += ms;
+  }
+  g_prof_recs.clear();
+  g_prof_pool_used = 0;
+  return TO_OK;
+}
+
+int32_t to_profile_count(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
+  return (int32_t)g_prof_agg.size();
+}
+
+to_status to_profile_entry(int32_t i, char* name, int32_t name_len, int64_t* launches,
+                           double* total_ms) {
+  std::lock_guard<std::mutex> lk(g_prof_mutex);
+  if (i < 0 || i >= (int32_t)g_prof_agg.size() || !name || name_len < 1 || !launches || !total_ms)
+    return fail(TO_E_INVAL, "bad profile entry query");
+  snprintf(name, (size_t)name_len, "%s", g_prof_agg[i].name.c_str());
+  *launches = g_prof_agg[i].launches;
+  *total_ms = g_prof_agg[i].ms;
+  return TO_OK;
+}
 
 }  // extern "C"

@@ -22,7 +22,7 @@ def capi():
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:to_status|const char\*)\s+(to_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:to_status|const char\*|int32_t)\s+(to_\w+)\s*\(", text, re.M)))
 
 
 def test_library_exports_every_declared_function(capi):

@@ -1,0 +1,230 @@
+"""GPU parity of the backward pass and the fused loss epilogues.
+
+The GPU adjoint, input gradient and parameter gradients (phase mask, lens
+focal length, Jones elements) are compared with the oracle's chain-rule
+gradients, which are themselves pinned by central finite differences in
+test_oracle_pins.py.  Tolerances: complex64 relative L2 <= 2e-5 on fields,
+<= 1e-4 on parameter gradients (sums over a batch in FP32); complex128
+<= 1e-12 / 1e-11.  Gradients are also checked against finite differences of
+the GPU forward in complex128 (relative error <= 1e-3, the stated bar for
+gradients), and for bitwise run-to-run determinism.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests._util import announce, crandn, rel, to_gpu, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = {np.complex64: 2e-5, np.complex128: 1e-12}
+PARAM_TOL = {np.complex64: 1e-4, np.complex128: 1e-11}
+
+
+def _tp():
+    import paper_2411_18591_amd as tp
+    return tp
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+@pytest.mark.parametrize("method", ["asm", "fresnel"])
+@pytest.mark.parametrize("shape", [(32, 32, 64, 64), (48, 100, 128, 256), (64, 64, 64, 64)])
+def test_backward_phase_mask(shape, method, dtype):
+    tp = _tp()
+    ny, nx, py, px = shape
+    announce(f"backward phase {shape} {method} {dtype.__name__}")
+    rng = np.random.default_rng(21)
+    B = 3
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    u = crandn(rng, B, ny, nx, dtype=dtype)
+    g = crandn(rng, B, ny, nx, dtype=dtype)
+    phi = (rng.random((ny, nx)) * 2 * np.pi).astype(rdt)
+    d, lam, z = (7e-6, 5e-6), 0.65e-6, 0.03
+    meth = oracle.ASM if method == "asm" else oracle.FRESNEL
+    M = oracle.phase_mask(phi)
+    g_mod = oracle.propagate(g, d[0], d[1], lam, z, meth, padded=(py, px), adjoint=True)
+    exp_gin = oracle.modulate(g_mod, M, conj=True)
+    exp_gphi = oracle.grad_phase(g_mod, oracle.modulate(u, M))
+    opt = tp.Optics(dy=d[0], dx=d[1], wavelength=lam, z=z, method=method, padded=(py, px))
+    gphi = torch.zeros((ny, nx), dtype=torch.float32 if dtype == np.complex64 else torch.float64,
+                       device="cuda")
+    gin = tp.propagate_backward(to_gpu(g, torch), opt, saved_in=to_gpu(u, torch), grad_phase=gphi,
+                                phase=to_gpu(phi, torch))
+    torch.cuda.synchronize()
+    assert rel(to_np(gin), exp_gin) <= FIELD_TOL[dtype]
+    assert rel(to_np(gphi), exp_gphi) <= PARAM_TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_adjoint_identity_on_gpu(dtype):
+    tp = _tp()
+    announce(f"adjoint identity {dtype.__name__}")
+    rng = np.random.default_rng(22)
+    u = crandn(rng, 1, 64, 64, dtype=dtype)
+    v = crandn(rng, 1, 64, 64, dtype=dtype)
+    opt = tp.Optics(dy=8e-6, dx=8e-6, wavelength=0.7e-6, z=0.1, pad=2)
+    Pu = to_np(tp.propagate(to_gpu(u, torch), opt))
+    PHv = to_np(tp.propagate_backward(to_gpu(v, torch), opt))
+    lhs, rhs = np.vdot(v.astype(complex), Pu.astype(complex)), np.vdot(PHv.astype(complex), u.astype(complex))
+    assert abs(lhs - rhs) / abs(lhs) <= (1e-5 if dtype == np.complex64 else 1e-13)
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_lens_gradient(dtype):
+    tp = _tp()
+    announce(f"lens gradient {dtype.__name__}")
+    rng = np.random.default_rng(23)
+    n, d, lam, f, z = 64, 5e-6, 0.6e-6, 0.05, 0.05
+    u = crandn(rng, 2, n, n, dtype=dtype)
+    g = crandn(rng, 2, n, n, dtype=dtype)
+    um = oracle.modulate(u, oracle.lens(n, n, d, d, lam, f))
+    g_mod = oracle.propagate(g, d, d, lam, z, oracle.FRESNEL, 2, adjoint=True)
+    exp_f = oracle.grad_lens_f(g_mod, um, n, n, d, d, lam, f)
+    exp_gin = oracle.modulate(g_mod, oracle.lens(n, n, d, d, lam, f), conj=True)
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, method="fresnel", pad=2)
+    gf = torch.zeros((), dtype=torch.float64, device="cuda")
+    gin = tp.propagate_backward(to_gpu(g, torch), opt, saved_in=to_gpu(u, torch), grad_f=gf, lens_f=f)
+    torch.cuda.synchronize()
+    assert rel(to_np(gin), exp_gin) <= FIELD_TOL[dtype]
+    assert abs(float(gf.item()) - exp_f) <= PARAM_TOL[dtype] * abs(exp_f)
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_jones_lens_forward_backward(dtype):
+    """Polarized fields: uniform Jones matrix (quarter-wave plate then a
+    polarizer) with a lens, Fresnel propagation, weighted-intensity loss,
+    gradient to the focal length and to the input."""
+    tp = _tp()
+    announce(f"jones + lens {dtype.__name__}")
+    rng = np.random.default_rng(24)
+    W_, n, d, lam, f, z = 2, 32, 6e-6, 0.55e-6, 0.04, 0.03
+    E = crandn(rng, W_, 3, n, n, dtype=dtype)
+    Wt = rng.random((n, n)).astype(np.float32 if dtype == np.complex64 else np.float64)
+    Jo = oracle.embed_jones(oracle.linear_polarizer(math.pi / 6) @ oracle.waveplate(math.pi / 4, math.pi / 2))
+    Jg = tp.jones3(tp.waveplate(math.pi / 4, math.pi / 2), tp.linear_polarizer(math.pi / 6))
+    assert np.abs(np.array(Jg) - Jo).max() < 1e-15
+    L = oracle.lens(n, n, d, d, lam, f)
+    Em = oracle.modulate(oracle.jones_apply(E, Jo), L)
+    out = oracle.propagate(Em, d, d, lam, z, oracle.FRESNEL, 2)
+    loss, gout = oracle.weighted_intensity(out, Wt, d, d)
+    g_mod = oracle.propagate(gout, d, d, lam, z, oracle.FRESNEL, 2, adjoint=True)
+    exp_f = oracle.grad_lens_f(g_mod, Em, n, n, d, d, lam, f)
+    exp_gin = oracle.jones_apply(oracle.modulate(g_mod, L, conj=True), Jo, conj_transpose=True)
+
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, method="fresnel", pad=2)
+    Eg = to_gpu(E, torch)
+    o, go, lo = tp.propagate_loss(Eg, opt, kind="weighted", ref=to_gpu(Wt, torch), scale=d * d,
+                                  ncomp=3, jones=Jg, lens_f=f)
+    gf = torch.zeros((), dtype=torch.float64, device="cuda")
+    gin = tp.propagate_backward(go, opt, saved_in=Eg, grad_f=gf, ncomp=3, jones=Jg, lens_f=f)
+    torch.cuda.synchronize()
+    assert rel(to_np(o), out) <= FIELD_TOL[dtype]
+    assert rel(to_np(go), gout) <= FIELD_TOL[dtype]
+    assert abs(float(lo.item()) - loss) <= PARAM_TOL[dtype] * abs(loss)
+    assert rel(to_np(gin), exp_gin) <= FIELD_TOL[dtype]
+    assert abs(float(gf.item()) - exp_f) <= PARAM_TOL[dtype] * abs(exp_f)
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_mse_epilogue(dtype):
+    tp = _tp()
+    announce(f"mse epilogue {dtype.__name__}")
+    rng = np.random.default_rng(25)
+    B, n = 3, 64
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    u = crandn(rng, B, n, n, dtype=dtype)
+    T = rng.random((n, n)).astype(rdt)
+    phi = (rng.random((n, n)) * 6).astype(rdt)
+    opt = tp.Optics(dy=8e-6, dx=8e-6, wavelength=0.7e-6, z=0.05, pad=2)
+    out = oracle.propagate(oracle.modulate(u, oracle.phase_mask(phi)), 8e-6, 8e-6, 0.7e-6, 0.05,
+                           oracle.ASM, 2)
+    loss, g = oracle.mse_intensity(out, T)
+    o, go, lo = tp.propagate_loss(to_gpu(u, torch), opt, kind="mse", ref=to_gpu(T, torch),
+                                  scale=1.0 / u.size, phase=to_gpu(phi, torch))
+    torch.cuda.synchronize()
+    assert rel(to_np(o), out) <= FIELD_TOL[dtype]
+    assert rel(to_np(go), g) <= 4 * FIELD_TOL[dtype]
+    assert abs(float(lo.item()) - loss) <= 4 * FIELD_TOL[dtype] * abs(loss)
+
+
+def test_diffractive_stack_gradients_c64():
+    """Three phase layers, MSE loss, all mask gradients vs the oracle."""
+    tp = _tp()
+    announce("diffractive stack 3 layers 128^2 b=4 c64")
+    rng = np.random.default_rng(26)
+    B, n, L = 4, 128, 3
+    d, lam, z = 8e-6, 0.7e-6, 0.05
+    u0 = crandn(rng, B, n, n, dtype=np.complex64)
+    phis = (rng.random((L, n, n)) * 2 * np.pi).astype(np.float32)
+    T = rng.random((n, n)).astype(np.float32)
+    us = oracle.stack_forward(u0, list(phis), d, d, lam, z, oracle.ASM, 2)
+    loss, g = oracle.mse_intensity(us[-1], T)
+    _, grads = oracle.stack_backward(us, list(phis), g, d, d, lam, z, oracle.ASM, 2)
+
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, pad=2)
+    Pg = to_gpu(phis, torch)
+    ug = [to_gpu(u0, torch)]
+    for l in range(L - 1):
+        ug.append(tp.propagate(ug[-1], opt, phase=Pg[l]))
+    o, go, lo = tp.propagate_loss(ug[-1], opt, kind="mse", ref=to_gpu(T, torch), scale=1.0 / u0.size,
+                                  phase=Pg[L - 1])
+    gp = torch.zeros_like(Pg)
+    for l in range(L - 1, -1, -1):
+        go = tp.propagate_backward(go, opt, saved_in=ug[l], grad_phase=gp[l], phase=Pg[l],
+                                   want_grad_in=l > 0)
+    torch.cuda.synchronize()
+    assert abs(float(lo.item()) - loss) <= 1e-4 * loss
+    for l in range(L):
+        assert rel(to_np(gp[l]), grads[l]) <= 2e-4, l
+
+
+def test_gradient_determinism():
+    tp = _tp()
+    announce("determinism")
+    rng = np.random.default_rng(27)
+    u = to_gpu(crandn(rng, 5, 64, 64, dtype=np.complex64), torch)
+    g = to_gpu(crandn(rng, 5, 64, 64, dtype=np.complex64), torch)
+    phi = to_gpu(rng.random((64, 64)).astype(np.float32), torch)
+    opt = tp.Optics(dy=8e-6, dx=8e-6, wavelength=0.7e-6, z=0.05, pad=2)
+    res = []
+    for _ in range(2):
+        gp = torch.zeros((64, 64), dtype=torch.float32, device="cuda")
+        gi = tp.propagate_backward(g, opt, saved_in=u, grad_phase=gp, phase=phi)
+        torch.cuda.synchronize()
+        res.append((to_np(gp), to_np(gi)))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+def test_autograd_finite_differences_c128():
+    """torch.autograd through the library vs central finite differences of
+    the library's own forward (complex128)."""
+    tp = _tp()
+    announce("autograd FD c128")
+    rng = np.random.default_rng(28)
+    n = 32
+    u = to_gpu(crandn(rng, 2, n, n), torch)
+    T = to_gpu(rng.random((n, n)), torch)
+    phi0 = rng.random((n, n)) * 6
+    opt = tp.Optics(dy=6e-6, dx=6e-6, wavelength=0.6e-6, z=0.02, pad=2)
+
+    def loss_of(phi_t, f_t):
+        out = tp.propagate_ad(u, opt, phase=phi_t, lens_f=f_t)
+        return ((out.abs() ** 2 - T) ** 2).mean()
+
+    phi = to_gpu(phi0, torch).requires_grad_(True)
+    f = torch.tensor(0.03, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = loss_of(phi, f)
+    L.backward()
+    h = 1e-6
+    dirn = to_gpu(rng.standard_normal((n, n)), torch)
+    with torch.no_grad():
+        fd = (loss_of(phi + h * dirn, f) - loss_of(phi - h * dirn, f)) / (2 * h)
+        an = torch.sum(phi.grad * dirn)
+        assert abs(float(fd - an)) <= 1e-3 * abs(float(an))
+        hf = 1e-7
+        fdf = (loss_of(phi, f + hf) - loss_of(phi, f - hf)) / (2 * hf)
+        assert abs(float(fdf - f.grad)) <= 1e-3 * abs(float(f.grad))
