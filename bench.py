@@ -99,9 +99,18 @@ def main():
     P = 2 * N
     print(f"[bench] generating inputs: {B} x {N}^2 fields, {L} masks", file=sys.stderr, flush=True)
     t0 = time.time()
-    u0_np = wl_def.fields()
-    masks_np = wl_def.masks()
-    target_np = wl_def.target()
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"toprop_bench_{B}_{N}_{L}.npz")
+    if os.path.exists(cache):
+        with np.load(cache) as z:
+            u0_np, masks_np, target_np = z["u0"], z["masks"], z["target"]
+    else:
+        u0_np = wl_def.fields()
+        masks_np = wl_def.masks()
+        target_np = wl_def.target()
+        try:
+            np.savez(cache, u0=u0_np, masks=masks_np, target=target_np)
+        except OSError:
+            pass
     print(f"[bench] inputs ready in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
 
     u = [torch.from_numpy(u0_np).to(dev)] + [torch.empty((B, N, N), dtype=torch.complex64, device=dev)

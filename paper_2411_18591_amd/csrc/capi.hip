@@ -66,6 +66,9 @@ struct DeviceCtx {
   bool init = false;
   cx<float>* tw32 = nullptr;
   cx<double>* tw64 = nullptr;
+  // separable transfer-function tables of the job being run: ex, ey
+  // (complex64) and sx, sy (float), kMaxLen entries each
+  void* tf = nullptr;
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
   double* partial = nullptr;
@@ -95,6 +98,8 @@ to_status get_ctx(DeviceCtx** out) {
     if ((e = hipMemcpy(c.tw64, h64.data(), sizeof(cx<double>) * kTwTotal, hipMemcpyHostToDevice)) !=
         hipSuccess)
       return hip_fail(e, "twiddle upload");
+    if ((e = hipMalloc(&c.tf, (size_t)kMaxLen * 2 * (sizeof(cx<float>) + sizeof(float)))) != hipSuccess)
+      return fail(TO_E_NOMEM, "table allocation failed: %s", hipGetErrorString(e));
     c.init = true;
   }
   *out = &c;
@@ -132,6 +137,17 @@ to_status ensure_partial(DeviceCtx* c, size_t count) {
     return fail(TO_E_NOMEM, "partial-sum allocation failed: %s", hipGetErrorString(e));
   c->partial_count = count;
   return TO_OK;
+}
+
+// Column-pass configuration (ColCfg variant); TOPROP_COL_VARIANT overrides
+// the default for tuning runs.
+int col_variant() {
+  static int v = [] {
+    const char* s = getenv("TOPROP_COL_VARIANT");
+    int x = s ? atoi(s) : 1;
+    return (x >= 0 && x < kColVariants) ? x : 1;
+  }();
+  return v;
 }
 
 size_t chunk_budget_bytes() {
@@ -274,7 +290,68 @@ TransferParams make_transfer(const to_job& j, bool conj) {
   p.fres_a = 0.5 * lam * z;
   p.inv_lxdx = 1.0 / ((double)j.px * j.dx);
   p.inv_lydy = 1.0 / ((double)j.py * j.dy);
+  p.fast = 0;
+  p.qh = (float)(0.5 * p.q);
+  p.ex = p.ey = nullptr;
+  p.sx = p.sy = nullptr;
   return p;
+}
+
+// Largest non-paraxial remainder (q/2) t^2 of the angular spectrum over the
+// padded grid, in cycles (infinite when some bin is evanescent).  The
+// largest |f| on a length-L grid of spacing d is 1/(2d) (bin -L/2).
+double asm_remainder_cycles(const to_job& j) {
+  const double fx = 0.5 / j.dx, fy = 0.5 / j.dy;
+  const double s = j.wavelength * j.wavelength * (fx * fx + fy * fy);
+  if (!(s < 1.0)) return INFINITY;
+  const double t = s / (1.0 + std::sqrt(1.0 - s));
+  return 0.5 * std::fabs(j.z / j.wavelength) * t * t;
+}
+
+// complex64 jobs use the separable transfer function when its FP32 remainder
+// term stays below this many cycles (error ~1e-7 cycles); otherwise, and for
+// complex128, the phase is evaluated per bin in FP64.
+constexpr double kFastRemainderCycles = 1.0;
+
+template <typename T>
+hipError_t prepare_transfer(const to_job& j, DeviceCtx* c, hipStream_t s, TransferParams* h) {
+  if (sizeof(T) != 4) return hipSuccess;
+  if (j.method == TO_ASM && !(asm_remainder_cycles(j) <= kFastRemainderCycles)) return hipSuccess;
+  cx<float>* ex = (cx<float>*)c->tf;
+  cx<float>* ey = ex + kMaxLen;
+  float* sx = (float*)(ey + kMaxLen);
+  float* sy = sx + kMaxLen;
+  hipError_t e = timed("tf_tables", j.px, false, s, [&] {
+    return launch_tf_tables(ex, sx, j.px, h->inv_lxdx, ey, sy, j.py, h->inv_lydy, h->fres_a,
+                            h->q_frac, h->lam2, s);
+  });
+  if (e != hipSuccess) return e;
+  h->fast = 1;
+  h->ex = ex;
+  h->ey = ey;
+  h->sx = sx;
+  h->sy = sy;
+  return hipSuccess;
+}
+
+// Fields per row block: a block pipelines the loads of its next field behind
+// the transform of the current one (and evaluates the element's modulation
+// once for all of them), while the launch keeps >= ~2048 blocks.
+int fields_per_block_rows(int row_blocks, int nfields) {
+  int fpb = (int)((int64_t)row_blocks * nfields / 2048);
+  if (fpb < 1) fpb = 1;
+  if (fpb > 8) fpb = 8;
+  if (fpb > nfields) fpb = nfields;
+  return fpb;
+}
+
+int fields_per_block(const to_job& j, int row_blocks, int nfields) {
+  (void)j;
+  int fpb = (int)((int64_t)row_blocks * nfields / 2048);
+  if (fpb < 1) fpb = 1;
+  if (fpb > 8) fpb = 8;
+  if (fpb > nfields) fpb = nfields;
+  return fpb;
 }
 
 template <typename T>
@@ -302,7 +379,7 @@ const cx<double>* twiddles<double>(DeviceCtx* c, int L) { return c->tw64 + tw_of
 
 // Geometry shared by the forward and backward launch sequences.
 struct Geometry {
-  int lx, ly, tc, tc_shift;
+  int lx, ly, tc, tm, tc_shift;
   bool half_x, half_y;
   int nc_kernel;          // 3 when a Jones element couples the components
   int64_t nfields;        // independent field groups seen by the row kernels
@@ -310,17 +387,25 @@ struct Geometry {
   int64_t comp_stride;    // elements between components
   int64_t s_stride;       // scratch elements per (field group, component)
   int64_t chunk;          // field groups per chunk
+  int rows_per_block;     // rows handled by one row-pass workgroup
+  int col_variant;        // column-pass configuration (see ColCfg)
 };
 
 template <typename T>
 to_status make_geometry(const to_job& j, bool jones, Geometry* g) {
   g->lx = j.px;
   g->ly = j.py;
-  g->tc = col_tile_width(g->ly, sizeof(T) == 8);
+  g->col_variant = col_variant();
+  // columns per column-pass block (cpb) and the scratch tile width (tm):
+  // a tile row segment is one 128-byte cache line when the rows allow it
+  g->tc = col_tile_width(g->ly, sizeof(T) == 8, g->col_variant);
   if (g->tc > g->lx) g->tc = g->lx;
-  if (g->tc <= 0 || g->lx % g->tc != 0)
+  g->tm = std::max<int>(g->tc, (int)(128 / sizeof(cx<T>)));
+  if (g->tm > g->lx) g->tm = g->lx;
+  if (g->tc <= 0 || g->lx % g->tc != 0 || g->tm % g->tc != 0)
     return fail(TO_E_UNSUPPORTED, "no column configuration for %dx%d", g->ly, g->lx);
-  g->tc_shift = ilog2i(g->tc);
+  g->tc_shift = ilog2i(g->tm);
+  g->rows_per_block = row_rows_per_block(g->lx);
   // Pruned first/last passes when the field fills at most half of the
   // padded extent along that axis.
   g->half_x = 2 * j.nx <= g->lx;
@@ -354,12 +439,14 @@ to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s) {
     if (st != TO_OK) return st;
   }
   cx<T>* scratch = (cx<T>*)c->scratch;
-  const TransferParams h = make_transfer(j, false);
+  TransferParams h = make_transfer(j, false);
   const ElementParams<T> el = make_element<T>(j, j.el_flags);
-  hipError_t e;
+  hipError_t e = prepare_transfer<T>(j, c, s, &h);
+  if (e != hipSuccess) return hip_fail(e, "transfer table launch");
   for (int64_t f0 = 0; f0 < g.nfields; f0 += g.chunk) {
     const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
     RowFwdArgs<T> ra;
+    ra.fpb = fields_per_block(j, (j.ny + g.rows_per_block - 1) / g.rows_per_block, nf);
     ra.in = (const cx<T>*)j.in + f0 * g.in_stride;
     ra.scratch = scratch;
     ra.in_stride = g.in_stride;
@@ -380,12 +467,13 @@ to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s) {
     ca.s_stride = g.s_stride;
     ca.ny = j.ny;
     ca.lx = g.lx;
-    ca.tcl = g.tc;
+    ca.tm = g.tm;
+    ca.cpb = g.tc;
     ca.nfields = nf * g.nc_kernel;
     ca.h = h;
     ca.tw = twiddles<T>(c, g.ly);
     e = timed("fwd.col", g.ly, dbl, s, [&] {
-      return Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, ca, s);
+      return Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, g.col_variant, ca, s);
     });
     if (e != hipSuccess) return hip_fail(e, "col launch");
     RowInvArgs<T> ia;
@@ -407,9 +495,11 @@ to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s) {
     ia.epi_grad = j.epi_grad ? (cx<T>*)j.epi_grad + f0 * g.in_stride : nullptr;
     ia.row_partial = c->partial;
     ia.backward = 0;
+    ia.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block, nf);
+    const int inv_blocks_y = (nf + ia.fpb - 1) / ia.fpb;
     ia.el = make_element<T>(j, 0);
     e = timed("fwd.row_inv", g.lx, dbl, s,
-              [&] { return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, nf, ia, s); });
+              [&] { return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, inv_blocks_y, ia, s); });
     if (e != hipSuccess) return hip_fail(e, "row_inv launch");
     if (j.epi != TO_EPI_NONE) {
       e = timed("fwd.loss_reduce", 0, dbl, s, [&] {
@@ -436,9 +526,10 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStre
     if (st != TO_OK) return st;
   }
   cx<T>* scratch = (cx<T>*)c->scratch;
-  const TransferParams h = make_transfer(j, true);
+  TransferParams h = make_transfer(j, true);
   const ElementParams<T> el = make_element<T>(j, j.el_flags);
-  hipError_t e;
+  hipError_t e = prepare_transfer<T>(j, c, s, &h);
+  if (e != hipSuccess) return hip_fail(e, "transfer table launch");
   // The gradient rows carry no element: the first two passes treat every
   // component as an independent field.
   const int64_t flat_per_group = g.nc_kernel;
@@ -455,6 +546,8 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStre
     ra.nx = j.nx;
     ra.tc_shift = g.tc_shift;
     ra.nfields = nf * (int)flat_per_group;
+    ra.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block,
+                                   nf * (int)flat_per_group);
     ra.el = make_element<T>(j, 0);
     ra.tw = twiddles<T>(c, g.lx);
     const bool dbl = sizeof(T) == 8;
@@ -467,12 +560,13 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStre
     ca.s_stride = g.s_stride;
     ca.ny = j.ny;
     ca.lx = g.lx;
-    ca.tcl = g.tc;
+    ca.tm = g.tm;
+    ca.cpb = g.tc;
     ca.nfields = nf * g.nc_kernel;
     ca.h = h;
     ca.tw = twiddles<T>(c, g.ly);
     e = timed("bwd.col", g.ly, dbl, s, [&] {
-      return Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, ca, s);
+      return Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, g.col_variant, ca, s);
     });
     if (e != hipSuccess) return hip_fail(e, "col launch");
     RowInvArgs<T> ia;
@@ -490,6 +584,7 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStre
     ia.tw = twiddles<T>(c, g.lx);
     ia.epi = TO_EPI_NONE;
     ia.backward = 1;
+    ia.fpb = nf;
     ia.el = el;
     ia.saved_in = gr.saved_in ? (const cx<T>*)gr.saved_in + f0 * g.in_stride : nullptr;
     ia.grad_phase = (T*)gr.grad_phase;

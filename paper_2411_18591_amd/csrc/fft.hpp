@@ -197,7 +197,7 @@ __device__ __forceinline__ void stockham_butterflies(cx<T>* v, int j, const cx<T
       constexpr int step = L / (NS * RP);
 #pragma unroll
       for (int i = 1; i < RP; ++i) {
-        cx<T> w = tw[i * k * step];
+        cx<T> w = tw[(uint32_t)(i * k * step)];
         if (D > 0) w.y = -w.y;
         u[i] = cmul(u[i], w);
       }

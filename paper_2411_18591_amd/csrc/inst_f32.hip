@@ -10,14 +10,43 @@ hipError_t launch_reduce_add(const double* src, int64_t n, double scale, double*
   return hipGetLastError();
 }
 
-int col_tile_width(int ly, bool is_double) {
+int col_tile_width(int ly, bool is_double, int variant) {
   int tc = 0;
   auto q = [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    tc = is_double ? ColCfg<double, L>::TC : ColCfg<float, L>::TC;
+    if (variant == 1)
+      tc = is_double ? ColCfg<double, L, 1>::TC : ColCfg<float, L, 1>::TC;
+    else if (variant == 2)
+      tc = is_double ? ColCfg<double, L, 2>::TC : ColCfg<float, L, 2>::TC;
+    else
+      tc = is_double ? ColCfg<double, L, 0>::TC : ColCfg<float, L, 0>::TC;
     return hipSuccess;
   };
   if (dispatch_len(ly, q) != hipSuccess) return 0;
   return tc;
+}
+}  // namespace toprop
+
+namespace toprop {
+hipError_t launch_tf_tables(cx<float>* ex, float* sx, int lx, double inv_lxdx, cx<float>* ey,
+                            float* sy, int ly, double inv_lydy, double fres_a, double q_frac,
+                            double lam2, hipStream_t s) {
+  const int n = lx + ly;
+  hipLaunchKernelGGL((tf_tables_kernel<float>), dim3((n + 255) / 256), dim3(256), 0, s, ex, sx, lx,
+                     inv_lxdx, ey, sy, ly, inv_lydy, fres_a, q_frac, lam2);
+  return hipGetLastError();
+}
+}  // namespace toprop
+
+namespace toprop {
+int row_rows_per_block(int lx) {
+  int g = 0;
+  auto q = [&](auto Lc) -> hipError_t {
+    constexpr int L = decltype(Lc)::value;
+    g = RowCfg<L>::G;
+    return hipSuccess;
+  };
+  if (dispatch_len(lx, q) != hipSuccess) return 1;
+  return g;
 }
 }  // namespace toprop

@@ -38,6 +38,18 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
+// Workgroups of a launch are dispatched round-robin over the 8 XCDs of the
+// MI355X (block b runs on XCD b mod 8), and each XCD has its own L2.  This
+// maps the dispatch index to a logical index so that every XCD receives one
+// contiguous range: neighbouring rows, whose column-tile segments share
+// cache lines, are then processed under the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  constexpr int kXcd = 8;
+  const int per = n / kXcd, rem = n % kXcd;
+  const int x = b % kXcd, k = b / kXcd;
+  return x * per + min(x, rem) + k;
+}
+
 // ---------------------------------------------------------------------------
 // Trigonometric helpers.  Phases are carried in cycles; sincospi takes half
 // cycles.
@@ -59,10 +71,15 @@ __device__ __forceinline__ cx<T> cis_cycles(double c) {
   double fr = c - rint(c);
   return cis_cycles_reduced(fr, T());
 }
+// exp(i a) for a phase in radians: converted to cycles and reduced to
+// [-0.5, 0.5] first, so sincospi needs no large-argument reduction.  The
+// conversion rounds a * (1/2pi) to FP32, an error below one ulp of a itself.
 __device__ __forceinline__ cx<float> cis_rad(float a) {
-  float s, c;
-  sincosf(a, &s, &c);
-  return {c, s};
+  const float c = a * 0.15915494309189533577f;
+  const float fr = c - rintf(c);
+  float s, co;
+  sincospif(2.0f * fr, &s, &co);
+  return {co, s};
 }
 __device__ __forceinline__ cx<double> cis_rad(double a) {
   double s, c;
@@ -82,6 +99,21 @@ struct TransferParams {
   double fres_a;    // lambda z / 2
   double inv_lxdx;  // 1 / (LX dx)
   double inv_lydy;  // 1 / (LY dy)
+  // Separable form (complex64 path only, chosen by the host when accurate):
+  //   H = ey[ky] ex[kx] exp(-2 pi i (q/2) t^2),  t = s / (1 + sqrt(1 - s)),
+  //   s = sx[kx] + sy[ky] = lambda^2 (fx^2 + fy^2)
+  // where ex = exp(-2 pi i (lambda z/2) fx^2) and ey = exp(2 pi i (frac(z/lambda)
+  // - (lambda z/2) fy^2)) are built in FP64 by tf_tables_kernel.  The last
+  // factor is the non-paraxial remainder of the angular spectrum, since
+  // z sqrt(1/lambda^2 - f^2) = z/lambda - (lambda z/2) f^2 - (q/2) t^2; the
+  // host uses this path only when (q/2) t^2 stays below one cycle, so FP32
+  // evaluates it to ~1e-7 cycles.  Fresnel: the remainder is absent.
+  int fast;
+  float qh;               // q / 2
+  const cx<float>* ex;
+  const cx<float>* ey;
+  const float* sx;
+  const float* sy;
 };
 
 // Transfer function at padded-grid bin (kx, ky), FFT order.
@@ -108,6 +140,55 @@ __device__ __forceinline__ cx<T> transfer_at(int kx, int ky, int lx, int ly, con
   cx<T> h = cis_cycles<T>(c);
   if (p.conj) h.y = -h.y;
   return h;
+}
+
+// Separable complex64 transfer function (see TransferParams).  `exk`/`sxk`
+// are the column's table entries.
+__device__ __forceinline__ cx<float> transfer_fast(cx<float> exk, float sxk, int ky, int ly,
+                                                   float lam_fy_unit, const TransferParams& p) {
+  cx<float> h = cmul(exk, p.ey[ky]);
+  if (p.method == 0) {
+    // s = lambda^2 (fx^2 + fy^2); the y part from the bin index in FP32
+    // (relative error ~1e-7 on a remainder below one cycle)
+    const float gy = (float)(ky < ly / 2 ? ky : ky - ly) * lam_fy_unit;
+    const float s = fmaf(gy, gy, sxk);
+    // v_sqrt / v_rcp (~1 ulp) and v_sin / v_cos, whose argument is in
+    // revolutions (|theta| <= 1 here; absolute error ~1.2e-7): the
+    // remainder needs ~1e-6 relative accuracy only.
+    const float t = s * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_sqrtf(1.0f - s));
+    const float theta = -p.qh * t * t;
+    h = cmul(h, cx<float>{__builtin_amdgcn_cosf(theta), __builtin_amdgcn_sinf(theta)});
+  }
+  if (p.conj) h.y = -h.y;
+  return h;
+}
+
+// FP64-built tables of the separable transfer function for one propagation:
+// entries 0..lx-1 are the x tables, lx..lx+ly-1 the y tables.
+template <typename T>
+__global__ void __launch_bounds__(256) tf_tables_kernel(cx<float>* ex, float* sx, int lx,
+                                                        double inv_lxdx, cx<float>* ey, float* sy,
+                                                        int ly, double inv_lydy, double fres_a,
+                                                        double q_frac, double lam2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < lx) {
+    const int ks = i < lx / 2 ? i : i - lx;
+    const double f = (double)ks * inv_lxdx;
+    const double c = -fres_a * f * f;
+    double s, co;
+    sincospi(2.0 * (c - rint(c)), &s, &co);
+    ex[i] = {(float)co, (float)s};
+    sx[i] = (float)(lam2 * f * f);
+  } else if (i < lx + ly) {
+    const int k = i - lx;
+    const int ks = k < ly / 2 ? k : k - ly;
+    const double f = (double)ks * inv_lydy;
+    const double c = q_frac - fres_a * f * f;
+    double s, co;
+    sincospi(2.0 * (c - rint(c)), &s, &co);
+    ey[k] = {(float)co, (float)s};
+    sy[k] = (float)(lam2 * f * f);
+  }
 }
 
 template <typename T>
@@ -152,6 +233,23 @@ __device__ __forceinline__ double lens_dphase_df(const ElementParams<T>& e, int 
 // `lds` points at element 0 of this transform's LDS region; element `pos`
 // lives at lds[pos * STRIDE].
 // ---------------------------------------------------------------------------
+// LDS position of transform element `pos`, padded against bank conflicts
+// (64 banks of 4 bytes, 64-bit accesses).  Rows (STRIDE 1): two pad slots
+// every 32 elements plus one every 128; column tiles (STRIDE = columns per
+// block, element (pos, c) at lds_pos(pos) * STRIDE + c): one pad row every 16
+// rows, which makes every Stockham write and read pattern conflict-free.
+template <int STRIDE>
+__device__ __forceinline__ constexpr int lds_pos(int pos) {
+  if constexpr (STRIDE == 1)
+    return pos + 2 * (pos >> 5) + (pos >> 7);
+  else
+    return pos + (pos >> 4);
+}
+template <int STRIDE>
+constexpr int lds_len(int L) {  // elements (per column) of a padded exchange buffer
+  return STRIDE == 1 ? L + 2 * (L >> 5) + (L >> 7) : L + (L >> 4);
+}
+
 template <typename T, int L, int R, int D, bool HALF_IN, int STRIDE>
 __device__ __forceinline__ void fft_wg(cx<T>* v, int j, cx<T>* lds, const cx<T>* __restrict__ tw) {
   using S = Schedule<L, R>;
@@ -163,15 +261,33 @@ __device__ __forceinline__ void fft_wg(cx<T>* v, int j, cx<T>* lds, const cx<T>*
     constexpr int NB = R / RP;
     stockham_butterflies<T, L, R, RP, NS, D, HALF_IN && P == 0>(v, j, tw);
     if constexpr (P + 1 < S::npass) {
+      // The padding is periodic (period 128 positions for rows, 16 for
+      // column tiles), so lds_pos(p + k*step) = lds_pos(p) + k*lds_pos(step)
+      // whenever step is a multiple of the period: the per-element offsets
+      // then become compile-time immediates on a per-thread base.
+      constexpr int PER = STRIDE == 1 ? 128 : 16;
       __syncthreads();
 #pragma unroll
-      for (int t = 0; t < NB; ++t)
+      for (int t = 0; t < NB; ++t) {
+        const int p0 = stockham_out_pos<L, R, RP, NS>(j, t, 0);
+        const int b0 = lds_pos<STRIDE>(p0) * STRIDE;
 #pragma unroll
-        for (int i = 0; i < RP; ++i)
-          lds[stockham_out_pos<L, R, RP, NS>(j, t, i) * STRIDE] = v[t + i * NB];
+        for (int i = 0; i < RP; ++i) {
+          if constexpr (NS % PER == 0)
+            lds[b0 + i * lds_pos<STRIDE>(NS) * STRIDE] = v[t + i * NB];
+          else
+            lds[lds_pos<STRIDE>(p0 + i * NS) * STRIDE] = v[t + i * NB];
+        }
+      }
       __syncthreads();
+      const int r0 = lds_pos<STRIDE>(j) * STRIDE;
 #pragma unroll
-      for (int m = 0; m < R; ++m) v[m] = lds[(j + m * TT) * STRIDE];
+      for (int m = 0; m < R; ++m) {
+        if constexpr (TT % PER == 0)
+          v[m] = lds[r0 + m * lds_pos<STRIDE>(TT) * STRIDE];
+        else
+          v[m] = lds[lds_pos<STRIDE>(j + m * TT) * STRIDE];
+      }
     }
   });
 }
@@ -189,6 +305,7 @@ struct RowFwdArgs {
   int ny, nx;
   int tc_shift;         // log2 of the column-tile width
   int nfields;          // fields in this chunk (field groups for NC = 3)
+  int fpb;              // fields per block (the modulation is evaluated once for them)
   ElementParams<T> el;
   const cx<T>* tw;      // twiddles of length LX
 };
@@ -199,7 +316,8 @@ struct ColArgs {
   int64_t s_stride;
   int ny;
   int lx;               // padded row length (for the signed x frequency)
-  int tcl;              // column-tile width of the scratch layout, <= TC
+  int tm;               // column-tile width of the scratch layout
+  int cpb;              // columns transformed per block (<= TC, divides tm)
   int nfields;
   TransferParams h;
   const cx<T>* tw;      // twiddles of length LY
@@ -225,6 +343,7 @@ struct RowInvArgs {
   double* row_partial;  // per (field, row) loss partial sums
   // backward: element adjoint and parameter gradients
   int backward;
+  int fpb;                // forward: fields per block (backward: all fields of the chunk)
   ElementParams<T> el;
   const cx<T>* saved_in;  // forward input of the layer
   T* grad_phase;          // [ny][nx], accumulated
@@ -238,95 +357,180 @@ struct RowInvArgs {
 template <typename T, int L, int R, int G, bool HALF, int NC>
 __global__ void __launch_bounds__(G * (L / R)) row_fwd_kernel(RowFwdArgs<T> a) {
   constexpr int TT = L / R;
-  __shared__ cx<T> lds[G * L];
+  __shared__ cx<T> lds[G * lds_len<1>(L)];
+  constexpr int RI = HALF ? R / 2 : R;  // registers that can hold a sample x < nx
   const int g = threadIdx.x / TT;
   const int j = threadIdx.x % TT;
-  const int y = blockIdx.x * G + g;
-  const int f = blockIdx.y;
-  const bool active = (y < a.ny) && (f < a.nfields);
+  const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
+  const bool rowok = y < a.ny;
   const int ny = a.ny, nx = a.nx;
+  const int f0 = blockIdx.y * a.fpb;
+  const int f1 = min(f0 + a.fpb, a.nfields);
+  const int tcm = (1 << a.tc_shift) - 1;
 
-  cx<T> v[NC][R];
+  // Scalar modulation of this thread's pixels, shared by every field.
+  const bool scalar_el = (a.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) != 0;
+  cx<T> mod[RI];
 #pragma unroll
-  for (int m = 0; m < R; ++m) {
+  for (int m = 0; m < RI; ++m) {
     const int x = j + m * TT;
-    const bool inside = active && x < nx && (!HALF || m < R / 2);
+    mod[m] = {T(1), T(0)};
+    if (scalar_el && rowok && x < nx) mod[m] = scalar_modulation(a.el, ny, nx, y, x);
+    // one pixel at a time: interleaving the sincos chains only costs registers
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // Loads of one field's row samples (zero outside the field).
+  auto load_row = [&](int f, int jv, int yv, cx<T> (&dst)[NC][RI]) {
+    const cx<T>* in_f = a.in + (int64_t)f * a.in_stride;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      cx<T> val = {T(0), T(0)};
-      if (inside) val = a.in[f * a.in_stride + c * a.comp_stride + (int64_t)y * nx + x];
-      v[c][m] = val;
+    for (int m = 0; m < RI; ++m) {
+      const int xv = jv + m * TT;
+      const bool inside = rowok && xv < nx;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        cx<T> val = {T(0), T(0)};
+        if (inside) val = in_f[(uint32_t)(c * a.comp_stride + yv * nx + xv)];
+        dst[c][m] = val;
+      }
     }
-    if (inside && a.el.flags) {
-      if constexpr (NC == 3) {
-        if (a.el.flags & EL_JONES) {
-          cx<T> o[3];
+  };
+  // Software pipeline over the block's fields: the next field's loads are
+  // issued before the current field's transform, so their latency overlaps
+  // the FFT passes.
+  cx<T> cur[NC][RI];
+  if (f0 < f1) load_row(f0, j, y, cur);
+
+#pragma unroll 1
+  for (int f = f0; f < f1; ++f) {
+    // Opaque copies of the thread's indices: the addresses below are then
+    // recomputed per field instead of being hoisted and kept live.
+    int jv = j, yv = y;
+    asm volatile("" : "+v"(jv), "+v"(yv));
+    cx<T> nxt[NC][RI];
+    if (f + 1 < f1) {
+      load_row(f + 1, jv, yv, nxt);
+    } else {
 #pragma unroll
-          for (int r = 0; r < 3; ++r) {
-            o[r] = cmul(a.el.jones[3 * r + 0], v[0][m]);
-            o[r] = cadd(o[r], cmul(a.el.jones[3 * r + 1], v[1][m]));
-            o[r] = cadd(o[r], cmul(a.el.jones[3 * r + 2], v[2][m]));
+      for (int m = 0; m < RI; ++m)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) nxt[c][m] = {T(0), T(0)};
+    }
+    cx<T> v[NC][R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c][m] = m < RI ? cur[c][m] : cx<T>{T(0), T(0)};
+      if (m < RI) {
+        if constexpr (NC == 3) {
+          if (a.el.flags & EL_JONES) {
+            cx<T> o[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+              o[r] = cmul(a.el.jones[3 * r + 0], v[0][m]);
+              o[r] = cadd(o[r], cmul(a.el.jones[3 * r + 1], v[1][m]));
+              o[r] = cadd(o[r], cmul(a.el.jones[3 * r + 2], v[2][m]));
+            }
+#pragma unroll
+            for (int r = 0; r < 3; ++r) v[r][m] = o[r];
           }
+        }
+        if (scalar_el) {
 #pragma unroll
-          for (int r = 0; r < 3; ++r) v[r][m] = o[r];
+          for (int c = 0; c < NC; ++c) v[c][m] = cmul(mod[m], v[c][m]);
         }
       }
-      if (a.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) {
-        const cx<T> mod = scalar_modulation(a.el, ny, nx, y, x);
+    }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) v[c][m] = cmul(mod, v[c][m]);
+    for (int c = 0; c < NC; ++c) {
+      fft_wg<T, L, R, -1, HALF, 1>(v[c], jv, lds + g * lds_len<1>(L), a.tw);
+      if (rowok) {
+        cx<T>* dst = a.scratch + (int64_t)(f * NC + c) * a.s_stride;
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+          const int kx = jv + m * TT;
+          dst[(uint32_t)((((kx >> a.tc_shift) * ny + yv) << a.tc_shift) + (kx & tcm))] = v[c][m];
+        }
       }
     }
-  }
-  const int tcm = (1 << a.tc_shift) - 1;
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    fft_wg<T, L, R, -1, HALF, 1>(v[c], j, lds + g * L, a.tw);
-    if (active) {
-      cx<T>* dst = a.scratch + (int64_t)(f * NC + c) * a.s_stride;
+    for (int m = 0; m < RI; ++m)
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const int kx = j + m * TT;
-        dst[((int64_t)(kx >> a.tc_shift) * ny + y) * (tcm + 1) + (kx & tcm)] = v[c][m];
-      }
-    }
+      for (int c = 0; c < NC; ++c) cur[c][m] = nxt[c][m];
   }
 }
 
 // ---------------------------------------------------------------------------
 // col: forward FFT along y, transfer function, inverse FFT, crop rows.
 // ---------------------------------------------------------------------------
+// Waves per SIMD that fit on a CU given a workgroup's LDS footprint (160 KiB
+// of LDS per CU, 4 SIMDs): the register budget the compiler may assume.
+constexpr int waves_per_simd(int threads, int lds_bytes) {
+  const int wg = lds_bytes > 0 ? 163840 / lds_bytes : 8;
+  const int w = (wg < 1 ? 1 : wg) * threads / 256;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 template <typename T, int L, int R, int TC, bool HALF>
-__global__ void __launch_bounds__(TC * (L / R)) col_kernel(ColArgs<T> a) {
+__global__ void __launch_bounds__(TC * (L / R))
+    __attribute__((amdgpu_waves_per_eu(1, waves_per_simd(TC * (L / R), lds_len<TC>(L) * TC * (int)sizeof(cx<T>)))))
+    col_kernel(ColArgs<T> a) {
   constexpr int TT = L / R;
-  __shared__ cx<T> lds[L * TC];
+  __shared__ cx<T> lds[lds_len<TC>(L) * TC];
   const int c = threadIdx.x % TC;
   const int j = threadIdx.x / TC;
-  const int tile = blockIdx.x;
+  // The scratch layout stores column tiles `tm` bins wide (a full cache line
+  // per row segment); a block transforms `cpb` (<= TC) of them.  Blocks that
+  // share a tile get consecutive logical indices, hence the same XCD and L2.
+  const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int tm = a.tm, cpb = a.cpb;
+  const int per = tm / cpb;
+  const int tile = lb / per, h = lb - tile * per;
   const int f = blockIdx.y;
   const int ny = a.ny;
-  const int tcl = a.tcl;  // tile width of the scratch layout (<= TC when the rows are short)
-  cx<T>* base = a.scratch + (int64_t)f * a.s_stride + (int64_t)tile * ny * tcl;
-  const bool active = f < a.nfields && c < tcl;
+  cx<T>* base = a.scratch + (int64_t)f * a.s_stride + (int64_t)tile * ny * tm + h * cpb;
+  const bool active = f < a.nfields && c < cpb;
 
   cx<T> v[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     const int y = j + m * TT;
     cx<T> val = {T(0), T(0)};
-    if (active && y < ny && (!HALF || m < R / 2)) val = base[(int64_t)y * tcl + c];
+    if (active && y < ny && (!HALF || m < R / 2)) val = base[(uint32_t)(y * tm + c)];
     v[m] = val;
   }
   fft_wg<T, L, R, -1, HALF, TC>(v, j, lds + c, a.tw);
-  const int kx = tile * tcl + c;
+  const int kx = tile * tm + h * cpb + c;
+  bool done = false;
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.h.fast) {
+      const int kxc = kx < a.lx ? kx : 0;
+      const cx<float> exk = a.h.ex[kxc];
+      const float sxk = a.h.sx[kxc];
+      const float lam_fy_unit = (float)(sqrt(a.h.lam2) * a.h.inv_lydy);
 #pragma unroll
-  for (int m = 0; m < R; ++m) v[m] = cmul(v[m], transfer_at<T>(kx, j + m * TT, a.lx, L, a.h));
-  fft_wg<T, L, R, +1, false, TC>(v, j, lds + c, a.tw);
+      for (int m = 0; m < R; ++m) {
+        v[m] = cmul(v[m], transfer_fast(exk, sxk, j + m * TT, L, lam_fy_unit, a.h));
+        // keep the table loads of a group of four close to their use
+        if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+      done = true;
+    }
+  }
+  if (!done) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = cmul(v[m], transfer_at<T>(kx, j + m * TT, a.lx, L, a.h));
+  }
+  // Opaque copy of j: the inverse transform reloads its twiddles instead of
+  // keeping the forward transform's (same addresses) live across the multiply.
+  int j2 = j;
+  asm volatile("" : "+v"(j2));
+  fft_wg<T, L, R, +1, false, TC>(v, j2, lds + c, a.tw);
   if (active) {
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int y = j + m * TT;
-      if ((!HALF || m < R / 2) && y < ny) base[(int64_t)y * tcl + c] = v[m];
+      if ((!HALF || m < R / 2) && y < ny) base[(uint32_t)(y * tm + c)] = v[m];
     }
   }
 }
@@ -372,78 +576,112 @@ __device__ __forceinline__ double group_sum(double v, double* red) {
 //     Fields are looped inside the block so each pixel's gradient is summed
 //     by one thread in a fixed order.
 // ---------------------------------------------------------------------------
-template <typename T, int L, int R, int G, bool HALF, int NC>
+template <typename T, int L, int R, int G, bool HALF, int NC, bool BWD>
 __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
+  constexpr bool kBwd = BWD;
   constexpr int TT = L / R;
   constexpr int NT = G * TT;
   constexpr int RO = HALF ? R / 2 : R;  // output registers that can hold x < nx
-  __shared__ cx<T> lds[G * L];
+  __shared__ cx<T> lds[G * lds_len<1>(L)];
   __shared__ double red[NT];
   const int g = threadIdx.x / TT;
   const int j = threadIdx.x % TT;
-  const int y = blockIdx.x * G + g;
+  const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
   const int ny = a.ny, nx = a.nx;
   const bool rowok = y < ny;
   const int tcm = (1 << a.tc_shift) - 1;
-  const bool loop_fields = a.backward != 0;
-  const int f_begin = loop_fields ? 0 : blockIdx.y;
-  const int f_end = loop_fields ? a.nfields : min((int)blockIdx.y + 1, a.nfields);
+  // Backward: one block owns its rows' parameter gradients, so it loops over
+  // every field of the chunk; forward: `fpb` fields per block.
+  const int f_begin = kBwd ? 0 : (int)blockIdx.y * a.fpb;
+  const int f_end = kBwd ? a.nfields : min(f_begin + a.fpb, a.nfields);
+  // Gather of one field's scratch row (tile layout).
+  auto load_row = [&](int f, int jv, int yv, int c, cx<T> (&dst)[R]) {
+    const cx<T>* src = a.scratch + (int64_t)(f * NC + c) * a.s_stride;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int kx = jv + m * TT;
+      cx<T> val = {T(0), T(0)};
+      if (rowok) val = src[(uint32_t)((((kx >> a.tc_shift) * ny + yv) << a.tc_shift) + (kx & tcm))];
+      dst[m] = val;
+    }
+  };
+  // Scalar rows are software-pipelined: the next field's row is loaded
+  // while the current one is transformed.
+  constexpr bool kPipe = NC == 1;
+  cx<T> pre[R];
+  if (kPipe && f_begin < f_end) load_row(f_begin, j, y, 0, pre);
 
   T gphase[RO];
+  cx<T> modr[RO];  // backward: scalar modulation of this thread's pixels (all fields)
+  double dpsi[RO];  // backward: d(lens phase)/df of this thread's pixels
 #pragma unroll
-  for (int m = 0; m < RO; ++m) gphase[m] = T(0);
+  for (int m = 0; m < RO; ++m) {
+    gphase[m] = T(0);
+    modr[m] = {T(1), T(0)};
+    dpsi[m] = 0.0;
+    const int x = j + m * TT;
+    if (kBwd && rowok && x < nx) {
+      if (a.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) modr[m] = scalar_modulation(a.el, ny, nx, y, x);
+      if (a.el.flags & EL_LENS) dpsi[m] = lens_dphase_df(a.el, ny, nx, y, x, a.lens_f);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
   double lens_acc = 0.0;
 
-  for (int f = f_begin; f < (loop_fields ? f_end : f_begin + 1); ++f) {
-    const bool active = rowok && f < f_end;
+#pragma unroll 1
+  for (int f = f_begin; f < f_end; ++f) {
+    const bool active = rowok;
+    // Opaque copies of the thread's indices (see row_fwd_kernel).
+    int jv = j, yv = y;
+    asm volatile("" : "+v"(jv), "+v"(yv));
     cx<T> v[NC][R];
+    if constexpr (kPipe) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const cx<T>* src = a.scratch + (int64_t)(f * NC + c) * a.s_stride;
+      for (int m = 0; m < R; ++m) v[0][m] = pre[m];
+      if (f + 1 < f_end) load_row(f + 1, jv, yv, 0, pre);
+      fft_wg<T, L, R, +1, false, 1>(v[0], jv, lds + g * lds_len<1>(L), a.tw);
+    } else {
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const int kx = j + m * TT;
-        cx<T> val = {T(0), T(0)};
-        if (active) val = src[((int64_t)(kx >> a.tc_shift) * ny + y) * (tcm + 1) + (kx & tcm)];
-        v[c][m] = val;
+      for (int c = 0; c < NC; ++c) {
+        load_row(f, jv, yv, c, v[c]);
+        fft_wg<T, L, R, +1, false, 1>(v[c], jv, lds + g * lds_len<1>(L), a.tw);
       }
-      fft_wg<T, L, R, +1, false, 1>(v[c], j, lds + g * L, a.tw);
     }
     double loss_acc = 0.0;
     if (active) {
 #pragma unroll
       for (int m = 0; m < RO; ++m) {
-        const int x = j + m * TT;
+        const int x = jv + m * TT;
         if (x >= nx) continue;
-        const int64_t pix = (int64_t)y * nx + x;
+        const uint32_t pix = (uint32_t)(yv * nx + x);
+        const int64_t fbase = (int64_t)f * a.out_stride;
 #pragma unroll
         for (int c = 0; c < NC; ++c) v[c][m] = cscale(v[c][m], a.scale);
-        if (!a.backward) {
+        if constexpr (!kBwd) {
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            const int64_t o = f * a.out_stride + c * a.comp_stride + pix;
-            a.out[o] = v[c][m];
+            const uint32_t o = (uint32_t)(c * a.comp_stride) + pix;
+            a.out[fbase + o] = v[c][m];
             if (a.epi == EPI_MSE) {
               const T I = v[c][m].x * v[c][m].x + v[c][m].y * v[c][m].y;
               const T d = I - a.epi_ref[pix];
               loss_acc += (double)d * (double)d;
-              a.epi_grad[o] = cscale(v[c][m], T(4) * a.epi_scale * d);
+              a.epi_grad[fbase + o] = cscale(v[c][m], T(4) * a.epi_scale * d);
             } else if (a.epi == EPI_WEIGHTED) {
               const T I = v[c][m].x * v[c][m].x + v[c][m].y * v[c][m].y;
               const T w = a.epi_ref[pix];
               loss_acc += (double)w * (double)I;
-              a.epi_grad[o] = cscale(v[c][m], T(2) * a.epi_scale * w);
+              a.epi_grad[fbase + o] = cscale(v[c][m], T(2) * a.epi_scale * w);
             }
           }
         } else {
           // g_mod is v; the modulated forward field is M u_in.
-          cx<T> mod = {T(1), T(0)};
+          const cx<T> mod = modr[m];
           const uint32_t fl = a.el.flags;
-          if (fl & (EL_PHASE | EL_COMPLEX | EL_LENS)) mod = scalar_modulation(a.el, ny, nx, y, x);
           if ((fl & (EL_PHASE | EL_LENS)) && a.saved_in) {
             cx<T> u[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) u[c] = a.saved_in[f * a.out_stride + c * a.comp_stride + pix];
+            for (int c = 0; c < NC; ++c) u[c] = a.saved_in[fbase + (uint32_t)(c * a.comp_stride) + pix];
             if constexpr (NC == 3) {
               if (fl & EL_JONES) {
                 cx<T> o[3];
@@ -464,7 +702,7 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
               im += v[c][m].y * um.x - v[c][m].x * um.y;  // Im(g conj(um))
             }
             if (fl & EL_PHASE) gphase[m] += im;
-            if (fl & EL_LENS) lens_acc += (double)im * lens_dphase_df(a.el, ny, nx, y, x, a.lens_f);
+            if (fl & EL_LENS) lens_acc += (double)im * dpsi[m];
           }
           if (a.out) {
             cx<T> gi[NC];
@@ -484,17 +722,17 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
               }
             }
 #pragma unroll
-            for (int c = 0; c < NC; ++c) a.out[f * a.out_stride + c * a.comp_stride + pix] = gi[c];
+            for (int c = 0; c < NC; ++c) a.out[fbase + (uint32_t)(c * a.comp_stride) + pix] = gi[c];
           }
         }
       }
     }
-    if (!a.backward && a.epi != EPI_NONE) {
+    if (!kBwd && a.epi != EPI_NONE) {
       const double s = group_sum<TT, G>(loss_acc, red);
       if (active && j == 0) a.row_partial[(int64_t)f * ny + y] = s;
     }
   }
-  if (a.backward) {
+  if constexpr (kBwd) {
     if (rowok && (a.el.flags & EL_PHASE) && a.grad_phase && a.saved_in) {
 #pragma unroll
       for (int m = 0; m < RO; ++m) {

@@ -21,27 +21,32 @@ struct RowCfg {
 };
 
 // Column pass: R points per thread, TC columns per workgroup, sized so that
-// the LDS exchange buffer (L * TC complex values) stays within 128 KiB.
-template <typename T, int L>
+// the LDS exchange buffer (L * TC complex values) stays within the variant's
+// budget: V = 0: 128 KiB, R = 16; V = 1: 64 KiB, R = 16 (two workgroups per
+// CU); V = 2: 64 KiB, R = 8.
+constexpr int kColVariants = 3;
+template <typename T, int L, int V = 0>
 struct ColCfg {
-  static constexpr int R = L <= 16 ? L : (L <= 256 ? 8 : 16);
+  static constexpr int R = L <= 16 ? L : (L <= 256 ? 8 : (V == 2 ? 8 : 16));
   static constexpr int TT = L / R;
-  static constexpr int lds_elems = (int)(131072 / sizeof(cx<T>));
+  static constexpr int lds_elems = (int)((V == 0 ? 131072 : 65536) / sizeof(cx<T>));
   static constexpr int tc0 = lds_elems / L > 16 ? 16 : lds_elems / L;
   static constexpr int tc1 = tc0 < 1 ? 1 : tc0;
   static constexpr int TC = tc1 * TT > 1024 ? 1024 / TT : tc1;
   static constexpr int threads = TC * TT;
 };
 
-// Column-tile width for a given column length (runtime query).
-int col_tile_width(int ly, bool is_double);
+// Column-tile width for a given column length and variant (runtime query).
+int col_tile_width(int ly, bool is_double, int variant);
+// Rows per workgroup of the row passes for a given row length.
+int row_rows_per_block(int lx);
 
 template <typename T>
 struct Launch {
   static hipError_t row_fwd(int lx, bool half, int nc, int ny, int nfields, const RowFwdArgs<T>& a,
                             hipStream_t s);
-  static hipError_t col(int ly, bool half, int ncols_tiles, int nfields, const ColArgs<T>& a,
-                        hipStream_t s);
+  static hipError_t col(int ly, bool half, int ncols_tiles, int nfields, int variant,
+                        const ColArgs<T>& a, hipStream_t s);
   static hipError_t row_inv(int lx, bool half, int nc, int ny, int nblocks_y,
                             const RowInvArgs<T>& a, hipStream_t s);
   static hipError_t modulate(int nc, const cx<T>* in, cx<T>* out, int64_t fstride, int64_t cstride,
@@ -51,5 +56,9 @@ struct Launch {
 
 hipError_t launch_reduce_add(const double* src, int64_t n, double scale, double* dst,
                              hipStream_t s);
+
+hipError_t launch_tf_tables(cx<float>* ex, float* sx, int lx, double inv_lxdx, cx<float>* ey,
+                            float* sy, int ly, double inv_lydy, double fres_a, double q_frac,
+                            double lam2, hipStream_t s);
 
 }  // namespace toprop

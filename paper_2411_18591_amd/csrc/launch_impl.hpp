@@ -30,7 +30,8 @@ hipError_t Launch<T>::row_fwd(int lx, bool half, int nc, int ny, int nfields, co
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
     using C = RowCfg<L>;
-    dim3 grid((ny + C::G - 1) / C::G, nfields);
+    const int fpb = a.fpb > 0 ? a.fpb : 1;
+    dim3 grid((ny + C::G - 1) / C::G, (nfields + fpb - 1) / fpb);
     dim3 block(C::threads);
     if (nc == 3) {
       if (half)
@@ -48,17 +49,25 @@ hipError_t Launch<T>::row_fwd(int lx, bool half, int nc, int ny, int nfields, co
 }
 
 template <typename T>
-hipError_t Launch<T>::col(int ly, bool half, int ntiles, int nfields, const ColArgs<T>& a,
-                          hipStream_t s) {
+hipError_t Launch<T>::col(int ly, bool half, int ntiles, int nfields, int variant,
+                          const ColArgs<T>& a, hipStream_t s) {
   return dispatch_len(ly, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    using C = ColCfg<T, L>;
-    dim3 grid(ntiles, nfields);
-    dim3 block(C::threads);
-    if (half)
-      hipLaunchKernelGGL((col_kernel<T, L, C::R, C::TC, true>), grid, block, 0, s, a);
+    auto go = [&](auto vc) {
+      using C = ColCfg<T, L, decltype(vc)::value>;
+      dim3 grid(ntiles, nfields);
+      dim3 block(C::threads);
+      if (half)
+        hipLaunchKernelGGL((col_kernel<T, L, C::R, C::TC, true>), grid, block, 0, s, a);
+      else
+        hipLaunchKernelGGL((col_kernel<T, L, C::R, C::TC, false>), grid, block, 0, s, a);
+    };
+    if (variant == 1)
+      go(std::integral_constant<int, 1>());
+    else if (variant == 2)
+      go(std::integral_constant<int, 2>());
     else
-      hipLaunchKernelGGL((col_kernel<T, L, C::R, C::TC, false>), grid, block, 0, s, a);
+      go(std::integral_constant<int, 0>());
     return hipGetLastError();
   });
 }
@@ -71,17 +80,24 @@ hipError_t Launch<T>::row_inv(int lx, bool half, int nc, int ny, int nblocks_y,
     using C = RowCfg<L>;
     dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
     dim3 block(C::threads);
-    if (nc == 3) {
-      if (half)
-        hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 3>), grid, block, 0, s, a);
-      else
-        hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 3>), grid, block, 0, s, a);
-    } else {
-      if (half)
-        hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 1>), grid, block, 0, s, a);
-      else
-        hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 1>), grid, block, 0, s, a);
-    }
+    auto go = [&](auto bwd) {
+      constexpr bool B = decltype(bwd)::value;
+      if (nc == 3) {
+        if (half)
+          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 3, B>), grid, block, 0, s, a);
+        else
+          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 3, B>), grid, block, 0, s, a);
+      } else {
+        if (half)
+          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 1, B>), grid, block, 0, s, a);
+        else
+          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 1, B>), grid, block, 0, s, a);
+      }
+    };
+    if (a.backward)
+      go(std::true_type());
+    else
+      go(std::false_type());
     return hipGetLastError();
   });
 }
