@@ -44,7 +44,25 @@ def parse():
     p.add_argument("--cpu-sample-layers", type=int, default=2,
                    help="layers (of the workload's masks) in the CPU oracle sample")
     p.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    p.add_argument("--plain-steps", type=int, default=1,
+                   help="timed steps of the unfused plain form (0 = skip the comparison)")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a 256 MiB device copy (for scaling FETCH_SIZE / WRITE_SIZE)")
     return p.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of known size: 3 x 256 MiB."""
+    import torch
+    x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 256 * 1024 * 1024, "copies": 3}))
+    return 0
 
 
 def fft_flops(L: int) -> float:
@@ -81,6 +99,8 @@ def kernel_model(name: str, wl, chunk_fields: int):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is described in DESIGN.md, not built)"}))
@@ -123,18 +143,18 @@ def main():
     opt = tp.Optics(dy=wl_def.d, dx=wl_def.d, wavelength=wl_def.wavelength, z=wl_def.z, pad=2)
     n_total = B * N * N
 
-    def step():
+    def step(plain=False):
         gmask.zero_()
         loss.zero_()
         for l in range(L - 1):
-            tp.propagate(u[l], opt, out=u[l + 1], phase=masks[l])
+            tp.propagate(u[l], opt, out=u[l + 1], phase=masks[l], plain=plain)
         tp.propagate_loss(u[L - 1], opt, kind="mse", ref=target, scale=1.0 / n_total,
-                          out=u[L], grad=gbuf[0], loss=loss, phase=masks[L - 1])
+                          out=u[L], grad=gbuf[0], loss=loss, phase=masks[L - 1], plain=plain)
         g_cur = 0
         for l in range(L - 1, -1, -1):
             nxt = 1 - g_cur
             tp.propagate_backward(gbuf[g_cur], opt, saved_in=u[l], grad_phase=gmask[l],
-                                  phase=masks[l], want_grad_in=l > 0, grad_in=gbuf[nxt])
+                                  phase=masks[l], want_grad_in=l > 0, grad_in=gbuf[nxt], plain=plain)
             g_cur = nxt
 
     print("[bench] warmup", file=sys.stderr, flush=True)
@@ -205,6 +225,26 @@ def main():
                         "kernel": name, "avg_us": round(avg_s * 1e6, 2),
                         "alu_view": {"achieved_TFLOP_s": round(tfs, 3), "frac": round(f_a, 4)}}
 
+    # The same step through the unfused plain form (one field per launch
+    # sequence, every intermediate in HBM), timed the same way.
+    plain = None
+    if args.plain_steps > 0:
+        loss_fused = float(loss.item())
+        print("[bench] plain form", file=sys.stderr, flush=True)
+        step(plain=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.plain_steps):
+            step(plain=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        p_ms = ev0.elapsed_time(ev1) / args.plain_steps
+        plain = {"value": round(props / (p_ms / 1000.0), 1), "unit": "propagations/s",
+                 "ms_per_step": round(p_ms, 3), "steps": args.plain_steps,
+                 "hbm_roofline_frac": round(step_bytes / (p_ms / 1000.0) / (HBM_PEAK_GBS * 1e9), 5),
+                 "loss_rel_diff_vs_fused": abs(float(loss.item()) - loss_fused) / abs(loss_fused),
+                 "fused_speedup": round(p_ms / ms_step, 2)}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, wl_def, u0_np, masks_np, target_np)
@@ -229,6 +269,7 @@ def main():
             "propagations_per_step": props,
         },
         "hbm_roofline_step": {"algorithmic_bytes": step_bytes, "frac": round(hbm_frac_step, 4)},
+        "plain_form": plain,
         "roofline": roofline,
         "kernels": kernels_out,
         "wall_s": round(t_wall, 3),

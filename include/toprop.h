@@ -180,6 +180,18 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
 to_status to_coherence_propagate(const to_job* job, to_dtype dtype, int32_t adjoint,
                                  const to_grad* grad, void* stream);
 
+/* Unfused reference form of to_propagate / to_propagate_backward, kept as the
+ * comparison baseline for the fused kernels: each field goes through one
+ * kernel per step of Eq. (field_propagation_tf) — modulate, zero-pad into a
+ * full py x px array, row FFTs, column FFTs, multiply by a stored table of
+ * H, inverse FFTs, crop — with every intermediate in device memory.  Same
+ * arguments and results (to rounding) as the fused entry points; Jones
+ * elements and the lens focal-length gradient are not supported here
+ * (TO_E_UNSUPPORTED).  Workspace: two py x px and two ny x nx complex arrays. */
+to_status to_propagate_plain(const to_job* jobs, int32_t njobs, to_dtype dtype, void* stream);
+to_status to_propagate_backward_plain(const to_job* jobs, const to_grad* grads, int32_t njobs,
+                                      to_dtype dtype, void* stream);
+
 /* Description of the calling thread's last non-TO_OK status ("" if none).   */
 const char* to_last_error(void);
 

@@ -205,19 +205,20 @@ def make_job(u: torch.Tensor, opt: Optics, *, out: Optional[torch.Tensor] = None
 # ---------------------------------------------------------------------------
 
 def propagate(u: torch.Tensor, opt: Optics, *, out: Optional[torch.Tensor] = None, ncomp: int = 1,
-              **element) -> torch.Tensor:
+              plain: bool = False, **element) -> torch.Tensor:
     """out = P_z(M u): modulation by the element (phase=, cmask=, lens_f=,
     jones=) fused into the first pass, then zero-padded propagation."""
     if out is None:
         out = torch.empty_like(u)
     job = make_job(u, opt, out=out, ncomp=ncomp, **element)
-    _capi.propagate([job], _dtype_code(u), _stream(u))
+    _capi.propagate([job], _dtype_code(u), _stream(u), plain=plain)
     return out
 
 
 def propagate_loss(u: torch.Tensor, opt: Optics, *, kind: str, ref: torch.Tensor, scale: float,
                    out: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None,
-                   loss: Optional[torch.Tensor] = None, ncomp: int = 1, **element):
+                   loss: Optional[torch.Tensor] = None, ncomp: int = 1, plain: bool = False,
+                   **element):
     """Forward propagation with a fused intensity-loss epilogue ("mse" or
     "weighted").  Returns (out, dL/d(out), loss) where loss is a float64
     device scalar (accumulated into `loss` if given)."""
@@ -227,7 +228,7 @@ def propagate_loss(u: torch.Tensor, opt: Optics, *, kind: str, ref: torch.Tensor
     loss = torch.zeros((), dtype=torch.float64, device=u.device) if loss is None else loss
     job = make_job(u, opt, out=out, ncomp=ncomp, epi=epi, epi_ref=ref, epi_scale=scale,
                    epi_grad=grad, epi_loss=loss, **element)
-    _capi.propagate([job], _dtype_code(u), _stream(u))
+    _capi.propagate([job], _dtype_code(u), _stream(u), plain=plain)
     return out, grad, loss
 
 
@@ -244,7 +245,8 @@ def modulate(u: torch.Tensor, *, dy: float, dx: float, wavelength: float, y0: fl
 
 
 def propagate_backward(grad_out: torch.Tensor, opt: Optics, *, saved_in=None, want_grad_in=True,
-                       grad_in=None, grad_phase=None, grad_f=None, ncomp: int = 1, **element):
+                       grad_in=None, grad_phase=None, grad_f=None, ncomp: int = 1, plain: bool = False,
+                       **element):
     """Backward of :func:`propagate`: returns dL/d(in) (or None); element
     gradients are accumulated into grad_phase / grad_f (device tensors)."""
     job = make_job(grad_out, opt, ncomp=ncomp, **element)
@@ -264,7 +266,7 @@ def propagate_backward(grad_out: torch.Tensor, opt: Optics, *, saved_in=None, wa
                                   grad_out.shape[-2:]))
     if grad_f is not None:
         g.grad_f = _ptr(_need(grad_f, "grad_f", torch.float64, grad_out))
-    _capi.propagate_backward([job], [g], _dtype_code(grad_out), _stream(grad_out))
+    _capi.propagate_backward([job], [g], _dtype_code(grad_out), _stream(grad_out), plain=plain)
     return grad_in
 
 

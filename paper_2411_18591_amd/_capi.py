@@ -44,6 +44,8 @@ EXPORTED = (
     "to_profile_end",
     "to_profile_count",
     "to_profile_entry",
+    "to_propagate_plain",
+    "to_propagate_backward_plain",
 )
 
 
@@ -131,6 +133,10 @@ def lib() -> ctypes.CDLL:
         L.to_profile_entry.argtypes = [c_int, ctypes.c_char_p, c_int, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)]
         L.to_profile_entry.restype = c_int
+        L.to_propagate_plain.argtypes = [JP, c_int, c_int, ctypes.c_void_p]
+        L.to_propagate_plain.restype = c_int
+        L.to_propagate_backward_plain.argtypes = [JP, GP, c_int, c_int, ctypes.c_void_p]
+        L.to_propagate_backward_plain.restype = c_int
         _lib = L
     return _lib
 
@@ -149,9 +155,10 @@ def grads_array(grads):
     return (Grad * len(grads))(*grads)
 
 
-def propagate(jobs, dtype: int, stream: int) -> None:
+def propagate(jobs, dtype: int, stream: int, plain: bool = False) -> None:
     arr = jobs_array(jobs)
-    check(lib().to_propagate(arr, len(jobs), dtype, ctypes.c_void_p(stream)))
+    fn = lib().to_propagate_plain if plain else lib().to_propagate
+    check(fn(arr, len(jobs), dtype, ctypes.c_void_p(stream)))
 
 
 def modulate(jobs, dtype: int, adjoint: bool, stream: int) -> None:
@@ -159,9 +166,9 @@ def modulate(jobs, dtype: int, adjoint: bool, stream: int) -> None:
     check(lib().to_modulate(arr, len(jobs), dtype, 1 if adjoint else 0, ctypes.c_void_p(stream)))
 
 
-def propagate_backward(jobs, grads, dtype: int, stream: int) -> None:
-    check(lib().to_propagate_backward(jobs_array(jobs), grads_array(grads), len(jobs), dtype,
-                                      ctypes.c_void_p(stream)))
+def propagate_backward(jobs, grads, dtype: int, stream: int, plain: bool = False) -> None:
+    fn = lib().to_propagate_backward_plain if plain else lib().to_propagate_backward
+    check(fn(jobs_array(jobs), grads_array(grads), len(jobs), dtype, ctypes.c_void_p(stream)))
 
 
 def coherence_propagate(job, dtype: int, adjoint: bool, grad, stream: int) -> None:

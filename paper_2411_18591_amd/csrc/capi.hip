@@ -14,6 +14,7 @@
 
 #include "../../include/toprop.h"
 #include "launch.hpp"
+#include "plain.hpp"
 
 using namespace toprop;
 
@@ -71,6 +72,8 @@ struct DeviceCtx {
   void* tf = nullptr;
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
+  void* plain = nullptr;  // workspace of the unfused baseline
+  size_t plain_bytes = 0;
   double* partial = nullptr;
   size_t partial_count = 0;
 };
@@ -121,6 +124,21 @@ to_status ensure_scratch(DeviceCtx* c, size_t bytes) {
     return fail(TO_E_NOMEM, "scratch allocation of %zu bytes failed: %s", bytes,
                 hipGetErrorString(e));
   c->scratch_bytes = bytes;
+  return TO_OK;
+}
+
+to_status ensure_plain(DeviceCtx* c, size_t bytes) {
+  if (c->plain_bytes >= bytes) return TO_OK;
+  hipError_t e;
+  if (c->plain) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    hipFree(c->plain);
+    c->plain = nullptr;
+    c->plain_bytes = 0;
+  }
+  if ((e = hipMalloc(&c->plain, bytes)) != hipSuccess)
+    return fail(TO_E_NOMEM, "workspace allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  c->plain_bytes = bytes;
   return TO_OK;
 }
 
@@ -617,9 +635,168 @@ to_status run_modulate(const to_job& j, int adjoint, hipStream_t s) {
   return TO_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Plain (unfused) form: one field at a time, one kernel per pipeline step.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PlainWork {
+  cx<T>* H;
+  cx<T>* pad;
+  cx<T>* tmp;
+  cx<T>* tmp2;
+  double* partial;
+};
+
+template <typename T>
+to_status plain_setup(const to_job& j, DeviceCtx* c, bool conj, hipStream_t s, PlainWork<T>* w) {
+  const size_t npad = (size_t)j.py * j.px, nf = (size_t)j.ny * j.nx;
+  const size_t bytes = (2 * npad + 2 * nf) * sizeof(cx<T>) + 1024 * sizeof(double);
+  to_status st = ensure_plain(c, bytes);
+  if (st != TO_OK) return st;
+  w->H = (cx<T>*)c->plain;
+  w->pad = w->H + npad;
+  w->tmp = w->pad + npad;
+  w->tmp2 = w->tmp + nf;
+  w->partial = (double*)(w->tmp2 + nf);
+  TransferParams h = make_transfer(j, conj);
+  h.conj = 0;  // the table holds H; the multiply kernel conjugates
+  hipError_t e = timed("plain.table", j.px, sizeof(T) == 8, s,
+                       [&] { return Plain<T>::table(w->H, j.py, j.px, h, s); });
+  if (e != hipSuccess) return hip_fail(e, "plain table launch");
+  return TO_OK;
+}
+
+template <typename T>
+to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
+  if (j.batch == 0) return TO_OK;
+  if (j.el_flags & TO_EL_JONES) return fail(TO_E_UNSUPPORTED, "the plain form has no Jones elements");
+  PlainWork<T> w;
+  to_status st = plain_setup<T>(j, c, false, s, &w);
+  if (st != TO_OK) return st;
+  const int64_t nf = (int64_t)j.ny * j.nx;
+  const int64_t fields = j.batch * j.ncomp;
+  const bool dbl = sizeof(T) == 8;
+  for (int64_t b = 0; b < fields; ++b) {
+    PlainJob<T> pj;
+    pj.ny = j.ny;
+    pj.nx = j.nx;
+    pj.py = j.py;
+    pj.px = j.px;
+    pj.in = (const cx<T>*)j.in + b * nf;
+    pj.out = (cx<T>*)j.out + b * nf;
+    pj.tmp = w.tmp;
+    pj.pad = w.pad;
+    pj.H = w.H;
+    pj.conj = 0;
+    pj.el = make_element<T>(j, j.el_flags);
+    pj.tw_x = twiddles<T>(c, j.px);
+    pj.tw_y = twiddles<T>(c, j.py);
+    hipError_t e = timed("plain.propagate", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
+    if (e != hipSuccess) return hip_fail(e, "plain propagation");
+    if (j.epi != TO_EPI_NONE) {
+      int nb = 0;
+      e = Plain<T>::loss(pj.out, (const T*)j.epi_ref, (cx<T>*)j.epi_grad + b * nf, w.partial, nf, j.epi,
+                         (T)j.epi_scale, &nb, s);
+      if (e != hipSuccess) return hip_fail(e, "plain loss");
+      if ((e = launch_reduce_add(w.partial, nb, j.epi_scale, j.epi_loss, s)) != hipSuccess)
+        return hip_fail(e, "plain loss reduction");
+    }
+  }
+  return TO_OK;
+}
+
+template <typename T>
+to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStream_t s) {
+  if (j.batch == 0) return TO_OK;
+  if (j.el_flags & TO_EL_JONES) return fail(TO_E_UNSUPPORTED, "the plain form has no Jones elements");
+  if (gr.grad_f) return fail(TO_E_UNSUPPORTED, "the plain form has no lens gradient");
+  PlainWork<T> w;
+  to_status st = plain_setup<T>(j, c, true, s, &w);
+  if (st != TO_OK) return st;
+  const int64_t nf = (int64_t)j.ny * j.nx;
+  const int64_t fields = j.batch * j.ncomp;
+  const bool dbl = sizeof(T) == 8;
+  const ElementParams<T> el = make_element<T>(j, j.el_flags);
+  for (int64_t b = 0; b < fields; ++b) {
+    PlainJob<T> pj;
+    pj.ny = j.ny;
+    pj.nx = j.nx;
+    pj.py = j.py;
+    pj.px = j.px;
+    pj.in = (const cx<T>*)gr.grad_out + b * nf;
+    pj.out = w.tmp2;  // g_mod = P^H grad_out
+    pj.tmp = w.tmp;
+    pj.pad = w.pad;
+    pj.H = w.H;
+    pj.conj = 1;
+    pj.el = make_element<T>(j, 0);
+    pj.tw_x = twiddles<T>(c, j.px);
+    pj.tw_y = twiddles<T>(c, j.py);
+    hipError_t e = timed("plain.adjoint", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
+    if (e != hipSuccess) return hip_fail(e, "plain adjoint");
+    if (gr.grad_phase && (j.el_flags & TO_EL_PHASE) && gr.saved_in) {
+      e = Plain<T>::phase_grad(w.tmp2, (const cx<T>*)gr.saved_in + b * nf, (T*)gr.grad_phase, j.ny, j.nx,
+                               el, s);
+      if (e != hipSuccess) return hip_fail(e, "plain phase gradient");
+    }
+    if (gr.grad_in) {
+      if (j.el_flags & (TO_EL_PHASE | TO_EL_COMPLEX | TO_EL_LENS))
+        e = Plain<T>::modulate(w.tmp2, (cx<T>*)gr.grad_in + b * nf, j.ny, j.nx, el, 1, s);
+      else
+        e = hipMemcpyAsync((cx<T>*)gr.grad_in + b * nf, w.tmp2, nf * sizeof(cx<T>),
+                           hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return hip_fail(e, "plain input gradient");
+    }
+  }
+  return TO_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+to_status to_propagate_plain(const to_job* jobs, int32_t njobs, to_dtype dtype, void* stream) {
+  if (njobs < 0) return fail(TO_E_INVAL, "njobs < 0");
+  if (njobs > 0 && !jobs) return fail(TO_E_INVAL, "jobs is NULL");
+  for (int i = 0; i < njobs; ++i) {
+    to_status st = validate(jobs[i], i, dtype, MODE_FWD);
+    if (st != TO_OK) return st;
+  }
+  if (njobs == 0) return TO_OK;
+  DeviceCtx* c;
+  to_status st = get_ctx(&c);
+  if (st != TO_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < njobs; ++i) {
+    st = dtype == TO_C64 ? run_forward_plain<float>(jobs[i], c, s) : run_forward_plain<double>(jobs[i], c, s);
+    if (st != TO_OK) return st;
+  }
+  return TO_OK;
+}
+
+to_status to_propagate_backward_plain(const to_job* jobs, const to_grad* grads, int32_t njobs,
+                                      to_dtype dtype, void* stream) {
+  if (njobs < 0) return fail(TO_E_INVAL, "njobs < 0");
+  if (njobs > 0 && (!jobs || !grads)) return fail(TO_E_INVAL, "jobs or grads is NULL");
+  for (int i = 0; i < njobs; ++i) {
+    to_status st = validate(jobs[i], i, dtype, MODE_BWD);
+    if (st != TO_OK) return st;
+    if (jobs[i].batch > 0 && !grads[i].grad_out) return fail(TO_E_INVAL, "job %d: grad_out is NULL", i);
+    if (jobs[i].batch > 0 && grads[i].grad_phase && (jobs[i].el_flags & TO_EL_PHASE) && !grads[i].saved_in)
+      return fail(TO_E_INVAL, "job %d: a parameter gradient needs saved_in", i);
+  }
+  if (njobs == 0) return TO_OK;
+  DeviceCtx* c;
+  to_status st = get_ctx(&c);
+  if (st != TO_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < njobs; ++i) {
+    st = dtype == TO_C64 ? run_backward_plain<float>(jobs[i], grads[i], c, s)
+                         : run_backward_plain<double>(jobs[i], grads[i], c, s);
+    if (st != TO_OK) return st;
+  }
+  return TO_OK;
+}
 
 to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* stream) {
   if (njobs < 0) return fail(TO_E_INVAL, "njobs < 0");
@@ -714,6 +891,8 @@ to_status to_release(void) {
     if (c.tw64) hipFree(c.tw64);
     if (c.scratch) hipFree(c.scratch);
     if (c.partial) hipFree(c.partial);
+    if (c.plain) hipFree(c.plain);
+    if (c.tf) hipFree(c.tf);
     c = DeviceCtx();
   }
   hipSetDevice(cur);

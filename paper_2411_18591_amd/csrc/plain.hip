@@ -1,0 +1,257 @@
+// Plain (unfused) form of the propagation, the comparison baseline for the
+// fused kernels: one field per launch sequence and one kernel per step of
+// the pipeline of Eq. (field_propagation_tf) — modulate, zero-pad into a
+// full py x px array, row FFTs, column FFTs, multiply by a stored transfer
+// function table, inverse column and row FFTs, crop and scale.  Every
+// intermediate is a full array in HBM.  The FFT building blocks are the same
+// Stockham register/LDS transforms as the fused path; only the fusion and the
+// batching are absent.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "../../include/toprop.h"
+#include "launch_impl.hpp"
+#include "plain.hpp"
+
+namespace toprop {
+
+template <typename T>
+__global__ void __launch_bounds__(256) plain_modulate_kernel(const cx<T>* in, cx<T>* out, int ny, int nx,
+                                                             ElementParams<T> el, int conj) {
+  const int64_t n = (int64_t)ny * nx;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / nx), x = (int)(i % nx);
+    cx<T> m = scalar_modulation(el, ny, nx, y, x);
+    if (conj) m.y = -m.y;
+    out[i] = cmul(m, in[i]);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) plain_pad_kernel(const cx<T>* in, cx<T>* pad, int ny, int nx, int py,
+                                                        int px) {
+  const int64_t n = (int64_t)py * px;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / px), x = (int)(i % px);
+    pad[i] = (y < ny && x < nx) ? in[(int64_t)y * nx + x] : cx<T>{T(0), T(0)};
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) plain_crop_kernel(const cx<T>* pad, cx<T>* out, int ny, int nx, int px,
+                                                         T scale) {
+  const int64_t n = (int64_t)ny * nx;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / nx), x = (int)(i % nx);
+    out[i] = cscale(pad[(int64_t)y * px + x], scale);
+  }
+}
+
+// Transfer function of every bin of the padded grid, stored as a table.
+template <typename T>
+__global__ void __launch_bounds__(256) plain_table_kernel(cx<T>* H, int py, int px, TransferParams p) {
+  const int64_t n = (int64_t)py * px;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int ky = (int)(i / px), kx = (int)(i % px);
+    H[i] = transfer_at<T>(kx, ky, px, py, p);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) plain_mul_kernel(cx<T>* a, const cx<T>* H, int64_t n, int conj) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    cx<T> h = H[i];
+    if (conj) h.y = -h.y;
+    a[i] = cmul(a[i], h);
+  }
+}
+
+// In-place FFTs of `rows` contiguous rows of length L.
+template <typename T, int L, int R, int G, int D>
+__global__ void __launch_bounds__(G * (L / R)) plain_row_fft_kernel(cx<T>* a, int rows, const cx<T>* tw) {
+  constexpr int TT = L / R;
+  __shared__ cx<T> lds[G * lds_len<1>(L)];
+  const int g = threadIdx.x / TT, j = threadIdx.x % TT;
+  const int row = blockIdx.x * G + g;
+  const bool ok = row < rows;
+  cx<T>* p = a + (int64_t)(ok ? row : 0) * L;
+  cx<T> v[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = ok ? p[j + m * TT] : cx<T>{T(0), T(0)};
+  fft_wg<T, L, R, D, false, 1>(v, j, lds + g * lds_len<1>(L), tw);
+  if (ok) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) p[j + m * TT] = v[m];
+  }
+}
+
+// In-place FFTs of the columns of a row-major [L][lx] array, TC columns per
+// block.
+template <typename T, int L, int R, int TC, int D>
+__global__ void __launch_bounds__(TC * (L / R)) plain_col_fft_kernel(cx<T>* a, int lx, const cx<T>* tw) {
+  constexpr int TT = L / R;
+  __shared__ cx<T> lds[lds_len<TC>(L) * TC];
+  const int c = threadIdx.x % TC, j = threadIdx.x / TC;
+  const int col = blockIdx.x * TC + c;
+  const bool ok = col < lx;
+  cx<T> v[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = ok ? a[(int64_t)(j + m * TT) * lx + col] : cx<T>{T(0), T(0)};
+  fft_wg<T, L, R, D, false, TC>(v, j, lds + c, tw);
+  if (ok) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) a[(int64_t)(j + m * TT) * lx + col] = v[m];
+  }
+}
+
+// MSE / weighted-intensity loss of one field: gradient and per-block loss
+// partial sums.
+template <typename T>
+__global__ void __launch_bounds__(256) plain_loss_kernel(const cx<T>* u, const T* ref, cx<T>* grad,
+                                                         double* partial, int64_t n, int kind, T scale) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> v = u[i];
+    const T I = v.x * v.x + v.y * v.y;
+    if (kind == EPI_MSE) {
+      const T d = I - ref[i];
+      acc += (double)d * (double)d;
+      grad[i] = cscale(v, T(4) * scale * d);
+    } else {
+      acc += (double)ref[i] * (double)I;
+      grad[i] = cscale(v, T(2) * scale * ref[i]);
+    }
+  }
+  const double s = block_sum<256>(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// grad_phase += Im(g conj(M u)) for one field (M = exp(i phi)).
+template <typename T>
+__global__ void __launch_bounds__(256) plain_phase_grad_kernel(const cx<T>* g, const cx<T>* u, T* gphi,
+                                                               int ny, int nx, ElementParams<T> el) {
+  const int64_t n = (int64_t)ny * nx;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / nx), x = (int)(i % nx);
+    const cx<T> um = cmul(scalar_modulation(el, ny, nx, y, x), u[i]);
+    gphi[i] += g[i].y * um.x - g[i].x * um.y;
+  }
+}
+
+namespace {
+int grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (int)(b > 16384 ? 16384 : (b < 1 ? 1 : b));
+}
+}  // namespace
+
+template <typename T>
+hipError_t Plain<T>::run(const PlainJob<T>& pj, hipStream_t s) {
+  const int ny = pj.ny, nx = pj.nx, py = pj.py, px = pj.px;
+  const int64_t npad = (int64_t)py * px, nf = (int64_t)ny * nx;
+  hipError_t e;
+  // 1. modulation (forward: M in; backward: none here)
+  const cx<T>* src = pj.in;
+  if (pj.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) {
+    hipLaunchKernelGGL((plain_modulate_kernel<T>), dim3(grid_for(nf)), dim3(256), 0, s, pj.in, pj.tmp,
+                       ny, nx, pj.el, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    src = pj.tmp;
+  }
+  // 2. zero padding
+  hipLaunchKernelGGL((plain_pad_kernel<T>), dim3(grid_for(npad)), dim3(256), 0, s, src, pj.pad, ny, nx, py,
+                     px);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 3-4. forward FFT: rows, then columns
+  if ((e = rows(px, pj.pad, py, -1, pj.tw_x, s)) != hipSuccess) return e;
+  if ((e = cols(py, pj.pad, px, -1, pj.tw_y, s)) != hipSuccess) return e;
+  // 5. transfer function from the stored table
+  hipLaunchKernelGGL((plain_mul_kernel<T>), dim3(grid_for(npad)), dim3(256), 0, s, pj.pad, pj.H, npad,
+                     pj.conj);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 6-7. inverse FFT: columns, then rows
+  if ((e = cols(py, pj.pad, px, +1, pj.tw_y, s)) != hipSuccess) return e;
+  if ((e = rows(px, pj.pad, py, +1, pj.tw_x, s)) != hipSuccess) return e;
+  // 8. crop and scale
+  hipLaunchKernelGGL((plain_crop_kernel<T>), dim3(grid_for(nf)), dim3(256), 0, s, pj.pad, pj.out, ny, nx,
+                     px, (T)(1.0 / ((double)py * (double)px)));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Plain<T>::table(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s) {
+  hipLaunchKernelGGL((plain_table_kernel<T>), dim3(grid_for((int64_t)py * px)), dim3(256), 0, s, H, py, px,
+                     p);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Plain<T>::rows(int L, cx<T>* a, int nrows, int dir, const cx<T>* tw, hipStream_t s) {
+  return dispatch_len(L, [&](auto Lc) -> hipError_t {
+    constexpr int LL = decltype(Lc)::value;
+    using C = RowCfg<LL>;
+    dim3 grid((nrows + C::G - 1) / C::G);
+    if (dir < 0)
+      hipLaunchKernelGGL((plain_row_fft_kernel<T, LL, C::R, C::G, -1>), grid, dim3(C::threads), 0, s, a, nrows,
+                         tw);
+    else
+      hipLaunchKernelGGL((plain_row_fft_kernel<T, LL, C::R, C::G, +1>), grid, dim3(C::threads), 0, s, a, nrows,
+                         tw);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t Plain<T>::cols(int L, cx<T>* a, int lx, int dir, const cx<T>* tw, hipStream_t s) {
+  return dispatch_len(L, [&](auto Lc) -> hipError_t {
+    constexpr int LL = decltype(Lc)::value;
+    using C = ColCfg<T, LL, 1>;
+    dim3 grid((lx + C::TC - 1) / C::TC);
+    if (dir < 0)
+      hipLaunchKernelGGL((plain_col_fft_kernel<T, LL, C::R, C::TC, -1>), grid, dim3(C::threads), 0, s, a, lx,
+                         tw);
+    else
+      hipLaunchKernelGGL((plain_col_fft_kernel<T, LL, C::R, C::TC, +1>), grid, dim3(C::threads), 0, s, a, lx,
+                         tw);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t Plain<T>::loss(const cx<T>* u, const T* ref, cx<T>* grad, double* partial, int64_t n, int kind,
+                          T scale, int* nblocks, hipStream_t s) {
+  *nblocks = grid_for(n) > 1024 ? 1024 : grid_for(n);
+  hipLaunchKernelGGL((plain_loss_kernel<T>), dim3(*nblocks), dim3(256), 0, s, u, ref, grad, partial, n, kind,
+                     scale);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Plain<T>::modulate(const cx<T>* in, cx<T>* out, int ny, int nx, const ElementParams<T>& el, int conj,
+                              hipStream_t s) {
+  hipLaunchKernelGGL((plain_modulate_kernel<T>), dim3(grid_for((int64_t)ny * nx)), dim3(256), 0, s, in, out,
+                     ny, nx, el, conj);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Plain<T>::phase_grad(const cx<T>* g, const cx<T>* u, T* gphi, int ny, int nx,
+                                const ElementParams<T>& el, hipStream_t s) {
+  hipLaunchKernelGGL((plain_phase_grad_kernel<T>), dim3(grid_for((int64_t)ny * nx)), dim3(256), 0, s, g, u,
+                     gphi, ny, nx, el);
+  return hipGetLastError();
+}
+
+template struct Plain<float>;
+template struct Plain<double>;
+
+}  // namespace toprop
