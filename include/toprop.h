@@ -172,11 +172,17 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
  *   adjoint != 0:  Gamma_out = M^H (P^H Gamma P) M, the adjoint of the
  *                  forward map under Re tr(A^H B).
  * When adjoint != 0 and grad is not NULL, grad->saved_in is the forward
- * input Gamma_in and grad->grad_phase (+=) receives dL/dphi of the phase
- * element, with job->in holding dL/dGamma_out:
+ * input Gamma_in (not aliasing job->out) and grad->grad_phase (+=) receives
+ * dL/dphi of the phase element, with job->in holding dL/dGamma_out:
  *   dL/dphi(r) = sum_b Im(G[r,b] conj(Gm[r,b])) - sum_a Im(G[a,r] conj(Gm[a,r])),
  *   G = P^H (dL/dGamma_out) P, Gm = M Gamma_in M^H.
- * Needs workspace for one extra copy of Gamma.                              */
+ * Forward epilogue (adjoint == 0) on the time-averaged intensity
+ * I(r) = Re Gamma_out(r, r):  TO_EPI_MSE  loss += epi_scale sum (I - T)^2,
+ * TO_EPI_WEIGHTED loss += epi_scale sum W I; epi_grad (complex, n x n)
+ * receives dL/dGamma_out, zero off the diagonal.
+ * Computed as two batched propagations of the n = ny nx rows (P^H along r2,
+ * then P along r1) around transposes; needs workspace for one extra copy of
+ * Gamma.  n must not exceed 46340; no Jones element.                         */
 to_status to_coherence_propagate(const to_job* job, to_dtype dtype, int32_t adjoint,
                                  const to_grad* grad, void* stream);
 

@@ -272,24 +272,48 @@ def propagate_backward(grad_out: torch.Tensor, opt: Optics, *, saved_in=None, wa
 
 def coherence_propagate(gamma: torch.Tensor, opt: Optics, *, adjoint: bool = False,
                         out: Optional[torch.Tensor] = None, saved_in=None, grad_phase=None,
-                        **element) -> torch.Tensor:
+                        loss_kind: Optional[str] = None, loss_ref=None, loss_scale: float = 1.0,
+                        loss=None, loss_grad=None, **element):
     """Propagate a mutual coherence function [ny, nx, ny, nx] (section
-    "Spatial coherence"): P (M G M^H) P^H, or its adjoint."""
+    "Spatial coherence"): P (M G M^H) P^H, or its adjoint M^H P^H G P M.
+
+    With ``loss_kind`` ("mse" or "weighted", forward only) the loss of the
+    output intensity Re Gamma(r, r) against ``loss_ref`` is accumulated into
+    ``loss`` and its gradient dL/dGamma_out written to ``loss_grad``; the
+    call then returns (out, loss_grad, loss).  With ``adjoint`` and
+    ``grad_phase``, dL/dphi of the phase element is accumulated using
+    ``saved_in`` (the forward input)."""
     ny, nx = int(gamma.shape[0]), int(gamma.shape[1])
     if gamma.dim() != 4 or tuple(gamma.shape) != (ny, nx, ny, nx):
         raise ValueError("gamma must be [ny, nx, ny, nx]")
+    if not gamma.is_contiguous():
+        raise ValueError("gamma must be contiguous")
     if out is None:
         out = torch.empty_like(gamma)
-    job = make_job(gamma[0, 0], opt, ncomp=1, **element)  # grid and element only
+    _need(out, "out", gamma.dtype, gamma, tuple(gamma.shape))
+    epi = {}
+    if loss_kind is not None:
+        loss_grad = torch.empty_like(gamma) if loss_grad is None else loss_grad
+        loss = torch.zeros((), dtype=torch.float64, device=gamma.device) if loss is None else loss
+        _need(loss_grad, "loss_grad", gamma.dtype, gamma, tuple(gamma.shape))
+        epi = dict(epi={"mse": _capi.TO_EPI_MSE, "weighted": _capi.TO_EPI_WEIGHTED}[loss_kind],
+                   epi_ref=loss_ref, epi_scale=loss_scale, epi_grad=loss_grad[0, 0], epi_loss=loss)
+    job = make_job(gamma[0, 0], opt, ncomp=1, **element, **epi)  # grid, element, epilogue
     job.batch = 1
     job.in_ = _ptr(gamma)
     job.out = _ptr(out)
+    if loss_kind is not None:
+        job.epi_grad = _ptr(loss_grad)
     g = None
     if adjoint and (saved_in is not None or grad_phase is not None):
         g = _capi.Grad()
-        g.saved_in = _ptr(saved_in)
-        g.grad_phase = _ptr(grad_phase)
+        if saved_in is not None:
+            g.saved_in = _ptr(_need(saved_in, "saved_in", gamma.dtype, gamma, tuple(gamma.shape)))
+        if grad_phase is not None:
+            g.grad_phase = _ptr(_need(grad_phase, "grad_phase", _real_dtype(gamma), gamma, (ny, nx)))
     _capi.coherence_propagate(job, _dtype_code(gamma), adjoint, g, _stream(gamma))
+    if loss_kind is not None:
+        return out, loss_grad, loss
     return out
 
 

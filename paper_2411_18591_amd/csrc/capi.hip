@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/toprop.h"
+#include "coherence.hpp"
 #include "launch.hpp"
 #include "plain.hpp"
 
@@ -74,6 +75,8 @@ struct DeviceCtx {
   size_t scratch_bytes = 0;
   void* plain = nullptr;  // workspace of the unfused baseline
   size_t plain_bytes = 0;
+  void* coh = nullptr;    // workspace of the coherence propagation
+  size_t coh_bytes = 0;
   double* partial = nullptr;
   size_t partial_count = 0;
 };
@@ -444,7 +447,8 @@ to_status make_geometry(const to_job& j, bool jones, Geometry* g) {
 }
 
 template <typename T>
-to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s) {
+to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s, bool conj_h = false,
+                      const cx<T>* coh_m = nullptr) {
   if (j.batch == 0) return TO_OK;
   Geometry g;
   const bool jones = (j.el_flags & TO_EL_JONES) != 0;
@@ -457,14 +461,16 @@ to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s) {
     if (st != TO_OK) return st;
   }
   cx<T>* scratch = (cx<T>*)c->scratch;
-  TransferParams h = make_transfer(j, false);
-  const ElementParams<T> el = make_element<T>(j, j.el_flags);
+  TransferParams h = make_transfer(j, conj_h);
+  const ElementParams<T> el = make_element<T>(j, coh_m ? 0u : j.el_flags);
   hipError_t e = prepare_transfer<T>(j, c, s, &h);
   if (e != hipSuccess) return hip_fail(e, "transfer table launch");
   for (int64_t f0 = 0; f0 < g.nfields; f0 += g.chunk) {
     const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
     RowFwdArgs<T> ra;
     ra.fpb = fields_per_block(j, (j.ny + g.rows_per_block - 1) / g.rows_per_block, nf);
+    ra.coh_m = coh_m;
+    ra.f_off = f0;
     ra.in = (const cx<T>*)j.in + f0 * g.in_stride;
     ra.scratch = scratch;
     ra.in_stride = g.in_stride;
@@ -632,6 +638,100 @@ to_status run_modulate(const to_job& j, int adjoint, hipStream_t s) {
   hipError_t e = Launch<T>::modulate(nc, (const cx<T>*)j.in, (cx<T>*)j.out, nc * npix, npix, j.ny,
                                      j.nx, (int)nfields, adjoint, el, s);
   if (e != hipSuccess) return hip_fail(e, "modulate launch");
+  return TO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Coherence propagation: Gamma (n x n, n = ny nx) -> P (M Gamma M^H) P^H as
+// two batched field propagations around transposes.
+//   forward:  A  rows r1:  row <- conj(P)(M(r1) conj(M) row)   [= Gm P^H]
+//             B  transpose
+//             C  rows r2:  row <- P row                         [= (P Gm P^H)^T]
+//             D  transpose                                      [= Gamma_z]
+//   adjoint:  A' rows: row <- P row [= G P]; B; C' rows: row <- conj(P) row
+//             [= (P^H G P)^T]; D transpose with the element adjoint M^H . M.
+// conj(P) = P^H because H is even in fx and fy.
+// ---------------------------------------------------------------------------
+to_status ensure_coh(DeviceCtx* c, size_t bytes) {
+  if (c->coh_bytes >= bytes) return TO_OK;
+  hipError_t e;
+  if (c->coh) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    hipFree(c->coh);
+    c->coh = nullptr;
+    c->coh_bytes = 0;
+  }
+  if ((e = hipMalloc(&c->coh, bytes)) != hipSuccess)
+    return fail(TO_E_NOMEM, "coherence workspace of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  c->coh_bytes = bytes;
+  return TO_OK;
+}
+
+template <typename T>
+to_status run_coherence(const to_job& j, int adjoint, const to_grad* gr, DeviceCtx* c, hipStream_t s) {
+  const int n = j.ny * j.nx;
+  const size_t nn = (size_t)n * n;
+  const size_t bytes = (nn + 2 * (size_t)n) * sizeof(cx<T>) + 3 * (size_t)n * sizeof(double);
+  to_status st = ensure_coh(c, bytes);
+  if (st != TO_OK) return st;
+  cx<T>* W = (cx<T>*)c->coh;
+  cx<T>* mt = W + nn;   // M(r)
+  cx<T>* mtc = mt + n;  // conj(M(r))
+  double* rowsum = (double*)(mtc + n);
+  double* colsum = rowsum + n;
+  double* part = colsum + n;
+  const bool dbl = sizeof(T) == 8;
+  const bool has_el = (j.el_flags & (TO_EL_PHASE | TO_EL_COMPLEX | TO_EL_LENS)) != 0;
+  const ElementParams<T> el = make_element<T>(j, j.el_flags);
+  hipError_t e;
+  if (has_el) {
+    if ((e = Coh<T>::mtable(mt, j.ny, j.nx, el, 0, s)) != hipSuccess) return hip_fail(e, "element table");
+    if ((e = Coh<T>::mtable(mtc, j.ny, j.nx, el, 1, s)) != hipSuccess) return hip_fail(e, "element table");
+  }
+  to_job rj = j;
+  rj.batch = n;
+  rj.ncomp = 1;
+  rj.el_flags = 0;
+  rj.epi = TO_EPI_NONE;
+  cx<T>* out = (cx<T>*)j.out;
+  auto transpose = [&](const cx<T>* a, cx<T>* b, const cx<T>* m) -> to_status {
+    hipError_t ee = timed("coh.transpose", n, dbl, s, [&] { return Coh<T>::transpose(a, b, n, m, s); });
+    return ee == hipSuccess ? TO_OK : hip_fail(ee, "transpose");
+  };
+  rj.in = j.in;
+  rj.out = out;
+  if (!adjoint) {
+    if ((st = run_forward<T>(rj, c, s, true, has_el ? mt : nullptr)) != TO_OK) return st;
+    if ((st = transpose(out, W, nullptr)) != TO_OK) return st;
+    rj.in = W;
+    rj.out = W;
+    if ((st = run_forward<T>(rj, c, s, false, nullptr)) != TO_OK) return st;
+    if ((st = transpose(W, out, nullptr)) != TO_OK) return st;
+    if (j.epi != TO_EPI_NONE) {
+      e = timed("coh.diag_loss", n, dbl, s, [&] {
+        return Coh<T>::diag_loss(out, (const T*)j.epi_ref, (cx<T>*)j.epi_grad, part, n, j.epi, (T)j.epi_scale,
+                                 s);
+      });
+      if (e != hipSuccess) return hip_fail(e, "coherence loss");
+      if ((e = launch_reduce_add(part, n, j.epi_scale, j.epi_loss, s)) != hipSuccess)
+        return hip_fail(e, "coherence loss reduction");
+    }
+    return TO_OK;
+  }
+  if ((st = run_forward<T>(rj, c, s, false, nullptr)) != TO_OK) return st;
+  if ((st = transpose(out, W, nullptr)) != TO_OK) return st;
+  rj.in = W;
+  rj.out = W;
+  if ((st = run_forward<T>(rj, c, s, true, nullptr)) != TO_OK) return st;
+  const bool want_phase = gr && gr->grad_phase && (j.el_flags & TO_EL_PHASE);
+  if (!want_phase) return transpose(W, out, has_el ? mtc : nullptr);
+  // G' = P^H G P in `out`, then the phase gradient, then M^H G' M in place
+  if ((st = transpose(W, out, nullptr)) != TO_OK) return st;
+  e = timed("coh.phase_grad", n, dbl, s, [&] {
+    return Coh<T>::phase_grad(out, (const cx<T>*)gr->saved_in, mt, rowsum, colsum, (T*)gr->grad_phase, n, s);
+  });
+  if (e != hipSuccess) return hip_fail(e, "coherence phase gradient");
+  if ((e = Coh<T>::scale(out, mt, n, s)) != hipSuccess) return hip_fail(e, "element adjoint");
   return TO_OK;
 }
 
@@ -865,15 +965,29 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
 
 to_status to_coherence_propagate(const to_job* job, to_dtype dtype, int32_t adjoint,
                                  const to_grad* grad, void* stream) {
-  (void)adjoint;
-  (void)grad;
-  (void)stream;
   if (!job) return fail(TO_E_INVAL, "job is NULL");
   to_status st = validate(*job, 0, dtype, MODE_COH);
   if (st != TO_OK) return st;
-  if (job->batch != 1 || job->ncomp != 1)
-    return fail(TO_E_INVAL, "coherence job needs batch == 1 and ncomp == 1");
-  return fail(TO_E_UNSUPPORTED, "coherence propagation is not available in this build");
+  const to_job& j = *job;
+  if (j.batch != 1 || j.ncomp != 1) return fail(TO_E_INVAL, "coherence job needs batch == 1 and ncomp == 1");
+  if (j.el_flags & TO_EL_JONES) return fail(TO_E_UNSUPPORTED, "coherence job with a Jones element");
+  if ((int64_t)j.ny * j.nx > 46340) return fail(TO_E_UNSUPPORTED, "coherence grid too large");
+  if (adjoint && j.epi != TO_EPI_NONE) return fail(TO_E_INVAL, "the adjoint has no loss epilogue");
+  if (j.epi != TO_EPI_NONE) {
+    if (j.epi != TO_EPI_MSE && j.epi != TO_EPI_WEIGHTED) return fail(TO_E_INVAL, "unknown epilogue %d", j.epi);
+    if (!j.epi_ref || !j.epi_grad || !j.epi_loss)
+      return fail(TO_E_INVAL, "epilogue needs epi_ref, epi_grad and epi_loss");
+    if (!std::isfinite(j.epi_scale)) return fail(TO_E_INVAL, "epi_scale not finite");
+  }
+  if (adjoint && grad && grad->grad_phase && (j.el_flags & TO_EL_PHASE)) {
+    if (!grad->saved_in) return fail(TO_E_INVAL, "the phase gradient needs saved_in (the forward input)");
+    if (grad->saved_in == j.out) return fail(TO_E_INVAL, "saved_in must not alias out");
+  }
+  DeviceCtx* c;
+  if ((st = get_ctx(&c)) != TO_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  return dtype == TO_C64 ? run_coherence<float>(j, adjoint, grad, c, s)
+                         : run_coherence<double>(j, adjoint, grad, c, s);
 }
 
 const char* to_last_error(void) { return g_last_error.c_str(); }
@@ -892,6 +1006,7 @@ to_status to_release(void) {
     if (c.scratch) hipFree(c.scratch);
     if (c.partial) hipFree(c.partial);
     if (c.plain) hipFree(c.plain);
+    if (c.coh) hipFree(c.coh);
     if (c.tf) hipFree(c.tf);
     c = DeviceCtx();
   }

@@ -306,6 +306,10 @@ struct RowFwdArgs {
   int tc_shift;         // log2 of the column-tile width
   int nfields;          // fields in this chunk (field groups for NC = 3)
   int fpb;              // fields per block (the modulation is evaluated once for them)
+  // Coherence rows: field f of the chunk is row r1 = f_off + f of a mutual
+  // coherence matrix; the modulation is coh_m[r1] conj(coh_m[pixel]).
+  const cx<T>* coh_m;
+  int64_t f_off;
   ElementParams<T> el;
   const cx<T>* tw;      // twiddles of length LX
 };
@@ -369,13 +373,17 @@ __global__ void __launch_bounds__(G * (L / R)) row_fwd_kernel(RowFwdArgs<T> a) {
   const int tcm = (1 << a.tc_shift) - 1;
 
   // Scalar modulation of this thread's pixels, shared by every field.
-  const bool scalar_el = (a.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) != 0;
+  const bool scalar_el = (a.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) != 0 || a.coh_m;
   cx<T> mod[RI];
 #pragma unroll
   for (int m = 0; m < RI; ++m) {
     const int x = j + m * TT;
     mod[m] = {T(1), T(0)};
-    if (scalar_el && rowok && x < nx) mod[m] = scalar_modulation(a.el, ny, nx, y, x);
+    if (a.coh_m) {
+      if (rowok && x < nx) mod[m] = cconj(a.coh_m[y * nx + x]);
+    } else if (scalar_el && rowok && x < nx) {
+      mod[m] = scalar_modulation(a.el, ny, nx, y, x);
+    }
     // one pixel at a time: interleaving the sincos chains only costs registers
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -417,10 +425,15 @@ __global__ void __launch_bounds__(G * (L / R)) row_fwd_kernel(RowFwdArgs<T> a) {
         for (int c = 0; c < NC; ++c) nxt[c][m] = {T(0), T(0)};
     }
     cx<T> v[NC][R];
+    const cx<T> fmod = a.coh_m ? a.coh_m[a.f_off + f] : cx<T>{T(1), T(0)};
 #pragma unroll
     for (int m = 0; m < R; ++m) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) v[c][m] = m < RI ? cur[c][m] : cx<T>{T(0), T(0)};
+      if (m < RI && a.coh_m) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c][m] = cmul(fmod, v[c][m]);
+      }
       if (m < RI) {
         if constexpr (NC == 3) {
           if (a.el.flags & EL_JONES) {

@@ -1,0 +1,136 @@
+"""GPU parity of the mutual-coherence propagation (section "Spatial
+coherence") against the FP64 oracle, whose coherence operator is pinned by
+its rank-one, sum-of-modes, Hermiticity, trace and adjoint reductions.
+
+Bars: complex64 relative L2 <= 2e-5 on Gamma, <= 1e-4 on mask gradients;
+complex128 <= 1e-12 / 1e-11."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests._util import announce, crandn, rel, to_gpu, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = {np.complex64: 2e-5, np.complex128: 1e-12}
+PARAM_TOL = {np.complex64: 1e-4, np.complex128: 1e-11}
+
+
+def _tp():
+    import paper_2411_18591_amd as tp
+    return tp
+
+
+def _random_gamma(rng, n, dtype):
+    A = crandn(rng, n * n, n * n) / n
+    return (A @ A.conj().T).reshape(n, n, n, n).astype(dtype)
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+@pytest.mark.parametrize("n", [4, 8, 16])
+def test_coherence_forward_adjoint_gradient(n, dtype):
+    tp = _tp()
+    announce(f"coherence n={n} {dtype.__name__}")
+    rng = np.random.default_rng(41 + n)
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    d, lam, z, f = 10e-6, 633e-9, 0.01, 0.03
+    G0 = _random_gamma(rng, n, dtype)
+    phi = (rng.random((n, n)) * 2 * np.pi).astype(rdt)
+    Gout = crandn(rng, n, n, n, n, dtype=dtype)
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, pad=2)
+    M = oracle.phase_mask(phi) * oracle.lens(n, n, d, d, lam, f)
+    args = (d, d, lam, z, oracle.ASM, 2)
+    exp_fwd = oracle.coherence_propagate(oracle.coherence_modulate(G0, M), *args)
+    Gp = oracle.coherence_propagate(Gout, *args, adjoint=True)
+    exp_adj = oracle.coherence_modulate(Gp, M, conj=True)
+    exp_gphi = oracle.coherence_grad_phase(Gp, oracle.coherence_modulate(G0, M))
+
+    g0 = to_gpu(G0, torch)
+    pg = to_gpu(phi, torch)
+    out = tp.coherence_propagate(g0, opt, phase=pg, lens_f=f)
+    gphi = torch.zeros_like(pg)
+    adj = tp.coherence_propagate(to_gpu(Gout, torch), opt, adjoint=True, saved_in=g0, grad_phase=gphi,
+                                 phase=pg, lens_f=f)
+    adj2 = tp.coherence_propagate(to_gpu(Gout, torch), opt, adjoint=True, phase=pg, lens_f=f)
+    torch.cuda.synchronize()
+    assert rel(to_np(out), exp_fwd) <= FIELD_TOL[dtype]
+    assert rel(to_np(adj), exp_adj) <= FIELD_TOL[dtype]
+    assert rel(to_np(adj2), exp_adj) <= FIELD_TOL[dtype]
+    assert rel(to_np(gphi), exp_gphi) <= PARAM_TOL[dtype]
+
+
+def test_coherence_rank_one_matches_field_propagation():
+    """Gamma = u u^H propagates to (P M u)(P M u)^H: the coherence path
+    against the field path of the same library."""
+    tp = _tp()
+    announce("coherence rank one vs field path")
+    rng = np.random.default_rng(50)
+    n = 16
+    u = crandn(rng, n, n, dtype=np.complex128)
+    G = np.einsum("ab,cd->abcd", u, np.conj(u))
+    phi = rng.random((n, n)) * 6
+    opt = tp.Optics(dy=8e-6, dx=8e-6, wavelength=0.6e-6, z=0.02, pad=2)
+    out = tp.coherence_propagate(to_gpu(G, torch), opt, phase=to_gpu(phi, torch))
+    pu = tp.propagate(to_gpu(u[None], torch), opt, phase=to_gpu(phi, torch))[0]
+    torch.cuda.synchronize()
+    pu = to_np(pu)
+    assert rel(to_np(out), np.einsum("ab,cd->abcd", pu, np.conj(pu))) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_coherence_diag_loss(dtype):
+    tp = _tp()
+    announce(f"coherence diag loss {dtype.__name__}")
+    rng = np.random.default_rng(51)
+    n = 8
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    G0 = _random_gamma(rng, n, dtype)
+    T = rng.random((n, n)).astype(rdt)
+    opt = tp.Optics(dy=10e-6, dx=10e-6, wavelength=633e-9, z=0.01, pad=2)
+    out, g, L = tp.coherence_propagate(to_gpu(G0, torch), opt, loss_kind="mse", loss_ref=to_gpu(T, torch),
+                                       loss_scale=1.0 / (n * n))
+    torch.cuda.synchronize()
+    Go = oracle.coherence_propagate(G0, 10e-6, 10e-6, 633e-9, 0.01, oracle.ASM, 2)
+    I = oracle.coherence_intensity(Go)
+    loss = float(np.mean((I - T) ** 2))
+    exp_g = np.zeros((n * n, n * n), complex)
+    np.fill_diagonal(exp_g, 2.0 / (n * n) * (I - T).ravel())
+    assert abs(float(L.item()) - loss) <= PARAM_TOL[dtype] * loss
+    assert rel(to_np(g).reshape(n * n, n * n), exp_g) <= 4 * FIELD_TOL[dtype]
+
+
+def test_gaussian_schell_workload_fwd_bwd():
+    """64^2 Gaussian Schell-model source (waist 150 um, coherence 50 um,
+    10 um, 633 nm), phase mask and lens f = 5 cm, AS 5 cm, MSE of the output
+    intensity, gradient to the mask: complex64 GPU against the FP64 oracle."""
+    tp = _tp()
+    announce("gaussian schell 64^2 coherence fwd+bwd c64")
+    w = workloads.CoherenceWorkload()
+    G0 = w.gamma()
+    phi = w.mask()
+    T = w.target()
+    n = w.n
+    opt = tp.Optics(dy=w.d, dx=w.d, wavelength=w.wavelength, z=w.z, pad=w.pad)
+    g0 = to_gpu(G0, torch)
+    pg = to_gpu(phi, torch)
+    out, g, L = tp.coherence_propagate(g0, opt, loss_kind="mse", loss_ref=to_gpu(T, torch),
+                                       loss_scale=1.0 / (n * n), phase=pg, lens_f=w.f)
+    gphi = torch.zeros_like(pg)
+    tp.coherence_propagate(g, opt, adjoint=True, saved_in=g0, grad_phase=gphi, phase=pg, lens_f=w.f)
+    torch.cuda.synchronize()
+
+    M = oracle.phase_mask(phi) * oracle.lens(n, n, w.d, w.d, w.wavelength, w.f)
+    args = (w.d, w.d, w.wavelength, w.z, oracle.ASM, w.pad)
+    Gm = oracle.coherence_modulate(G0, M)
+    Go = oracle.coherence_propagate(Gm, *args)
+    I = oracle.coherence_intensity(Go)
+    loss = float(np.mean((I - T) ** 2))
+    Gd = np.zeros((n * n, n * n), complex)
+    np.fill_diagonal(Gd, 2.0 / (n * n) * (I - T).ravel())
+    Gp = oracle.coherence_propagate(Gd.reshape(n, n, n, n), *args, adjoint=True)
+    exp_gphi = oracle.coherence_grad_phase(Gp, Gm)
+    assert rel(to_np(out), Go) <= 2e-5
+    assert abs(float(L.item()) - loss) <= 1e-4 * loss
+    assert rel(to_np(gphi), exp_gphi) <= 1e-4
