@@ -143,8 +143,19 @@ typedef struct to_grad {
 
 /* Forward propagation of every job (Eq. (field_propagation_tf) after the
  * element of Eq. (field_modulation)): out = P_z (M in), with the optional
- * loss epilogue.  Jobs run in order on `stream`; a job may read the output
- * of an earlier one.                                                         */
+ * loss epilogue.  Jobs may differ in every field (the batch dimension of the
+ * paper's tensors, generalised to uneven grids, wavelengths and distances).
+ *
+ * Scheduling: jobs whose device ranges conflict (one writes what another
+ * reads or writes, judged from the pointers and sizes in the records) run
+ * in call order; independent jobs are spread longest-first over up to four
+ * "lanes": the caller's `stream` and three library streams (default
+ * priority) that wait on an event recorded on `stream` at entry and are
+ * joined back into it at exit.  All work therefore completes in `stream`
+ * order, and the call may be captured into a HIP graph from `stream` (after
+ * one uncaptured call of the same shapes has sized the workspaces).  Calls
+ * issued concurrently on different caller streams of one device share the
+ * lanes' workspaces and must be serialised by the caller.                    */
 to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* stream);
 
 /* Modulation only (Eq. (field_modulation) / the Jones product):
@@ -160,7 +171,10 @@ to_status to_modulate(const to_job* jobs, int32_t njobs, to_dtype dtype, int32_t
  *   grad_f     += sum (pi r^2 / (lambda f^2)) Im(g_mod conj(M saved_in)).
  * P_z^H is the same pipeline with conj(H).  The per-layer input is taken
  * from `saved_in` (recomputation: no padded spectra are stored).  The
- * job's epilogue fields are ignored.  grads[i] belongs to jobs[i].           */
+ * job's epilogue fields are ignored.  grads[i] belongs to jobs[i].  Jobs
+ * are scheduled over the lanes as in to_propagate; jobs that accumulate
+ * into the same grad_phase or grad_f run in call order on one lane, so the
+ * accumulation order (and the result) does not depend on the schedule.     */
 to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_t njobs,
                                 to_dtype dtype, void* stream);
 

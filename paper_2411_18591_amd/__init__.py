@@ -25,7 +25,8 @@ from ._capi import ToError  # noqa: F401
 
 __all__ = [
     "Optics", "propagate", "modulate", "propagate_backward", "coherence_propagate",
-    "propagate_ad", "linear_polarizer", "waveplate", "jones3", "version",
+    "propagate_ad", "propagate_jobs", "propagate_backward_jobs", "linear_polarizer", "waveplate",
+    "jones3", "version",
 ]
 
 ASM = "asm"
@@ -268,6 +269,67 @@ def propagate_backward(grad_out: torch.Tensor, opt: Optics, *, saved_in=None, wa
         g.grad_f = _ptr(_need(grad_f, "grad_f", torch.float64, grad_out))
     _capi.propagate_backward([job], [g], _dtype_code(grad_out), _stream(grad_out), plain=plain)
     return grad_in
+
+
+def _common_dtype(tensors) -> int:
+    codes = {_dtype_code(t) for t in tensors}
+    devs = {t.device for t in tensors}
+    if len(codes) != 1 or len(devs) != 1:
+        raise ValueError("all jobs of one call must share the dtype and the device")
+    return codes.pop()
+
+
+def propagate_jobs(fields: Sequence[torch.Tensor], opts: Sequence[Optics], *, outs=None, elements=None,
+                   ncomp: int = 1, plain: bool = False):
+    """One library call over several independent propagations, each with its
+    own grid, optics and element (the uneven batch).  Independent jobs run
+    concurrently on the library's lanes; a job that reads what an earlier job
+    of the call writes runs after it.  Returns the output tensors."""
+    n = len(fields)
+    if len(opts) != n:
+        raise ValueError("one Optics per field")
+    outs = [torch.empty_like(u) for u in fields] if outs is None else list(outs)
+    elements = [{}] * n if elements is None else list(elements)
+    if n == 0:
+        return outs
+    dt = _common_dtype(fields)
+    jobs = [make_job(u, o, out=y, ncomp=ncomp, **el) for u, o, y, el in zip(fields, opts, outs, elements)]
+    _capi.propagate(jobs, dt, _stream(fields[0]), plain=plain)
+    return outs
+
+
+def propagate_backward_jobs(grads_out: Sequence[torch.Tensor], opts: Sequence[Optics], *, saved_ins=None,
+                            grad_ins=None, grad_phases=None, elements=None, ncomp: int = 1,
+                            plain: bool = False):
+    """Backward of :func:`propagate_jobs` in one call: returns dL/d(in) per
+    job; element gradients accumulate into ``grad_phases[i]`` (jobs that
+    share a gradient tensor are run in call order on one lane)."""
+    n = len(grads_out)
+    if len(opts) != n:
+        raise ValueError("one Optics per gradient")
+    grad_ins = [torch.empty_like(g) for g in grads_out] if grad_ins is None else list(grad_ins)
+    saved_ins = [None] * n if saved_ins is None else list(saved_ins)
+    grad_phases = [None] * n if grad_phases is None else list(grad_phases)
+    elements = [{}] * n if elements is None else list(elements)
+    if n == 0:
+        return grad_ins
+    dt = _common_dtype(grads_out)
+    jobs, grs = [], []
+    for go, o, gi, si, gp, el in zip(grads_out, opts, grad_ins, saved_ins, grad_phases, elements):
+        j = make_job(go, o, ncomp=ncomp, **el)
+        j.in_ = None
+        g = _capi.Grad()
+        g.grad_out = _ptr(go)
+        if gi is not None:
+            g.grad_in = _ptr(_need(gi, "grad_in", go.dtype, go, tuple(go.shape)))
+        if si is not None:
+            g.saved_in = _ptr(_need(si, "saved_in", go.dtype, go, tuple(go.shape)))
+        if gp is not None:
+            g.grad_phase = _ptr(_need(gp, "grad_phase", _real_dtype(go), go, go.shape[-2:]))
+        jobs.append(j)
+        grs.append(g)
+    _capi.propagate_backward(jobs, grs, dt, _stream(grads_out[0]), plain=plain)
+    return grad_ins
 
 
 def coherence_propagate(gamma: torch.Tensor, opt: Optics, *, adjoint: bool = False,

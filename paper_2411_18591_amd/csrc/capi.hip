@@ -64,21 +64,34 @@ std::vector<cx<T>> build_twiddles() {
   return h;
 }
 
+// Independent jobs of one call run concurrently on up to kLanes "lanes":
+// lane 0 is the caller's stream, lanes 1.. are library streams (default
+// priority) forked from and joined back into it with events.  Each lane has
+// its own scratch, reduction partials and transfer-function tables.
+constexpr int kLanes = 4;
+
+struct Lane {
+  hipStream_t stream = nullptr;  // null for lane 0 (the caller's stream is used)
+  hipEvent_t done = nullptr;
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  double* partial = nullptr;
+  size_t partial_count = 0;
+  // separable transfer-function tables of the job being run: ex, ey
+  // (complex64) and sx, sy (float), kMaxLen entries each
+  void* tf = nullptr;
+};
+
 struct DeviceCtx {
   bool init = false;
   cx<float>* tw32 = nullptr;
   cx<double>* tw64 = nullptr;
-  // separable transfer-function tables of the job being run: ex, ey
-  // (complex64) and sx, sy (float), kMaxLen entries each
-  void* tf = nullptr;
-  void* scratch = nullptr;
-  size_t scratch_bytes = 0;
+  Lane lane[kLanes];
+  hipEvent_t fork = nullptr;
   void* plain = nullptr;  // workspace of the unfused baseline
   size_t plain_bytes = 0;
   void* coh = nullptr;    // workspace of the coherence propagation
   size_t coh_bytes = 0;
-  double* partial = nullptr;
-  size_t partial_count = 0;
 };
 
 std::mutex g_mutex;
@@ -104,17 +117,28 @@ to_status get_ctx(DeviceCtx** out) {
     if ((e = hipMemcpy(c.tw64, h64.data(), sizeof(cx<double>) * kTwTotal, hipMemcpyHostToDevice)) !=
         hipSuccess)
       return hip_fail(e, "twiddle upload");
-    if ((e = hipMalloc(&c.tf, (size_t)kMaxLen * 2 * (sizeof(cx<float>) + sizeof(float)))) != hipSuccess)
-      return fail(TO_E_NOMEM, "table allocation failed: %s", hipGetErrorString(e));
+    for (int l = 0; l < kLanes; ++l) {
+      Lane& ln = c.lane[l];
+      if ((e = hipMalloc(&ln.tf, (size_t)kMaxLen * 2 * (sizeof(cx<float>) + sizeof(float)))) != hipSuccess)
+        return fail(TO_E_NOMEM, "table allocation failed: %s", hipGetErrorString(e));
+      if (l > 0) {
+        if ((e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking)) != hipSuccess)
+          return hip_fail(e, "hipStreamCreateWithFlags");
+      }
+      if ((e = hipEventCreateWithFlags(&ln.done, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    if ((e = hipEventCreateWithFlags(&c.fork, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "hipEventCreateWithFlags");
     c.init = true;
   }
   *out = &c;
   return TO_OK;
 }
 
-// Grow the scratch buffer to at least `bytes` (synchronizes the device when
-// it has to reallocate, since queued work may still use the old buffer).
-to_status ensure_scratch(DeviceCtx* c, size_t bytes) {
+// Grow a lane's scratch buffer to at least `bytes` (synchronizes the device
+// when it has to reallocate, since queued work may still use the old buffer).
+to_status ensure_scratch(Lane* c, size_t bytes) {
   if (c->scratch_bytes >= bytes) return TO_OK;
   hipError_t e;
   if (c->scratch) {
@@ -145,7 +169,7 @@ to_status ensure_plain(DeviceCtx* c, size_t bytes) {
   return TO_OK;
 }
 
-to_status ensure_partial(DeviceCtx* c, size_t count) {
+to_status ensure_partial(Lane* c, size_t count) {
   if (c->partial_count >= count) return TO_OK;
   hipError_t e;
   if (c->partial) {
@@ -335,7 +359,7 @@ double asm_remainder_cycles(const to_job& j) {
 constexpr double kFastRemainderCycles = 1.0;
 
 template <typename T>
-hipError_t prepare_transfer(const to_job& j, DeviceCtx* c, hipStream_t s, TransferParams* h) {
+hipError_t prepare_transfer(const to_job& j, Lane* c, hipStream_t s, TransferParams* h) {
   if (sizeof(T) != 4) return hipSuccess;
   if (j.method == TO_ASM && !(asm_remainder_cycles(j) <= kFastRemainderCycles)) return hipSuccess;
   cx<float>* ex = (cx<float>*)c->tf;
@@ -447,23 +471,23 @@ to_status make_geometry(const to_job& j, bool jones, Geometry* g) {
 }
 
 template <typename T>
-to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s, bool conj_h = false,
+to_status run_forward(const to_job& j, DeviceCtx* c, Lane* ln, hipStream_t s, bool conj_h = false,
                       const cx<T>* coh_m = nullptr) {
   if (j.batch == 0) return TO_OK;
   Geometry g;
   const bool jones = (j.el_flags & TO_EL_JONES) != 0;
   to_status st = make_geometry<T>(j, jones, &g);
   if (st != TO_OK) return st;
-  st = ensure_scratch(c, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
+  st = ensure_scratch(ln, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
   if (st != TO_OK) return st;
   if (j.epi != TO_EPI_NONE) {
-    st = ensure_partial(c, (size_t)g.chunk * j.ny);
+    st = ensure_partial(ln, (size_t)g.chunk * j.ny);
     if (st != TO_OK) return st;
   }
-  cx<T>* scratch = (cx<T>*)c->scratch;
+  cx<T>* scratch = (cx<T>*)ln->scratch;
   TransferParams h = make_transfer(j, conj_h);
   const ElementParams<T> el = make_element<T>(j, coh_m ? 0u : j.el_flags);
-  hipError_t e = prepare_transfer<T>(j, c, s, &h);
+  hipError_t e = prepare_transfer<T>(j, ln, s, &h);
   if (e != hipSuccess) return hip_fail(e, "transfer table launch");
   for (int64_t f0 = 0; f0 < g.nfields; f0 += g.chunk) {
     const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
@@ -517,7 +541,7 @@ to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s, bool conj_h 
     ia.epi_ref = (const T*)j.epi_ref;
     ia.epi_scale = (T)j.epi_scale;
     ia.epi_grad = j.epi_grad ? (cx<T>*)j.epi_grad + f0 * g.in_stride : nullptr;
-    ia.row_partial = c->partial;
+    ia.row_partial = ln->partial;
     ia.backward = 0;
     ia.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block, nf);
     const int inv_blocks_y = (nf + ia.fpb - 1) / ia.fpb;
@@ -527,7 +551,7 @@ to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s, bool conj_h 
     if (e != hipSuccess) return hip_fail(e, "row_inv launch");
     if (j.epi != TO_EPI_NONE) {
       e = timed("fwd.loss_reduce", 0, dbl, s, [&] {
-        return launch_reduce_add(c->partial, (int64_t)nf * j.ny, j.epi_scale, j.epi_loss, s);
+        return launch_reduce_add(ln->partial, (int64_t)nf * j.ny, j.epi_scale, j.epi_loss, s);
       });
       if (e != hipSuccess) return hip_fail(e, "loss reduction launch");
     }
@@ -536,23 +560,23 @@ to_status run_forward(const to_job& j, DeviceCtx* c, hipStream_t s, bool conj_h 
 }
 
 template <typename T>
-to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStream_t s) {
+to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, Lane* ln, hipStream_t s) {
   if (j.batch == 0) return TO_OK;
   Geometry g;
   const bool jones = (j.el_flags & TO_EL_JONES) != 0;
   to_status st = make_geometry<T>(j, jones, &g);
   if (st != TO_OK) return st;
-  st = ensure_scratch(c, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
+  st = ensure_scratch(ln, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
   if (st != TO_OK) return st;
   const bool want_f = (j.el_flags & TO_EL_LENS) && gr.grad_f;
   if (want_f) {
-    st = ensure_partial(c, (size_t)j.ny);
+    st = ensure_partial(ln, (size_t)j.ny);
     if (st != TO_OK) return st;
   }
-  cx<T>* scratch = (cx<T>*)c->scratch;
+  cx<T>* scratch = (cx<T>*)ln->scratch;
   TransferParams h = make_transfer(j, true);
   const ElementParams<T> el = make_element<T>(j, j.el_flags);
-  hipError_t e = prepare_transfer<T>(j, c, s, &h);
+  hipError_t e = prepare_transfer<T>(j, ln, s, &h);
   if (e != hipSuccess) return hip_fail(e, "transfer table launch");
   // The gradient rows carry no element: the first two passes treat every
   // component as an independent field.
@@ -613,13 +637,13 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStre
     ia.saved_in = gr.saved_in ? (const cx<T>*)gr.saved_in + f0 * g.in_stride : nullptr;
     ia.grad_phase = (T*)gr.grad_phase;
     ia.lens_f = j.el_f;
-    ia.lens_partial = want_f ? c->partial : nullptr;
+    ia.lens_partial = want_f ? ln->partial : nullptr;
     e = timed("bwd.row_inv", g.lx, dbl, s,
               [&] { return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, 1, ia, s); });
     if (e != hipSuccess) return hip_fail(e, "row_inv launch");
     if (want_f) {
       e = timed("bwd.lens_reduce", 0, dbl, s,
-                [&] { return launch_reduce_add(c->partial, j.ny, 1.0, gr.grad_f, s); });
+                [&] { return launch_reduce_add(ln->partial, j.ny, 1.0, gr.grad_f, s); });
       if (e != hipSuccess) return hip_fail(e, "lens gradient reduction launch");
     }
   }
@@ -639,6 +663,135 @@ to_status run_modulate(const to_job& j, int adjoint, hipStream_t s) {
                                      j.nx, (int)nfields, adjoint, el, s);
   if (e != hipSuccess) return hip_fail(e, "modulate launch");
   return TO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scheduling of the jobs of one call over the lanes.
+// ---------------------------------------------------------------------------
+struct Span {
+  uintptr_t lo, hi;
+};
+Span span(const void* p, size_t bytes) {
+  const uintptr_t a = (uintptr_t)p;
+  return p ? Span{a, a + bytes} : Span{0, 0};
+}
+bool overlaps(const Span& a, const Span& b) { return a.hi > a.lo && b.hi > b.lo && a.lo < b.hi && b.lo < a.hi; }
+
+size_t field_bytes(const to_job& j, to_dtype dt) {
+  return (size_t)j.batch * j.ncomp * j.ny * j.nx * (dt == TO_C64 ? sizeof(cx<float>) : sizeof(cx<double>));
+}
+
+// Ranges a job reads besides its field: the element's mask tables and the
+// epilogue's reference.
+void element_spans(const to_job& j, to_dtype dt, std::vector<Span>* rd) {
+  const size_t px = (size_t)j.ny * j.nx, re = dt == TO_C64 ? sizeof(float) : sizeof(double);
+  if (j.el_flags & TO_EL_PHASE) rd->push_back(span(j.el_phase, px * re));
+  if (j.el_flags & TO_EL_COMPLEX) rd->push_back(span(j.el_complex, px * 2 * re));
+  if (j.epi != TO_EPI_NONE) rd->push_back(span(j.epi_ref, px * re));
+}
+
+// Relative cost of a job: FFT work of its padded grid.
+double job_cost(const to_job& j) {
+  const double n = (double)j.px * (double)j.py;
+  return (double)j.batch * j.ncomp * n * std::log2(n > 2 ? n : 2.0);
+}
+
+template <typename T>
+void workspace_need(const to_job& j, bool backward, size_t* scratch_bytes, size_t* partial_count) {
+  *scratch_bytes = 0;
+  *partial_count = 0;
+  if (j.batch == 0) return;
+  Geometry g;
+  if (make_geometry<T>(j, (j.el_flags & TO_EL_JONES) != 0, &g) != TO_OK) return;
+  *scratch_bytes = (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>);
+  if (!backward && j.epi != TO_EPI_NONE) *partial_count = (size_t)g.chunk * j.ny;
+  if (backward && (j.el_flags & TO_EL_LENS)) *partial_count = (size_t)j.ny;
+}
+
+// Runs jobs 0..n-1.  Jobs whose written ranges overlap another job's read or
+// written ranges form one group and stay in call order on one lane; groups
+// are assigned longest-first to the least-loaded lane.  Lane 0 is the
+// caller's stream; the other lanes fork from it and join back with events,
+// so the whole call can be captured in a hipGraph.
+template <typename Run, typename Need>
+to_status run_on_lanes(DeviceCtx* c, hipStream_t s, int n, const std::vector<std::vector<Span>>& rd,
+                       const std::vector<std::vector<Span>>& wr, const std::vector<double>& cost, Run&& run,
+                       Need&& need) {
+  // union-find over conflicting jobs
+  std::vector<int> parent(n);
+  for (int i = 0; i < n; ++i) parent[i] = i;
+  auto find = [&](int i) {
+    while (parent[i] != i) i = parent[i] = parent[parent[i]];
+    return i;
+  };
+  for (int i = 0; i < n; ++i)
+    for (int k = i + 1; k < n; ++k) {
+      bool conflict = false;
+      for (const Span& w : wr[i]) {
+        for (const Span& r : rd[k]) conflict |= overlaps(w, r);
+        for (const Span& r : wr[k]) conflict |= overlaps(w, r);
+      }
+      for (const Span& w : wr[k])
+        for (const Span& r : rd[i]) conflict |= overlaps(w, r);
+      if (conflict) parent[find(i)] = find(k);
+    }
+  std::vector<int> root(n);
+  std::vector<double> gcost(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    root[i] = find(i);
+    gcost[root[i]] += cost[i];
+  }
+  std::vector<int> groups;
+  for (int i = 0; i < n; ++i)
+    if (root[i] == i) groups.push_back(i);
+  const int nl = std::min<int>(kLanes, (int)groups.size());
+  std::vector<int> lane_of(n, 0);
+  if (nl > 1) {
+    std::sort(groups.begin(), groups.end(), [&](int a, int b) { return gcost[a] > gcost[b]; });
+    std::vector<double> load(nl, 0.0);
+    std::vector<int> glane(n, 0);
+    for (int gi : groups) {
+      int best = 0;
+      for (int l = 1; l < nl; ++l)
+        if (load[l] < load[best]) best = l;
+      glane[gi] = best;
+      load[best] += gcost[gi];
+    }
+    for (int i = 0; i < n; ++i) lane_of[i] = glane[root[i]];
+  }
+  // size every lane's workspace before anything is enqueued
+  for (int l = 0; l < nl || l == 0; ++l) {
+    size_t sb = 0, pc = 0;
+    for (int i = 0; i < n; ++i) {
+      if (lane_of[i] != l) continue;
+      size_t a, b;
+      need(i, &a, &b);
+      sb = std::max(sb, a);
+      pc = std::max(pc, b);
+    }
+    to_status st;
+    if (sb && (st = ensure_scratch(&c->lane[l], sb)) != TO_OK) return st;
+    if (pc && (st = ensure_partial(&c->lane[l], pc)) != TO_OK) return st;
+  }
+  hipError_t e;
+  if (nl > 1) {
+    if ((e = hipEventRecord(c->fork, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    for (int l = 1; l < nl; ++l)
+      if ((e = hipStreamWaitEvent(c->lane[l].stream, c->fork, 0)) != hipSuccess)
+        return hip_fail(e, "hipStreamWaitEvent");
+  }
+  to_status result = TO_OK;
+  for (int i = 0; i < n && result == TO_OK; ++i) {
+    const int l = lane_of[i];
+    result = run(i, &c->lane[l], l == 0 ? s : c->lane[l].stream);
+  }
+  if (nl > 1) {  // join even after an error so no lane is left detached
+    for (int l = 1; l < nl; ++l) {
+      if ((e = hipEventRecord(c->lane[l].done, c->lane[l].stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      if ((e = hipStreamWaitEvent(s, c->lane[l].done, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    }
+  }
+  return result;
 }
 
 // ---------------------------------------------------------------------------
@@ -701,11 +854,11 @@ to_status run_coherence(const to_job& j, int adjoint, const to_grad* gr, DeviceC
   rj.in = j.in;
   rj.out = out;
   if (!adjoint) {
-    if ((st = run_forward<T>(rj, c, s, true, has_el ? mt : nullptr)) != TO_OK) return st;
+    if ((st = run_forward<T>(rj, c, &c->lane[0], s, true, has_el ? mt : nullptr)) != TO_OK) return st;
     if ((st = transpose(out, W, nullptr)) != TO_OK) return st;
     rj.in = W;
     rj.out = W;
-    if ((st = run_forward<T>(rj, c, s, false, nullptr)) != TO_OK) return st;
+    if ((st = run_forward<T>(rj, c, &c->lane[0], s, false, nullptr)) != TO_OK) return st;
     if ((st = transpose(W, out, nullptr)) != TO_OK) return st;
     if (j.epi != TO_EPI_NONE) {
       e = timed("coh.diag_loss", n, dbl, s, [&] {
@@ -718,11 +871,11 @@ to_status run_coherence(const to_job& j, int adjoint, const to_grad* gr, DeviceC
     }
     return TO_OK;
   }
-  if ((st = run_forward<T>(rj, c, s, false, nullptr)) != TO_OK) return st;
+  if ((st = run_forward<T>(rj, c, &c->lane[0], s, false, nullptr)) != TO_OK) return st;
   if ((st = transpose(out, W, nullptr)) != TO_OK) return st;
   rj.in = W;
   rj.out = W;
-  if ((st = run_forward<T>(rj, c, s, true, nullptr)) != TO_OK) return st;
+  if ((st = run_forward<T>(rj, c, &c->lane[0], s, true, nullptr)) != TO_OK) return st;
   const bool want_phase = gr && gr->grad_phase && (j.el_flags & TO_EL_PHASE);
   if (!want_phase) return transpose(W, out, has_el ? mtc : nullptr);
   // G' = P^H G P in `out`, then the phase gradient, then M^H G' M in place
@@ -910,11 +1063,30 @@ to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* 
   to_status st = get_ctx(&c);
   if (st != TO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  std::vector<std::vector<Span>> rd(njobs), wr(njobs);
+  std::vector<double> cost(njobs);
   for (int i = 0; i < njobs; ++i) {
-    st = dtype == TO_C64 ? run_forward<float>(jobs[i], c, s) : run_forward<double>(jobs[i], c, s);
-    if (st != TO_OK) return st;
+    const to_job& j = jobs[i];
+    const size_t fb = field_bytes(j, dtype);
+    rd[i].push_back(span(j.in, fb));
+    wr[i].push_back(span(j.out, fb));
+    element_spans(j, dtype, &rd[i]);
+    if (j.epi != TO_EPI_NONE) {
+      wr[i].push_back(span(j.epi_grad, fb));
+      wr[i].push_back(span(j.epi_loss, sizeof(double)));
+    }
+    cost[i] = job_cost(j);
   }
-  return TO_OK;
+  auto run = [&](int i, Lane* ln, hipStream_t ls) {
+    return dtype == TO_C64 ? run_forward<float>(jobs[i], c, ln, ls) : run_forward<double>(jobs[i], c, ln, ls);
+  };
+  auto need = [&](int i, size_t* sb, size_t* pc) {
+    if (dtype == TO_C64)
+      workspace_need<float>(jobs[i], false, sb, pc);
+    else
+      workspace_need<double>(jobs[i], false, sb, pc);
+  };
+  return run_on_lanes(c, s, njobs, rd, wr, cost, run, need);
 }
 
 to_status to_modulate(const to_job* jobs, int32_t njobs, to_dtype dtype, int32_t adjoint,
@@ -955,12 +1127,32 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
   to_status st = get_ctx(&c);
   if (st != TO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  std::vector<std::vector<Span>> rd(njobs), wr(njobs);
+  std::vector<double> cost(njobs);
   for (int i = 0; i < njobs; ++i) {
-    st = dtype == TO_C64 ? run_backward<float>(jobs[i], grads[i], c, s)
-                         : run_backward<double>(jobs[i], grads[i], c, s);
-    if (st != TO_OK) return st;
+    const to_job& j = jobs[i];
+    const to_grad& g = grads[i];
+    const size_t fb = field_bytes(j, dtype);
+    const size_t rb = (size_t)j.ny * j.nx * (dtype == TO_C64 ? sizeof(float) : sizeof(double));
+    rd[i].push_back(span(g.grad_out, fb));
+    rd[i].push_back(span(g.saved_in, fb));
+    element_spans(j, dtype, &rd[i]);
+    wr[i].push_back(span(g.grad_in, fb));
+    wr[i].push_back(span(g.grad_phase, rb));
+    wr[i].push_back(span(g.grad_f, sizeof(double)));
+    cost[i] = job_cost(j);
   }
-  return TO_OK;
+  auto run = [&](int i, Lane* ln, hipStream_t ls) {
+    return dtype == TO_C64 ? run_backward<float>(jobs[i], grads[i], c, ln, ls)
+                           : run_backward<double>(jobs[i], grads[i], c, ln, ls);
+  };
+  auto need = [&](int i, size_t* sb, size_t* pc) {
+    if (dtype == TO_C64)
+      workspace_need<float>(jobs[i], true, sb, pc);
+    else
+      workspace_need<double>(jobs[i], true, sb, pc);
+  };
+  return run_on_lanes(c, s, njobs, rd, wr, cost, run, need);
 }
 
 to_status to_coherence_propagate(const to_job* job, to_dtype dtype, int32_t adjoint,
@@ -998,16 +1190,22 @@ to_status to_release(void) {
   hipGetDevice(&cur);
   for (size_t d = 0; d < g_ctx.size(); ++d) {
     DeviceCtx& c = g_ctx[d];
-    if (!c.init && !c.scratch && !c.partial) continue;
+    if (!c.init) continue;
     hipSetDevice((int)d);
     hipDeviceSynchronize();
     if (c.tw32) hipFree(c.tw32);
     if (c.tw64) hipFree(c.tw64);
-    if (c.scratch) hipFree(c.scratch);
-    if (c.partial) hipFree(c.partial);
+    for (int l = 0; l < kLanes; ++l) {
+      Lane& ln = c.lane[l];
+      if (ln.scratch) hipFree(ln.scratch);
+      if (ln.partial) hipFree(ln.partial);
+      if (ln.tf) hipFree(ln.tf);
+      if (ln.done) hipEventDestroy(ln.done);
+      if (l > 0 && ln.stream) hipStreamDestroy(ln.stream);
+    }
+    if (c.fork) hipEventDestroy(c.fork);
     if (c.plain) hipFree(c.plain);
     if (c.coh) hipFree(c.coh);
-    if (c.tf) hipFree(c.tf);
     c = DeviceCtx();
   }
   hipSetDevice(cur);

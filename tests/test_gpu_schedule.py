@@ -1,0 +1,267 @@
+"""Batch scheduling on the GPU: several jobs in one library call (uneven
+grids, wavelengths and distances; the paper's batch dimension generalised),
+spread over the library's concurrent lanes, and the same calls captured in a
+HIP graph.
+
+Checks: each job of a multi-job call is bit-identical to the same job run
+alone (the schedule changes no arithmetic); jobs that read what an earlier
+job writes, or accumulate into the same loss or gradient, see call order;
+FP64-oracle parity per job (complex64 relative L2 <= 2e-5); the adjoint
+identity <P u, g> = <u, P^H g> for every job of the uneven workload; graph
+replays equal eager runs."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests._util import announce, crandn, rel, to_gpu, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-5
+
+
+def _tp():
+    import paper_2411_18591_amd as tp
+    return tp
+
+
+def _mixed_jobs(rng, dtype=np.complex64):
+    """Ten jobs of different grids, methods, wavelengths and distances, some
+    with elements; ragged sizes included."""
+    tp = _tp()
+    specs = [
+        (64, 64, "asm", {}), (96, 80, "asm", {"phase": True}), (128, 128, "fresnel", {}),
+        (33, 47, "asm", {"lens_f": 0.05}), (200, 256, "asm", {}), (64, 64, "fresnel", {"phase": True}),
+        (16, 16, "asm", {}), (256, 128, "asm", {"lens_f": -0.1, "phase": True}), (8, 300, "asm", {}),
+        (100, 100, "asm", {}),
+    ]
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    jobs = []
+    for k, (ny, nx, method, el) in enumerate(specs):
+        u = crandn(rng, 1 + k % 3, ny, nx, dtype=dtype)
+        d = float(rng.uniform(4e-6, 12e-6))
+        lam = float(rng.uniform(450e-9, 750e-9))
+        z = float(rng.uniform(0.005, 0.05))
+        opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, method=method, pad=2)
+        M = np.ones((ny, nx), complex)
+        gel, nel = {}, {}
+        if el.get("phase"):
+            phi = (rng.random((ny, nx)) * 2 * np.pi).astype(rdt)
+            gel["phase"] = to_gpu(phi, torch)
+            M = M * oracle.phase_mask(phi)
+        if "lens_f" in el:
+            gel["lens_f"] = el["lens_f"]
+            M = M * oracle.lens(ny, nx, d, d, lam, el["lens_f"])
+        jobs.append(dict(u=u, opt=opt, el=gel, M=M, meth=oracle.ASM if method == "asm" else oracle.FRESNEL))
+    return jobs
+
+
+def test_mixed_jobs_one_call_match_oracle_and_solo_runs():
+    tp = _tp()
+    announce("schedule: 10 mixed jobs forward in one call")
+    rng = np.random.default_rng(900)
+    jobs = _mixed_jobs(rng)
+    us = [to_gpu(j["u"], torch) for j in jobs]
+    outs = tp.propagate_jobs(us, [j["opt"] for j in jobs], elements=[j["el"] for j in jobs])
+    solo = [tp.propagate(u, j["opt"], **j["el"]) for u, j in zip(us, jobs)]
+    torch.cuda.synchronize()
+    for k, (j, o, s) in enumerate(zip(jobs, outs, solo)):
+        assert torch.equal(o, s), f"job {k} differs from its solo run"
+        o_ = j["opt"]
+        exp = oracle.propagate(oracle.modulate(j["u"], j["M"]), o_.dy, o_.dx, o_.wavelength, o_.z, j["meth"],
+                               padded=o_.padded_shape(*j["u"].shape[-2:]))
+        e = rel(to_np(o), exp)
+        assert e <= TOL, (k, e)
+
+
+def test_mixed_jobs_backward_shared_and_separate_gradients():
+    """Four backward jobs of different wavelengths and distances in one
+    call: jobs 0, 1 and 3 share one phase mask and accumulate into one
+    grad_phase tensor, job 2 has its own.  Equal, bit for bit, to single-job
+    calls made in call order, and to the oracle's sum over the sharing jobs."""
+    tp = _tp()
+    announce("schedule: backward jobs, shared grad_phase")
+    rng = np.random.default_rng(901)
+    n = 64
+    opt = [tp.Optics(dy=8e-6, dx=8e-6, wavelength=lam, z=z, pad=2)
+           for lam, z in ((500e-9, 0.02), (600e-9, 0.03), (700e-9, 0.01), (550e-9, 0.04))]
+    phi = (rng.random((n, n)) * 2 * np.pi).astype(np.float32)
+    phi_other = (rng.random((n, n)) * 2 * np.pi).astype(np.float32)
+    pg, pg2 = to_gpu(phi, torch), to_gpu(phi_other, torch)
+    # jobs 0, 1, 3 share mask pg and gradient gsh; job 2 has its own
+    masks = [pg, pg, pg2, pg]
+    saved = [crandn(rng, 2, n, n, dtype=np.complex64) for _ in range(4)]
+    gouts = [crandn(rng, 2, n, n, dtype=np.complex64) for _ in range(4)]
+    gsh = torch.zeros(n, n, dtype=torch.float32, device="cuda")
+    g2 = torch.zeros(n, n, dtype=torch.float32, device="cuda")
+    sv = [to_gpu(s, torch) for s in saved]
+    go = [to_gpu(g, torch) for g in gouts]
+    gins = tp.propagate_backward_jobs(go, opt, saved_ins=sv, grad_phases=[gsh, gsh, g2, gsh],
+                                      elements=[{"phase": m} for m in masks])
+    # sequential single-job calls in call order give the same accumulation order
+    gsh_seq = torch.zeros_like(gsh)
+    g2_seq = torch.zeros_like(g2)
+    gins_seq = [tp.propagate_backward(g, o, saved_in=s, grad_phase=(g2_seq if k == 2 else gsh_seq), phase=m)
+                for k, (g, o, s, m) in enumerate(zip(go, opt, sv, masks))]
+    torch.cuda.synchronize()
+    for a, b in zip(gins, gins_seq):
+        assert torch.equal(a, b)
+    assert torch.equal(gsh, gsh_seq) and torch.equal(g2, g2_seq)
+    # oracle: grad_phase sums over the jobs sharing the mask
+    exp_sh = np.zeros((n, n))
+    for k in (0, 1, 3):
+        o = opt[k]
+        gm = oracle.propagate(gouts[k], o.dy, o.dx, o.wavelength, o.z, oracle.ASM, 2, adjoint=True)
+        exp_sh += oracle.grad_phase(gm, oracle.modulate(saved[k], oracle.phase_mask(phi)))
+        exp_gin = oracle.modulate(gm, oracle.phase_mask(phi), conj=True)
+        assert rel(to_np(gins[k]), exp_gin) <= TOL
+    assert rel(to_np(gsh), exp_sh) <= 1e-4
+
+
+def test_dependent_jobs_keep_call_order():
+    """A chain u -> v -> w inside one call, a write-after-write pair, three
+    jobs accumulating into one loss scalar, and independent jobs between
+    them."""
+    tp = _tp()
+    announce("schedule: dependent jobs")
+    rng = np.random.default_rng(902)
+    n = 96
+    o1 = tp.Optics(dy=6e-6, dx=6e-6, wavelength=600e-9, z=0.02, pad=2)
+    o2 = tp.Optics(dy=6e-6, dx=6e-6, wavelength=600e-9, z=0.015, pad=2)
+    u = to_gpu(crandn(rng, 2, n, n, dtype=np.complex64), torch)
+    x = to_gpu(crandn(rng, 4, 128, 128, dtype=np.complex64), torch)
+    a1 = to_gpu(crandn(rng, 1, n, n, dtype=np.complex64), torch)
+    a2 = to_gpu(crandn(rng, 1, n, n, dtype=np.complex64), torch)
+    v = torch.empty_like(u)
+    w = torch.empty_like(u)
+    y = torch.empty_like(x)
+    ww = torch.empty_like(a1)
+    ox = tp.Optics(dy=4e-6, dx=4e-6, wavelength=500e-9, z=0.01, pad=2)
+    outs = tp.propagate_jobs([u, x, v, a1, a2], [o1, ox, o2, o1, o2], outs=[v, y, w, ww, ww])
+    torch.cuda.synchronize()
+    v_ref = tp.propagate(u, o1)
+    w_ref = tp.propagate(v_ref, o2)
+    y_ref = tp.propagate(x, ox)
+    ww_ref = tp.propagate(a2, o2)
+    torch.cuda.synchronize()
+    assert torch.equal(w, w_ref) and torch.equal(y, y_ref) and torch.equal(ww, ww_ref)
+    assert outs[2] is w
+
+    # three forward jobs with an MSE epilogue accumulating into one scalar
+    T = to_gpu((rng.random((n, n))).astype(np.float32), torch)
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    fields = [to_gpu(crandn(rng, 1, n, n, dtype=np.complex64), torch) for _ in range(3)]
+    grads = [torch.empty_like(f) for f in fields]
+    fouts = [torch.empty_like(f) for f in fields]  # kept alive until the call is done
+    jobs = [tp.make_job(f, o1, out=y, epi=tp._capi.TO_EPI_MSE, epi_ref=T, epi_scale=0.5,
+                        epi_grad=g, epi_loss=loss) for f, y, g in zip(fields, fouts, grads)]
+    keep = [tp.propagate_loss(f, o1, kind="mse", ref=T, scale=0.5) for f in fields]
+    tp._capi.propagate(jobs, tp._capi.TO_C64, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    total = sum(float(k[2].item()) for k in keep)
+    assert abs(float(loss.item()) - total) <= 1e-12 * abs(total)
+    for g, y, k in zip(grads, fouts, keep):
+        assert torch.equal(g, k[1]) and torch.equal(y, k[0])
+
+
+def test_graph_capture_replays_match_eager():
+    """Forward + backward of several jobs captured into one HIP graph (the
+    lanes fork and join inside it); three replays with new inputs copied in
+    and eager work in between, each against an eager run."""
+    tp = _tp()
+    announce("schedule: hipGraph capture of multi-job forward+backward")
+    rng = np.random.default_rng(903)
+    shapes = [(64, 64), (128, 96), (32, 32), (256, 256)]
+    opts = [tp.Optics(dy=5e-6, dx=5e-6, wavelength=600e-9 + 20e-9 * k, z=0.01 + 0.005 * k, pad=2)
+            for k in range(len(shapes))]
+    phis = [to_gpu((rng.random(s) * 2 * np.pi).astype(np.float32), torch) for s in shapes]
+    fields = [torch.zeros((2,) + s, dtype=torch.complex64, device="cuda") for s in shapes]
+    gouts = [torch.zeros_like(f) for f in fields]
+    outs = [torch.empty_like(f) for f in fields]
+    gins = [torch.empty_like(f) for f in fields]
+    gph = [torch.zeros(s, dtype=torch.float32, device="cuda") for s in shapes]
+    els = [{"phase": p} for p in phis]
+
+    def step():
+        for g in gph:
+            g.zero_()
+        tp.propagate_jobs(fields, opts, outs=outs, elements=els)
+        tp.propagate_backward_jobs(gouts, opts, saved_ins=fields, grad_ins=gins, grad_phases=gph, elements=els)
+
+    def fill(seed):
+        r = np.random.default_rng(seed)
+        for f, g in zip(fields, gouts):
+            f.copy_(to_gpu(crandn(r, *f.shape, dtype=np.complex64), torch))
+            g.copy_(to_gpu(crandn(r, *g.shape, dtype=np.complex64), torch))
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fill(1)
+        step()  # sizes the workspaces outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        fill(100 + rep)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = [t.clone() for t in outs + gins + gph]
+        junk = tp.propagate(to_gpu(crandn(rng, 1, 48, 48, dtype=np.complex64), torch), opts[0])  # eager work
+        step()
+        torch.cuda.synchronize()
+        ref = outs + gins + gph
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), f"replay {rep} differs from eager"
+        del junk
+
+
+@pytest.mark.timeout(600)
+def test_uneven_workload_128_jobs():
+    """The uneven-batch workload: 128 jobs, N in {256 ... 4096}, lambda in
+    [400, 800] nm, z log-uniform in [1 mm, 50 cm], spacing in [2, 20] um,
+    ASM, 2x padding, complex64; one forward call and one backward call over
+    all jobs.  Per job: bit-identical to its solo run, the adjoint identity
+    <P u, g> = <u, P^H g> within 1e-5 of |P u| |g|; FP64-oracle parity for
+    every 256^2 job and the first 512^2 and 1024^2 jobs (the oracle's cost
+    bounds the rest to the properties)."""
+    tp = _tp()
+    wl = workloads.uneven_jobs()
+    announce(f"schedule: uneven workload, {len(wl)} jobs, sum N^2 = {sum(j.n * j.n for j in wl):.3e}")
+    us, gs, opts = [], [], []
+    for j in wl:
+        us.append(to_gpu(j.field(), torch))
+        gs.append(to_gpu(j.upstream_grad(), torch))
+        opts.append(tp.Optics(dy=j.d, dx=j.d, wavelength=j.wavelength, z=j.z, pad=2))
+    outs = tp.propagate_jobs(us, opts)
+    gins = tp.propagate_backward_jobs(gs, opts)
+    torch.cuda.synchronize()
+    announce("uneven: forward and backward calls done")
+    oracle_sizes = {512: 1, 1024: 1}
+    for k, (j, u, g, o, gi, opt) in enumerate(zip(wl, us, gs, outs, gins, opts)):
+        so = tp.propagate(u, opt)
+        sg = tp.propagate_backward(g, opt)
+        torch.cuda.synchronize()
+        assert torch.equal(o, so), f"job {k} forward differs from its solo run"
+        assert torch.equal(gi, sg), f"job {k} backward differs from its solo run"
+        lhs = torch.vdot(g.reshape(-1).to(torch.complex128), o.reshape(-1).to(torch.complex128))
+        rhs = torch.vdot(gi.reshape(-1).to(torch.complex128), u.reshape(-1).to(torch.complex128))
+        scale = float(torch.linalg.vector_norm(o.to(torch.complex128)) * torch.linalg.vector_norm(
+            g.to(torch.complex128)))
+        assert abs(complex(lhs) - complex(rhs)) <= 1e-5 * scale, (k, j.n)
+        check = j.n == 256 or oracle_sizes.get(j.n, 0) > 0
+        if check:
+            if j.n in oracle_sizes:
+                oracle_sizes[j.n] -= 1
+            announce(f"uneven: oracle parity job {k} N={j.n}")
+            exp = oracle.propagate(j.field().astype(np.complex128), j.d, j.d, j.wavelength, j.z, oracle.ASM, 2)
+            assert rel(to_np(o), exp) <= TOL, (k, j.n)
+            expg = oracle.propagate(j.upstream_grad().astype(np.complex128), j.d, j.d, j.wavelength, j.z,
+                                    oracle.ASM, 2, adjoint=True)
+            assert rel(to_np(gi), expg) <= TOL, (k, j.n)
