@@ -299,23 +299,25 @@ def propagate_jobs(fields: Sequence[torch.Tensor], opts: Sequence[Optics], *, ou
 
 
 def propagate_backward_jobs(grads_out: Sequence[torch.Tensor], opts: Sequence[Optics], *, saved_ins=None,
-                            grad_ins=None, grad_phases=None, elements=None, ncomp: int = 1,
+                            grad_ins=None, grad_phases=None, grad_fs=None, elements=None, ncomp: int = 1,
                             plain: bool = False):
     """Backward of :func:`propagate_jobs` in one call: returns dL/d(in) per
-    job; element gradients accumulate into ``grad_phases[i]`` (jobs that
-    share a gradient tensor are run in call order on one lane)."""
+    job (``grad_ins[i]`` None: not formed); element gradients accumulate
+    into ``grad_phases[i]`` / ``grad_fs[i]`` (jobs that share a gradient
+    tensor are run in call order on one lane)."""
     n = len(grads_out)
     if len(opts) != n:
         raise ValueError("one Optics per gradient")
     grad_ins = [torch.empty_like(g) for g in grads_out] if grad_ins is None else list(grad_ins)
     saved_ins = [None] * n if saved_ins is None else list(saved_ins)
     grad_phases = [None] * n if grad_phases is None else list(grad_phases)
+    grad_fs = [None] * n if grad_fs is None else list(grad_fs)
     elements = [{}] * n if elements is None else list(elements)
     if n == 0:
         return grad_ins
     dt = _common_dtype(grads_out)
     jobs, grs = [], []
-    for go, o, gi, si, gp, el in zip(grads_out, opts, grad_ins, saved_ins, grad_phases, elements):
+    for go, o, gi, si, gp, gf, el in zip(grads_out, opts, grad_ins, saved_ins, grad_phases, grad_fs, elements):
         j = make_job(go, o, ncomp=ncomp, **el)
         j.in_ = None
         g = _capi.Grad()
@@ -326,6 +328,8 @@ def propagate_backward_jobs(grads_out: Sequence[torch.Tensor], opts: Sequence[Op
             g.saved_in = _ptr(_need(si, "saved_in", go.dtype, go, tuple(go.shape)))
         if gp is not None:
             g.grad_phase = _ptr(_need(gp, "grad_phase", _real_dtype(go), go, go.shape[-2:]))
+        if gf is not None:
+            g.grad_f = _ptr(_need(gf, "grad_f", torch.float64, go))
         jobs.append(j)
         grs.append(g)
     _capi.propagate_backward(jobs, grs, dt, _stream(grads_out[0]), plain=plain)
