@@ -65,30 +65,34 @@ def copy_calibration():
     return 0
 
 
+# Files that hold the propagation kernels' device code and launch shapes.
+KERNEL_SOURCES = ("fft.hpp", "kernels.hpp", "launch.hpp", "launch_impl.hpp", "inst_f32.hip", "inst_f64.hip")
+
+
 def kernel_source_digest() -> str:
-    """SHA-256 over the library's kernel sources (name + bytes, sorted)."""
+    """SHA-256 over the propagation kernels' sources (name + bytes)."""
     import hashlib
     d = os.path.join(ROOT, "paper_2411_18591_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel_label: str):
+def measured_traffic(kernel_label: str, launch_fields: int):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
-    counter runs, or None when none were taken for this kernel or the kernel
-    sources changed since."""
+    counter runs, or None when none were taken for this kernel, the kernel
+    sources changed since, or a launch now covers a different number of
+    fields."""
     path = os.path.join(ROOT, "profiles", "diffnet_1024_c64_hbm_traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != kernel_source_digest():
+    if rec.get("source_sha256") != kernel_source_digest() or rec.get("launch_fields") != launch_fields:
         return None
     ent = rec.get("per_launch", {}).get(kernel_label.split(".", 1)[-1])
     return None if ent is None else int(ent["bytes"])
@@ -226,7 +230,7 @@ def main():
         tfs = fl / avg_s / 1e12
         f_h = gbs / HBM_PEAK_GBS
         f_a = tfs / VALU_FP32_PEAK_TFLOPS
-        traffic = measured_traffic(name) if (N, B, L) == (1024, 64, 5) else None
+        traffic = measured_traffic(name, chunk) if (N, B, L) == (1024, 64, 5) else None
         if f_a >= f_h:
             roofline = {"bound": "alu", "achieved": round(tfs, 3), "peak": VALU_FP32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(f_a, 4), "traffic": traffic,

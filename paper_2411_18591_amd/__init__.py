@@ -26,7 +26,7 @@ from ._capi import ToError  # noqa: F401
 __all__ = [
     "Optics", "propagate", "modulate", "propagate_backward", "coherence_propagate",
     "propagate_ad", "propagate_jobs", "propagate_backward_jobs", "linear_polarizer", "waveplate",
-    "jones3", "version",
+    "jones3", "version", "autotune", "plan_get", "plan_set", "plan_clear", "plan_load", "plan_save",
 ]
 
 ASM = "asm"
@@ -334,6 +334,48 @@ def propagate_backward_jobs(grads_out: Sequence[torch.Tensor], opts: Sequence[Op
         grs.append(g)
     _capi.propagate_backward(jobs, grs, dt, _stream(grads_out[0]), plain=plain)
     return grad_ins
+
+
+def autotune(u: torch.Tensor, opt: Optics, *, out: Optional[torch.Tensor] = None, ncomp: int = 1,
+             **element):
+    """Time the launch schedules for this field's padded grid and dtype,
+    keep the fastest in the library's plan table (used by every later call
+    of that shape), and propagate u once with it.  Returns (out, plan)."""
+    if out is None:
+        out = torch.empty_like(u)
+    job = make_job(u, opt, out=out, ncomp=ncomp, **element)
+    plan = _capi.autotune(job, _dtype_code(u), _stream(u))
+    return out, plan
+
+
+def _dtype_of(dtype) -> int:
+    if dtype in (torch.complex64, "c64"):
+        return _capi.TO_C64
+    if dtype in (torch.complex128, "c128"):
+        return _capi.TO_C128
+    raise TypeError("dtype must be torch.complex64 or torch.complex128")
+
+
+def plan_get(py: int, px: int, dtype=torch.complex64):
+    """The plan stored for a padded grid and dtype, or None."""
+    return _capi.plan_get(py, px, _dtype_of(dtype))
+
+
+def plan_set(py: int, px: int, col_variant: int, chunk_mb: int, dtype=torch.complex64, us: float = 0.0):
+    _capi.plan_set(py, px, _dtype_of(dtype), col_variant, chunk_mb, us)
+
+
+def plan_clear():
+    _capi.plan_clear()
+
+
+def plan_load(path: str):
+    """Merge a plan file into the table (rejected whole if any line is bad)."""
+    _capi.plan_load(path)
+
+
+def plan_save(path: str):
+    _capi.plan_save(path)
 
 
 def coherence_propagate(gamma: torch.Tensor, opt: Optics, *, adjoint: bool = False,

@@ -46,6 +46,12 @@ EXPORTED = (
     "to_profile_entry",
     "to_propagate_plain",
     "to_propagate_backward_plain",
+    "to_autotune",
+    "to_plan_get",
+    "to_plan_set",
+    "to_plan_clear",
+    "to_plan_load",
+    "to_plan_save",
 )
 
 
@@ -86,6 +92,14 @@ class Grad(ctypes.Structure):
         ("saved_in", ctypes.c_void_p),
         ("grad_phase", ctypes.c_void_p),
         ("grad_f", ctypes.c_void_p),
+    ]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [
+        ("col_variant", ctypes.c_int32),
+        ("chunk_mb", ctypes.c_int32),
+        ("us", ctypes.c_double),
     ]
 
 
@@ -137,6 +151,19 @@ def lib() -> ctypes.CDLL:
         L.to_propagate_plain.restype = c_int
         L.to_propagate_backward_plain.argtypes = [JP, GP, c_int, c_int, ctypes.c_void_p]
         L.to_propagate_backward_plain.restype = c_int
+        PP = ctypes.POINTER(Plan)
+        L.to_autotune.argtypes = [JP, c_int, ctypes.c_void_p, PP]
+        L.to_autotune.restype = c_int
+        L.to_plan_get.argtypes = [c_int, c_int, c_int, PP, ctypes.POINTER(c_int)]
+        L.to_plan_get.restype = c_int
+        L.to_plan_set.argtypes = [c_int, c_int, c_int, PP]
+        L.to_plan_set.restype = c_int
+        L.to_plan_clear.argtypes = []
+        L.to_plan_clear.restype = c_int
+        L.to_plan_load.argtypes = [ctypes.c_char_p]
+        L.to_plan_load.restype = c_int
+        L.to_plan_save.argtypes = [ctypes.c_char_p]
+        L.to_plan_save.restype = c_int
         _lib = L
     return _lib
 
@@ -175,6 +202,36 @@ def coherence_propagate(job, dtype: int, adjoint: bool, grad, stream: int) -> No
     jp = ctypes.byref(job)
     gp = ctypes.byref(grad) if grad is not None else None
     check(lib().to_coherence_propagate(jp, dtype, 1 if adjoint else 0, gp, ctypes.c_void_p(stream)))
+
+
+def autotune(job, dtype: int, stream: int) -> dict:
+    p = Plan()
+    check(lib().to_autotune(ctypes.byref(job), dtype, ctypes.c_void_p(stream), ctypes.byref(p)))
+    return {"col_variant": p.col_variant, "chunk_mb": p.chunk_mb, "us": p.us}
+
+
+def plan_get(py: int, px: int, dtype: int):
+    p = Plan()
+    found = ctypes.c_int32()
+    check(lib().to_plan_get(py, px, dtype, ctypes.byref(p), ctypes.byref(found)))
+    return {"col_variant": p.col_variant, "chunk_mb": p.chunk_mb, "us": p.us} if found.value else None
+
+
+def plan_set(py: int, px: int, dtype: int, col_variant: int, chunk_mb: int, us: float = 0.0) -> None:
+    p = Plan(col_variant, chunk_mb, us)
+    check(lib().to_plan_set(py, px, dtype, ctypes.byref(p)))
+
+
+def plan_clear() -> None:
+    check(lib().to_plan_clear())
+
+
+def plan_load(path: str) -> None:
+    check(lib().to_plan_load(os.fsencode(path)))
+
+
+def plan_save(path: str) -> None:
+    check(lib().to_plan_save(os.fsencode(path)))
 
 
 def profile_begin() -> None:

@@ -16,6 +16,7 @@
 #include "coherence.hpp"
 #include "launch.hpp"
 #include "plain.hpp"
+#include "plan.hpp"
 
 using namespace toprop;
 
@@ -184,25 +185,52 @@ to_status ensure_partial(Lane* c, size_t count) {
   return TO_OK;
 }
 
-// Column-pass configuration (ColCfg variant); TOPROP_COL_VARIANT overrides
-// the default for tuning runs.
-int col_variant() {
+// Launch schedule of a job: column-pass configuration (ColCfg variant) and
+// chunk budget.  Precedence: the autotuner's candidate being timed (this
+// thread) > TOPROP_COL_VARIANT / TOPROP_CHUNK_MB > plan table > defaults.
+constexpr int kDefaultColVariant = 1;
+constexpr int kDefaultChunkMb = 128;
+thread_local const PlanEntry* t_force_plan = nullptr;
+
+int env_col_variant() {  // -1: not set
   static int v = [] {
     const char* s = getenv("TOPROP_COL_VARIANT");
-    int x = s ? atoi(s) : 1;
-    return (x >= 0 && x < kColVariants) ? x : 1;
+    if (!s) return -1;
+    int x = atoi(s);
+    return (x >= 0 && x < kColVariants) ? x : -1;
   }();
   return v;
 }
 
-size_t chunk_budget_bytes() {
-  static size_t budget = [] {
+long env_chunk_mb() {  // -1: not set
+  static long mb = [] {
     const char* s = getenv("TOPROP_CHUNK_MB");
-    long mb = s ? atol(s) : 128;
-    if (mb < 1) mb = 1;
-    return (size_t)mb << 20;
+    if (!s) return -1L;
+    long x = atol(s);
+    return x >= 1 ? x : -1L;
   }();
-  return budget;
+  return mb;
+}
+
+struct Schedule {
+  int col_variant;
+  size_t chunk_bytes;
+};
+
+Schedule schedule_for(int dtype, int ly, int lx) {
+  if (t_force_plan) return {t_force_plan->col_variant, (size_t)t_force_plan->chunk_mb << 20};
+  Schedule sc{kDefaultColVariant, (size_t)kDefaultChunkMb << 20};
+  PlanEntry pe;
+  const bool have = plan_lookup(dtype, ly, lx, &pe);
+  if (env_col_variant() >= 0)
+    sc.col_variant = env_col_variant();
+  else if (have)
+    sc.col_variant = pe.col_variant;
+  if (env_chunk_mb() >= 1)
+    sc.chunk_bytes = (size_t)env_chunk_mb() << 20;
+  else if (have)
+    sc.chunk_bytes = (size_t)pe.chunk_mb << 20;
+  return sc;
 }
 
 // ---------------------------------------------------------------------------
@@ -440,10 +468,15 @@ template <typename T>
 to_status make_geometry(const to_job& j, bool jones, Geometry* g) {
   g->lx = j.px;
   g->ly = j.py;
-  g->col_variant = col_variant();
+  const Schedule sc = schedule_for(sizeof(T) == 8 ? 1 : 0, g->ly, g->lx);
+  g->col_variant = sc.col_variant;
   // columns per column-pass block (cpb) and the scratch tile width (tm):
   // a tile row segment is one 128-byte cache line when the rows allow it
   g->tc = col_tile_width(g->ly, sizeof(T) == 8, g->col_variant);
+  if (g->tc <= 0) {  // configuration not available at this length
+    g->col_variant = kDefaultColVariant;
+    g->tc = col_tile_width(g->ly, sizeof(T) == 8, g->col_variant);
+  }
   if (g->tc > g->lx) g->tc = g->lx;
   g->tm = std::max<int>(g->tc, (int)(128 / sizeof(cx<T>)));
   if (g->tm > g->lx) g->tm = g->lx;
@@ -462,7 +495,7 @@ to_status make_geometry(const to_job& j, bool jones, Geometry* g) {
   g->comp_stride = npix;
   g->s_stride = (int64_t)g->lx * j.ny;
   const size_t per = (size_t)g->s_stride * g->nc_kernel * sizeof(cx<T>);
-  int64_t ch = (int64_t)(chunk_budget_bytes() / per);
+  int64_t ch = (int64_t)(sc.chunk_bytes / per);
   if (ch < 1) ch = 1;
   if (ch > g->nfields) ch = g->nfields;
   if (ch > 65535) ch = 65535;
@@ -1004,6 +1037,40 @@ to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, h
   return TO_OK;
 }
 
+
+// Times one forward propagation of `j` under the schedule `pe` (lane 0,
+// stream s): one untimed run, then the mean of `reps` runs between events.
+template <typename T>
+to_status time_candidate(const to_job& j, DeviceCtx* c, hipStream_t s, const PlanEntry& pe, int reps,
+                         hipEvent_t ea, hipEvent_t eb, double* us) {
+  t_force_plan = &pe;
+  size_t sb, pc;
+  workspace_need<T>(j, false, &sb, &pc);
+  to_status st = TO_OK;
+  if (sb) st = ensure_scratch(&c->lane[0], sb);
+  if (st == TO_OK && pc) st = ensure_partial(&c->lane[0], pc);
+  if (st == TO_OK) st = run_forward<T>(j, c, &c->lane[0], s);
+  hipError_t e = hipSuccess;
+  if (st == TO_OK) e = hipEventRecord(ea, s);
+  for (int r = 0; r < reps && st == TO_OK && e == hipSuccess; ++r) st = run_forward<T>(j, c, &c->lane[0], s);
+  if (st == TO_OK && e == hipSuccess) e = hipEventRecord(eb, s);
+  if (st == TO_OK && e == hipSuccess) e = hipEventSynchronize(eb);
+  float ms = 0.f;
+  if (st == TO_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
+  t_force_plan = nullptr;
+  if (st != TO_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "autotune timing");
+  *us = 1000.0 * ms / reps;
+  return TO_OK;
+}
+
+to_status plan_args(int32_t py, int32_t px, to_dtype dtype) {
+  if (dtype != TO_C64 && dtype != TO_C128) return fail(TO_E_INVAL, "dtype must be TO_C64 or TO_C128");
+  (void)py;
+  (void)px;
+  return TO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1180,6 +1247,114 @@ to_status to_coherence_propagate(const to_job* job, to_dtype dtype, int32_t adjo
   hipStream_t s = (hipStream_t)stream;
   return dtype == TO_C64 ? run_coherence<float>(j, adjoint, grad, c, s)
                          : run_coherence<double>(j, adjoint, grad, c, s);
+}
+
+to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* result) {
+  if (!job) return fail(TO_E_INVAL, "job is NULL");
+  to_status st = validate(*job, 0, dtype, MODE_FWD);
+  if (st != TO_OK) return st;
+  if (job->batch == 0) return fail(TO_E_INVAL, "autotune needs a job with batch >= 1");
+  DeviceCtx* c;
+  if ((st = get_ctx(&c)) != TO_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int dt = dtype == TO_C64 ? 0 : 1;
+  // tuning copy: no epilogue, output into a temporary buffer (the job may be
+  // in place, and every candidate runs it several times)
+  to_job tj = *job;
+  tj.epi = TO_EPI_NONE;
+  tj.epi_grad = nullptr;
+  tj.epi_loss = nullptr;
+  tj.epi_ref = nullptr;
+  void* tmp = nullptr;
+  hipError_t e = hipMalloc(&tmp, field_bytes(*job, dtype));
+  if (e != hipSuccess) return fail(TO_E_NOMEM, "autotune output allocation failed: %s", hipGetErrorString(e));
+  tj.out = tmp;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if ((e = hipEventCreate(&ea)) != hipSuccess || (e = hipEventCreate(&eb)) != hipSuccess) {
+    if (ea) hipEventDestroy(ea);
+    hipFree(tmp);
+    return hip_fail(e, "hipEventCreate");
+  }
+  static const int kChunkMb[] = {32, 64, 128, 256};
+  PlanEntry best{kDefaultColVariant, kDefaultChunkMb, -1.0};
+  std::vector<std::pair<int, int64_t>> seen;  // (variant, chunk fields) already timed
+  for (int v = 0; v < kColVariants && st == TO_OK; ++v) {
+    for (int mb : kChunkMb) {
+      PlanEntry pe{v, mb, 0.0};
+      Geometry g;
+      t_force_plan = &pe;
+      const to_status gs = dtype == TO_C64 ? make_geometry<float>(tj, (tj.el_flags & TO_EL_JONES) != 0, &g)
+                                           : make_geometry<double>(tj, (tj.el_flags & TO_EL_JONES) != 0, &g);
+      t_force_plan = nullptr;
+      if (gs != TO_OK || g.col_variant != v) continue;
+      const std::pair<int, int64_t> key(v, g.chunk);
+      bool dup = false;
+      for (auto& k : seen) dup |= k == key;
+      if (dup) continue;  // a larger budget that changes nothing
+      seen.push_back(key);
+      double us = 0.0;
+      st = dtype == TO_C64 ? time_candidate<float>(tj, c, s, pe, 3, ea, eb, &us)
+                           : time_candidate<double>(tj, c, s, pe, 3, ea, eb, &us);
+      if (st != TO_OK) break;
+      if (best.us < 0 || us < best.us) {
+        best = pe;
+        best.us = us;
+      }
+    }
+  }
+  hipEventDestroy(ea);
+  hipEventDestroy(eb);
+  hipFree(tmp);  // the timed runs were synchronized above
+  if (st != TO_OK) return st;
+  plan_store(dt, job->py, job->px, best);
+  if (!plan_env_path().empty()) {
+    std::string err;
+    plan_save_file(plan_env_path().c_str(), &err);  // best effort: the table holds the plan
+  }
+  if (result) *result = {best.col_variant, best.chunk_mb, best.us};
+  // the job itself, once, under the stored plan
+  return to_propagate(job, 1, dtype, stream);
+}
+
+to_status to_plan_get(int32_t py, int32_t px, to_dtype dtype, to_plan* plan, int32_t* found) {
+  to_status st = plan_args(py, px, dtype);
+  if (st != TO_OK) return st;
+  if (!plan || !found) return fail(TO_E_INVAL, "plan or found is NULL");
+  PlanEntry pe;
+  *found = plan_lookup(dtype == TO_C64 ? 0 : 1, py, px, &pe) ? 1 : 0;
+  if (*found) *plan = {pe.col_variant, pe.chunk_mb, pe.us};
+  return TO_OK;
+}
+
+to_status to_plan_set(int32_t py, int32_t px, to_dtype dtype, const to_plan* plan) {
+  to_status st = plan_args(py, px, dtype);
+  if (st != TO_OK) return st;
+  if (!plan) return fail(TO_E_INVAL, "plan is NULL");
+  const PlanEntry pe{plan->col_variant, plan->chunk_mb, plan->us};
+  std::string err;
+  const int dt = dtype == TO_C64 ? 0 : 1;
+  if (!plan_entry_valid(dt, py, px, pe, &err)) return fail(TO_E_INVAL, "%s", err.c_str());
+  plan_store(dt, py, px, pe);
+  return TO_OK;
+}
+
+to_status to_plan_clear(void) {
+  plan_clear();
+  return TO_OK;
+}
+
+to_status to_plan_load(const char* path) {
+  if (!path) return fail(TO_E_INVAL, "path is NULL");
+  std::string err;
+  if (plan_load_file(path, &err) != 0) return fail(TO_E_INVAL, "%s", err.c_str());
+  return TO_OK;
+}
+
+to_status to_plan_save(const char* path) {
+  if (!path) return fail(TO_E_INVAL, "path is NULL");
+  std::string err;
+  if (plan_save_file(path, &err) != 0) return fail(TO_E_INVAL, "%s", err.c_str());
+  return TO_OK;
 }
 
 const char* to_last_error(void) { return g_last_error.c_str(); }

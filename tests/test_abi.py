@@ -40,7 +40,8 @@ def test_struct_layout_matches_header(capi):
     fields = [f for f, _ in capi.Job._fields_]
     gfields = [f for f, _ in capi.Grad._fields_]
     src = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){"]
-    src.append('printf("%zu %zu\\n", sizeof(to_job), sizeof(to_grad));')
+    src.append('printf("%zu %zu %zu %zu %zu\\n", sizeof(to_job), sizeof(to_grad), sizeof(to_plan), '
+               'offsetof(to_plan, chunk_mb), offsetof(to_plan, us));')
     for f in fields:
         cf = "in" if f == "in_" else f
         src.append(f'printf("%zu\\n", offsetof(to_job, {cf}));')
@@ -56,6 +57,8 @@ def test_struct_layout_matches_header(capi):
     sizes = [int(x) for x in out]
     assert sizes[0] == ctypes.sizeof(capi.Job)
     assert sizes[1] == ctypes.sizeof(capi.Grad)
+    assert sizes[2:5] == [ctypes.sizeof(capi.Plan), capi.Plan.chunk_mb.offset, capi.Plan.us.offset]
+    sizes = sizes[:2] + sizes[5:]
     for f, off in zip(fields, sizes[2:2 + len(fields)]):
         assert getattr(capi.Job, f).offset == off, f
     for f, off in zip(gfields, sizes[2 + len(fields):]):

@@ -265,3 +265,43 @@ def test_uneven_workload_128_jobs():
             expg = oracle.propagate(j.upstream_grad().astype(np.complex128), j.d, j.d, j.wavelength, j.z,
                                     oracle.ASM, 2, adjoint=True)
             assert rel(to_np(gi), expg) <= TOL, (k, j.n)
+
+
+def test_autotune_stores_a_plan_and_keeps_parity():
+    """The autotuner times the schedules on a job, stores the fastest for
+    its padded grid, and leaves the job's output (in place too) and its
+    loss epilogue exactly as one propagation under that plan would."""
+    tp = _tp()
+    announce("autotune 4 x 256^2 c64 (padded 512^2)")
+    tp.plan_clear()
+    rng = np.random.default_rng(904)
+    n, d, lam, z = 256, 6e-6, 600e-9, 0.02
+    u = crandn(rng, 4, n, n, dtype=np.complex64)
+    phi = (rng.random((n, n)) * 2 * np.pi).astype(np.float32)
+    T = rng.random((n, n)).astype(np.float32)
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, pad=2)
+    ug, pg, Tg = to_gpu(u, torch), to_gpu(phi, torch), to_gpu(T, torch)
+    out, plan = tp.autotune(ug, opt, phase=pg)
+    torch.cuda.synchronize()
+    assert 0 <= plan["col_variant"] < 3 and plan["chunk_mb"] in (32, 64, 128, 256) and plan["us"] > 0
+    stored = tp.plan_get(2 * n, 2 * n)
+    assert (stored["col_variant"], stored["chunk_mb"]) == (plan["col_variant"], plan["chunk_mb"])
+    exp = oracle.propagate(oracle.modulate(u, oracle.phase_mask(phi)), d, d, lam, z, oracle.ASM, 2)
+    assert rel(to_np(out), exp) <= TOL
+    again = tp.propagate(ug, opt, phase=pg)  # uses the stored plan
+    torch.cuda.synchronize()
+    assert torch.equal(out, again)
+
+    # in place, with a loss epilogue: one propagation's worth of output and loss
+    w = ug.clone()
+    g = torch.empty_like(w)
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    job = tp.make_job(w, opt, out=w, phase=pg, epi=tp._capi.TO_EPI_MSE, epi_ref=Tg, epi_scale=0.25,
+                      epi_grad=g, epi_loss=loss)
+    tp._capi.autotune(job, tp._capi.TO_C64, torch.cuda.current_stream().cuda_stream)
+    # the reference runs under the plan this second tuning stored
+    ref_out, ref_g, ref_loss = tp.propagate_loss(ug, opt, kind="mse", ref=Tg, scale=0.25, phase=pg)
+    torch.cuda.synchronize()
+    assert torch.equal(w, ref_out) and torch.equal(g, ref_g)
+    assert float(loss.item()) == float(ref_loss.item())
+    tp.plan_clear()
