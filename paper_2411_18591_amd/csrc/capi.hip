@@ -464,6 +464,14 @@ struct Geometry {
   int col_variant;        // column-pass configuration (see ColCfg)
 };
 
+// Fields per column-pass block: as many as keep at least two blocks per
+// CU in flight (512 on 256 CUs), so the transfer function each block forms
+// is reused across fields.
+int col_fields_per_block(int ntiles, int nfields) {
+  const int64_t f = (int64_t)nfields * ntiles / 512;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(nfields, f));
+}
+
 template <typename T>
 to_status make_geometry(const to_job& j, bool jones, Geometry* g) {
   g->lx = j.px;
@@ -551,6 +559,7 @@ to_status run_forward(const to_job& j, DeviceCtx* c, Lane* ln, hipStream_t s, bo
     ca.tm = g.tm;
     ca.cpb = g.tc;
     ca.nfields = nf * g.nc_kernel;
+    ca.fpc = col_fields_per_block(g.lx / g.tc, ca.nfields);
     ca.h = h;
     ca.tw = twiddles<T>(c, g.ly);
     e = timed("fwd.col", g.ly, dbl, s, [&] {
@@ -644,6 +653,7 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, Lane* l
     ca.tm = g.tm;
     ca.cpb = g.tc;
     ca.nfields = nf * g.nc_kernel;
+    ca.fpc = col_fields_per_block(g.lx / g.tc, ca.nfields);
     ca.h = h;
     ca.tw = twiddles<T>(c, g.ly);
     e = timed("bwd.col", g.ly, dbl, s, [&] {

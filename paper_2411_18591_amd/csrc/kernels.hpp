@@ -323,6 +323,7 @@ struct ColArgs {
   int tm;               // column-tile width of the scratch layout
   int cpb;              // columns transformed per block (<= TC, divides tm)
   int nfields;
+  int fpc;              // fields per block: the transfer function is formed once for them
   TransferParams h;
   const cx<T>* tw;      // twiddles of length LY
 };
@@ -499,21 +500,15 @@ __global__ void __launch_bounds__(TC * (L / R))
   const int tm = a.tm, cpb = a.cpb;
   const int per = tm / cpb;
   const int tile = lb / per, h = lb - tile * per;
-  const int f = blockIdx.y;
   const int ny = a.ny;
-  cx<T>* base = a.scratch + (int64_t)f * a.s_stride + (int64_t)tile * ny * tm + h * cpb;
-  const bool active = f < a.nfields && c < cpb;
+  const int f_begin = (int)blockIdx.y * a.fpc;
+  const int f_end = min(f_begin + a.fpc, a.nfields);
+  const bool active = c < cpb;
 
-  cx<T> v[R];
-#pragma unroll
-  for (int m = 0; m < R; ++m) {
-    const int y = j + m * TT;
-    cx<T> val = {T(0), T(0)};
-    if (active && y < ny && (!HALF || m < R / 2)) val = base[(uint32_t)(y * tm + c)];
-    v[m] = val;
-  }
-  fft_wg<T, L, R, -1, HALF, TC>(v, j, lds + c, a.tw);
+  // Transfer function at this thread's bins, formed once and applied to
+  // every field of the block.
   const int kx = tile * tm + h * cpb + c;
+  cx<T> hv[R];
   bool done = false;
   if constexpr (std::is_same<T, float>::value) {
     if (a.h.fast) {
@@ -522,28 +517,45 @@ __global__ void __launch_bounds__(TC * (L / R))
       const float sxk = a.h.sx[kxc];
       const float lam_fy_unit = (float)(sqrt(a.h.lam2) * a.h.inv_lydy);
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        v[m] = cmul(v[m], transfer_fast(exk, sxk, j + m * TT, L, lam_fy_unit, a.h));
-        // keep the table loads of a group of four close to their use
-        if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-      }
+      for (int m = 0; m < R; ++m) hv[m] = transfer_fast(exk, sxk, j + m * TT, L, lam_fy_unit, a.h);
       done = true;
     }
   }
   if (!done) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = cmul(v[m], transfer_at<T>(kx, j + m * TT, a.lx, L, a.h));
+    for (int m = 0; m < R; ++m) hv[m] = transfer_at<T>(kx, j + m * TT, a.lx, L, a.h);
   }
-  // Opaque copy of j: the inverse transform reloads its twiddles instead of
-  // keeping the forward transform's (same addresses) live across the multiply.
-  int j2 = j;
-  asm volatile("" : "+v"(j2));
-  fft_wg<T, L, R, +1, false, TC>(v, j2, lds + c, a.tw);
-  if (active) {
+
+  for (int f = f_begin; f < f_end; ++f) {
+    // Opaque per-field copy of j: the twiddle loads (addresses depend on j
+    // only) are not hoisted out of the field loop, which would hold every
+    // twiddle of both transforms in registers.
+    int j1 = j;
+    asm volatile("" : "+v"(j1));
+    cx<T>* base = a.scratch + (int64_t)f * a.s_stride + (int64_t)tile * ny * tm + h * cpb;
+    cx<T> v[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int y = j + m * TT;
-      if ((!HALF || m < R / 2) && y < ny) base[(uint32_t)(y * tm + c)] = v[m];
+      cx<T> val = {T(0), T(0)};
+      if (active && y < ny && (!HALF || m < R / 2)) val = base[(uint32_t)(y * tm + c)];
+      v[m] = val;
+    }
+    fft_wg<T, L, R, -1, HALF, TC>(v, j1, lds + c, a.tw);
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = cmul(v[m], hv[m]);
+    // Opaque copy of j: the inverse transform reloads its twiddles instead
+    // of keeping the forward transform's (same addresses) live across the
+    // multiply.
+    int j2 = j;
+    asm volatile("" : "+v"(j2));
+    fft_wg<T, L, R, +1, false, TC>(v, j2, lds + c, a.tw);
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int y = j + m * TT;
+        if ((!HALF || m < R / 2) && y < ny) base[(uint32_t)(y * tm + c)] = v[m];
+      }
     }
   }
 }

@@ -55,7 +55,7 @@ hipError_t Launch<T>::col(int ly, bool half, int ntiles, int nfields, int varian
     constexpr int L = decltype(Lc)::value;
     auto go = [&](auto vc) {
       using C = ColCfg<T, L, decltype(vc)::value>;
-      dim3 grid(ntiles, nfields);
+      dim3 grid(ntiles, (nfields + a.fpc - 1) / a.fpc);
       dim3 block(C::threads);
       if (half)
         hipLaunchKernelGGL((col_kernel<T, L, C::R, C::TC, true>), grid, block, 0, s, a);
