@@ -119,6 +119,14 @@ def kernel_model(name: str, wl, chunk_fields: int):
     elif ".col_" in name:
         by = f * 2 * N * P * c
         fl = f * P * (2 * fft_flops(P) + 6 * P)
+    elif ".row_mid_" in name:
+        # fused layer boundary: intermediate in, layer output (forward) or
+        # input gradient (backward) out, intermediate of the next layer out
+        if name.startswith("fwd"):
+            by = f * (2 * N * P * c + N * N * c) + N * N * 4
+        else:  # also reads the saved layer input; mask in, gradient partials out
+            by = f * (2 * N * P * c + 2 * N * N * c) + 2 * N * N * 4
+        fl = f * N * 2 * fft_flops(P)
     elif ".row_inv_" in name:
         if name.startswith("fwd"):
             by = f * (N * P * c + N * N * c)

@@ -70,6 +70,10 @@ std::vector<cx<T>> build_twiddles() {
 // priority) forked from and joined back into it with events.  Each lane has
 // its own scratch, reduction partials and transfer-function tables.
 constexpr int kLanes = 4;
+// Longest chain of propagations run with fused layer boundaries (one set of
+// transfer-function tables per layer).
+constexpr int kMaxChain = 16;
+constexpr size_t kTableSlotBytes = (size_t)kMaxLen * 2 * (sizeof(cx<float>) + sizeof(float));
 
 struct Lane {
   hipStream_t stream = nullptr;  // null for lane 0 (the caller's stream is used)
@@ -78,8 +82,8 @@ struct Lane {
   size_t scratch_bytes = 0;
   double* partial = nullptr;
   size_t partial_count = 0;
-  // separable transfer-function tables of the job being run: ex, ey
-  // (complex64) and sx, sy (float), kMaxLen entries each
+  // separable transfer-function tables: ex, ey (complex64) and sx, sy
+  // (float), kMaxLen entries each, one slot per layer of a chain
   void* tf = nullptr;
 };
 
@@ -120,7 +124,7 @@ to_status get_ctx(DeviceCtx** out) {
       return hip_fail(e, "twiddle upload");
     for (int l = 0; l < kLanes; ++l) {
       Lane& ln = c.lane[l];
-      if ((e = hipMalloc(&ln.tf, (size_t)kMaxLen * 2 * (sizeof(cx<float>) + sizeof(float)))) != hipSuccess)
+      if ((e = hipMalloc(&ln.tf, kTableSlotBytes * kMaxChain)) != hipSuccess)
         return fail(TO_E_NOMEM, "table allocation failed: %s", hipGetErrorString(e));
       if (l > 0) {
         if ((e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking)) != hipSuccess)
@@ -387,10 +391,10 @@ double asm_remainder_cycles(const to_job& j) {
 constexpr double kFastRemainderCycles = 1.0;
 
 template <typename T>
-hipError_t prepare_transfer(const to_job& j, Lane* c, hipStream_t s, TransferParams* h) {
+hipError_t prepare_transfer(const to_job& j, Lane* c, hipStream_t s, TransferParams* h, int slot = 0) {
   if (sizeof(T) != 4) return hipSuccess;
   if (j.method == TO_ASM && !(asm_remainder_cycles(j) <= kFastRemainderCycles)) return hipSuccess;
-  cx<float>* ex = (cx<float>*)c->tf;
+  cx<float>* ex = (cx<float>*)((char*)c->tf + (size_t)slot * kTableSlotBytes);
   cx<float>* ey = ex + kMaxLen;
   float* sx = (float*)(ey + kMaxLen);
   float* sy = sx + kMaxLen;
@@ -511,206 +515,6 @@ to_status make_geometry(const to_job& j, bool jones, Geometry* g) {
   return TO_OK;
 }
 
-template <typename T>
-to_status run_forward(const to_job& j, DeviceCtx* c, Lane* ln, hipStream_t s, bool conj_h = false,
-                      const cx<T>* coh_m = nullptr) {
-  if (j.batch == 0) return TO_OK;
-  Geometry g;
-  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
-  to_status st = make_geometry<T>(j, jones, &g);
-  if (st != TO_OK) return st;
-  st = ensure_scratch(ln, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
-  if (st != TO_OK) return st;
-  if (j.epi != TO_EPI_NONE) {
-    st = ensure_partial(ln, (size_t)g.chunk * j.ny);
-    if (st != TO_OK) return st;
-  }
-  cx<T>* scratch = (cx<T>*)ln->scratch;
-  TransferParams h = make_transfer(j, conj_h);
-  const ElementParams<T> el = make_element<T>(j, coh_m ? 0u : j.el_flags);
-  hipError_t e = prepare_transfer<T>(j, ln, s, &h);
-  if (e != hipSuccess) return hip_fail(e, "transfer table launch");
-  for (int64_t f0 = 0; f0 < g.nfields; f0 += g.chunk) {
-    const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
-    RowFwdArgs<T> ra;
-    ra.fpb = fields_per_block(j, (j.ny + g.rows_per_block - 1) / g.rows_per_block, nf);
-    ra.coh_m = coh_m;
-    ra.f_off = f0;
-    ra.in = (const cx<T>*)j.in + f0 * g.in_stride;
-    ra.scratch = scratch;
-    ra.in_stride = g.in_stride;
-    ra.comp_stride = g.comp_stride;
-    ra.s_stride = g.s_stride;
-    ra.ny = j.ny;
-    ra.nx = j.nx;
-    ra.tc_shift = g.tc_shift;
-    ra.nfields = nf;
-    ra.el = el;
-    ra.tw = twiddles<T>(c, g.lx);
-    const bool dbl = sizeof(T) == 8;
-    e = timed("fwd.row_fwd", g.lx, dbl, s,
-              [&] { return Launch<T>::row_fwd(g.lx, g.half_x, g.nc_kernel, j.ny, nf, ra, s); });
-    if (e != hipSuccess) return hip_fail(e, "row_fwd launch");
-    ColArgs<T> ca;
-    ca.scratch = scratch;
-    ca.s_stride = g.s_stride;
-    ca.ny = j.ny;
-    ca.lx = g.lx;
-    ca.tm = g.tm;
-    ca.cpb = g.tc;
-    ca.nfields = nf * g.nc_kernel;
-    ca.fpc = col_fields_per_block(g.lx / g.tc, ca.nfields);
-    ca.h = h;
-    ca.tw = twiddles<T>(c, g.ly);
-    e = timed("fwd.col", g.ly, dbl, s, [&] {
-      return Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, g.col_variant, ca, s);
-    });
-    if (e != hipSuccess) return hip_fail(e, "col launch");
-    RowInvArgs<T> ia;
-    memset(&ia, 0, sizeof(ia));
-    ia.scratch = scratch;
-    ia.s_stride = g.s_stride;
-    ia.comp_stride = g.comp_stride;
-    ia.out = (cx<T>*)j.out + f0 * g.in_stride;
-    ia.out_stride = g.in_stride;
-    ia.ny = j.ny;
-    ia.nx = j.nx;
-    ia.tc_shift = g.tc_shift;
-    ia.nfields = nf;
-    ia.scale = (T)(1.0 / ((double)g.lx * (double)g.ly));
-    ia.tw = twiddles<T>(c, g.lx);
-    ia.epi = j.epi;
-    ia.epi_ref = (const T*)j.epi_ref;
-    ia.epi_scale = (T)j.epi_scale;
-    ia.epi_grad = j.epi_grad ? (cx<T>*)j.epi_grad + f0 * g.in_stride : nullptr;
-    ia.row_partial = ln->partial;
-    ia.backward = 0;
-    ia.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block, nf);
-    const int inv_blocks_y = (nf + ia.fpb - 1) / ia.fpb;
-    ia.el = make_element<T>(j, 0);
-    e = timed("fwd.row_inv", g.lx, dbl, s,
-              [&] { return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, inv_blocks_y, ia, s); });
-    if (e != hipSuccess) return hip_fail(e, "row_inv launch");
-    if (j.epi != TO_EPI_NONE) {
-      e = timed("fwd.loss_reduce", 0, dbl, s, [&] {
-        return launch_reduce_add(ln->partial, (int64_t)nf * j.ny, j.epi_scale, j.epi_loss, s);
-      });
-      if (e != hipSuccess) return hip_fail(e, "loss reduction launch");
-    }
-  }
-  return TO_OK;
-}
-
-template <typename T>
-to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, Lane* ln, hipStream_t s) {
-  if (j.batch == 0) return TO_OK;
-  Geometry g;
-  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
-  to_status st = make_geometry<T>(j, jones, &g);
-  if (st != TO_OK) return st;
-  st = ensure_scratch(ln, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
-  if (st != TO_OK) return st;
-  const bool want_f = (j.el_flags & TO_EL_LENS) && gr.grad_f;
-  if (want_f) {
-    st = ensure_partial(ln, (size_t)j.ny);
-    if (st != TO_OK) return st;
-  }
-  cx<T>* scratch = (cx<T>*)ln->scratch;
-  TransferParams h = make_transfer(j, true);
-  const ElementParams<T> el = make_element<T>(j, j.el_flags);
-  hipError_t e = prepare_transfer<T>(j, ln, s, &h);
-  if (e != hipSuccess) return hip_fail(e, "transfer table launch");
-  // The gradient rows carry no element: the first two passes treat every
-  // component as an independent field.
-  const int64_t flat_per_group = g.nc_kernel;
-  for (int64_t f0 = 0; f0 < g.nfields; f0 += g.chunk) {
-    const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
-    RowFwdArgs<T> ra;
-    memset(&ra, 0, sizeof(ra));
-    ra.in = (const cx<T>*)gr.grad_out + f0 * g.in_stride;
-    ra.scratch = scratch;
-    ra.in_stride = g.comp_stride;
-    ra.comp_stride = g.comp_stride;
-    ra.s_stride = g.s_stride;
-    ra.ny = j.ny;
-    ra.nx = j.nx;
-    ra.tc_shift = g.tc_shift;
-    ra.nfields = nf * (int)flat_per_group;
-    ra.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block,
-                                   nf * (int)flat_per_group);
-    ra.el = make_element<T>(j, 0);
-    ra.tw = twiddles<T>(c, g.lx);
-    const bool dbl = sizeof(T) == 8;
-    e = timed("bwd.row_fwd", g.lx, dbl, s, [&] {
-      return Launch<T>::row_fwd(g.lx, g.half_x, 1, j.ny, nf * (int)flat_per_group, ra, s);
-    });
-    if (e != hipSuccess) return hip_fail(e, "row_fwd launch");
-    ColArgs<T> ca;
-    ca.scratch = scratch;
-    ca.s_stride = g.s_stride;
-    ca.ny = j.ny;
-    ca.lx = g.lx;
-    ca.tm = g.tm;
-    ca.cpb = g.tc;
-    ca.nfields = nf * g.nc_kernel;
-    ca.fpc = col_fields_per_block(g.lx / g.tc, ca.nfields);
-    ca.h = h;
-    ca.tw = twiddles<T>(c, g.ly);
-    e = timed("bwd.col", g.ly, dbl, s, [&] {
-      return Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, nf * g.nc_kernel, g.col_variant, ca, s);
-    });
-    if (e != hipSuccess) return hip_fail(e, "col launch");
-    RowInvArgs<T> ia;
-    memset(&ia, 0, sizeof(ia));
-    ia.scratch = scratch;
-    ia.s_stride = g.s_stride;
-    ia.comp_stride = g.comp_stride;
-    ia.out = gr.grad_in ? (cx<T>*)gr.grad_in + f0 * g.in_stride : nullptr;
-    ia.out_stride = g.in_stride;
-    ia.ny = j.ny;
-    ia.nx = j.nx;
-    ia.tc_shift = g.tc_shift;
-    ia.nfields = nf;
-    ia.scale = (T)(1.0 / ((double)g.lx * (double)g.ly));
-    ia.tw = twiddles<T>(c, g.lx);
-    ia.epi = TO_EPI_NONE;
-    ia.backward = 1;
-    ia.fpb = nf;
-    ia.el = el;
-    ia.saved_in = gr.saved_in ? (const cx<T>*)gr.saved_in + f0 * g.in_stride : nullptr;
-    ia.grad_phase = (T*)gr.grad_phase;
-    ia.lens_f = j.el_f;
-    ia.lens_partial = want_f ? ln->partial : nullptr;
-    e = timed("bwd.row_inv", g.lx, dbl, s,
-              [&] { return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, 1, ia, s); });
-    if (e != hipSuccess) return hip_fail(e, "row_inv launch");
-    if (want_f) {
-      e = timed("bwd.lens_reduce", 0, dbl, s,
-                [&] { return launch_reduce_add(ln->partial, j.ny, 1.0, gr.grad_f, s); });
-      if (e != hipSuccess) return hip_fail(e, "lens gradient reduction launch");
-    }
-  }
-  return TO_OK;
-}
-
-template <typename T>
-to_status run_modulate(const to_job& j, int adjoint, hipStream_t s) {
-  if (j.batch == 0) return TO_OK;
-  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
-  const int64_t npix = (int64_t)j.ny * j.nx;
-  const int nc = jones ? 3 : 1;
-  const int64_t nfields = jones ? j.batch : j.batch * j.ncomp;
-  if (nfields > INT32_MAX) return fail(TO_E_UNSUPPORTED, "too many fields");
-  const ElementParams<T> el = make_element<T>(j, j.el_flags);
-  hipError_t e = Launch<T>::modulate(nc, (const cx<T>*)j.in, (cx<T>*)j.out, nc * npix, npix, j.ny,
-                                     j.nx, (int)nfields, adjoint, el, s);
-  if (e != hipSuccess) return hip_fail(e, "modulate launch");
-  return TO_OK;
-}
-
-// ---------------------------------------------------------------------------
-// Scheduling of the jobs of one call over the lanes.
-// ---------------------------------------------------------------------------
 struct Span {
   uintptr_t lo, hi;
 };
@@ -733,6 +537,437 @@ void element_spans(const to_job& j, to_dtype dt, std::vector<Span>* rd) {
   if (j.epi != TO_EPI_NONE) rd->push_back(span(j.epi_ref, px * re));
 }
 
+// Argument records of the three passes for one chunk of `nf` fields.
+template <typename T>
+RowFwdArgs<T> row_fwd_args(const to_job& j, const Geometry& g, DeviceCtx* c, cx<T>* scratch, const cx<T>* in,
+                           int64_t in_stride, int nf, const ElementParams<T>& el, const cx<T>* coh_m,
+                           int64_t f0) {
+  RowFwdArgs<T> ra;
+  memset(&ra, 0, sizeof(ra));
+  ra.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block, nf);
+  ra.coh_m = coh_m;
+  ra.f_off = f0;
+  ra.in = in;
+  ra.scratch = scratch;
+  ra.in_stride = in_stride;
+  ra.comp_stride = g.comp_stride;
+  ra.s_stride = g.s_stride;
+  ra.ny = j.ny;
+  ra.nx = j.nx;
+  ra.tc_shift = g.tc_shift;
+  ra.nfields = nf;
+  ra.el = el;
+  ra.tw = twiddles<T>(c, g.lx);
+  return ra;
+}
+
+template <typename T>
+ColArgs<T> col_args(const to_job& j, const Geometry& g, DeviceCtx* c, cx<T>* scratch, int nf,
+                    const TransferParams& h) {
+  ColArgs<T> ca;
+  ca.scratch = scratch;
+  ca.s_stride = g.s_stride;
+  ca.ny = j.ny;
+  ca.lx = g.lx;
+  ca.tm = g.tm;
+  ca.cpb = g.tc;
+  ca.nfields = nf;
+  ca.fpc = col_fields_per_block(g.lx / g.tc, nf);
+  ca.h = h;
+  ca.tw = twiddles<T>(c, g.ly);
+  return ca;
+}
+
+template <typename T>
+RowInvArgs<T> row_inv_args(const to_job& j, const Geometry& g, DeviceCtx* c, cx<T>* scratch, int nf) {
+  RowInvArgs<T> ia;
+  memset(&ia, 0, sizeof(ia));
+  ia.scratch = scratch;
+  ia.s_stride = g.s_stride;
+  ia.comp_stride = g.comp_stride;
+  ia.out_stride = g.in_stride;
+  ia.ny = j.ny;
+  ia.nx = j.nx;
+  ia.tc_shift = g.tc_shift;
+  ia.nfields = nf;
+  ia.scale = (T)(1.0 / ((double)g.lx * (double)g.ly));
+  ia.tw = twiddles<T>(c, g.lx);
+  ia.epi = TO_EPI_NONE;
+  return ia;
+}
+
+// Launches of one chunk's passes (profiled under `phase`).
+template <typename T>
+hipError_t launch_row_fwd(const char* phase, const Geometry& g, int ny, int nf, int nc, const RowFwdArgs<T>& ra,
+                          hipStream_t s) {
+  return timed(phase, g.lx, sizeof(T) == 8, s,
+               [&] { return Launch<T>::row_fwd(g.lx, g.half_x, nc, ny, nf, ra, s); });
+}
+
+template <typename T>
+hipError_t launch_col(const char* phase, const Geometry& g, const ColArgs<T>& ca, hipStream_t s) {
+  return timed(phase, g.ly, sizeof(T) == 8, s, [&] {
+    return Launch<T>::col(g.ly, g.half_y, g.lx / g.tc, ca.nfields, g.col_variant, ca, s);
+  });
+}
+
+// Forward row_inv with the job's epilogue, then the loss reduction.
+template <typename T>
+to_status finish_forward_chunk(const to_job& j, const Geometry& g, DeviceCtx* c, Lane* ln, cx<T>* scratch,
+                               int64_t f0, int nf, hipStream_t s) {
+  RowInvArgs<T> ia = row_inv_args<T>(j, g, c, scratch, nf);
+  ia.out = (cx<T>*)j.out + f0 * g.in_stride;
+  ia.epi = j.epi;
+  ia.epi_ref = (const T*)j.epi_ref;
+  ia.epi_scale = (T)j.epi_scale;
+  ia.epi_grad = j.epi_grad ? (cx<T>*)j.epi_grad + f0 * g.in_stride : nullptr;
+  ia.row_partial = ln->partial;
+  ia.backward = 0;
+  ia.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block, nf);
+  const int inv_blocks_y = (nf + ia.fpb - 1) / ia.fpb;
+  ia.el = make_element<T>(j, 0);
+  const bool dbl = sizeof(T) == 8;
+  hipError_t e = timed("fwd.row_inv", g.lx, dbl, s, [&] {
+    return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, inv_blocks_y, ia, s);
+  });
+  if (e != hipSuccess) return hip_fail(e, "row_inv launch");
+  if (j.epi != TO_EPI_NONE) {
+    e = timed("fwd.loss_reduce", 0, dbl, s, [&] {
+      return launch_reduce_add(ln->partial, (int64_t)nf * j.ny, j.epi_scale, j.epi_loss, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "loss reduction launch");
+  }
+  return TO_OK;
+}
+
+// Backward row_inv of one chunk (element adjoint, parameter gradients), then
+// the lens-gradient reduction.
+template <typename T>
+to_status finish_backward_chunk(const to_job& j, const to_grad& gr, const Geometry& g, DeviceCtx* c, Lane* ln,
+                                cx<T>* scratch, int64_t f0, int nf, hipStream_t s) {
+  const bool want_f = (j.el_flags & TO_EL_LENS) && gr.grad_f;
+  RowInvArgs<T> ia = row_inv_args<T>(j, g, c, scratch, nf);
+  ia.out = gr.grad_in ? (cx<T>*)gr.grad_in + f0 * g.in_stride : nullptr;
+  ia.backward = 1;
+  ia.fpb = nf;
+  ia.el = make_element<T>(j, j.el_flags);
+  ia.saved_in = gr.saved_in ? (const cx<T>*)gr.saved_in + f0 * g.in_stride : nullptr;
+  ia.grad_phase = (T*)gr.grad_phase;
+  ia.lens_f = j.el_f;
+  ia.lens_partial = want_f ? ln->partial : nullptr;
+  const bool dbl = sizeof(T) == 8;
+  hipError_t e = timed("bwd.row_inv", g.lx, dbl, s,
+                       [&] { return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, 1, ia, s); });
+  if (e != hipSuccess) return hip_fail(e, "row_inv launch");
+  if (want_f) {
+    e = timed("bwd.lens_reduce", 0, dbl, s,
+              [&] { return launch_reduce_add(ln->partial, j.ny, 1.0, gr.grad_f, s); });
+    if (e != hipSuccess) return hip_fail(e, "lens gradient reduction launch");
+  }
+  return TO_OK;
+}
+
+template <typename T>
+to_status run_forward(const to_job& j, DeviceCtx* c, Lane* ln, hipStream_t s, bool conj_h = false,
+                      const cx<T>* coh_m = nullptr) {
+  if (j.batch == 0) return TO_OK;
+  Geometry g;
+  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
+  to_status st = make_geometry<T>(j, jones, &g);
+  if (st != TO_OK) return st;
+  st = ensure_scratch(ln, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
+  if (st != TO_OK) return st;
+  if (j.epi != TO_EPI_NONE) {
+    st = ensure_partial(ln, (size_t)g.chunk * j.ny);
+    if (st != TO_OK) return st;
+  }
+  cx<T>* scratch = (cx<T>*)ln->scratch;
+  TransferParams h = make_transfer(j, conj_h);
+  const ElementParams<T> el = make_element<T>(j, coh_m ? 0u : j.el_flags);
+  hipError_t e = prepare_transfer<T>(j, ln, s, &h);
+  if (e != hipSuccess) return hip_fail(e, "transfer table launch");
+  for (int64_t f0 = 0; f0 < g.nfields; f0 += g.chunk) {
+    const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
+    RowFwdArgs<T> ra = row_fwd_args<T>(j, g, c, scratch, (const cx<T>*)j.in + f0 * g.in_stride, g.in_stride, nf,
+                                       el, coh_m, f0);
+    if ((e = launch_row_fwd<T>("fwd.row_fwd", g, j.ny, nf, g.nc_kernel, ra, s)) != hipSuccess)
+      return hip_fail(e, "row_fwd launch");
+    if ((e = launch_col<T>("fwd.col", g, col_args<T>(j, g, c, scratch, nf * g.nc_kernel, h), s)) != hipSuccess)
+      return hip_fail(e, "col launch");
+    if ((st = finish_forward_chunk<T>(j, g, c, ln, scratch, f0, nf, s)) != TO_OK) return st;
+  }
+  return TO_OK;
+}
+
+template <typename T>
+to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, Lane* ln, hipStream_t s) {
+  if (j.batch == 0) return TO_OK;
+  Geometry g;
+  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
+  to_status st = make_geometry<T>(j, jones, &g);
+  if (st != TO_OK) return st;
+  st = ensure_scratch(ln, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
+  if (st != TO_OK) return st;
+  if ((j.el_flags & TO_EL_LENS) && gr.grad_f) {
+    st = ensure_partial(ln, (size_t)j.ny);
+    if (st != TO_OK) return st;
+  }
+  cx<T>* scratch = (cx<T>*)ln->scratch;
+  TransferParams h = make_transfer(j, true);
+  hipError_t e = prepare_transfer<T>(j, ln, s, &h);
+  if (e != hipSuccess) return hip_fail(e, "transfer table launch");
+  // The gradient rows carry no element: the first two passes treat every
+  // component as an independent field.
+  const ElementParams<T> none = make_element<T>(j, 0);
+  for (int64_t f0 = 0; f0 < g.nfields; f0 += g.chunk) {
+    const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
+    const int flat = nf * g.nc_kernel;
+    RowFwdArgs<T> ra = row_fwd_args<T>(j, g, c, scratch, (const cx<T>*)gr.grad_out + f0 * g.in_stride,
+                                       g.comp_stride, flat, none, nullptr, 0);
+    if ((e = launch_row_fwd<T>("bwd.row_fwd", g, j.ny, flat, 1, ra, s)) != hipSuccess)
+      return hip_fail(e, "row_fwd launch");
+    if ((e = launch_col<T>("bwd.col", g, col_args<T>(j, g, c, scratch, flat, h), s)) != hipSuccess)
+      return hip_fail(e, "col launch");
+    if ((st = finish_backward_chunk<T>(j, gr, g, c, ln, scratch, f0, nf, s)) != TO_OK) return st;
+  }
+  return TO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Chains: consecutive jobs of one call where each propagation's input is the
+// previous one's output (the layers of a diffractive network).  They run
+// chunk by chunk through all layers, the boundary between two layers in one
+// fused row pass (row_mid), so a chunk's intermediate stays in the last-level
+// cache across layers and no layer output is read back.  Results equal those
+// of running the jobs one by one.
+// ---------------------------------------------------------------------------
+bool same_grid(const to_job& a, const to_job& b) {
+  return a.ny == b.ny && a.nx == b.nx && a.py == b.py && a.px == b.px && a.batch == b.batch &&
+         a.ncomp == b.ncomp && !(a.el_flags & TO_EL_JONES) && !(b.el_flags & TO_EL_JONES) && a.batch > 0;
+}
+
+// Field buffers of a chain may be shared between layers only whole (same
+// start, same layout), so that processing chunk by chunk reads and writes
+// every field in the order the one-by-one run would.
+bool whole_or_disjoint(const std::vector<Span>& v) {
+  for (size_t i = 0; i < v.size(); ++i)
+    for (size_t k = i + 1; k < v.size(); ++k)
+      if (overlaps(v[i], v[k]) && (v[i].lo != v[k].lo || v[i].hi != v[k].hi)) return false;
+  return true;
+}
+
+bool env_no_chain() {
+  static const bool v = getenv("TOPROP_NO_CHAIN") != nullptr;
+  return v;
+}
+
+// Length of the forward chain starting at jobs[i] (1 = no chain).
+int forward_chain_len(const to_job* jobs, int n, int i, to_dtype dt) {
+  if (env_no_chain()) return 1;
+  int len = 1;
+  while (i + len < n && len < kMaxChain) {
+    const to_job& a = jobs[i + len - 1];
+    const to_job& b = jobs[i + len];
+    if (!same_grid(a, b) || a.epi != TO_EPI_NONE || b.in != a.out || a.out == nullptr) break;
+    std::vector<Span> v;
+    for (int k = i; k <= i + len; ++k) {
+      const size_t fb = field_bytes(jobs[k], dt);
+      v.push_back(span(jobs[k].in, fb));
+      v.push_back(span(jobs[k].out, fb));
+      if (jobs[k].epi != TO_EPI_NONE) v.push_back(span(jobs[k].epi_grad, fb));
+    }
+    if (!whole_or_disjoint(v)) break;
+    ++len;
+  }
+  return len;
+}
+
+int backward_chain_len(const to_job* jobs, const to_grad* grads, int n, int i, to_dtype dt) {
+  if (env_no_chain()) return 1;
+  int len = 1;
+  while (i + len < n && len < kMaxChain) {
+    const int a = i + len - 1, b = i + len;
+    if (!same_grid(jobs[a], jobs[b]) || !grads[a].grad_in || grads[b].grad_out != grads[a].grad_in) break;
+    std::vector<Span> v;
+    for (int k = i; k <= b; ++k) {
+      const size_t fb = field_bytes(jobs[k], dt);
+      v.push_back(span(grads[k].grad_out, fb));
+      v.push_back(span(grads[k].grad_in, fb));
+      v.push_back(span(grads[k].saved_in, fb));
+    }
+    if (!whole_or_disjoint(v)) break;
+    ++len;
+  }
+  return len;
+}
+
+template <typename T>
+to_status run_forward_chain(const to_job* jobs, int n, DeviceCtx* c, Lane* ln, hipStream_t s) {
+  const to_job& j0 = jobs[0];
+  const to_job& jl = jobs[n - 1];
+  Geometry g;
+  to_status st = make_geometry<T>(j0, false, &g);
+  if (st != TO_OK) return st;
+  st = ensure_scratch(ln, (size_t)g.s_stride * g.chunk * sizeof(cx<T>));
+  if (st != TO_OK) return st;
+  if (jl.epi != TO_EPI_NONE && (st = ensure_partial(ln, (size_t)g.chunk * j0.ny)) != TO_OK) return st;
+  cx<T>* scratch = (cx<T>*)ln->scratch;
+  TransferParams h[kMaxChain];
+  ElementParams<T> el[kMaxChain];
+  hipError_t e;
+  for (int l = 0; l < n; ++l) {
+    h[l] = make_transfer(jobs[l], false);
+    if ((e = prepare_transfer<T>(jobs[l], ln, s, &h[l], l)) != hipSuccess) return hip_fail(e, "transfer table launch");
+    el[l] = make_element<T>(jobs[l], jobs[l].el_flags);
+  }
+  const int row_blocks = (j0.ny + g.rows_per_block - 1) / g.rows_per_block;
+  for (int64_t f0 = 0; f0 < g.nfields; f0 += g.chunk) {
+    const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
+    RowFwdArgs<T> ra = row_fwd_args<T>(j0, g, c, scratch, (const cx<T>*)j0.in + f0 * g.in_stride, g.in_stride,
+                                       nf, el[0], nullptr, f0);
+    if ((e = launch_row_fwd<T>("fwd.row_fwd", g, j0.ny, nf, 1, ra, s)) != hipSuccess)
+      return hip_fail(e, "row_fwd launch");
+    if ((e = launch_col<T>("fwd.col", g, col_args<T>(j0, g, c, scratch, nf, h[0]), s)) != hipSuccess)
+      return hip_fail(e, "col launch");
+    for (int l = 0; l + 1 < n; ++l) {
+      RowMidArgs<T> ma;
+      ma.scratch = scratch;
+      ma.s_stride = g.s_stride;
+      ma.out = (cx<T>*)jobs[l].out + f0 * g.in_stride;
+      ma.out_stride = g.in_stride;
+      ma.ny = j0.ny;
+      ma.nx = j0.nx;
+      ma.tc_shift = g.tc_shift;
+      ma.nfields = nf;
+      ma.fpb = fields_per_block_rows(row_blocks, nf);
+      ma.scale = (T)(1.0 / ((double)g.lx * (double)g.ly));
+      ma.el = el[l + 1];
+      ma.tw = twiddles<T>(c, g.lx);
+      e = timed("fwd.row_mid", g.lx, sizeof(T) == 8, s, [&] {
+        return Launch<T>::row_mid(g.lx, g.half_x, j0.ny, (nf + ma.fpb - 1) / ma.fpb, ma, s);
+      });
+      if (e != hipSuccess) return hip_fail(e, "row_mid launch");
+      if ((e = launch_col<T>("fwd.col", g, col_args<T>(jobs[l + 1], g, c, scratch, nf, h[l + 1]), s)) != hipSuccess)
+        return hip_fail(e, "col launch");
+    }
+    if ((st = finish_forward_chunk<T>(jl, g, c, ln, scratch, f0, nf, s)) != TO_OK) return st;
+  }
+  return TO_OK;
+}
+
+// Field groups of the fused backward boundary: each block takes `fpb`
+// fields, and the groups' gradient partials are combined in order.
+int mid_bwd_fields_per_block(int row_blocks, int nf) {
+  return std::max(1, fields_per_block_rows(row_blocks, nf) / 2);
+}
+
+// Reduction partials (doubles) of a backward chain's fused boundaries: lens
+// partials [groups][ny], then phase-gradient partials [groups][ny][nx] of
+// type T when there is more than one group.
+template <typename T>
+size_t chain_bwd_partial_count(const to_job& j, const Geometry& g) {
+  const int row_blocks = (j.ny + g.rows_per_block - 1) / g.rows_per_block;
+  const int nf = (int)g.chunk;
+  const int fpb = mid_bwd_fields_per_block(row_blocks, nf);
+  const int groups = (nf + fpb - 1) / fpb;
+  size_t n = (size_t)groups * j.ny;
+  if (groups > 1) n += ((size_t)groups * j.ny * j.nx * sizeof(T) + sizeof(double) - 1) / sizeof(double);
+  return n;
+}
+
+template <typename T>
+to_status run_backward_chain(const to_job* jobs, const to_grad* grads, int n, DeviceCtx* c, Lane* ln,
+                             hipStream_t s) {
+  const to_job& j0 = jobs[0];
+  Geometry g;
+  to_status st = make_geometry<T>(j0, false, &g);
+  if (st != TO_OK) return st;
+  st = ensure_scratch(ln, (size_t)g.s_stride * g.chunk * sizeof(cx<T>));
+  if (st != TO_OK) return st;
+  if ((st = ensure_partial(ln, chain_bwd_partial_count<T>(j0, g))) != TO_OK) return st;
+  const int row_blocks = (j0.ny + g.rows_per_block - 1) / g.rows_per_block;
+  cx<T>* scratch = (cx<T>*)ln->scratch;
+  TransferParams h[kMaxChain];
+  hipError_t e;
+  for (int l = 0; l < n; ++l) {
+    h[l] = make_transfer(jobs[l], true);
+    if ((e = prepare_transfer<T>(jobs[l], ln, s, &h[l], l)) != hipSuccess) return hip_fail(e, "transfer table launch");
+  }
+  const ElementParams<T> none = make_element<T>(j0, 0);
+  const bool dbl = sizeof(T) == 8;
+  for (int64_t f0 = 0; f0 < g.nfields; f0 += g.chunk) {
+    const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
+    RowFwdArgs<T> ra = row_fwd_args<T>(j0, g, c, scratch, (const cx<T>*)grads[0].grad_out + f0 * g.in_stride,
+                                       g.comp_stride, nf, none, nullptr, 0);
+    if ((e = launch_row_fwd<T>("bwd.row_fwd", g, j0.ny, nf, 1, ra, s)) != hipSuccess)
+      return hip_fail(e, "row_fwd launch");
+    if ((e = launch_col<T>("bwd.col", g, col_args<T>(j0, g, c, scratch, nf, h[0]), s)) != hipSuccess)
+      return hip_fail(e, "col launch");
+    for (int l = 0; l + 1 < n; ++l) {
+      const to_job& j = jobs[l];
+      const to_grad& gr = grads[l];
+      const bool want_f = (j.el_flags & TO_EL_LENS) && gr.grad_f;
+      RowMidBwdArgs<T> mb;
+      mb.scratch = scratch;
+      mb.s_stride = g.s_stride;
+      mb.grad_in = (cx<T>*)gr.grad_in + f0 * g.in_stride;
+      mb.saved_in = gr.saved_in ? (const cx<T>*)gr.saved_in + f0 * g.in_stride : nullptr;
+      mb.stride = g.in_stride;
+      mb.ny = j.ny;
+      mb.nx = j.nx;
+      mb.tc_shift = g.tc_shift;
+      mb.nfields = nf;
+      mb.fpb = mid_bwd_fields_per_block(row_blocks, nf);
+      const int groups = (nf + mb.fpb - 1) / mb.fpb;
+      mb.scale = (T)(1.0 / ((double)g.lx * (double)g.ly));
+      mb.el = make_element<T>(j, j.el_flags);
+      const bool want_phase = (j.el_flags & TO_EL_PHASE) && gr.grad_phase && gr.saved_in;
+      mb.grad_phase = (T*)gr.grad_phase;
+      mb.gphase_part = (want_phase && groups > 1) ? (T*)(ln->partial + (size_t)groups * j.ny) : nullptr;
+      mb.lens_f = j.el_f;
+      mb.lens_partial = want_f ? ln->partial : nullptr;
+      mb.tw = twiddles<T>(c, g.lx);
+      e = timed("bwd.row_mid", g.lx, dbl, s,
+                [&] { return Launch<T>::row_mid_bwd(g.lx, g.half_x, j.ny, groups, mb, s); });
+      if (e != hipSuccess) return hip_fail(e, "row_mid_bwd launch");
+      if (mb.gphase_part) {
+        e = timed("bwd.phase_combine", 0, dbl, s, [&] {
+          return launch_sum_parts<T>(mb.gphase_part, groups, (int64_t)j.ny * j.nx, (T*)gr.grad_phase, s);
+        });
+        if (e != hipSuccess) return hip_fail(e, "phase gradient combine launch");
+      }
+      if (want_f) {
+        e = timed("bwd.lens_reduce", 0, dbl, s,
+                  [&] { return launch_reduce_add(ln->partial, (int64_t)groups * j.ny, 1.0, gr.grad_f, s); });
+        if (e != hipSuccess) return hip_fail(e, "lens gradient reduction launch");
+      }
+      if ((e = launch_col<T>("bwd.col", g, col_args<T>(jobs[l + 1], g, c, scratch, nf, h[l + 1]), s)) != hipSuccess)
+        return hip_fail(e, "col launch");
+    }
+    if ((st = finish_backward_chunk<T>(jobs[n - 1], grads[n - 1], g, c, ln, scratch, f0, nf, s)) != TO_OK)
+      return st;
+  }
+  return TO_OK;
+}
+
+template <typename T>
+to_status run_modulate(const to_job& j, int adjoint, hipStream_t s) {
+  if (j.batch == 0) return TO_OK;
+  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
+  const int64_t npix = (int64_t)j.ny * j.nx;
+  const int nc = jones ? 3 : 1;
+  const int64_t nfields = jones ? j.batch : j.batch * j.ncomp;
+  if (nfields > INT32_MAX) return fail(TO_E_UNSUPPORTED, "too many fields");
+  const ElementParams<T> el = make_element<T>(j, j.el_flags);
+  hipError_t e = Launch<T>::modulate(nc, (const cx<T>*)j.in, (cx<T>*)j.out, nc * npix, npix, j.ny,
+                                     j.nx, (int)nfields, adjoint, el, s);
+  if (e != hipSuccess) return hip_fail(e, "modulate launch");
+  return TO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scheduling of the jobs of one call over the lanes.
+// ---------------------------------------------------------------------------
 // Relative cost of a job: FFT work of its padded grid.
 double job_cost(const to_job& j) {
   const double n = (double)j.px * (double)j.py;
@@ -1140,30 +1375,52 @@ to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* 
   to_status st = get_ctx(&c);
   if (st != TO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  std::vector<std::vector<Span>> rd(njobs), wr(njobs);
-  std::vector<double> cost(njobs);
-  for (int i = 0; i < njobs; ++i) {
-    const to_job& j = jobs[i];
-    const size_t fb = field_bytes(j, dtype);
-    rd[i].push_back(span(j.in, fb));
-    wr[i].push_back(span(j.out, fb));
-    element_spans(j, dtype, &rd[i]);
-    if (j.epi != TO_EPI_NONE) {
-      wr[i].push_back(span(j.epi_grad, fb));
-      wr[i].push_back(span(j.epi_loss, sizeof(double)));
-    }
-    cost[i] = job_cost(j);
+  // scheduling units: single jobs and chains of layers
+  std::vector<int> ubeg, ulen;
+  for (int i = 0; i < njobs;) {
+    const int len = forward_chain_len(jobs, njobs, i, dtype);
+    ubeg.push_back(i);
+    ulen.push_back(len);
+    i += len;
   }
-  auto run = [&](int i, Lane* ln, hipStream_t ls) {
-    return dtype == TO_C64 ? run_forward<float>(jobs[i], c, ln, ls) : run_forward<double>(jobs[i], c, ln, ls);
+  const int nu = (int)ubeg.size();
+  std::vector<std::vector<Span>> rd(nu), wr(nu);
+  std::vector<double> cost(nu, 0.0);
+  for (int u = 0; u < nu; ++u) {
+    for (int i = ubeg[u]; i < ubeg[u] + ulen[u]; ++i) {
+      const to_job& j = jobs[i];
+      const size_t fb = field_bytes(j, dtype);
+      rd[u].push_back(span(j.in, fb));
+      wr[u].push_back(span(j.out, fb));
+      element_spans(j, dtype, &rd[u]);
+      if (j.epi != TO_EPI_NONE) {
+        wr[u].push_back(span(j.epi_grad, fb));
+        wr[u].push_back(span(j.epi_loss, sizeof(double)));
+      }
+      cost[u] += job_cost(j);
+    }
+  }
+  auto run = [&](int u, Lane* ln, hipStream_t ls) {
+    const to_job* js = jobs + ubeg[u];
+    if (ulen[u] > 1)
+      return dtype == TO_C64 ? run_forward_chain<float>(js, ulen[u], c, ln, ls)
+                             : run_forward_chain<double>(js, ulen[u], c, ln, ls);
+    return dtype == TO_C64 ? run_forward<float>(*js, c, ln, ls) : run_forward<double>(*js, c, ln, ls);
   };
-  auto need = [&](int i, size_t* sb, size_t* pc) {
-    if (dtype == TO_C64)
-      workspace_need<float>(jobs[i], false, sb, pc);
-    else
-      workspace_need<double>(jobs[i], false, sb, pc);
+  auto need = [&](int u, size_t* sb, size_t* pc) {
+    *sb = 0;
+    *pc = 0;
+    for (int i = ubeg[u]; i < ubeg[u] + ulen[u]; ++i) {
+      size_t a = 0, b = 0;
+      if (dtype == TO_C64)
+        workspace_need<float>(jobs[i], false, &a, &b);
+      else
+        workspace_need<double>(jobs[i], false, &a, &b);
+      *sb = std::max(*sb, a);
+      *pc = std::max(*pc, b);
+    }
   };
-  return run_on_lanes(c, s, njobs, rd, wr, cost, run, need);
+  return run_on_lanes(c, s, nu, rd, wr, cost, run, need);
 }
 
 to_status to_modulate(const to_job* jobs, int32_t njobs, to_dtype dtype, int32_t adjoint,
@@ -1204,32 +1461,61 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
   to_status st = get_ctx(&c);
   if (st != TO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  std::vector<std::vector<Span>> rd(njobs), wr(njobs);
-  std::vector<double> cost(njobs);
-  for (int i = 0; i < njobs; ++i) {
-    const to_job& j = jobs[i];
-    const to_grad& g = grads[i];
-    const size_t fb = field_bytes(j, dtype);
-    const size_t rb = (size_t)j.ny * j.nx * (dtype == TO_C64 ? sizeof(float) : sizeof(double));
-    rd[i].push_back(span(g.grad_out, fb));
-    rd[i].push_back(span(g.saved_in, fb));
-    element_spans(j, dtype, &rd[i]);
-    wr[i].push_back(span(g.grad_in, fb));
-    wr[i].push_back(span(g.grad_phase, rb));
-    wr[i].push_back(span(g.grad_f, sizeof(double)));
-    cost[i] = job_cost(j);
+  std::vector<int> ubeg, ulen;
+  for (int i = 0; i < njobs;) {
+    const int len = backward_chain_len(jobs, grads, njobs, i, dtype);
+    ubeg.push_back(i);
+    ulen.push_back(len);
+    i += len;
   }
-  auto run = [&](int i, Lane* ln, hipStream_t ls) {
+  const int nu = (int)ubeg.size();
+  std::vector<std::vector<Span>> rd(nu), wr(nu);
+  std::vector<double> cost(nu, 0.0);
+  for (int u = 0; u < nu; ++u) {
+    for (int i = ubeg[u]; i < ubeg[u] + ulen[u]; ++i) {
+      const to_job& j = jobs[i];
+      const to_grad& g = grads[i];
+      const size_t fb = field_bytes(j, dtype);
+      const size_t rb = (size_t)j.ny * j.nx * (dtype == TO_C64 ? sizeof(float) : sizeof(double));
+      rd[u].push_back(span(g.grad_out, fb));
+      rd[u].push_back(span(g.saved_in, fb));
+      element_spans(j, dtype, &rd[u]);
+      wr[u].push_back(span(g.grad_in, fb));
+      wr[u].push_back(span(g.grad_phase, rb));
+      wr[u].push_back(span(g.grad_f, sizeof(double)));
+      cost[u] += job_cost(j);
+    }
+  }
+  auto run = [&](int u, Lane* ln, hipStream_t ls) {
+    const int i = ubeg[u];
+    if (ulen[u] > 1)
+      return dtype == TO_C64 ? run_backward_chain<float>(jobs + i, grads + i, ulen[u], c, ln, ls)
+                             : run_backward_chain<double>(jobs + i, grads + i, ulen[u], c, ln, ls);
     return dtype == TO_C64 ? run_backward<float>(jobs[i], grads[i], c, ln, ls)
                            : run_backward<double>(jobs[i], grads[i], c, ln, ls);
   };
-  auto need = [&](int i, size_t* sb, size_t* pc) {
-    if (dtype == TO_C64)
-      workspace_need<float>(jobs[i], true, sb, pc);
-    else
-      workspace_need<double>(jobs[i], true, sb, pc);
+  auto need = [&](int u, size_t* sb, size_t* pc) {
+    *sb = 0;
+    *pc = 0;
+    for (int i = ubeg[u]; i < ubeg[u] + ulen[u]; ++i) {
+      size_t a = 0, b = 0;
+      if (dtype == TO_C64)
+        workspace_need<float>(jobs[i], true, &a, &b);
+      else
+        workspace_need<double>(jobs[i], true, &a, &b);
+      *sb = std::max(*sb, a);
+      *pc = std::max(*pc, b);
+    }
+    if (ulen[u] > 1) {
+      Geometry g;
+      const to_job& j0 = jobs[ubeg[u]];
+      if (dtype == TO_C64 && make_geometry<float>(j0, false, &g) == TO_OK)
+        *pc = std::max(*pc, chain_bwd_partial_count<float>(j0, g));
+      if (dtype == TO_C128 && make_geometry<double>(j0, false, &g) == TO_OK)
+        *pc = std::max(*pc, chain_bwd_partial_count<double>(j0, g));
+    }
   };
-  return run_on_lanes(c, s, njobs, rd, wr, cost, run, need);
+  return run_on_lanes(c, s, nu, rd, wr, cost, run, need);
 }
 
 to_status to_coherence_propagate(const to_job* job, to_dtype dtype, int32_t adjoint,

@@ -50,3 +50,13 @@ int row_rows_per_block(int lx) {
   return g;
 }
 }  // namespace toprop
+
+namespace toprop {
+template <>
+hipError_t launch_sum_parts<float>(const float* part, int groups, int64_t n, float* dst, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL((sum_parts_kernel<float>), dim3((unsigned)blocks), dim3(256), 0, s, part, groups, n, dst);
+  return hipGetLastError();
+}
+}  // namespace toprop

@@ -660,6 +660,18 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
     int jv = j, yv = y;
     asm volatile("" : "+v"(jv), "+v"(yv));
     cx<T> v[NC][R];
+    // backward, scalar rows: this field's layer input, loaded before the
+    // transform so its latency overlaps it
+    cx<T> uin[kBwd && kPipe ? RO : 1];
+    if constexpr (kBwd && kPipe) {
+      const bool want = (a.el.flags & (EL_PHASE | EL_LENS)) && a.saved_in;
+#pragma unroll
+      for (int m = 0; m < RO; ++m) {
+        const int x = jv + m * TT;
+        uin[m] = {T(0), T(0)};
+        if (want && rowok && x < nx) uin[m] = a.saved_in[(int64_t)f * a.out_stride + (uint32_t)(yv * nx + x)];
+      }
+    }
     if constexpr (kPipe) {
 #pragma unroll
       for (int m = 0; m < R; ++m) v[0][m] = pre[m];
@@ -705,8 +717,12 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
           const uint32_t fl = a.el.flags;
           if ((fl & (EL_PHASE | EL_LENS)) && a.saved_in) {
             cx<T> u[NC];
+            if constexpr (kPipe) {
+              u[0] = uin[m];
+            } else {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) u[c] = a.saved_in[fbase + (uint32_t)(c * a.comp_stride) + pix];
+              for (int c = 0; c < NC; ++c) u[c] = a.saved_in[fbase + (uint32_t)(c * a.comp_stride) + pix];
+            }
             if constexpr (NC == 3) {
               if (fl & EL_JONES) {
                 cx<T> o[3];
@@ -769,6 +785,259 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
       const double s = group_sum<TT, G>(lens_acc, red);
       if (rowok && j == 0) a.lens_partial[y] = s;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// row_mid: the boundary between two propagations of a chain (the output of
+// one layer is the input of the next), fused: per row, the inverse FFT of
+// the finished layer, crop and 1/(LX LY) scale, store of that layer's
+// output, the next layer's element, the forward FFT of the next layer, back
+// into the same scratch row.  Bit-identical to row_inv followed by row_fwd.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct RowMidArgs {
+  cx<T>* scratch;       // the chunk's intermediate, read and rewritten in place
+  int64_t s_stride;
+  cx<T>* out;           // the finished layer's output (first field of the chunk)
+  int64_t out_stride;   // elements between fields of `out`
+  int ny, nx;
+  int tc_shift;
+  int nfields;
+  int fpb;              // fields per block (the element is evaluated once for them)
+  T scale;              // 1 / (LX LY)
+  ElementParams<T> el;  // element in front of the next layer
+  const cx<T>* tw;
+};
+
+template <typename T, int L, int R, int G, bool HALF>
+__global__ void __launch_bounds__(G * (L / R)) row_mid_kernel(RowMidArgs<T> a) {
+  constexpr int TT = L / R;
+  constexpr int RO = HALF ? R / 2 : R;  // registers that can hold x < nx
+  __shared__ cx<T> lds[G * lds_len<1>(L)];
+  const int g = threadIdx.x / TT;
+  const int j = threadIdx.x % TT;
+  const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
+  const int ny = a.ny, nx = a.nx;
+  const bool rowok = y < ny;
+  const int tcm = (1 << a.tc_shift) - 1;
+  const int f_begin = (int)blockIdx.y * a.fpb;
+  const int f_end = min(f_begin + a.fpb, a.nfields);
+
+  const bool scalar_el = (a.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) != 0;
+  cx<T> mod[RO];
+#pragma unroll
+  for (int m = 0; m < RO; ++m) {
+    const int x = j + m * TT;
+    mod[m] = {T(1), T(0)};
+    if (scalar_el && rowok && x < nx) mod[m] = scalar_modulation(a.el, ny, nx, y, x);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  auto load_row = [&](int f, int jv, int yv, cx<T> (&dst)[R]) {
+    const cx<T>* src = a.scratch + (int64_t)f * a.s_stride;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int kx = jv + m * TT;
+      cx<T> val = {T(0), T(0)};
+      if (rowok) val = src[(uint32_t)((((kx >> a.tc_shift) * ny + yv) << a.tc_shift) + (kx & tcm))];
+      dst[m] = val;
+    }
+  };
+  cx<T> pre[R];
+  if (f_begin < f_end) load_row(f_begin, j, y, pre);
+
+#pragma unroll 1
+  for (int f = f_begin; f < f_end; ++f) {
+    int jv = j, yv = y;
+    asm volatile("" : "+v"(jv), "+v"(yv));
+    cx<T> v[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = pre[m];
+    if (f + 1 < f_end) load_row(f + 1, jv, yv, pre);
+    fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
+    cx<T>* out_f = a.out + (int64_t)f * a.out_stride;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int x = jv + m * TT;
+      if (m < RO && rowok && x < nx) {
+        v[m] = cscale(v[m], a.scale);
+        out_f[(uint32_t)(yv * nx + x)] = v[m];
+        if (scalar_el) v[m] = cmul(mod[m], v[m]);
+      } else {
+        v[m] = {T(0), T(0)};
+      }
+    }
+    // fresh opaque index: the forward transform reloads its twiddles rather
+    // than keeping the inverse transform's (same addresses) live
+    int jw = jv, yw = yv;
+    asm volatile("" : "+v"(jw), "+v"(yw));
+    fft_wg<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
+    if (rowok) {
+      cx<T>* dst = a.scratch + (int64_t)f * a.s_stride;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int kx = jw + m * TT;
+        dst[(uint32_t)((((kx >> a.tc_shift) * ny + yw) << a.tc_shift) + (kx & tcm))] = v[m];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// row_mid_bwd: the same boundary in the backward pass of a chain.  Per row:
+// inverse FFT of g_mod = P^H g of layer l, crop and scale, the layer's
+// parameter gradients, g_l = M^H g_mod (stored when requested), which is the
+// upstream gradient of layer l-1, then the forward FFT of g_l back into the
+// scratch row.  Like row_inv's backward, a block loops over its fields so each pixel's gradient is summed by one thread in a fixed
+// order.  A block takes `fpb` fields (a field group); with several groups
+// each writes its own gradient partials, combined afterwards in group order.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct RowMidBwdArgs {
+  cx<T>* scratch;
+  int64_t s_stride;
+  cx<T>* grad_in;         // g_l (first field of the chunk), or null
+  const cx<T>* saved_in;  // the layer's forward input, or null (no parameter gradients)
+  int64_t stride;         // elements between fields of grad_in / saved_in
+  int ny, nx;
+  int tc_shift;
+  int nfields;
+  T scale;
+  ElementParams<T> el;    // layer l's element
+  int fpb;                // fields per block (a field group)
+  T* grad_phase;          // [ny][nx], accumulated, or null
+  T* gphase_part;         // several field groups: [group][ny][nx] partials (overwritten)
+  double lens_f;
+  double* lens_partial;   // per (field group, row) partial sums of dL/df, or null
+  const cx<T>* tw;
+};
+
+template <typename T, int L, int R, int G, bool HALF>
+__global__ void __launch_bounds__(G * (L / R)) row_mid_bwd_kernel(RowMidBwdArgs<T> a) {
+  constexpr int TT = L / R;
+  constexpr int NT = G * TT;
+  constexpr int RO = HALF ? R / 2 : R;
+  __shared__ cx<T> lds[G * lds_len<1>(L)];
+  __shared__ double red[NT];
+  const int g = threadIdx.x / TT;
+  const int j = threadIdx.x % TT;
+  const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
+  const int ny = a.ny, nx = a.nx;
+  const bool rowok = y < ny;
+  const int tcm = (1 << a.tc_shift) - 1;
+  const uint32_t fl = a.el.flags;
+  const bool want_param = (fl & (EL_PHASE | EL_LENS)) && a.saved_in;
+
+  T gphase[RO];
+  cx<T> modr[RO];
+  double dpsi[RO];
+#pragma unroll
+  for (int m = 0; m < RO; ++m) {
+    gphase[m] = T(0);
+    modr[m] = {T(1), T(0)};
+    dpsi[m] = 0.0;
+    const int x = j + m * TT;
+    if (rowok && x < nx) {
+      if (fl & (EL_PHASE | EL_COMPLEX | EL_LENS)) modr[m] = scalar_modulation(a.el, ny, nx, y, x);
+      if (fl & EL_LENS) dpsi[m] = lens_dphase_df(a.el, ny, nx, y, x, a.lens_f);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  double lens_acc = 0.0;
+  auto load_row = [&](int f, int jv, int yv, cx<T> (&dst)[R]) {
+    const cx<T>* src = a.scratch + (int64_t)f * a.s_stride;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int kx = jv + m * TT;
+      cx<T> val = {T(0), T(0)};
+      if (rowok) val = src[(uint32_t)((((kx >> a.tc_shift) * ny + yv) << a.tc_shift) + (kx & tcm))];
+      dst[m] = val;
+    }
+  };
+  const int f_begin = (int)blockIdx.y * a.fpb;
+  const int f_end = min(f_begin + a.fpb, a.nfields);
+  cx<T> pre[R];
+  if (f_begin < f_end) load_row(f_begin, j, y, pre);
+
+#pragma unroll 1
+  for (int f = f_begin; f < f_end; ++f) {
+    int jv = j, yv = y;
+    asm volatile("" : "+v"(jv), "+v"(yv));
+    cx<T> v[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = pre[m];
+    if (f + 1 < f_end) load_row(f + 1, jv, yv, pre);
+    // the layer input of this field's row, loaded before the transform so
+    // its latency overlaps it
+    const int64_t fbase = (int64_t)f * a.stride;
+    cx<T> uin[RO];
+#pragma unroll
+    for (int m = 0; m < RO; ++m) {
+      const int x = jv + m * TT;
+      uin[m] = {T(0), T(0)};
+      if (want_param && rowok && x < nx) uin[m] = a.saved_in[fbase + (uint32_t)(yv * nx + x)];
+    }
+    fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int x = jv + m * TT;
+      if (m < RO && rowok && x < nx) {
+        const uint32_t pix = (uint32_t)(yv * nx + x);
+        v[m] = cscale(v[m], a.scale);  // g_mod
+        const cx<T> mod = modr[m];
+        if (want_param) {
+          const cx<T> um = cmul(mod, uin[m]);
+          const T im = v[m].y * um.x - v[m].x * um.y;  // Im(g conj(M u))
+          if (fl & EL_PHASE) gphase[m] += im;
+          if (fl & EL_LENS) lens_acc += (double)im * dpsi[m];
+        }
+        v[m] = cmulc(v[m], mod);  // g_l = conj(M) g_mod
+        if (a.grad_in) a.grad_in[fbase + pix] = v[m];
+      } else {
+        v[m] = {T(0), T(0)};
+      }
+    }
+    // fresh opaque index: the forward transform reloads its twiddles rather
+    // than keeping the inverse transform's (same addresses) live
+    int jw = jv, yw = yv;
+    asm volatile("" : "+v"(jw), "+v"(yw));
+    fft_wg<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
+    if (rowok) {
+      cx<T>* dst = a.scratch + (int64_t)f * a.s_stride;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int kx = jw + m * TT;
+        dst[(uint32_t)((((kx >> a.tc_shift) * ny + yw) << a.tc_shift) + (kx & tcm))] = v[m];
+      }
+    }
+  }
+  if (rowok && (fl & EL_PHASE) && a.grad_phase && a.saved_in) {
+#pragma unroll
+    for (int m = 0; m < RO; ++m) {
+      const int x = j + m * TT;
+      if (x < nx) {
+        if (a.gphase_part)
+          a.gphase_part[((int64_t)blockIdx.y * ny + y) * nx + x] = gphase[m];
+        else
+          a.grad_phase[(int64_t)y * nx + x] += gphase[m];
+      }
+    }
+  }
+  if ((fl & EL_LENS) && a.lens_partial) {
+    const double s = group_sum<TT, G>(lens_acc, red);
+    if (rowok && j == 0) a.lens_partial[(int64_t)blockIdx.y * ny + y] = s;
+  }
+}
+
+// dst[i] += sum over g of part[g][i], g in order (deterministic combine of
+// per-field-group gradient partials).
+template <typename T>
+__global__ void __launch_bounds__(256) sum_parts_kernel(const T* __restrict__ part, int groups, int64_t n,
+                                                        T* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    T acc = part[i];
+    for (int g = 1; g < groups; ++g) acc += part[(int64_t)g * n + i];
+    dst[i] += acc;
   }
 }
 

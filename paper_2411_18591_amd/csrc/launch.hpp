@@ -49,6 +49,9 @@ struct Launch {
                         const ColArgs<T>& a, hipStream_t s);
   static hipError_t row_inv(int lx, bool half, int nc, int ny, int nblocks_y,
                             const RowInvArgs<T>& a, hipStream_t s);
+  static hipError_t row_mid(int lx, bool half, int ny, int nblocks_y, const RowMidArgs<T>& a, hipStream_t s);
+  static hipError_t row_mid_bwd(int lx, bool half, int ny, int nblocks_y, const RowMidBwdArgs<T>& a,
+                                hipStream_t s);
   static hipError_t modulate(int nc, const cx<T>* in, cx<T>* out, int64_t fstride, int64_t cstride,
                              int ny, int nx, int nfields, int adjoint, const ElementParams<T>& el,
                              hipStream_t s);
@@ -56,6 +59,10 @@ struct Launch {
 
 hipError_t launch_reduce_add(const double* src, int64_t n, double scale, double* dst,
                              hipStream_t s);
+
+// dst[i] += sum_g part[g * n + i] for g = 0 .. groups-1, in order.
+template <typename T>
+hipError_t launch_sum_parts(const T* part, int groups, int64_t n, T* dst, hipStream_t s);
 
 hipError_t launch_tf_tables(cx<float>* ex, float* sx, int lx, double inv_lxdx, cx<float>* ey,
                             float* sy, int ly, double inv_lydy, double fres_a, double q_frac,

@@ -73,6 +73,38 @@ hipError_t Launch<T>::col(int ly, bool half, int ntiles, int nfields, int varian
 }
 
 template <typename T>
+hipError_t Launch<T>::row_mid(int lx, bool half, int ny, int nblocks_y, const RowMidArgs<T>& a,
+                              hipStream_t s) {
+  return dispatch_len(lx, [&](auto Lc) -> hipError_t {
+    constexpr int L = decltype(Lc)::value;
+    using C = RowCfg<L>;
+    dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
+    dim3 block(C::threads);
+    if (half)
+      hipLaunchKernelGGL((row_mid_kernel<T, L, C::R, C::G, true>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((row_mid_kernel<T, L, C::R, C::G, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t Launch<T>::row_mid_bwd(int lx, bool half, int ny, int nblocks_y, const RowMidBwdArgs<T>& a,
+                                  hipStream_t s) {
+  return dispatch_len(lx, [&](auto Lc) -> hipError_t {
+    constexpr int L = decltype(Lc)::value;
+    using C = RowCfg<L>;
+    dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
+    dim3 block(C::threads);
+    if (half)
+      hipLaunchKernelGGL((row_mid_bwd_kernel<T, L, C::R, C::G, true>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((row_mid_bwd_kernel<T, L, C::R, C::G, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
 hipError_t Launch<T>::row_inv(int lx, bool half, int nc, int ny, int nblocks_y,
                               const RowInvArgs<T>& a, hipStream_t s) {
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {

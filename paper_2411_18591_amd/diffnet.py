@@ -17,7 +17,7 @@ from __future__ import annotations
 
 import torch
 
-from . import Optics, propagate, propagate_backward, propagate_loss
+from . import Optics, _capi, propagate_backward_jobs, propagate_jobs
 
 
 class DiffractiveNet:
@@ -36,24 +36,29 @@ class DiffractiveNet:
         self.loss = torch.zeros((), dtype=torch.float64, device=u0.device)
 
     def forward(self, plain: bool = False) -> torch.Tensor:
-        """u_1 .. u_L and the loss (device float64 scalar); dL/du_L in gbuf[0]."""
+        """u_1 .. u_L and the loss (device float64 scalar); dL/du_L in gbuf[0].
+        All layers go to the library in one call: it recognises the chain
+        (each layer reads the previous one's output) and runs it chunk by
+        chunk with fused layer boundaries."""
         self.loss.zero_()
-        for l in range(self.L - 1):
-            propagate(self.u[l], self.opt, out=self.u[l + 1], phase=self.masks[l], plain=plain)
-        propagate_loss(self.u[self.L - 1], self.opt, kind="mse", ref=self.target, scale=self.scale,
-                       out=self.u[self.L], grad=self.gbuf[0], loss=self.loss, phase=self.masks[self.L - 1],
-                       plain=plain)
+        L = self.L
+        elements = [{"phase": self.masks[l]} for l in range(L)]
+        elements[-1].update(epi=_capi.TO_EPI_MSE, epi_ref=self.target, epi_scale=self.scale,
+                            epi_grad=self.gbuf[0], epi_loss=self.loss)
+        propagate_jobs(self.u[:L], [self.opt] * L, outs=self.u[1:], elements=elements, plain=plain)
         return self.loss
 
     def backward(self, plain: bool = False) -> torch.Tensor:
-        """dL/dphi_l for every mask into gmask (overwritten)."""
+        """dL/dphi_l for every mask into gmask (overwritten), in one call
+        (layers L-1 .. 0, the gradient buffers alternating)."""
         self.gmask.zero_()
-        cur = 0
-        for l in range(self.L - 1, -1, -1):
-            nxt = 1 - cur
-            propagate_backward(self.gbuf[cur], self.opt, saved_in=self.u[l], grad_phase=self.gmask[l],
-                               phase=self.masks[l], want_grad_in=l > 0, grad_in=self.gbuf[nxt], plain=plain)
-            cur = nxt
+        L = self.L
+        layers = list(range(L - 1, -1, -1))
+        gout = [self.gbuf[k % 2] for k in range(L)]
+        gin = [self.gbuf[(k + 1) % 2] if l > 0 else None for k, l in enumerate(layers)]
+        propagate_backward_jobs(gout, [self.opt] * L, saved_ins=[self.u[l] for l in layers], grad_ins=gin,
+                                grad_phases=[self.gmask[l] for l in layers],
+                                elements=[{"phase": self.masks[l]} for l in layers], plain=plain)
         return self.gmask
 
     def step(self, plain: bool = False):
