@@ -39,11 +39,14 @@ hipError_t launch_tf_tables(cx<float>* ex, float* sx, int lx, double inv_lxdx, c
 }  // namespace toprop
 
 namespace toprop {
-int row_rows_per_block(int lx) {
+int row_rows_per_block(int lx, bool is_double, bool heavy) {
   int g = 0;
   auto q = [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    g = RowCfg<L>::G;
+    if (is_double)
+      g = heavy ? RowCfg<double, L, true>::G : RowCfg<double, L>::G;
+    else
+      g = heavy ? RowCfg<float, L, true>::G : RowCfg<float, L>::G;
     return hipSuccess;
   };
   if (dispatch_len(lx, q) != hipSuccess) return 1;

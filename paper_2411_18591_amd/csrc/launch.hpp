@@ -11,10 +11,13 @@ namespace toprop {
 constexpr int kMinLen = 8;
 constexpr int kMaxLen = 8192;
 
-// Row passes: R points per thread, G rows per workgroup.
-template <int L>
+// Row passes: R points per thread, G rows per workgroup.  Heavy kernels
+// (backward epilogues, three coupled components) keep R = 8 at length 2048,
+// where R = 16 would cost them occupancy; so does complex128.
+template <typename T, int L, bool Heavy = false>
 struct RowCfg {
-  static constexpr int R = L <= 16 ? L : (L <= 2048 ? 8 : 16);
+  static constexpr int R =
+      L <= 16 ? L : (L <= 1024 ? 8 : ((L == 2048 && (Heavy || sizeof(T) == 8)) ? 8 : 16));
   static constexpr int TT = L / R;
   static constexpr int G = TT >= 256 ? 1 : 256 / TT;
   static constexpr int threads = G * TT;
@@ -39,7 +42,7 @@ struct ColCfg {
 // Column-tile width for a given column length and variant (runtime query).
 int col_tile_width(int ly, bool is_double, int variant);
 // Rows per workgroup of the row passes for a given row length.
-int row_rows_per_block(int lx);
+int row_rows_per_block(int lx, bool is_double, bool heavy);
 
 template <typename T>
 struct Launch {

@@ -29,20 +29,21 @@ hipError_t Launch<T>::row_fwd(int lx, bool half, int nc, int ny, int nfields, co
                               hipStream_t s) {
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    using C = RowCfg<L>;
     const int fpb = a.fpb > 0 ? a.fpb : 1;
-    dim3 grid((ny + C::G - 1) / C::G, (nfields + fpb - 1) / fpb);
-    dim3 block(C::threads);
     if (nc == 3) {
+      using C = RowCfg<T, L, true>;
+      dim3 grid((ny + C::G - 1) / C::G, (nfields + fpb - 1) / fpb);
       if (half)
-        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, true, 3>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, true, 3>), grid, dim3(C::threads), 0, s, a);
       else
-        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, false, 3>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, false, 3>), grid, dim3(C::threads), 0, s, a);
     } else {
+      using C = RowCfg<T, L>;
+      dim3 grid((ny + C::G - 1) / C::G, (nfields + fpb - 1) / fpb);
       if (half)
-        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, true, 1>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, true, 1>), grid, dim3(C::threads), 0, s, a);
       else
-        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, false, 1>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, false, 1>), grid, dim3(C::threads), 0, s, a);
     }
     return hipGetLastError();
   });
@@ -77,7 +78,7 @@ hipError_t Launch<T>::row_mid(int lx, bool half, int ny, int nblocks_y, const Ro
                               hipStream_t s) {
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    using C = RowCfg<L>;
+    using C = RowCfg<T, L>;
     dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
     dim3 block(C::threads);
     if (half)
@@ -93,7 +94,7 @@ hipError_t Launch<T>::row_mid_bwd(int lx, bool half, int ny, int nblocks_y, cons
                                   hipStream_t s) {
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    using C = RowCfg<L>;
+    using C = RowCfg<T, L, true>;
     dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
     dim3 block(C::threads);
     if (half)
@@ -109,21 +110,22 @@ hipError_t Launch<T>::row_inv(int lx, bool half, int nc, int ny, int nblocks_y,
                               const RowInvArgs<T>& a, hipStream_t s) {
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    using C = RowCfg<L>;
-    dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
-    dim3 block(C::threads);
     auto go = [&](auto bwd) {
       constexpr bool B = decltype(bwd)::value;
       if (nc == 3) {
+        using C = RowCfg<T, L, true>;
+        dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
         if (half)
-          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 3, B>), grid, block, 0, s, a);
+          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 3, B>), grid, dim3(C::threads), 0, s, a);
         else
-          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 3, B>), grid, block, 0, s, a);
+          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 3, B>), grid, dim3(C::threads), 0, s, a);
       } else {
+        using C = RowCfg<T, L, B>;
+        dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
         if (half)
-          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 1, B>), grid, block, 0, s, a);
+          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 1, B>), grid, dim3(C::threads), 0, s, a);
         else
-          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 1, B>), grid, block, 0, s, a);
+          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 1, B>), grid, dim3(C::threads), 0, s, a);
       }
     };
     if (a.backward)

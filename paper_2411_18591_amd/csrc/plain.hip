@@ -198,7 +198,7 @@ template <typename T>
 hipError_t Plain<T>::rows(int L, cx<T>* a, int nrows, int dir, const cx<T>* tw, hipStream_t s) {
   return dispatch_len(L, [&](auto Lc) -> hipError_t {
     constexpr int LL = decltype(Lc)::value;
-    using C = RowCfg<LL>;
+    using C = RowCfg<T, LL>;
     dim3 grid((nrows + C::G - 1) / C::G);
     if (dir < 0)
       hipLaunchKernelGGL((plain_row_fft_kernel<T, LL, C::R, C::G, -1>), grid, dim3(C::threads), 0, s, a, nrows,
