@@ -188,8 +188,6 @@ def main():
     print("[bench] timed region", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream(dev)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    if not args.no_profile:
-        _capi.profile_begin()
     torch.cuda.synchronize()
     ev0.record(stream)
     t_wall = time.perf_counter()
@@ -198,12 +196,28 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
-    prof = _capi.profile_end() if not args.no_profile else {}
     ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
     props = 2 * B * L
     value = props / (ms_step / 1000.0)
     print(f"[bench] {ms_step:.3f} ms/step, loss {float(loss.item()):.6e}", file=sys.stderr, flush=True)
+
+    # Per-kernel durations: the same K steps again, every launch bracketed by
+    # HIP events on its own stream (the events cost a few microseconds per
+    # launch, so this pass is kept out of the throughput above).
+    prof = {}
+    prof_ms_step = None
+    if not args.no_profile:
+        print("[bench] profiled pass", file=sys.stderr, flush=True)
+        _capi.profile_begin()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        prof = _capi.profile_end()
+        prof_ms_step = ev0.elapsed_time(ev1) / args.steps
 
     # Algorithmic HBM bytes of one step (fields in/out of every propagation,
     # the loss gradient, masks and mask gradients; no padded intermediates).
@@ -294,6 +308,7 @@ def main():
             "propagations_per_step": props,
         },
         "hbm_roofline_step": {"algorithmic_bytes": step_bytes, "frac": round(hbm_frac_step, 4)},
+        "profiled_pass_ms_per_step": None if prof_ms_step is None else round(prof_ms_step, 4),
         "plain_form": plain,
         "roofline": roofline,
         "kernels": kernels_out,
