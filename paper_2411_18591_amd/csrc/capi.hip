@@ -860,7 +860,7 @@ to_status run_forward_chain(const to_job* jobs, int n, DeviceCtx* c, Lane* ln, h
 // Field groups of the fused backward boundary: each block takes `fpb`
 // fields, and the groups' gradient partials are combined in order.
 int mid_bwd_fields_per_block(int row_blocks, int nf) {
-  return std::max(1, fields_per_block_rows(row_blocks, nf) / 2);
+  return fields_per_block_rows(row_blocks, nf);
 }
 
 // Reduction partials (doubles) of a backward chain's fused boundaries: lens
