@@ -86,22 +86,35 @@ typedef enum { TO_C64 = 0, TO_C128 = 1 } to_dtype;
  *                 optical axis (thin lens, no pupil);
  *   TO_EL_JONES   J = el_jones, a uniform 3x3 complex matrix mixing the
  *                 three components (needs ncomp == 3); a 2x2 Jones matrix is
- *                 embedded with J[2][2] = 1.                                 */
+ *                 embedded with J[2][2] = 1;
+ *   TO_EL_JONES_MAP  J = J(r) from el_jones_map, a spatially varying 3x3
+ *                 matrix (complex of the job's dtype, [3][3][ny][nx]: entry
+ *                 (r, c) is the plane 3 r + c); needs ncomp == 3, excludes
+ *                 TO_EL_JONES (section "Polarization": Jones matrices act per
+ *                 pixel).                                                    */
 #define TO_EL_PHASE 1u
 #define TO_EL_COMPLEX 2u
 #define TO_EL_LENS 4u
 #define TO_EL_JONES 8u
+#define TO_EL_JONES_MAP 16u
 
 /* Epilogue of a forward propagation (fused into its last pass), computed per
  * component from the intensity I = |u|^2 of the propagated field:
- *   TO_EPI_MSE      loss += epi_scale * sum (I - T)^2 over fields, comps and
- *                   pixels (T = epi_ref, broadcast over fields/comps);
- *                   epi_grad = 4 epi_scale (I - T) u  (use epi_scale = 1/n
- *                   for a mean);
- *   TO_EPI_WEIGHTED loss += epi_scale * sum W I  (W = epi_ref);
- *                   epi_grad = 2 epi_scale W u.
+ *   TO_EPI_MSE       loss += epi_scale * sum (I - T)^2 over fields, comps and
+ *                    pixels (T = epi_ref, broadcast over fields/comps);
+ *                    epi_grad = 4 epi_scale (I - T) u  (use epi_scale = 1/n
+ *                    for a mean);
+ *   TO_EPI_WEIGHTED  loss += epi_scale * sum W I  (W = epi_ref);
+ *                    epi_grad = 2 epi_scale W u.
+ *   TO_EPI_INTENSITY epi_out[b][y][x] += epi_scale * sum over components of
+ *                    I (the detected intensity, section "Polarization", and
+ *                    with one job per wavelength sharing epi_out, the
+ *                    incoherent polychromatic sum of Eq. (I_poly), epi_scale
+ *                    being the wavelength's weight).  `out` may be NULL (the
+ *                    field is then not stored).  Its gradient, given dL/dI,
+ *                    is the TO_EPI_WEIGHTED epilogue with W = dL/dI.
  * epi_loss is one device double, accumulated.                                */
-typedef enum { TO_EPI_NONE = 0, TO_EPI_MSE = 1, TO_EPI_WEIGHTED = 2 } to_epilogue;
+typedef enum { TO_EPI_NONE = 0, TO_EPI_MSE = 1, TO_EPI_WEIGHTED = 2, TO_EPI_INTENSITY = 3 } to_epilogue;
 
 /* One propagation job: `batch` fields of `ncomp` components, all on the same
  * grid, through the same element and the same free-space distance.          */
@@ -122,12 +135,14 @@ typedef struct to_job {
   const void* el_complex; /* TO_EL_COMPLEX: complex [ny][nx]                    */
   double el_f;            /* TO_EL_LENS: focal length [m], != 0                 */
   double el_jones[18];    /* TO_EL_JONES: row-major 3x3, (re, im) pairs          */
-  const void* epi_ref;    /* TO_EPI_*: real [ny][nx] target (MSE) or weight      */
+  const void* epi_ref;    /* MSE / WEIGHTED: real [ny][nx] target or weight      */
   double epi_scale;
-  void* epi_grad;         /* TO_EPI_*: complex, same layout as `out`             */
-  double* epi_loss;       /* TO_EPI_*: one device double, accumulated            */
+  void* epi_grad;         /* MSE / WEIGHTED: complex, same layout as `out`       */
+  double* epi_loss;       /* MSE / WEIGHTED: one device double, accumulated      */
   const void* in;         /* complex [batch][ncomp][ny][nx]                      */
   void* out;              /* complex [batch][ncomp][ny][nx]; may equal `in`      */
+  void* epi_out;          /* INTENSITY: real [batch][ny][nx], accumulated        */
+  const void* el_jones_map; /* TO_EL_JONES_MAP: complex [3][3][ny][nx]           */
 } to_job;
 
 /* Gradient buffers of one job for to_propagate_backward.                    */
@@ -193,7 +208,8 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
  * Forward epilogue (adjoint == 0) on the time-averaged intensity
  * I(r) = Re Gamma_out(r, r):  TO_EPI_MSE  loss += epi_scale sum (I - T)^2,
  * TO_EPI_WEIGHTED loss += epi_scale sum W I; epi_grad (complex, n x n)
- * receives dL/dGamma_out, zero off the diagonal.
+ * receives dL/dGamma_out, zero off the diagonal; TO_EPI_INTENSITY
+ * epi_out[y][x] += epi_scale I(r) (real [ny][nx]).
  * Computed as two batched propagations of the n = ny nx rows (P^H along r2,
  * then P along r1) around transposes; needs workspace for one extra copy of
  * Gamma.  n must not exceed 46340; no Jones element.                         */

@@ -303,6 +303,26 @@ def power(u, dy: float, dx: float) -> float:
     return float(np.sum(np.abs(u) ** 2) * dx * dy)
 
 
+def intensity(u, ncomp: int = 1) -> np.ndarray:
+    """Detected intensity of fields ``[..., ny, nx]`` (ncomp = 1) or
+    ``[..., 3, ny, nx]`` (ncomp = 3): ``sum over components |u_c|^2``
+    (section "Polarization": the intensity of a polarized field is the sum
+    over its components)."""
+    a = np.abs(np.asarray(u)) ** 2
+    return a.sum(axis=-3) if ncomp == 3 else a
+
+
+def incoherent_sum(fields, weights, ncomp: int = 1) -> np.ndarray:
+    """Eq. (I_poly): the intensity of light made of mutually incoherent
+    wavelengths is the weighted sum of the per-wavelength intensities,
+    ``sum_k w_k I(u_k)`` (no cross terms)."""
+    total = None
+    for u, w in zip(fields, weights):
+        t = float(w) * intensity(u, ncomp)
+        total = t if total is None else total + t
+    return total
+
+
 def inner(u, v, dy: float, dx: float) -> complex:
     """Inner product ``sum u conj(v) dx dy``, as in Eq. (loss_func)."""
     return complex(np.sum(np.asarray(u) * np.conj(np.asarray(v))) * dx * dy)

@@ -25,7 +25,7 @@ from ._capi import ToError  # noqa: F401
 
 __all__ = [
     "Optics", "propagate", "modulate", "propagate_backward", "coherence_propagate",
-    "propagate_ad", "propagate_jobs", "propagate_backward_jobs", "linear_polarizer", "waveplate",
+    "propagate_ad", "propagate_intensity", "propagate_jobs", "propagate_backward_jobs", "linear_polarizer", "waveplate",
     "jones3", "version", "autotune", "plan_get", "plan_set", "plan_clear", "plan_load", "plan_save",
 ]
 
@@ -146,8 +146,8 @@ def _field_dims(u: torch.Tensor, ncomp: int):
 
 
 def make_job(u: torch.Tensor, opt: Optics, *, out: Optional[torch.Tensor] = None, ncomp: int = 1,
-             phase=None, cmask=None, lens_f=None, jones=None, epi: int = _capi.TO_EPI_NONE,
-             epi_ref=None, epi_scale: float = 1.0, epi_grad=None, epi_loss=None):
+             phase=None, cmask=None, lens_f=None, jones=None, jones_map=None, epi: int = _capi.TO_EPI_NONE,
+             epi_ref=None, epi_scale: float = 1.0, epi_grad=None, epi_loss=None, epi_out=None):
     """Fill a to_job record for field tensor u (and the given element /
     epilogue tensors).  Returns the record; the caller keeps the tensors
     alive until the stream work is done."""
@@ -186,14 +186,25 @@ def make_job(u: torch.Tensor, opt: Optics, *, out: Optional[torch.Tensor] = None
                 flat += [v.real, v.imag]
         j.el_jones[:] = flat
         flags |= _capi.TO_EL_JONES
+    if jones_map is not None:
+        _need(jones_map, "jones_map", u.dtype, u, (3, 3, ny, nx))
+        j.el_jones_map = _ptr(jones_map)
+        flags |= _capi.TO_EL_JONES_MAP
     j.el_flags = flags
     j.epi = int(epi)
-    if epi != _capi.TO_EPI_NONE:
+    if epi in (_capi.TO_EPI_MSE, _capi.TO_EPI_WEIGHTED):
         _need(epi_ref, "epi_ref", rdt, u, (ny, nx))
         _need(epi_grad, "epi_grad", u.dtype, u, tuple(u.shape))
         _need(epi_loss, "epi_loss", torch.float64, u)
         j.epi_ref, j.epi_grad, j.epi_loss = _ptr(epi_ref), _ptr(epi_grad), _ptr(epi_loss)
-        j.epi_scale = float(epi_scale)
+    elif epi == _capi.TO_EPI_INTENSITY:
+        _need(epi_out, "epi_out", rdt, u)
+        if epi_out.numel() != batch * ny * nx:
+            raise ValueError(f"epi_out must hold {batch} x {ny} x {nx} intensities")
+        j.epi_out = _ptr(epi_out)
+    elif epi != _capi.TO_EPI_NONE:
+        raise ValueError(f"unknown epilogue {epi}")
+    j.epi_scale = float(epi_scale)
     j.in_ = _ptr(u)
     if out is not None:
         _need(out, "out", u.dtype, u, tuple(u.shape))
@@ -231,6 +242,23 @@ def propagate_loss(u: torch.Tensor, opt: Optics, *, kind: str, ref: torch.Tensor
                    epi_grad=grad, epi_loss=loss, **element)
     _capi.propagate([job], _dtype_code(u), _stream(u), plain=plain)
     return out, grad, loss
+
+
+def propagate_intensity(u: torch.Tensor, opt: Optics, *, intensity: Optional[torch.Tensor] = None,
+                        weight: float = 1.0, out: Optional[torch.Tensor] = None, ncomp: int = 1,
+                        **element) -> torch.Tensor:
+    """Detected intensity after propagation: ``intensity[b] += weight *
+    sum_c |P_z(M u)_c|^2`` (shape [batch, ny, nx], real, accumulated; zeros
+    if not given).  Called once per wavelength with a shared ``intensity``
+    and the wavelength's weight, this is the incoherent polychromatic sum of
+    Eq. (I_poly).  The propagated field is stored only if ``out`` is given."""
+    ny, nx, batch = _field_dims(u, ncomp)
+    if intensity is None:
+        intensity = torch.zeros((batch, ny, nx), dtype=_real_dtype(u), device=u.device)
+    job = make_job(u, opt, out=out, ncomp=ncomp, epi=_capi.TO_EPI_INTENSITY, epi_out=intensity,
+                   epi_scale=weight, **element)
+    _capi.propagate([job], _dtype_code(u), _stream(u))
+    return intensity
 
 
 def modulate(u: torch.Tensor, *, dy: float, dx: float, wavelength: float, y0: float = 0.0,
@@ -388,7 +416,9 @@ def coherence_propagate(gamma: torch.Tensor, opt: Optics, *, adjoint: bool = Fal
     With ``loss_kind`` ("mse" or "weighted", forward only) the loss of the
     output intensity Re Gamma(r, r) against ``loss_ref`` is accumulated into
     ``loss`` and its gradient dL/dGamma_out written to ``loss_grad``; the
-    call then returns (out, loss_grad, loss).  With ``adjoint`` and
+    call then returns (out, loss_grad, loss).  With ``loss_kind="intensity"``
+    the call returns (out, I) with I[y, x] += loss_scale * Re Gamma(r, r)
+    (I = ``loss_grad`` if given, else a new zero tensor).  With ``adjoint`` and
     ``grad_phase``, dL/dphi of the phase element is accumulated using
     ``saved_in`` (the forward input)."""
     ny, nx = int(gamma.shape[0]), int(gamma.shape[1])
@@ -400,6 +430,20 @@ def coherence_propagate(gamma: torch.Tensor, opt: Optics, *, adjoint: bool = Fal
         out = torch.empty_like(gamma)
     _need(out, "out", gamma.dtype, gamma, tuple(gamma.shape))
     epi = {}
+    if loss_kind == "intensity":
+        # time-averaged intensity Re Gamma(r, r), accumulated (scaled) into loss_grad
+        inten = torch.zeros((ny, nx), dtype=_real_dtype(gamma), device=gamma.device) if loss_grad is None \
+            else loss_grad
+        _need(inten, "intensity", _real_dtype(gamma), gamma, (ny, nx))
+        job = make_job(gamma[0, 0], opt, ncomp=1, **element)
+        job.epi = _capi.TO_EPI_INTENSITY
+        job.epi_scale = float(loss_scale)
+        job.epi_out = _ptr(inten)
+        job.batch = 1
+        job.in_ = _ptr(gamma)
+        job.out = _ptr(out)
+        _capi.coherence_propagate(job, _dtype_code(gamma), adjoint, None, _stream(gamma))
+        return out, inten
     if loss_kind is not None:
         loss_grad = torch.empty_like(gamma) if loss_grad is None else loss_grad
         loss = torch.zeros((), dtype=torch.float64, device=gamma.device) if loss is None else loss

@@ -27,10 +27,12 @@ TO_EL_PHASE = 1
 TO_EL_COMPLEX = 2
 TO_EL_LENS = 4
 TO_EL_JONES = 8
+TO_EL_JONES_MAP = 16
 
 TO_EPI_NONE = 0
 TO_EPI_MSE = 1
 TO_EPI_WEIGHTED = 2
+TO_EPI_INTENSITY = 3
 
 EXPORTED = (
     "to_propagate",
@@ -82,6 +84,8 @@ class Job(ctypes.Structure):
         ("epi_loss", ctypes.c_void_p),
         ("in_", ctypes.c_void_p),
         ("out", ctypes.c_void_p),
+        ("epi_out", ctypes.c_void_p),
+        ("el_jones_map", ctypes.c_void_p),
     ]
 
 

@@ -324,10 +324,14 @@ to_status validate(const to_job& j, int idx, to_dtype dt, Mode mode) {
   if (!std::isfinite(j.y0) || !std::isfinite(j.x0)) return fail(TO_E_INVAL, "job %d: offset not finite", idx);
   if (j.batch < 0) return fail(TO_E_INVAL, "job %d: batch %lld < 0", idx, (long long)j.batch);
   if (j.ncomp != 1 && j.ncomp != 3) return fail(TO_E_INVAL, "job %d: ncomp must be 1 or 3", idx);
-  const uint32_t known = TO_EL_PHASE | TO_EL_COMPLEX | TO_EL_LENS | TO_EL_JONES;
+  const uint32_t known = TO_EL_PHASE | TO_EL_COMPLEX | TO_EL_LENS | TO_EL_JONES | TO_EL_JONES_MAP;
   if (j.el_flags & ~known) return fail(TO_E_INVAL, "job %d: unknown element flags 0x%x", idx, j.el_flags);
-  if ((j.el_flags & TO_EL_JONES) && j.ncomp != 3)
+  if ((j.el_flags & (TO_EL_JONES | TO_EL_JONES_MAP)) && j.ncomp != 3)
     return fail(TO_E_INVAL, "job %d: a Jones element needs ncomp == 3", idx);
+  if ((j.el_flags & TO_EL_JONES) && (j.el_flags & TO_EL_JONES_MAP))
+    return fail(TO_E_INVAL, "job %d: uniform and mapped Jones matrices are exclusive", idx);
+  if ((j.el_flags & TO_EL_JONES_MAP) && !j.el_jones_map)
+    return fail(TO_E_INVAL, "job %d: el_jones_map is NULL", idx);
   if ((j.el_flags & TO_EL_PHASE) && !j.el_phase) return fail(TO_E_INVAL, "job %d: el_phase is NULL", idx);
   if ((j.el_flags & TO_EL_COMPLEX) && !j.el_complex)
     return fail(TO_E_INVAL, "job %d: el_complex is NULL", idx);
@@ -336,13 +340,16 @@ to_status validate(const to_job& j, int idx, to_dtype dt, Mode mode) {
   if (j.el_flags & TO_EL_JONES)
     for (int k = 0; k < 18; ++k)
       if (!std::isfinite(j.el_jones[k])) return fail(TO_E_INVAL, "job %d: Jones matrix not finite", idx);
-  if (j.batch > 0 && mode != MODE_BWD && (!j.in || !j.out))
+  const bool intensity_only = mode == MODE_FWD && j.epi == TO_EPI_INTENSITY;
+  if (j.batch > 0 && mode != MODE_BWD && (!j.in || (!j.out && !intensity_only)))
     return fail(TO_E_INVAL, "job %d: in/out is NULL", idx);
   if (mode == MODE_FWD && j.batch > 0) {
-    if (j.epi != TO_EPI_NONE && j.epi != TO_EPI_MSE && j.epi != TO_EPI_WEIGHTED)
+    if (j.epi != TO_EPI_NONE && j.epi != TO_EPI_MSE && j.epi != TO_EPI_WEIGHTED && j.epi != TO_EPI_INTENSITY)
       return fail(TO_E_INVAL, "job %d: unknown epilogue %d", idx, j.epi);
-    if (j.epi != TO_EPI_NONE && (!j.epi_ref || !j.epi_grad || !j.epi_loss))
+    if ((j.epi == TO_EPI_MSE || j.epi == TO_EPI_WEIGHTED) && (!j.epi_ref || !j.epi_grad || !j.epi_loss))
       return fail(TO_E_INVAL, "job %d: epilogue needs epi_ref, epi_grad and epi_loss", idx);
+    if (j.epi == TO_EPI_INTENSITY && !j.epi_out)
+      return fail(TO_E_INVAL, "job %d: the intensity epilogue needs epi_out", idx);
     if (j.epi != TO_EPI_NONE && !std::isfinite(j.epi_scale))
       return fail(TO_E_INVAL, "job %d: epi_scale not finite", idx);
   }
@@ -444,6 +451,8 @@ ElementParams<T> make_element(const to_job& j, uint32_t flags) {
   e.y0 = j.y0;
   e.x0 = j.x0;
   for (int k = 0; k < 9; ++k) e.jones[k] = {(T)j.el_jones[2 * k], (T)j.el_jones[2 * k + 1]};
+  e.jones_map = (const cx<T>*)j.el_jones_map;
+  e.plane = (int64_t)j.ny * j.nx;
   return e;
 }
 
@@ -468,6 +477,14 @@ struct Geometry {
   int rows_per_block_bwd; // the same for the backward epilogue passes
   int col_variant;        // column-pass configuration (see ColCfg)
 };
+
+// Components of a field processed together by one workgroup: a Jones
+// element mixes them, and the intensity epilogue sums over them.
+bool has_jones(const to_job& j) { return (j.el_flags & (TO_EL_JONES | TO_EL_JONES_MAP)) != 0; }
+
+bool coupled(const to_job& j) { return has_jones(j) || (j.epi == TO_EPI_INTENSITY && j.ncomp == 3); }
+
+bool has_loss(const to_job& j) { return j.epi == TO_EPI_MSE || j.epi == TO_EPI_WEIGHTED; }
 
 // Fields per column-pass block: as many as keep at least two blocks per
 // CU in flight (512 on 256 CUs), so the transfer function each block forms
@@ -536,7 +553,8 @@ void element_spans(const to_job& j, to_dtype dt, std::vector<Span>* rd) {
   const size_t px = (size_t)j.ny * j.nx, re = dt == TO_C64 ? sizeof(float) : sizeof(double);
   if (j.el_flags & TO_EL_PHASE) rd->push_back(span(j.el_phase, px * re));
   if (j.el_flags & TO_EL_COMPLEX) rd->push_back(span(j.el_complex, px * 2 * re));
-  if (j.epi != TO_EPI_NONE) rd->push_back(span(j.epi_ref, px * re));
+  if (j.el_flags & TO_EL_JONES_MAP) rd->push_back(span(j.el_jones_map, 9 * px * 2 * re));
+  if (has_loss(j)) rd->push_back(span(j.epi_ref, px * re));
 }
 
 // Argument records of the three passes for one chunk of `nf` fields.
@@ -618,7 +636,8 @@ template <typename T>
 to_status finish_forward_chunk(const to_job& j, const Geometry& g, DeviceCtx* c, Lane* ln, cx<T>* scratch,
                                int64_t f0, int nf, hipStream_t s) {
   RowInvArgs<T> ia = row_inv_args<T>(j, g, c, scratch, nf);
-  ia.out = (cx<T>*)j.out + f0 * g.in_stride;
+  ia.out = j.out ? (cx<T>*)j.out + f0 * g.in_stride : nullptr;
+  ia.epi_out = j.epi == TO_EPI_INTENSITY ? (T*)j.epi_out + f0 * (int64_t)j.ny * j.nx : nullptr;
   ia.epi = j.epi;
   ia.epi_ref = (const T*)j.epi_ref;
   ia.epi_scale = (T)j.epi_scale;
@@ -633,7 +652,7 @@ to_status finish_forward_chunk(const to_job& j, const Geometry& g, DeviceCtx* c,
     return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, inv_blocks_y, ia, s);
   });
   if (e != hipSuccess) return hip_fail(e, "row_inv launch");
-  if (j.epi != TO_EPI_NONE) {
+  if (has_loss(j)) {
     e = timed("fwd.loss_reduce", 0, dbl, s, [&] {
       return launch_reduce_add(ln->partial, (int64_t)nf * j.ny, j.epi_scale, j.epi_loss, s);
     });
@@ -674,12 +693,11 @@ to_status run_forward(const to_job& j, DeviceCtx* c, Lane* ln, hipStream_t s, bo
                       const cx<T>* coh_m = nullptr) {
   if (j.batch == 0) return TO_OK;
   Geometry g;
-  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
-  to_status st = make_geometry<T>(j, jones, &g);
+  to_status st = make_geometry<T>(j, coupled(j), &g);
   if (st != TO_OK) return st;
   st = ensure_scratch(ln, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
   if (st != TO_OK) return st;
-  if (j.epi != TO_EPI_NONE) {
+  if (has_loss(j)) {
     st = ensure_partial(ln, (size_t)g.chunk * j.ny);
     if (st != TO_OK) return st;
   }
@@ -705,8 +723,7 @@ template <typename T>
 to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, Lane* ln, hipStream_t s) {
   if (j.batch == 0) return TO_OK;
   Geometry g;
-  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
-  to_status st = make_geometry<T>(j, jones, &g);
+  to_status st = make_geometry<T>(j, has_jones(j), &g);
   if (st != TO_OK) return st;
   st = ensure_scratch(ln, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
   if (st != TO_OK) return st;
@@ -745,7 +762,7 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, Lane* l
 // ---------------------------------------------------------------------------
 bool same_grid(const to_job& a, const to_job& b) {
   return a.ny == b.ny && a.nx == b.nx && a.py == b.py && a.px == b.px && a.batch == b.batch &&
-         a.ncomp == b.ncomp && !(a.el_flags & TO_EL_JONES) && !(b.el_flags & TO_EL_JONES) && a.batch > 0;
+         a.ncomp == b.ncomp && !has_jones(a) && !has_jones(b) && a.batch > 0;
 }
 
 // Field buffers of a chain may be shared between layers only whole (same
@@ -771,12 +788,13 @@ int forward_chain_len(const to_job* jobs, int n, int i, to_dtype dt) {
     const to_job& a = jobs[i + len - 1];
     const to_job& b = jobs[i + len];
     if (!same_grid(a, b) || a.epi != TO_EPI_NONE || b.in != a.out || a.out == nullptr) break;
+    if (coupled(b)) break;
     std::vector<Span> v;
     for (int k = i; k <= i + len; ++k) {
       const size_t fb = field_bytes(jobs[k], dt);
       v.push_back(span(jobs[k].in, fb));
       v.push_back(span(jobs[k].out, fb));
-      if (jobs[k].epi != TO_EPI_NONE) v.push_back(span(jobs[k].epi_grad, fb));
+      if (has_loss(jobs[k])) v.push_back(span(jobs[k].epi_grad, fb));
     }
     if (!whole_or_disjoint(v)) break;
     ++len;
@@ -812,7 +830,7 @@ to_status run_forward_chain(const to_job* jobs, int n, DeviceCtx* c, Lane* ln, h
   if (st != TO_OK) return st;
   st = ensure_scratch(ln, (size_t)g.s_stride * g.chunk * sizeof(cx<T>));
   if (st != TO_OK) return st;
-  if (jl.epi != TO_EPI_NONE && (st = ensure_partial(ln, (size_t)g.chunk * j0.ny)) != TO_OK) return st;
+  if (has_loss(jl) && (st = ensure_partial(ln, (size_t)g.chunk * j0.ny)) != TO_OK) return st;
   cx<T>* scratch = (cx<T>*)ln->scratch;
   TransferParams h[kMaxChain];
   ElementParams<T> el[kMaxChain];
@@ -955,7 +973,7 @@ to_status run_backward_chain(const to_job* jobs, const to_grad* grads, int n, De
 template <typename T>
 to_status run_modulate(const to_job& j, int adjoint, hipStream_t s) {
   if (j.batch == 0) return TO_OK;
-  const bool jones = (j.el_flags & TO_EL_JONES) != 0;
+  const bool jones = has_jones(j);
   const int64_t npix = (int64_t)j.ny * j.nx;
   const int nc = jones ? 3 : 1;
   const int64_t nfields = jones ? j.batch : j.batch * j.ncomp;
@@ -982,9 +1000,9 @@ void workspace_need(const to_job& j, bool backward, size_t* scratch_bytes, size_
   *partial_count = 0;
   if (j.batch == 0) return;
   Geometry g;
-  if (make_geometry<T>(j, (j.el_flags & TO_EL_JONES) != 0, &g) != TO_OK) return;
+  if (make_geometry<T>(j, backward ? has_jones(j) : coupled(j), &g) != TO_OK) return;
   *scratch_bytes = (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>);
-  if (!backward && j.epi != TO_EPI_NONE) *partial_count = (size_t)g.chunk * j.ny;
+  if (!backward && has_loss(j)) *partial_count = (size_t)g.chunk * j.ny;
   if (backward && (j.el_flags & TO_EL_LENS)) *partial_count = (size_t)j.ny;
 }
 
@@ -1140,7 +1158,11 @@ to_status run_coherence(const to_job& j, int adjoint, const to_grad* gr, DeviceC
     rj.out = W;
     if ((st = run_forward<T>(rj, c, &c->lane[0], s, false, nullptr)) != TO_OK) return st;
     if ((st = transpose(W, out, nullptr)) != TO_OK) return st;
-    if (j.epi != TO_EPI_NONE) {
+    if (j.epi == TO_EPI_INTENSITY) {
+      e = timed("coh.diag_intensity", n, dbl, s,
+                [&] { return Coh<T>::diag_intensity(out, (T*)j.epi_out, n, (T)j.epi_scale, s); });
+      if (e != hipSuccess) return hip_fail(e, "coherence intensity");
+    } else if (j.epi != TO_EPI_NONE) {
       e = timed("coh.diag_loss", n, dbl, s, [&] {
         return Coh<T>::diag_loss(out, (const T*)j.epi_ref, (cx<T>*)j.epi_grad, part, n, j.epi, (T)j.epi_scale,
                                  s);
@@ -1202,7 +1224,8 @@ to_status plain_setup(const to_job& j, DeviceCtx* c, bool conj, hipStream_t s, P
 template <typename T>
 to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
   if (j.batch == 0) return TO_OK;
-  if (j.el_flags & TO_EL_JONES) return fail(TO_E_UNSUPPORTED, "the plain form has no Jones elements");
+  if (has_jones(j)) return fail(TO_E_UNSUPPORTED, "the plain form has no Jones elements");
+  if (j.epi == TO_EPI_INTENSITY) return fail(TO_E_UNSUPPORTED, "the plain form has no intensity epilogue");
   PlainWork<T> w;
   to_status st = plain_setup<T>(j, c, false, s, &w);
   if (st != TO_OK) return st;
@@ -1241,7 +1264,7 @@ to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
 template <typename T>
 to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStream_t s) {
   if (j.batch == 0) return TO_OK;
-  if (j.el_flags & TO_EL_JONES) return fail(TO_E_UNSUPPORTED, "the plain form has no Jones elements");
+  if (has_jones(j)) return fail(TO_E_UNSUPPORTED, "the plain form has no Jones elements");
   if (gr.grad_f) return fail(TO_E_UNSUPPORTED, "the plain form has no lens gradient");
   PlainWork<T> w;
   to_status st = plain_setup<T>(j, c, true, s, &w);
@@ -1395,10 +1418,12 @@ to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* 
       rd[u].push_back(span(j.in, fb));
       wr[u].push_back(span(j.out, fb));
       element_spans(j, dtype, &rd[u]);
-      if (j.epi != TO_EPI_NONE) {
+      if (has_loss(j)) {
         wr[u].push_back(span(j.epi_grad, fb));
         wr[u].push_back(span(j.epi_loss, sizeof(double)));
       }
+      if (j.epi == TO_EPI_INTENSITY)
+        wr[u].push_back(span(j.epi_out, (size_t)j.batch * j.ny * j.nx * (dtype == TO_C64 ? 4 : 8)));
       cost[u] += job_cost(j);
     }
   }
@@ -1527,13 +1552,15 @@ to_status to_coherence_propagate(const to_job* job, to_dtype dtype, int32_t adjo
   if (st != TO_OK) return st;
   const to_job& j = *job;
   if (j.batch != 1 || j.ncomp != 1) return fail(TO_E_INVAL, "coherence job needs batch == 1 and ncomp == 1");
-  if (j.el_flags & TO_EL_JONES) return fail(TO_E_UNSUPPORTED, "coherence job with a Jones element");
+  if (has_jones(j)) return fail(TO_E_UNSUPPORTED, "coherence job with a Jones element");
   if ((int64_t)j.ny * j.nx > 46340) return fail(TO_E_UNSUPPORTED, "coherence grid too large");
-  if (adjoint && j.epi != TO_EPI_NONE) return fail(TO_E_INVAL, "the adjoint has no loss epilogue");
+  if (adjoint && j.epi != TO_EPI_NONE) return fail(TO_E_INVAL, "the adjoint has no epilogue");
   if (j.epi != TO_EPI_NONE) {
-    if (j.epi != TO_EPI_MSE && j.epi != TO_EPI_WEIGHTED) return fail(TO_E_INVAL, "unknown epilogue %d", j.epi);
-    if (!j.epi_ref || !j.epi_grad || !j.epi_loss)
+    if (j.epi != TO_EPI_MSE && j.epi != TO_EPI_WEIGHTED && j.epi != TO_EPI_INTENSITY)
+      return fail(TO_E_INVAL, "unknown epilogue %d", j.epi);
+    if (has_loss(j) && (!j.epi_ref || !j.epi_grad || !j.epi_loss))
       return fail(TO_E_INVAL, "epilogue needs epi_ref, epi_grad and epi_loss");
+    if (j.epi == TO_EPI_INTENSITY && !j.epi_out) return fail(TO_E_INVAL, "the intensity epilogue needs epi_out");
     if (!std::isfinite(j.epi_scale)) return fail(TO_E_INVAL, "epi_scale not finite");
   }
   if (adjoint && grad && grad->grad_phase && (j.el_flags & TO_EL_PHASE)) {
@@ -1563,6 +1590,7 @@ to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* 
   tj.epi_grad = nullptr;
   tj.epi_loss = nullptr;
   tj.epi_ref = nullptr;
+  tj.epi_out = nullptr;
   void* tmp = nullptr;
   hipError_t e = hipMalloc(&tmp, field_bytes(*job, dtype));
   if (e != hipSuccess) return fail(TO_E_NOMEM, "autotune output allocation failed: %s", hipGetErrorString(e));
@@ -1581,8 +1609,8 @@ to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* 
       PlanEntry pe{v, mb, 0.0};
       Geometry g;
       t_force_plan = &pe;
-      const to_status gs = dtype == TO_C64 ? make_geometry<float>(tj, (tj.el_flags & TO_EL_JONES) != 0, &g)
-                                           : make_geometry<double>(tj, (tj.el_flags & TO_EL_JONES) != 0, &g);
+      const to_status gs = dtype == TO_C64 ? make_geometry<float>(tj, coupled(tj), &g)
+                                           : make_geometry<double>(tj, coupled(tj), &g);
       t_force_plan = nullptr;
       if (gs != TO_OK || g.col_variant != v) continue;
       const std::pair<int, int64_t> key(v, g.chunk);

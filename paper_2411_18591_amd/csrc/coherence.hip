@@ -93,6 +93,14 @@ __global__ void __launch_bounds__(256) coh_diag_loss_kernel(const cx<T>* __restr
   if (threadIdx.x == 0) partial[r] = s;
 }
 
+// out[r] += scale * Re Gamma(r, r): the time-averaged intensity.
+template <typename T>
+__global__ void __launch_bounds__(256) coh_diag_intensity_kernel(const cx<T>* __restrict__ g, T* __restrict__ out,
+                                                                 int n, T scale) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) out[r] += scale * g[(int64_t)r * n + r].x;
+}
+
 // t(a, b) = Im(G(a, b) conj(Gm(a, b))), Gm = m[a] conj(m[b]) Gamma(a, b).
 template <typename T>
 __device__ __forceinline__ double coh_grad_term(const cx<T>* G, const cx<T>* Gam, const cx<T>* m, int n, int a,
@@ -166,6 +174,12 @@ template <typename T>
 hipError_t Coh<T>::diag_loss(const cx<T>* g, const T* ref, cx<T>* grad, double* partial, int n, int kind, T scale,
                              hipStream_t s) {
   hipLaunchKernelGGL((coh_diag_loss_kernel<T>), dim3(n), dim3(256), 0, s, g, ref, grad, partial, n, kind, scale);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Coh<T>::diag_intensity(const cx<T>* g, T* out, int n, T scale, hipStream_t s) {
+  hipLaunchKernelGGL((coh_diag_intensity_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, s, g, out, n, scale);
   return hipGetLastError();
 }
 

@@ -14,6 +14,8 @@ struct Coh {
   static hipError_t mtable(cx<T>* m, int ny, int nx, const ElementParams<T>& el, int conj, hipStream_t s);
   // g[a][b] *= conj(m[a]) m[b]
   static hipError_t scale(cx<T>* g, const cx<T>* m, int n, hipStream_t s);
+  // out[r] += scale * Re g[r][r]
+  static hipError_t diag_intensity(const cx<T>* g, T* out, int n, T scale, hipStream_t s);
   static hipError_t diag_loss(const cx<T>* g, const T* ref, cx<T>* grad, double* partial, int n, int kind,
                               T scale, hipStream_t s);
   static hipError_t phase_grad(const cx<T>* G, const cx<T>* Gam, const cx<T>* m, double* rowsum, double* colsum,

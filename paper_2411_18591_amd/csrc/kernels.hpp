@@ -27,8 +27,8 @@
 namespace toprop {
 
 // Element flags (mirrors the public header).
-enum : uint32_t { EL_PHASE = 1u, EL_COMPLEX = 2u, EL_LENS = 4u, EL_JONES = 8u };
-enum : int { EPI_NONE = 0, EPI_MSE = 1, EPI_WEIGHTED = 2 };
+enum : uint32_t { EL_PHASE = 1u, EL_COMPLEX = 2u, EL_LENS = 4u, EL_JONES = 8u, EL_JONES_MAP = 16u };
+enum : int { EPI_NONE = 0, EPI_MSE = 1, EPI_WEIGHTED = 2, EPI_INTENSITY = 3 };
 
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -199,7 +199,43 @@ struct ElementParams {
   double lens_a;          // 1 / (2 lambda f): lens phase = -r^2 * lens_a cycles
   double dy, dx, y0, x0;  // grid spacing and offset of the optical axis
   cx<T> jones[9];         // row-major 3x3
+  const cx<T>* jones_map; // EL_JONES_MAP: [3][3][ny][nx], entry (r, c) at plane 3 r + c
+  int64_t plane;          // ny * nx
 };
+
+// Jones matrix entry k = 3 r + c at pixel `pix` (uniform or mapped).
+template <typename T>
+__device__ __forceinline__ cx<T> jones_entry(const ElementParams<T>& e, int64_t pix, int k) {
+  return (e.flags & EL_JONES_MAP) ? e.jones_map[k * e.plane + pix] : e.jones[k];
+}
+
+// v <- J v at pixel `pix`.
+template <typename T>
+__device__ __forceinline__ void apply_jones(const ElementParams<T>& e, int64_t pix, cx<T>* v) {
+  cx<T> o[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    o[r] = cmul(jones_entry(e, pix, 3 * r + 0), v[0]);
+    o[r] = cadd(o[r], cmul(jones_entry(e, pix, 3 * r + 1), v[1]));
+    o[r] = cadd(o[r], cmul(jones_entry(e, pix, 3 * r + 2), v[2]));
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) v[r] = o[r];
+}
+
+// v <- J^H v at pixel `pix`.
+template <typename T>
+__device__ __forceinline__ void apply_jones_adjoint(const ElementParams<T>& e, int64_t pix, cx<T>* v) {
+  cx<T> o[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    o[r] = cmulc(v[0], jones_entry(e, pix, 0 * 3 + r));
+    o[r] = cadd(o[r], cmulc(v[1], jones_entry(e, pix, 1 * 3 + r)));
+    o[r] = cadd(o[r], cmulc(v[2], jones_entry(e, pix, 2 * 3 + r)));
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) v[r] = o[r];
+}
 
 // Scalar modulation at pixel (y, x): phase mask, complex mask, thin lens.
 template <typename T>
@@ -345,6 +381,7 @@ struct RowInvArgs {
   const T* epi_ref;     // MSE target or intensity weight, [ny][nx]
   T epi_scale;
   cx<T>* epi_grad;      // dL/d(out), same layout as out
+  T* epi_out;           // intensity epilogue: [field][ny][nx], accumulated
   double* row_partial;  // per (field, row) loss partial sums
   // backward: element adjoint and parameter gradients
   int backward;
@@ -437,16 +474,11 @@ __global__ void __launch_bounds__(G * (L / R)) row_fwd_kernel(RowFwdArgs<T> a) {
       }
       if (m < RI) {
         if constexpr (NC == 3) {
-          if (a.el.flags & EL_JONES) {
-            cx<T> o[3];
+          if ((a.el.flags & (EL_JONES | EL_JONES_MAP)) && rowok && jv + m * TT < nx) {
+            cx<T> w[3] = {v[0][m], v[1][m], v[2][m]};
+            apply_jones(a.el, (int64_t)yv * nx + (jv + m * TT), w);
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-              o[r] = cmul(a.el.jones[3 * r + 0], v[0][m]);
-              o[r] = cadd(o[r], cmul(a.el.jones[3 * r + 1], v[1][m]));
-              o[r] = cadd(o[r], cmul(a.el.jones[3 * r + 2], v[2][m]));
-            }
-#pragma unroll
-            for (int r = 0; r < 3; ++r) v[r][m] = o[r];
+            for (int r = 0; r < 3; ++r) v[r][m] = w[r];
           }
         }
         if (scalar_el) {
@@ -695,10 +727,16 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) v[c][m] = cscale(v[c][m], a.scale);
         if constexpr (!kBwd) {
+          if (a.epi == EPI_INTENSITY) {
+            T I = T(0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) I += v[c][m].x * v[c][m].x + v[c][m].y * v[c][m].y;
+            a.epi_out[(int64_t)f * ny * nx + pix] += a.epi_scale * I;
+          }
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             const uint32_t o = (uint32_t)(c * a.comp_stride) + pix;
-            a.out[fbase + o] = v[c][m];
+            if (a.out) a.out[fbase + o] = v[c][m];
             if (a.epi == EPI_MSE) {
               const T I = v[c][m].x * v[c][m].x + v[c][m].y * v[c][m].y;
               const T d = I - a.epi_ref[pix];
@@ -724,17 +762,7 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
               for (int c = 0; c < NC; ++c) u[c] = a.saved_in[fbase + (uint32_t)(c * a.comp_stride) + pix];
             }
             if constexpr (NC == 3) {
-              if (fl & EL_JONES) {
-                cx<T> o[3];
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                  o[r] = cmul(a.el.jones[3 * r + 0], u[0]);
-                  o[r] = cadd(o[r], cmul(a.el.jones[3 * r + 1], u[1]));
-                  o[r] = cadd(o[r], cmul(a.el.jones[3 * r + 2], u[2]));
-                }
-#pragma unroll
-                for (int r = 0; r < 3; ++r) u[r] = o[r];
-              }
+              if (fl & (EL_JONES | EL_JONES_MAP)) apply_jones(a.el, (int64_t)pix, u);
             }
             T im = T(0);
 #pragma unroll
@@ -750,17 +778,7 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) gi[c] = cmulc(v[c][m], mod);  // conj(M) g
             if constexpr (NC == 3) {
-              if (fl & EL_JONES) {  // J^H g
-                cx<T> o[3];
-#pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                  o[r] = cmulc(gi[0], a.el.jones[0 * 3 + r]);
-                  o[r] = cadd(o[r], cmulc(gi[1], a.el.jones[1 * 3 + r]));
-                  o[r] = cadd(o[r], cmulc(gi[2], a.el.jones[2 * 3 + r]));
-                }
-#pragma unroll
-                for (int r = 0; r < 3; ++r) gi[r] = o[r];
-              }
+              if (fl & (EL_JONES | EL_JONES_MAP)) apply_jones_adjoint(a.el, (int64_t)pix, gi);  // J^H g
             }
 #pragma unroll
             for (int c = 0; c < NC; ++c) a.out[fbase + (uint32_t)(c * a.comp_stride) + pix] = gi[c];
@@ -768,7 +786,7 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
         }
       }
     }
-    if (!kBwd && a.epi != EPI_NONE) {
+    if (!kBwd && (a.epi == EPI_MSE || a.epi == EPI_WEIGHTED)) {
       const double s = group_sum<TT, G>(loss_acc, red);
       if (active && j == 0) a.row_partial[(int64_t)f * ny + y] = s;
     }
@@ -1071,17 +1089,7 @@ __global__ void __launch_bounds__(256) modulate_kernel(const cx<T>* in, cx<T>* o
     if (adjoint) mod.y = -mod.y;
     if (!adjoint) {
       if constexpr (NC == 3) {
-        if (el.flags & EL_JONES) {
-          cx<T> o[3];
-#pragma unroll
-          for (int r = 0; r < 3; ++r) {
-            o[r] = cmul(el.jones[3 * r + 0], v[0]);
-            o[r] = cadd(o[r], cmul(el.jones[3 * r + 1], v[1]));
-            o[r] = cadd(o[r], cmul(el.jones[3 * r + 2], v[2]));
-          }
-#pragma unroll
-          for (int r = 0; r < 3; ++r) v[r] = o[r];
-        }
+        if (el.flags & (EL_JONES | EL_JONES_MAP)) apply_jones(el, pix, v);
       }
 #pragma unroll
       for (int c = 0; c < NC; ++c) v[c] = cmul(mod, v[c]);
@@ -1089,17 +1097,7 @@ __global__ void __launch_bounds__(256) modulate_kernel(const cx<T>* in, cx<T>* o
 #pragma unroll
       for (int c = 0; c < NC; ++c) v[c] = cmul(mod, v[c]);
       if constexpr (NC == 3) {
-        if (el.flags & EL_JONES) {
-          cx<T> o[3];
-#pragma unroll
-          for (int r = 0; r < 3; ++r) {
-            o[r] = cmulc(v[0], el.jones[0 * 3 + r]);
-            o[r] = cadd(o[r], cmulc(v[1], el.jones[1 * 3 + r]));
-            o[r] = cadd(o[r], cmulc(v[2], el.jones[2 * 3 + r]));
-          }
-#pragma unroll
-          for (int r = 0; r < 3; ++r) v[r] = o[r];
-        }
+        if (el.flags & (EL_JONES | EL_JONES_MAP)) apply_jones_adjoint(el, pix, v);
       }
     }
 #pragma unroll

@@ -98,6 +98,14 @@ def good_job(capi):
     (lambda j: setattr(j, "out", None), "TO_E_INVAL"),
     (lambda j: setattr(j, "epi", 1), "TO_E_INVAL"),         # epilogue buffers NULL
     (lambda j: setattr(j, "epi", 9), "TO_E_INVAL"),
+    (lambda j: setattr(j, "epi", 3), "TO_E_INVAL"),         # intensity without epi_out
+    (lambda j: (setattr(j, "ncomp", 3), setattr(j, "el_flags", 16)), "TO_E_INVAL"),   # Jones map NULL
+    (lambda j: (setattr(j, "ncomp", 3), setattr(j, "el_flags", 24), setattr(j, "el_jones_map", 0x7000)),
+     "TO_E_INVAL"),                                         # uniform and mapped Jones together
+    (lambda j: (setattr(j, "el_flags", 16), setattr(j, "el_jones_map", 0x7000)), "TO_E_INVAL"),  # ncomp 1
+    (lambda j: (setattr(j, "epi", 3), setattr(j, "epi_out", 0x6000), setattr(j, "in_", None)), "TO_E_INVAL"),
+    (lambda j: (setattr(j, "epi", 3), setattr(j, "epi_out", 0x6000), setattr(j, "epi_scale", float("nan"))),
+     "TO_E_INVAL"),
 ])
 def test_validation_rejects_bad_jobs(capi, mutate, status):
     j = good_job(capi)

@@ -228,3 +228,35 @@ def test_autograd_finite_differences_c128():
         hf = 1e-7
         fdf = (loss_of(phi, f + hf) - loss_of(phi, f - hf)) / (2 * hf)
         assert abs(float(fdf - f.grad)) <= 1e-3 * abs(float(f.grad))
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_jones_map_forward_backward(dtype):
+    """A spatially varying Jones matrix J(r) (random complex 3x3 per pixel)
+    with a lens: forward field, modulation alone, input gradient (J^H) and
+    focal-length gradient against the oracle's per-pixel Jones product."""
+    tp = _tp()
+    announce(f"jones map {dtype.__name__}")
+    rng = np.random.default_rng(28)
+    B, n, d, lam, f, z = 2, 32, 6e-6, 0.6e-6, 0.05, 0.01
+    E = crandn(rng, B, 3, n, n, dtype=dtype)
+    Jm = crandn(rng, 3, 3, n, n, dtype=dtype) / 2
+    G = crandn(rng, B, 3, n, n, dtype=dtype)
+    L = oracle.lens(n, n, d, d, lam, f)
+    Em = oracle.modulate(oracle.jones_apply(E, Jm), L)
+    out = oracle.propagate(Em, d, d, lam, z, oracle.ASM, 2)
+    g_mod = oracle.propagate(G, d, d, lam, z, oracle.ASM, 2, adjoint=True)
+    exp_gin = oracle.jones_apply(oracle.modulate(g_mod, L, conj=True), Jm, conj_transpose=True)
+    exp_f = oracle.grad_lens_f(g_mod, Em, n, n, d, d, lam, f)
+
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, pad=2)
+    Eg, Jg = to_gpu(E, torch), to_gpu(Jm, torch)
+    o = tp.propagate(Eg, opt, ncomp=3, jones_map=Jg, lens_f=f)
+    mo = tp.modulate(Eg, dy=d, dx=d, wavelength=lam, ncomp=3, jones_map=Jg, lens_f=f)
+    gf = torch.zeros((), dtype=torch.float64, device="cuda")
+    gin = tp.propagate_backward(to_gpu(G, torch), opt, saved_in=Eg, grad_f=gf, ncomp=3, jones_map=Jg, lens_f=f)
+    torch.cuda.synchronize()
+    assert rel(to_np(o), out) <= FIELD_TOL[dtype]
+    assert rel(to_np(mo), Em) <= FIELD_TOL[dtype] / 4
+    assert rel(to_np(gin), exp_gin) <= FIELD_TOL[dtype]
+    assert abs(float(gf.item()) - exp_f) <= PARAM_TOL[dtype] * abs(exp_f)

@@ -1,0 +1,129 @@
+"""The intensity epilogue on the GPU: the detected intensity of propagated
+fields (sum over polarization components), accumulated across jobs with
+per-wavelength weights (the incoherent polychromatic sum, Eq. (I_poly)), and
+the time-averaged intensity Re Gamma(r, r) of a propagated mutual coherence.
+Against the FP64 oracle's fields and its intensity / incoherent_sum /
+coherence_intensity (pinned on the CPU).  Bar: complex64 relative L2 <= 4e-5
+(intensities are squares of fields at 2e-5), complex128 <= 1e-12."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests._util import announce, crandn, rel, to_gpu, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {np.complex64: 4e-5, np.complex128: 1e-12}
+
+
+def _tp():
+    import paper_2411_18591_amd as tp
+    return tp
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_polychromatic_polarized_intensity(dtype):
+    """Three wavelengths, 3-component fields through a quarter-wave plate,
+    a polarizer and a lens, Fresnel propagation; the three jobs share one
+    intensity buffer with weights 0.5, 1, 2 and do not store the fields."""
+    tp = _tp()
+    announce(f"polychromatic intensity {dtype.__name__}")
+    rng = np.random.default_rng(810)
+    n, d, z, f = 48, 6e-6, 0.02, 0.05
+    lams = (480e-9, 560e-9, 640e-9)
+    wts = (0.5, 1.0, 2.0)
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    E = [crandn(rng, 2, 3, n, n, dtype=dtype) for _ in lams]
+    Jg = tp.jones3(tp.waveplate(math.pi / 4, math.pi / 2), tp.linear_polarizer(0.4))
+    Jo = oracle.embed_jones(oracle.linear_polarizer(0.4) @ oracle.waveplate(math.pi / 4, math.pi / 2))
+    I = torch.zeros((2, n, n), dtype=torch.float32 if dtype == np.complex64 else torch.float64, device="cuda")
+    opts = [tp.Optics(dy=d, dx=d, wavelength=lam, z=z, method="fresnel", pad=2) for lam in lams]
+    els = [dict(jones=Jg, lens_f=f, epi=tp._capi.TO_EPI_INTENSITY, epi_out=I, epi_scale=w) for w in wts]
+    keep = [to_gpu(e, torch) for e in E]
+    jobs = [tp.make_job(k, o, ncomp=3, **el) for k, o, el in zip(keep, opts, els)]
+    tp._capi.propagate(jobs, tp._capi.TO_C64 if dtype == np.complex64 else tp._capi.TO_C128,
+                       torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    outs = []
+    for e, lam, o in zip(E, lams, opts):
+        m = oracle.modulate(oracle.jones_apply(e, Jo), oracle.lens(n, n, d, d, lam, f))
+        outs.append(oracle.propagate(m, d, d, lam, z, oracle.FRESNEL, padded=o.padded_shape(n, n)))
+    exp = oracle.incoherent_sum(outs, wts, ncomp=3)
+    assert rel(to_np(I), exp) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_scalar_batch_intensity_and_field(dtype):
+    """A batch of scalar fields: per-field intensity, the field stored too."""
+    tp = _tp()
+    announce(f"scalar batch intensity {dtype.__name__}")
+    rng = np.random.default_rng(811)
+    u = crandn(rng, 3, 40, 56, dtype=dtype)
+    phi = (rng.random((40, 56)) * 6).astype(np.float32 if dtype == np.complex64 else np.float64)
+    opt = tp.Optics(dy=5e-6, dx=5e-6, wavelength=600e-9, z=0.01, pad=2)
+    ug = to_gpu(u, torch)
+    out = torch.empty_like(ug)
+    I = tp.propagate_intensity(ug, opt, out=out, weight=1.0, phase=to_gpu(phi, torch))
+    torch.cuda.synchronize()
+    field = oracle.propagate(oracle.modulate(u, oracle.phase_mask(phi)), 5e-6, 5e-6, 600e-9, 0.01, oracle.ASM,
+                             padded=opt.padded_shape(40, 56))
+    assert rel(to_np(out), field) <= TOL[dtype] / 2
+    assert rel(to_np(I), oracle.intensity(field)) <= TOL[dtype]
+
+
+def test_polarized_intensity_without_jones():
+    """Three uncoupled components (no Jones element): the epilogue still sums
+    them per pixel."""
+    tp = _tp()
+    announce("3-component intensity without Jones")
+    rng = np.random.default_rng(812)
+    E = crandn(rng, 2, 3, 32, 32, dtype=np.complex128)
+    opt = tp.Optics(dy=4e-6, dx=4e-6, wavelength=500e-9, z=0.005, pad=2)
+    I = tp.propagate_intensity(to_gpu(E, torch), opt, ncomp=3, weight=0.75, lens_f=0.03)
+    torch.cuda.synchronize()
+    m = oracle.modulate(E, oracle.lens(32, 32, 4e-6, 4e-6, 500e-9, 0.03))
+    field = oracle.propagate(m, 4e-6, 4e-6, 500e-9, 0.005, oracle.ASM, 2)
+    assert rel(to_np(I), 0.75 * oracle.intensity(field, ncomp=3)) <= 1e-12
+
+
+def test_chain_ending_in_intensity():
+    """A chain of phase layers whose last job detects the intensity: fused
+    chain against one call per layer."""
+    tp = _tp()
+    announce("chain with intensity epilogue")
+    rng = np.random.default_rng(813)
+    B, n, L = 3, 64, 3
+    u0 = to_gpu(crandn(rng, B, n, n, dtype=np.complex64), torch)
+    P = to_gpu((rng.random((L, n, n)) * 6).astype(np.float32), torch)
+    opt = tp.Optics(dy=8e-6, dx=8e-6, wavelength=700e-9, z=0.02, pad=2)
+    u = [u0] + [torch.empty_like(u0) for _ in range(L - 1)]
+    I = torch.zeros((B, n, n), dtype=torch.float32, device="cuda")
+    els = [{"phase": P[l]} for l in range(L)]
+    els[-1].update(epi=tp._capi.TO_EPI_INTENSITY, epi_out=I, epi_scale=1.0)
+    jobs = [tp.make_job(u[l], opt, out=u[l + 1] if l + 1 < L else None, **els[l]) for l in range(L)]
+    tp._capi.propagate(jobs, tp._capi.TO_C64, torch.cuda.current_stream().cuda_stream)
+    v = u0
+    for l in range(L - 1):
+        v = tp.propagate(v, opt, phase=P[l])
+    I2 = tp.propagate_intensity(v, opt, phase=P[L - 1])
+    torch.cuda.synchronize()
+    assert rel(to_np(I), to_np(I2)) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_coherence_intensity(dtype):
+    tp = _tp()
+    announce(f"coherence intensity {dtype.__name__}")
+    rng = np.random.default_rng(814)
+    n = 8
+    A = crandn(rng, n * n, n * n) / n
+    G0 = (A @ A.conj().T).reshape(n, n, n, n).astype(dtype)
+    opt = tp.Optics(dy=10e-6, dx=10e-6, wavelength=633e-9, z=0.01, pad=2)
+    out, I = tp.coherence_propagate(to_gpu(G0, torch), opt, loss_kind="intensity", loss_scale=2.0)
+    torch.cuda.synchronize()
+    Go = oracle.coherence_propagate(G0, 10e-6, 10e-6, 633e-9, 0.01, oracle.ASM, 2)
+    assert rel(to_np(out), Go) <= TOL[dtype] / 2
+    assert rel(to_np(I), 2.0 * oracle.coherence_intensity(Go)) <= TOL[dtype]

@@ -496,3 +496,44 @@ def test_coherence_mask_gradient_finite_differences():
         pm[y, x] -= h
         fd = (loss_of(pp)[0] - loss_of(pm)[0]) / (2 * h)
         assert abs(fd - grad[y, x]) <= 1e-6 * max(abs(fd), 1e-6)
+
+
+def test_intensity_malus_law_components():
+    """Intensity of a 3-component field is the sum over components: an
+    x-polarized unit field behind a linear polarizer at theta carries
+    cos^2(theta) (Malus's law, closed form)."""
+    E = np.zeros((3, 4, 4), complex)
+    E[0] = 1.0
+    for th in (0.0, 0.3, np.pi / 4, 1.2, np.pi / 2):
+        J = oracle.embed_jones(oracle.linear_polarizer(th))
+        I = oracle.intensity(oracle.jones_apply(E, J), ncomp=3)
+        assert np.allclose(I, np.cos(th) ** 2, atol=1e-15)
+    rng = np.random.default_rng(61)
+    u = rng.standard_normal((2, 5, 6)) + 1j * rng.standard_normal((2, 5, 6))
+    assert np.allclose(oracle.intensity(u), u.real ** 2 + u.imag ** 2, rtol=1e-14, atol=0)
+
+
+def test_incoherent_sum_has_no_cross_terms():
+    """Eq. (I_poly): mutually incoherent wavelengths add in intensity.  The
+    coherent superposition differs from it by exactly the interference term
+    2 Re(u1 conj(u2)); the weights scale linearly."""
+    rng = np.random.default_rng(62)
+    u1 = rng.standard_normal((6, 7)) + 1j * rng.standard_normal((6, 7))
+    u2 = rng.standard_normal((6, 7)) + 1j * rng.standard_normal((6, 7))
+    inc = oracle.incoherent_sum([u1, u2], [1.0, 1.0])
+    coh = np.abs(u1 + u2) ** 2
+    assert np.allclose(coh - inc, 2 * np.real(u1 * np.conj(u2)), atol=1e-12)
+    w = oracle.incoherent_sum([u1, u2], [0.25, 2.0])
+    assert np.allclose(w, 0.25 * np.abs(u1) ** 2 + 2.0 * np.abs(u2) ** 2, atol=1e-12)
+
+
+def test_incoherent_sum_equals_coherence_diagonal():
+    """A partially coherent field given as incoherent modes, Gamma = sum_k
+    w_k u_k u_k^H, has the time-averaged intensity Re Gamma(r, r) =
+    sum_k w_k |u_k|^2 (section "Spatial coherence")."""
+    rng = np.random.default_rng(63)
+    n = 4
+    modes = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for _ in range(3)]
+    w = [0.5, 1.5, 0.25]
+    G = sum(wk * np.einsum("ab,cd->abcd", u, np.conj(u)) for wk, u in zip(w, modes))
+    assert np.allclose(oracle.coherence_intensity(G), oracle.incoherent_sum(modes, w), atol=1e-12)
