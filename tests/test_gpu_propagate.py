@@ -158,3 +158,28 @@ def test_polarizer_listing_on_gpu():
         torch.cuda.synchronize()
         p = float(np.sum(np.abs(to_np(F)) ** 2) * d * d)
         assert abs(p - case["power"]) < 1e-14
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_evanescent_cutoff(dtype):
+    """Spacing below lambda / sqrt(2): the outer spectrum is evanescent and
+    cut (H = 0); the library takes its per-bin FP64 transfer path.  Parity
+    with the oracle, and a plane wave at an evanescent grid frequency is
+    removed entirely."""
+    # spacings chosen so that no bin lies within 5e-4 of the cutoff circle
+    # (a bin on it in exact arithmetic is a floating-point tie: the FP64
+    # kernel and the long-double oracle may round it to either side)
+    e = run_case(48, 40, 128, 128, "asm", dtype, d=(0.37e-6, 0.43e-6), lam=0.8e-6, z=2e-6)
+    assert e <= TOL[dtype], e
+    tp = _tp()
+    n, d, lam = 32, 0.4e-6, 0.8e-6
+    k = 12  # grid frequency f = k / (n d) on both axes: lambda^2 (2 f^2) = 1.125 > 1
+    y = np.arange(n)[:, None]
+    x = np.arange(n)[None, :]
+    u = np.exp(2j * np.pi * (k * x + k * y) / n).astype(dtype)[None]
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=1e-6, pad=1, padded=(n, n))
+    out = to_np(tp.propagate(to_gpu(u, torch), opt))
+    torch.cuda.synchronize()
+    fx = k / (n * d)
+    assert lam * lam * 2 * fx * fx > 1.0  # the wave is evanescent
+    assert np.abs(out).max() <= 1e-6 * np.abs(u).max()
