@@ -198,3 +198,43 @@ def test_long_chain_splits():
         v = tp.propagate(v, opt, phase=phis[l])
     torch.cuda.synchronize()
     assert rel(to_np(u[L]), to_np(v)) <= 1e-13
+
+
+def test_training_step_graph_capture():
+    """The diffractive-network training step (one chained call forward, one
+    backward) captured in a HIP graph: three replays with new inputs, each
+    equal to an eager step."""
+    tp = _tp()
+    from paper_2411_18591_amd.diffnet import DiffractiveNet
+    announce("training step in a HIP graph")
+    rng = np.random.default_rng(730)
+    B, n, L = 4, 64, 3
+    opt = tp.Optics(dy=8e-6, dx=8e-6, wavelength=700e-9, z=0.02, pad=2)
+    net = DiffractiveNet(torch.zeros((B, n, n), dtype=torch.complex64, device="cuda"),
+                         to_gpu((rng.random((L, n, n)) * 6).astype(np.float32), torch),
+                         to_gpu(rng.random((n, n)).astype(np.float32), torch), opt)
+
+    def fill(seed):
+        r = np.random.default_rng(seed)
+        net.u[0].copy_(to_gpu(crandn(r, B, n, n, dtype=np.complex64), torch))
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fill(1)
+        net.step()  # sizes the workspaces outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        net.step()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        fill(200 + rep)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = [net.loss.clone(), net.gmask.clone(), net.u[L].clone()]
+        net.step()
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], net.loss) and torch.equal(got[1], net.gmask) and torch.equal(got[2], net.u[L]), rep
