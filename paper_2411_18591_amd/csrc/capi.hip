@@ -148,7 +148,7 @@ to_status ensure_scratch(Lane* c, size_t bytes) {
   hipError_t e;
   if (c->scratch) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    hipFree(c->scratch);
+    (void)hipFree(c->scratch);
     c->scratch = nullptr;
     c->scratch_bytes = 0;
   }
@@ -164,7 +164,7 @@ to_status ensure_plain(DeviceCtx* c, size_t bytes) {
   hipError_t e;
   if (c->plain) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    hipFree(c->plain);
+    (void)hipFree(c->plain);
     c->plain = nullptr;
     c->plain_bytes = 0;
   }
@@ -179,7 +179,7 @@ to_status ensure_partial(Lane* c, size_t count) {
   hipError_t e;
   if (c->partial) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    hipFree(c->partial);
+    (void)hipFree(c->partial);
     c->partial = nullptr;
     c->partial_count = 0;
   }
@@ -245,6 +245,7 @@ Schedule schedule_for(int dtype, int ly, int lx) {
 struct ProfRec {
   std::string name;
   hipEvent_t a, b;
+  bool valid;  // both events recorded
 };
 struct ProfAgg {
   std::string name;
@@ -277,7 +278,8 @@ int prof_start(const char* name, int L, bool dbl, hipStream_t s) {
   r.a = prof_event();
   r.b = prof_event();
   if (!r.a || !r.b) return -1;
-  hipEventRecord(r.a, s);
+  if (hipEventRecord(r.a, s) != hipSuccess) return -1;  // launch not timed
+  r.valid = false;
   g_prof_recs.push_back(r);
   return (int)g_prof_recs.size() - 1;
 }
@@ -285,7 +287,7 @@ int prof_start(const char* name, int L, bool dbl, hipStream_t s) {
 void prof_stop(int tok, hipStream_t s) {
   if (tok < 0) return;
   std::lock_guard<std::mutex> lk(g_prof_mutex);
-  hipEventRecord(g_prof_recs[tok].b, s);
+  g_prof_recs[tok].valid = hipEventRecord(g_prof_recs[tok].b, s) == hipSuccess;
 }
 
 template <typename F>
@@ -422,15 +424,6 @@ hipError_t prepare_transfer(const to_job& j, Lane* c, hipStream_t s, TransferPar
 // the transform of the current one (and evaluates the element's modulation
 // once for all of them), while the launch keeps >= ~2048 blocks.
 int fields_per_block_rows(int row_blocks, int nfields) {
-  int fpb = (int)((int64_t)row_blocks * nfields / 2048);
-  if (fpb < 1) fpb = 1;
-  if (fpb > 8) fpb = 8;
-  if (fpb > nfields) fpb = nfields;
-  return fpb;
-}
-
-int fields_per_block(const to_job& j, int row_blocks, int nfields) {
-  (void)j;
   int fpb = (int)((int64_t)row_blocks * nfields / 2048);
   if (fpb < 1) fpb = 1;
   if (fpb > 8) fpb = 8;
@@ -1108,7 +1101,7 @@ to_status ensure_coh(DeviceCtx* c, size_t bytes) {
   hipError_t e;
   if (c->coh) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    hipFree(c->coh);
+    (void)hipFree(c->coh);
     c->coh = nullptr;
     c->coh_bytes = 0;
   }
@@ -1597,8 +1590,8 @@ to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* 
   tj.out = tmp;
   hipEvent_t ea = nullptr, eb = nullptr;
   if ((e = hipEventCreate(&ea)) != hipSuccess || (e = hipEventCreate(&eb)) != hipSuccess) {
-    if (ea) hipEventDestroy(ea);
-    hipFree(tmp);
+    if (ea) (void)hipEventDestroy(ea);
+    (void)hipFree(tmp);
     return hip_fail(e, "hipEventCreate");
   }
   static const int kChunkMb[] = {32, 64, 128, 256};
@@ -1628,9 +1621,9 @@ to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* 
       }
     }
   }
-  hipEventDestroy(ea);
-  hipEventDestroy(eb);
-  hipFree(tmp);  // the timed runs were synchronized above
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  (void)hipFree(tmp);  // the timed runs were synchronized above
   if (st != TO_OK) return st;
   plan_store(dt, job->py, job->px, best);
   if (!plan_env_path().empty()) {
@@ -1687,30 +1680,35 @@ const char* to_last_error(void) { return g_last_error.c_str(); }
 
 to_status to_release(void) {
   std::lock_guard<std::mutex> lk(g_mutex);
+  // release everything even after an error; report the first one
+  hipError_t first = hipSuccess;
+  auto note = [&](hipError_t e) {
+    if (first == hipSuccess && e != hipSuccess) first = e;
+  };
   int cur = 0;
-  hipGetDevice(&cur);
+  note(hipGetDevice(&cur));
   for (size_t d = 0; d < g_ctx.size(); ++d) {
     DeviceCtx& c = g_ctx[d];
     if (!c.init) continue;
-    hipSetDevice((int)d);
-    hipDeviceSynchronize();
-    if (c.tw32) hipFree(c.tw32);
-    if (c.tw64) hipFree(c.tw64);
+    note(hipSetDevice((int)d));
+    note(hipDeviceSynchronize());
+    if (c.tw32) note(hipFree(c.tw32));
+    if (c.tw64) note(hipFree(c.tw64));
     for (int l = 0; l < kLanes; ++l) {
       Lane& ln = c.lane[l];
-      if (ln.scratch) hipFree(ln.scratch);
-      if (ln.partial) hipFree(ln.partial);
-      if (ln.tf) hipFree(ln.tf);
-      if (ln.done) hipEventDestroy(ln.done);
-      if (l > 0 && ln.stream) hipStreamDestroy(ln.stream);
+      if (ln.scratch) note(hipFree(ln.scratch));
+      if (ln.partial) note(hipFree(ln.partial));
+      if (ln.tf) note(hipFree(ln.tf));
+      if (ln.done) note(hipEventDestroy(ln.done));
+      if (l > 0 && ln.stream) note(hipStreamDestroy(ln.stream));
     }
-    if (c.fork) hipEventDestroy(c.fork);
-    if (c.plain) hipFree(c.plain);
-    if (c.coh) hipFree(c.coh);
+    if (c.fork) note(hipEventDestroy(c.fork));
+    if (c.plain) note(hipFree(c.plain));
+    if (c.coh) note(hipFree(c.coh));
     c = DeviceCtx();
   }
-  hipSetDevice(cur);
-  return TO_OK;
+  note(hipSetDevice(cur));
+  return first == hipSuccess ? TO_OK : hip_fail(first, "to_release");
 }
 
 const char* to_version(void) { return "toprop 0.1.0 gfx950"; }
@@ -1729,6 +1727,7 @@ to_status to_profile_end(void) {
   g_prof_on = false;
   g_prof_agg.clear();
   for (const ProfRec& r : g_prof_recs) {
+    if (!r.valid) continue;
     hipError_t e = hipEventSynchronize(r.b);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     float ms = 0.f;
