@@ -443,9 +443,11 @@ __global__ void __launch_bounds__(G * (L / R)) row_fwd_kernel(RowFwdArgs<T> a) {
   };
   // Software pipeline over the block's fields: the next field's loads are
   // issued before the current field's transform, so their latency overlaps
-  // the FFT passes.
+  // the FFT passes (measured faster than loading at the top of each
+  // iteration at both 8 and 16 points per thread).
+  constexpr bool kPipe = true;
   cx<T> cur[NC][RI];
-  if (f0 < f1) load_row(f0, j, y, cur);
+  if (kPipe && f0 < f1) load_row(f0, j, y, cur);
 
 #pragma unroll 1
   for (int f = f0; f < f1; ++f) {
@@ -453,14 +455,18 @@ __global__ void __launch_bounds__(G * (L / R)) row_fwd_kernel(RowFwdArgs<T> a) {
     // recomputed per field instead of being hoisted and kept live.
     int jv = j, yv = y;
     asm volatile("" : "+v"(jv), "+v"(yv));
-    cx<T> nxt[NC][RI];
-    if (f + 1 < f1) {
-      load_row(f + 1, jv, yv, nxt);
+    cx<T> nxt[NC][kPipe ? RI : 1];
+    if constexpr (kPipe) {
+      if (f + 1 < f1) {
+        load_row(f + 1, jv, yv, nxt);
+      } else {
+#pragma unroll
+        for (int m = 0; m < RI; ++m)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) nxt[c][m] = {T(0), T(0)};
+      }
     } else {
-#pragma unroll
-      for (int m = 0; m < RI; ++m)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) nxt[c][m] = {T(0), T(0)};
+      load_row(f, jv, yv, cur);
     }
     cx<T> v[NC][R];
     const cx<T> fmod = a.coh_m ? a.coh_m[a.f_off + f] : cx<T>{T(1), T(0)};
@@ -499,10 +505,12 @@ __global__ void __launch_bounds__(G * (L / R)) row_fwd_kernel(RowFwdArgs<T> a) {
         }
       }
     }
+    if constexpr (kPipe) {
 #pragma unroll
-    for (int m = 0; m < RI; ++m)
+      for (int m = 0; m < RI; ++m)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) cur[c][m] = nxt[c][m];
+        for (int c = 0; c < NC; ++c) cur[c][m] = nxt[c][m];
+    }
   }
 }
 
@@ -662,9 +670,10 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
       dst[m] = val;
     }
   };
-  // Scalar rows are software-pipelined: the next field's row is loaded
-  // while the current one is transformed.
-  constexpr bool kPipe = NC == 1;
+  // Scalar rows with 8 points per thread are software-pipelined: the next
+  // field's row is loaded while the current one is transformed (with 16 the
+  // registers are worth more as occupancy).
+  constexpr bool kPipe = NC == 1 && R <= 8;
   cx<T> pre[R];
   if (kPipe && f_begin < f_end) load_row(f_begin, j, y, 0, pre);
 
@@ -861,17 +870,27 @@ __global__ void __launch_bounds__(G * (L / R)) row_mid_kernel(RowMidArgs<T> a) {
       dst[m] = val;
     }
   };
-  cx<T> pre[R];
-  if (f_begin < f_end) load_row(f_begin, j, y, pre);
+  // With 8 points per thread the next field's row is loaded while the
+  // current one is transformed; with 16 the registers that costs are worth
+  // more as occupancy, and the row is loaded at the top of its iteration.
+  constexpr bool kPipe = R <= 8;
+  cx<T> pre[kPipe ? R : 1];
+  if constexpr (kPipe) {
+    if (f_begin < f_end) load_row(f_begin, j, y, pre);
+  }
 
 #pragma unroll 1
   for (int f = f_begin; f < f_end; ++f) {
     int jv = j, yv = y;
     asm volatile("" : "+v"(jv), "+v"(yv));
     cx<T> v[R];
+    if constexpr (kPipe) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = pre[m];
-    if (f + 1 < f_end) load_row(f + 1, jv, yv, pre);
+      for (int m = 0; m < R; ++m) v[m] = pre[m];
+      if (f + 1 < f_end) load_row(f + 1, jv, yv, pre);
+    } else {
+      load_row(f, jv, yv, v);
+    }
     fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
     cx<T>* out_f = a.out + (int64_t)f * a.out_stride;
 #pragma unroll
