@@ -467,7 +467,6 @@ struct Geometry {
   int64_t s_stride;       // scratch elements per (field group, component)
   int64_t chunk;          // field groups per chunk
   int rows_per_block;     // rows handled by one row-pass workgroup
-  int rows_per_block_bwd; // the same for the backward epilogue passes
   int col_variant;        // column-pass configuration (see ColCfg)
 };
 
@@ -507,7 +506,6 @@ to_status make_geometry(const to_job& j, bool jones, Geometry* g) {
     return fail(TO_E_UNSUPPORTED, "no column configuration for %dx%d", g->ly, g->lx);
   g->tc_shift = ilog2i(g->tm);
   g->rows_per_block = row_rows_per_block(g->lx, sizeof(T) == 8, jones);
-  g->rows_per_block_bwd = row_rows_per_block(g->lx, sizeof(T) == 8, true);
   // Pruned first/last passes when the field fills at most half of the
   // padded extent along that axis.
   g->half_x = 2 * j.nx <= g->lx;
@@ -879,7 +877,7 @@ int mid_bwd_fields_per_block(int row_blocks, int nf) {
 // type T when there is more than one group.
 template <typename T>
 size_t chain_bwd_partial_count(const to_job& j, const Geometry& g) {
-  const int row_blocks = (j.ny + g.rows_per_block_bwd - 1) / g.rows_per_block_bwd;
+  const int row_blocks = (j.ny + g.rows_per_block - 1) / g.rows_per_block;
   const int nf = (int)g.chunk;
   const int fpb = mid_bwd_fields_per_block(row_blocks, nf);
   const int groups = (nf + fpb - 1) / fpb;
@@ -898,7 +896,7 @@ to_status run_backward_chain(const to_job* jobs, const to_grad* grads, int n, De
   st = ensure_scratch(ln, (size_t)g.s_stride * g.chunk * sizeof(cx<T>));
   if (st != TO_OK) return st;
   if ((st = ensure_partial(ln, chain_bwd_partial_count<T>(j0, g))) != TO_OK) return st;
-  const int row_blocks = (j0.ny + g.rows_per_block_bwd - 1) / g.rows_per_block_bwd;
+  const int row_blocks = (j0.ny + g.rows_per_block - 1) / g.rows_per_block;
   cx<T>* scratch = (cx<T>*)ln->scratch;
   TransferParams h[kMaxChain];
   hipError_t e;

@@ -967,16 +967,13 @@ __global__ void __launch_bounds__(G * (L / R)) row_mid_bwd_kernel(RowMidBwdArgs<
 
   T gphase[RO];
   cx<T> modr[RO];
-  double dpsi[RO];
 #pragma unroll
   for (int m = 0; m < RO; ++m) {
     gphase[m] = T(0);
     modr[m] = {T(1), T(0)};
-    dpsi[m] = 0.0;
     const int x = j + m * TT;
     if (rowok && x < nx) {
       if (fl & (EL_PHASE | EL_COMPLEX | EL_LENS)) modr[m] = scalar_modulation(a.el, ny, nx, y, x);
-      if (fl & EL_LENS) dpsi[m] = lens_dphase_df(a.el, ny, nx, y, x, a.lens_f);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -993,28 +990,40 @@ __global__ void __launch_bounds__(G * (L / R)) row_mid_bwd_kernel(RowMidBwdArgs<
   };
   const int f_begin = (int)blockIdx.y * a.fpb;
   const int f_end = min(f_begin + a.fpb, a.nfields);
-  cx<T> pre[R];
-  if (f_begin < f_end) load_row(f_begin, j, y, pre);
+  constexpr bool kPipe = R <= 8;
+  cx<T> pre[kPipe ? R : 1];
+  if constexpr (kPipe) {
+    if (f_begin < f_end) load_row(f_begin, j, y, pre);
+  }
 
 #pragma unroll 1
   for (int f = f_begin; f < f_end; ++f) {
     int jv = j, yv = y;
     asm volatile("" : "+v"(jv), "+v"(yv));
     cx<T> v[R];
+    if constexpr (kPipe) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = pre[m];
-    if (f + 1 < f_end) load_row(f + 1, jv, yv, pre);
-    // the layer input of this field's row, loaded before the transform so
-    // its latency overlaps it
+      for (int m = 0; m < R; ++m) v[m] = pre[m];
+      if (f + 1 < f_end) load_row(f + 1, jv, yv, pre);
+    } else {
+      load_row(f, jv, yv, v);
+    }
+    // the layer input of this field's row; with 8 points per thread it is
+    // loaded before the transform so its latency overlaps it, with 16 after
+    // it (registers)
     const int64_t fbase = (int64_t)f * a.stride;
     cx<T> uin[RO];
+    auto load_in = [&]() {
 #pragma unroll
-    for (int m = 0; m < RO; ++m) {
-      const int x = jv + m * TT;
-      uin[m] = {T(0), T(0)};
-      if (want_param && rowok && x < nx) uin[m] = a.saved_in[fbase + (uint32_t)(yv * nx + x)];
-    }
+      for (int m = 0; m < RO; ++m) {
+        const int x = jv + m * TT;
+        uin[m] = {T(0), T(0)};
+        if (want_param && rowok && x < nx) uin[m] = a.saved_in[fbase + (uint32_t)(yv * nx + x)];
+      }
+    };
+    if constexpr (kPipe) load_in();
     fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
+    if constexpr (!kPipe) load_in();
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int x = jv + m * TT;
@@ -1026,7 +1035,8 @@ __global__ void __launch_bounds__(G * (L / R)) row_mid_bwd_kernel(RowMidBwdArgs<
           const cx<T> um = cmul(mod, uin[m]);
           const T im = v[m].y * um.x - v[m].x * um.y;  // Im(g conj(M u))
           if (fl & EL_PHASE) gphase[m] += im;
-          if (fl & EL_LENS) lens_acc += (double)im * dpsi[m];
+          // d(lens phase)/df, formed where needed (lens layers are rare)
+          if (fl & EL_LENS) lens_acc += (double)im * lens_dphase_df(a.el, ny, nx, yv, x, a.lens_f);
         }
         v[m] = cmulc(v[m], mod);  // g_l = conj(M) g_mod
         if (a.grad_in) a.grad_in[fbase + pix] = v[m];

@@ -12,8 +12,8 @@ constexpr int kMinLen = 8;
 constexpr int kMaxLen = 8192;
 
 // Row passes: R points per thread, G rows per workgroup.  Heavy kernels
-// (backward epilogues, three coupled components) keep R = 8 at length 2048,
-// where R = 16 would cost them occupancy; so does complex128.
+// (the backward row_inv epilogue, three coupled components) keep R = 8 at
+// length 2048, where R = 16 would cost them occupancy; so does complex128.
 template <typename T, int L, bool Heavy = false>
 struct RowCfg {
   static constexpr int R =

@@ -94,7 +94,7 @@ hipError_t Launch<T>::row_mid_bwd(int lx, bool half, int ny, int nblocks_y, cons
                                   hipStream_t s) {
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    using C = RowCfg<T, L, true>;
+    using C = RowCfg<T, L>;
     dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
     dim3 block(C::threads);
     if (half)
