@@ -949,8 +949,12 @@ struct RowMidBwdArgs {
   const cx<T>* tw;
 };
 
+// Four waves per SIMD are requested for the half-padded case (a few
+// spilled dwords are cheaper than a fourth of the occupancy); the unpadded
+// case, with more live registers, is left to the compiler.
 template <typename T, int L, int R, int G, bool HALF>
-__global__ void __launch_bounds__(G * (L / R)) row_mid_bwd_kernel(RowMidBwdArgs<T> a) {
+__global__ void __launch_bounds__(G * (L / R)) __attribute__((amdgpu_waves_per_eu(HALF ? 4 : 1, 8)))
+    row_mid_bwd_kernel(RowMidBwdArgs<T> a) {
   constexpr int TT = L / R;
   constexpr int NT = G * TT;
   constexpr int RO = HALF ? R / 2 : R;
