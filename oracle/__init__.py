@@ -37,6 +37,7 @@ _SRC_PATH = os.path.join(_HERE, "oracle.c")
 
 ASM = 0
 FRESNEL = 1
+DI = 2
 
 
 def build(force: bool = False) -> str:
@@ -71,6 +72,8 @@ def _load():
         lib.orc_fft2.restype = c_i
         lib.orc_transfer.argtypes = [c_p, c_l, c_l, c_d, c_d, c_d, c_d, c_i]
         lib.orc_transfer.restype = None
+        lib.orc_di_transfer.argtypes = [c_p, c_l, c_l, c_l, c_l, c_d, c_d, c_d, c_d]
+        lib.orc_di_transfer.restype = c_i
         lib.orc_propagate.argtypes = [c_p, c_p, c_l, c_l, c_l, c_l, c_l, c_d, c_d, c_d, c_d, c_i, c_i]
         lib.orc_propagate.restype = c_i
         lib.orc_propagate_offset.argtypes = [c_p, c_p, c_l, c_l, c_l, c_l, c_l, c_l, c_d, c_d, c_d, c_d, c_i]
@@ -162,6 +165,42 @@ def transfer(py: int, px: int, dy: float, dx: float, wavelength: float, z: float
     return H
 
 
+def di_transfer(ny: int, nx: int, py: int, px: int, dy: float, dx: float, wavelength: float,
+                z: float) -> np.ndarray:
+    """Transfer function of the direct-integration (DI) method for an
+    ``ny x nx`` field on the ``py x px`` padded grid, FFT order: the DFT of
+    the impulse response of Eq. (impulse_response) sampled at every lateral
+    offset two samples of the field can have (zero elsewhere), times the area
+    element ``dx dy`` of the Riemann sum of Eq. (field_propagation).  Needs
+    ``py >= 2 ny - 1`` and ``px >= 2 nx - 1`` (linear, not circular,
+    convolution on the kept window).
+
+    Pinned through :func:`propagate` with ``method=DI`` against the
+    brute-force sum :func:`rs_direct`."""
+    H = np.empty((py, px), dtype=np.complex128)
+    if _load().orc_di_transfer(_ptr(H), ny, nx, py, px, dy, dx, wavelength, z) != 0:
+        raise ValueError("DI needs power-of-two padded extents with py >= 2 ny - 1, px >= 2 nx - 1")
+    return H
+
+
+def critical_distance(ny: int, nx: int, dy: float, dx: float, wavelength: float) -> float:
+    """Critical distance of Eq. (sampling_condition), ``L dx / lambda`` with
+    L the aperture length (the field's extent, n d).  The paper states it for
+    one axis; for unequal axes this oracle takes the smaller of the two
+    axes' values, so the AS method is chosen only where both axes favour it."""
+    return min(ny * dy * dy, nx * dx * dx) / wavelength
+
+
+def resolve_method(ny: int, nx: int, dy: float, dx: float, wavelength: float, z: float) -> int:
+    """The method the automatic choice of section "Computational Fourier
+    optics" selects: AS below the critical distance, DI at or beyond it.
+    Distances <= 0 (identity and back-propagation) always take AS, whose
+    transfer function at -z is the exact adjoint."""
+    if z > 0 and z >= critical_distance(ny, nx, dy, dx, wavelength):
+        return DI
+    return ASM
+
+
 def padded_shape(ny: int, nx: int, pad: int = 2, padded=None):
     """Padded grid: ``padded`` = (py, px) if given, else (pad*ny, pad*nx)."""
     if padded is not None:
@@ -178,10 +217,15 @@ def propagate(u, dy: float, dx: float, wavelength: float, z: float, method: int 
     (py, px)); with ``adjoint`` the transfer function is conjugated, which
     gives the Hermitian adjoint of the operator.
 
+    With ``method=DI`` the transfer function is :func:`di_transfer` (the
+    padding must then reach 2 n - 1 per axis): the result is the discrete
+    Rayleigh-Sommerfeld sum of Eq. (field_propagation).
+
     Pinned by: explicit circular convolution, plane-wave eigenfunction, z=0
     identity, adjoint identity, Parseval, pad-placement invariance, group
     law, Gaussian-beam closed form, lens f-f Fourier identity, Dirichlet
-    aperture pattern, Rayleigh-Sommerfeld convergence."""
+    aperture pattern, Rayleigh-Sommerfeld convergence; DI: equality with the
+    brute-force sum :func:`rs_direct`, invariance under extra padding."""
     u = _c128(u)
     shape = u.shape
     ny, nx = shape[-2:]
@@ -208,7 +252,11 @@ def propagate_offset(u, dy, dx, wavelength, z, method, pad, oy, ox) -> np.ndarra
 
 def rs_direct(u, dy: float, dx: float, wavelength: float, z: float) -> np.ndarray:
     """Brute-force Rayleigh-Sommerfeld sum, Eq. (field_propagation) with the
-    impulse response of Eq. (impulse_response); O(N^4), tiny grids only."""
+    impulse response of Eq. (impulse_response); O(N^4), tiny grids only.
+
+    Pinned by a single-pixel input, whose output is the sampled impulse
+    response: checked against -(1/2 pi) d/dz (exp(i k d) / d), the z
+    derivative of the free-space Green's function, by finite differences."""
     u = _c128(u)
     ny, nx = u.shape
     out = np.empty_like(u)

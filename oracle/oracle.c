@@ -12,6 +12,10 @@
  *     with the transfer function of Eq. (transfer_function), evaluated on a
  *     zero-padded grid with the discrete Fourier transform;
  *   - the Fresnel transfer-function variant of the same pipeline;
+ *   - the direct-integration (DI) method: Eq. (field_propagation) as a
+ *     discrete linear convolution with the sampled impulse response of
+ *     Eq. (impulse_response), computed with the same zero-padded DFT
+ *     pipeline (the transfer function is the DFT of the sampled response);
  *   - the adjoint of that linear operator;
  *   - a brute-force Rayleigh-Sommerfeld sum of Eq. (field_propagation) with
  *     the impulse response of Eq. (impulse_response), used as a physics
@@ -35,6 +39,7 @@ typedef double _Complex cplx;
 
 #define ORC_ASM 0
 #define ORC_FRESNEL 1
+#define ORC_DI 2
 
 static const long double TWO_PI_L = 6.283185307179586476925286766559005768L;
 
@@ -174,6 +179,59 @@ void orc_transfer(cplx *H, long py, long px, double dy, double dx, double lam, d
     }
 }
 
+/* Impulse response of Eq. (impulse_response) at lateral offset (ox, oy):
+ *   h = z / (i lambda d) * (1 + i / (k d)) * exp(i k d) / d,
+ *   d = sqrt(ox^2 + oy^2 + z^2),  k = 2 pi / lambda,
+ * with the phase k d carried as d / lambda cycles in long double. */
+static cplx impulse_response(long double oy, long double ox, double lam, double z)
+{
+    long double L = (long double)lam, Z = (long double)z;
+    long double d = sqrtl(ox * ox + oy * oy + Z * Z);
+    long double kd = TWO_PI_L * d / L;
+    cplx pre = (double)(Z / (L * d * d)) / I;
+    cplx corr = 1.0 + I * (double)(1.0L / kd);
+    return pre * corr * cis_cycles(d / L);
+}
+
+/* Transfer function of the DI method on a py x px grid (FFT order): the
+ * forward DFT of the impulse response sampled at the lateral offsets the
+ * discrete convolution of an ny x nx field with itself can produce, times
+ * the area element dx dy of the Riemann sum of Eq. (field_propagation).
+ * Entry (ky, kx) of the sampled response holds the offset (sy dy, sx dx)
+ * with sy = ky (ky < py/2) or ky - py (signed, as the circular index of a
+ * difference of two positions); offsets with |sy| >= ny or |sx| >= nx can
+ * never occur between two samples of the field and are zero.  With
+ * py >= 2 ny - 1 and px >= 2 nx - 1 the circular convolution of the
+ * zero-padded field with this array equals the linear one on the kept
+ * window.  Returns -1 when the padding is too small for that. */
+int orc_di_transfer(cplx *H, long ny, long nx, long py, long px, double dy, double dx, double lam,
+                    double z)
+{
+    if (py < 2 * ny - 1 || px < 2 * nx - 1 || !is_pow2(py) || !is_pow2(px)) return -1;
+    for (long ky = 0; ky < py; ++ky) {
+        long sy = (ky < py / 2) ? ky : ky - py;
+        for (long kx = 0; kx < px; ++kx) {
+            long sx = (kx < px / 2) ? kx : kx - px;
+            if (labs(sy) >= ny || labs(sx) >= nx) {
+                H[ky * px + kx] = 0.0;
+                continue;
+            }
+            H[ky * px + kx] = impulse_response((long double)sy * dy, (long double)sx * dx, lam, z) * dx * dy;
+        }
+    }
+    return orc_fft2(H, py, px, -1);
+}
+
+/* Transfer function of `method` for an ny x nx field on a py x px grid. */
+static int method_transfer(cplx *H, long ny, long nx, long py, long px, double dy, double dx,
+                           double lam, double z, int method)
+{
+    if (method == ORC_DI) return orc_di_transfer(H, ny, nx, py, px, dy, dx, lam, z);
+    if (method != ORC_ASM && method != ORC_FRESNEL) return -1;
+    orc_transfer(H, py, px, dy, dx, lam, z, method);
+    return 0;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Propagation                                                             */
 /* ---------------------------------------------------------------------- */
@@ -189,7 +247,8 @@ void orc_transfer(cplx *H, long py, long px, double dy, double dx, double lam, d
  *      unitary up to the 1/(py*px) factor);
  *   4. inverse 2-D DFT scaled by 1/(py*px);
  *   5. crop the same window.
- * H is passed in (from orc_transfer) so a batch shares one table. */
+ * H is passed in (from orc_transfer or orc_di_transfer) so a batch shares
+ * one table. */
 static void propagate_one(const cplx *in, cplx *out, cplx *work, const cplx *H, long ny,
                           long nx, long py, long px, int adjoint)
 {
@@ -214,7 +273,10 @@ int orc_propagate(const cplx *in, cplx *out, long batch, long ny, long nx, long 
     if (ny < 1 || nx < 1 || py < ny || px < nx) return -1;
     if (!is_pow2(py) || !is_pow2(px)) return -1;
     cplx *H = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
-    orc_transfer(H, py, px, dy, dx, lam, z, method);
+    if (method_transfer(H, ny, nx, py, px, dy, dx, lam, z, method) != 0) {
+        free(H);
+        return -1;
+    }
 #pragma omp parallel
     {
         cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
@@ -237,7 +299,11 @@ int orc_propagate_offset(const cplx *in, cplx *out, long ny, long nx, long py, l
         return -1;
     cplx *H = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
     cplx *work = (cplx *)calloc((size_t)(py * px), sizeof(cplx));
-    orc_transfer(H, py, px, dy, dx, lam, z, method);
+    if (method_transfer(H, ny, nx, py, px, dy, dx, lam, z, method) != 0) {
+        free(work);
+        free(H);
+        return -1;
+    }
     for (long r = 0; r < ny; ++r)
         memcpy(work + (r + oy) * px + ox, in + r * nx, sizeof(cplx) * (size_t)nx);
     orc_fft2(work, py, px, -1);

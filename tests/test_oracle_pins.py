@@ -13,6 +13,11 @@ a wrong frequency ordering or window) fails at least one of them:
 * Physics: Gaussian-beam q-parameter closed form, the exact discrete lens
   Fourier-transform identity, the Dirichlet (discrete sinc) pattern of a
   square aperture, brute-force Rayleigh-Sommerfeld integration.
+* Direct integration: the brute-force sum's impulse response against the z
+  derivative of the free-space Green's function; the FFT form of the DI
+  method against the brute-force sum (forward and adjoint, ragged and
+  non-square grids), invariance under extra padding, the critical distance
+  as the Nyquist limit of the Fresnel chirp.
 * Polarization: the powers printed in the paper's polarizer listing, Malus's
   law, a quarter-wave plate plus polarizer.
 * Coherence: reductions to the field propagator.
@@ -298,6 +303,121 @@ def test_rayleigh_sommerfeld_brute_force_converges():
         errs.append(rel(a, r))
     assert errs[0] < 3e-5
     assert errs[1] < errs[0] and errs[1] < 1e-5
+
+
+# --------------------------------------------------------------------------
+# Direct integration (DI) and the choice of method
+# --------------------------------------------------------------------------
+
+def _green(oy, ox, z, lam):
+    d = np.sqrt(oy * oy + ox * ox + z * z)
+    return np.exp(2j * np.pi * (d / lam)) / d
+
+
+@pytest.mark.parametrize("geom", [(20e-6, 1.0e-6, 2e-6, 1.5e-6), (3e-4, 0.6e-6, 4e-6, 4e-6)])
+def test_rs_impulse_response_is_green_derivative(geom):
+    """A single-pixel input returns the sampled impulse response times dx dy;
+    Eq. (impulse_response) equals -(1/2 pi) d/dz of exp(i k d)/d.  The
+    derivative is taken by a fourth-order central difference in z (an
+    independent evaluation: a dropped 1/(kd) term, a wrong sign of i or a
+    missing z/d factor each change the result by more than the bound)."""
+    z, lam, dy, dx = geom
+    ny, nx = 6, 5
+    u = np.zeros((ny, nx), complex)
+    r0, c0 = 2, 1
+    u[r0, c0] = 1.0
+    out = oracle.rs_direct(u, dy, dx, lam, z)
+    oy = (np.arange(ny)[:, None] - r0) * dy
+    ox = (np.arange(nx)[None, :] - c0) * dx
+    h = 1e-3 * lam
+    deriv = (-_green(oy, ox, z + 2 * h, lam) + 8 * _green(oy, ox, z + h, lam)
+             - 8 * _green(oy, ox, z - h, lam) + _green(oy, ox, z - 2 * h, lam)) / (12 * h)
+    expect = -deriv / (2 * np.pi) * dx * dy
+    assert rel(out, expect) < 1e-8
+    # the 1/(kd) correction is well above the bound in the first geometry
+    k = 2 * np.pi / lam
+    d = np.sqrt(oy ** 2 + ox ** 2 + z ** 2)
+    if geom[0] < 1e-4:
+        assert float(np.max(1.0 / (k * d))) > 1e-3
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 16, 16), (5, 7, 16, 16), (6, 10, 16, 32), (3, 9, 8, 32), (1, 6, 8, 16)])
+def test_di_equals_brute_force_sum(shape):
+    """DI through the zero-padded DFT equals the direct Riemann sum of
+    Eq. (field_propagation) on the same grid: the dense operator of the
+    brute-force sum, built column by column, against the FFT form applied to
+    random fields, forward and adjoint."""
+    ny, nx, py, px = shape
+    dy, dx, lam, z = 1.5e-6, 2.0e-6, 0.6e-6, 2.5e-5
+    rng = np.random.default_rng(700 + ny * nx)
+    n = ny * nx
+    A = np.empty((n, n), complex)
+    for p in range(n):
+        e = np.zeros(n, complex)
+        e[p] = 1.0
+        A[:, p] = oracle.rs_direct(e.reshape(ny, nx), dy, dx, lam, z).ravel()
+    u = crandn(rng, 3, ny, nx)
+    fwd = oracle.propagate(u, dy, dx, lam, z, oracle.DI, padded=(py, px))
+    adj = oracle.propagate(u, dy, dx, lam, z, oracle.DI, padded=(py, px), adjoint=True)
+    ur = u.reshape(3, n)
+    assert rel(fwd.reshape(3, n), ur @ A.T) < 1e-12
+    assert rel(adj.reshape(3, n), ur @ A.conj()) < 1e-12
+
+
+def test_di_invariant_under_extra_padding():
+    """Beyond 2 n - 1 samples per axis, padding adds only offsets no pair of
+    samples has: the result does not change, and the window's position in
+    the padded grid does not matter."""
+    rng = np.random.default_rng(711)
+    u = crandn(rng, 12, 20)
+    args = (3e-6, 2e-6, 0.5e-6, 4e-4, oracle.DI)
+    a = oracle.propagate(u, *args, padded=(32, 64))
+    b = oracle.propagate(u, *args, padded=(128, 64))
+    c = oracle.propagate(u, *args, padded=(32, 256))
+    assert rel(b, a) < 1e-13 and rel(c, a) < 1e-13
+    H = oracle.di_transfer(12, 20, 32, 64, 3e-6, 2e-6, 0.5e-6, 4e-4)
+    assert np.allclose(H, H[np.r_[0, 31:0:-1]][:, np.r_[0, 63:0:-1]], rtol=0, atol=1e-15 * np.abs(H).max())
+
+
+def test_di_needs_linear_convolution_padding():
+    u = np.ones((8, 8), complex)
+    with pytest.raises(ValueError):
+        oracle.propagate(u, 1e-6, 1e-6, 0.5e-6, 1e-4, oracle.DI, padded=(8, 16))
+    with pytest.raises(ValueError):
+        oracle.di_transfer(9, 8, 16, 16, 1e-6, 1e-6, 0.5e-6, 1e-4)
+    assert oracle.di_transfer(8, 8, 16, 16, 1e-6, 1e-6, 0.5e-6, 1e-4).shape == (16, 16)
+
+
+@pytest.mark.parametrize("n", [64, 250])
+def test_critical_distance_is_the_fresnel_chirp_nyquist_limit(n):
+    """Eq. (sampling_condition): at z = L dx / lambda the phase of the
+    transfer function's chirp advances by pi (N-1)/N between the last two
+    bins of the unpadded grid, i.e. it reaches the Nyquist rate; a shorter
+    distance stays below it.  Evaluated from the oracle's Fresnel transfer
+    function (power-of-two length) and from the closed-form chirp."""
+    d, lam = 8e-6, 0.7e-6
+    zc = oracle.critical_distance(n, n, d, d, lam)
+    f = (np.arange(n) - n // 2) / (n * d)
+    steps = np.abs(np.diff(-np.pi * lam * zc * f ** 2))
+    assert abs(steps.max() - np.pi * (n - 1) / n) < 1e-9
+    if n == 64:
+        H = oracle.transfer(1, n, d, d, lam, zc, oracle.FRESNEL)[0]
+        Hs = np.fft.fftshift(H)
+        ang = np.abs(np.angle(Hs[1:] / Hs[:-1]))
+        assert abs(ang.max() - np.pi * (n - 1) / n) < 1e-9
+        H2 = oracle.transfer(1, n, d, d, lam, 0.9 * zc, oracle.FRESNEL)[0]
+        Hs2 = np.fft.fftshift(H2)
+        assert np.abs(np.angle(Hs2[1:] / Hs2[:-1])).max() < 0.9 * np.pi
+
+
+def test_resolve_method():
+    zc = oracle.critical_distance(128, 256, 4e-6, 2e-6, 0.5e-6)
+    assert zc == pytest.approx(min(128 * 16e-12, 256 * 4e-12) / 0.5e-6, rel=1e-15)
+    assert oracle.resolve_method(128, 256, 4e-6, 2e-6, 0.5e-6, 0.999 * zc) == oracle.ASM
+    assert oracle.resolve_method(128, 256, 4e-6, 2e-6, 0.5e-6, zc) == oracle.DI
+    assert oracle.resolve_method(128, 256, 4e-6, 2e-6, 0.5e-6, 10 * zc) == oracle.DI
+    assert oracle.resolve_method(128, 256, 4e-6, 2e-6, 0.5e-6, 0.0) == oracle.ASM
+    assert oracle.resolve_method(128, 256, 4e-6, 2e-6, 0.5e-6, -10 * zc) == oracle.ASM
 
 
 # --------------------------------------------------------------------------
