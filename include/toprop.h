@@ -9,7 +9,10 @@
  *   - propagation by the angular-spectrum method, Eq. (field_propagation_tf)
  *     with the transfer function of Eq. (transfer_function), on a zero-padded
  *     grid ("configurable zero-padding"), or by the Fresnel transfer
- *     function (the paraxial alternative the same section mentions);
+ *     function (the paraxial alternative the same section mentions), or by
+ *     direct integration (DI) of Eq. (field_propagation) with the impulse
+ *     response of Eq. (impulse_response), and the automatic choice between
+ *     AS and DI by the critical distance of Eq. (sampling_condition);
  *   - gradients of both for gradient-based optimization (section
  *     "Gradient-based optimization");
  *   - propagation of a mutual coherence function (section "Spatial
@@ -39,7 +42,25 @@
  *               H = 0 where fx^2 + fy^2 > 1/lambda^2 (evanescent cut-off);
  *   TO_FRESNEL: H = exp(2 pi i (z/lambda - lambda z (fx^2 + fy^2) / 2)),
  *   with fx = k / (px dx), fy = k / (py dy) in FFT order (bins k >= px / 2
- *   are negative).
+ *   are negative);
+ *   TO_DI:      H = DFT of h(sy dy, sx dx) dx dy on the padded grid, h the
+ *               impulse response of Eq. (impulse_response),
+ *                 h = z / (i lambda d) (1 + i / (k d)) exp(i k d) / d,
+ *                 d = sqrt(ox^2 + oy^2 + z^2), k = 2 pi / lambda,
+ *               sampled at the signed circular offsets sy (= ky for
+ *               ky < py/2, ky - py otherwise; likewise sx) with |sy| < ny and
+ *               |sx| < nx, zero elsewhere.  The propagation is then the
+ *               discrete Riemann sum of Eq. (field_propagation) over the
+ *               field's samples (a linear convolution), which needs
+ *               py >= 2 ny - 1, px >= 2 nx - 1 (TO_E_UNSUPPORTED otherwise)
+ *               and z > 0 (TO_E_INVAL otherwise).  The table is built on the
+ *               GPU (sampling, then a forward 2-D FFT) once per call for
+ *               each distinct geometry, unless the job supplies one
+ *               (to_job.tf_table, from to_transfer_table);
+ *   TO_AUTO:    TO_DI when z >= z_crit, TO_ASM otherwise (including z <= 0),
+ *               with z_crit = min(nx dx^2, ny dy^2) / lambda: the critical
+ *               distance L dx / lambda of Eq. (sampling_condition) for the
+ *               aperture length L = n d of each axis, the smaller one taken.
  *   The phase is evaluated in FP64 and reduced modulo one cycle before the
  *   sine and cosine; c64 fields then use FP32 arithmetic.
  * Gradients.  For a real loss L of a complex array u, the gradient array is
@@ -75,7 +96,7 @@ typedef enum {
   TO_E_HIP = -4
 } to_status;
 
-typedef enum { TO_ASM = 0, TO_FRESNEL = 1 } to_method;
+typedef enum { TO_ASM = 0, TO_FRESNEL = 1, TO_DI = 2, TO_AUTO = 3 } to_method;
 typedef enum { TO_C64 = 0, TO_C128 = 1 } to_dtype;
 
 /* Element applied before the propagation (fused into its first pass).  Flags
@@ -143,6 +164,10 @@ typedef struct to_job {
   void* out;              /* complex [batch][ncomp][ny][nx]; may equal `in`      */
   void* epi_out;          /* INTENSITY: real [batch][ny][nx], accumulated        */
   const void* el_jones_map; /* TO_EL_JONES_MAP: complex [3][3][ny][nx]           */
+  const void* tf_table;   /* TO_DI (also when TO_AUTO resolves to it): NULL, or
+                             the job's transfer function as written by
+                             to_transfer_table, complex [py][px]; read only.
+                             Ignored for the other methods.                    */
 } to_job;
 
 /* Gradient buffers of one job for to_propagate_backward.                    */
@@ -274,6 +299,19 @@ const char* to_last_error(void);
 
 /* Frees the library's workspace on every device (waits for the device).     */
 to_status to_release(void);
+
+/* Transfer function of the job's propagation (after TO_AUTO is resolved):
+ * table[ky][kx] = H at padded-grid bin (ky, kx), FFT order, complex of
+ * `dtype`, py x px, caller-owned device memory.  For TO_DI this is the table
+ * a DI job may carry in tf_table, so that repeated calls with the same
+ * geometry (ny, nx, py, px, dy, dx, wavelength, z) skip its construction;
+ * it must not be written while a call that reads it is in flight.  The
+ * job's field pointers, element and epilogue are ignored.                    */
+to_status to_transfer_table(const to_job* job, to_dtype dtype, void* table, void* stream);
+
+/* The method a job runs with: job->method, or for TO_AUTO the choice by the
+ * critical distance described with the transfer functions.  Host only.      */
+to_status to_resolve_method(const to_job* job, int32_t* method);
 
 /* Library version, e.g. "toprop 0.1.0 gfx950".                              */
 const char* to_version(void);

@@ -1,6 +1,8 @@
-"""MI355X-native batched free-space propagation (angular spectrum / Fresnel
-transfer function) with fused element modulation, after the TorchOptics
-paper (Filipovich & Lvovsky, arXiv 2411.18591).
+"""MI355X-native batched free-space propagation (angular spectrum, Fresnel
+transfer function, direct integration of the Rayleigh-Sommerfeld integral,
+or the automatic choice between AS and DI by the critical distance) with
+fused element modulation, after the TorchOptics paper (Filipovich &
+Lvovsky, arXiv 2411.18591).
 
 This module is a thin PyTorch binding of the C-ABI in ``include/toprop.h``:
 it marshals tensor pointers, shapes and physical parameters into ``to_job``
@@ -27,11 +29,15 @@ __all__ = [
     "Optics", "propagate", "modulate", "propagate_backward", "coherence_propagate",
     "propagate_ad", "propagate_intensity", "propagate_jobs", "propagate_backward_jobs", "linear_polarizer", "waveplate",
     "jones3", "version", "autotune", "plan_get", "plan_set", "plan_clear", "plan_load", "plan_save",
+    "transfer_table", "resolve_method",
 ]
 
 ASM = "asm"
 FRESNEL = "fresnel"
-_METHODS = {ASM: _capi.TO_ASM, FRESNEL: _capi.TO_FRESNEL}
+DI = "di"
+AUTO = "auto"
+_METHODS = {ASM: _capi.TO_ASM, FRESNEL: _capi.TO_FRESNEL, DI: _capi.TO_DI, AUTO: _capi.TO_AUTO}
+_METHOD_NAMES = {v: k for k, v in _METHODS.items()}
 
 
 def version() -> str:
@@ -115,7 +121,9 @@ class Optics:
     """Geometry and free-space parameters of one propagation.
 
     The padded grid is ``padded`` = (py, px) if given, else each extent is
-    ``pad`` times the field rounded up to a power of two."""
+    ``pad`` times the field rounded up to a power of two.  ``method`` is
+    "asm", "fresnel", "di" (direct integration; needs pad >= 2 and z > 0) or
+    "auto" (DI at or beyond the critical distance, AS below it)."""
     dy: float
     dx: float
     wavelength: float
@@ -147,10 +155,13 @@ def _field_dims(u: torch.Tensor, ncomp: int):
 
 def make_job(u: torch.Tensor, opt: Optics, *, out: Optional[torch.Tensor] = None, ncomp: int = 1,
              phase=None, cmask=None, lens_f=None, jones=None, jones_map=None, epi: int = _capi.TO_EPI_NONE,
-             epi_ref=None, epi_scale: float = 1.0, epi_grad=None, epi_loss=None, epi_out=None):
+             epi_ref=None, epi_scale: float = 1.0, epi_grad=None, epi_loss=None, epi_out=None,
+             tf_table=None):
     """Fill a to_job record for field tensor u (and the given element /
-    epilogue tensors).  Returns the record; the caller keeps the tensors
-    alive until the stream work is done."""
+    epilogue tensors; ``tf_table``: a direct-integration table from
+    :func:`transfer_table`, reused instead of being rebuilt in the call).
+    Returns the record; the caller keeps the tensors alive until the stream
+    work is done."""
     if not u.is_contiguous():
         raise ValueError("field must be contiguous")
     _dtype_code(u)
@@ -209,7 +220,43 @@ def make_job(u: torch.Tensor, opt: Optics, *, out: Optional[torch.Tensor] = None
     if out is not None:
         _need(out, "out", u.dtype, u, tuple(u.shape))
         j.out = _ptr(out)
+    if tf_table is not None:
+        _need(tf_table, "tf_table", u.dtype, u, (j.py, j.px))
+        j.tf_table = _ptr(tf_table)
     return j
+
+
+def _geometry_job(opt: Optics, ny: int, nx: int):
+    if opt.method not in _METHODS:
+        raise ValueError(f"method must be one of {list(_METHODS)}")
+    j = _capi.Job()
+    j.ny, j.nx = int(ny), int(nx)
+    j.py, j.px = opt.padded_shape(ny, nx)
+    j.method = _METHODS[opt.method]
+    j.dy, j.dx, j.wavelength, j.z = float(opt.dy), float(opt.dx), float(opt.wavelength), float(opt.z)
+    j.y0, j.x0 = float(opt.y0), float(opt.x0)
+    j.ncomp = 1
+    return j
+
+
+def transfer_table(opt: Optics, ny: int, nx: int, dtype=torch.complex64, device=None) -> torch.Tensor:
+    """The transfer function ``[py, px]`` (FFT order) the library applies to
+    ny x nx fields under ``opt``; for direct integration, the DFT of the
+    sampled impulse response, which a job may carry (``make_job(...,
+    tf_table=...)``) so that calls with the same geometry skip building it.
+    Computed on the GPU, on the current stream."""
+    j = _geometry_job(opt, ny, nx)
+    dev = torch.device("cuda") if device is None else torch.device(device)
+    H = torch.empty((j.py, j.px), dtype=dtype, device=dev)
+    code = _dtype_code(H)
+    _capi.transfer_table(j, code, H.data_ptr(), torch.cuda.current_stream(dev).cuda_stream)
+    return H
+
+
+def resolve_method(opt: Optics, ny: int, nx: int) -> str:
+    """The method the library runs for ny x nx fields under ``opt`` ("auto"
+    resolved by the critical distance)."""
+    return _METHOD_NAMES[_capi.resolve_method(_geometry_job(opt, ny, nx))]
 
 
 # ---------------------------------------------------------------------------

@@ -20,6 +20,8 @@ TO_E_HIP = -4
 
 TO_ASM = 0
 TO_FRESNEL = 1
+TO_DI = 2
+TO_AUTO = 3
 TO_C64 = 0
 TO_C128 = 1
 
@@ -36,6 +38,8 @@ TO_EPI_INTENSITY = 3
 
 EXPORTED = (
     "to_propagate",
+    "to_transfer_table",
+    "to_resolve_method",
     "to_modulate",
     "to_propagate_backward",
     "to_coherence_propagate",
@@ -86,6 +90,7 @@ class Job(ctypes.Structure):
         ("out", ctypes.c_void_p),
         ("epi_out", ctypes.c_void_p),
         ("el_jones_map", ctypes.c_void_p),
+        ("tf_table", ctypes.c_void_p),
     ]
 
 
@@ -168,6 +173,10 @@ def lib() -> ctypes.CDLL:
         L.to_plan_load.restype = c_int
         L.to_plan_save.argtypes = [ctypes.c_char_p]
         L.to_plan_save.restype = c_int
+        L.to_transfer_table.argtypes = [JP, c_int, ctypes.c_void_p, ctypes.c_void_p]
+        L.to_transfer_table.restype = c_int
+        L.to_resolve_method.argtypes = [JP, ctypes.POINTER(c_int)]
+        L.to_resolve_method.restype = c_int
         _lib = L
     return _lib
 
@@ -212,6 +221,16 @@ def autotune(job, dtype: int, stream: int) -> dict:
     p = Plan()
     check(lib().to_autotune(ctypes.byref(job), dtype, ctypes.c_void_p(stream), ctypes.byref(p)))
     return {"col_variant": p.col_variant, "chunk_mb": p.chunk_mb, "us": p.us}
+
+
+def transfer_table(job, dtype: int, table: int, stream: int) -> None:
+    check(lib().to_transfer_table(ctypes.byref(job), dtype, ctypes.c_void_p(table), ctypes.c_void_p(stream)))
+
+
+def resolve_method(job) -> int:
+    m = ctypes.c_int32()
+    check(lib().to_resolve_method(ctypes.byref(job), ctypes.byref(m)))
+    return m.value
 
 
 def plan_get(py: int, px: int, dtype: int):

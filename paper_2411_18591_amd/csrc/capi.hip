@@ -17,6 +17,7 @@
 #include "launch.hpp"
 #include "plain.hpp"
 #include "plan.hpp"
+#include "transfer.hpp"
 
 using namespace toprop;
 
@@ -97,6 +98,8 @@ struct DeviceCtx {
   size_t plain_bytes = 0;
   void* coh = nullptr;    // workspace of the coherence propagation
   size_t coh_bytes = 0;
+  void* di = nullptr;     // direct-integration tables built within a call
+  size_t di_bytes = 0;
 };
 
 std::mutex g_mutex;
@@ -171,6 +174,21 @@ to_status ensure_plain(DeviceCtx* c, size_t bytes) {
   if ((e = hipMalloc(&c->plain, bytes)) != hipSuccess)
     return fail(TO_E_NOMEM, "workspace allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
   c->plain_bytes = bytes;
+  return TO_OK;
+}
+
+to_status ensure_di(DeviceCtx* c, size_t bytes) {
+  if (c->di_bytes >= bytes) return TO_OK;
+  hipError_t e;
+  if (c->di) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    (void)hipFree(c->di);
+    c->di = nullptr;
+    c->di_bytes = 0;
+  }
+  if ((e = hipMalloc(&c->di, bytes)) != hipSuccess)
+    return fail(TO_E_NOMEM, "direct-integration table of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  c->di_bytes = bytes;
   return TO_OK;
 }
 
@@ -300,6 +318,20 @@ hipError_t timed(const char* name, int L, bool dbl, hipStream_t s, F&& f) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Critical distance of Eq. (sampling_condition), L dx / lambda with the
+// aperture length L = n d of each axis; the smaller axis value is taken, so
+// the automatic choice keeps the AS method only where both axes favour it.
+double critical_distance(const to_job& j) {
+  return std::min((double)j.ny * j.dy * j.dy, (double)j.nx * j.dx * j.dx) / j.wavelength;
+}
+
+// The method a job runs with (TO_AUTO resolved: DI at or beyond the critical
+// distance, AS below it and for z <= 0, where AS at -z is the exact adjoint).
+int resolved_method(const to_job& j) {
+  if (j.method != TO_AUTO) return j.method;
+  return (j.z > 0.0 && j.z >= critical_distance(j)) ? TO_DI : TO_ASM;
+}
+
 // Host-side validation of one job.  `what` selects which pointers matter.
 enum Mode { MODE_FWD, MODE_BWD, MODE_MOD, MODE_COH };
 
@@ -316,13 +348,22 @@ to_status validate(const to_job& j, int idx, to_dtype dt, Mode mode) {
       return fail(TO_E_UNSUPPORTED,
                   "job %d: padded grid %lldx%lld must be powers of two in [%d, %d]", idx,
                   (long long)ly, (long long)lx, kMinLen, kMaxLen);
-    if (j.method != TO_ASM && j.method != TO_FRESNEL)
+    if (j.method != TO_ASM && j.method != TO_FRESNEL && j.method != TO_DI && j.method != TO_AUTO)
       return fail(TO_E_INVAL, "job %d: unknown method %d", idx, j.method);
     if (!std::isfinite(j.z)) return fail(TO_E_INVAL, "job %d: z is not finite", idx);
   }
   if (!finite_pos(j.dy) || !finite_pos(j.dx))
     return fail(TO_E_INVAL, "job %d: spacing must be finite and > 0", idx);
   if (!finite_pos(j.wavelength)) return fail(TO_E_INVAL, "job %d: wavelength must be finite and > 0", idx);
+  if (mode != MODE_MOD && resolved_method(j) == TO_DI) {
+    if (!(j.z > 0.0))
+      return fail(TO_E_INVAL, "job %d: direct integration needs z > 0 (got %g)", idx, j.z);
+    if ((int64_t)j.py < 2 * (int64_t)j.ny - 1 || (int64_t)j.px < 2 * (int64_t)j.nx - 1)
+      return fail(TO_E_UNSUPPORTED,
+                  "job %d: direct integration needs a padded grid of at least 2n-1 per axis (field %dx%d, "
+                  "padded %dx%d)",
+                  idx, j.ny, j.nx, j.py, j.px);
+  }
   if (!std::isfinite(j.y0) || !std::isfinite(j.x0)) return fail(TO_E_INVAL, "job %d: offset not finite", idx);
   if (j.batch < 0) return fail(TO_E_INVAL, "job %d: batch %lld < 0", idx, (long long)j.batch);
   if (j.ncomp != 1 && j.ncomp != 3) return fail(TO_E_INVAL, "job %d: ncomp must be 1 or 3", idx);
@@ -363,7 +404,9 @@ to_status validate(const to_job& j, int idx, to_dtype dt, Mode mode) {
 
 TransferParams make_transfer(const to_job& j, bool conj) {
   TransferParams p;
-  p.method = j.method;
+  const int m = resolved_method(j);
+  p.method = m == TO_DI ? 2 : m;
+  p.table = m == TO_DI ? j.tf_table : nullptr;
   p.conj = conj ? 1 : 0;
   const double lam = j.wavelength, z = j.z;
   p.lam2 = lam * lam;
@@ -401,8 +444,8 @@ constexpr double kFastRemainderCycles = 1.0;
 
 template <typename T>
 hipError_t prepare_transfer(const to_job& j, Lane* c, hipStream_t s, TransferParams* h, int slot = 0) {
-  if (sizeof(T) != 4) return hipSuccess;
-  if (j.method == TO_ASM && !(asm_remainder_cycles(j) <= kFastRemainderCycles)) return hipSuccess;
+  if (sizeof(T) != 4 || h->table) return hipSuccess;
+  if (h->method == TO_ASM && !(asm_remainder_cycles(j) <= kFastRemainderCycles)) return hipSuccess;
   cx<float>* ex = (cx<float>*)((char*)c->tf + (size_t)slot * kTableSlotBytes);
   cx<float>* ey = ex + kMaxLen;
   float* sx = (float*)(ey + kMaxLen);
@@ -546,6 +589,7 @@ void element_spans(const to_job& j, to_dtype dt, std::vector<Span>* rd) {
   if (j.el_flags & TO_EL_COMPLEX) rd->push_back(span(j.el_complex, px * 2 * re));
   if (j.el_flags & TO_EL_JONES_MAP) rd->push_back(span(j.el_jones_map, 9 * px * 2 * re));
   if (has_loss(j)) rd->push_back(span(j.epi_ref, px * re));
+  if (resolved_method(j) == TO_DI && j.tf_table) rd->push_back(span(j.tf_table, (size_t)j.py * j.px * 2 * re));
 }
 
 // Argument records of the three passes for one chunk of `nf` fields.
@@ -1205,6 +1249,10 @@ to_status plain_setup(const to_job& j, DeviceCtx* c, bool conj, hipStream_t s, P
   w->tmp2 = w->tmp + nf;
   w->partial = (double*)(w->tmp2 + nf);
   TransferParams h = make_transfer(j, conj);
+  if (h.table) {  // direct integration: the call's (or the caller's) table
+    w->H = (cx<T>*)h.table;
+    return TO_OK;
+  }
   h.conj = 0;  // the table holds H; the multiply kernel conjugates
   hipError_t e = timed("plain.table", j.px, sizeof(T) == 8, s,
                        [&] { return Plain<T>::table(w->H, j.py, j.px, h, s); });
@@ -1325,6 +1373,78 @@ to_status time_candidate(const to_job& j, DeviceCtx* c, hipStream_t s, const Pla
   return TO_OK;
 }
 
+// frac(z / lambda), exact: see make_transfer.
+double exact_cycles_frac(double z, double lam) {
+  const double qh = z / lam;
+  const double r = std::fma(-qh, lam, z);
+  return (qh - std::floor(qh)) + r / lam;
+}
+
+DiParams di_params(const to_job& j) {
+  DiParams p;
+  p.ny = j.ny;
+  p.nx = j.nx;
+  p.py = j.py;
+  p.px = j.px;
+  p.dy = j.dy;
+  p.dx = j.dx;
+  p.z = j.z;
+  p.lam = j.wavelength;
+  p.q_frac = exact_cycles_frac(j.z, j.wavelength);
+  return p;
+}
+
+bool same_di_geometry(const to_job& a, const to_job& b) {
+  return a.ny == b.ny && a.nx == b.nx && a.py == b.py && a.px == b.px && a.dy == b.dy && a.dx == b.dx &&
+         a.wavelength == b.wavelength && a.z == b.z;
+}
+
+// Copies the (validated) jobs of a call with TO_AUTO resolved, and gives every
+// direct-integration job that carries no table of its own one built on `s`
+// before any other work of the call (one table per distinct geometry, in the
+// device's DI area; every lane forks from `s` after it, and the area is only
+// rebuilt by a later call, which `s` orders after this one).
+template <typename T>
+to_status prepare_jobs(const to_job* jobs, int n, DeviceCtx* c, hipStream_t s, std::vector<to_job>* out) {
+  out->assign(jobs, jobs + n);
+  std::vector<int> first;       // index of the job whose geometry each table has
+  std::vector<size_t> offset;   // byte offset of each table in the DI area
+  std::vector<int> table_of(n, -1);
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    to_job& j = (*out)[i];
+    j.method = resolved_method(j);
+    if (j.method != TO_DI || j.tf_table || j.batch == 0) continue;
+    int k = 0;
+    while (k < (int)first.size() && !same_di_geometry((*out)[first[k]], j)) ++k;
+    if (k == (int)first.size()) {
+      first.push_back(i);
+      offset.push_back(total);
+      total += ((size_t)j.py * j.px * sizeof(cx<T>) + 255) & ~(size_t)255;
+    }
+    table_of[i] = k;
+  }
+  if (first.empty()) return TO_OK;
+  to_status st = ensure_di(c, total);
+  if (st != TO_OK) return st;
+  for (size_t k = 0; k < first.size(); ++k) {
+    const to_job& j = (*out)[first[k]];
+    cx<T>* H = (cx<T>*)((char*)c->di + offset[k]);
+    hipError_t e = timed("di_table", j.px, sizeof(T) == 8, s, [&] {
+      return TransferTable<T>::direct_integration(H, di_params(j), twiddles<T>(c, j.px), twiddles<T>(c, j.py), s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "direct-integration table");
+  }
+  for (int i = 0; i < n; ++i)
+    if (table_of[i] >= 0) (*out)[i].tf_table = (char*)c->di + offset[table_of[i]];
+  return TO_OK;
+}
+
+to_status prepare_jobs_dt(const to_job* jobs, int n, to_dtype dt, DeviceCtx* c, hipStream_t s,
+                          std::vector<to_job>* out) {
+  return dt == TO_C64 ? prepare_jobs<float>(jobs, n, c, s, out) : prepare_jobs<double>(jobs, n, c, s, out);
+}
+
 to_status plan_args(int32_t py, int32_t px, to_dtype dtype) {
   if (dtype != TO_C64 && dtype != TO_C128) return fail(TO_E_INVAL, "dtype must be TO_C64 or TO_C128");
   (void)py;
@@ -1348,6 +1468,9 @@ to_status to_propagate_plain(const to_job* jobs, int32_t njobs, to_dtype dtype, 
   to_status st = get_ctx(&c);
   if (st != TO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  std::vector<to_job> prepared;
+  if ((st = prepare_jobs_dt(jobs, njobs, dtype, c, s, &prepared)) != TO_OK) return st;
+  jobs = prepared.data();
   for (int i = 0; i < njobs; ++i) {
     st = dtype == TO_C64 ? run_forward_plain<float>(jobs[i], c, s) : run_forward_plain<double>(jobs[i], c, s);
     if (st != TO_OK) return st;
@@ -1371,6 +1494,9 @@ to_status to_propagate_backward_plain(const to_job* jobs, const to_grad* grads, 
   to_status st = get_ctx(&c);
   if (st != TO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  std::vector<to_job> prepared;
+  if ((st = prepare_jobs_dt(jobs, njobs, dtype, c, s, &prepared)) != TO_OK) return st;
+  jobs = prepared.data();
   for (int i = 0; i < njobs; ++i) {
     st = dtype == TO_C64 ? run_backward_plain<float>(jobs[i], grads[i], c, s)
                          : run_backward_plain<double>(jobs[i], grads[i], c, s);
@@ -1391,6 +1517,9 @@ to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* 
   to_status st = get_ctx(&c);
   if (st != TO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  std::vector<to_job> prepared;
+  if ((st = prepare_jobs_dt(jobs, njobs, dtype, c, s, &prepared)) != TO_OK) return st;
+  jobs = prepared.data();
   // scheduling units: single jobs and chains of layers
   std::vector<int> ubeg, ulen;
   for (int i = 0; i < njobs;) {
@@ -1479,6 +1608,9 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
   to_status st = get_ctx(&c);
   if (st != TO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  std::vector<to_job> prepared;
+  if ((st = prepare_jobs_dt(jobs, njobs, dtype, c, s, &prepared)) != TO_OK) return st;
+  jobs = prepared.data();
   std::vector<int> ubeg, ulen;
   for (int i = 0; i < njobs;) {
     const int len = backward_chain_len(jobs, grads, njobs, i, dtype);
@@ -1561,8 +1693,10 @@ to_status to_coherence_propagate(const to_job* job, to_dtype dtype, int32_t adjo
   DeviceCtx* c;
   if ((st = get_ctx(&c)) != TO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  return dtype == TO_C64 ? run_coherence<float>(j, adjoint, grad, c, s)
-                         : run_coherence<double>(j, adjoint, grad, c, s);
+  std::vector<to_job> prepared;
+  if ((st = prepare_jobs_dt(job, 1, dtype, c, s, &prepared)) != TO_OK) return st;
+  return dtype == TO_C64 ? run_coherence<float>(prepared[0], adjoint, grad, c, s)
+                         : run_coherence<double>(prepared[0], adjoint, grad, c, s);
 }
 
 to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* result) {
@@ -1576,7 +1710,9 @@ to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* 
   const int dt = dtype == TO_C64 ? 0 : 1;
   // tuning copy: no epilogue, output into a temporary buffer (the job may be
   // in place, and every candidate runs it several times)
-  to_job tj = *job;
+  std::vector<to_job> prepared;
+  if ((st = prepare_jobs_dt(job, 1, dtype, c, s, &prepared)) != TO_OK) return st;
+  to_job tj = prepared[0];
   tj.epi = TO_EPI_NONE;
   tj.epi_grad = nullptr;
   tj.epi_loss = nullptr;
@@ -1703,10 +1839,51 @@ to_status to_release(void) {
     if (c.fork) note(hipEventDestroy(c.fork));
     if (c.plain) note(hipFree(c.plain));
     if (c.coh) note(hipFree(c.coh));
+    if (c.di) note(hipFree(c.di));
     c = DeviceCtx();
   }
   note(hipSetDevice(cur));
   return first == hipSuccess ? TO_OK : hip_fail(first, "to_release");
+}
+
+to_status to_transfer_table(const to_job* job, to_dtype dtype, void* table, void* stream) {
+  if (!job) return fail(TO_E_INVAL, "job is NULL");
+  if (!table) return fail(TO_E_INVAL, "table is NULL");
+  to_job j = *job;
+  j.batch = 0;  // the field pointers, element and epilogue play no part
+  j.el_flags = 0;
+  j.epi = TO_EPI_NONE;
+  to_status st = validate(j, 0, dtype, MODE_FWD);
+  if (st != TO_OK) return st;
+  DeviceCtx* c;
+  if ((st = get_ctx(&c)) != TO_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  j.method = resolved_method(j);
+  const bool dbl = dtype == TO_C128;
+  hipError_t e;
+  if (j.method == TO_DI) {
+    e = dbl ? TransferTable<double>::direct_integration((cx<double>*)table, di_params(j), twiddles<double>(c, j.px),
+                                                        twiddles<double>(c, j.py), s)
+            : TransferTable<float>::direct_integration((cx<float>*)table, di_params(j), twiddles<float>(c, j.px),
+                                                       twiddles<float>(c, j.py), s);
+  } else {
+    const TransferParams h = make_transfer(j, false);
+    e = dbl ? TransferTable<double>::analytic((cx<double>*)table, j.py, j.px, h, s)
+            : TransferTable<float>::analytic((cx<float>*)table, j.py, j.px, h, s);
+  }
+  return e == hipSuccess ? TO_OK : hip_fail(e, "transfer table");
+}
+
+to_status to_resolve_method(const to_job* job, int32_t* method) {
+  if (!job || !method) return fail(TO_E_INVAL, "job or method is NULL");
+  to_job j = *job;
+  j.batch = 0;
+  j.el_flags = 0;
+  j.epi = TO_EPI_NONE;
+  to_status st = validate(j, 0, TO_C64, MODE_FWD);
+  if (st != TO_OK) return st;
+  *method = resolved_method(j);
+  return TO_OK;
 }
 
 const char* to_version(void) { return "toprop 0.1.0 gfx950"; }

@@ -91,8 +91,10 @@ __device__ __forceinline__ cx<double> cis_rad(double a) {
 // Parameters
 // ---------------------------------------------------------------------------
 struct TransferParams {
-  int method;       // 0 = angular spectrum, 1 = Fresnel transfer function
+  int method;       // 0 = angular spectrum, 1 = Fresnel transfer function,
+                    // 2 = table (direct integration: H read from `table`)
   int conj;         // multiply by conj(H) (adjoint)
+  const void* table;  // method 2: complex of the field type, [LY][LX], FFT order
   double lam2;      // lambda^2
   double q;         // z / lambda
   double q_frac;    // frac(z / lambda), computed exactly on the host
@@ -560,6 +562,18 @@ __global__ void __launch_bounds__(TC * (L / R))
       for (int m = 0; m < R; ++m) hv[m] = transfer_fast(exk, sxk, j + m * TT, L, lam_fy_unit, a.h);
       done = true;
     }
+  }
+  if (!done && a.h.table) {
+    // tabulated H (direct integration): one contiguous row segment of the
+    // table per bin row
+    const cx<T>* tab = static_cast<const cx<T>*>(a.h.table) + (active ? kx : 0);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      cx<T> t = tab[(int64_t)(j + m * TT) * a.lx];
+      if (a.h.conj) t.y = -t.y;
+      hv[m] = t;
+    }
+    done = true;
   }
   if (!done) {
 #pragma unroll

@@ -1,0 +1,30 @@
+// Transfer-function tables: the direct-integration (DI) table, and the
+// tabulated AS / Fresnel transfer function of a job.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace toprop {
+
+// Geometry of a DI table (see di_sample_kernel).
+struct DiParams {
+  int ny, nx;      // field grid: offsets |sy| < ny, |sx| < nx are sampled
+  int py, px;      // padded grid
+  double dy, dx;   // spacing [m]
+  double z;        // distance [m], > 0
+  double lam;      // wavelength [m]
+  double q_frac;   // frac(z / lambda), computed exactly on the host
+};
+
+template <typename T>
+struct TransferTable {
+  // DI: H = FFT2(sampled impulse response * dx dy), [py][px] row-major,
+  // built in place in H.
+  static hipError_t direct_integration(cx<T>* H, const DiParams& p, const cx<T>* tw_x, const cx<T>* tw_y,
+                                       hipStream_t s);
+  // AS / Fresnel: H at every bin of the padded grid.
+  static hipError_t analytic(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s);
+};
+
+}  // namespace toprop

@@ -106,6 +106,11 @@ def good_job(capi):
     (lambda j: (setattr(j, "epi", 3), setattr(j, "epi_out", 0x6000), setattr(j, "in_", None)), "TO_E_INVAL"),
     (lambda j: (setattr(j, "epi", 3), setattr(j, "epi_out", 0x6000), setattr(j, "epi_scale", float("nan"))),
      "TO_E_INVAL"),
+    (lambda j: (setattr(j, "method", 2), setattr(j, "z", 0.0)), "TO_E_INVAL"),        # DI needs z > 0
+    (lambda j: (setattr(j, "method", 2), setattr(j, "z", -0.1)), "TO_E_INVAL"),
+    (lambda j: (setattr(j, "method", 2), setattr(j, "py", 16)), "TO_E_UNSUPPORTED"),  # < 2 ny - 1
+    (lambda j: (setattr(j, "method", 2), setattr(j, "nx", 17), setattr(j, "px", 32)), "TO_E_UNSUPPORTED"),
+    (lambda j: (setattr(j, "method", 3), setattr(j, "z", 10.0), setattr(j, "px", 16)), "TO_E_UNSUPPORTED"),
 ])
 def test_validation_rejects_bad_jobs(capi, mutate, status):
     j = good_job(capi)
@@ -143,3 +148,47 @@ def test_missing_library_fails_loudly(capi, monkeypatch, tmp_path):
     monkeypatch.setattr(capi, "_lib", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         capi.lib()
+
+
+def _resolve(capi, j):
+    m = ctypes.c_int32(-1)
+    rc = capi.lib().to_resolve_method(ctypes.byref(j), ctypes.byref(m))
+    return rc, m.value
+
+
+def test_resolve_method_matches_the_oracle(capi):
+    """The automatic choice (Eq. (sampling_condition)) in the library's host
+    code against the oracle's, over random geometries around the critical
+    distance, both signs of z, and unequal axes."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(31)
+    for _ in range(400):
+        j = good_job(capi)
+        j.ny, j.nx = int(rng.integers(1, 600)), int(rng.integers(1, 600))
+        j.py, j.px = 2048, 2048
+        j.dy, j.dx = float(rng.uniform(1e-6, 2e-5)), float(rng.uniform(1e-6, 2e-5))
+        j.wavelength = float(rng.uniform(4e-7, 8e-7))
+        zc = oracle.critical_distance(j.ny, j.nx, j.dy, j.dx, j.wavelength)
+        j.z = float(zc * rng.choice([-1.5, 0.0, 0.5, 0.999999, 1.0, 1.000001, 3.0]))
+        j.method = capi.TO_AUTO
+        rc, m = _resolve(capi, j)
+        assert rc == capi.TO_OK
+        assert m == oracle.resolve_method(j.ny, j.nx, j.dy, j.dx, j.wavelength, j.z), (j.ny, j.nx, j.z / zc)
+    j = good_job(capi)
+    for meth in (capi.TO_ASM, capi.TO_FRESNEL, capi.TO_DI):
+        j.method = meth
+        assert _resolve(capi, j) == (capi.TO_OK, meth)
+    j.method = 7
+    assert _resolve(capi, j)[0] == capi.TO_E_INVAL
+    assert capi.lib().to_resolve_method(None, None) == capi.TO_E_INVAL
+
+
+def test_transfer_table_validation(capi):
+    lib = capi.lib()
+    j = good_job(capi)
+    assert lib.to_transfer_table(ctypes.byref(j), capi.TO_C64, None, None) == capi.TO_E_INVAL
+    assert lib.to_transfer_table(None, capi.TO_C64, 0x1000, None) == capi.TO_E_INVAL
+    j.method = capi.TO_DI
+    j.py = 16
+    assert lib.to_transfer_table(ctypes.byref(j), capi.TO_C64, 0x1000, None) == capi.TO_E_UNSUPPORTED

@@ -1,0 +1,261 @@
+"""Direct integration (DI) and the automatic choice of method on the GPU:
+the DI transfer table (the DFT of the sampled impulse response of
+Eq. (impulse_response)) and every path that applies it — single jobs,
+backward with the mask gradient, chains of layers, several geometries in one
+call, the plain form, a caller-supplied table, coherence functions — against
+the FP64 oracle, whose DI form is pinned on the CPU against the brute-force
+Rayleigh-Sommerfeld sum.  Bars: complex64 relative L2 <= 2e-5, complex128
+<= 1e-12 (fields); mask gradients c64 <= 1e-4 of the oracle's."""
+import numpy as np
+import pytest
+
+import oracle
+from tests._util import announce, crandn, rel, to_gpu, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {np.complex64: 2e-5, np.complex128: 1e-12}
+
+
+def _tp():
+    import paper_2411_18591_amd as tp
+    return tp
+
+
+def _di_opt(tp, d=(4e-6, 5e-6), lam=0.6e-6, z=None, ny=24, nx=40, method="di", padded=None):
+    dy, dx = d
+    if z is None:
+        z = 1.3 * oracle.critical_distance(ny, nx, dy, dx, lam)
+    return tp.Optics(dy=dy, dx=dx, wavelength=lam, z=z, method=method, pad=2, padded=padded)
+
+
+def _oracle(u, opt, adjoint=False, method=None):
+    ny, nx = u.shape[-2:]
+    meth = {"asm": oracle.ASM, "fresnel": oracle.FRESNEL, "di": oracle.DI}[method or opt.method]
+    return oracle.propagate(u, opt.dy, opt.dx, opt.wavelength, opt.z, meth, adjoint=adjoint,
+                            padded=opt.padded_shape(ny, nx))
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+@pytest.mark.parametrize("shape", [(24, 40, 64, 128), (64, 64, 128, 128), (7, 33, 16, 128), (100, 3, 256, 8)])
+def test_di_table(shape, dtype):
+    """The GPU-built DI table (FP64 sampling, FFT in the field's precision)
+    against the oracle's (long-double phases, FP64 FFT)."""
+    tp = _tp()
+    ny, nx, py, px = shape
+    announce(f"DI table {shape} {dtype.__name__}")
+    opt = _di_opt(tp, ny=ny, nx=nx, padded=(py, px))
+    H = tp.transfer_table(opt, ny, nx, dtype=torch.complex64 if dtype == np.complex64 else torch.complex128)
+    torch.cuda.synchronize()
+    exp = oracle.di_transfer(ny, nx, py, px, opt.dy, opt.dx, opt.wavelength, opt.z)
+    assert rel(to_np(H), exp) <= TOL[dtype] / 4
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_analytic_tables(dtype):
+    """to_transfer_table for the AS (with evanescent bins) and Fresnel
+    methods against the oracle's transfer functions."""
+    tp = _tp()
+    announce(f"AS / Fresnel tables {dtype.__name__}")
+    tdt = torch.complex64 if dtype == np.complex64 else torch.complex128
+    for method, meth in (("asm", oracle.ASM), ("fresnel", oracle.FRESNEL)):
+        opt = tp.Optics(dy=0.37e-6, dx=0.43e-6, wavelength=0.8e-6, z=3e-5, method=method, pad=2)
+        H = tp.transfer_table(opt, 32, 64, dtype=tdt)
+        torch.cuda.synchronize()
+        exp = oracle.transfer(64, 128, 0.37e-6, 0.43e-6, 0.8e-6, 3e-5, meth)
+        assert rel(to_np(H), exp) <= TOL[dtype] / 4, method
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+@pytest.mark.parametrize("shape", [(24, 40, 64, 128), (33, 17, 128, 64), (64, 64, 128, 128), (1, 9, 8, 32)])
+def test_di_forward_and_adjoint(shape, dtype):
+    tp = _tp()
+    ny, nx, py, px = shape
+    announce(f"DI propagate {shape} {dtype.__name__}")
+    rng = np.random.default_rng(960 + ny + nx)
+    u = crandn(rng, 3, ny, nx, dtype=dtype)
+    opt = _di_opt(tp, ny=ny, nx=nx, padded=(py, px))
+    ug = to_gpu(u, torch)
+    out = tp.propagate(ug, opt)
+    gin = tp.propagate_backward(ug, opt)
+    torch.cuda.synchronize()
+    assert rel(to_np(out), _oracle(u, opt)) <= TOL[dtype]
+    assert rel(to_np(gin), _oracle(u, opt, adjoint=True)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_di_with_elements_and_mask_gradient(dtype):
+    """Phase mask and lens before a DI propagation, forward against the
+    oracle; backward: dL/d(in) and dL/dphi against the oracle's adjoint and
+    gradient formulas."""
+    tp = _tp()
+    announce(f"DI elements + gradient {dtype.__name__}")
+    rng = np.random.default_rng(970)
+    ny, nx = 48, 40
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    u = crandn(rng, 2, ny, nx, dtype=dtype)
+    g = crandn(rng, 2, ny, nx, dtype=dtype)
+    phi = (rng.random((ny, nx)) * 6.2).astype(rdt)
+    opt = _di_opt(tp, ny=ny, nx=nx)
+    f = 0.02
+    ug, gg, pg = to_gpu(u, torch), to_gpu(g, torch), to_gpu(phi, torch)
+    out = tp.propagate(ug, opt, phase=pg, lens_f=f)
+    gphi = torch.zeros_like(pg)
+    gin = tp.propagate_backward(gg, opt, saved_in=ug, grad_phase=gphi, phase=pg, lens_f=f)
+    torch.cuda.synchronize()
+    M = oracle.phase_mask(phi) * oracle.lens(ny, nx, opt.dy, opt.dx, opt.wavelength, f)
+    um = oracle.modulate(u, M)
+    assert rel(to_np(out), _oracle(um, opt)) <= TOL[dtype]
+    gmod = _oracle(g, opt, adjoint=True)
+    assert rel(to_np(gin), oracle.modulate(gmod, M, conj=True)) <= TOL[dtype]
+    gtol = 1e-4 if dtype == np.complex64 else 1e-11
+    assert rel(to_np(gphi), oracle.grad_phase(gmod, um)) <= gtol
+
+
+def test_auto_selects_by_critical_distance():
+    """method="auto" runs AS below the critical distance and DI at or beyond
+    it: bitwise equal to the explicit method, and the resolution matches the
+    oracle's."""
+    tp = _tp()
+    announce("auto method")
+    rng = np.random.default_rng(971)
+    ny, nx = 32, 48
+    u = to_gpu(crandn(rng, 2, ny, nx, dtype=np.complex64), torch)
+    zc = oracle.critical_distance(ny, nx, 4e-6, 5e-6, 0.6e-6)
+    for z, want in ((0.5 * zc, "asm"), (zc, "di"), (2.0 * zc, "di"), (-zc, "asm")):
+        auto = _di_opt(tp, ny=ny, nx=nx, z=z, method="auto")
+        expl = _di_opt(tp, ny=ny, nx=nx, z=z, method=want)
+        assert tp.resolve_method(auto, ny, nx) == want
+        assert oracle.resolve_method(ny, nx, 4e-6, 5e-6, 0.6e-6, z) == {"asm": oracle.ASM, "di": oracle.DI}[want]
+        a = tp.propagate(u, auto)
+        b = tp.propagate(u, expl)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), z / zc
+
+
+def test_caller_table_equals_built_table():
+    """A job carrying the table from transfer_table gives bitwise the result
+    of the table the library builds within the call, forward and backward."""
+    tp = _tp()
+    announce("DI caller table")
+    rng = np.random.default_rng(972)
+    ny, nx = 40, 56
+    u = to_gpu(crandn(rng, 3, ny, nx, dtype=np.complex64), torch)
+    opt = _di_opt(tp, ny=ny, nx=nx)
+    H = tp.transfer_table(opt, ny, nx)
+    a = tp.propagate(u, opt)
+    out = torch.empty_like(u)
+    job = tp.make_job(u, opt, out=out, tf_table=H)
+    tp._capi.propagate([job], tp._capi.TO_C64, torch.cuda.current_stream().cuda_stream)
+    gb = tp.propagate_backward(u, opt)
+    gout = torch.empty_like(u)
+    jb = tp.make_job(u, opt, tf_table=H)
+    jb.in_ = None
+    g = tp._capi.Grad()
+    g.grad_out = u.data_ptr()
+    g.grad_in = gout.data_ptr()
+    tp._capi.propagate_backward([jb], [g], tp._capi.TO_C64, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(a, out)
+    assert torch.equal(gb, gout)
+
+
+def test_mixed_geometries_in_one_call():
+    """DI jobs of three geometries (two sharing one), AS jobs and a Fresnel
+    job in one call: every output bitwise equal to its solo run, DI ones
+    against the oracle."""
+    tp = _tp()
+    announce("DI mixed call")
+    rng = np.random.default_rng(973)
+    specs = [(24, 40, "di", 1.3), (24, 40, "di", 1.3), (32, 32, "di", 2.0), (24, 40, "asm", 0.5),
+             (16, 48, "fresnel", 0.7), (24, 40, "di", 3.0)]
+    fields, opts = [], []
+    for ny, nx, m, k in specs:
+        fields.append(to_gpu(crandn(rng, 2, ny, nx, dtype=np.complex64), torch))
+        z = k * oracle.critical_distance(ny, nx, 4e-6, 5e-6, 0.6e-6)
+        opts.append(_di_opt(tp, ny=ny, nx=nx, z=z, method=m))
+    outs = tp.propagate_jobs(fields, opts)
+    solo = [tp.propagate(f, o) for f, o in zip(fields, opts)]
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(outs, solo)):
+        assert torch.equal(a, b), i
+    for i, (f, o) in enumerate(zip(fields, opts)):
+        if o.method == "di":
+            assert rel(to_np(outs[i]), _oracle(to_np(f), o)) <= TOL[np.complex64], i
+
+
+def test_di_chain_training_step():
+    """A 3-layer phase-mask network with DI layers and the MSE loss, forward
+    and backward through the fused chains, against the oracle's stack."""
+    from paper_2411_18591_amd.diffnet import DiffractiveNet
+    tp = _tp()
+    announce("DI chain training step")
+    rng = np.random.default_rng(974)
+    B, n, L = 2, 64, 3
+    d, lam = 8e-6, 0.7e-6
+    z = 1.2 * oracle.critical_distance(n, n, d, d, lam)
+    u0 = crandn(rng, B, n, n, dtype=np.complex128)
+    phis = rng.random((L, n, n)) * 6.2
+    T = rng.random((n, n))
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, method="di", pad=2)
+    net = DiffractiveNet(to_gpu(u0, torch), to_gpu(phis, torch), to_gpu(T, torch), opt)
+    net.step()
+    torch.cuda.synchronize()
+    us = oracle.stack_forward(u0, phis, d, d, lam, z, oracle.DI, 2)
+    assert rel(to_np(net.u[L]), us[L]) <= 1e-12
+    uL = us[L]
+    scale = 1.0 / uL.size
+    gL = 4 * scale * (np.abs(uL) ** 2 - T) * uL
+    _, grads = oracle.stack_backward(us, phis, gL, d, d, lam, z, oracle.DI, 2)
+    assert rel(to_np(net.gmask), np.stack(grads)) <= 1e-11
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_di_coherence(adjoint):
+    tp = _tp()
+    announce(f"DI coherence adjoint={adjoint}")
+    rng = np.random.default_rng(975)
+    n = 8
+    A = crandn(rng, n * n, n * n) / n
+    G0 = (A @ A.conj().T).reshape(n, n, n, n)
+    opt = tp.Optics(dy=10e-6, dx=10e-6, wavelength=633e-9, z=0.002, method="di", pad=2)
+    out = tp.coherence_propagate(to_gpu(G0, torch), opt, adjoint=adjoint)
+    torch.cuda.synchronize()
+    exp = oracle.coherence_propagate(G0, 10e-6, 10e-6, 633e-9, 0.002, oracle.DI, 2, adjoint=adjoint)
+    assert rel(to_np(out), exp) <= 1e-12
+
+
+def test_di_plain_form():
+    """The unfused plain form applies the same DI table: forward and adjoint
+    against the fused path (c128) and the oracle."""
+    tp = _tp()
+    announce("DI plain form")
+    rng = np.random.default_rng(976)
+    u = crandn(rng, 2, 24, 40)
+    opt = _di_opt(tp)
+    ug = to_gpu(u, torch)
+    a = tp.propagate(ug, opt, plain=True)
+    b = tp.propagate(ug, opt)
+    ga = tp.propagate_backward(ug, opt, plain=True)
+    torch.cuda.synchronize()
+    assert rel(to_np(a), to_np(b)) <= 1e-13
+    assert rel(to_np(a), _oracle(u, opt)) <= 1e-12
+    assert rel(to_np(ga), _oracle(u, opt, adjoint=True)) <= 1e-12
+
+
+def test_di_at_the_network_geometry():
+    """1024^2 fields, 8 um, 700 nm, z = 10 cm (beyond the critical distance
+    of 9.36 cm, where the automatic choice takes DI), padded to 2048^2: c64
+    through the automatic method against the oracle's DI."""
+    tp = _tp()
+    announce("DI 1024^2 network geometry")
+    rng = np.random.default_rng(977)
+    n, d, lam, z = 1024, 8e-6, 0.7e-6, 0.1
+    u = crandn(rng, 2, n, n, dtype=np.complex64)
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, method="auto", pad=2)
+    assert tp.resolve_method(opt, n, n) == "di"
+    out = tp.propagate(to_gpu(u, torch), opt)
+    torch.cuda.synchronize()
+    exp = oracle.propagate(u, d, d, lam, z, oracle.DI, 2)
+    assert rel(to_np(out), exp) <= TOL[np.complex64]
