@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--batch", type=int, default=64)
     p.add_argument("--n", type=int, default=1024)
     p.add_argument("--layers", type=int, default=5)
+    p.add_argument("--method", choices=["asm", "di", "auto"], default="asm",
+                   help="propagation method of the network's layers (the headline figure is asm)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-fields", type=int, default=0,
                    help="fields in the CPU oracle sample (0 = min(8, host cores))")
@@ -175,7 +177,9 @@ def main():
             pass
     print(f"[bench] inputs ready in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
 
-    opt = tp.Optics(dy=wl_def.d, dx=wl_def.d, wavelength=wl_def.wavelength, z=wl_def.z, pad=2)
+    opt = tp.Optics(dy=wl_def.d, dx=wl_def.d, wavelength=wl_def.wavelength, z=wl_def.z, pad=2,
+                    method=args.method)
+    method = tp.resolve_method(opt, N, N).upper()
     net = DiffractiveNet(torch.from_numpy(u0_np).to(dev), torch.from_numpy(masks_np).to(dev),
                          torch.from_numpy(target_np).to(dev), opt)
     loss = net.loss
@@ -252,7 +256,7 @@ def main():
         tfs = fl / avg_s / 1e12
         f_h = gbs / HBM_PEAK_GBS
         f_a = tfs / VALU_FP32_PEAK_TFLOPS
-        traffic = measured_traffic(name, chunk) if (N, B, L) == (1024, 64, 5) else None
+        traffic = measured_traffic(name, chunk) if (N, B, L, method) == (1024, 64, 5, "ASM") else None
         if f_a >= f_h:
             roofline = {"bound": "alu", "achieved": round(tfs, 3), "peak": VALU_FP32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(f_a, 4), "traffic": traffic,
@@ -286,10 +290,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, wl_def, u0_np, masks_np, target_np)
+        cpu = cpu_baseline(args, wl_def, u0_np, masks_np, target_np, method)
 
     out = {
-        "metric": "fwd+bwd ASM propagations/s at 1024^2 c64; % of HBM roofline vs plain form",
+        "metric": f"fwd+bwd {method} propagations/s at 1024^2 c64; % of HBM roofline vs plain form",
         "value": round(value, 1),
         "unit": "propagations/s",
         "n_gpus": 1,
@@ -303,7 +307,7 @@ def main():
         "data": "synthetic (seeded blurred-noise fields, uniform random phase masks, blurred target)",
         "config": {
             "workload": f"diffractive network: {B} x {N}^2 complex64 fields, {L} phase masks, "
-                        f"ASM z=10 cm, 8 um, 700 nm, padded to {P}^2, MSE loss, fwd+bwd to masks",
+                        f"{method} z=10 cm, 8 um, 700 nm, padded to {P}^2, MSE loss, fwd+bwd to masks",
             "global_batch": B, "grid": N, "padded": P, "layers": L,
             "propagations_per_step": props,
         },
@@ -319,7 +323,7 @@ def main():
     return 0
 
 
-def cpu_baseline(args, wl_def, u0_np, masks_np, target_np):
+def cpu_baseline(args, wl_def, u0_np, masks_np, target_np, method="ASM"):
     """The FP64 oracle timed on the host on a bounded sample of the same
     workload: `k` fields through the same 5 layers, forward and backward."""
     import numpy as np
@@ -335,10 +339,11 @@ def cpu_baseline(args, wl_def, u0_np, masks_np, target_np):
     phis = [m.astype(np.float64) for m in masks_np[:nl]]
     T = target_np.astype(np.float64)
     d, lam, z = wl_def.d, wl_def.wavelength, wl_def.z
+    meth = oracle.DI if method == "DI" else oracle.ASM
     t0 = time.perf_counter()
-    us = oracle.stack_forward(u0, phis, d, d, lam, z, oracle.ASM, 2)
+    us = oracle.stack_forward(u0, phis, d, d, lam, z, meth, 2)
     _, g = oracle.mse_intensity(us[-1], T)
-    oracle.stack_backward(us, phis, g, d, d, lam, z, oracle.ASM, 2)
+    oracle.stack_backward(us, phis, g, d, d, lam, z, meth, 2)
     dt = time.perf_counter() - t0
     props = 2 * k * nl
     return {"value": round(props / dt, 3), "unit": "propagations/s", "cores": min(k, cores),

@@ -12,12 +12,15 @@ propagation; the backward pass runs the adjoint propagations back to the
 first mask, two gradient buffers alternating.
 
 Every propagation goes through the library's fused kernels (or, with
-``plain=True``, through its unfused plain form)."""
+``plain=True``, through its unfused plain form).  When the optics resolve to
+direct integration (method "di", or "auto" beyond the critical distance),
+the DI transfer table is built once here and carried by every job, since
+the geometry does not change between steps."""
 from __future__ import annotations
 
 import torch
 
-from . import Optics, _capi, propagate_backward_jobs, propagate_jobs
+from . import Optics, _capi, propagate_backward_jobs, propagate_jobs, resolve_method, transfer_table
 
 
 class DiffractiveNet:
@@ -34,6 +37,16 @@ class DiffractiveNet:
         self.gmask = torch.zeros_like(masks)
         self.gbuf = [torch.empty_like(u0) for _ in range(2)]
         self.loss = torch.zeros((), dtype=torch.float64, device=u0.device)
+        ny, nx = u0.shape[1:]
+        self.tf_table = None
+        if resolve_method(opt, ny, nx) == "di":
+            self.tf_table = transfer_table(opt, ny, nx, dtype=u0.dtype, device=u0.device)
+
+    def _element(self, l: int) -> dict:
+        el = {"phase": self.masks[l]}
+        if self.tf_table is not None:
+            el["tf_table"] = self.tf_table
+        return el
 
     def forward(self, plain: bool = False) -> torch.Tensor:
         """u_1 .. u_L and the loss (device float64 scalar); dL/du_L in gbuf[0].
@@ -42,7 +55,7 @@ class DiffractiveNet:
         chunk with fused layer boundaries."""
         self.loss.zero_()
         L = self.L
-        elements = [{"phase": self.masks[l]} for l in range(L)]
+        elements = [self._element(l) for l in range(L)]
         elements[-1].update(epi=_capi.TO_EPI_MSE, epi_ref=self.target, epi_scale=self.scale,
                             epi_grad=self.gbuf[0], epi_loss=self.loss)
         propagate_jobs(self.u[:L], [self.opt] * L, outs=self.u[1:], elements=elements, plain=plain)
@@ -58,7 +71,7 @@ class DiffractiveNet:
         gin = [self.gbuf[(k + 1) % 2] if l > 0 else None for k, l in enumerate(layers)]
         propagate_backward_jobs(gout, [self.opt] * L, saved_ins=[self.u[l] for l in layers], grad_ins=gin,
                                 grad_phases=[self.gmask[l] for l in layers],
-                                elements=[{"phase": self.masks[l]} for l in layers], plain=plain)
+                                elements=[self._element(l) for l in layers], plain=plain)
         return self.gmask
 
     def step(self, plain: bool = False):
