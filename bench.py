@@ -13,6 +13,10 @@ them in the library's HIP kernels (the Python side only enqueues calls).
 
 Prints one JSON line (see the keys below).  --gpus must be 1: this build
 runs on a single GPU.
+
+``--workload poly4f`` measures the polychromatic 4f imaging workload instead
+(251 wavelengths x 3 propagations of a 1000^2 complex64 field padded to
+2048^2, weighted incoherent sum fused): forward propagations per second.
 """
 from __future__ import annotations
 
@@ -40,6 +44,8 @@ def parse():
     p.add_argument("--layers", type=int, default=5)
     p.add_argument("--method", choices=["asm", "di", "auto"], default="asm",
                    help="propagation method of the network's layers (the headline figure is asm)")
+    p.add_argument("--workload", choices=["diffnet", "poly4f"], default="diffnet")
+    p.add_argument("--fwhm-nm", type=float, default=10.0, help="poly4f: spectral FWHM")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-fields", type=int, default=0,
                    help="fields in the CPU oracle sample (0 = min(8, host cores))")
@@ -148,6 +154,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is described in DESIGN.md, not built)"}))
         return 2
+    if args.workload == "poly4f":
+        return run_poly4f(args)
     import numpy as np
     import torch
 
@@ -317,6 +325,134 @@ def main():
         "roofline": roofline,
         "kernels": kernels_out,
         "wall_s": round(t_wall, 3),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+def dominant_roofline(prof, wl, chunk):
+    """Roofline entry of the kernel with the largest GPU time (no traffic)."""
+    kern = []
+    for name, (cnt, ms) in prof.items():
+        m = kernel_model(name, wl, chunk)
+        if m:
+            kern.append((ms, name, cnt, m))
+    if not kern:
+        return None
+    ms, name, cnt, (by, fl) = max(kern)
+    avg_s = ms / cnt / 1000.0
+    gbs, tfs = by / avg_s / 1e9, fl / avg_s / 1e12
+    f_h, f_a = gbs / HBM_PEAK_GBS, tfs / VALU_FP32_PEAK_TFLOPS
+    if f_a >= f_h:
+        return {"bound": "alu", "achieved": round(tfs, 3), "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(f_a, 4), "traffic": None, "kernel": name, "avg_us": round(avg_s * 1e6, 2),
+                "hbm_view": {"achieved_GB_s": round(gbs, 1), "frac": round(f_h, 4)}}
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(f_h, 4), "traffic": None, "kernel": name, "avg_us": round(avg_s * 1e6, 2),
+            "alu_view": {"achieved_TFLOP_s": round(tfs, 3), "frac": round(f_a, 4)}}
+
+
+def run_poly4f(args):
+    """Polychromatic 4f imaging: one image = every wavelength through
+    P_f, lens, P_2f, lens, P_f with the weighted intensity summed (one
+    library call)."""
+    import numpy as np
+    import torch
+
+    import paper_2411_18591_amd as tp
+    from paper_2411_18591_amd import _capi
+    from paper_2411_18591_amd.fourf import FourF
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl = workloads.Polychromatic4fWorkload(fwhm=args.fwhm_nm * 1e-9)
+    u_np = wl.field()
+    u = torch.from_numpy(u_np).to(dev)
+    lams, wts = wl.wavelengths(), wl.weights()
+    sys4f = FourF(wl.f, wl.d, wl.d, method=args.method)
+    methods = sorted({tp.resolve_method(sys4f._opt(lam, z), wl.n, wl.n) for lam in lams for z in (wl.f, 2 * wl.f)})
+    I = torch.zeros((wl.n, wl.n), dtype=torch.float32, device=dev)
+
+    def step():
+        I.zero_()
+        sys4f.image(u, lams, wts, out=I)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    props = 3 * len(lams)
+    prof = {}
+    if not args.no_profile:
+        _capi.profile_begin()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        prof = _capi.profile_end()
+    P = 2048
+    wlm = {"n": wl.n, "padded": P}
+    roofline = dominant_roofline(prof, wlm, 1)
+    c = 8
+    step_bytes = props * 2 * wl.n * wl.n * c
+    kernels_out = {k: {"launches": n, "avg_us": round(1000.0 * ms / n, 2)} for k, (n, ms) in
+                   sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        pick = [len(lams) // 2 - 1, len(lams) // 2, len(lams) // 2 + 1]
+        ua = u_np.astype(np.complex128)
+        meth = {"ASM": oracle.ASM, "DI": oracle.DI}
+        t0 = time.perf_counter()
+        acc = np.zeros((wl.n, wl.n))
+        for k in pick:
+            lam = lams[k]
+            L = oracle.lens(wl.n, wl.n, wl.d, wl.d, lam, wl.f)
+            def prop(v, z):
+                m = meth.get(args.method.upper())
+                if m is None:
+                    m = oracle.resolve_method(wl.n, wl.n, wl.d, wl.d, lam, z)
+                return oracle.propagate(v, wl.d, wl.d, lam, z, m, padded=(P, P))
+            v = prop(ua, wl.f)
+            v = prop(oracle.modulate(v, L), 2 * wl.f)
+            v = prop(oracle.modulate(v, L), wl.f)
+            acc += wts[k] * oracle.intensity(v)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(3 * len(pick) / dt, 3), "unit": "propagations/s", "cores": 1, "kind": "oracle",
+               "sample": f"3 of {len(lams)} wavelengths through the 4f system ({3 * len(pick)} FP64 "
+                         f"propagations of 1000^2 -> 2048^2, {dt:.1f} s; one field, one thread)"}
+    out = {
+        "metric": "polychromatic 4f imaging: forward propagations/s at 1000^2 c64",
+        "value": round(props / (ms_step / 1000.0), 1),
+        "unit": "propagations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic (seeded blurred-noise amplitude, uniform phase; Gaussian spectrum)",
+        "config": {
+            "workload": f"polychromatic 4f imaging: {len(lams)} wavelengths 575-825 nm (FWHM "
+                        f"{args.fwhm_nm:g} nm), 1000^2 complex64, 10 um, f = 200 mm, padded to 2048^2, "
+                        f"methods {'/'.join(methods)}, weighted intensity sum fused",
+            "wavelengths": len(lams), "grid": wl.n, "padded": P, "propagations_per_step": props,
+        },
+        "hbm_roofline_step": {"algorithmic_bytes": step_bytes,
+                              "frac": round(step_bytes / (ms_step / 1000.0) / (HBM_PEAK_GBS * 1e9), 4)},
+        "roofline": roofline,
+        "kernels": kernels_out,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -100,6 +100,8 @@ struct DeviceCtx {
   size_t coh_bytes = 0;
   void* di = nullptr;     // direct-integration tables built within a call
   size_t di_bytes = 0;
+  void* sep = nullptr;    // separable complex64 transfer-function tables of a call
+  size_t sep_bytes = 0;
 };
 
 std::mutex g_mutex;
@@ -177,19 +179,25 @@ to_status ensure_plain(DeviceCtx* c, size_t bytes) {
   return TO_OK;
 }
 
-to_status ensure_di(DeviceCtx* c, size_t bytes) {
-  if (c->di_bytes >= bytes) return TO_OK;
+// Grow a device-wide table area (synchronizes the device when it has to
+// reallocate, since queued work may still read the old one).
+to_status ensure_area(void** area, size_t* have, size_t bytes, const char* what) {
+  if (*have >= bytes) return TO_OK;
   hipError_t e;
-  if (c->di) {
+  if (*area) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    (void)hipFree(c->di);
-    c->di = nullptr;
-    c->di_bytes = 0;
+    (void)hipFree(*area);
+    *area = nullptr;
+    *have = 0;
   }
-  if ((e = hipMalloc(&c->di, bytes)) != hipSuccess)
-    return fail(TO_E_NOMEM, "direct-integration table of %zu bytes failed: %s", bytes, hipGetErrorString(e));
-  c->di_bytes = bytes;
+  if ((e = hipMalloc(area, bytes)) != hipSuccess)
+    return fail(TO_E_NOMEM, "%s of %zu bytes failed: %s", what, bytes, hipGetErrorString(e));
+  *have = bytes;
   return TO_OK;
+}
+
+to_status ensure_di(DeviceCtx* c, size_t bytes) {
+  return ensure_area(&c->di, &c->di_bytes, bytes, "direct-integration table");
 }
 
 to_status ensure_partial(Lane* c, size_t count) {
@@ -446,6 +454,14 @@ template <typename T>
 hipError_t prepare_transfer(const to_job& j, Lane* c, hipStream_t s, TransferParams* h, int slot = 0) {
   if (sizeof(T) != 4 || h->table) return hipSuccess;
   if (h->method == TO_ASM && !(asm_remainder_cycles(j) <= kFastRemainderCycles)) return hipSuccess;
+  if (j.tf_table) {  // built for the whole call at entry (prepare_jobs)
+    h->fast = 1;
+    h->ex = (const cx<float>*)j.tf_table;
+    h->ey = h->ex + j.px;
+    h->sx = (const float*)(h->ey + j.py);
+    h->sy = h->sx + j.px;
+    return hipSuccess;
+  }
   cx<float>* ex = (cx<float>*)((char*)c->tf + (size_t)slot * kTableSlotBytes);
   cx<float>* ey = ex + kMaxLen;
   float* sx = (float*)(ey + kMaxLen);
@@ -1404,6 +1420,61 @@ bool same_di_geometry(const to_job& a, const to_job& b) {
 // before any other work of the call (one table per distinct geometry, in the
 // device's DI area; every lane forks from `s` after it, and the area is only
 // rebuilt by a later call, which `s` orders after this one).
+bool same_sep_geometry(const to_job& a, const to_job& b) {
+  return a.py == b.py && a.px == b.px && a.dy == b.dy && a.dx == b.dx && a.wavelength == b.wavelength &&
+         a.z == b.z;
+}
+
+// complex64 jobs whose transfer function takes the separable form get their
+// 1-D tables from one batched launch for the whole call (one table per
+// distinct padded grid, spacing, wavelength and distance), carried in the
+// prepared copy's tf_table.
+to_status prepare_separable(std::vector<to_job>* jobs, DeviceCtx* c, hipStream_t s) {
+  const int n = (int)jobs->size();
+  std::vector<int> first, table_of(n, -1);
+  std::vector<size_t> offset;
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    const to_job& j = (*jobs)[i];
+    if (j.batch == 0 || j.method == TO_DI) continue;
+    if (j.method == TO_ASM && !(asm_remainder_cycles(j) <= kFastRemainderCycles)) continue;
+    int k = 0;
+    while (k < (int)first.size() && !same_sep_geometry((*jobs)[first[k]], j)) ++k;
+    if (k == (int)first.size()) {
+      first.push_back(i);
+      offset.push_back(total);
+      total += ((size_t)(j.px + j.py) * (sizeof(cx<float>) + sizeof(float)) + 255) & ~(size_t)255;
+    }
+    table_of[i] = k;
+  }
+  if (first.empty()) return TO_OK;
+  to_status st = ensure_area(&c->sep, &c->sep_bytes, total, "transfer-function tables");
+  if (st != TO_OK) return st;
+  for (size_t k0 = 0; k0 < first.size(); k0 += kSepBatch) {
+    SepTableBatch b;
+    memset(&b, 0, sizeof(b));
+    for (size_t k = k0; k < first.size() && k < k0 + kSepBatch; ++k) {
+      const to_job& j = (*jobs)[first[k]];
+      const TransferParams h = make_transfer(j, false);
+      SepTableDesc& d = b.d[b.count++];
+      d.base = (char*)c->sep + offset[k];
+      d.lx = j.px;
+      d.ly = j.py;
+      d.inv_lxdx = h.inv_lxdx;
+      d.inv_lydy = h.inv_lydy;
+      d.fres_a = h.fres_a;
+      d.q_frac = h.q_frac;
+      d.lam2 = h.lam2;
+      b.maxlen = std::max(b.maxlen, j.px + j.py);
+    }
+    hipError_t e = timed("tf_tables", b.maxlen, false, s, [&] { return separable_tables(b, s); });
+    if (e != hipSuccess) return hip_fail(e, "transfer-function tables");
+  }
+  for (int i = 0; i < n; ++i)
+    if (table_of[i] >= 0) (*jobs)[i].tf_table = (char*)c->sep + offset[table_of[i]];
+  return TO_OK;
+}
+
 template <typename T>
 to_status prepare_jobs(const to_job* jobs, int n, DeviceCtx* c, hipStream_t s, std::vector<to_job>* out) {
   out->assign(jobs, jobs + n);
@@ -1414,6 +1485,7 @@ to_status prepare_jobs(const to_job* jobs, int n, DeviceCtx* c, hipStream_t s, s
   for (int i = 0; i < n; ++i) {
     to_job& j = (*out)[i];
     j.method = resolved_method(j);
+    if (j.method != TO_DI) j.tf_table = nullptr;  // the field is read for DI only
     if (j.method != TO_DI || j.tf_table || j.batch == 0) continue;
     int k = 0;
     while (k < (int)first.size() && !same_di_geometry((*out)[first[k]], j)) ++k;
@@ -1440,9 +1512,16 @@ to_status prepare_jobs(const to_job* jobs, int n, DeviceCtx* c, hipStream_t s, s
   return TO_OK;
 }
 
+template <typename T>
+to_status prepare_all(const to_job* jobs, int n, DeviceCtx* c, hipStream_t s, std::vector<to_job>* out) {
+  to_status st = prepare_jobs<T>(jobs, n, c, s, out);
+  if (st == TO_OK && sizeof(T) == 4) st = prepare_separable(out, c, s);
+  return st;
+}
+
 to_status prepare_jobs_dt(const to_job* jobs, int n, to_dtype dt, DeviceCtx* c, hipStream_t s,
                           std::vector<to_job>* out) {
-  return dt == TO_C64 ? prepare_jobs<float>(jobs, n, c, s, out) : prepare_jobs<double>(jobs, n, c, s, out);
+  return dt == TO_C64 ? prepare_all<float>(jobs, n, c, s, out) : prepare_all<double>(jobs, n, c, s, out);
 }
 
 to_status plan_args(int32_t py, int32_t px, to_dtype dtype) {
@@ -1840,6 +1919,7 @@ to_status to_release(void) {
     if (c.plain) note(hipFree(c.plain));
     if (c.coh) note(hipFree(c.coh));
     if (c.di) note(hipFree(c.di));
+    if (c.sep) note(hipFree(c.sep));
     c = DeviceCtx();
   }
   note(hipSetDevice(cur));

@@ -165,14 +165,11 @@ __device__ __forceinline__ cx<float> transfer_fast(cx<float> exk, float sxk, int
   return h;
 }
 
-// FP64-built tables of the separable transfer function for one propagation:
-// entries 0..lx-1 are the x tables, lx..lx+ly-1 the y tables.
-template <typename T>
-__global__ void __launch_bounds__(256) tf_tables_kernel(cx<float>* ex, float* sx, int lx,
-                                                        double inv_lxdx, cx<float>* ey, float* sy,
-                                                        int ly, double inv_lydy, double fres_a,
-                                                        double q_frac, double lam2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Entry i of the FP64-built tables of the separable transfer function of one
+// propagation: entries 0..lx-1 are the x tables, lx..lx+ly-1 the y tables.
+__device__ __forceinline__ void tf_table_entry(int i, cx<float>* ex, float* sx, int lx, double inv_lxdx,
+                                               cx<float>* ey, float* sy, int ly, double inv_lydy,
+                                               double fres_a, double q_frac, double lam2) {
   if (i < lx) {
     const int ks = i < lx / 2 ? i : i - lx;
     const double f = (double)ks * inv_lxdx;
@@ -191,6 +188,15 @@ __global__ void __launch_bounds__(256) tf_tables_kernel(cx<float>* ex, float* sx
     ey[k] = {(float)co, (float)s};
     sy[k] = (float)(lam2 * f * f);
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) tf_tables_kernel(cx<float>* ex, float* sx, int lx,
+                                                        double inv_lxdx, cx<float>* ey, float* sy,
+                                                        int ly, double inv_lydy, double fres_a,
+                                                        double q_frac, double lam2) {
+  tf_table_entry(blockIdx.x * blockDim.x + threadIdx.x, ex, sx, lx, inv_lxdx, ey, sy, ly, inv_lydy, fres_a,
+                 q_frac, lam2);
 }
 
 template <typename T>

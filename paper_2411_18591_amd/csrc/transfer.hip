@@ -73,6 +73,22 @@ hipError_t TransferTable<T>::analytic(cx<T>* H, int py, int px, const TransferPa
   return Plain<T>::table(H, py, px, p, s);
 }
 
+__global__ void __launch_bounds__(256) separable_tables_kernel(SepTableBatch b) {
+  const SepTableDesc& d = b.d[blockIdx.y];
+  cx<float>* ex = static_cast<cx<float>*>(d.base);
+  cx<float>* ey = ex + d.lx;
+  float* sx = reinterpret_cast<float*>(ey + d.ly);
+  float* sy = sx + d.lx;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  tf_table_entry(i, ex, sx, d.lx, d.inv_lxdx, ey, sy, d.ly, d.inv_lydy, d.fres_a, d.q_frac, d.lam2);
+}
+
+hipError_t separable_tables(const SepTableBatch& b, hipStream_t s) {
+  if (b.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(separable_tables_kernel, dim3((b.maxlen + 255) / 256, b.count), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
 template struct TransferTable<float>;
 template struct TransferTable<double>;
 

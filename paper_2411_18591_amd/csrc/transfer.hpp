@@ -17,6 +17,22 @@ struct DiParams {
   double q_frac;   // frac(z / lambda), computed exactly on the host
 };
 
+// Separable complex64 transfer-function tables (see TransferParams) of many
+// propagations, built by one launch: table k is {ex[lx], ey[ly], sx[lx],
+// sy[ly]} at `base[k]`.
+struct SepTableDesc {
+  void* base;
+  int lx, ly;
+  double inv_lxdx, inv_lydy, fres_a, q_frac, lam2;
+};
+constexpr int kSepBatch = 32;  // tables per launch (kernel arguments stay < 4 KiB)
+struct SepTableBatch {
+  int count;
+  int maxlen;  // largest lx + ly of the batch
+  SepTableDesc d[kSepBatch];
+};
+hipError_t separable_tables(const SepTableBatch& b, hipStream_t s);
+
 template <typename T>
 struct TransferTable {
   // DI: H = FFT2(sampled impulse response * dx dy), [py][px] row-major,

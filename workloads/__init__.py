@@ -145,6 +145,47 @@ class DiffractiveNetWorkload:
 
 
 @dataclass
+class Polychromatic4fWorkload:
+    """Wide-band light through a 4f imaging system (the polychromatic
+    example of the paper's "Polychromatic fields" section, on the 4f system
+    of its first listing): 1000^2 grid, 10 um spacing, lenses f = 200 mm at
+    z = f and z = 3f, image at z = 4f; 251 wavelengths evenly spaced over
+    575-825 nm with Gaussian spectral weights (mean 700 nm, FWHM 10, 20, 40
+    or 80 nm, normalised to unit sum); the detected image is the
+    weight-summed intensity (Eq. (I_poly)).
+
+    The paper's input file is not available: the input is a stand-in with
+    uniform phase and the amplitude of U[0,1) noise blurred with sigma 6 px
+    (seed 6001), squared for contrast, complex64.  Padding 2x (1000 ->
+    2048, the next power of two)."""
+    n: int = 1000
+    d: float = 10e-6
+    f: float = 0.2
+    count: int = 251
+    lam_lo: float = 575e-9
+    lam_hi: float = 825e-9
+    mean: float = 700e-9
+    fwhm: float = 10e-9
+    pad: int = 2
+
+    def wavelengths(self) -> np.ndarray:
+        return np.linspace(self.lam_lo, self.lam_hi, self.count)
+
+    def weights(self) -> np.ndarray:
+        """Gaussian spectrum exp(-4 ln 2 (lambda - mean)^2 / FWHM^2),
+        normalised to unit sum (float64)."""
+        lam = self.wavelengths()
+        w = np.exp(-4.0 * math.log(2.0) * ((lam - self.mean) / self.fwhm) ** 2)
+        return w / w.sum()
+
+    def field(self, n: int | None = None) -> np.ndarray:
+        n = self.n if n is None else n
+        a = blurred_uniform(6001, (n, n), 6.0)
+        a = (a - a.min()) / (a.max() - a.min())
+        return (a * a).astype(np.complex64)
+
+
+@dataclass
 class PolarizedWorkload:
     """3-component field x W wavelengths, Fresnel propagation after a
     quarter-wave plate (fast axis 45 deg), a linear polarizer (30 deg) and a
