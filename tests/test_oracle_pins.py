@@ -421,6 +421,68 @@ def test_resolve_method():
 
 
 # --------------------------------------------------------------------------
+# Resampling onto another grid
+# --------------------------------------------------------------------------
+
+def test_bilinear_reproduces_bilinear_functions():
+    """Bilinear interpolation is exact for f = a + b x + c y + d x y at every
+    output sample inside the input grid's hull (a closed form independent of
+    the interpolation code)."""
+    gin = (12, 17, 3e-6, 2e-6, 1e-6, -2e-6)
+    gout = (23, 19, 1.3e-6, 1.7e-6, 0.4e-6, 0.5e-6)
+    yi = oracle.coords(12, 3e-6, 1e-6)[:, None]
+    xi = oracle.coords(17, 2e-6, -2e-6)[None, :]
+    f = lambda y, x: (0.3 - 0.2j) + 1e5 * x * (1 + 2j) - 2e5 * y + 3e10 * x * y * 1j
+    out = oracle.resample(f(yi, xi), gin, gout, oracle.BILINEAR)
+    Y = oracle.coords(23, 1.3e-6, 0.4e-6)[:, None]
+    X = oracle.coords(19, 1.7e-6, 0.5e-6)[None, :]
+    inside = (Y >= yi.min()) & (Y <= yi.max()) & (X >= xi.min()) & (X <= xi.max())
+    assert inside.sum() > 100
+    exp = f(Y, X) * np.ones_like(out)
+    assert np.max(np.abs(out - exp)[inside]) < 1e-13 * np.max(np.abs(exp))
+    assert np.all(out[~((Y >= yi.min() - 3e-6) & (Y <= yi.max() + 3e-6) & (X >= xi.min() - 2e-6) & (X <= xi.max() + 2e-6))] == 0)
+
+
+def test_nearest_is_the_closest_sample():
+    """Nearest neighbour against a brute-force search for the closest input
+    sample of every output sample (distances not within 1e-9 of a tie);
+    zero outside the input window."""
+    gin = (9, 14, 5e-6, 4e-6, 2e-6, 1e-6)
+    gout = (21, 25, 2.1e-6, 2.9e-6, -1.1e-6, 3.3e-6)
+    rng = np.random.default_rng(751)
+    u = crandn(rng, 2, 9, 14)
+    out = oracle.resample(u, gin, gout, oracle.NEAREST)
+    yi, xi = oracle.coords(9, 5e-6, 2e-6), oracle.coords(14, 4e-6, 1e-6)
+    Y, X = oracle.coords(21, 2.1e-6, -1.1e-6), oracle.coords(25, 2.9e-6, 3.3e-6)
+    for q in range(21):
+        for r in range(25):
+            ky = int(np.argmin(np.abs(yi - Y[q])))
+            kx = int(np.argmin(np.abs(xi - X[r])))
+            iny = abs(yi[ky] - Y[q]) < 0.5 * 5e-6
+            inx = abs(xi[kx] - X[r]) < 0.5 * 4e-6
+            exp = u[:, ky, kx] if (iny and inx) else 0
+            assert np.all(out[:, q, r] == exp), (q, r)
+
+
+def test_resample_identity_and_adjoint():
+    rng = np.random.default_rng(752)
+    gin = (7, 10, 2e-6, 3e-6, 0.0, 1e-6)
+    u = crandn(rng, 3, 7, 10)
+    for mode in (oracle.NEAREST, oracle.BILINEAR):
+        assert np.array_equal(oracle.resample(u, gin, gin, mode), u)
+    gout = (11, 6, 1.1e-6, 4.7e-6, 0.3e-6, -0.6e-6)
+    for mode in (oracle.NEAREST, oracle.BILINEAR):
+        A = np.empty((66, 70), complex)
+        for p in range(70):
+            e = np.zeros(70, complex)
+            e[p] = 1.0
+            A[:, p] = oracle.resample(e.reshape(7, 10), gin, gout, mode).ravel()
+        g = crandn(rng, 3, 11, 6)
+        adj = oracle.resample_adjoint(g, gin, gout, mode)
+        assert rel(adj.reshape(3, 70), g.reshape(3, 66) @ A.conj()) < 1e-14
+
+
+# --------------------------------------------------------------------------
 # Polarization
 # --------------------------------------------------------------------------
 
