@@ -309,6 +309,33 @@ to_status to_release(void);
  * job's field pointers, element and epilogue are ignored.                    */
 to_status to_transfer_table(const to_job* job, to_dtype dtype, void* table, void* stream);
 
+/* Resampling onto another grid (section "Computational Fourier optics":
+ * where input and output grids have different spacings, the field is
+ * propagated on the input spacing and then interpolated onto the output
+ * grid, bilinearly or to the nearest sample).  A grid is ny x nx samples of
+ * spacing (dy, dx), sample (y, x) at ((y - ny/2) dy + y0, (x - nx/2) dx + x0)
+ * as everywhere in this library.  Along each axis, output sample j reads the
+ * input at the fractional index
+ *   t = ((j - n_out/2) (d_out / d_in) + (o_out - o_in) / d_in) + n_in/2
+ * (FP64, evaluated in this order without fused multiply-adds, so identical
+ * grids map exactly): TO_BILINEAR weights 1 - a and a (a = t - floor t) on
+ * samples floor t and floor t + 1, TO_NEAREST takes sample floor(t + 1/2);
+ * the 2-D weights are products of the axis weights, and samples outside the
+ * input window read zero.
+ *   adjoint == 0: src [batch][grid_in], dst [batch][grid_out], dst = R src;
+ *   adjoint != 0: src [batch][grid_out], dst [batch][grid_in], dst = R^T src
+ *                 (the gradient map: the weights are real), computed as a
+ *                 gather in a fixed order (deterministic, no atomics).
+ * dst is overwritten and must not overlap src (TO_E_INVAL).                  */
+typedef enum { TO_NEAREST = 0, TO_BILINEAR = 1 } to_interp;
+typedef struct to_grid {
+  int32_t ny, nx;   /* samples, >= 1                                          */
+  double dy, dx;    /* spacing [m], > 0                                       */
+  double y0, x0;    /* offset of the grid from the optical axis [m]           */
+} to_grid;
+to_status to_resample(const void* src, void* dst, const to_grid* grid_in, const to_grid* grid_out, int64_t batch,
+                      int32_t interp, int32_t adjoint, to_dtype dtype, void* stream);
+
 /* The method a job runs with: job->method, or for TO_AUTO the choice by the
  * critical distance described with the transfer functions.  Host only.      */
 to_status to_resolve_method(const to_job* job, int32_t* method);

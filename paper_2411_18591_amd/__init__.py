@@ -29,7 +29,7 @@ __all__ = [
     "Optics", "propagate", "modulate", "propagate_backward", "coherence_propagate",
     "propagate_ad", "propagate_intensity", "propagate_jobs", "propagate_backward_jobs", "linear_polarizer", "waveplate",
     "jones3", "version", "autotune", "plan_get", "plan_set", "plan_clear", "plan_load", "plan_save",
-    "transfer_table", "resolve_method",
+    "transfer_table", "resolve_method", "Grid", "resample", "propagate_to",
 ]
 
 ASM = "asm"
@@ -251,6 +251,59 @@ def transfer_table(opt: Optics, ny: int, nx: int, dtype=torch.complex64, device=
     code = _dtype_code(H)
     _capi.transfer_table(j, code, H.data_ptr(), torch.cuda.current_stream(dev).cuda_stream)
     return H
+
+
+@dataclass
+class Grid:
+    """A sampling grid: ny x nx samples of spacing (dy, dx), offset (y0, x0)
+    from the optical axis (sample ny//2, nx//2 on it when the offset is 0)."""
+    ny: int
+    nx: int
+    dy: float
+    dx: float
+    y0: float = 0.0
+    x0: float = 0.0
+
+    def _rec(self):
+        g = _capi.Grid()
+        g.ny, g.nx = int(self.ny), int(self.nx)
+        g.dy, g.dx, g.y0, g.x0 = float(self.dy), float(self.dx), float(self.y0), float(self.x0)
+        return g
+
+
+_INTERP = {"nearest": _capi.TO_NEAREST, "bilinear": _capi.TO_BILINEAR}
+
+
+def resample(u: torch.Tensor, grid_in: Grid, grid_out: Grid, interp: str = "bilinear", *,
+             adjoint: bool = False, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Interpolate fields ``[..., ny, nx]`` on ``grid_in`` onto ``grid_out``
+    (``adjoint``: the transpose map, from a gradient on grid_out to one on
+    grid_in).  Zero outside the input window."""
+    if interp not in _INTERP:
+        raise ValueError(f"interp must be one of {list(_INTERP)}")
+    src_g, dst_g = (grid_out, grid_in) if adjoint else (grid_in, grid_out)
+    if tuple(u.shape[-2:]) != (src_g.ny, src_g.nx):
+        raise ValueError(f"field must end in ({src_g.ny}, {src_g.nx})")
+    if not u.is_contiguous():
+        raise ValueError("field must be contiguous")
+    batch = u.numel() // (src_g.ny * src_g.nx)
+    shape = tuple(u.shape[:-2]) + (dst_g.ny, dst_g.nx)
+    if out is None:
+        out = torch.empty(shape, dtype=u.dtype, device=u.device)
+    _need(out, "out", u.dtype, u, shape)
+    _capi.resample(u.data_ptr(), out.data_ptr(), grid_in._rec(), grid_out._rec(), batch, _INTERP[interp], adjoint,
+                   _dtype_code(u), _stream(u))
+    return out
+
+
+def propagate_to(u: torch.Tensor, opt: Optics, grid_out: Grid, interp: str = "bilinear", **element) -> torch.Tensor:
+    """Propagation onto a grid of other spacing (section "Computational
+    Fourier optics"): propagate on the input grid (spacing and window of u),
+    then interpolate onto ``grid_out``; the output window reads zero beyond
+    the input window."""
+    ny, nx = u.shape[-2], u.shape[-1]
+    mid = propagate(u, opt, **element)
+    return resample(mid, Grid(ny, nx, opt.dy, opt.dx, opt.y0, opt.x0), grid_out, interp)
 
 
 def resolve_method(opt: Optics, ny: int, nx: int) -> str:

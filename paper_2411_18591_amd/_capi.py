@@ -22,6 +22,8 @@ TO_ASM = 0
 TO_FRESNEL = 1
 TO_DI = 2
 TO_AUTO = 3
+TO_NEAREST = 0
+TO_BILINEAR = 1
 TO_C64 = 0
 TO_C128 = 1
 
@@ -38,6 +40,7 @@ TO_EPI_INTENSITY = 3
 
 EXPORTED = (
     "to_propagate",
+    "to_resample",
     "to_transfer_table",
     "to_resolve_method",
     "to_modulate",
@@ -91,6 +94,17 @@ class Job(ctypes.Structure):
         ("epi_out", ctypes.c_void_p),
         ("el_jones_map", ctypes.c_void_p),
         ("tf_table", ctypes.c_void_p),
+    ]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [
+        ("ny", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("dy", ctypes.c_double),
+        ("dx", ctypes.c_double),
+        ("y0", ctypes.c_double),
+        ("x0", ctypes.c_double),
     ]
 
 
@@ -177,6 +191,10 @@ def lib() -> ctypes.CDLL:
         L.to_transfer_table.restype = c_int
         L.to_resolve_method.argtypes = [JP, ctypes.POINTER(c_int)]
         L.to_resolve_method.restype = c_int
+        GR = ctypes.POINTER(Grid)
+        L.to_resample.argtypes = [ctypes.c_void_p, ctypes.c_void_p, GR, GR, ctypes.c_int64, c_int, c_int, c_int,
+                                  ctypes.c_void_p]
+        L.to_resample.restype = c_int
         _lib = L
     return _lib
 
@@ -225,6 +243,13 @@ def autotune(job, dtype: int, stream: int) -> dict:
 
 def transfer_table(job, dtype: int, table: int, stream: int) -> None:
     check(lib().to_transfer_table(ctypes.byref(job), dtype, ctypes.c_void_p(table), ctypes.c_void_p(stream)))
+
+
+def resample(src: int, dst: int, grid_in, grid_out, batch: int, interp: int, adjoint: bool, dtype: int,
+             stream: int) -> None:
+    check(lib().to_resample(ctypes.c_void_p(src), ctypes.c_void_p(dst), ctypes.byref(grid_in),
+                            ctypes.byref(grid_out), batch, interp, 1 if adjoint else 0, dtype,
+                            ctypes.c_void_p(stream)))
 
 
 def resolve_method(job) -> int:

@@ -17,6 +17,7 @@
 #include "launch.hpp"
 #include "plain.hpp"
 #include "plan.hpp"
+#include "resample.hpp"
 #include "transfer.hpp"
 
 using namespace toprop;
@@ -1952,6 +1953,47 @@ to_status to_transfer_table(const to_job* job, to_dtype dtype, void* table, void
             : TransferTable<float>::analytic((cx<float>*)table, j.py, j.px, h, s);
   }
   return e == hipSuccess ? TO_OK : hip_fail(e, "transfer table");
+}
+
+to_status to_resample(const void* src, void* dst, const to_grid* grid_in, const to_grid* grid_out, int64_t batch,
+                      int32_t interp, int32_t adjoint, to_dtype dtype, void* stream) {
+  if (dtype != TO_C64 && dtype != TO_C128) return fail(TO_E_INVAL, "dtype %d is not TO_C64/TO_C128", (int)dtype);
+  if (!grid_in || !grid_out) return fail(TO_E_INVAL, "grid_in or grid_out is NULL");
+  if (interp != TO_NEAREST && interp != TO_BILINEAR) return fail(TO_E_INVAL, "unknown interpolation %d", interp);
+  if (batch < 0) return fail(TO_E_INVAL, "batch %lld < 0", (long long)batch);
+  const to_grid* gs[2] = {grid_in, grid_out};
+  for (const to_grid* g : gs) {
+    if (g->ny < 1 || g->nx < 1) return fail(TO_E_INVAL, "grid %dx%d must be >= 1", g->ny, g->nx);
+    if (!finite_pos(g->dy) || !finite_pos(g->dx)) return fail(TO_E_INVAL, "grid spacing must be finite and > 0");
+    if (!std::isfinite(g->y0) || !std::isfinite(g->x0)) return fail(TO_E_INVAL, "grid offset not finite");
+  }
+  const int64_t pin = (int64_t)grid_in->ny * grid_in->nx, pout = (int64_t)grid_out->ny * grid_out->nx;
+  if (batch > 0 && std::max(pin, pout) > (int64_t(1) << 40) / batch)
+    return fail(TO_E_UNSUPPORTED, "resampling batch too large");
+  if (batch == 0) return TO_OK;
+  if (!src || !dst) return fail(TO_E_INVAL, "src or dst is NULL");
+  const size_t elt = dtype == TO_C64 ? sizeof(cx<float>) : sizeof(cx<double>);
+  const size_t sb = (size_t)batch * (adjoint ? pout : pin) * elt, db = (size_t)batch * (adjoint ? pin : pout) * elt;
+  if (overlaps(span(src, sb), span(dst, db))) return fail(TO_E_INVAL, "src and dst overlap");
+  auto axis = [](int n_in, double d_in, double o_in, int n_out, double d_out, double o_out) {
+    AxisMap m;
+    m.n_in = n_in;
+    m.n_out = n_out;
+    m.half_in = n_in / 2;
+    m.half_out = n_out / 2;
+    m.ratio = d_out / d_in;
+    m.shift = (o_out - o_in) / d_in;
+    return m;
+  };
+  const AxisMap ay = axis(grid_in->ny, grid_in->dy, grid_in->y0, grid_out->ny, grid_out->dy, grid_out->y0);
+  const AxisMap ax = axis(grid_in->nx, grid_in->dx, grid_in->x0, grid_out->nx, grid_out->dx, grid_out->x0);
+  hipStream_t s = (hipStream_t)stream;
+  const bool dbl = dtype == TO_C128;
+  hipError_t e = timed(adjoint ? "resample_adjoint" : "resample", 0, dbl, s, [&] {
+    return dbl ? Resample<double>::run((const cx<double>*)src, (cx<double>*)dst, batch, ay, ax, interp, adjoint != 0, s)
+               : Resample<float>::run((const cx<float>*)src, (cx<float>*)dst, batch, ay, ax, interp, adjoint != 0, s);
+  });
+  return e == hipSuccess ? TO_OK : hip_fail(e, "resample");
 }
 
 to_status to_resolve_method(const to_job* job, int32_t* method) {

@@ -150,6 +150,56 @@ def test_missing_library_fails_loudly(capi, monkeypatch, tmp_path):
         capi.lib()
 
 
+def test_grid_layout_matches_header(capi):
+    src = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){",
+           'printf("%zu", sizeof(to_grid));']
+    for f, _ in capi.Grid._fields_:
+        src.append(f'printf(" %zu", offsetof(to_grid, {f}));')
+    src.append("return 0;}")
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "grid.c")
+        exe = os.path.join(d, "grid")
+        open(c, "w").write("\n".join(src))
+        subprocess.check_call(["gcc", "-std=c11", "-o", exe, c])
+        vals = [int(x) for x in subprocess.check_output([exe]).decode().split()]
+    assert vals[0] == ctypes.sizeof(capi.Grid)
+    assert vals[1:] == [getattr(capi.Grid, f).offset for f, _ in capi.Grid._fields_]
+
+
+def _grid(capi, ny=8, nx=9, dy=1e-6, dx=2e-6):
+    g = capi.Grid()
+    g.ny, g.nx, g.dy, g.dx = ny, nx, dy, dx
+    return g
+
+
+@pytest.mark.parametrize("case,status", [
+    (dict(gin=None), "TO_E_INVAL"),
+    (dict(interp=5), "TO_E_INVAL"),
+    (dict(batch=-1), "TO_E_INVAL"),
+    (dict(dtype=7), "TO_E_INVAL"),
+    (dict(gin_ny=0), "TO_E_INVAL"),
+    (dict(gout_dx=0.0), "TO_E_INVAL"),
+    (dict(gout_dy=float("nan")), "TO_E_INVAL"),
+    (dict(src=None), "TO_E_INVAL"),
+    (dict(dst=0x1000 + 64), "TO_E_INVAL"),   # overlaps src
+    (dict(batch=0, src=None, dst=None), "TO_OK"),
+])
+def test_resample_validation(capi, case, status):
+    gin, gout = _grid(capi), _grid(capi, 5, 6, 1.5e-6, 2.5e-6)
+    if "gin_ny" in case:
+        gin.ny = case["gin_ny"]
+    if "gout_dx" in case:
+        gout.dx = case["gout_dx"]
+    if "gout_dy" in case:
+        gout.dy = case["gout_dy"]
+    src = case.get("src", 0x1000)
+    dst = case.get("dst", 0x9000000)
+    gp = None if case.get("gin", 1) is None else ctypes.byref(gin)
+    rc = capi.lib().to_resample(src, dst, gp, ctypes.byref(gout), case.get("batch", 2), case.get("interp", 1), 0,
+                                case.get("dtype", capi.TO_C64), None)
+    assert rc == getattr(capi, status)
+
+
 def _resolve(capi, j):
     m = ctypes.c_int32(-1)
     rc = capi.lib().to_resolve_method(ctypes.byref(j), ctypes.byref(m))
