@@ -103,6 +103,8 @@ struct DeviceCtx {
   size_t di_bytes = 0;
   void* sep = nullptr;    // separable complex64 transfer-function tables of a call
   size_t sep_bytes = 0;
+  void* rs = nullptr;     // per-axis tables of a resampling call
+  size_t rs_bytes = 0;
 };
 
 std::mutex g_mutex;
@@ -1921,6 +1923,7 @@ to_status to_release(void) {
     if (c.coh) note(hipFree(c.coh));
     if (c.di) note(hipFree(c.di));
     if (c.sep) note(hipFree(c.sep));
+    if (c.rs) note(hipFree(c.rs));
     c = DeviceCtx();
   }
   note(hipSetDevice(cur));
@@ -1987,11 +1990,18 @@ to_status to_resample(const void* src, void* dst, const to_grid* grid_in, const 
   };
   const AxisMap ay = axis(grid_in->ny, grid_in->dy, grid_in->y0, grid_out->ny, grid_out->dy, grid_out->y0);
   const AxisMap ax = axis(grid_in->nx, grid_in->dx, grid_in->x0, grid_out->nx, grid_out->dx, grid_out->x0);
+  DeviceCtx* c;
+  to_status st = get_ctx(&c);
+  if (st != TO_OK) return st;
+  if ((st = ensure_area(&c->rs, &c->rs_bytes, resample_table_bytes(ay, ax), "resampling tables")) != TO_OK)
+    return st;
   hipStream_t s = (hipStream_t)stream;
   const bool dbl = dtype == TO_C128;
   hipError_t e = timed(adjoint ? "resample_adjoint" : "resample", 0, dbl, s, [&] {
-    return dbl ? Resample<double>::run((const cx<double>*)src, (cx<double>*)dst, batch, ay, ax, interp, adjoint != 0, s)
-               : Resample<float>::run((const cx<float>*)src, (cx<float>*)dst, batch, ay, ax, interp, adjoint != 0, s);
+    return dbl ? Resample<double>::run((const cx<double>*)src, (cx<double>*)dst, batch, ay, ax, interp, adjoint != 0,
+                                       c->rs, s)
+               : Resample<float>::run((const cx<float>*)src, (cx<float>*)dst, batch, ay, ax, interp, adjoint != 0,
+                                      c->rs, s);
   });
   return e == hipSuccess ? TO_OK : hip_fail(e, "resample");
 }

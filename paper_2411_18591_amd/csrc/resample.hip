@@ -16,9 +16,12 @@
 // The adjoint (the weights are real: the transpose) is a gather, one thread
 // per input sample: it visits the output samples whose stencil can contain
 // it (a range of each axis found by inverting t, widened by one sample on
-// each side) and recomputes their t exactly as the forward map does, so
-// forward and adjoint agree on every weight; no atomics, fixed order.
+// each side) and takes their weights from the same tap tables the forward
+// map uses, so forward and adjoint agree on every weight; no atomics, fixed
+// order.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "resample.hpp"
 
@@ -30,132 +33,170 @@ __device__ __forceinline__ double frac_index(int j, const AxisMap& m) {
   return __dadd_rn(__dadd_rn(__dmul_rn((double)(j - m.half_out), m.ratio), m.shift), (double)m.half_in);
 }
 
-// Taps of output sample j along one axis: up to two (index, weight) pairs.
-__device__ __forceinline__ int axis_taps(int j, const AxisMap& m, int mode, int* idx, double* w) {
-  // far outside the input window every tap is out of range: clamping keeps
-  // the integer conversion defined without changing which taps are inside
-  const double t = fmin(fmax(frac_index(j, m), -4.0), (double)m.n_in + 4.0);
-  if (mode == 0) {
-    idx[0] = (int)floor(__dadd_rn(t, 0.5));
-    w[0] = 1.0;
-    return 1;
+// Fractional index clamped to [-4, n_in + 4]: far outside the input window
+// every tap is out of range, and the clamp keeps the integer conversion
+// defined without changing which taps are inside.
+__device__ __forceinline__ double clamped_index(int j, const AxisMap& m) {
+  return fmin(fmax(frac_index(j, m), -4.0), (double)m.n_in + 4.0);
+}
+
+// First tap index of output sample j (nondecreasing in j).
+__device__ __forceinline__ int first_tap(int j, const AxisMap& m, int mode) {
+  const double t = clamped_index(j, m);
+  return (int)floor(mode == 0 ? __dadd_rn(t, 0.5) : t);
+}
+
+// Smallest j in [0, n_out] with first_tap(j) >= v (n_out if none).
+__device__ __forceinline__ int lower_bound_tap(int v, const AxisMap& m, int mode) {
+  int lo = 0, hi = m.n_out;
+  while (lo < hi) {
+    const int mid = lo + (hi - lo) / 2;
+    if (first_tap(mid, m, mode) >= v)
+      hi = mid;
+    else
+      lo = mid + 1;
   }
-  const double f = floor(t);
-  const double a = __dadd_rn(t, -f);
-  idx[0] = (int)f;
-  w[0] = __dadd_rn(1.0, -a);
-  idx[1] = (int)f + 1;
-  w[1] = a;
-  return 2;
-}
-
-// Weight of input index i in output sample j's stencil (0 if absent).
-__device__ __forceinline__ double axis_weight(int j, int i, const AxisMap& m, int mode) {
-  int idx[2];
-  double w[2];
-  const int k = axis_taps(j, m, mode, idx, w);
-  double r = 0.0;
-  for (int q = 0; q < k; ++q)
-    if (idx[q] == i) r = w[q];
-  return r;
-}
-
-// Output samples whose stencil may contain input index i: [lo, hi].
-__device__ __forceinline__ void axis_range(int i, const AxisMap& m, int* lo, int* hi) {
-  const double a = (double)(i - 1 - m.half_in) - m.shift;
-  const double b = (double)(i + 1 - m.half_in) - m.shift;
-  double jl = floor(a / m.ratio) + m.half_out - 1;
-  double jh = ceil(b / m.ratio) + m.half_out + 1;
-  jl = jl < 0 ? 0 : jl;
-  jh = jh > m.n_out - 1 ? m.n_out - 1 : jh;
-  *lo = (int)jl;
-  *hi = (int)jh;
+  return lo;
 }
 
 }  // namespace
 
+// Per-axis tables, built once per call: the taps of every output sample
+// (index i0 and weights w0, w1 of samples i0 and i0 + 1; nearest: w1 = 0),
+// and for every input sample i the range of output samples whose taps
+// include it: those with i0 in [i - 1, i] (bilinear) or i0 = i (nearest),
+// found by binary search since i0 does not decrease with the output index.
+template <typename W>
+__global__ void __launch_bounds__(256) resample_tables_kernel(AxisMap ay, AxisMap ax, int mode, AxisTap<W>* tap_y,
+                                                              AxisTap<W>* tap_x, AxisRange* rng_y, AxisRange* rng_x) {
+  const AxisMap& m = blockIdx.y == 0 ? ay : ax;
+  AxisTap<W>* tap = blockIdx.y == 0 ? tap_y : tap_x;
+  AxisRange* rng = blockIdx.y == 0 ? rng_y : rng_x;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m.n_out) {
+    const double t = clamped_index(e, m);
+    AxisTap<W> a;
+    if (mode == 0) {
+      a.i0 = (int)floor(__dadd_rn(t, 0.5));
+      a.w0 = W(1);
+      a.w1 = W(0);
+    } else {
+      const double f = floor(t);
+      const double fr = __dadd_rn(t, -f);
+      a.i0 = (int)f;
+      a.w0 = (W)__dadd_rn(1.0, -fr);
+      a.w1 = (W)fr;
+    }
+    tap[e] = a;
+  } else if (e < m.n_out + m.n_in) {
+    const int i = e - m.n_out;
+    AxisRange r;
+    r.lo = lower_bound_tap(mode == 0 ? i : i - 1, m, mode);
+    r.hi = lower_bound_tap(i + 1, m, mode) - 1;
+    rng[i] = r;
+  }
+}
+
+// Forward: a workgroup per output row q (and a share of the fields); the
+// row's taps are uniform over the workgroup, the columns' taps are coalesced
+// table reads.
 template <typename T>
 __global__ void __launch_bounds__(256) resample_kernel(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
-                                                       int64_t batch, AxisMap ay, AxisMap ax, int mode) {
-  const int64_t plane_out = (int64_t)ay.n_out * ax.n_out;
-  const int64_t plane_in = (int64_t)ay.n_in * ax.n_in;
-  const int64_t total = batch * plane_out;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = e / plane_out;
-    const int64_t p = e - b * plane_out;
-    const int q = (int)(p / ax.n_out), r = (int)(p - (int64_t)q * ax.n_out);
-    int iy[2], ix[2];
-    double wy[2], wx[2];
-    const int ky = axis_taps(q, ay, mode, iy, wy);
-    const int kx = axis_taps(r, ax, mode, ix, wx);
-    const cx<T>* s = src + b * plane_in;
-    cx<T> acc = {T(0), T(0)};
-    for (int u = 0; u < ky; ++u) {
-      if (iy[u] < 0 || iy[u] >= ay.n_in) continue;
-      for (int v = 0; v < kx; ++v) {
-        if (ix[v] < 0 || ix[v] >= ax.n_in) continue;
-        const T w = (T)(wy[u] * wx[v]);
-        const cx<T> val = s[(int64_t)iy[u] * ax.n_in + ix[v]];
-        acc.x += w * val.x;
-        acc.y += w * val.y;
+                                                       int64_t batch, int ny, int nx, int my, int mx,
+                                                       const AxisTap<double>* __restrict__ tap_y,
+                                                       const AxisTap<double>* __restrict__ tap_x) {
+  const int q = blockIdx.x;
+  const AxisTap<double> ty = tap_y[q];
+  const int iy[2] = {ty.i0, ty.i0 + 1};
+  const double wy[2] = {ty.w0, ty.w1};
+  for (int r = threadIdx.x; r < mx; r += blockDim.x) {
+    const AxisTap<double> tx = tap_x[r];
+    const int ix[2] = {tx.i0, tx.i0 + 1};
+    const double wx[2] = {tx.w0, tx.w1};
+    for (int64_t b = blockIdx.y; b < batch; b += gridDim.y) {
+      const cx<T>* s = src + b * ((int64_t)ny * nx);
+      cx<T> acc = {T(0), T(0)};
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (iy[u] < 0 || iy[u] >= ny) continue;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          if (ix[v] < 0 || ix[v] >= nx) continue;
+          const T w = (T)(wy[u] * wx[v]);
+          const cx<T> val = s[(int64_t)iy[u] * nx + ix[v]];
+          acc.x += w * val.x;
+          acc.y += w * val.y;
+        }
       }
+      dst[b * ((int64_t)my * mx) + (int64_t)q * mx + r] = acc;
     }
-    dst[e] = acc;
   }
 }
 
+__device__ __forceinline__ double tap_weight(const AxisTap<double>& t, int i) {
+  return t.i0 == i ? t.w0 : (t.i0 + 1 == i ? t.w1 : 0.0);
+}
+
+// Adjoint: a workgroup per input row i (and a share of the fields); a
+// gather over the output samples whose taps include (i, k), in a fixed
+// order.
 template <typename T>
 __global__ void __launch_bounds__(256) resample_adjoint_kernel(const cx<T>* __restrict__ src,
-                                                               cx<T>* __restrict__ dst, int64_t batch,
-                                                               AxisMap ay, AxisMap ax, int mode) {
-  const int64_t plane_out = (int64_t)ay.n_out * ax.n_out;
-  const int64_t plane_in = (int64_t)ay.n_in * ax.n_in;
-  const int64_t total = batch * plane_in;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = e / plane_in;
-    const int64_t p = e - b * plane_in;
-    const int i = (int)(p / ax.n_in), k = (int)(p - (int64_t)i * ax.n_in);
-    int qlo, qhi, rlo, rhi;
-    axis_range(i, ay, &qlo, &qhi);
-    axis_range(k, ax, &rlo, &rhi);
-    const cx<T>* g = src + b * plane_out;
+                                                               cx<T>* __restrict__ dst, int64_t batch, int ny,
+                                                               int nx, int my, int mx,
+                                                               const AxisTap<double>* __restrict__ tap_y,
+                                                               const AxisTap<double>* __restrict__ tap_x,
+                                                               const AxisRange* __restrict__ rng_y,
+                                                               const AxisRange* __restrict__ rng_x) {
+  const int i = blockIdx.x;
+  const AxisRange ry = rng_y[i];
+  for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+  const AxisRange rx = rng_x[k];
+  for (int64_t b = blockIdx.y; b < batch; b += gridDim.y) {
+    const cx<T>* g = src + b * ((int64_t)my * mx);
     cx<T> acc = {T(0), T(0)};
-    for (int q = qlo; q <= qhi; ++q) {
-      const double wy = axis_weight(q, i, ay, mode);
+    for (int q = ry.lo; q <= ry.hi; ++q) {
+      const double wy = tap_weight(tap_y[q], i);
       if (wy == 0.0) continue;
-      for (int r = rlo; r <= rhi; ++r) {
-        const double wx = axis_weight(r, k, ax, mode);
+      for (int r = rx.lo; r <= rx.hi; ++r) {
+        const double wx = tap_weight(tap_x[r], k);
         if (wx == 0.0) continue;
         const T w = (T)(wy * wx);
-        const cx<T> val = g[(int64_t)q * ax.n_out + r];
+        const cx<T> val = g[(int64_t)q * mx + r];
         acc.x += w * val.x;
         acc.y += w * val.y;
       }
     }
-    dst[e] = acc;
+    dst[b * ((int64_t)ny * nx) + (int64_t)i * nx + k] = acc;
+  }
   }
 }
 
-namespace {
-int resample_grid(int64_t n) {
-  int64_t b = (n + 255) / 256;
-  return (int)(b > 65536 ? 65536 : (b < 1 ? 1 : b));
+size_t resample_table_bytes(const AxisMap& ay, const AxisMap& ax) {
+  return (size_t)(ay.n_out + ax.n_out) * sizeof(AxisTap<double>) + (size_t)(ay.n_in + ax.n_in) * sizeof(AxisRange);
 }
-}  // namespace
 
 template <typename T>
 hipError_t Resample<T>::run(const cx<T>* src, cx<T>* dst, int64_t batch, const AxisMap& ay, const AxisMap& ax,
-                            int mode, bool adjoint, hipStream_t s) {
+                            int mode, bool adjoint, void* tables, hipStream_t s) {
+  AxisTap<double>* tap_y = static_cast<AxisTap<double>*>(tables);
+  AxisTap<double>* tap_x = tap_y + ay.n_out;
+  AxisRange* rng_y = reinterpret_cast<AxisRange*>(tap_x + ax.n_out);
+  AxisRange* rng_x = rng_y + ay.n_in;
+  const int tn = std::max(ay.n_out + ay.n_in, ax.n_out + ax.n_in);
+  hipLaunchKernelGGL((resample_tables_kernel<double>), dim3((tn + 255) / 256, 2), dim3(256), 0, s, ay, ax, mode,
+                     tap_y, tap_x, rng_y, rng_x);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // rows x field shares: enough workgroups to fill the GPU several times
+  const int rows = adjoint ? ay.n_in : ay.n_out;
+  const int zb = (int)std::max<int64_t>(1, std::min<int64_t>(batch, (16384 + rows - 1) / rows));
   if (adjoint) {
-    const int64_t n = batch * ay.n_in * ax.n_in;
-    hipLaunchKernelGGL((resample_adjoint_kernel<T>), dim3(resample_grid(n)), dim3(256), 0, s, src, dst, batch, ay,
-                       ax, mode);
+    hipLaunchKernelGGL((resample_adjoint_kernel<T>), dim3(ay.n_in, zb), dim3(256), 0, s, src, dst, batch, ay.n_in,
+                       ax.n_in, ay.n_out, ax.n_out, tap_y, tap_x, rng_y, rng_x);
   } else {
-    const int64_t n = batch * ay.n_out * ax.n_out;
-    hipLaunchKernelGGL((resample_kernel<T>), dim3(resample_grid(n)), dim3(256), 0, s, src, dst, batch, ay, ax,
-                       mode);
+    hipLaunchKernelGGL((resample_kernel<T>), dim3(ay.n_out, zb), dim3(256), 0, s, src, dst, batch, ay.n_in,
+                       ax.n_in, ay.n_out, ax.n_out, tap_y, tap_x);
   }
   return hipGetLastError();
 }
