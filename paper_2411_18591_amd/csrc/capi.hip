@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/toprop.h"
+#include "accum.hpp"
 #include "coherence.hpp"
 #include "launch.hpp"
 #include "plain.hpp"
@@ -105,6 +106,8 @@ struct DeviceCtx {
   size_t sep_bytes = 0;
   void* rs = nullptr;     // per-axis tables of a resampling call
   size_t rs_bytes = 0;
+  void* acc = nullptr;    // private intensity accumulators of the lanes of a call
+  size_t acc_bytes = 0;
 };
 
 std::mutex g_mutex;
@@ -1060,15 +1063,32 @@ void workspace_need(const to_job& j, bool backward, size_t* scratch_bytes, size_
   if (backward && (j.el_flags & TO_EL_LENS)) *partial_count = (size_t)j.ny;
 }
 
+// An accumulation into a shared real array by the intensity epilogue of
+// job `job` (an index into the call's prepared jobs) of scheduling unit
+// `unit`.
+struct AccUse {
+  int unit;
+  int job;
+  Span span;
+};
+
+bool same_span(const Span& a, const Span& b) { return a.lo == b.lo && a.hi == b.hi; }
+
 // Runs jobs 0..n-1.  Jobs whose written ranges overlap another job's read or
 // written ranges form one group and stay in call order on one lane; groups
 // are assigned longest-first to the least-loaded lane.  Lane 0 is the
 // caller's stream; the other lanes fork from it and join back with events,
 // so the whole call can be captured in a hipGraph.
+// Accumulations (`acc`) into the same array do not conflict with each
+// other: when they land on several lanes, every lane but the lowest
+// accumulates into a private zeroed copy (its jobs' epi_out is redirected
+// in `jobs`), and the copies are added into the array in lane order after
+// the join.  `elt` is the array's element size.
 template <typename Run, typename Need>
 to_status run_on_lanes(DeviceCtx* c, hipStream_t s, int n, const std::vector<std::vector<Span>>& rd,
                        const std::vector<std::vector<Span>>& wr, const std::vector<double>& cost, Run&& run,
-                       Need&& need) {
+                       Need&& need, const std::vector<AccUse>* acc = nullptr, to_job* jobs = nullptr,
+                       size_t elt = 0) {
   // union-find over conflicting jobs
   std::vector<int> parent(n);
   for (int i = 0; i < n; ++i) parent[i] = i;
@@ -1076,6 +1096,9 @@ to_status run_on_lanes(DeviceCtx* c, hipStream_t s, int n, const std::vector<std
     while (parent[i] != i) i = parent[i] = parent[parent[i]];
     return i;
   };
+  std::vector<std::vector<Span>> accs(n);
+  if (acc)
+    for (const AccUse& a : *acc) accs[a.unit].push_back(a.span);
   for (int i = 0; i < n; ++i)
     for (int k = i + 1; k < n; ++k) {
       bool conflict = false;
@@ -1085,6 +1108,17 @@ to_status run_on_lanes(DeviceCtx* c, hipStream_t s, int n, const std::vector<std
       }
       for (const Span& w : wr[k])
         for (const Span& r : rd[i]) conflict |= overlaps(w, r);
+      // accumulations: against everything else as writes; against each
+      // other only when they overlap without being the same array
+      for (int side = 0; side < 2; ++side) {
+        const int a = side ? k : i, b = side ? i : k;
+        for (const Span& w : accs[a]) {
+          for (const Span& r : rd[b]) conflict |= overlaps(w, r);
+          for (const Span& r : wr[b]) conflict |= overlaps(w, r);
+        }
+      }
+      for (const Span& x : accs[i])
+        for (const Span& y : accs[k]) conflict |= overlaps(x, y) && !same_span(x, y);
       if (conflict) parent[find(i)] = find(k);
     }
   std::vector<int> root(n);
@@ -1111,6 +1145,54 @@ to_status run_on_lanes(DeviceCtx* c, hipStream_t s, int n, const std::vector<std
     }
     for (int i = 0; i < n; ++i) lane_of[i] = glane[root[i]];
   }
+  // private accumulators: per distinct array, every lane using it but the
+  // lowest gets a zeroed copy
+  struct Private {
+    int lane;
+    Span target;
+    size_t offset;
+  };
+  std::vector<Private> privs;
+  size_t priv_total = 0;
+  if (acc && nl > 1) {
+    std::vector<Span> arrays;
+    for (const AccUse& a : *acc) {
+      bool seen = false;
+      for (const Span& x : arrays) seen |= same_span(x, a.span);
+      if (!seen) arrays.push_back(a.span);
+    }
+    for (const Span& arr : arrays) {
+      int lo_lane = kLanes;
+      for (const AccUse& a : *acc)
+        if (same_span(a.span, arr)) lo_lane = std::min(lo_lane, lane_of[a.unit]);
+      for (int l = lo_lane + 1; l < nl; ++l) {
+        bool used = false;
+        for (const AccUse& a : *acc) used |= same_span(a.span, arr) && lane_of[a.unit] == l;
+        if (!used) continue;
+        privs.push_back({l, arr, priv_total});
+        priv_total += ((size_t)(arr.hi - arr.lo) + 255) & ~(size_t)255;
+      }
+    }
+  }
+  if (!privs.empty()) {
+    to_status st = ensure_area(&c->acc, &c->acc_bytes, priv_total, "private accumulators");
+    if (st != TO_OK) return st;
+    for (const AccUse& a : *acc)
+      for (const Private& p : privs)
+        if (p.lane == lane_of[a.unit] && same_span(p.target, a.span)) jobs[a.job].epi_out = (char*)c->acc + p.offset;
+  }
+  auto accum_zero = [&](const Private& p, hipStream_t ls) {
+    const int64_t cnt = (int64_t)((p.target.hi - p.target.lo) / elt);
+    void* ptr = (char*)c->acc + p.offset;
+    return elt == sizeof(double) ? Accum<double>::zero((double*)ptr, cnt, ls) : Accum<float>::zero((float*)ptr, cnt, ls);
+  };
+  auto accum_add = [&](const Private& p) {
+    const int64_t cnt = (int64_t)((p.target.hi - p.target.lo) / elt);
+    const void* ptr = (char*)c->acc + p.offset;
+    void* dst = (void*)p.target.lo;
+    return elt == sizeof(double) ? Accum<double>::add((double*)dst, (const double*)ptr, cnt, s)
+                                 : Accum<float>::add((float*)dst, (const float*)ptr, cnt, s);
+  };
   // size every lane's workspace before anything is enqueued
   for (int l = 0; l < nl || l == 0; ++l) {
     size_t sb = 0, pc = 0;
@@ -1133,6 +1215,9 @@ to_status run_on_lanes(DeviceCtx* c, hipStream_t s, int n, const std::vector<std
         return hip_fail(e, "hipStreamWaitEvent");
   }
   to_status result = TO_OK;
+  for (const Private& p : privs)
+    if (result == TO_OK && (e = accum_zero(p, c->lane[p.lane].stream)) != hipSuccess)
+      result = hip_fail(e, "accumulator reset");
   for (int i = 0; i < n && result == TO_OK; ++i) {
     const int l = lane_of[i];
     result = run(i, &c->lane[l], l == 0 ? s : c->lane[l].stream);
@@ -1143,6 +1228,8 @@ to_status run_on_lanes(DeviceCtx* c, hipStream_t s, int n, const std::vector<std
       if ((e = hipStreamWaitEvent(s, c->lane[l].done, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
     }
   }
+  for (const Private& p : privs)  // in lane order: deterministic
+    if (result == TO_OK && (e = accum_add(p)) != hipSuccess) result = hip_fail(e, "accumulator combine");
   return result;
 }
 
@@ -1613,6 +1700,8 @@ to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* 
   const int nu = (int)ubeg.size();
   std::vector<std::vector<Span>> rd(nu), wr(nu);
   std::vector<double> cost(nu, 0.0);
+  std::vector<AccUse> acc;
+  const size_t relt = dtype == TO_C64 ? sizeof(float) : sizeof(double);
   for (int u = 0; u < nu; ++u) {
     for (int i = ubeg[u]; i < ubeg[u] + ulen[u]; ++i) {
       const to_job& j = jobs[i];
@@ -1624,8 +1713,8 @@ to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* 
         wr[u].push_back(span(j.epi_grad, fb));
         wr[u].push_back(span(j.epi_loss, sizeof(double)));
       }
-      if (j.epi == TO_EPI_INTENSITY)
-        wr[u].push_back(span(j.epi_out, (size_t)j.batch * j.ny * j.nx * (dtype == TO_C64 ? 4 : 8)));
+      if (j.epi == TO_EPI_INTENSITY && j.batch > 0)
+        acc.push_back({u, i, span(j.epi_out, (size_t)j.batch * j.ny * j.nx * relt)});
       cost[u] += job_cost(j);
     }
   }
@@ -1649,7 +1738,7 @@ to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* 
       *pc = std::max(*pc, b);
     }
   };
-  return run_on_lanes(c, s, nu, rd, wr, cost, run, need);
+  return run_on_lanes(c, s, nu, rd, wr, cost, run, need, &acc, prepared.data(), relt);
 }
 
 to_status to_modulate(const to_job* jobs, int32_t njobs, to_dtype dtype, int32_t adjoint,
@@ -1924,6 +2013,7 @@ to_status to_release(void) {
     if (c.di) note(hipFree(c.di));
     if (c.sep) note(hipFree(c.sep));
     if (c.rs) note(hipFree(c.rs));
+    if (c.acc) note(hipFree(c.acc));
     c = DeviceCtx();
   }
   note(hipSetDevice(cur));

@@ -103,23 +103,50 @@ def test_fresnel_4f_inverts_the_image(dtype):
 
 def test_paper_scale_spectrum():
     """1000^2 (padded 2048^2), 251 wavelengths, FWHM 10 nm, AS: the one-call
-    image equals one call per wavelength accumulating in the same order
-    (bitwise); a three-line spectrum against the oracle."""
+    image with one set of buffers (call-order sum) equals one call per
+    wavelength bitwise; with four sets (chains concurrent on the lanes,
+    private accumulators combined in lane order) it is deterministic
+    (bitwise over repeats) and equal to the call-order sum to rounding; a
+    three-line spectrum against the oracle."""
     FourF = _fourf()
     announce("4f 1000^2 x 251 wavelengths")
     wl = workloads.Polychromatic4fWorkload()
     u = to_gpu(wl.field(), torch)
     sys = FourF(wl.f, wl.d, wl.d, method="asm")
     lams, wts = wl.wavelengths(), wl.weights()
-    I = sys.image(u, lams, wts)
-    I2 = torch.zeros_like(I)
+    I1 = sys.image(u, lams, wts, sets=1)
+    I2 = torch.zeros_like(I1)
     for lam, w in zip(lams, wts):
         sys.image(u, [lam], [w], out=I2)
+    I = sys.image(u, lams, wts)
+    Ib = sys.image(u, lams, wts)
     torch.cuda.synchronize()
-    assert torch.equal(I, I2)
+    assert torch.equal(I1, I2)
+    assert torch.equal(I, Ib)
+    assert rel(to_np(I), to_np(I1)) <= 1e-6
     assert float(I.min()) >= 0.0 and float(I.sum()) > 0.0
     pick = [100, 125, 150]
     I3 = sys.image(u, lams[pick], [0.2, 0.5, 0.3])
     torch.cuda.synchronize()
     exp = _oracle_image(wl.field().astype(np.complex128), wl.d, wl.f, lams[pick], [0.2, 0.5, 0.3], oracle.ASM)
     assert rel(to_np(I3), exp) <= 4e-5
+
+
+def test_cached_di_tables_give_the_same_image():
+    """With the DI tables kept by the system (built once by
+    to_transfer_table), images equal the per-call-table images bitwise."""
+    FourF = _fourf()
+    announce("4f cached DI tables")
+    rng = np.random.default_rng(992)
+    ny, nx, d = 48, 40, 10e-6
+    wl = workloads.Polychromatic4fWorkload(count=7, fwhm=40e-9)
+    lams, wts = wl.wavelengths(), wl.weights()
+    f = 2.0 * max(oracle.critical_distance(ny, nx, d, d, lam) for lam in lams)
+    u = to_gpu(crandn(rng, 2, ny, nx, dtype=np.complex64), torch)
+    a = FourF(f, d, d, method="auto").image(u, lams, wts)
+    cached = FourF(f, d, d, method="auto", cache_tables=True)
+    b = cached.image(u, lams, wts)
+    c = cached.image(u, lams, wts)
+    torch.cuda.synchronize()
+    assert len(cached._tables) == 2 * len(lams)
+    assert torch.equal(a, b) and torch.equal(b, c)
