@@ -142,7 +142,7 @@ def coords(n: int, d: float, offset: float = 0.0) -> np.ndarray:
 def fftfreq(n: int, d: float) -> np.ndarray:
     """Spatial frequency (cycles/m) of each DFT bin, FFT order."""
     k = np.arange(n)
-    k = np.where(k < n // 2, k, k - n)
+    k = np.where(2 * k < n, k, k - n)
     return k / (n * float(d))
 
 
@@ -179,7 +179,7 @@ def di_transfer(ny: int, nx: int, py: int, px: int, dy: float, dx: float, wavele
     brute-force sum :func:`rs_direct`."""
     H = np.empty((py, px), dtype=np.complex128)
     if _load().orc_di_transfer(_ptr(H), ny, nx, py, px, dy, dx, wavelength, z) != 0:
-        raise ValueError("DI needs power-of-two padded extents with py >= 2 ny - 1, px >= 2 nx - 1")
+        raise ValueError("DI needs padded extents py >= 2 ny - 1, px >= 2 nx - 1")
     return H
 
 
@@ -219,7 +219,8 @@ def propagate(u, dy: float, dx: float, wavelength: float, z: float, method: int 
 
     With ``method=DI`` the transfer function is :func:`di_transfer` (the
     padding must then reach 2 n - 1 per axis): the result is the discrete
-    Rayleigh-Sommerfeld sum of Eq. (field_propagation).
+    Rayleigh-Sommerfeld sum of Eq. (field_propagation).  Padded extents that
+    are not powers of two take the naive DFT (small grids only).
 
     Pinned by: explicit circular convolution, plane-wave eigenfunction, z=0
     identity, adjoint identity, Parseval, pad-placement invariance, group
@@ -239,12 +240,14 @@ def propagate(u, dy: float, dx: float, wavelength: float, z: float, method: int 
     return out
 
 
-def propagate_offset(u, dy, dx, wavelength, z, method, pad, oy, ox) -> np.ndarray:
-    """Propagation with the field at window offset (oy, ox) in the padded grid."""
+def propagate_offset(u, dy, dx, wavelength, z, method, pad, oy, ox, padded=None) -> np.ndarray:
+    """Propagation with the field at window offset (oy, ox) in the padded grid
+    (``pad`` times the field, or the explicit ``padded`` = (py, px))."""
     u = _c128(u)
     ny, nx = u.shape
     out = np.empty_like(u)
-    if _load().orc_propagate_offset(_ptr(u), _ptr(out), ny, nx, pad * ny, pad * nx, oy, ox, dy, dx,
+    py, px = padded_shape(ny, nx, pad, padded)
+    if _load().orc_propagate_offset(_ptr(u), _ptr(out), ny, nx, py, px, oy, ox, dy, dx,
                                     wavelength, z, method) != 0:
         raise ValueError("bad offset")
     return out

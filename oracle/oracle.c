@@ -127,15 +127,47 @@ int orc_fft2(cplx *a, long ny, long nx, int sign)
     return 0;
 }
 
+/* In-place 1-D transform of any length: the radix-2 FFT for powers of two,
+ * the naive DFT (integer-reduced long-double angles) otherwise. */
+static void dft_any(cplx *x, long n, int sign, cplx *tmp)
+{
+    if (is_pow2(n)) {
+        orc_fft(x, n, sign);
+        return;
+    }
+    orc_dft(x, tmp, n, sign);
+    memcpy(x, tmp, sizeof(cplx) * (size_t)n);
+}
+
+/* 2-D transform of a row-major ny x nx array of any extents (rows, then
+ * columns).  Non-power-of-two extents take O(n^2) per line: small grids. */
+int orc_dft2_any(cplx *a, long ny, long nx, int sign)
+{
+    if (ny < 1 || nx < 1) return -1;
+    long m = ny > nx ? ny : nx;
+    cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)m);
+    cplx *col = (cplx *)malloc(sizeof(cplx) * (size_t)ny);
+    for (long r = 0; r < ny; ++r) dft_any(a + r * nx, nx, sign, tmp);
+    for (long c = 0; c < nx; ++c) {
+        for (long r = 0; r < ny; ++r) col[r] = a[r * nx + c];
+        dft_any(col, ny, sign, tmp);
+        for (long r = 0; r < ny; ++r) a[r * nx + c] = col[r];
+    }
+    free(col);
+    free(tmp);
+    return 0;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Transfer functions                                                      */
 /* ---------------------------------------------------------------------- */
 
 /* Spatial frequency of DFT bin k on a length-n grid of spacing d, in cycles
- * per metre, with numpy's fftfreq ordering (bins n/2 .. n-1 are negative). */
+ * per metre, with numpy's fftfreq ordering (bins with 2k >= n are negative,
+ * which for odd n keeps bin (n-1)/2 positive). */
 static long double freq_of_bin(long k, long n, double d)
 {
-    long ks = (k < n / 2) ? k : k - n;
+    long ks = (2 * k < n) ? k : k - n;
     return (long double)ks / ((long double)n * (long double)d);
 }
 
@@ -207,11 +239,11 @@ static cplx impulse_response(long double oy, long double ox, double lam, double 
 int orc_di_transfer(cplx *H, long ny, long nx, long py, long px, double dy, double dx, double lam,
                     double z)
 {
-    if (py < 2 * ny - 1 || px < 2 * nx - 1 || !is_pow2(py) || !is_pow2(px)) return -1;
+    if (py < 2 * ny - 1 || px < 2 * nx - 1) return -1;
     for (long ky = 0; ky < py; ++ky) {
-        long sy = (ky < py / 2) ? ky : ky - py;
+        long sy = (2 * ky < py) ? ky : ky - py;
         for (long kx = 0; kx < px; ++kx) {
-            long sx = (kx < px / 2) ? kx : kx - px;
+            long sx = (2 * kx < px) ? kx : kx - px;
             if (labs(sy) >= ny || labs(sx) >= nx) {
                 H[ky * px + kx] = 0.0;
                 continue;
@@ -219,7 +251,7 @@ int orc_di_transfer(cplx *H, long ny, long nx, long py, long px, double dy, doub
             H[ky * px + kx] = impulse_response((long double)sy * dy, (long double)sx * dx, lam, z) * dx * dy;
         }
     }
-    return orc_fft2(H, py, px, -1);
+    return orc_dft2_any(H, py, px, -1);
 }
 
 /* Transfer function of `method` for an ny x nx field on a py x px grid. */
@@ -256,22 +288,22 @@ static void propagate_one(const cplx *in, cplx *out, cplx *work, const cplx *H, 
     memset(work, 0, sizeof(cplx) * (size_t)(py * px));
     for (long r = 0; r < ny; ++r)
         memcpy(work + (r + oy) * px + ox, in + r * nx, sizeof(cplx) * (size_t)nx);
-    orc_fft2(work, py, px, -1);
+    orc_dft2_any(work, py, px, -1);
     for (long i = 0; i < py * px; ++i) work[i] *= adjoint ? conj(H[i]) : H[i];
-    orc_fft2(work, py, px, +1);
+    orc_dft2_any(work, py, px, +1);
     double scale = 1.0 / ((double)py * (double)px);
     for (long r = 0; r < ny; ++r)
         for (long c = 0; c < nx; ++c) out[r * nx + c] = work[(r + oy) * px + c + ox] * scale;
 }
 
 /* Batched propagation of `batch` contiguous ny x nx fields on a py x px
- * padded grid.  Returns -1 for an unsupported size (padded extents must be
- * powers of two no smaller than the field). */
+ * padded grid.  Returns -1 for an unsupported size (padded extents no
+ * smaller than the field; extents that are not powers of two use the naive
+ * DFT, so they are meant for small grids). */
 int orc_propagate(const cplx *in, cplx *out, long batch, long ny, long nx, long py, long px,
                   double dy, double dx, double lam, double z, int method, int adjoint)
 {
     if (ny < 1 || nx < 1 || py < ny || px < nx) return -1;
-    if (!is_pow2(py) || !is_pow2(px)) return -1;
     cplx *H = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
     if (method_transfer(H, ny, nx, py, px, dy, dx, lam, z, method) != 0) {
         free(H);
@@ -295,8 +327,7 @@ int orc_propagate(const cplx *in, cplx *out, long batch, long ny, long nx, long 
 int orc_propagate_offset(const cplx *in, cplx *out, long ny, long nx, long py, long px, long oy,
                          long ox, double dy, double dx, double lam, double z, int method)
 {
-    if (!is_pow2(py) || !is_pow2(px) || oy < 0 || ox < 0 || oy + ny > py || ox + nx > px)
-        return -1;
+    if (oy < 0 || ox < 0 || oy + ny > py || ox + nx > px) return -1;
     cplx *H = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
     cplx *work = (cplx *)calloc((size_t)(py * px), sizeof(cplx));
     if (method_transfer(H, ny, nx, py, px, dy, dx, lam, z, method) != 0) {
@@ -306,9 +337,9 @@ int orc_propagate_offset(const cplx *in, cplx *out, long ny, long nx, long py, l
     }
     for (long r = 0; r < ny; ++r)
         memcpy(work + (r + oy) * px + ox, in + r * nx, sizeof(cplx) * (size_t)nx);
-    orc_fft2(work, py, px, -1);
+    orc_dft2_any(work, py, px, -1);
     for (long i = 0; i < py * px; ++i) work[i] *= H[i];
-    orc_fft2(work, py, px, +1);
+    orc_dft2_any(work, py, px, +1);
     double scale = 1.0 / ((double)py * (double)px);
     for (long r = 0; r < ny; ++r)
         for (long c = 0; c < nx; ++c) out[r * nx + c] = work[(r + oy) * px + c + ox] * scale;

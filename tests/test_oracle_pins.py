@@ -115,6 +115,49 @@ def test_plane_wave_eigenfunction(method, mx, my):
     assert np.abs(out - np.exp(1j * phase) * u).max() < 1e-12
 
 
+@pytest.mark.parametrize("method", [oracle.ASM, oracle.FRESNEL])
+@pytest.mark.parametrize("n,mx,my", [(48, 7, -11), (48, -24, 5), (45, 22, -22), (45, -3, 17), (20, 10, -9)])
+def test_plane_wave_eigenfunction_any_length(method, n, mx, my):
+    """The eigenfunction pin on grids whose extent is not a power of two
+    (the naive DFT path), odd lengths included: bin (n-1)/2 of an odd grid
+    is the positive frequency, as in numpy's fftfreq."""
+    d, lam, z = 1.0e-6, 0.7e-6, 1.0e-4
+    u = plane_wave(n, mx, my)
+    out = oracle.propagate(u, d, d, lam, z, method, padded=(n, n))
+    alpha, beta = lam * mx / (n * d), lam * my / (n * d)
+    k = 2 * np.pi / lam
+    if method == oracle.ASM:
+        phase = k * z * math.cos(math.asin(math.hypot(alpha, beta)))
+    else:
+        phase = k * z * (1.0 - 0.5 * (alpha * alpha + beta * beta))
+    assert np.abs(out - np.exp(1j * phase) * u).max() < 1e-11
+    assert np.allclose(oracle.fftfreq(n, d) * n * d, np.fft.fftfreq(n) * n)
+
+
+def test_any_length_padding_invariants():
+    """Non-power-of-two padded grids (1000-like 2x padding of a 25 x 15
+    field: 50 x 30, and an odd 49 x 31): the window position does not
+    matter, the adjoint identity holds, and DI equals the brute-force sum on
+    the smallest admissible odd padding (2n - 1)."""
+    rng = np.random.default_rng(760)
+    u = crandn(rng, 25, 15)
+    v = crandn(rng, 25, 15)
+    args = (4e-6, 3e-6, 0.6e-6, 2e-3)
+    for py, px in ((50, 30), (49, 31)):
+        a = oracle.propagate(u, *args, oracle.ASM, padded=(py, px))
+        for oy, ox in ((0, 0), (py - 25, px - 15), (7, 3)):
+            b = oracle.propagate_offset(u, *args, oracle.ASM, 0, oy, ox, padded=(py, px))
+            assert rel(b, a) < 1e-13, (py, px, oy, ox)
+        lhs = np.vdot(v, a)
+        rhs = np.vdot(oracle.propagate(v, *args, oracle.ASM, padded=(py, px), adjoint=True), u)
+        assert abs(lhs - rhs) < 1e-12 * np.linalg.norm(a) * np.linalg.norm(v)
+    ny, nx = 6, 5
+    uu = crandn(rng, ny, nx)
+    dy, dx, lam, z = 1.5e-6, 2e-6, 0.6e-6, 2.5e-5
+    di = oracle.propagate(uu, dy, dx, lam, z, oracle.DI, padded=(2 * ny - 1, 2 * nx - 1))
+    assert rel(di, oracle.rs_direct(uu, dy, dx, lam, z)) < 1e-12
+
+
 def test_evanescent_plane_wave_is_removed():
     n, d, lam = 32, 0.4e-6, 0.7e-6
     u = plane_wave(n, 14, 14)  # fx^2 + fy^2 > 1/lambda^2
