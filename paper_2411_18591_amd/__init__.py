@@ -121,7 +121,9 @@ class Optics:
     """Geometry and free-space parameters of one propagation.
 
     The padded grid is ``padded`` = (py, px) if given, else each extent is
-    ``pad`` times the field rounded up to a power of two.  ``method`` is
+    ``pad`` times the field, rounded up to a power of two unless
+    ``round_pow2`` is False (extents that are not powers of two, up to 4096,
+    run through the unfused path with Bluestein transforms).  ``method`` is
     "asm", "fresnel", "di" (direct integration; needs pad >= 2 and z > 0) or
     "auto" (DI at or beyond the critical distance, AS below it)."""
     dy: float
@@ -133,10 +135,13 @@ class Optics:
     y0: float = 0.0
     x0: float = 0.0
     padded: Optional[tuple] = None
+    round_pow2: bool = True
 
     def padded_shape(self, ny: int, nx: int):
         if self.padded is not None:
             return int(self.padded[0]), int(self.padded[1])
+        if not self.round_pow2:
+            return self.pad * ny, self.pad * nx
         return next_pow2(self.pad * ny), next_pow2(self.pad * nx)
 
 

@@ -108,6 +108,15 @@ struct DeviceCtx {
   size_t rs_bytes = 0;
   void* acc = nullptr;    // private intensity accumulators of the lanes of a call
   size_t acc_bytes = 0;
+  // Bluestein tables of the non-power-of-two lengths used so far
+  struct Blue {
+    int L;
+    bool dbl;
+    int M;
+    void* w;
+    void* Bf;
+  };
+  std::vector<Blue> blue;
 };
 
 std::mutex g_mutex;
@@ -332,6 +341,17 @@ hipError_t timed(const char* name, int L, bool dbl, hipStream_t s, F&& f) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Padded extents: powers of two in [kMinLen, kMaxLen] (the fused path), or
+// other lengths up to kMaxAnyLen, transformed by Bluestein's method in the
+// plain path (the convolution length, a power of two >= 2L - 1, stays
+// within kMaxLen).
+constexpr int kMaxAnyLen = 4096;
+bool extent_ok(int64_t L) {
+  return is_pow2(L) ? (L >= kMinLen && L <= kMaxLen) : (L >= 3 && L <= kMaxAnyLen);
+}
+bool pow2_grid(const to_job& j) { return is_pow2(j.py) && is_pow2(j.px); }
+bool has_jones(const to_job& j);
+
 // Critical distance of Eq. (sampling_condition), L dx / lambda with the
 // aperture length L = n d of each axis; the smaller axis value is taken, so
 // the automatic choice keeps the AS method only where both axes favour it.
@@ -357,11 +377,16 @@ to_status validate(const to_job& j, int idx, to_dtype dt, Mode mode) {
     if (ly < j.ny || lx < j.nx)
       return fail(TO_E_INVAL, "job %d: padded grid %lldx%lld smaller than the field %dx%d", idx,
                   (long long)ly, (long long)lx, j.ny, j.nx);
-    if (!is_pow2(ly) || !is_pow2(lx) || ly < kMinLen || lx < kMinLen || ly > kMaxLen ||
-        lx > kMaxLen)
+    if (!extent_ok(ly) || !extent_ok(lx))
       return fail(TO_E_UNSUPPORTED,
-                  "job %d: padded grid %lldx%lld must be powers of two in [%d, %d]", idx,
-                  (long long)ly, (long long)lx, kMinLen, kMaxLen);
+                  "job %d: padded grid %lldx%lld: each extent must be a power of two in [%d, %d] or any "
+                  "length in [3, %d]",
+                  idx, (long long)ly, (long long)lx, kMinLen, kMaxLen, kMaxAnyLen);
+    if (!pow2_grid(j) && mode == MODE_COH)
+      return fail(TO_E_UNSUPPORTED, "job %d: coherence propagation needs power-of-two padded extents", idx);
+    if (!pow2_grid(j) && (has_jones(j) || j.epi == TO_EPI_INTENSITY))
+      return fail(TO_E_UNSUPPORTED,
+                  "job %d: Jones elements and the intensity epilogue need power-of-two padded extents", idx);
     if (j.method != TO_ASM && j.method != TO_FRESNEL && j.method != TO_DI && j.method != TO_AUTO)
       return fail(TO_E_INVAL, "job %d: unknown method %d", idx, j.method);
     if (!std::isfinite(j.z)) return fail(TO_E_INVAL, "job %d: z is not finite", idx);
@@ -520,6 +545,47 @@ template <>
 const cx<float>* twiddles<float>(DeviceCtx* c, int L) { return c->tw32 + tw_offset(L); }
 template <>
 const cx<double>* twiddles<double>(DeviceCtx* c, int L) { return c->tw64 + tw_offset(L); }
+
+// Transforms of length L: the power-of-two twiddles, or the Bluestein tables
+// of L (built on first use, on `s`, which is then synchronized: a first use
+// is not for graph capture).
+template <typename T>
+to_status line_fft(DeviceCtx* c, int L, hipStream_t s, LineFft<T>* out) {
+  out->L = L;
+  out->M = 0;
+  out->w = out->Bf = nullptr;
+  if (is_pow2(L)) {
+    out->tw = twiddles<T>(c, L);
+    return TO_OK;
+  }
+  int M = 1;
+  while (M < 2 * L - 1) M *= 2;
+  if (M > kMaxLen) return fail(TO_E_UNSUPPORTED, "length %d is too long for Bluestein's transform", L);
+  const bool dbl = sizeof(T) == 8;
+  for (const auto& b : c->blue)
+    if (b.L == L && b.dbl == dbl) {
+      out->M = b.M;
+      out->tw = twiddles<T>(c, b.M);
+      out->w = (const cx<T>*)b.w;
+      out->Bf = (const cx<T>*)b.Bf;
+      return TO_OK;
+    }
+  DeviceCtx::Blue b{L, dbl, M, nullptr, nullptr};
+  hipError_t e;
+  if ((e = hipMalloc(&b.w, sizeof(cx<T>) * L)) != hipSuccess ||
+      (e = hipMalloc(&b.Bf, sizeof(cx<T>) * M)) != hipSuccess) {
+    if (b.w) (void)hipFree(b.w);
+    return fail(TO_E_NOMEM, "Bluestein tables: %s", hipGetErrorString(e));
+  }
+  if ((e = Bluestein<T>::build(L, M, (cx<T>*)b.w, (cx<T>*)b.Bf, twiddles<T>(c, M), s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
+    (void)hipFree(b.w);
+    (void)hipFree(b.Bf);
+    return hip_fail(e, "Bluestein tables");
+  }
+  c->blue.push_back(b);
+  return line_fft<T>(c, L, s, out);
+}
 
 // Geometry shared by the forward and backward launch sequences.
 struct Geometry {
@@ -819,7 +885,7 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, Lane* l
 // ---------------------------------------------------------------------------
 bool same_grid(const to_job& a, const to_job& b) {
   return a.ny == b.ny && a.nx == b.nx && a.py == b.py && a.px == b.px && a.batch == b.batch &&
-         a.ncomp == b.ncomp && !has_jones(a) && !has_jones(b) && a.batch > 0;
+         a.ncomp == b.ncomp && !has_jones(a) && !has_jones(b) && a.batch > 0 && pow2_grid(a);
 }
 
 // Field buffers of a chain may be shared between layers only whole (same
@@ -1055,7 +1121,7 @@ template <typename T>
 void workspace_need(const to_job& j, bool backward, size_t* scratch_bytes, size_t* partial_count) {
   *scratch_bytes = 0;
   *partial_count = 0;
-  if (j.batch == 0) return;
+  if (j.batch == 0 || !pow2_grid(j)) return;
   Geometry g;
   if (make_geometry<T>(j, backward ? has_jones(j) : coupled(j), &g) != TO_OK) return;
   *scratch_bytes = (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>);
@@ -1336,6 +1402,7 @@ to_status run_coherence(const to_job& j, int adjoint, const to_grad* gr, DeviceC
 // ---------------------------------------------------------------------------
 template <typename T>
 struct PlainWork {
+  LineFft<T> fx, fy;
   cx<T>* H;
   cx<T>* pad;
   cx<T>* tmp;
@@ -1344,11 +1411,36 @@ struct PlainWork {
 };
 
 template <typename T>
+size_t plain_bytes(const to_job& j) {
+  const size_t npad = (size_t)j.py * j.px, nf = (size_t)j.ny * j.nx;
+  return (2 * npad + 2 * nf) * sizeof(cx<T>) + 1024 * sizeof(double);
+}
+
+// Jobs of to_propagate / to_propagate_backward whose padded grid is not a
+// power of two run through the plain path; its workspace and Bluestein
+// tables are made ready before the lanes fork (both may synchronize).
+template <typename T>
+to_status prepare_plain_jobs(const to_job* jobs, int n, DeviceCtx* c, hipStream_t s) {
+  size_t bytes = 0;
+  for (int i = 0; i < n; ++i) {
+    const to_job& j = jobs[i];
+    if (j.batch == 0 || pow2_grid(j)) continue;
+    bytes = std::max(bytes, plain_bytes<T>(j));
+    LineFft<T> f;
+    to_status st;
+    if ((st = line_fft<T>(c, j.px, s, &f)) != TO_OK || (st = line_fft<T>(c, j.py, s, &f)) != TO_OK) return st;
+  }
+  return bytes ? ensure_plain(c, bytes) : TO_OK;
+}
+
+template <typename T>
 to_status plain_setup(const to_job& j, DeviceCtx* c, bool conj, hipStream_t s, PlainWork<T>* w) {
   const size_t npad = (size_t)j.py * j.px, nf = (size_t)j.ny * j.nx;
-  const size_t bytes = (2 * npad + 2 * nf) * sizeof(cx<T>) + 1024 * sizeof(double);
+  const size_t bytes = plain_bytes<T>(j);
   to_status st = ensure_plain(c, bytes);
   if (st != TO_OK) return st;
+  if ((st = line_fft<T>(c, j.px, s, &w->fx)) != TO_OK) return st;
+  if ((st = line_fft<T>(c, j.py, s, &w->fy)) != TO_OK) return st;
   w->H = (cx<T>*)c->plain;
   w->pad = w->H + npad;
   w->tmp = w->pad + npad;
@@ -1390,8 +1482,8 @@ to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
     pj.H = w.H;
     pj.conj = 0;
     pj.el = make_element<T>(j, j.el_flags);
-    pj.tw_x = twiddles<T>(c, j.px);
-    pj.tw_y = twiddles<T>(c, j.py);
+    pj.fx = w.fx;
+    pj.fy = w.fy;
     hipError_t e = timed("plain.propagate", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain propagation");
     if (j.epi != TO_EPI_NONE) {
@@ -1431,8 +1523,8 @@ to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, h
     pj.H = w.H;
     pj.conj = 1;
     pj.el = make_element<T>(j, 0);
-    pj.tw_x = twiddles<T>(c, j.px);
-    pj.tw_y = twiddles<T>(c, j.py);
+    pj.fx = w.fx;
+    pj.fy = w.fy;
     hipError_t e = timed("plain.adjoint", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain adjoint");
     if (gr.grad_phase && (j.el_flags & TO_EL_PHASE) && gr.saved_in) {
@@ -1526,7 +1618,7 @@ to_status prepare_separable(std::vector<to_job>* jobs, DeviceCtx* c, hipStream_t
   size_t total = 0;
   for (int i = 0; i < n; ++i) {
     const to_job& j = (*jobs)[i];
-    if (j.batch == 0 || j.method == TO_DI) continue;
+    if (j.batch == 0 || j.method == TO_DI || !pow2_grid(j)) continue;
     if (j.method == TO_ASM && !(asm_remainder_cycles(j) <= kFastRemainderCycles)) continue;
     int k = 0;
     while (k < (int)first.size() && !same_sep_geometry((*jobs)[first[k]], j)) ++k;
@@ -1592,8 +1684,11 @@ to_status prepare_jobs(const to_job* jobs, int n, DeviceCtx* c, hipStream_t s, s
   for (size_t k = 0; k < first.size(); ++k) {
     const to_job& j = (*out)[first[k]];
     cx<T>* H = (cx<T>*)((char*)c->di + offset[k]);
+    LineFft<T> fx, fy;
+    if ((st = line_fft<T>(c, j.px, s, &fx)) != TO_OK) return st;
+    if ((st = line_fft<T>(c, j.py, s, &fy)) != TO_OK) return st;
     hipError_t e = timed("di_table", j.px, sizeof(T) == 8, s, [&] {
-      return TransferTable<T>::direct_integration(H, di_params(j), twiddles<T>(c, j.px), twiddles<T>(c, j.py), s);
+      return TransferTable<T>::direct_integration(H, di_params(j), fx, fy, s);
     });
     if (e != hipSuccess) return hip_fail(e, "direct-integration table");
   }
@@ -1689,6 +1784,8 @@ to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* 
   std::vector<to_job> prepared;
   if ((st = prepare_jobs_dt(jobs, njobs, dtype, c, s, &prepared)) != TO_OK) return st;
   jobs = prepared.data();
+  st = dtype == TO_C64 ? prepare_plain_jobs<float>(jobs, njobs, c, s) : prepare_plain_jobs<double>(jobs, njobs, c, s);
+  if (st != TO_OK) return st;
   // scheduling units: single jobs and chains of layers
   std::vector<int> ubeg, ulen;
   for (int i = 0; i < njobs;) {
@@ -1715,11 +1812,14 @@ to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* 
       }
       if (j.epi == TO_EPI_INTENSITY && j.batch > 0)
         acc.push_back({u, i, span(j.epi_out, (size_t)j.batch * j.ny * j.nx * relt)});
+      if (!pow2_grid(j)) wr[u].push_back(Span{1, 2});  // the plain path's one workspace
       cost[u] += job_cost(j);
     }
   }
   auto run = [&](int u, Lane* ln, hipStream_t ls) {
     const to_job* js = jobs + ubeg[u];
+    if (!pow2_grid(*js))
+      return dtype == TO_C64 ? run_forward_plain<float>(*js, c, ls) : run_forward_plain<double>(*js, c, ls);
     if (ulen[u] > 1)
       return dtype == TO_C64 ? run_forward_chain<float>(js, ulen[u], c, ln, ls)
                              : run_forward_chain<double>(js, ulen[u], c, ln, ls);
@@ -1772,6 +1872,8 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
                               (g.grad_f && (jobs[i].el_flags & TO_EL_LENS));
       if (want_param && !g.saved_in)
         return fail(TO_E_INVAL, "job %d: a parameter gradient needs saved_in", i);
+      if (!pow2_grid(jobs[i]) && g.grad_f && (jobs[i].el_flags & TO_EL_LENS))
+        return fail(TO_E_UNSUPPORTED, "job %d: the lens gradient needs power-of-two padded extents", i);
     }
   }
   if (njobs == 0) return TO_OK;
@@ -1782,6 +1884,8 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
   std::vector<to_job> prepared;
   if ((st = prepare_jobs_dt(jobs, njobs, dtype, c, s, &prepared)) != TO_OK) return st;
   jobs = prepared.data();
+  st = dtype == TO_C64 ? prepare_plain_jobs<float>(jobs, njobs, c, s) : prepare_plain_jobs<double>(jobs, njobs, c, s);
+  if (st != TO_OK) return st;
   std::vector<int> ubeg, ulen;
   for (int i = 0; i < njobs;) {
     const int len = backward_chain_len(jobs, grads, njobs, i, dtype);
@@ -1804,11 +1908,15 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
       wr[u].push_back(span(g.grad_in, fb));
       wr[u].push_back(span(g.grad_phase, rb));
       wr[u].push_back(span(g.grad_f, sizeof(double)));
+      if (!pow2_grid(j)) wr[u].push_back(Span{1, 2});  // the plain path's one workspace
       cost[u] += job_cost(j);
     }
   }
   auto run = [&](int u, Lane* ln, hipStream_t ls) {
     const int i = ubeg[u];
+    if (!pow2_grid(jobs[i]))
+      return dtype == TO_C64 ? run_backward_plain<float>(jobs[i], grads[i], c, ls)
+                             : run_backward_plain<double>(jobs[i], grads[i], c, ls);
     if (ulen[u] > 1)
       return dtype == TO_C64 ? run_backward_chain<float>(jobs + i, grads + i, ulen[u], c, ln, ls)
                              : run_backward_chain<double>(jobs + i, grads + i, ulen[u], c, ln, ls);
@@ -1875,6 +1983,7 @@ to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* 
   to_status st = validate(*job, 0, dtype, MODE_FWD);
   if (st != TO_OK) return st;
   if (job->batch == 0) return fail(TO_E_INVAL, "autotune needs a job with batch >= 1");
+  if (!pow2_grid(*job)) return fail(TO_E_UNSUPPORTED, "autotune needs power-of-two padded extents");
   DeviceCtx* c;
   if ((st = get_ctx(&c)) != TO_OK) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -2014,6 +2123,10 @@ to_status to_release(void) {
     if (c.sep) note(hipFree(c.sep));
     if (c.rs) note(hipFree(c.rs));
     if (c.acc) note(hipFree(c.acc));
+    for (auto& b : c.blue) {
+      if (b.w) note(hipFree(b.w));
+      if (b.Bf) note(hipFree(b.Bf));
+    }
     c = DeviceCtx();
   }
   note(hipSetDevice(cur));
@@ -2036,10 +2149,17 @@ to_status to_transfer_table(const to_job* job, to_dtype dtype, void* table, void
   const bool dbl = dtype == TO_C128;
   hipError_t e;
   if (j.method == TO_DI) {
-    e = dbl ? TransferTable<double>::direct_integration((cx<double>*)table, di_params(j), twiddles<double>(c, j.px),
-                                                        twiddles<double>(c, j.py), s)
-            : TransferTable<float>::direct_integration((cx<float>*)table, di_params(j), twiddles<float>(c, j.px),
-                                                       twiddles<float>(c, j.py), s);
+    if (dbl) {
+      LineFft<double> fx, fy;
+      if ((st = line_fft<double>(c, j.px, s, &fx)) != TO_OK || (st = line_fft<double>(c, j.py, s, &fy)) != TO_OK)
+        return st;
+      e = TransferTable<double>::direct_integration((cx<double>*)table, di_params(j), fx, fy, s);
+    } else {
+      LineFft<float> fx, fy;
+      if ((st = line_fft<float>(c, j.px, s, &fx)) != TO_OK || (st = line_fft<float>(c, j.py, s, &fy)) != TO_OK)
+        return st;
+      e = TransferTable<float>::direct_integration((cx<float>*)table, di_params(j), fx, fy, s);
+    }
   } else {
     const TransferParams h = make_transfer(j, false);
     e = dbl ? TransferTable<double>::analytic((cx<double>*)table, j.py, j.px, h, s)

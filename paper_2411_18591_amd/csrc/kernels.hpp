@@ -126,8 +126,8 @@ struct TransferParams {
 //   Fresnel TF: c = z/lambda - (lambda z / 2)(fx^2 + fy^2).
 template <typename T>
 __device__ __forceinline__ cx<T> transfer_at(int kx, int ky, int lx, int ly, const TransferParams& p) {
-  const int kxs = kx < lx / 2 ? kx : kx - lx;
-  const int kys = ky < ly / 2 ? ky : ky - ly;
+  const int kxs = 2 * kx < lx ? kx : kx - lx;
+  const int kys = 2 * ky < ly ? ky : ky - ly;
   const double fx = (double)kxs * p.inv_lxdx;
   const double fy = (double)kys * p.inv_lydy;
   const double rho2 = fx * fx + fy * fy;
@@ -152,7 +152,7 @@ __device__ __forceinline__ cx<float> transfer_fast(cx<float> exk, float sxk, int
   if (p.method == 0) {
     // s = lambda^2 (fx^2 + fy^2); the y part from the bin index in FP32
     // (relative error ~1e-7 on a remainder below one cycle)
-    const float gy = (float)(ky < ly / 2 ? ky : ky - ly) * lam_fy_unit;
+    const float gy = (float)(2 * ky < ly ? ky : ky - ly) * lam_fy_unit;
     const float s = fmaf(gy, gy, sxk);
     // v_sqrt / v_rcp (~1 ulp) and v_sin / v_cos, whose argument is in
     // revolutions (|theta| <= 1 here; absolute error ~1.2e-7): the
@@ -171,7 +171,7 @@ __device__ __forceinline__ void tf_table_entry(int i, cx<float>* ex, float* sx, 
                                                cx<float>* ey, float* sy, int ly, double inv_lydy,
                                                double fres_a, double q_frac, double lam2) {
   if (i < lx) {
-    const int ks = i < lx / 2 ? i : i - lx;
+    const int ks = 2 * i < lx ? i : i - lx;
     const double f = (double)ks * inv_lxdx;
     const double c = -fres_a * f * f;
     double s, co;
@@ -180,7 +180,7 @@ __device__ __forceinline__ void tf_table_entry(int i, cx<float>* ex, float* sx, 
     sx[i] = (float)(lam2 * f * f);
   } else if (i < lx + ly) {
     const int k = i - lx;
-    const int ks = k < ly / 2 ? k : k - ly;
+    const int ks = 2 * k < ly ? k : k - ly;
     const double f = (double)ks * inv_lydy;
     const double c = q_frac - fres_a * f * f;
     double s, co;

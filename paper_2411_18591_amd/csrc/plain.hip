@@ -5,7 +5,8 @@
 // function table, inverse column and row FFTs, crop and scale.  Every
 // intermediate is a full array in HBM.  The FFT building blocks are the same
 // Stockham register/LDS transforms as the fused path; only the fusion and the
-// batching are absent.
+// batching are absent.  It is also the path for padded extents that are not
+// powers of two, whose lines go through Bluestein's transform.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -172,15 +173,15 @@ hipError_t Plain<T>::run(const PlainJob<T>& pj, hipStream_t s) {
                      px);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // 3-4. forward FFT: rows, then columns
-  if ((e = rows(px, pj.pad, py, -1, pj.tw_x, s)) != hipSuccess) return e;
-  if ((e = cols(py, pj.pad, px, -1, pj.tw_y, s)) != hipSuccess) return e;
+  if ((e = rows_any(pj.fx, pj.pad, py, -1, s)) != hipSuccess) return e;
+  if ((e = cols_any(pj.fy, pj.pad, px, -1, s)) != hipSuccess) return e;
   // 5. transfer function from the stored table
   hipLaunchKernelGGL((plain_mul_kernel<T>), dim3(grid_for(npad)), dim3(256), 0, s, pj.pad, pj.H, npad,
                      pj.conj);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // 6-7. inverse FFT: columns, then rows
-  if ((e = cols(py, pj.pad, px, +1, pj.tw_y, s)) != hipSuccess) return e;
-  if ((e = rows(px, pj.pad, py, +1, pj.tw_x, s)) != hipSuccess) return e;
+  if ((e = cols_any(pj.fy, pj.pad, px, +1, s)) != hipSuccess) return e;
+  if ((e = rows_any(pj.fx, pj.pad, py, +1, s)) != hipSuccess) return e;
   // 8. crop and scale
   hipLaunchKernelGGL((plain_crop_kernel<T>), dim3(grid_for(nf)), dim3(256), 0, s, pj.pad, pj.out, ny, nx,
                      px, (T)(1.0 / ((double)py * (double)px)));
@@ -224,6 +225,16 @@ hipError_t Plain<T>::cols(int L, cx<T>* a, int lx, int dir, const cx<T>* tw, hip
                          tw);
     return hipGetLastError();
   });
+}
+
+template <typename T>
+hipError_t Plain<T>::rows_any(const LineFft<T>& f, cx<T>* a, int nrows, int dir, hipStream_t s) {
+  return f.M == 0 ? rows(f.L, a, nrows, dir, f.tw, s) : Bluestein<T>::rows(f, a, nrows, dir, s);
+}
+
+template <typename T>
+hipError_t Plain<T>::cols_any(const LineFft<T>& f, cx<T>* a, int lx, int dir, hipStream_t s) {
+  return f.M == 0 ? cols(f.L, a, lx, dir, f.tw, s) : Bluestein<T>::cols(f, a, lx, dir, s);
 }
 
 template <typename T>

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "bluestein.hpp"
 #include "kernels.hpp"
 
 namespace toprop {
@@ -17,8 +18,8 @@ struct PlainJob {
   const cx<T>* H;    // [py][px] transfer-function table
   int conj;          // multiply by conj(H)
   ElementParams<T> el;  // forward element (flags 0 = none)
-  const cx<T>* tw_x;    // twiddles of length px
-  const cx<T>* tw_y;    // twiddles of length py
+  LineFft<T> fx;        // transforms of length px
+  LineFft<T> fy;        // transforms of length py
 };
 
 template <typename T>
@@ -27,6 +28,9 @@ struct Plain {
   static hipError_t table(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s);
   static hipError_t rows(int L, cx<T>* a, int nrows, int dir, const cx<T>* tw, hipStream_t s);
   static hipError_t cols(int L, cx<T>* a, int lx, int dir, const cx<T>* tw, hipStream_t s);
+  // Any length: the power-of-two passes above, or Bluestein's transform.
+  static hipError_t rows_any(const LineFft<T>& f, cx<T>* a, int nrows, int dir, hipStream_t s);
+  static hipError_t cols_any(const LineFft<T>& f, cx<T>* a, int lx, int dir, hipStream_t s);
   static hipError_t loss(const cx<T>* u, const T* ref, cx<T>* grad, double* partial, int64_t n, int kind,
                          T scale, int* nblocks, hipStream_t s);
   static hipError_t modulate(const cx<T>* in, cx<T>* out, int ny, int nx, const ElementParams<T>& el, int conj,

@@ -32,8 +32,8 @@ __global__ void __launch_bounds__(256) di_sample_kernel(cx<T>* H, DiParams p) {
   const double area = p.dy * p.dx;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int ky = (int)(i / p.px), kx = (int)(i - (int64_t)ky * p.px);
-    const int sy = ky < p.py / 2 ? ky : ky - p.py;
-    const int sx = kx < p.px / 2 ? kx : kx - p.px;
+    const int sy = 2 * ky < p.py ? ky : ky - p.py;
+    const int sx = 2 * kx < p.px ? kx : kx - p.px;
     if (abs(sy) >= p.ny || abs(sx) >= p.nx) {
       H[i] = {T(0), T(0)};
       continue;
@@ -59,13 +59,13 @@ int table_grid(int64_t n) {
 }  // namespace
 
 template <typename T>
-hipError_t TransferTable<T>::direct_integration(cx<T>* H, const DiParams& p, const cx<T>* tw_x,
-                                                const cx<T>* tw_y, hipStream_t s) {
+hipError_t TransferTable<T>::direct_integration(cx<T>* H, const DiParams& p, const LineFft<T>& fx,
+                                                const LineFft<T>& fy, hipStream_t s) {
   hipLaunchKernelGGL((di_sample_kernel<T>), dim3(table_grid((int64_t)p.py * p.px)), dim3(256), 0, s, H, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = Plain<T>::rows(p.px, H, p.py, -1, tw_x, s)) != hipSuccess) return e;
-  return Plain<T>::cols(p.py, H, p.px, -1, tw_y, s);
+  if ((e = Plain<T>::rows_any(fx, H, p.py, -1, s)) != hipSuccess) return e;
+  return Plain<T>::cols_any(fy, H, p.px, -1, s);
 }
 
 template <typename T>

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "bluestein.hpp"
 #include "kernels.hpp"
 
 namespace toprop {
@@ -37,7 +38,7 @@ template <typename T>
 struct TransferTable {
   // DI: H = FFT2(sampled impulse response * dx dy), [py][px] row-major,
   // built in place in H.
-  static hipError_t direct_integration(cx<T>* H, const DiParams& p, const cx<T>* tw_x, const cx<T>* tw_y,
+  static hipError_t direct_integration(cx<T>* H, const DiParams& p, const LineFft<T>& fx, const LineFft<T>& fy,
                                        hipStream_t s);
   // AS / Fresnel: H at every bin of the padded grid.
   static hipError_t analytic(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s);

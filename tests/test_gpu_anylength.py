@@ -1,0 +1,145 @@
+"""Padded grids whose extents are not powers of two (the paper's own
+examples pad 1000, 250 and 50 samples to 2000, 500 and 100): the library
+runs them through its unfused path, transforming each line with Bluestein's
+chirp-z method on its power-of-two FFTs.  Against the FP64 oracle (whose
+transform of such lengths is the naive DFT, pinned on the CPU): even and odd
+lengths, AS / Fresnel / DI (at the smallest admissible DI padding, 2n - 1),
+forward and adjoint, elements, the MSE epilogue and the mask gradient,
+mixed with power-of-two jobs in one call; at the paper's 1000^2 -> 2000^2
+scale, a separable Fresnel Gaussian against the oracle's 1-D transforms."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests._util import announce, crandn, rel, to_gpu, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {np.complex64: 2e-5, np.complex128: 1e-12}
+METH = {"asm": oracle.ASM, "fresnel": oracle.FRESNEL, "di": oracle.DI}
+
+
+def _tp():
+    import paper_2411_18591_amd as tp
+    return tp
+
+
+def _oracle(u, opt, adjoint=False):
+    ny, nx = u.shape[-2:]
+    return oracle.propagate(u, opt.dy, opt.dx, opt.wavelength, opt.z, METH[opt.method], adjoint=adjoint,
+                            padded=opt.padded_shape(ny, nx))
+
+
+CASES = [
+    # (ny, nx, py, px, method)
+    (25, 15, 50, 30, "asm"),      # even, 2x padding
+    (24, 40, 49, 81, "fresnel"),  # odd extents
+    (50, 50, 100, 100, "asm"),    # the paper's 50^2 example, padded 2x
+    (30, 17, 59, 33, "di"),       # DI at 2n - 1 (odd)
+    (2, 3, 3, 5, "asm"),          # the smallest lengths
+    (20, 36, 20, 64, "fresnel"),  # one extent unpadded and not a power of two, the other a power of two
+]
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+@pytest.mark.parametrize("case", CASES)
+def test_forward_and_adjoint(case, dtype):
+    tp = _tp()
+    ny, nx, py, px, method = case
+    announce(f"any-length {case} {dtype.__name__}")
+    rng = np.random.default_rng(1200 + ny * nx)
+    u = crandn(rng, 3, ny, nx, dtype=dtype)
+    z = 1.5 * oracle.critical_distance(ny, nx, 4e-6, 5e-6, 0.6e-6) if method == "di" else 3e-4
+    opt = tp.Optics(dy=4e-6, dx=5e-6, wavelength=0.6e-6, z=z, method=method, padded=(py, px))
+    ug = to_gpu(u, torch)
+    out = tp.propagate(ug, opt)
+    gin = tp.propagate_backward(ug, opt)
+    torch.cuda.synchronize()
+    assert rel(to_np(out), _oracle(u, opt)) <= TOL[dtype]
+    assert rel(to_np(gin), _oracle(u, opt, adjoint=True)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_elements_loss_and_mask_gradient(dtype):
+    """Phase mask + lens, the MSE epilogue (loss and dL/du), and the
+    backward pass with the mask gradient, on a 2x padded 40 x 30 field
+    (80 x 60)."""
+    tp = _tp()
+    announce(f"any-length elements + loss {dtype.__name__}")
+    rng = np.random.default_rng(1210)
+    ny, nx = 40, 30
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    u = crandn(rng, 2, ny, nx, dtype=dtype)
+    phi = (rng.random((ny, nx)) * 6).astype(rdt)
+    T = rng.random((ny, nx)).astype(rdt)
+    opt = tp.Optics(dy=5e-6, dx=5e-6, wavelength=0.7e-6, z=2e-3, pad=2, round_pow2=False)
+    assert opt.padded_shape(ny, nx) == (80, 60)
+    ug, pg = to_gpu(u, torch), to_gpu(phi, torch)
+    out, grad, loss = tp.propagate_loss(ug, opt, kind="mse", ref=to_gpu(T, torch), scale=0.5, phase=pg,
+                                        lens_f=0.05)
+    gphi = torch.zeros_like(pg)
+    gin = tp.propagate_backward(grad, opt, saved_in=ug, grad_phase=gphi, phase=pg, lens_f=0.05)
+    torch.cuda.synchronize()
+    M = oracle.phase_mask(phi) * oracle.lens(ny, nx, 5e-6, 5e-6, 0.7e-6, 0.05)
+    um = oracle.modulate(u, M)
+    v = _oracle(um, opt)
+    assert rel(to_np(out), v) <= TOL[dtype]
+    Ie = np.abs(v) ** 2 - T
+    assert abs(float(loss.item()) - 0.5 * float((Ie ** 2).sum())) <= 1e-4 * 0.5 * float((Ie ** 2).sum())
+    g = 4 * 0.5 * Ie * v
+    assert rel(to_np(grad), g) <= 4 * TOL[dtype]
+    gmod = _oracle(to_np(grad).astype(np.complex128), opt, adjoint=True)
+    assert rel(to_np(gin), oracle.modulate(gmod, M, conj=True)) <= 4 * TOL[dtype]
+    assert rel(to_np(gphi), oracle.grad_phase(gmod, um)) <= (1e-4 if dtype == np.complex64 else 1e-10)
+
+
+def test_mixed_with_power_of_two_jobs():
+    """Non-power-of-two jobs (the plain path, kept on one lane) and fused
+    power-of-two jobs in one call: every output bitwise equal to its solo
+    run."""
+    tp = _tp()
+    announce("any-length mixed call")
+    rng = np.random.default_rng(1220)
+    shapes = [(25, 15, False), (32, 32, True), (24, 40, False), (48, 16, True), (25, 15, False)]
+    fields, opts = [], []
+    for ny, nx, p2 in shapes:
+        fields.append(to_gpu(crandn(rng, 2, ny, nx, dtype=np.complex64), torch))
+        opts.append(tp.Optics(dy=4e-6, dx=4e-6, wavelength=0.6e-6, z=3e-4, pad=2, round_pow2=p2))
+    outs = tp.propagate_jobs(fields, opts)
+    solo = [tp.propagate(f, o) for f, o in zip(fields, opts)]
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(outs, solo)):
+        assert torch.equal(a, b), i
+    assert rel(to_np(outs[2]), _oracle(to_np(fields[2]), opts[2])) <= TOL[np.complex64]
+
+
+def _prop1d(v, h, n):
+    """1-D zero-padded propagation with the oracle's naive DFT (any length)."""
+    x = np.zeros(h.size, dtype=np.complex128)
+    x[: v.size] = v
+    return oracle.dft(oracle.dft(x, -1) * h, +1)[:n] / h.size
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_paper_scale_separable(dtype):
+    """1000^2 Gaussian through a lens, Fresnel, padded to 2000^2 (the
+    paper's 4f grid at 2x padding): the field is separable, so every output
+    pixel is H(0,0) a(y) a(x) with a the 1-D propagation computed with the
+    oracle's naive DFT of length 2000 and its Fresnel transfer function."""
+    tp = _tp()
+    n, d, lam, z, f, w0 = 1000, 10e-6, 700e-9, 0.05, 0.2, 1.5e-3
+    announce(f"any-length 1000^2 -> 2000^2 {dtype.__name__}")
+    g1 = workloads.gaussian_amplitude(n, 1, d, d, w0)[:, 0]
+    l1 = oracle.lens(n, 1, d, d, lam, f)[:, 0]
+    col = oracle.transfer(2 * n, 1, d, d, lam, z, oracle.FRESNEL)[:, 0]
+    a = _prop1d(g1 * l1, col / col[0], n)
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, method="fresnel", pad=2, round_pow2=False)
+    u = workloads.gaussian_amplitude(n, n, d, d, w0).astype(dtype)[None]
+    out = tp.propagate(to_gpu(u, torch), opt, lens_f=f)
+    rows = np.array([0, 1, n // 3, n // 2, n - 1])
+    got = to_np(out[0][torch.from_numpy(rows).cuda()])
+    torch.cuda.synchronize()
+    exp = col[0] * a[rows, None] * a[None, :]
+    assert rel(got, exp) <= TOL[dtype]
