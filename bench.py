@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--layers", type=int, default=5)
     p.add_argument("--method", choices=["asm", "di", "auto"], default="asm",
                    help="propagation method of the network's layers (the headline figure is asm)")
-    p.add_argument("--workload", choices=["diffnet", "poly4f", "resample"], default="diffnet")
+    p.add_argument("--workload", choices=["diffnet", "poly4f", "resample", "anylength"], default="diffnet")
     p.add_argument("--fwhm-nm", type=float, default=10.0, help="poly4f: spectral FWHM")
     p.add_argument("--cache-tables", action="store_true",
                    help="poly4f: build the DI tables once, before the timed region (reported separately)")
@@ -160,6 +160,8 @@ def main():
         return run_poly4f(args)
     if args.workload == "resample":
         return run_resample(args)
+    if args.workload == "anylength":
+        return run_anylength(args)
     import numpy as np
     import torch
 
@@ -544,6 +546,61 @@ def run_resample(args):
         "config": {"workload": f"resampling: {B} x {n}^2 complex64 (8 um) -> {m}^2 (5.5 um), bilinear, "
                                "forward and adjoint"},
         "roofline": roofline, "kernels": kern, "cpu_baseline": cpu}))
+    return 0
+
+
+def run_anylength(args):
+    """Padding that is not a power of two: 16 complex64 fields of 1000^2
+    (8 um, 700 nm, AS 10 cm, phase mask) padded 2x to 2000^2 (the unfused
+    path with Bluestein transforms), forward and adjoint, beside the same
+    fields padded to 2048^2 (the fused path)."""
+    import numpy as np
+    import torch
+
+    import paper_2411_18591_amd as tp
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    B, n = 16, 1000
+    gen = torch.Generator(device=dev).manual_seed(7101)
+    u = torch.randn((B, n, n), dtype=torch.complex64, device=dev, generator=gen)
+    phi = torch.rand((n, n), dtype=torch.float32, device=dev, generator=gen) * 6.2832
+    res = {}
+    for name, rp in (("2000", False), ("2048", True)):
+        opt = tp.Optics(dy=8e-6, dx=8e-6, wavelength=0.7e-6, z=0.1, pad=2, round_pow2=rp)
+        out = torch.empty_like(u)
+        gin = torch.empty_like(u)
+
+        def step():
+            tp.propagate(u, opt, out=out, phase=phi)
+            tp.propagate_backward(out, opt, grad_in=gin, phase=phi)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream(dev)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        res[name] = {"ms_per_step": round(ms, 3), "propagations_per_s": round(2 * B / (ms / 1000.0), 1),
+                     "padded": opt.padded_shape(n, n)}
+    ms = res["2000"]["ms_per_step"]
+    step_bytes = 2 * B * n * n * 16
+    print(json.dumps({
+        "metric": "fwd+adjoint propagations/s at 1000^2 padded 2000^2 c64 (non-power-of-two padding)",
+        "value": res["2000"]["propagations_per_s"], "unit": "propagations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic (seeded complex Gaussian fields, uniform phase mask)",
+        "config": {"workload": f"{B} x {n}^2 complex64, AS z = 10 cm, 8 um, 700 nm, phase mask, padded 2x to "
+                               "2000^2 (unfused path, Bluestein transforms); the same fields padded to 2048^2 "
+                               "(fused path) for comparison"},
+        "hbm_roofline_step": {"algorithmic_bytes": step_bytes,
+                              "frac": round(step_bytes / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9), 5)},
+        "pow2_2048": res["2048"], "roofline": None, "cpu_baseline": None}))
     return 0
 
 

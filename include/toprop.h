@@ -33,16 +33,21 @@
  *   (integer division), i.e. sample ny/2 is on the optical axis when the
  *   offset is zero.
  * Padding.  Propagation zero-pads the ny x nx field to the py x px grid of
- *   the job (powers of two in [8, 8192]); the field may be ragged (e.g.
- *   1000 x 1000 padded to 2048 x 2048).  The operator is the circular
+ *   the job; the field may be ragged (e.g. 1000 x 1000 padded to 2048 x
+ *   2048).  Padded extents are powers of two in [8, 8192] (the fused
+ *   kernels) or other lengths in [3, 4096] (e.g. 2000: an unfused pipeline
+ *   whose lines are transformed by Bluestein's method, chosen automatically;
+ *   without Jones elements, the intensity epilogue, the lens gradient or
+ *   coherence propagation, which return TO_E_UNSUPPORTED there, and with a
+ *   stream synchronization on the first use of each such length).  The operator is the circular
  *   convolution on the padded grid restricted to the field window, so the
  *   window position inside the padded grid does not change the result.
  * Transfer function (cycles, lambda = wavelength):
  *   TO_ASM:     H = exp(2 pi i z sqrt(1/lambda^2 - fx^2 - fy^2)),
  *               H = 0 where fx^2 + fy^2 > 1/lambda^2 (evanescent cut-off);
  *   TO_FRESNEL: H = exp(2 pi i (z/lambda - lambda z (fx^2 + fy^2) / 2)),
- *   with fx = k / (px dx), fy = k / (py dy) in FFT order (bins k >= px / 2
- *   are negative);
+ *   with fx = k / (px dx), fy = k / (py dy) in FFT order (bins with
+ *   2 k >= px are negative: k - px);
  *   TO_DI:      H = DFT of h(sy dy, sx dx) dx dy on the padded grid, h the
  *               impulse response of Eq. (impulse_response),
  *                 h = z / (i lambda d) (1 + i / (k d)) exp(i k d) / d,
@@ -141,7 +146,7 @@ typedef enum { TO_EPI_NONE = 0, TO_EPI_MSE = 1, TO_EPI_WEIGHTED = 2, TO_EPI_INTE
  * grid, through the same element and the same free-space distance.          */
 typedef struct to_job {
   int32_t ny, nx;     /* field grid (rows, columns), >= 1                      */
-  int32_t py, px;     /* padded grid: powers of two in [8, 8192], py >= ny,
+  int32_t py, px;     /* padded grid (see Padding above), py >= ny,
                          px >= nx (py = 2 ny, px = 2 nx is "2x padding")      */
   int32_t method;     /* to_method                                             */
   int32_t ncomp;      /* components per field: 1 (scalar) or 3 (polarized)    */
