@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-fields", type=int, default=0,
                    help="fields in the CPU oracle sample (0 = min(8, host cores))")
-    p.add_argument("--cpu-sample-layers", type=int, default=2,
+    p.add_argument("--cpu-sample-layers", type=int, default=3,
                    help="layers (of the workload's masks) in the CPU oracle sample")
     p.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
     p.add_argument("--plain-steps", type=int, default=1,
