@@ -109,26 +109,50 @@ __global__ void __launch_bounds__(256) resample_kernel(const cx<T>* __restrict__
   const AxisTap<double> ty = tap_y[q];
   const int iy[2] = {ty.i0, ty.i0 + 1};
   const double wy[2] = {ty.w0, ty.w1};
+  // FB fields at a time: their 4 FB gathers are in flight together
+  constexpr int FB = 4;
   for (int r = threadIdx.x; r < mx; r += blockDim.x) {
     const AxisTap<double> tx = tap_x[r];
     const int ix[2] = {tx.i0, tx.i0 + 1};
     const double wx[2] = {tx.w0, tx.w1};
-    for (int64_t b = blockIdx.y; b < batch; b += gridDim.y) {
-      const cx<T>* s = src + b * ((int64_t)ny * nx);
-      cx<T> acc = {T(0), T(0)};
+    int64_t off[2][2];
+    T w[2][2];
+    bool in[2][2];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        if (iy[u] < 0 || iy[u] >= ny) continue;
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          if (ix[v] < 0 || ix[v] >= nx) continue;
-          const T w = (T)(wy[u] * wx[v]);
-          const cx<T> val = s[(int64_t)iy[u] * nx + ix[v]];
-          acc.x += w * val.x;
-          acc.y += w * val.y;
-        }
+      for (int v = 0; v < 2; ++v) {
+        in[u][v] = iy[u] >= 0 && iy[u] < ny && ix[v] >= 0 && ix[v] < nx;
+        off[u][v] = in[u][v] ? (int64_t)iy[u] * nx + ix[v] : 0;
+        w[u][v] = (T)(wy[u] * wx[v]);
       }
-      dst[b * ((int64_t)my * mx) + (int64_t)q * mx + r] = acc;
+    for (int64_t b0 = blockIdx.y; b0 < batch; b0 += (int64_t)FB * gridDim.y) {
+      cx<T> val[FB][2][2];
+#pragma unroll
+      for (int k = 0; k < FB; ++k) {
+        const int64_t b = b0 + (int64_t)k * gridDim.y;
+        const cx<T>* s = src + (b < batch ? b : 0) * ((int64_t)ny * nx);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v)
+            val[k][u][v] = (b < batch && in[u][v]) ? s[off[u][v]] : cx<T>{T(0), T(0)};
+      }
+#pragma unroll
+      for (int k = 0; k < FB; ++k) {
+        const int64_t b = b0 + (int64_t)k * gridDim.y;
+        if (b >= batch) break;
+        cx<T> acc = {T(0), T(0)};
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            if (!in[u][v]) continue;
+            acc.x += w[u][v] * val[k][u][v].x;
+            acc.y += w[u][v] * val[k][u][v].y;
+          }
+        dst[b * ((int64_t)my * mx) + (int64_t)q * mx + r] = acc;
+      }
     }
   }
 }
@@ -150,25 +174,43 @@ __global__ void __launch_bounds__(256) resample_adjoint_kernel(const cx<T>* __re
                                                                const AxisRange* __restrict__ rng_x) {
   const int i = blockIdx.x;
   const AxisRange ry = rng_y[i];
+  constexpr int FB = 4;  // fields whose gathers are in flight together
   for (int k = threadIdx.x; k < nx; k += blockDim.x) {
-  const AxisRange rx = rng_x[k];
-  for (int64_t b = blockIdx.y; b < batch; b += gridDim.y) {
-    const cx<T>* g = src + b * ((int64_t)my * mx);
-    cx<T> acc = {T(0), T(0)};
-    for (int q = ry.lo; q <= ry.hi; ++q) {
-      const double wy = tap_weight(tap_y[q], i);
-      if (wy == 0.0) continue;
-      for (int r = rx.lo; r <= rx.hi; ++r) {
-        const double wx = tap_weight(tap_x[r], k);
-        if (wx == 0.0) continue;
-        const T w = (T)(wy * wx);
-        const cx<T> val = g[(int64_t)q * mx + r];
-        acc.x += w * val.x;
-        acc.y += w * val.y;
+    const AxisRange rx = rng_x[k];
+    for (int64_t b0 = blockIdx.y; b0 < batch; b0 += (int64_t)FB * gridDim.y) {
+      const cx<T>* g[FB];
+      bool ok[FB];
+#pragma unroll
+      for (int f = 0; f < FB; ++f) {
+        const int64_t b = b0 + (int64_t)f * gridDim.y;
+        ok[f] = b < batch;
+        g[f] = src + (ok[f] ? b : 0) * ((int64_t)my * mx);
       }
+      cx<T> acc[FB];
+#pragma unroll
+      for (int f = 0; f < FB; ++f) acc[f] = {T(0), T(0)};
+      for (int q = ry.lo; q <= ry.hi; ++q) {
+        const double wy = tap_weight(tap_y[q], i);
+        if (wy == 0.0) continue;
+        for (int r = rx.lo; r <= rx.hi; ++r) {
+          const double wx = tap_weight(tap_x[r], k);
+          if (wx == 0.0) continue;
+          const T w = (T)(wy * wx);
+          const int64_t o = (int64_t)q * mx + r;
+          cx<T> val[FB];
+#pragma unroll
+          for (int f = 0; f < FB; ++f) val[f] = ok[f] ? g[f][o] : cx<T>{T(0), T(0)};
+#pragma unroll
+          for (int f = 0; f < FB; ++f) {
+            acc[f].x += w * val[f].x;
+            acc[f].y += w * val[f].y;
+          }
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < FB; ++f)
+        if (ok[f]) dst[(b0 + (int64_t)f * gridDim.y) * ((int64_t)ny * nx) + (int64_t)i * nx + k] = acc[f];
     }
-    dst[b * ((int64_t)ny * nx) + (int64_t)i * nx + k] = acc;
-  }
   }
 }
 
