@@ -44,7 +44,8 @@ def parse():
     p.add_argument("--layers", type=int, default=5)
     p.add_argument("--method", choices=["asm", "di", "auto"], default="asm",
                    help="propagation method of the network's layers (the headline figure is asm)")
-    p.add_argument("--workload", choices=["diffnet", "poly4f", "resample", "anylength"], default="diffnet")
+    p.add_argument("--workload", choices=["diffnet", "poly4f", "resample", "anylength", "suite"],
+                   default="diffnet")
     p.add_argument("--fwhm-nm", type=float, default=10.0, help="poly4f: spectral FWHM")
     p.add_argument("--cache-tables", action="store_true",
                    help="poly4f: build the DI tables once, before the timed region (reported separately)")
@@ -162,6 +163,8 @@ def main():
         return run_resample(args)
     if args.workload == "anylength":
         return run_anylength(args)
+    if args.workload == "suite":
+        return run_suite(args)
     import numpy as np
     import torch
 
@@ -601,6 +604,127 @@ def run_anylength(args):
         "hbm_roofline_step": {"algorithmic_bytes": step_bytes,
                               "frac": round(step_bytes / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9), 5)},
         "pow2_2048": res["2048"], "roofline": None, "cpu_baseline": None}))
+    return 0
+
+
+def _timed(step, steps, warmup):
+    """Mean milliseconds of `step` between two events (after `warmup` runs),
+    and the per-kernel profile of one more pass."""
+    import torch
+
+    from paper_2411_18591_amd import _capi
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    _capi.profile_begin()
+    step()
+    torch.cuda.synchronize()
+    prof = _capi.profile_end()
+    top = sorted(prof.items(), key=lambda kv: -kv[1][1])[:3]
+    return ms, {k: {"launches": n, "avg_us": round(1000.0 * t / n, 2)} for k, (n, t) in top}
+
+
+def run_suite(args):
+    """The survey's other workloads, one step each, timed on one GPU:
+    a Gaussian beam through z, lens, z (256^2 complex128: latency); polarized
+    focusing (8 wavelengths x 3 components x 2048^2 complex64, Jones + lens,
+    Fresnel, weighted-intensity loss, gradient to f); a Gaussian Schell
+    source (64^4 complex64 coherence, mask + lens, MSE of the diagonal,
+    gradient to the mask); 128 uneven jobs (256^2 .. 4096^2, forward and
+    adjoint in one call each)."""
+    import numpy as np
+    import torch
+
+    import paper_2411_18591_amd as tp
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    res = {}
+
+    g = workloads.GaussianLensWorkload()
+    u = torch.from_numpy(g.field()).to(dev)
+    o1 = tp.Optics(dy=g.d, dx=g.d, wavelength=g.wavelength, z=g.z1, pad=g.pad)
+    o2 = tp.Optics(dy=g.d, dx=g.d, wavelength=g.wavelength, z=g.z2, pad=g.pad)
+    mid, out = torch.empty_like(u), torch.empty_like(u)
+
+    def gauss():
+        tp.propagate_jobs([u, mid], [o1, o2], outs=[mid, out], elements=[{}, {"lens_f": g.f}])
+    ms, top = _timed(gauss, max(args.steps, 20), args.warmup)
+    res["gaussian_lens_256_c128"] = {"ms_per_step": round(ms, 4), "propagations_per_step": 2, "kernels": top}
+
+    w = workloads.PolarizedWorkload()
+    E = torch.from_numpy(w.field()).to(dev)
+    W = torch.from_numpy(w.weight()).to(dev)
+    K = len(w.wavelengths)
+    outs, grads = torch.empty_like(E), torch.empty_like(E)
+    losses = torch.zeros(K, dtype=torch.float64, device=dev)
+    gfs = torch.zeros(K, dtype=torch.float64, device=dev)
+    J = tp.jones3(tp.waveplate(w.qwp_angle, np.pi / 2), tp.linear_polarizer(w.lp_angle))
+    opts = [tp.Optics(dy=w.d, dx=w.d, wavelength=float(lam), z=w.z, method="fresnel", pad=w.pad)
+            for lam in w.wavelengths]
+    els = [dict(jones=J, lens_f=w.f, epi=tp._capi.TO_EPI_WEIGHTED, epi_ref=W, epi_scale=w.d * w.d,
+                epi_grad=grads[k], epi_loss=losses[k]) for k in range(K)]
+
+    def polarized():
+        losses.zero_()
+        gfs.zero_()
+        tp.propagate_jobs(list(E), opts, outs=list(outs), elements=els, ncomp=3)
+        tp.propagate_backward_jobs(list(grads), opts, saved_ins=list(E), grad_ins=[None] * K, grad_fs=list(gfs),
+                                   elements=[dict(jones=J, lens_f=w.f)] * K, ncomp=3)
+    ms, top = _timed(polarized, args.steps, args.warmup)
+    res["polarized_8x3x2048_c64"] = {"ms_per_step": round(ms, 3), "propagations_per_step": 2 * 3 * K,
+                                     "propagations_per_s": round(2 * 3 * K / (ms / 1000.0), 1), "kernels": top}
+    del E, outs, grads
+
+    c = workloads.CoherenceWorkload()
+    G0 = torch.from_numpy(c.gamma()).to(dev)
+    pg = torch.from_numpy(c.mask()).to(dev)
+    T = torch.from_numpy(c.target()).to(dev)
+    oc = tp.Optics(dy=c.d, dx=c.d, wavelength=c.wavelength, z=c.z, pad=c.pad)
+    n = c.n
+    gphi = torch.zeros_like(pg)
+
+    def coherence():
+        out, gG, L = tp.coherence_propagate(G0, oc, loss_kind="mse", loss_ref=T, loss_scale=1.0 / (n * n),
+                                            phase=pg, lens_f=c.f)
+        gphi.zero_()
+        tp.coherence_propagate(gG, oc, adjoint=True, saved_in=G0, grad_phase=gphi, phase=pg, lens_f=c.f)
+    ms, top = _timed(coherence, args.steps, args.warmup)
+    slices = 4 * n * n
+    res["gaussian_schell_64^4_c64"] = {"ms_per_step": round(ms, 3), "slice_propagations_per_step": slices,
+                                        "slice_propagations_per_s": round(slices / (ms / 1000.0), 1),
+                                        "kernels": top}
+    del G0
+
+    jobs = workloads.uneven_jobs()
+    us, gs, ops = [], [], []
+    gen = torch.Generator(device=dev).manual_seed(5301)
+    for j in jobs:
+        us.append(torch.randn((j.n, j.n), dtype=torch.complex64, device=dev, generator=gen))
+        gs.append(torch.randn((j.n, j.n), dtype=torch.complex64, device=dev, generator=gen))
+        ops.append(tp.Optics(dy=j.d, dx=j.d, wavelength=j.wavelength, z=j.z, pad=2))
+    uo = [torch.empty_like(x) for x in us]
+    gi = [torch.empty_like(x) for x in gs]
+
+    def uneven():
+        tp.propagate_jobs(us, ops, outs=uo)
+        tp.propagate_backward_jobs(gs, ops, grad_ins=gi)
+    ms, top = _timed(uneven, args.steps, args.warmup)
+    elems = sum(j.n * j.n for j in jobs)
+    res["uneven_128_jobs_c64"] = {"ms_per_step": round(ms, 3), "propagations_per_step": 2 * len(jobs),
+                                  "propagations_per_s": round(2 * len(jobs) / (ms / 1000.0), 1),
+                                  "field_elements_per_job_sum": elems, "kernels": top}
+    print(json.dumps({"metric": "other workloads: time per step", "unit": "ms", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "data": "synthetic (seeded, as in workloads/)", "configs": res}))
     return 0
 
 

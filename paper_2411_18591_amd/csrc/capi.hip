@@ -612,8 +612,13 @@ bool has_loss(const to_job& j) { return j.epi == TO_EPI_MSE || j.epi == TO_EPI_W
 // Fields per column-pass block: as many as keep at least two blocks per
 // CU in flight (512 on 256 CUs), so the transfer function each block forms
 // is reused across fields.
-int col_fields_per_block(int ntiles, int nfields) {
-  const int64_t f = (int64_t)nfields * ntiles / 512;
+// Fields per column-pass block: the transfer function is formed once per
+// block and reused for its fields, while the launch keeps enough blocks:
+// 512 for columns of 2048 points and more, proportionally more for shorter
+// columns (whose per-field work is too short to hide latency in few blocks).
+int col_fields_per_block(int ntiles, int nfields, int ly) {
+  const int64_t target = 512 * std::max(1, std::min(16, 2048 / std::max(ly, 1)));
+  const int64_t f = (int64_t)nfields * ntiles / target;
   return (int)std::max<int64_t>(1, std::min<int64_t>(nfields, f));
 }
 
@@ -715,7 +720,7 @@ ColArgs<T> col_args(const to_job& j, const Geometry& g, DeviceCtx* c, cx<T>* scr
   ca.tm = g.tm;
   ca.cpb = g.tc;
   ca.nfields = nf;
-  ca.fpc = col_fields_per_block(g.lx / g.tc, nf);
+  ca.fpc = col_fields_per_block(g.lx / g.tc, nf, g.ly);
   ca.h = h;
   ca.tw = twiddles<T>(c, g.ly);
   return ca;
@@ -1329,15 +1334,15 @@ template <typename T>
 to_status run_coherence(const to_job& j, int adjoint, const to_grad* gr, DeviceCtx* c, hipStream_t s) {
   const int n = j.ny * j.nx;
   const size_t nn = (size_t)n * n;
-  const size_t bytes = (nn + 2 * (size_t)n) * sizeof(cx<T>) + 3 * (size_t)n * sizeof(double);
+  const size_t bytes = (nn + 2 * (size_t)n) * sizeof(cx<T>) + (2 + kCohRowChunks) * (size_t)n * sizeof(double);
   to_status st = ensure_coh(c, bytes);
   if (st != TO_OK) return st;
   cx<T>* W = (cx<T>*)c->coh;
   cx<T>* mt = W + nn;   // M(r)
   cx<T>* mtc = mt + n;  // conj(M(r))
   double* rowsum = (double*)(mtc + n);
-  double* colsum = rowsum + n;
-  double* part = colsum + n;
+  double* part = rowsum + n;
+  double* colsum = part + n;  // kCohRowChunks * n column partials
   const bool dbl = sizeof(T) == 8;
   const bool has_el = (j.el_flags & (TO_EL_PHASE | TO_EL_COMPLEX | TO_EL_LENS)) != 0;
   const ElementParams<T> el = make_element<T>(j, j.el_flags);

@@ -123,28 +123,35 @@ __global__ void __launch_bounds__(256) coh_rowsum_kernel(const cx<T>* G, const c
   if (threadIdx.x == 0) rowsum[a] = s;
 }
 
-// Column sums: colsum[b] = sum_a t(a, b); a block covers 64 columns with 4
-// row groups, fixed order.
+// Column sums in kCohRowChunks row chunks: colpart[c][b] = sum over the rows
+// a of chunk c of t(a, b); a block covers 64 columns of one chunk with 4 row
+// groups, fixed order (enough blocks to fill the GPU: columns x chunks).
 template <typename T>
 __global__ void __launch_bounds__(256) coh_colsum_kernel(const cx<T>* G, const cx<T>* Gam, const cx<T>* m,
-                                                         double* colsum, int n) {
+                                                         double* colpart, int n) {
   __shared__ double red[4][64];
   const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
   const int b = blockIdx.x * 64 + tx;
+  const int rows = (n + kCohRowChunks - 1) / kCohRowChunks;
+  const int a0 = blockIdx.y * rows, a1 = min(a0 + rows, n);
   double acc = 0.0;
   if (b < n)
-    for (int a = ty; a < n; a += 4) acc += coh_grad_term(G, Gam, m, n, a, b);
+    for (int a = a0 + ty; a < a1; a += 4) acc += coh_grad_term(G, Gam, m, n, a, b);
   red[ty][tx] = acc;
   __syncthreads();
-  if (ty == 0 && b < n) colsum[b] = ((red[0][tx] + red[1][tx]) + red[2][tx]) + red[3][tx];
+  if (ty == 0 && b < n)
+    colpart[(int64_t)blockIdx.y * n + b] = ((red[0][tx] + red[1][tx]) + red[2][tx]) + red[3][tx];
 }
 
-// grad_phase[r] += rowsum[r] - colsum[r].
+// grad_phase[r] += rowsum[r] - sum over chunks (in order) of colpart[c][r].
 template <typename T>
-__global__ void __launch_bounds__(256) coh_grad_combine_kernel(const double* rowsum, const double* colsum, T* gphi,
+__global__ void __launch_bounds__(256) coh_grad_combine_kernel(const double* rowsum, const double* colpart, T* gphi,
                                                                int n) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < n) gphi[r] += (T)(rowsum[r] - colsum[r]);
+  if (r >= n) return;
+  double col = 0.0;
+  for (int c = 0; c < kCohRowChunks; ++c) col += colpart[(int64_t)c * n + r];
+  gphi[r] += (T)(rowsum[r] - col);
 }
 
 template <typename T>
@@ -189,7 +196,8 @@ hipError_t Coh<T>::phase_grad(const cx<T>* G, const cx<T>* Gam, const cx<T>* m, 
   hipLaunchKernelGGL((coh_rowsum_kernel<T>), dim3(n), dim3(256), 0, s, G, Gam, m, rowsum, n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((coh_colsum_kernel<T>), dim3((n + 63) / 64), dim3(256), 0, s, G, Gam, m, colsum, n);
+  hipLaunchKernelGGL((coh_colsum_kernel<T>), dim3((n + 63) / 64, kCohRowChunks), dim3(256), 0, s, G, Gam, m, colsum,
+                     n);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((coh_grad_combine_kernel<T>), dim3((n + 255) / 256), dim3(256), 0, s, rowsum, colsum, gphi,
                      n);

@@ -6,6 +6,10 @@
 
 namespace toprop {
 
+// Row chunks of the column sums of the mask gradient (partials summed in
+// chunk order: deterministic).
+constexpr int kCohRowChunks = 32;
+
 template <typename T>
 struct Coh {
   // out = transpose(in) (n x n), optionally scaled by conj(m[a]) m[b] at the
@@ -18,6 +22,7 @@ struct Coh {
   static hipError_t diag_intensity(const cx<T>* g, T* out, int n, T scale, hipStream_t s);
   static hipError_t diag_loss(const cx<T>* g, const T* ref, cx<T>* grad, double* partial, int n, int kind,
                               T scale, hipStream_t s);
+  // colsum: kCohRowChunks * n doubles of column partials
   static hipError_t phase_grad(const cx<T>* G, const cx<T>* Gam, const cx<T>* m, double* rowsum, double* colsum,
                                T* gphi, int n, hipStream_t s);
 };
