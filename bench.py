@@ -11,7 +11,7 @@ the adjoint propagations and accumulates the 5 mask gradients.  That is
 64 x 5 forward + 64 x 5 adjoint = 640 propagations per step, every one of
 them in the library's HIP kernels (the Python side only enqueues calls).
 
-Prints one JSON line (see the keys below).  --gpus must be 1: this build
+Prints one JSON line (see the keys below).  --gpus must be 1: the library
 runs on a single GPU.
 
 ``--workload poly4f`` measures the polychromatic 4f imaging workload instead
@@ -154,8 +154,8 @@ def main():
     if args.copy_calibration:
         return copy_calibration()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
+                                   "(sharding across GPUs is not implemented)"}))
         return 2
     if args.workload == "poly4f":
         return run_poly4f(args)
@@ -633,7 +633,7 @@ def _timed(step, steps, warmup):
 
 
 def run_suite(args):
-    """The survey's other workloads, one step each, timed on one GPU:
+    """The other workloads, one step each, timed on one GPU:
     a Gaussian beam through z, lens, z (256^2 complex128: latency); polarized
     focusing (8 wavelengths x 3 components x 2048^2 complex64, Jones + lens,
     Fresnel, weighted-intensity loss, gradient to f); a Gaussian Schell
