@@ -135,8 +135,9 @@ def kernel_model(name: str, wl, chunk_fields: int):
         # input gradient (backward) out, intermediate of the next layer out
         if name.startswith("fwd"):
             by = f * (2 * N * P * c + N * N * c) + N * N * 4
-        else:  # also reads the saved layer input; mask in, gradient partials out
-            by = f * (2 * N * P * c + 2 * N * N * c) + 2 * N * N * 4
+        else:  # reads the saved layer input (the link gradient, transient in
+            # the training step, is not stored); mask in, gradient partials out
+            by = f * (2 * N * P * c + N * N * c) + 2 * N * N * 4
         fl = f * N * 2 * fft_flops(P)
     elif ".row_inv_" in name:
         if name.startswith("fwd"):

@@ -184,7 +184,13 @@ typedef struct to_grad {
   void* grad_phase;      /* TO_EL_PHASE: real [ny][nx], += dL/dphi summed over
                             fields and components, or NULL                       */
   double* grad_f;        /* TO_EL_LENS: one device double, += dL/df, or NULL     */
+  uint32_t flags;        /* TO_GRAD_* (0 = none)                                 */
 } to_grad;
+
+/* grad_in is read by nothing but the next job of the same call (the link of
+ * a backward chain, its grad_out): where the library fuses the two layers it
+ * may leave grad_in unwritten (its contents are then unspecified).          */
+#define TO_GRAD_IN_TRANSIENT 1u
 
 /* Forward propagation of every job (Eq. (field_propagation_tf) after the
  * element of Eq. (field_modulation)): out = P_z (M in), with the optional

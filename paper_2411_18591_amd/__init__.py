@@ -433,11 +433,13 @@ def propagate_jobs(fields: Sequence[torch.Tensor], opts: Sequence[Optics], *, ou
 
 def propagate_backward_jobs(grads_out: Sequence[torch.Tensor], opts: Sequence[Optics], *, saved_ins=None,
                             grad_ins=None, grad_phases=None, grad_fs=None, elements=None, ncomp: int = 1,
-                            plain: bool = False):
+                            plain: bool = False, transient=None):
     """Backward of :func:`propagate_jobs` in one call: returns dL/d(in) per
     job (``grad_ins[i]`` None: not formed); element gradients accumulate
     into ``grad_phases[i]`` / ``grad_fs[i]`` (jobs that share a gradient
-    tensor are run in call order on one lane)."""
+    tensor are run in call order on one lane).  ``transient[i]`` True:
+    ``grad_ins[i]`` only links job i to job i + 1 (its grad_out), and may be
+    left unwritten where the library fuses the two layers."""
     n = len(grads_out)
     if len(opts) != n:
         raise ValueError("one Optics per gradient")
@@ -446,11 +448,13 @@ def propagate_backward_jobs(grads_out: Sequence[torch.Tensor], opts: Sequence[Op
     grad_phases = [None] * n if grad_phases is None else list(grad_phases)
     grad_fs = [None] * n if grad_fs is None else list(grad_fs)
     elements = [{}] * n if elements is None else list(elements)
+    transient = [False] * n if transient is None else list(transient)
     if n == 0:
         return grad_ins
     dt = _common_dtype(grads_out)
     jobs, grs = [], []
-    for go, o, gi, si, gp, gf, el in zip(grads_out, opts, grad_ins, saved_ins, grad_phases, grad_fs, elements):
+    for go, o, gi, si, gp, gf, el, tr in zip(grads_out, opts, grad_ins, saved_ins, grad_phases, grad_fs, elements,
+                                             transient):
         j = make_job(go, o, ncomp=ncomp, **el)
         j.in_ = None
         g = _capi.Grad()
@@ -463,6 +467,7 @@ def propagate_backward_jobs(grads_out: Sequence[torch.Tensor], opts: Sequence[Op
             g.grad_phase = _ptr(_need(gp, "grad_phase", _real_dtype(go), go, go.shape[-2:]))
         if gf is not None:
             g.grad_f = _ptr(_need(gf, "grad_f", torch.float64, go))
+        g.flags = _capi.TO_GRAD_IN_TRANSIENT if tr else 0
         jobs.append(j)
         grs.append(g)
     _capi.propagate_backward(jobs, grs, dt, _stream(grads_out[0]), plain=plain)

@@ -32,6 +32,7 @@ TO_EL_COMPLEX = 2
 TO_EL_LENS = 4
 TO_EL_JONES = 8
 TO_EL_JONES_MAP = 16
+TO_GRAD_IN_TRANSIENT = 1
 
 TO_EPI_NONE = 0
 TO_EPI_MSE = 1
@@ -115,6 +116,7 @@ class Grad(ctypes.Structure):
         ("saved_in", ctypes.c_void_p),
         ("grad_phase", ctypes.c_void_p),
         ("grad_f", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
     ]
 
 

@@ -1058,7 +1058,8 @@ to_status run_backward_chain(const to_job* jobs, const to_grad* grads, int n, De
       RowMidBwdArgs<T> mb;
       mb.scratch = scratch;
       mb.s_stride = g.s_stride;
-      mb.grad_in = (cx<T>*)gr.grad_in + f0 * g.in_stride;
+      // the link to the next layer: left unwritten when only that layer reads it
+      mb.grad_in = (gr.flags & TO_GRAD_IN_TRANSIENT) ? nullptr : (cx<T>*)gr.grad_in + f0 * g.in_stride;
       mb.saved_in = gr.saved_in ? (const cx<T>*)gr.saved_in + f0 * g.in_stride : nullptr;
       mb.stride = g.in_stride;
       mb.ny = j.ny;
@@ -1871,6 +1872,7 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
     to_status st = validate(jobs[i], i, dtype, MODE_BWD);
     if (st != TO_OK) return st;
     const to_grad& g = grads[i];
+    if (g.flags & ~TO_GRAD_IN_TRANSIENT) return fail(TO_E_INVAL, "job %d: unknown gradient flags 0x%x", i, g.flags);
     if (jobs[i].batch > 0) {
       if (!g.grad_out) return fail(TO_E_INVAL, "job %d: grad_out is NULL", i);
       const bool want_param = (g.grad_phase && (jobs[i].el_flags & TO_EL_PHASE)) ||

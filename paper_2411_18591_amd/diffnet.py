@@ -63,15 +63,18 @@ class DiffractiveNet:
 
     def backward(self, plain: bool = False) -> torch.Tensor:
         """dL/dphi_l for every mask into gmask (overwritten), in one call
-        (layers L-1 .. 0, the gradient buffers alternating)."""
+        (layers L-1 .. 0, the gradient buffers alternating; their contents
+        afterwards are unspecified: they only link the layers)."""
         self.gmask.zero_()
         L = self.L
         layers = list(range(L - 1, -1, -1))
         gout = [self.gbuf[k % 2] for k in range(L)]
         gin = [self.gbuf[(k + 1) % 2] if l > 0 else None for k, l in enumerate(layers)]
+        # the intermediate gradients only link consecutive layers of the chain
         propagate_backward_jobs(gout, [self.opt] * L, saved_ins=[self.u[l] for l in layers], grad_ins=gin,
                                 grad_phases=[self.gmask[l] for l in layers],
-                                elements=[self._element(l) for l in layers], plain=plain)
+                                elements=[self._element(l) for l in layers], plain=plain,
+                                transient=[g is not None for g in gin])
         return self.gmask
 
     def step(self, plain: bool = False):

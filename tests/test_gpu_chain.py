@@ -238,3 +238,39 @@ def test_training_step_graph_capture():
         net.step()
         torch.cuda.synchronize()
         assert torch.equal(got[0], net.loss) and torch.equal(got[1], net.gmask) and torch.equal(got[2], net.u[L]), rep
+
+
+def test_transient_links_give_the_same_gradients():
+    """Backward chain whose intermediate gradient buffers are marked
+    transient (only the next layer reads them): the fused boundaries may skip
+    storing them; the mask gradients and the first layer's input gradient
+    are bitwise those of the same call without the flag."""
+    tp = _tp()
+    announce("transient backward links")
+    rng = np.random.default_rng(760)
+    B, n, L = 3, 64, 4
+    u0, phis, T = _stack(rng, B, n, n, L, np.complex64)
+    opt = tp.Optics(dy=8e-6, dx=8e-6, wavelength=0.7e-6, z=0.02, pad=2)
+    Pg = to_gpu(phis, torch)
+    u = [to_gpu(u0, torch)] + [torch.empty_like(to_gpu(u0, torch)) for _ in range(L)]
+    tp.propagate_jobs(u[:L], [opt] * L, outs=u[1:], elements=[{"phase": Pg[l]} for l in range(L)])
+    gL = to_gpu(crandn(rng, B, n, n, dtype=np.complex64), torch)
+    layers = list(range(L - 1, -1, -1))
+
+    def run(transient):
+        g = [gL.clone(), torch.empty_like(gL)]
+        gm = torch.zeros_like(Pg)
+        gout = [g[k % 2] for k in range(L)]
+        gin = [g[(k + 1) % 2] for k in range(L)]
+        gin[-1] = torch.empty_like(gL)  # the first layer's input gradient, kept
+        tp.propagate_backward_jobs(gout, [opt] * L, saved_ins=[u[l] for l in layers], grad_ins=gin,
+                                   grad_phases=[gm[l] for l in layers],
+                                   elements=[{"phase": Pg[l]} for l in layers],
+                                   transient=[transient and k < L - 1 for k in range(L)])
+        torch.cuda.synchronize()
+        return gm.clone(), gin[-1].clone()
+
+    gm_a, gi_a = run(False)
+    gm_b, gi_b = run(True)
+    assert torch.equal(gm_a, gm_b)
+    assert torch.equal(gi_a, gi_b)
