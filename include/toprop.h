@@ -204,9 +204,15 @@ typedef struct to_grad {
  * priority) that wait on an event recorded on `stream` at entry and are
  * joined back into it at exit.  All work therefore completes in `stream`
  * order, and the call may be captured into a HIP graph from `stream` (after
- * one uncaptured call of the same shapes has sized the workspaces).  Calls
- * issued concurrently on different caller streams of one device share the
- * lanes' workspaces and must be serialised by the caller.                    */
+ * one uncaptured call of the same shapes has sized the workspaces; a later
+ * call that grows a workspace invalidates graphs captured before it).  Jobs
+ * whose intensity epilogues add into the same epi_out range do not conflict
+ * with each other: such jobs on different lanes add into private zeroed
+ * copies, which are added into epi_out in lane order after the lanes join
+ * (deterministic for a given call; the order differs from the call order,
+ * so sums agree with a one-job-per-call loop to rounding).  Calls issued
+ * concurrently on different caller streams of one device share the lanes'
+ * workspaces and must be serialised by the caller.                           */
 to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* stream);
 
 /* Modulation only (Eq. (field_modulation) / the Jones product):
