@@ -307,8 +307,10 @@ def main():
                  "fused_speedup": round(p_ms / ms_step, 2)}
 
     cpu = None
+    parity = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, wl_def, u0_np, masks_np, target_np, method)
+        cpu, sample = cpu_baseline(args, wl_def, u0_np, masks_np, target_np, method)
+        parity = parity_on_sample(sample, u0_np, masks_np, target_np, opt)
 
     out = {
         "metric": f"fwd+bwd {method} propagations/s at 1024^2 c64; % of HBM roofline vs plain form",
@@ -336,6 +338,7 @@ def main():
         "kernels": kernels_out,
         "wall_s": round(t_wall, 3),
         "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
     }
     print(json.dumps(out))
     return 0
@@ -749,14 +752,36 @@ def cpu_baseline(args, wl_def, u0_np, masks_np, target_np, method="ASM"):
     t0 = time.perf_counter()
     us = oracle.stack_forward(u0, phis, d, d, lam, z, meth, 2)
     _, g = oracle.mse_intensity(us[-1], T)
-    oracle.stack_backward(us, phis, g, d, d, lam, z, meth, 2)
+    _, grads = oracle.stack_backward(us, phis, g, d, d, lam, z, meth, 2)
     dt = time.perf_counter() - t0
     props = 2 * k * nl
-    return {"value": round(props / dt, 3), "unit": "propagations/s", "cores": min(k, cores),
-            "kind": "oracle",
-            "sample": f"{k} of {wl_def.batch} fields through the first {nl} of {wl_def.layers} "
-                      f"layers, fwd+bwd with MSE loss ({props} FP64 propagations at the same "
-                      f"1024^2 -> 2048^2 shape, {dt:.1f} s; OpenMP over fields)"}
+    cpu = {"value": round(props / dt, 3), "unit": "propagations/s", "cores": min(k, cores),
+           "kind": "oracle",
+           "sample": f"{k} of {wl_def.batch} fields through the first {nl} of {wl_def.layers} "
+                     f"layers, fwd+bwd with MSE loss ({props} FP64 propagations at the same "
+                     f"1024^2 -> 2048^2 shape, {dt:.1f} s; OpenMP over fields)"}
+    return cpu, (k, nl, us[-1], np.stack(grads))
+
+
+def parity_on_sample(sample, u0_np, masks_np, target_np, opt):
+    """The library on the oracle's sample (same fields, masks, target and
+    loss): relative L2 errors of the output field and the mask gradients."""
+    import numpy as np
+    import torch
+
+    from paper_2411_18591_amd.diffnet import DiffractiveNet
+    k, nl, u_ref, g_ref = sample
+    dev = torch.device("cuda", 0)
+    net = DiffractiveNet(torch.from_numpy(u0_np[:k]).to(dev), torch.from_numpy(masks_np[:nl]).to(dev),
+                         torch.from_numpy(target_np).to(dev), opt)
+    net.step()
+    torch.cuda.synchronize()
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    return {"output_field_rel_l2": rel(net.u[nl].cpu().numpy(), u_ref),
+            "mask_gradients_rel_l2": rel(net.gmask.cpu().numpy(), g_ref),
+            "sample": f"the oracle's sample: {k} fields, {nl} layers", "bar": "c64 field <= 2e-5"}
 
 
 if __name__ == "__main__":
