@@ -755,8 +755,14 @@ def cpu_baseline(args, wl_def, u0_np, masks_np, target_np, method="ASM"):
     _, grads = oracle.stack_backward(us, phis, g, d, d, lam, z, meth, 2)
     dt = time.perf_counter() - t0
     props = 2 * k * nl
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     cpu = {"value": round(props / dt, 3), "unit": "propagations/s", "cores": min(k, cores),
-           "kind": "oracle",
+           "kind": "oracle", "host_cpu": model, "host_cpus_visible": cores,
            "sample": f"{k} of {wl_def.batch} fields through the first {nl} of {wl_def.layers} "
                      f"layers, fwd+bwd with MSE loss ({props} FP64 propagations at the same "
                      f"1024^2 -> 2048^2 shape, {dt:.1f} s; OpenMP over fields)"}
