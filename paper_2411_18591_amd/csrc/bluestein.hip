@@ -109,6 +109,26 @@ __global__ void __launch_bounds__(TC * (M / R)) bluestein_cols_kernel(cx<T>* a, 
   }
 }
 
+// 32 x 32 tiles through LDS (one padding column: conflict-free columns).
+template <typename T>
+__global__ void __launch_bounds__(256) bluestein_transpose_kernel(const cx<T>* __restrict__ in,
+                                                                  cx<T>* __restrict__ out, int rows, int cols) {
+  __shared__ cx<T> tile[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) {
+    const int r = r0 + ty + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[ty + k][tx] = in[(int64_t)r * cols + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) {
+    const int c = c0 + ty + k, r = r0 + tx;
+    if (r < rows && c < cols) out[(int64_t)c * rows + r] = tile[tx][ty + k];
+  }
+}
+
 namespace {
 template <typename F>
 hipError_t dispatch_pow2(int M, F&& f) {
@@ -157,6 +177,13 @@ hipError_t Bluestein<T>::cols(const LineFft<T>& f, cx<T>* a, int lx, int dir, hi
                        dim3(C::threads), 0, s, a, f.L, lx, dir, f.w, f.Bf, f.tw);
     return hipGetLastError();
   });
+}
+
+template <typename T>
+hipError_t Bluestein<T>::transpose(const cx<T>* in, cx<T>* out, int rows, int cols, hipStream_t s) {
+  hipLaunchKernelGGL((bluestein_transpose_kernel<T>), dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, s, in,
+                     out, rows, cols);
+  return hipGetLastError();
 }
 
 template struct Bluestein<float>;

@@ -27,6 +27,8 @@ struct Bluestein {
   // row-major [f.L][lx] array.
   static hipError_t rows(const LineFft<T>& f, cx<T>* a, int nrows, int dir, hipStream_t s);
   static hipError_t cols(const LineFft<T>& f, cx<T>* a, int lx, int dir, hipStream_t s);
+  // out[c][r] = in[r][c] for a row-major rows x cols array.
+  static hipError_t transpose(const cx<T>* in, cx<T>* out, int rows, int cols, hipStream_t s);
 };
 
 }  // namespace toprop

@@ -1414,12 +1414,14 @@ struct PlainWork {
   cx<T>* tmp;
   cx<T>* tmp2;
   double* partial;
+  cx<T>* tr;  // transpose buffer of the Bluestein column passes (non-power-of-two grids), or null
 };
 
 template <typename T>
 size_t plain_bytes(const to_job& j) {
   const size_t npad = (size_t)j.py * j.px, nf = (size_t)j.ny * j.nx;
-  return (2 * npad + 2 * nf) * sizeof(cx<T>) + 1024 * sizeof(double);
+  const size_t tr = is_pow2(j.py) ? 0 : npad;  // columns of Bluestein length run as transposed rows
+  return (2 * npad + 2 * nf + tr) * sizeof(cx<T>) + 1024 * sizeof(double);
 }
 
 // Jobs of to_propagate / to_propagate_backward whose padded grid is not a
@@ -1452,6 +1454,7 @@ to_status plain_setup(const to_job& j, DeviceCtx* c, bool conj, hipStream_t s, P
   w->tmp = w->pad + npad;
   w->tmp2 = w->tmp + nf;
   w->partial = (double*)(w->tmp2 + nf);
+  w->tr = is_pow2(j.py) ? nullptr : (cx<T>*)(w->partial + 1024);
   TransferParams h = make_transfer(j, conj);
   if (h.table) {  // direct integration: the call's (or the caller's) table
     w->H = (cx<T>*)h.table;
@@ -1490,6 +1493,7 @@ to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
     pj.el = make_element<T>(j, j.el_flags);
     pj.fx = w.fx;
     pj.fy = w.fy;
+    pj.tr = w.tr;
     hipError_t e = timed("plain.propagate", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain propagation");
     if (j.epi != TO_EPI_NONE) {
@@ -1531,6 +1535,7 @@ to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, h
     pj.el = make_element<T>(j, 0);
     pj.fx = w.fx;
     pj.fy = w.fy;
+    pj.tr = w.tr;
     hipError_t e = timed("plain.adjoint", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain adjoint");
     if (gr.grad_phase && (j.el_flags & TO_EL_PHASE) && gr.saved_in) {

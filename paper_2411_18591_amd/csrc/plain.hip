@@ -174,13 +174,13 @@ hipError_t Plain<T>::run(const PlainJob<T>& pj, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // 3-4. forward FFT: rows, then columns
   if ((e = rows_any(pj.fx, pj.pad, py, -1, s)) != hipSuccess) return e;
-  if ((e = cols_any(pj.fy, pj.pad, px, -1, s)) != hipSuccess) return e;
+  if ((e = cols_any(pj.fy, pj.pad, px, -1, s, pj.tr)) != hipSuccess) return e;
   // 5. transfer function from the stored table
   hipLaunchKernelGGL((plain_mul_kernel<T>), dim3(grid_for(npad)), dim3(256), 0, s, pj.pad, pj.H, npad,
                      pj.conj);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // 6-7. inverse FFT: columns, then rows
-  if ((e = cols_any(pj.fy, pj.pad, px, +1, s)) != hipSuccess) return e;
+  if ((e = cols_any(pj.fy, pj.pad, px, +1, s, pj.tr)) != hipSuccess) return e;
   if ((e = rows_any(pj.fx, pj.pad, py, +1, s)) != hipSuccess) return e;
   // 8. crop and scale
   hipLaunchKernelGGL((plain_crop_kernel<T>), dim3(grid_for(nf)), dim3(256), 0, s, pj.pad, pj.out, ny, nx,
@@ -233,8 +233,14 @@ hipError_t Plain<T>::rows_any(const LineFft<T>& f, cx<T>* a, int nrows, int dir,
 }
 
 template <typename T>
-hipError_t Plain<T>::cols_any(const LineFft<T>& f, cx<T>* a, int lx, int dir, hipStream_t s) {
-  return f.M == 0 ? cols(f.L, a, lx, dir, f.tw, s) : Bluestein<T>::cols(f, a, lx, dir, s);
+hipError_t Plain<T>::cols_any(const LineFft<T>& f, cx<T>* a, int lx, int dir, hipStream_t s, cx<T>* tr) {
+  if (f.M == 0) return cols(f.L, a, lx, dir, f.tw, s);
+  if (!tr) return Bluestein<T>::cols(f, a, lx, dir, s);
+  // strided columns gather poorly: transpose, transform rows, transpose back
+  hipError_t e;
+  if ((e = Bluestein<T>::transpose(a, tr, f.L, lx, s)) != hipSuccess) return e;
+  if ((e = Bluestein<T>::rows(f, tr, lx, dir, s)) != hipSuccess) return e;
+  return Bluestein<T>::transpose(tr, a, lx, f.L, s);
 }
 
 template <typename T>

@@ -20,6 +20,7 @@ struct PlainJob {
   ElementParams<T> el;  // forward element (flags 0 = none)
   LineFft<T> fx;        // transforms of length px
   LineFft<T> fy;        // transforms of length py
+  cx<T>* tr;            // [px][py] workspace for Bluestein columns, or null
 };
 
 template <typename T>
@@ -30,7 +31,9 @@ struct Plain {
   static hipError_t cols(int L, cx<T>* a, int lx, int dir, const cx<T>* tw, hipStream_t s);
   // Any length: the power-of-two passes above, or Bluestein's transform.
   static hipError_t rows_any(const LineFft<T>& f, cx<T>* a, int nrows, int dir, hipStream_t s);
-  static hipError_t cols_any(const LineFft<T>& f, cx<T>* a, int lx, int dir, hipStream_t s);
+  // Bluestein columns run as rows of the transposed array when `tr` (f.L *
+  // lx elements) is given, else column-wise.
+  static hipError_t cols_any(const LineFft<T>& f, cx<T>* a, int lx, int dir, hipStream_t s, cx<T>* tr = nullptr);
   static hipError_t loss(const cx<T>* u, const T* ref, cx<T>* grad, double* partial, int64_t n, int kind,
                          T scale, int* nblocks, hipStream_t s);
   static hipError_t modulate(const cx<T>* in, cx<T>* out, int ny, int nx, const ElementParams<T>& el, int conj,
