@@ -559,8 +559,9 @@ def run_resample(args):
 def run_anylength(args):
     """Padding that is not a power of two: 16 complex64 fields of 1000^2
     (8 um, 700 nm, AS 10 cm, phase mask) padded 2x to 2000^2 (the unfused
-    path with Bluestein transforms), forward and adjoint, beside the same
-    fields padded to 2048^2 (the fused path)."""
+    path with mixed-radix line transforms), forward and adjoint, beside the
+    same fields padded to 2002^2 (2 * 7 * 11 * 13: Bluestein line transforms)
+    and to 2048^2 (the fused path)."""
     import numpy as np
     import torch
 
@@ -573,8 +574,8 @@ def run_anylength(args):
     u = torch.randn((B, n, n), dtype=torch.complex64, device=dev, generator=gen)
     phi = torch.rand((n, n), dtype=torch.float32, device=dev, generator=gen) * 6.2832
     res = {}
-    for name, rp in (("2000", False), ("2048", True)):
-        opt = tp.Optics(dy=8e-6, dx=8e-6, wavelength=0.7e-6, z=0.1, pad=2, round_pow2=rp)
+    for name, P in (("2000", 2000), ("2002", 2002), ("2048", 2048)):
+        opt = tp.Optics(dy=8e-6, dx=8e-6, wavelength=0.7e-6, z=0.1, padded=(P, P))
         out = torch.empty_like(u)
         gin = torch.empty_like(u)
 
@@ -603,11 +604,11 @@ def run_anylength(args):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c64", "data": "synthetic (seeded complex Gaussian fields, uniform phase mask)",
         "config": {"workload": f"{B} x {n}^2 complex64, AS z = 10 cm, 8 um, 700 nm, phase mask, padded 2x to "
-                               "2000^2 (unfused path, Bluestein transforms); the same fields padded to 2048^2 "
-                               "(fused path) for comparison"},
+                               "2000^2 (unfused path, mixed-radix line transforms); the same fields padded to "
+                               "2002^2 (Bluestein line transforms) and 2048^2 (fused path) for comparison"},
         "hbm_roofline_step": {"algorithmic_bytes": step_bytes,
                               "frac": round(step_bytes / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9), 5)},
-        "pow2_2048": res["2048"], "roofline": None, "cpu_baseline": None}))
+        "bluestein_2002": res["2002"], "pow2_2048": res["2048"], "roofline": None, "cpu_baseline": None}))
     return 0
 
 

@@ -36,7 +36,8 @@
  *   the job; the field may be ragged (e.g. 1000 x 1000 padded to 2048 x
  *   2048).  Padded extents are powers of two in [8, 8192] (the fused
  *   kernels) or other lengths in [3, 4096] (e.g. 2000: an unfused pipeline
- *   whose lines are transformed by Bluestein's method, chosen automatically;
+ *   whose lines are transformed by a mixed-radix FFT when the length is
+ *   2^a 3^b 5^c 7^d, else by Bluestein's method, chosen automatically;
  *   without Jones elements, the intensity epilogue, the lens gradient or
  *   coherence propagation, which return TO_E_UNSUPPORTED there, and with a
  *   stream synchronization on the first use of each such length).  The operator is the circular

@@ -123,7 +123,7 @@ class Optics:
     The padded grid is ``padded`` = (py, px) if given, else each extent is
     ``pad`` times the field, rounded up to a power of two unless
     ``round_pow2`` is False (extents that are not powers of two, up to 4096,
-    run through the unfused path with Bluestein transforms).  ``method`` is
+    run through the unfused path with mixed-radix or Bluestein transforms).  ``method`` is
     "asm", "fresnel", "di" (direct integration; needs pad >= 2 and z > 0) or
     "auto" (DI at or beyond the critical distance, AS below it)."""
     dy: float

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "mixed.hpp"
 
 namespace toprop {
 
@@ -12,10 +13,11 @@ namespace toprop {
 template <typename T>
 struct LineFft {
   int L;            // transform length
-  int M;            // 0: L is a power of two; else the convolution length (power of two >= 2L - 1)
-  const cx<T>* tw;  // twiddles of length L (power of two) or M
+  int M;            // 0: L is a power of two or mixed-radix; else the convolution length (power of two >= 2L - 1)
+  const cx<T>* tw;  // twiddles of length L (power of two or mixed-radix) or M
   const cx<T>* w;   // chirp exp(i pi n^2 / L), n < L (Bluestein only)
   const cx<T>* Bf;  // length-M DFT of the chirp kernel (Bluestein only)
+  MixedPlan mp;     // mp.np > 0: L = 2^a 3^b 5^c 7^d, transformed by the mixed-radix passes
 };
 
 template <typename T>

@@ -108,7 +108,9 @@ struct DeviceCtx {
   size_t rs_bytes = 0;
   void* acc = nullptr;    // private intensity accumulators of the lanes of a call
   size_t acc_bytes = 0;
-  // Bluestein tables of the non-power-of-two lengths used so far
+  // Tables of the non-power-of-two lengths used so far: Bluestein's chirp
+  // and kernel spectrum (M > 0), or the twiddles of a mixed-radix length
+  // (M = -1, twiddles in w)
   struct Blue {
     int L;
     bool dbl;
@@ -342,9 +344,9 @@ hipError_t timed(const char* name, int L, bool dbl, hipStream_t s, F&& f) {
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 // Padded extents: powers of two in [kMinLen, kMaxLen] (the fused path), or
-// other lengths up to kMaxAnyLen, transformed by Bluestein's method in the
-// plain path (the convolution length, a power of two >= 2L - 1, stays
-// within kMaxLen).
+// other lengths up to kMaxAnyLen, transformed in the plain path by the
+// mixed-radix passes (2^a 3^b 5^c 7^d) or by Bluestein's method (whose
+// convolution length, a power of two >= 2L - 1, stays within kMaxLen).
 constexpr int kMaxAnyLen = 4096;
 bool extent_ok(int64_t L) {
   return is_pow2(L) ? (L >= kMinLen && L <= kMaxLen) : (L >= 3 && L <= kMaxAnyLen);
@@ -554,14 +556,35 @@ to_status line_fft(DeviceCtx* c, int L, hipStream_t s, LineFft<T>* out) {
   out->L = L;
   out->M = 0;
   out->w = out->Bf = nullptr;
+  out->mp.np = 0;
   if (is_pow2(L)) {
     out->tw = twiddles<T>(c, L);
     return TO_OK;
   }
+  const bool dbl = sizeof(T) == 8;
+  MixedPlan mp;
+  if (mixed_plan(L, &mp)) {
+    // 2^a 3^b 5^c 7^d: the mixed-radix passes with twiddles of length L
+    // (kept in the Bluestein cache with M = -1 and no chirp tables)
+    for (const auto& b : c->blue)
+      if (b.L == L && b.dbl == dbl && b.M < 0) {
+        out->tw = (const cx<T>*)b.w;
+        out->mp = mp;
+        return TO_OK;
+      }
+    DeviceCtx::Blue b{L, dbl, -1, nullptr, nullptr};
+    hipError_t e = hipMalloc(&b.w, sizeof(cx<T>) * L);
+    if (e != hipSuccess) return fail(TO_E_NOMEM, "mixed-radix twiddles: %s", hipGetErrorString(e));
+    if ((e = Mixed<T>::twiddles(L, (cx<T>*)b.w, s)) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess) {
+      (void)hipFree(b.w);
+      return hip_fail(e, "mixed-radix twiddles");
+    }
+    c->blue.push_back(b);
+    return line_fft<T>(c, L, s, out);
+  }
   int M = 1;
   while (M < 2 * L - 1) M *= 2;
   if (M > kMaxLen) return fail(TO_E_UNSUPPORTED, "length %d is too long for Bluestein's transform", L);
-  const bool dbl = sizeof(T) == 8;
   for (const auto& b : c->blue)
     if (b.L == L && b.dbl == dbl) {
       out->M = b.M;
@@ -1414,13 +1437,14 @@ struct PlainWork {
   cx<T>* tmp;
   cx<T>* tmp2;
   double* partial;
-  cx<T>* tr;  // transpose buffer of the Bluestein column passes (non-power-of-two grids), or null
+  cx<T>* tr;  // transpose buffer of the column passes of non-power-of-two grids, or null
+  bool fast;  // Plain::run_mixed applies (the table is stored transposed)
 };
 
 template <typename T>
 size_t plain_bytes(const to_job& j) {
   const size_t npad = (size_t)j.py * j.px, nf = (size_t)j.ny * j.nx;
-  const size_t tr = is_pow2(j.py) ? 0 : npad;  // columns of Bluestein length run as transposed rows
+  const size_t tr = (is_pow2(j.py) && is_pow2(j.px)) ? 0 : npad;  // columns run as transposed rows
   return (2 * npad + 2 * nf + tr) * sizeof(cx<T>) + 1024 * sizeof(double);
 }
 
@@ -1454,15 +1478,24 @@ to_status plain_setup(const to_job& j, DeviceCtx* c, bool conj, hipStream_t s, P
   w->tmp = w->pad + npad;
   w->tmp2 = w->tmp + nf;
   w->partial = (double*)(w->tmp2 + nf);
-  w->tr = is_pow2(j.py) ? nullptr : (cx<T>*)(w->partial + 1024);
+  const bool pow2 = is_pow2(j.py) && is_pow2(j.px);
+  w->tr = pow2 ? nullptr : (cx<T>*)(w->partial + 1024);
+  MixedPlan qy, qx;
+  w->fast = !pow2 && mixed_plan(j.py, &qy, true) && mixed_plan(j.px, &qx, true);
   TransferParams h = make_transfer(j, conj);
+  hipError_t e;
   if (h.table) {  // direct integration: the call's (or the caller's) table
-    w->H = (cx<T>*)h.table;
-    return TO_OK;
+    if (!w->fast) {
+      w->H = (cx<T>*)h.table;
+      return TO_OK;
+    }
+    e = timed("plain.table", j.px, sizeof(T) == 8, s,
+              [&] { return Bluestein<T>::transpose((const cx<T>*)h.table, w->H, j.py, j.px, s); });
+    return e == hipSuccess ? TO_OK : hip_fail(e, "plain table transpose");
   }
   h.conj = 0;  // the table holds H; the multiply kernel conjugates
-  hipError_t e = timed("plain.table", j.px, sizeof(T) == 8, s,
-                       [&] { return Plain<T>::table(w->H, j.py, j.px, h, s); });
+  e = timed("plain.table", j.px, sizeof(T) == 8, s,
+            [&] { return Plain<T>::table(w->H, j.py, j.px, h, s, w->fast); });
   if (e != hipSuccess) return hip_fail(e, "plain table launch");
   return TO_OK;
 }
@@ -1494,6 +1527,7 @@ to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
     pj.fx = w.fx;
     pj.fy = w.fy;
     pj.tr = w.tr;
+    pj.ht = w.fast ? 1 : 0;
     hipError_t e = timed("plain.propagate", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain propagation");
     if (j.epi != TO_EPI_NONE) {
@@ -1536,6 +1570,7 @@ to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, h
     pj.fx = w.fx;
     pj.fy = w.fy;
     pj.tr = w.tr;
+    pj.ht = w.fast ? 1 : 0;
     hipError_t e = timed("plain.adjoint", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain adjoint");
     if (gr.grad_phase && (j.el_flags & TO_EL_PHASE) && gr.saved_in) {

@@ -6,7 +6,8 @@
 // intermediate is a full array in HBM.  The FFT building blocks are the same
 // Stockham register/LDS transforms as the fused path; only the fusion and the
 // batching are absent.  It is also the path for padded extents that are not
-// powers of two, whose lines go through Bluestein's transform.
+// powers of two: their lines go through the mixed-radix transform (lengths
+// 2^a 3^b 5^c 7^d, with the fused sequence of run_mixed) or Bluestein's.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -54,11 +55,13 @@ __global__ void __launch_bounds__(256) plain_crop_kernel(const cx<T>* pad, cx<T>
 
 // Transfer function of every bin of the padded grid, stored as a table.
 template <typename T>
-__global__ void __launch_bounds__(256) plain_table_kernel(cx<T>* H, int py, int px, TransferParams p) {
+__global__ void __launch_bounds__(256) plain_table_kernel(cx<T>* H, int py, int px, TransferParams p,
+                                                          int transposed) {
   const int64_t n = (int64_t)py * px;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int ky = (int)(i / px), kx = (int)(i % px);
+    const int ky = transposed ? (int)(i % py) : (int)(i / px);
+    const int kx = transposed ? (int)(i / py) : (int)(i % px);
     H[i] = transfer_at<T>(kx, ky, px, py, p);
   }
 }
@@ -156,7 +159,68 @@ int grid_for(int64_t n) {
 }  // namespace
 
 template <typename T>
+hipError_t Plain<T>::run_mixed(const PlainJob<T>& pj, hipStream_t s) {
+  const int ny = pj.ny, nx = pj.nx, py = pj.py, px = pj.px;
+  MixedPlan qx = pj.fx.mp, qy = pj.fy.mp;  // power-of-two extents: plans of radix 16, 8, 4, 2
+  if ((!qx.np && !mixed_plan(px, &qx, true)) || (!qy.np && !mixed_plan(py, &qy, true)) || !pj.tr)
+    return hipErrorInvalidValue;
+  hipError_t e;
+  const cx<T>* src = pj.in;
+  if (pj.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) {
+    hipLaunchKernelGGL((plain_modulate_kernel<T>), dim3(grid_for((int64_t)ny * nx)), dim3(256), 0, s, pj.in,
+                       pj.tmp, ny, nx, pj.el, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    src = pj.tmp;
+  }
+  // rows: the ny field rows, zero-extended to px, into pad [ny][px]
+  MixedArgs<T> r{};
+  r.in = src;
+  r.in_ls = nx;
+  r.in_es = 1;
+  r.nin = nx;
+  r.out = pj.pad;
+  r.out_ls = px;
+  r.out_es = 1;
+  r.nout = px;
+  r.scale = T(1);
+  r.nlines = ny;
+  r.L = px;
+  r.plan = qx;
+  r.tw = pj.fx.tw;
+  if ((e = Mixed<T>::launch(r, -1, s)) != hipSuccess) return e;
+  // columns as rows of tr [px][ny]: zero-extended to py, forward, times the
+  // transposed table, inverse, cropped to ny, in place
+  if ((e = Bluestein<T>::transpose(pj.pad, pj.tr, ny, px, s)) != hipSuccess) return e;
+  MixedArgs<T> c{};
+  c.in = pj.tr;
+  c.out = pj.tr;
+  c.in_ls = c.out_ls = ny;
+  c.in_es = c.out_es = 1;
+  c.nin = c.nout = ny;
+  c.h = pj.H;
+  c.h_ls = py;
+  c.conj = pj.conj;
+  c.scale = T(1);
+  c.nlines = px;
+  c.L = py;
+  c.plan = qy;
+  c.tw = pj.fy.tw;
+  if ((e = Mixed<T>::launch(c, 0, s)) != hipSuccess) return e;
+  if ((e = Bluestein<T>::transpose(pj.tr, pj.pad, px, ny, s)) != hipSuccess) return e;
+  // inverse rows, cropped to nx and scaled, into the output
+  r.in = pj.pad;
+  r.in_ls = px;
+  r.nin = px;
+  r.out = pj.out;
+  r.out_ls = nx;
+  r.nout = nx;
+  r.scale = (T)(1.0 / ((double)py * (double)px));
+  return Mixed<T>::launch(r, +1, s);
+}
+
+template <typename T>
 hipError_t Plain<T>::run(const PlainJob<T>& pj, hipStream_t s) {
+  if (pj.ht) return run_mixed(pj, s);
   const int ny = pj.ny, nx = pj.nx, py = pj.py, px = pj.px;
   const int64_t npad = (int64_t)py * px, nf = (int64_t)ny * nx;
   hipError_t e;
@@ -189,9 +253,9 @@ hipError_t Plain<T>::run(const PlainJob<T>& pj, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t Plain<T>::table(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s) {
+hipError_t Plain<T>::table(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s, bool transposed) {
   hipLaunchKernelGGL((plain_table_kernel<T>), dim3(grid_for((int64_t)py * px)), dim3(256), 0, s, H, py, px,
-                     p);
+                     p, transposed ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -229,17 +293,22 @@ hipError_t Plain<T>::cols(int L, cx<T>* a, int lx, int dir, const cx<T>* tw, hip
 
 template <typename T>
 hipError_t Plain<T>::rows_any(const LineFft<T>& f, cx<T>* a, int nrows, int dir, hipStream_t s) {
+  if (f.mp.np > 0) return Mixed<T>::lines(f.L, f.mp, f.tw, a, nrows, f.L, 1, dir, s);
   return f.M == 0 ? rows(f.L, a, nrows, dir, f.tw, s) : Bluestein<T>::rows(f, a, nrows, dir, s);
 }
 
 template <typename T>
 hipError_t Plain<T>::cols_any(const LineFft<T>& f, cx<T>* a, int lx, int dir, hipStream_t s, cx<T>* tr) {
-  if (f.M == 0) return cols(f.L, a, lx, dir, f.tw, s);
-  if (!tr) return Bluestein<T>::cols(f, a, lx, dir, s);
+  const bool mixed = f.mp.np > 0;
+  if (!mixed && f.M == 0) return cols(f.L, a, lx, dir, f.tw, s);
+  if (!tr)
+    return mixed ? Mixed<T>::lines(f.L, f.mp, f.tw, a, lx, 1, lx, dir, s) : Bluestein<T>::cols(f, a, lx, dir, s);
   // strided columns gather poorly: transpose, transform rows, transpose back
   hipError_t e;
   if ((e = Bluestein<T>::transpose(a, tr, f.L, lx, s)) != hipSuccess) return e;
-  if ((e = Bluestein<T>::rows(f, tr, lx, dir, s)) != hipSuccess) return e;
+  if ((e = mixed ? Mixed<T>::lines(f.L, f.mp, f.tw, tr, lx, f.L, 1, dir, s) : Bluestein<T>::rows(f, tr, lx, dir, s)) !=
+      hipSuccess)
+    return e;
   return Bluestein<T>::transpose(tr, a, lx, f.L, s);
 }
 

@@ -21,12 +21,20 @@ struct PlainJob {
   LineFft<T> fx;        // transforms of length px
   LineFft<T> fy;        // transforms of length py
   cx<T>* tr;            // [px][py] workspace for Bluestein columns, or null
+  int ht;               // 1: H is stored transposed ([px][py]) and the job takes run_mixed
 };
 
 template <typename T>
 struct Plain {
   static hipError_t run(const PlainJob<T>& pj, hipStream_t s);
-  static hipError_t table(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s);
+  // Grids with an extent that is not a power of two and both extents of the
+  // form 2^a 3^b 5^c 7^d (<= 4096): zero padding, crop, the transfer
+  // function and both column transforms fused into three mixed-radix
+  // launches around two transposes, and only the ny rows that are not zero
+  // transformed.  Needs H transposed (pj.ht) and tr of px * ny elements.
+  static hipError_t run_mixed(const PlainJob<T>& pj, hipStream_t s);
+  // The table of every bin, [py][px], or [px][py] with `transposed`.
+  static hipError_t table(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s, bool transposed = false);
   static hipError_t rows(int L, cx<T>* a, int nrows, int dir, const cx<T>* tw, hipStream_t s);
   static hipError_t cols(int L, cx<T>* a, int lx, int dir, const cx<T>* tw, hipStream_t s);
   // Any length: the power-of-two passes above, or Bluestein's transform.

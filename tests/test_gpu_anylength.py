@@ -1,12 +1,16 @@
 """Padded grids whose extents are not powers of two (the paper's own
 examples pad 1000, 250 and 50 samples to 2000, 500 and 100): the library
-runs them through its unfused path, transforming each line with Bluestein's
-chirp-z method on its power-of-two FFTs.  Against the FP64 oracle (whose
-transform of such lengths is the naive DFT, pinned on the CPU): even and odd
-lengths, AS / Fresnel / DI (at the smallest admissible DI padding, 2n - 1),
-forward and adjoint, elements, the MSE epilogue and the mask gradient,
-mixed with power-of-two jobs in one call; at the paper's 1000^2 -> 2000^2
-scale, a separable Fresnel Gaussian against the oracle's 1-D transforms."""
+runs them through its unfused path, transforming each line with the
+mixed-radix passes (lengths 2^a 3^b 5^c 7^d) or with Bluestein's chirp-z
+method on its power-of-two FFTs (any other length).  Against the FP64 oracle
+(whose transform of such lengths is the naive DFT, pinned on the CPU): even
+and odd lengths, every radix (2, 3, 4, 5, 7, 8, 16), both line methods in
+one job, a line of 2100 points (256 threads per line), AS / Fresnel / DI (at
+the smallest admissible DI padding, 2n - 1), forward and adjoint, elements,
+the MSE epilogue and the mask gradient, mixed with power-of-two jobs in one
+call; at the paper's 1000^2 -> 2000^2 scale (and 2002^2, a Bluestein
+length), a separable Fresnel Gaussian against the oracle's 1-D
+transforms."""
 import numpy as np
 import pytest
 
@@ -33,13 +37,17 @@ def _oracle(u, opt, adjoint=False):
 
 
 CASES = [
-    # (ny, nx, py, px, method)
-    (25, 15, 50, 30, "asm"),      # even, 2x padding
-    (24, 40, 49, 81, "fresnel"),  # odd extents
-    (50, 50, 100, 100, "asm"),    # the paper's 50^2 example, padded 2x
-    (30, 17, 59, 33, "di"),       # DI at 2n - 1 (odd)
-    (2, 3, 3, 5, "asm"),          # the smallest lengths
+    # (ny, nx, py, px, method); line methods: M mixed-radix, B Bluestein
+    (25, 15, 50, 30, "asm"),      # even, 2x padding (M 2*5*5, M 2*5*3)
+    (24, 40, 49, 81, "fresnel"),  # odd extents (M 7*7, M 3^4)
+    (50, 50, 100, 100, "asm"),    # the paper's 50^2 example, padded 2x (M 4*5*5)
+    (30, 17, 59, 33, "di"),       # DI at 2n - 1 (odd; B 59, B 33)
+    (20, 13, 40, 25, "di"),       # DI at 2n - 1 and 2n (M 8*5, M 5*5)
+    (2, 3, 3, 5, "asm"),          # the smallest lengths (M 3, M 5)
     (20, 36, 20, 64, "fresnel"),  # one extent unpadded and not a power of two, the other a power of two
+    (26, 20, 53, 40, "asm"),      # B 53 columns, M 8*5 rows
+    (105, 9, 210, 18, "fresnel"), # every odd radix (M 2*5*3*7, M 2*3*3)
+    (2, 1050, 3, 2100, "asm"),    # long mixed-radix rows, 256 threads per line (M 3, M 4*5*5*3*7)
 ]
 
 
@@ -50,7 +58,7 @@ def test_forward_and_adjoint(case, dtype):
     ny, nx, py, px, method = case
     announce(f"any-length {case} {dtype.__name__}")
     rng = np.random.default_rng(1200 + ny * nx)
-    u = crandn(rng, 3, ny, nx, dtype=dtype)
+    u = crandn(rng, 1 if px > 1000 else 3, ny, nx, dtype=dtype)
     z = 1.5 * oracle.critical_distance(ny, nx, 4e-6, 5e-6, 0.6e-6) if method == "di" else 3e-4
     opt = tp.Optics(dy=4e-6, dx=5e-6, wavelength=0.6e-6, z=z, method=method, padded=(py, px))
     ug = to_gpu(u, torch)
@@ -122,20 +130,22 @@ def _prop1d(v, h, n):
     return oracle.dft(oracle.dft(x, -1) * h, +1)[:n] / h.size
 
 
+@pytest.mark.parametrize("P", [2000, 2002])
 @pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
-def test_paper_scale_separable(dtype):
-    """1000^2 Gaussian through a lens, Fresnel, padded to 2000^2 (the
-    paper's 4f grid at 2x padding): the field is separable, so every output
-    pixel is H(0,0) a(y) a(x) with a the 1-D propagation computed with the
-    oracle's naive DFT of length 2000 and its Fresnel transfer function."""
+def test_paper_scale_separable(dtype, P):
+    """1000^2 Gaussian through a lens, Fresnel, padded to P^2 (2000: the
+    paper's 4f grid at 2x padding, mixed-radix lines; 2002 = 2*7*11*13:
+    Bluestein lines): the field is separable, so every output pixel is
+    H(0,0) a(y) a(x) with a the 1-D propagation computed with the oracle's
+    naive DFT of length P and its Fresnel transfer function."""
     tp = _tp()
     n, d, lam, z, f, w0 = 1000, 10e-6, 700e-9, 0.05, 0.2, 1.5e-3
-    announce(f"any-length 1000^2 -> 2000^2 {dtype.__name__}")
+    announce(f"any-length 1000^2 -> {P}^2 {dtype.__name__}")
     g1 = workloads.gaussian_amplitude(n, 1, d, d, w0)[:, 0]
     l1 = oracle.lens(n, 1, d, d, lam, f)[:, 0]
-    col = oracle.transfer(2 * n, 1, d, d, lam, z, oracle.FRESNEL)[:, 0]
+    col = oracle.transfer(P, 1, d, d, lam, z, oracle.FRESNEL)[:, 0]
     a = _prop1d(g1 * l1, col / col[0], n)
-    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, method="fresnel", pad=2, round_pow2=False)
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, method="fresnel", padded=(P, P))
     u = workloads.gaussian_amplitude(n, n, d, d, w0).astype(dtype)[None]
     out = tp.propagate(to_gpu(u, torch), opt, lens_f=f)
     rows = np.array([0, 1, n // 3, n // 2, n - 1])
