@@ -107,8 +107,16 @@ struct LineIo {
   const cx<T>* in;
   cx<T>* out;
   const cx<T>* h;
-  int64_t in_es, out_es;
+  int in_es, out_es;  // q * es < 2^31: checked on the host
 };
+
+// b mod ns for b, ns <= 4096 from a float reciprocal of ns (uniform), with
+// one correction step: the quotient estimate is off by at most one.
+__device__ __forceinline__ int mod_small(int b, int ns, float inv_ns) {
+  int k = b - (int)((float)b * inv_ns) * ns;
+  k = k < 0 ? k + ns : k;
+  return k >= ns ? k - ns : k;
+}
 
 template <typename T, int R, int D, bool IN_G, bool OUT_G, bool MULH>
 __device__ __forceinline__ void mixed_pass(cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok, int NS,
@@ -117,26 +125,38 @@ __device__ __forceinline__ void mixed_pass(cx<T>* ll, const LineIo<T>& io, const
   const int L = a.L;
   const int nb = L / R;
   const int step = L / (NS * R);
+  const float inv_ns = 1.0f / (float)NS;
   cx<T> v[NB][R];
+  int kk[NB];
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
     const int b = j + t * TL;
     const bool act = b < nb;
+    kk[t] = NS > 1 ? mod_small(b, NS, inv_ns) : 0;
+    // Loads are unconditional (from a valid address) so that no branch
+    // surrounds them: a butterfly past nb is computed on whatever it read
+    // and never stored; padding (q >= nin) and absent lines select zero.
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int q = b + r * nb;
-      if constexpr (IN_G)
-        v[t][r] = (act && ok && q < a.nin) ? io.in[q * io.in_es] : cx<T>{T(0), T(0)};
-      else
-        v[t][r] = act ? ll[pidx(q)] : cx<T>{T(0), T(0)};
+      const int q = act ? b + r * nb : 0;
+      if constexpr (IN_G) {
+        const bool valid = ok && q < a.nin;
+        const cx<T> x = io.in[(valid ? q : 0) * io.in_es];
+        v[t][r] = valid ? x : cx<T>{T(0), T(0)};
+      } else {
+        v[t][r] = ll[pidx(q)];
+      }
     }
     if (NS > 1) {
-      const int k = b % NS;
+      // w^r for r < R from w = exp(D 2 pi i k / (NS R)): one table load, the
+      // rest by products (squares for even r)
+      cx<T> w[R];
+      w[1] = a.tw[kk[t] * step];  // k step < L
+      if (D > 0) w[1].y = -w[1].y;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const cx<T> w = a.tw[r * k * step];  // r k step < L
-        v[t][r] = D < 0 ? cmul(v[t][r], w) : cmulc(v[t][r], w);
-      }
+      for (int r = 2; r < R; ++r) w[r] = (r % 2 == 0) ? cmul(w[r / 2], w[r / 2]) : cmul(w[r - 1], w[1]);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[t][r] = cmul(v[t][r], w[r]);
     }
     small_dft<R, D, T>(v[t]);
   }
@@ -145,7 +165,7 @@ __device__ __forceinline__ void mixed_pass(cx<T>* ll, const LineIo<T>& io, const
   for (int t = 0; t < NB; ++t) {
     const int b = j + t * TL;
     if (b >= nb) continue;
-    const int k = b % NS;
+    const int k = kk[t];
     const int base = (b - k) * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -209,8 +229,8 @@ __global__ void __launch_bounds__(256) mixed_lines_kernel(MixedArgs<T> a) {
   const int line = blockIdx.x * G + g;
   const bool ok = line < a.nlines;
   const int64_t li = ok ? line : 0;
-  const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + li * a.h_ls : nullptr, a.in_es,
-                     a.out_es};
+  const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + li * a.h_ls : nullptr, (int)a.in_es,
+                     (int)a.out_es};
   cx<T>* ll = lds + g * (pidx(a.L - 1) + 1);
   if constexpr (MODE == 0) {
     mixed_transform<T, -1, true, false, true>(ll, io, a, ok, j, TL);
@@ -218,6 +238,149 @@ __global__ void __launch_bounds__(256) mixed_lines_kernel(MixedArgs<T> a) {
   } else {
     mixed_transform<T, MODE, true, true, false>(ll, io, a, ok, j, TL);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Lengths fixed at compile time (the paper's padded extents 2000, 500, 100
+// and 1000): the plan, strides and divisors are constants, every LDS and
+// global offset of a pass is an immediate from one per-butterfly base, and
+// the line needs no LDS padding: the first pass, whose natural stores
+// (position b R1 + r) would stride across the banks, stores output r of
+// butterfly b at r L/R1 + b instead, and the second pass reads position p
+// from (p mod R1) L/R1 + p / R1.  Global element strides are 1.
+// ---------------------------------------------------------------------------
+struct CPlan {
+  int np;
+  int r[kMixedMaxPasses];
+};
+constexpr CPlan cplan(int L) {
+  CPlan p{};
+  int a = L, e2 = 0;
+  while (a % 2 == 0) a /= 2, ++e2;
+  for (; e2 >= 4; e2 -= 4) p.r[p.np++] = 16;
+  if (e2 == 1 && p.np > 0)
+    p.r[p.np - 1] = 8, p.r[p.np++] = 4;
+  else if (e2 > 0)
+    p.r[p.np++] = 1 << e2;
+  for (int q : {5, 3, 7})
+    while (a % q == 0) a /= q, p.r[p.np++] = q;
+  return p;
+}
+constexpr int threads_per_line(int L) {
+  int t = 1;
+  while (kLinePoints * t < L) t *= 2;
+  return t;
+}
+
+template <typename T, int L, int R, int NS, int D, int R1, bool IN_G, bool OUT_G, bool MULH, bool IN_T, bool OUT_T>
+__device__ __forceinline__ void fixed_pass(cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok, int j) {
+  constexpr int TL = threads_per_line(L);
+  constexpr int NB = (kLinePoints + R - 1) / R;
+  constexpr int nb = L / R;
+  constexpr int step = L / (NS * R);
+  constexpr int nb1 = L / R1;
+  cx<T> v[NB][R];
+  int bb[NB], kk[NB];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    const int b = j + t * TL;
+    const int bs = (t * TL + TL <= nb || b < nb) ? b : 0;  // an absent butterfly reads butterfly 0
+    bb[t] = b;
+    kk[t] = bs % NS;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = bs + r * nb;
+      if constexpr (IN_G) {
+        const bool valid = ok && q < a.nin;
+        const cx<T> x = io.in[valid ? q : 0];
+        v[t][r] = valid ? x : cx<T>{T(0), T(0)};
+      } else if constexpr (IN_T) {
+        v[t][r] = ll[(q % R1) * nb1 + q / R1];
+      } else {
+        v[t][r] = ll[q];
+      }
+    }
+    if constexpr (NS > 1) {
+      cx<T> w[R];
+      w[1] = a.tw[kk[t] * step];
+      if (D > 0) w[1].y = -w[1].y;
+#pragma unroll
+      for (int r = 2; r < R; ++r) w[r] = (r % 2 == 0) ? cmul(w[r / 2], w[r / 2]) : cmul(w[r - 1], w[1]);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[t][r] = cmul(v[t][r], w[r]);
+    }
+    small_dft<R, D, T>(v[t]);
+  }
+  if constexpr (!IN_G && !OUT_G) __syncthreads();
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    const int b = bb[t];
+    if (t * TL + TL > nb && b >= nb) continue;
+    const int k = kk[t];
+    const int base = (b - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cx<T> y = v[t][r];
+      if constexpr (OUT_T) {
+        ll[b + r * nb] = y;
+      } else {
+        const int q = base + r * NS;
+        if constexpr (MULH) {
+          cx<T> h = io.h[q];
+          if (a.conj) h.y = -h.y;
+          y = cmul(y, h);
+        }
+        if constexpr (OUT_G) {
+          if (ok && q < a.nout) io.out[q] = cscale(y, a.scale);
+        } else {
+          ll[q] = y;
+        }
+      }
+    }
+  }
+  if constexpr (!OUT_G) __syncthreads();
+}
+
+template <typename T, int L, int D, int P, int NS, bool IN_G, bool OUT_G, bool MULH>
+__device__ __forceinline__ void fixed_passes(cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok,
+                                             int j) {
+  constexpr CPlan pl = cplan(L);
+  constexpr int R = pl.r[P];
+  constexpr bool first = P == 0, last = P == pl.np - 1;
+  fixed_pass<T, L, R, NS, D, pl.r[0], first && IN_G, last && OUT_G, last && MULH, P == 1, first && !last>(
+      ll, io, a, ok, j);
+  if constexpr (!last) fixed_passes<T, L, D, P + 1, NS * R, IN_G, OUT_G, MULH>(ll, io, a, ok, j);
+}
+
+template <typename T, int L, int MODE>
+__global__ void __launch_bounds__(256) mixed_fixed_kernel(MixedArgs<T> a) {
+  constexpr int TL = threads_per_line(L), G = 256 / TL;
+  __shared__ cx<T> lds[G * L];
+  const int g = threadIdx.x / TL, j = threadIdx.x % TL;
+  const int line = blockIdx.x * G + g;
+  const bool ok = line < a.nlines;
+  const int64_t li = ok ? line : 0;
+  const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + li * a.h_ls : nullptr, 1, 1};
+  cx<T>* ll = lds + g * L;
+  if constexpr (MODE == 0) {
+    fixed_passes<T, L, -1, 0, 1, true, false, true>(ll, io, a, ok, j);
+    fixed_passes<T, L, +1, 0, 1, false, true, false>(ll, io, a, ok, j);
+  } else {
+    fixed_passes<T, L, MODE, 0, 1, true, true, false>(ll, io, a, ok, j);
+  }
+}
+
+template <typename T, int L>
+hipError_t launch_fixed(const MixedArgs<T>& a, int mode, hipStream_t s) {
+  constexpr int G = 256 / threads_per_line(L);
+  const dim3 grid((a.nlines + G - 1) / G);
+  if (mode < 0)
+    hipLaunchKernelGGL((mixed_fixed_kernel<T, L, -1>), grid, dim3(256), 0, s, a);
+  else if (mode > 0)
+    hipLaunchKernelGGL((mixed_fixed_kernel<T, L, +1>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((mixed_fixed_kernel<T, L, 0>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -250,8 +413,20 @@ hipError_t Mixed<T>::launch(MixedArgs<T> a, int mode, hipStream_t s) {
     prod *= r;
   }
   if (prod != a.L || a.nin < 0 || a.nin > a.L || a.nout < 0 || a.nout > a.L) return hipErrorInvalidValue;
+  if (a.nin < 1 || a.nout < 1) return hipErrorInvalidValue;
+  if (a.in_es < 1 || a.out_es < 1 || a.in_es * a.L >= (int64_t(1) << 31) || a.out_es * a.L >= (int64_t(1) << 31))
+    return hipErrorInvalidValue;  // element offsets are 32-bit in the kernel
   if (mode == 0 && !a.h) return hipErrorInvalidValue;
   if (a.nlines <= 0) return hipSuccess;
+  if (a.in_es == 1 && a.out_es == 1) {
+    switch (a.L) {
+      case 2000: return launch_fixed<T, 2000>(a, mode, s);
+      case 1000: return launch_fixed<T, 1000>(a, mode, s);
+      case 500: return launch_fixed<T, 500>(a, mode, s);
+      case 100: return launch_fixed<T, 100>(a, mode, s);
+      default: break;
+    }
+  }
   int shift = 0;
   while ((kLinePoints << shift) < a.L) ++shift;  // L <= 16 TL, TL <= 256
   a.tl_shift = shift;

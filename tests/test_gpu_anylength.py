@@ -5,7 +5,8 @@ mixed-radix passes (lengths 2^a 3^b 5^c 7^d) or with Bluestein's chirp-z
 method on its power-of-two FFTs (any other length).  Against the FP64 oracle
 (whose transform of such lengths is the naive DFT, pinned on the CPU): even
 and odd lengths, every radix (2, 3, 4, 5, 7, 8, 16), both line methods in
-one job, a line of 2100 points (256 threads per line), AS / Fresnel / DI (at
+one job, a line of 2100 points (256 threads per line), the lengths with
+compile-time kernels (100, 500, 1000, 2000), AS / Fresnel / DI (at
 the smallest admissible DI padding, 2n - 1), forward and adjoint, elements,
 the MSE epilogue and the mask gradient, mixed with power-of-two jobs in one
 call; at the paper's 1000^2 -> 2000^2 scale (and 2002^2, a Bluestein
@@ -48,6 +49,8 @@ CASES = [
     (26, 20, 53, 40, "asm"),      # B 53 columns, M 8*5 rows
     (105, 9, 210, 18, "fresnel"), # every odd radix (M 2*5*3*7, M 2*3*3)
     (2, 1050, 3, 2100, "asm"),    # long mixed-radix rows, 256 threads per line (M 3, M 4*5*5*3*7)
+    (250, 7, 500, 14, "asm"),     # compile-time length 500 in the column launch (the paper's 250^2 padded)
+    (3, 500, 6, 1000, "fresnel"), # compile-time length 1000 in the row launches
 ]
 
 
