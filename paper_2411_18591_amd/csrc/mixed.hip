@@ -108,6 +108,7 @@ struct LineIo {
   cx<T>* out;
   const cx<T>* h;
   int in_es, out_es;  // q * es < 2^31: checked on the host
+  int line;
 };
 
 // b mod ns for b, ns <= 4096 from a float reciprocal of ns (uniform), with
@@ -118,7 +119,7 @@ __device__ __forceinline__ int mod_small(int b, int ns, float inv_ns) {
   return k >= ns ? k - ns : k;
 }
 
-template <typename T, int R, int D, bool IN_G, bool OUT_G, bool MULH>
+template <typename T, int R, int D, bool IN_G, bool OUT_G, bool MULH, bool EL>
 __device__ __forceinline__ void mixed_pass(cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok, int NS,
                                            int j, int TL) {
   constexpr int NB = (kLinePoints + R - 1) / R;  // butterflies per thread
@@ -141,7 +142,8 @@ __device__ __forceinline__ void mixed_pass(cx<T>* ll, const LineIo<T>& io, const
       const int q = act ? b + r * nb : 0;
       if constexpr (IN_G) {
         const bool valid = ok && q < a.nin;
-        const cx<T> x = io.in[(valid ? q : 0) * io.in_es];
+        cx<T> x = io.in[(valid ? q : 0) * io.in_es];
+        if constexpr (EL) x = cmul(scalar_modulation(a.el, a.nlines, a.nin, io.line, valid ? q : 0), x);
         v[t][r] = valid ? x : cx<T>{T(0), T(0)};
       } else {
         v[t][r] = ll[pidx(q)];
@@ -186,31 +188,31 @@ __device__ __forceinline__ void mixed_pass(cx<T>* ll, const LineIo<T>& io, const
   if constexpr (!OUT_G) __syncthreads();
 }
 
-template <typename T, int D, bool IN_G, bool OUT_G, bool MULH>
+template <typename T, int D, bool IN_G, bool OUT_G, bool MULH, bool EL = false>
 __device__ __forceinline__ void mixed_pass_r(int R, cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok,
                                              int NS, int j, int TL) {
   switch (R) {
-    case 2: mixed_pass<T, 2, D, IN_G, OUT_G, MULH>(ll, io, a, ok, NS, j, TL); break;
-    case 3: mixed_pass<T, 3, D, IN_G, OUT_G, MULH>(ll, io, a, ok, NS, j, TL); break;
-    case 4: mixed_pass<T, 4, D, IN_G, OUT_G, MULH>(ll, io, a, ok, NS, j, TL); break;
-    case 5: mixed_pass<T, 5, D, IN_G, OUT_G, MULH>(ll, io, a, ok, NS, j, TL); break;
-    case 7: mixed_pass<T, 7, D, IN_G, OUT_G, MULH>(ll, io, a, ok, NS, j, TL); break;
-    case 8: mixed_pass<T, 8, D, IN_G, OUT_G, MULH>(ll, io, a, ok, NS, j, TL); break;
-    default: mixed_pass<T, 16, D, IN_G, OUT_G, MULH>(ll, io, a, ok, NS, j, TL); break;
+    case 2: mixed_pass<T, 2, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
+    case 3: mixed_pass<T, 3, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
+    case 4: mixed_pass<T, 4, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
+    case 5: mixed_pass<T, 5, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
+    case 7: mixed_pass<T, 7, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
+    case 8: mixed_pass<T, 8, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
+    default: mixed_pass<T, 16, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
   }
 }
 
 // The passes of one transform: the first reads global memory (IN_G), the
 // last writes it (OUT_G) and/or multiplies by h (MULH).
-template <typename T, int D, bool IN_G, bool OUT_G, bool MULH>
+template <typename T, int D, bool IN_G, bool OUT_G, bool MULH, bool EL = false>
 __device__ __forceinline__ void mixed_transform(cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok,
                                                 int j, int TL) {
   const MixedPlan& p = a.plan;
   if (p.np == 1) {
-    mixed_pass_r<T, D, IN_G, OUT_G, MULH>(p.r[0], ll, io, a, ok, 1, j, TL);
+    mixed_pass_r<T, D, IN_G, OUT_G, MULH, EL>(p.r[0], ll, io, a, ok, 1, j, TL);
     return;
   }
-  mixed_pass_r<T, D, IN_G, false, false>(p.r[0], ll, io, a, ok, 1, j, TL);
+  mixed_pass_r<T, D, IN_G, false, false, EL>(p.r[0], ll, io, a, ok, 1, j, TL);
   int ns = p.r[0];
   for (int i = 1; i < p.np - 1; ++i) {
     mixed_pass_r<T, D, false, false, false>(p.r[i], ll, io, a, ok, ns, j, TL);
@@ -220,8 +222,9 @@ __device__ __forceinline__ void mixed_transform(cx<T>* ll, const LineIo<T>& io, 
 }
 
 // MODE -1 / +1: one forward / inverse transform per line; MODE 0: forward
-// transform, multiplication by the line's h, inverse transform.
-template <typename T, int MODE>
+// transform, multiplication by the line's h, inverse transform.  EL: the
+// forward transform applies a.el to what it reads.
+template <typename T, int MODE, bool EL>
 __global__ void __launch_bounds__(256) mixed_lines_kernel(MixedArgs<T> a) {
   __shared__ cx<T> lds[kMixedLds];
   const int TL = 1 << a.tl_shift, G = 256 >> a.tl_shift;
@@ -230,13 +233,13 @@ __global__ void __launch_bounds__(256) mixed_lines_kernel(MixedArgs<T> a) {
   const bool ok = line < a.nlines;
   const int64_t li = ok ? line : 0;
   const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + li * a.h_ls : nullptr, (int)a.in_es,
-                     (int)a.out_es};
+                     (int)a.out_es, (int)li};
   cx<T>* ll = lds + g * (pidx(a.L - 1) + 1);
   if constexpr (MODE == 0) {
     mixed_transform<T, -1, true, false, true>(ll, io, a, ok, j, TL);
     mixed_transform<T, +1, false, true, false>(ll, io, a, ok, j, TL);
   } else {
-    mixed_transform<T, MODE, true, true, false>(ll, io, a, ok, j, TL);
+    mixed_transform<T, MODE, true, true, false, EL>(ll, io, a, ok, j, TL);
   }
 }
 
@@ -272,7 +275,8 @@ constexpr int threads_per_line(int L) {
   return t;
 }
 
-template <typename T, int L, int R, int NS, int D, int R1, bool IN_G, bool OUT_G, bool MULH, bool IN_T, bool OUT_T>
+template <typename T, int L, int R, int NS, int D, int R1, bool IN_G, bool OUT_G, bool MULH, bool IN_T, bool OUT_T,
+          bool EL>
 __device__ __forceinline__ void fixed_pass(cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok, int j) {
   constexpr int TL = threads_per_line(L);
   constexpr int NB = (kLinePoints + R - 1) / R;
@@ -292,7 +296,8 @@ __device__ __forceinline__ void fixed_pass(cx<T>* ll, const LineIo<T>& io, const
       const int q = bs + r * nb;
       if constexpr (IN_G) {
         const bool valid = ok && q < a.nin;
-        const cx<T> x = io.in[valid ? q : 0];
+        cx<T> x = io.in[valid ? q : 0];
+        if constexpr (EL) x = cmul(scalar_modulation(a.el, a.nlines, a.nin, io.line, valid ? q : 0), x);
         v[t][r] = valid ? x : cx<T>{T(0), T(0)};
       } else if constexpr (IN_T) {
         v[t][r] = ll[(q % R1) * nb1 + q / R1];
@@ -341,32 +346,33 @@ __device__ __forceinline__ void fixed_pass(cx<T>* ll, const LineIo<T>& io, const
   if constexpr (!OUT_G) __syncthreads();
 }
 
-template <typename T, int L, int D, int P, int NS, bool IN_G, bool OUT_G, bool MULH>
+template <typename T, int L, int D, int P, int NS, bool IN_G, bool OUT_G, bool MULH, bool EL = false>
 __device__ __forceinline__ void fixed_passes(cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok,
                                              int j) {
   constexpr CPlan pl = cplan(L);
   constexpr int R = pl.r[P];
   constexpr bool first = P == 0, last = P == pl.np - 1;
-  fixed_pass<T, L, R, NS, D, pl.r[0], first && IN_G, last && OUT_G, last && MULH, P == 1, first && !last>(
-      ll, io, a, ok, j);
-  if constexpr (!last) fixed_passes<T, L, D, P + 1, NS * R, IN_G, OUT_G, MULH>(ll, io, a, ok, j);
+  fixed_pass<T, L, R, NS, D, pl.r[0], first && IN_G, last && OUT_G, last && MULH, P == 1, first && !last,
+             first && EL>(ll, io, a, ok, j);
+  if constexpr (!last) fixed_passes<T, L, D, P + 1, NS * R, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, j);
 }
 
-template <typename T, int L, int MODE>
-__global__ void __launch_bounds__(256) mixed_fixed_kernel(MixedArgs<T> a) {
+// The column launch of complex64 holds 128 registers (four waves per SIMD).
+template <typename T, int L, int MODE, bool EL>
+__global__ void __launch_bounds__(256, (MODE == 0 && sizeof(T) == 4) ? 4 : 1) mixed_fixed_kernel(MixedArgs<T> a) {
   constexpr int TL = threads_per_line(L), G = 256 / TL;
   __shared__ cx<T> lds[G * L];
   const int g = threadIdx.x / TL, j = threadIdx.x % TL;
   const int line = blockIdx.x * G + g;
   const bool ok = line < a.nlines;
   const int64_t li = ok ? line : 0;
-  const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + li * a.h_ls : nullptr, 1, 1};
+  const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + li * a.h_ls : nullptr, 1, 1, (int)li};
   cx<T>* ll = lds + g * L;
   if constexpr (MODE == 0) {
     fixed_passes<T, L, -1, 0, 1, true, false, true>(ll, io, a, ok, j);
     fixed_passes<T, L, +1, 0, 1, false, true, false>(ll, io, a, ok, j);
   } else {
-    fixed_passes<T, L, MODE, 0, 1, true, true, false>(ll, io, a, ok, j);
+    fixed_passes<T, L, MODE, 0, 1, true, true, false, EL>(ll, io, a, ok, j);
   }
 }
 
@@ -374,12 +380,14 @@ template <typename T, int L>
 hipError_t launch_fixed(const MixedArgs<T>& a, int mode, hipStream_t s) {
   constexpr int G = 256 / threads_per_line(L);
   const dim3 grid((a.nlines + G - 1) / G);
-  if (mode < 0)
-    hipLaunchKernelGGL((mixed_fixed_kernel<T, L, -1>), grid, dim3(256), 0, s, a);
+  if (mode < 0 && a.el.flags)
+    hipLaunchKernelGGL((mixed_fixed_kernel<T, L, -1, true>), grid, dim3(256), 0, s, a);
+  else if (mode < 0)
+    hipLaunchKernelGGL((mixed_fixed_kernel<T, L, -1, false>), grid, dim3(256), 0, s, a);
   else if (mode > 0)
-    hipLaunchKernelGGL((mixed_fixed_kernel<T, L, +1>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((mixed_fixed_kernel<T, L, +1, false>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((mixed_fixed_kernel<T, L, 0>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((mixed_fixed_kernel<T, L, 0, false>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -416,7 +424,8 @@ hipError_t Mixed<T>::launch(MixedArgs<T> a, int mode, hipStream_t s) {
   if (a.nin < 1 || a.nout < 1) return hipErrorInvalidValue;
   if (a.in_es < 1 || a.out_es < 1 || a.in_es * a.L >= (int64_t(1) << 31) || a.out_es * a.L >= (int64_t(1) << 31))
     return hipErrorInvalidValue;  // element offsets are 32-bit in the kernel
-  if (mode == 0 && !a.h) return hipErrorInvalidValue;
+  if ((mode == 0 && !a.h) || (mode > 0 && a.el.flags)) return hipErrorInvalidValue;
+  if (a.el.flags & ~(uint32_t)(EL_PHASE | EL_COMPLEX | EL_LENS)) return hipErrorInvalidValue;
   if (a.nlines <= 0) return hipSuccess;
   if (a.in_es == 1 && a.out_es == 1) {
     switch (a.L) {
@@ -432,12 +441,14 @@ hipError_t Mixed<T>::launch(MixedArgs<T> a, int mode, hipStream_t s) {
   a.tl_shift = shift;
   const int G = 256 >> shift;
   const dim3 grid((a.nlines + G - 1) / G);
-  if (mode < 0)
-    hipLaunchKernelGGL((mixed_lines_kernel<T, -1>), grid, dim3(256), 0, s, a);
+  if (mode < 0 && a.el.flags)
+    hipLaunchKernelGGL((mixed_lines_kernel<T, -1, true>), grid, dim3(256), 0, s, a);
+  else if (mode < 0)
+    hipLaunchKernelGGL((mixed_lines_kernel<T, -1, false>), grid, dim3(256), 0, s, a);
   else if (mode > 0)
-    hipLaunchKernelGGL((mixed_lines_kernel<T, +1>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((mixed_lines_kernel<T, +1, false>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((mixed_lines_kernel<T, 0>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((mixed_lines_kernel<T, 0, false>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

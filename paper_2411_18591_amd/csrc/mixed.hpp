@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "fft.hpp"
+#include "kernels.hpp"
 
 namespace toprop {
 
@@ -31,7 +32,9 @@ bool mixed_plan(int L, MixedPlan* p, bool pow2 = false);
 // out + i * out_ls (out[q * out_es]); in == out with equal strides is in
 // place.  With a transfer table h (the convolution mode), the forward
 // transform of line i is multiplied by h[i * h_ls + k] (conjugated if
-// `conj`) and transformed back.
+// `conj`) and transformed back.  A forward launch applies the element `el`
+// (phase mask, complex mask, lens; flags 0: none) to the field it reads,
+// taking line i as field row i of an nlines x nin field.
 template <typename T>
 struct MixedArgs {
   const cx<T>* in;
@@ -42,6 +45,7 @@ struct MixedArgs {
   T scale;
   MixedPlan plan;
   const cx<T>* tw;  // exp(-2 pi i m / L), m < L
+  ElementParams<T> el;
 };
 
 template <typename T>

@@ -165,16 +165,12 @@ hipError_t Plain<T>::run_mixed(const PlainJob<T>& pj, hipStream_t s) {
   if ((!qx.np && !mixed_plan(px, &qx, true)) || (!qy.np && !mixed_plan(py, &qy, true)) || !pj.tr)
     return hipErrorInvalidValue;
   hipError_t e;
-  const cx<T>* src = pj.in;
-  if (pj.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) {
-    hipLaunchKernelGGL((plain_modulate_kernel<T>), dim3(grid_for((int64_t)ny * nx)), dim3(256), 0, s, pj.in,
-                       pj.tmp, ny, nx, pj.el, 0);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    src = pj.tmp;
-  }
-  // rows: the ny field rows, zero-extended to px, into pad [ny][px]
+  // rows: the ny field rows, modulated by the element and zero-extended to
+  // px, into pad [ny][px]
   MixedArgs<T> r{};
-  r.in = src;
+  r.el = pj.el;
+  r.el.flags &= EL_PHASE | EL_COMPLEX | EL_LENS;
+  r.in = pj.in;
   r.in_ls = nx;
   r.in_es = 1;
   r.nin = nx;
@@ -208,6 +204,7 @@ hipError_t Plain<T>::run_mixed(const PlainJob<T>& pj, hipStream_t s) {
   if ((e = Mixed<T>::launch(c, 0, s)) != hipSuccess) return e;
   if ((e = Bluestein<T>::transpose(pj.tr, pj.pad, px, ny, s)) != hipSuccess) return e;
   // inverse rows, cropped to nx and scaled, into the output
+  r.el.flags = 0;
   r.in = pj.pad;
   r.in_ls = px;
   r.nin = px;

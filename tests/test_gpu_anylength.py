@@ -72,21 +72,23 @@ def test_forward_and_adjoint(case, dtype):
     assert rel(to_np(gin), _oracle(u, opt, adjoint=True)) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("shape", [(40, 30), (50, 50)])
 @pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
-def test_elements_loss_and_mask_gradient(dtype):
+def test_elements_loss_and_mask_gradient(dtype, shape):
     """Phase mask + lens, the MSE epilogue (loss and dL/du), and the
-    backward pass with the mask gradient, on a 2x padded 40 x 30 field
-    (80 x 60)."""
+    backward pass with the mask gradient, on a 2x padded field: 40 x 30
+    (80 x 60, the run-time-length kernels) and 50 x 50 (100 x 100, the
+    compile-time-length kernels, the elements applied in the row launch)."""
     tp = _tp()
-    announce(f"any-length elements + loss {dtype.__name__}")
+    announce(f"any-length elements + loss {shape} {dtype.__name__}")
     rng = np.random.default_rng(1210)
-    ny, nx = 40, 30
+    ny, nx = shape
     rdt = np.float32 if dtype == np.complex64 else np.float64
     u = crandn(rng, 2, ny, nx, dtype=dtype)
     phi = (rng.random((ny, nx)) * 6).astype(rdt)
     T = rng.random((ny, nx)).astype(rdt)
     opt = tp.Optics(dy=5e-6, dx=5e-6, wavelength=0.7e-6, z=2e-3, pad=2, round_pow2=False)
-    assert opt.padded_shape(ny, nx) == (80, 60)
+    assert opt.padded_shape(ny, nx) == (2 * ny, 2 * nx)
     ug, pg = to_gpu(u, torch), to_gpu(phi, torch)
     out, grad, loss = tp.propagate_loss(ug, opt, kind="mse", ref=to_gpu(T, torch), scale=0.5, phase=pg,
                                         lens_f=0.05)
