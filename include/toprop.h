@@ -38,9 +38,9 @@
  *   kernels) or other lengths in [3, 4096] (e.g. 2000: an unfused pipeline
  *   whose lines are transformed by a mixed-radix FFT when the length is
  *   2^a 3^b 5^c 7^d, else by Bluestein's method, chosen automatically;
- *   without Jones elements, the intensity epilogue, the lens gradient or
- *   coherence propagation, which return TO_E_UNSUPPORTED there, and with a
- *   stream synchronization on the first use of each such length).  The operator is the circular
+ *   without Jones elements, the lens gradient or coherence propagation,
+ *   which return TO_E_UNSUPPORTED there, and with a stream synchronization
+ *   on the first use of each such length).  The operator is the circular
  *   convolution on the padded grid restricted to the field window, so the
  *   window position inside the padded grid does not change the result.
  * Transfer function (cycles, lambda = wavelength):

@@ -386,9 +386,8 @@ to_status validate(const to_job& j, int idx, to_dtype dt, Mode mode) {
                   idx, (long long)ly, (long long)lx, kMinLen, kMaxLen, kMaxAnyLen);
     if (!pow2_grid(j) && mode == MODE_COH)
       return fail(TO_E_UNSUPPORTED, "job %d: coherence propagation needs power-of-two padded extents", idx);
-    if (!pow2_grid(j) && (has_jones(j) || j.epi == TO_EPI_INTENSITY))
-      return fail(TO_E_UNSUPPORTED,
-                  "job %d: Jones elements and the intensity epilogue need power-of-two padded extents", idx);
+    if (!pow2_grid(j) && has_jones(j))
+      return fail(TO_E_UNSUPPORTED, "job %d: Jones elements need power-of-two padded extents", idx);
     if (j.method != TO_ASM && j.method != TO_FRESNEL && j.method != TO_DI && j.method != TO_AUTO)
       return fail(TO_E_INVAL, "job %d: unknown method %d", idx, j.method);
     if (!std::isfinite(j.z)) return fail(TO_E_INVAL, "job %d: z is not finite", idx);
@@ -1504,7 +1503,7 @@ template <typename T>
 to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
   if (j.batch == 0) return TO_OK;
   if (has_jones(j)) return fail(TO_E_UNSUPPORTED, "the plain form has no Jones elements");
-  if (j.epi == TO_EPI_INTENSITY) return fail(TO_E_UNSUPPORTED, "the plain form has no intensity epilogue");
+  const bool intensity = j.epi == TO_EPI_INTENSITY;
   PlainWork<T> w;
   to_status st = plain_setup<T>(j, c, false, s, &w);
   if (st != TO_OK) return st;
@@ -1518,7 +1517,7 @@ to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
     pj.py = j.py;
     pj.px = j.px;
     pj.in = (const cx<T>*)j.in + b * nf;
-    pj.out = (cx<T>*)j.out + b * nf;
+    pj.out = j.out ? (cx<T>*)j.out + b * nf : w.tmp2;  // an intensity-only job keeps the field in the workspace
     pj.tmp = w.tmp;
     pj.pad = w.pad;
     pj.H = w.H;
@@ -1530,7 +1529,11 @@ to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
     pj.ht = w.fast ? 1 : 0;
     hipError_t e = timed("plain.propagate", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain propagation");
-    if (j.epi != TO_EPI_NONE) {
+    if (intensity) {
+      // epi_out[b / ncomp] += epi_scale |field|^2, the components in order
+      e = Plain<T>::intensity(pj.out, (T*)j.epi_out + (b / j.ncomp) * nf, nf, (T)j.epi_scale, s);
+      if (e != hipSuccess) return hip_fail(e, "plain intensity");
+    } else if (j.epi != TO_EPI_NONE) {
       int nb = 0;
       e = Plain<T>::loss(pj.out, (const T*)j.epi_ref, (cx<T>*)j.epi_grad + b * nf, w.partial, nf, j.epi,
                          (T)j.epi_scale, &nb, s);

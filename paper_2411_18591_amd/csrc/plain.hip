@@ -67,6 +67,15 @@ __global__ void __launch_bounds__(256) plain_table_kernel(cx<T>* H, int py, int 
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256) plain_intensity_kernel(const cx<T>* u, T* I, int64_t n, T scale) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> v = u[i];
+    I[i] += scale * (v.x * v.x + v.y * v.y);
+  }
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256) plain_mul_kernel(cx<T>* a, const cx<T>* H, int64_t n, int conj) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -307,6 +316,12 @@ hipError_t Plain<T>::cols_any(const LineFft<T>& f, cx<T>* a, int lx, int dir, hi
       hipSuccess)
     return e;
   return Bluestein<T>::transpose(tr, a, lx, f.L, s);
+}
+
+template <typename T>
+hipError_t Plain<T>::intensity(const cx<T>* u, T* I, int64_t n, T scale, hipStream_t s) {
+  hipLaunchKernelGGL((plain_intensity_kernel<T>), dim3(grid_for(n)), dim3(256), 0, s, u, I, n, scale);
+  return hipGetLastError();
 }
 
 template <typename T>

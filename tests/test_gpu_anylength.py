@@ -158,3 +158,31 @@ def test_paper_scale_separable(dtype, P):
     torch.cuda.synchronize()
     exp = col[0] * a[rows, None] * a[None, :]
     assert rel(got, exp) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_intensity_epilogue(dtype):
+    """The intensity epilogue on a padded 30 x 25 -> 60 x 50 grid: a batch of
+    two 3-component fields (no Jones element) through a lens, accumulated
+    with weight 0.75 into an image that already holds values, the field not
+    stored; then a scalar batch with the field stored too."""
+    tp = _tp()
+    announce(f"any-length intensity {dtype.__name__}")
+    rng = np.random.default_rng(1230)
+    ny, nx, d, lam, z = 30, 25, 4e-6, 500e-9, 0.004
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    E = crandn(rng, 2, 3, ny, nx, dtype=dtype)
+    I0 = rng.random((2, ny, nx)).astype(rdt)
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, padded=(60, 50))
+    I = to_gpu(I0.copy(), torch)
+    tp.propagate_intensity(to_gpu(E, torch), opt, intensity=I, ncomp=3, weight=0.75, lens_f=0.03)
+    u = crandn(rng, 3, ny, nx, dtype=dtype)
+    out = to_gpu(np.zeros_like(u), torch)
+    Is = tp.propagate_intensity(to_gpu(u, torch), opt, out=out)
+    torch.cuda.synchronize()
+    m = oracle.modulate(E, oracle.lens(ny, nx, d, d, lam, 0.03))
+    field = oracle.propagate(m, d, d, lam, z, oracle.ASM, padded=(60, 50))
+    assert rel(to_np(I), I0 + 0.75 * oracle.intensity(field, ncomp=3)) <= TOL[dtype]
+    fs = oracle.propagate(u, d, d, lam, z, oracle.ASM, padded=(60, 50))
+    assert rel(to_np(out), fs) <= TOL[dtype]
+    assert rel(to_np(Is), oracle.intensity(fs)) <= 2 * TOL[dtype]

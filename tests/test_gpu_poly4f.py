@@ -132,6 +132,26 @@ def test_paper_scale_spectrum():
     assert rel(to_np(I3), exp) <= 4e-5
 
 
+@pytest.mark.parametrize("method", [oracle.ASM, "auto"])
+def test_4f_at_padding_that_is_not_a_power_of_two(method):
+    """The 4f image on 48 x 40 fields padded to 96 x 80 (the paper's own
+    2x padding without rounding up; mixed-radix lines), AS and the automatic
+    AS/DI choice, against the oracle's composition on the same grid."""
+    FourF = _fourf()
+    name = "asm" if method == oracle.ASM else "auto"
+    announce(f"4f padded 96 x 80 {name}")
+    rng = np.random.default_rng(993)
+    ny, nx, d = 48, 40, 10e-6
+    wl = workloads.Polychromatic4fWorkload(count=7, fwhm=80e-9)
+    lams, wts = wl.wavelengths(), wl.weights()
+    f = 0.75 * max(oracle.critical_distance(ny, nx, d, d, lam) for lam in lams)
+    u = crandn(rng, 2, ny, nx, dtype=np.complex64)
+    I = FourF(f, d, d, method=name, padded=(96, 80)).image(to_gpu(u, torch), lams, wts)
+    torch.cuda.synchronize()
+    exp = _oracle_image(u, d, f, lams, wts, method, padded=(96, 80))
+    assert rel(to_np(I), exp) <= 4e-5
+
+
 def test_cached_di_tables_give_the_same_image():
     """With the DI tables kept by the system (built once by
     to_transfer_table), images equal the per-call-table images bitwise."""
