@@ -1549,7 +1549,6 @@ template <typename T>
 to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStream_t s) {
   if (j.batch == 0) return TO_OK;
   if (has_jones(j)) return fail(TO_E_UNSUPPORTED, "the plain form has no Jones elements");
-  if (gr.grad_f) return fail(TO_E_UNSUPPORTED, "the plain form has no lens gradient");
   PlainWork<T> w;
   to_status st = plain_setup<T>(j, c, true, s, &w);
   if (st != TO_OK) return st;
@@ -1580,6 +1579,13 @@ to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, h
       e = Plain<T>::phase_grad(w.tmp2, (const cx<T>*)gr.saved_in + b * nf, (T*)gr.grad_phase, j.ny, j.nx,
                                el, s);
       if (e != hipSuccess) return hip_fail(e, "plain phase gradient");
+    }
+    if (gr.grad_f && (j.el_flags & TO_EL_LENS) && gr.saved_in) {
+      int nb = 0;
+      e = Plain<T>::lens_grad(w.tmp2, (const cx<T>*)gr.saved_in + b * nf, w.partial, j.ny, j.nx, el, j.el_f, &nb,
+                              s);
+      if (e == hipSuccess) e = launch_reduce_add(w.partial, nb, 1.0, gr.grad_f, s);
+      if (e != hipSuccess) return hip_fail(e, "plain lens gradient");
     }
     if (gr.grad_in) {
       if (j.el_flags & (TO_EL_PHASE | TO_EL_COMPLEX | TO_EL_LENS))
@@ -1922,8 +1928,6 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
                               (g.grad_f && (jobs[i].el_flags & TO_EL_LENS));
       if (want_param && !g.saved_in)
         return fail(TO_E_INVAL, "job %d: a parameter gradient needs saved_in", i);
-      if (!pow2_grid(jobs[i]) && g.grad_f && (jobs[i].el_flags & TO_EL_LENS))
-        return fail(TO_E_UNSUPPORTED, "job %d: the lens gradient needs power-of-two padded extents", i);
     }
   }
   if (njobs == 0) return TO_OK;

@@ -160,6 +160,32 @@ __global__ void __launch_bounds__(256) plain_phase_grad_kernel(const cx<T>* g, c
   }
 }
 
+// Per-block partial sums, in FP64, of the lens focal-length gradient of
+// one field: sum over pixels of d(lens phase)/df * Im(g conj(M u)), where
+// M u is the modulated saved input.  Fixed grid and tree order:
+// deterministic.
+template <typename T>
+__global__ void __launch_bounds__(256) plain_lens_grad_kernel(const cx<T>* g, const cx<T>* u, double* partial,
+                                                              int ny, int nx, ElementParams<T> el, double f) {
+  __shared__ double red[256];
+  const int64_t n = (int64_t)ny * nx;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(i / nx), x = (int)(i % nx);
+    const cx<T> um = cmul(scalar_modulation(el, ny, nx, y, x), u[i]);
+    const double im = (double)g[i].y * (double)um.x - (double)g[i].x * (double)um.y;
+    acc += lens_dphase_df(el, ny, nx, y, x, f) * im;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 namespace {
 int grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
@@ -316,6 +342,15 @@ hipError_t Plain<T>::cols_any(const LineFft<T>& f, cx<T>* a, int lx, int dir, hi
       hipSuccess)
     return e;
   return Bluestein<T>::transpose(tr, a, lx, f.L, s);
+}
+
+template <typename T>
+hipError_t Plain<T>::lens_grad(const cx<T>* g, const cx<T>* u, double* partial, int ny, int nx,
+                               const ElementParams<T>& el, double f, int* nblocks, hipStream_t s) {
+  const int64_t n = (int64_t)ny * nx;
+  *nblocks = grid_for(n) > 1024 ? 1024 : grid_for(n);
+  hipLaunchKernelGGL((plain_lens_grad_kernel<T>), dim3(*nblocks), dim3(256), 0, s, g, u, partial, ny, nx, el, f);
+  return hipGetLastError();
 }
 
 template <typename T>

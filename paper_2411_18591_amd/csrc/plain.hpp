@@ -42,6 +42,11 @@ struct Plain {
   // Bluestein columns run as rows of the transposed array when `tr` (f.L *
   // lx elements) is given, else column-wise.
   static hipError_t cols_any(const LineFft<T>& f, cx<T>* a, int lx, int dir, hipStream_t s, cx<T>* tr = nullptr);
+  // Lens focal-length gradient of one field (g = P^H grad_out, u the saved
+  // input): per-block FP64 partial sums into partial[0 .. *nblocks), at most
+  // 1024 blocks.
+  static hipError_t lens_grad(const cx<T>* g, const cx<T>* u, double* partial, int ny, int nx,
+                              const ElementParams<T>& el, double f, int* nblocks, hipStream_t s);
   // I[i] += scale |u[i]|^2, i < n (the intensity epilogue)
   static hipError_t intensity(const cx<T>* u, T* I, int64_t n, T scale, hipStream_t s);
   static hipError_t loss(const cx<T>* u, const T* ref, cx<T>* grad, double* partial, int64_t n, int kind,

@@ -186,3 +186,34 @@ def test_intensity_epilogue(dtype):
     fs = oracle.propagate(u, d, d, lam, z, oracle.ASM, padded=(60, 50))
     assert rel(to_np(out), fs) <= TOL[dtype]
     assert rel(to_np(Is), oracle.intensity(fs)) <= 2 * TOL[dtype]
+
+
+@pytest.mark.parametrize("padded", [(120, 100), (127, 100)])
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_lens_gradient(dtype, padded):
+    """dL/df of the lens focal length with a phase mask in front, on 60 x 50
+    fields padded to 120 x 100 (mixed radix) and 127 x 100 (a Bluestein
+    column length), Fresnel: against the oracle's grad_lens_f with the
+    oracle's adjoint propagation, and grad_in against M^H P^H g."""
+    tp = _tp()
+    announce(f"any-length lens gradient {padded} {dtype.__name__}")
+    rng = np.random.default_rng(1240)
+    ny, nx, d, lam, f, z = 60, 50, 5e-6, 0.6e-6, 0.05, 0.02
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    u = crandn(rng, 2, ny, nx, dtype=dtype)
+    g = crandn(rng, 2, ny, nx, dtype=dtype)
+    phi = (rng.random((ny, nx)) * 6).astype(rdt)
+    M = oracle.phase_mask(phi) * oracle.lens(ny, nx, d, d, lam, f)
+    um = oracle.modulate(u, M)
+    g_mod = oracle.propagate(g, d, d, lam, z, oracle.FRESNEL, adjoint=True, padded=padded)
+    exp_f = oracle.grad_lens_f(g_mod, um, ny, nx, d, d, lam, f)
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, method="fresnel", padded=padded)
+    gf = torch.zeros((), dtype=torch.float64, device="cuda")
+    pg = to_gpu(phi, torch)
+    gphi = torch.zeros_like(pg)
+    gin = tp.propagate_backward(to_gpu(g, torch), opt, saved_in=to_gpu(u, torch), grad_f=gf, grad_phase=gphi,
+                                phase=pg, lens_f=f)
+    torch.cuda.synchronize()
+    assert rel(to_np(gin), oracle.modulate(g_mod, M, conj=True)) <= TOL[dtype]
+    assert abs(float(gf.item()) - exp_f) <= (1e-4 if dtype == np.complex64 else 1e-11) * abs(exp_f)
+    assert rel(to_np(gphi), oracle.grad_phase(g_mod, um)) <= (1e-4 if dtype == np.complex64 else 1e-10)
