@@ -38,9 +38,9 @@
  *   kernels) or other lengths in [3, 4096] (e.g. 2000: an unfused pipeline
  *   whose lines are transformed by a mixed-radix FFT when the length is
  *   2^a 3^b 5^c 7^d, else by Bluestein's method, chosen automatically;
- *   without Jones elements or coherence propagation, which return
- *   TO_E_UNSUPPORTED there, and with a stream synchronization on the first
- *   use of each such length).  The operator is the circular
+ *   without coherence propagation, which returns TO_E_UNSUPPORTED there,
+ *   and with a stream synchronization on the first use of each such
+ *   length).  The operator is the circular
  *   convolution on the padded grid restricted to the field window, so the
  *   window position inside the padded grid does not change the result.
  * Transfer function (cycles, lambda = wavelength):
@@ -264,8 +264,9 @@ to_status to_coherence_propagate(const to_job* job, to_dtype dtype, int32_t adjo
  * kernel per step of Eq. (field_propagation_tf) — modulate, zero-pad into a
  * full py x px array, row FFTs, column FFTs, multiply by a stored table of
  * H, inverse FFTs, crop — with every intermediate in device memory.  Same
- * arguments and results (to rounding) as the fused entry points; Jones
- * elements are not supported here (TO_E_UNSUPPORTED).  Workspace: two py x px and two ny x nx complex arrays. */
+ * arguments and results (to rounding) as the fused entry points (a Jones
+ * element is applied to the three components by a modulation kernel before
+ * they are propagated one by one).  Workspace: two py x px and two ny x nx complex arrays. */
 to_status to_propagate_plain(const to_job* jobs, int32_t njobs, to_dtype dtype, void* stream);
 to_status to_propagate_backward_plain(const to_job* jobs, const to_grad* grads, int32_t njobs,
                                       to_dtype dtype, void* stream);

@@ -386,8 +386,6 @@ to_status validate(const to_job& j, int idx, to_dtype dt, Mode mode) {
                   idx, (long long)ly, (long long)lx, kMinLen, kMaxLen, kMaxAnyLen);
     if (!pow2_grid(j) && mode == MODE_COH)
       return fail(TO_E_UNSUPPORTED, "job %d: coherence propagation needs power-of-two padded extents", idx);
-    if (!pow2_grid(j) && has_jones(j))
-      return fail(TO_E_UNSUPPORTED, "job %d: Jones elements need power-of-two padded extents", idx);
     if (j.method != TO_ASM && j.method != TO_FRESNEL && j.method != TO_DI && j.method != TO_AUTO)
       return fail(TO_E_INVAL, "job %d: unknown method %d", idx, j.method);
     if (!std::isfinite(j.z)) return fail(TO_E_INVAL, "job %d: z is not finite", idx);
@@ -1444,7 +1442,8 @@ template <typename T>
 size_t plain_bytes(const to_job& j) {
   const size_t npad = (size_t)j.py * j.px, nf = (size_t)j.ny * j.nx;
   const size_t tr = (is_pow2(j.py) && is_pow2(j.px)) ? 0 : npad;  // columns run as transposed rows
-  return (2 * npad + 2 * nf + tr) * sizeof(cx<T>) + 1024 * sizeof(double);
+  const size_t nt = has_jones(j) ? 3 * nf : nf;                    // a Jones element mixes three components
+  return (2 * npad + 2 * nt + tr) * sizeof(cx<T>) + 1024 * sizeof(double);
 }
 
 // Jobs of to_propagate / to_propagate_backward whose padded grid is not a
@@ -1474,9 +1473,10 @@ to_status plain_setup(const to_job& j, DeviceCtx* c, bool conj, hipStream_t s, P
   if ((st = line_fft<T>(c, j.py, s, &w->fy)) != TO_OK) return st;
   w->H = (cx<T>*)c->plain;
   w->pad = w->H + npad;
+  const size_t nt = has_jones(j) ? 3 * nf : nf;
   w->tmp = w->pad + npad;
-  w->tmp2 = w->tmp + nf;
-  w->partial = (double*)(w->tmp2 + nf);
+  w->tmp2 = w->tmp + nt;
+  w->partial = (double*)(w->tmp2 + nt);
   const bool pow2 = is_pow2(j.py) && is_pow2(j.px);
   w->tr = pow2 ? nullptr : (cx<T>*)(w->partial + 1024);
   MixedPlan qy, qx;
@@ -1502,27 +1502,34 @@ to_status plain_setup(const to_job& j, DeviceCtx* c, bool conj, hipStream_t s, P
 template <typename T>
 to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
   if (j.batch == 0) return TO_OK;
-  if (has_jones(j)) return fail(TO_E_UNSUPPORTED, "the plain form has no Jones elements");
   const bool intensity = j.epi == TO_EPI_INTENSITY;
+  const bool jones = has_jones(j);
   PlainWork<T> w;
   to_status st = plain_setup<T>(j, c, false, s, &w);
   if (st != TO_OK) return st;
   const int64_t nf = (int64_t)j.ny * j.nx;
   const int64_t fields = j.batch * j.ncomp;
   const bool dbl = sizeof(T) == 8;
+  const ElementParams<T> el = make_element<T>(j, j.el_flags);
   for (int64_t b = 0; b < fields; ++b) {
+    if (jones && b % 3 == 0) {
+      // the element of the three components of field b / 3 (M J E) into tmp
+      hipError_t e = Launch<T>::modulate(3, (const cx<T>*)j.in + b * nf, w.tmp, 3 * nf, nf, j.ny, j.nx, 1, 0, el,
+                                         s);
+      if (e != hipSuccess) return hip_fail(e, "plain Jones element");
+    }
     PlainJob<T> pj;
     pj.ny = j.ny;
     pj.nx = j.nx;
     pj.py = j.py;
     pj.px = j.px;
-    pj.in = (const cx<T>*)j.in + b * nf;
+    pj.in = jones ? w.tmp + (b % 3) * nf : (const cx<T>*)j.in + b * nf;
     pj.out = j.out ? (cx<T>*)j.out + b * nf : w.tmp2;  // an intensity-only job keeps the field in the workspace
     pj.tmp = w.tmp;
     pj.pad = w.pad;
     pj.H = w.H;
     pj.conj = 0;
-    pj.el = make_element<T>(j, j.el_flags);
+    pj.el = jones ? make_element<T>(j, 0) : el;  // with a Jones element, applied above
     pj.fx = w.fx;
     pj.fy = w.fy;
     pj.tr = w.tr;
@@ -1545,10 +1552,68 @@ to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
   return TO_OK;
 }
 
+// Backward of a job with a Jones element, one three-component field at a
+// time: g_mod = P^H grad_out per component (into tmp2), the modulated
+// input M J saved_in (into tmp) for the parameter gradients, which sum
+// Im(g_mod conj(M J saved_in)) over the components in order, and
+// grad_in = J^H conj(M) g_mod.
+template <typename T>
+to_status run_backward_plain_jones(const to_job& j, const to_grad& gr, const PlainWork<T>& w,
+                                   const ElementParams<T>& el, hipStream_t s) {
+  const int64_t nf = (int64_t)j.ny * j.nx;
+  const bool dbl = sizeof(T) == 8;
+  ElementParams<T> none = el;  // the grid geometry and lens coefficient, no modulation
+  none.flags = 0;
+  const bool want_phase = gr.grad_phase && (j.el_flags & TO_EL_PHASE) && gr.saved_in;
+  const bool want_f = gr.grad_f && (j.el_flags & TO_EL_LENS) && gr.saved_in;
+  for (int64_t f = 0; f < j.batch; ++f) {
+    hipError_t e = hipSuccess;
+    for (int comp = 0; comp < 3 && e == hipSuccess; ++comp) {
+      PlainJob<T> pj;
+      pj.ny = j.ny;
+      pj.nx = j.nx;
+      pj.py = j.py;
+      pj.px = j.px;
+      pj.in = (const cx<T>*)gr.grad_out + (3 * f + comp) * nf;
+      pj.out = w.tmp2 + comp * nf;
+      pj.tmp = w.tmp;
+      pj.pad = w.pad;
+      pj.H = w.H;
+      pj.conj = 1;
+      pj.el = none;
+      pj.fx = w.fx;
+      pj.fy = w.fy;
+      pj.tr = w.tr;
+      pj.ht = w.fast ? 1 : 0;
+      e = timed("plain.adjoint", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
+    }
+    if (e != hipSuccess) return hip_fail(e, "plain adjoint");
+    if (want_phase || want_f) {
+      e = Launch<T>::modulate(3, (const cx<T>*)gr.saved_in + 3 * f * nf, w.tmp, 3 * nf, nf, j.ny, j.nx, 1, 0, el,
+                              s);
+      for (int comp = 0; comp < 3 && e == hipSuccess; ++comp) {
+        if (want_phase)
+          e = Plain<T>::phase_grad(w.tmp2 + comp * nf, w.tmp + comp * nf, (T*)gr.grad_phase, j.ny, j.nx, none, s);
+        if (want_f && e == hipSuccess) {
+          int nb = 0;
+          e = Plain<T>::lens_grad(w.tmp2 + comp * nf, w.tmp + comp * nf, w.partial, j.ny, j.nx, none, j.el_f, &nb,
+                                  s);
+          if (e == hipSuccess) e = launch_reduce_add(w.partial, nb, 1.0, gr.grad_f, s);
+        }
+      }
+      if (e != hipSuccess) return hip_fail(e, "plain parameter gradients");
+    }
+    if (gr.grad_in) {
+      e = Launch<T>::modulate(3, w.tmp2, (cx<T>*)gr.grad_in + 3 * f * nf, 3 * nf, nf, j.ny, j.nx, 1, 1, el, s);
+      if (e != hipSuccess) return hip_fail(e, "plain input gradient");
+    }
+  }
+  return TO_OK;
+}
+
 template <typename T>
 to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, hipStream_t s) {
   if (j.batch == 0) return TO_OK;
-  if (has_jones(j)) return fail(TO_E_UNSUPPORTED, "the plain form has no Jones elements");
   PlainWork<T> w;
   to_status st = plain_setup<T>(j, c, true, s, &w);
   if (st != TO_OK) return st;
@@ -1556,6 +1621,7 @@ to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, h
   const int64_t fields = j.batch * j.ncomp;
   const bool dbl = sizeof(T) == 8;
   const ElementParams<T> el = make_element<T>(j, j.el_flags);
+  if (has_jones(j)) return run_backward_plain_jones<T>(j, gr, w, el, s);
   for (int64_t b = 0; b < fields; ++b) {
     PlainJob<T> pj;
     pj.ny = j.ny;

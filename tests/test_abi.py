@@ -85,8 +85,6 @@ def good_job(capi):
     (lambda j: (setattr(j, "nx", 4), setattr(j, "px", 4)), "TO_E_UNSUPPORTED"),  # power of two below 8
     (lambda j: setattr(j, "px", 16384), "TO_E_UNSUPPORTED"),
     (lambda j: (setattr(j, "nx", 16), setattr(j, "px", 5000)), "TO_E_UNSUPPORTED"),  # not a power of two, > 4096
-    (lambda j: (setattr(j, "px", 48), setattr(j, "ncomp", 3), setattr(j, "el_flags", 8)),
-     "TO_E_UNSUPPORTED"),                                   # Jones element on a non-power-of-two grid
     (lambda j: setattr(j, "dx", 0.0), "TO_E_INVAL"),
     (lambda j: setattr(j, "dy", float("nan")), "TO_E_INVAL"),
     (lambda j: setattr(j, "wavelength", -1.0), "TO_E_INVAL"),

@@ -12,6 +12,8 @@ the MSE epilogue and the mask gradient, mixed with power-of-two jobs in one
 call; at the paper's 1000^2 -> 2000^2 scale (and 2002^2, a Bluestein
 length), a separable Fresnel Gaussian against the oracle's 1-D
 transforms."""
+import math
+
 import numpy as np
 import pytest
 
@@ -217,3 +219,54 @@ def test_lens_gradient(dtype, padded):
     assert rel(to_np(gin), oracle.modulate(g_mod, M, conj=True)) <= TOL[dtype]
     assert abs(float(gf.item()) - exp_f) <= (1e-4 if dtype == np.complex64 else 1e-11) * abs(exp_f)
     assert rel(to_np(gphi), oracle.grad_phase(g_mod, um)) <= (1e-4 if dtype == np.complex64 else 1e-10)
+
+
+@pytest.mark.parametrize("padded", [(50, 60), (53, 60)])
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_jones_forward_backward(dtype, padded):
+    """Polarized fields on 25 x 30 grids padded to 50 x 60 (mixed radix) and
+    53 x 60 (Bluestein columns): a uniform Jones matrix (quarter-wave plate
+    then a polarizer) with a phase mask and a lens, Fresnel, the
+    weighted-intensity loss, gradients to the input, the mask and the focal
+    length; then the same element with a per-pixel Jones map into the
+    intensity epilogue."""
+    tp = _tp()
+    announce(f"any-length jones {padded} {dtype.__name__}")
+    rng = np.random.default_rng(1250)
+    ny, nx, d, lam, f, z = 25, 30, 6e-6, 0.55e-6, 0.04, 0.03
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    E = crandn(rng, 2, 3, ny, nx, dtype=dtype)
+    Wt = rng.random((ny, nx)).astype(rdt)
+    phi = (rng.random((ny, nx)) * 6).astype(rdt)
+    Jo = oracle.embed_jones(oracle.linear_polarizer(math.pi / 6) @ oracle.waveplate(math.pi / 4, math.pi / 2))
+    Jg = tp.jones3(tp.waveplate(math.pi / 4, math.pi / 2), tp.linear_polarizer(math.pi / 6))
+    M = oracle.phase_mask(phi) * oracle.lens(ny, nx, d, d, lam, f)
+    Em = oracle.modulate(oracle.jones_apply(E, Jo), M)
+    out = oracle.propagate(Em, d, d, lam, z, oracle.FRESNEL, padded=padded)
+    loss, gout = oracle.weighted_intensity(out, Wt, d, d)
+    g_mod = oracle.propagate(gout, d, d, lam, z, oracle.FRESNEL, adjoint=True, padded=padded)
+    exp_f = oracle.grad_lens_f(g_mod, Em, ny, nx, d, d, lam, f)
+    exp_phi = oracle.grad_phase(g_mod, Em, reduce_axes=(0, 1))
+    exp_gin = oracle.jones_apply(oracle.modulate(g_mod, M, conj=True), Jo, conj_transpose=True)
+
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, method="fresnel", padded=padded)
+    Eg, pg = to_gpu(E, torch), to_gpu(phi, torch)
+    o, go, lo = tp.propagate_loss(Eg, opt, kind="weighted", ref=to_gpu(Wt, torch), scale=d * d,
+                                  ncomp=3, jones=Jg, phase=pg, lens_f=f)
+    gf = torch.zeros((), dtype=torch.float64, device="cuda")
+    gphi = torch.zeros_like(pg)
+    gin = tp.propagate_backward(go, opt, saved_in=Eg, grad_f=gf, grad_phase=gphi, ncomp=3, jones=Jg, phase=pg,
+                                lens_f=f)
+    torch.cuda.synchronize()
+    assert rel(to_np(o), out) <= TOL[dtype]
+    assert rel(to_np(go), gout) <= TOL[dtype]
+    assert abs(float(lo.item()) - loss) <= (1e-4 if dtype == np.complex64 else 1e-11) * abs(loss)
+    assert rel(to_np(gin), exp_gin) <= TOL[dtype]
+    assert abs(float(gf.item()) - exp_f) <= (1e-4 if dtype == np.complex64 else 1e-11) * abs(exp_f)
+    assert rel(to_np(gphi), exp_phi) <= (1e-4 if dtype == np.complex64 else 1e-10)
+
+    Jmap = crandn(rng, 3, 3, ny, nx, dtype=dtype)
+    I = tp.propagate_intensity(Eg, opt, ncomp=3, weight=0.5, jones_map=to_gpu(Jmap, torch))
+    torch.cuda.synchronize()
+    fm = oracle.propagate(oracle.jones_apply(E, Jmap), d, d, lam, z, oracle.FRESNEL, padded=padded)
+    assert rel(to_np(I), 0.5 * oracle.intensity(fm, ncomp=3)) <= 2 * TOL[dtype]
