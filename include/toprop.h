@@ -37,10 +37,10 @@
  *   2048).  Padded extents are powers of two in [8, 8192] (the fused
  *   kernels) or other lengths in [3, 4096] (e.g. 2000: an unfused pipeline
  *   whose lines are transformed by a mixed-radix FFT when the length is
- *   2^a 3^b 5^c 7^d, else by Bluestein's method, chosen automatically;
- *   without coherence propagation, which returns TO_E_UNSUPPORTED there,
- *   and with a stream synchronization on the first use of each such
- *   length).  The operator is the circular
+ *   2^a 3^b 5^c 7^d, else by Bluestein's method, chosen automatically,
+ *   with a stream synchronization on the first use of each such length;
+ *   coherence propagation on such grids runs its batched propagations one
+ *   field at a time through that pipeline).  The operator is the circular
  *   convolution on the padded grid restricted to the field window, so the
  *   window position inside the padded grid does not change the result.
  * Transfer function (cycles, lambda = wavelength):

@@ -384,8 +384,6 @@ to_status validate(const to_job& j, int idx, to_dtype dt, Mode mode) {
                   "job %d: padded grid %lldx%lld: each extent must be a power of two in [%d, %d] or any "
                   "length in [3, %d]",
                   idx, (long long)ly, (long long)lx, kMinLen, kMaxLen, kMaxAnyLen);
-    if (!pow2_grid(j) && mode == MODE_COH)
-      return fail(TO_E_UNSUPPORTED, "job %d: coherence propagation needs power-of-two padded extents", idx);
     if (j.method != TO_ASM && j.method != TO_FRESNEL && j.method != TO_DI && j.method != TO_AUTO)
       return fail(TO_E_INVAL, "job %d: unknown method %d", idx, j.method);
     if (!std::isfinite(j.z)) return fail(TO_E_INVAL, "job %d: z is not finite", idx);
@@ -1352,6 +1350,9 @@ to_status ensure_coh(DeviceCtx* c, size_t bytes) {
 }
 
 template <typename T>
+to_status run_batch_plain(const to_job& j, DeviceCtx* c, bool conj_h, const cx<T>* coh_mc, hipStream_t s);
+
+template <typename T>
 to_status run_coherence(const to_job& j, int adjoint, const to_grad* gr, DeviceCtx* c, hipStream_t s) {
   const int n = j.ny * j.nx;
   const size_t nn = (size_t)n * n;
@@ -1384,12 +1385,19 @@ to_status run_coherence(const to_job& j, int adjoint, const to_grad* gr, DeviceC
   };
   rj.in = j.in;
   rj.out = out;
+  // the n batched propagations: fused kernels, or the plain path's any-length
+  // sequence one field at a time (its element applied as a separate step)
+  const bool fused = pow2_grid(j);
+  auto batch = [&](bool conj_h, const cx<T>* m) -> to_status {
+    return fused ? run_forward<T>(rj, c, &c->lane[0], s, conj_h, m)
+                 : run_batch_plain<T>(rj, c, conj_h, m ? mtc : nullptr, s);
+  };
   if (!adjoint) {
-    if ((st = run_forward<T>(rj, c, &c->lane[0], s, true, has_el ? mt : nullptr)) != TO_OK) return st;
+    if ((st = batch(true, has_el ? mt : nullptr)) != TO_OK) return st;
     if ((st = transpose(out, W, nullptr)) != TO_OK) return st;
     rj.in = W;
     rj.out = W;
-    if ((st = run_forward<T>(rj, c, &c->lane[0], s, false, nullptr)) != TO_OK) return st;
+    if ((st = batch(false, nullptr)) != TO_OK) return st;
     if ((st = transpose(W, out, nullptr)) != TO_OK) return st;
     if (j.epi == TO_EPI_INTENSITY) {
       e = timed("coh.diag_intensity", n, dbl, s,
@@ -1406,11 +1414,11 @@ to_status run_coherence(const to_job& j, int adjoint, const to_grad* gr, DeviceC
     }
     return TO_OK;
   }
-  if ((st = run_forward<T>(rj, c, &c->lane[0], s, false, nullptr)) != TO_OK) return st;
+  if ((st = batch(false, nullptr)) != TO_OK) return st;
   if ((st = transpose(out, W, nullptr)) != TO_OK) return st;
   rj.in = W;
   rj.out = W;
-  if ((st = run_forward<T>(rj, c, &c->lane[0], s, true, nullptr)) != TO_OK) return st;
+  if ((st = batch(true, nullptr)) != TO_OK) return st;
   const bool want_phase = gr && gr->grad_phase && (j.el_flags & TO_EL_PHASE);
   if (!want_phase) return transpose(W, out, has_el ? mtc : nullptr);
   // G' = P^H G P in `out`, then the phase gradient, then M^H G' M in place
@@ -1665,6 +1673,52 @@ to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, h
   return TO_OK;
 }
 
+
+// The batched propagations of a coherence matrix on a padded grid that is
+// not a power of two: j.batch fields [ny][nx] from j.in to j.out (in place
+// allowed), P or P^H (conj_h), one field at a time through the plain path.
+// coh_mc = conj(M): the element as the coherence modulation
+// Gamma(r1, r2) M(r1) conj(M(r2)), applied first (into j.out).
+template <typename T>
+to_status run_batch_plain(const to_job& j, DeviceCtx* c, bool conj_h, const cx<T>* coh_mc, hipStream_t s) {
+  if (j.batch == 0) return TO_OK;
+  const int64_t nf = (int64_t)j.ny * j.nx;
+  const bool dbl = sizeof(T) == 8;
+  const cx<T>* src = (const cx<T>*)j.in;
+  hipError_t e;
+  if (coh_mc) {
+    if (j.in != j.out &&
+        (e = hipMemcpyAsync(j.out, j.in, (size_t)j.batch * nf * sizeof(cx<T>), hipMemcpyDeviceToDevice, s)) !=
+            hipSuccess)
+      return hip_fail(e, "coherence copy");
+    if ((e = Coh<T>::scale((cx<T>*)j.out, coh_mc, (int)nf, s)) != hipSuccess) return hip_fail(e, "element");
+    src = (const cx<T>*)j.out;
+  }
+  PlainWork<T> w;
+  to_status st = plain_setup<T>(j, c, conj_h, s, &w);
+  if (st != TO_OK) return st;
+  for (int64_t b = 0; b < j.batch; ++b) {
+    PlainJob<T> pj;
+    pj.ny = j.ny;
+    pj.nx = j.nx;
+    pj.py = j.py;
+    pj.px = j.px;
+    pj.in = src + b * nf;
+    pj.out = (cx<T>*)j.out + b * nf;
+    pj.tmp = w.tmp;
+    pj.pad = w.pad;
+    pj.H = w.H;
+    pj.conj = conj_h ? 1 : 0;
+    pj.el = make_element<T>(j, 0);
+    pj.fx = w.fx;
+    pj.fy = w.fy;
+    pj.tr = w.tr;
+    pj.ht = w.fast ? 1 : 0;
+    e = timed("plain.coh_batch", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
+    if (e != hipSuccess) return hip_fail(e, "plain propagation");
+  }
+  return TO_OK;
+}
 
 // Times one forward propagation of `j` under the schedule `pe` (lane 0,
 // stream s): one untimed run, then the mean of `reps` runs between events.

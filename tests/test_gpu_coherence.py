@@ -134,3 +134,62 @@ def test_gaussian_schell_workload_fwd_bwd():
     assert rel(to_np(out), Go) <= 2e-5
     assert abs(float(L.item()) - loss) <= 1e-4 * loss
     assert rel(to_np(gphi), exp_gphi) <= 1e-4
+
+
+@pytest.mark.parametrize("shape", [(6, 5), (11, 9)])
+@pytest.mark.parametrize("dtype", [np.complex64, np.complex128])
+def test_coherence_padding_not_a_power_of_two(shape, dtype):
+    """Coherence on fields padded 2x without rounding up: 6 x 5 -> 12 x 10
+    (mixed radix) and 11 x 9 -> 22 x 18 (Bluestein columns): forward with a
+    phase mask and a lens, adjoint with the mask gradient, against the
+    oracle (whose padding is 2n)."""
+    tp = _tp()
+    ny, nx = shape
+    announce(f"coherence padded 2x {shape} {dtype.__name__}")
+    rng = np.random.default_rng(60 + ny)
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    d, lam, z, f = 10e-6, 633e-9, 0.004, 0.03
+    n = ny * nx
+    A = crandn(rng, n, n) / n
+    G0 = (A @ A.conj().T).reshape(ny, nx, ny, nx).astype(dtype)
+    phi = (rng.random((ny, nx)) * 2 * np.pi).astype(rdt)
+    Gout = crandn(rng, ny, nx, ny, nx, dtype=dtype)
+    opt = tp.Optics(dy=d, dx=d, wavelength=lam, z=z, pad=2, round_pow2=False)
+    assert opt.padded_shape(ny, nx) == (2 * ny, 2 * nx)
+    M = oracle.phase_mask(phi) * oracle.lens(ny, nx, d, d, lam, f)
+    args = (d, d, lam, z, oracle.ASM, 2)
+    exp_fwd = oracle.coherence_propagate(oracle.coherence_modulate(G0, M), *args)
+    Gp = oracle.coherence_propagate(Gout, *args, adjoint=True)
+    exp_adj = oracle.coherence_modulate(Gp, M, conj=True)
+    exp_gphi = oracle.coherence_grad_phase(Gp, oracle.coherence_modulate(G0, M))
+    g0, pg = to_gpu(G0, torch), to_gpu(phi, torch)
+    out = tp.coherence_propagate(g0, opt, phase=pg, lens_f=f)
+    gphi = torch.zeros_like(pg)
+    adj = tp.coherence_propagate(to_gpu(Gout, torch), opt, adjoint=True, saved_in=g0, grad_phase=gphi,
+                                 phase=pg, lens_f=f)
+    torch.cuda.synchronize()
+    assert rel(to_np(out), exp_fwd) <= FIELD_TOL[dtype]
+    assert rel(to_np(adj), exp_adj) <= FIELD_TOL[dtype]
+    assert rel(to_np(gphi), exp_gphi) <= PARAM_TOL[dtype]
+
+
+def test_coherence_paper_grid_rank_one():
+    """The paper's Gaussian Schell-model grid, 50^2 padded 2x to 100^2: a
+    rank-one Gamma = u u^H through a phase mask propagates to
+    (P M u)(P M u)^H, against the library's field path at the same padding
+    (itself checked against the oracle)."""
+    tp = _tp()
+    announce("coherence 50^2 -> 100^2 rank one")
+    rng = np.random.default_rng(70)
+    n = 50
+    u = crandn(rng, n, n, dtype=np.complex128)
+    phi = rng.random((n, n)) * 6
+    opt = tp.Optics(dy=10e-6, dx=10e-6, wavelength=700e-9, z=0.02, pad=2, round_pow2=False)
+    ug = to_gpu(u, torch)
+    G = torch.einsum("ab,cd->abcd", ug, ug.conj()).contiguous()
+    out = tp.coherence_propagate(G, opt, phase=to_gpu(phi, torch))
+    pu = tp.propagate(ug[None].contiguous(), opt, phase=to_gpu(phi, torch))[0]
+    exp = torch.einsum("ab,cd->abcd", pu, pu.conj())
+    torch.cuda.synchronize()
+    err = float(torch.linalg.vector_norm(out - exp) / torch.linalg.vector_norm(exp))
+    assert err <= 1e-12
