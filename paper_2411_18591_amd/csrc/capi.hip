@@ -1444,14 +1444,28 @@ struct PlainWork {
   double* partial;
   cx<T>* tr;  // transpose buffer of the column passes of non-power-of-two grids, or null
   bool fast;  // Plain::run_mixed applies (the table is stored transposed)
+  int64_t chunk;  // fields per batched run_mixed pass (pad and tr hold that many)
 };
+
+// Fields that go through one pass of the mixed-radix sequence together
+// (Plain::run_mixed with nbatch): up to 64 MiB of [ny][px] rows per
+// pass; 1 where that sequence does not apply.
+template <typename T>
+int64_t plain_chunk(const to_job& j) {
+  MixedPlan a, b;
+  if ((is_pow2(j.py) && is_pow2(j.px)) || !mixed_plan(j.py, &a, true) || !mixed_plan(j.px, &b, true)) return 1;
+  const int64_t per = (int64_t)j.ny * j.px * (int64_t)sizeof(cx<T>);
+  const int64_t fields = std::max<int64_t>(1, j.batch * j.ncomp);
+  return std::max<int64_t>(1, std::min<int64_t>(fields, (int64_t(64) << 20) / per));
+}
 
 template <typename T>
 size_t plain_bytes(const to_job& j) {
   const size_t npad = (size_t)j.py * j.px, nf = (size_t)j.ny * j.nx;
-  const size_t tr = (is_pow2(j.py) && is_pow2(j.px)) ? 0 : npad;  // columns run as transposed rows
-  const size_t nt = has_jones(j) ? 3 * nf : nf;                    // a Jones element mixes three components
-  return (2 * npad + 2 * nt + tr) * sizeof(cx<T>) + 1024 * sizeof(double);
+  const size_t padsz = std::max(npad, (size_t)plain_chunk<T>(j) * j.ny * j.px);
+  const size_t tr = (is_pow2(j.py) && is_pow2(j.px)) ? 0 : padsz;  // columns run as transposed rows
+  const size_t nt = has_jones(j) ? 3 * nf : nf;                      // a Jones element mixes three components
+  return (npad + padsz + 2 * nt + tr) * sizeof(cx<T>) + 1024 * sizeof(double);
 }
 
 // Jobs of to_propagate / to_propagate_backward whose padded grid is not a
@@ -1482,7 +1496,8 @@ to_status plain_setup(const to_job& j, DeviceCtx* c, bool conj, hipStream_t s, P
   w->H = (cx<T>*)c->plain;
   w->pad = w->H + npad;
   const size_t nt = has_jones(j) ? 3 * nf : nf;
-  w->tmp = w->pad + npad;
+  w->chunk = plain_chunk<T>(j);
+  w->tmp = w->pad + std::max(npad, (size_t)w->chunk * j.ny * j.px);
   w->tmp2 = w->tmp + nt;
   w->partial = (double*)(w->tmp2 + nt);
   const bool pow2 = is_pow2(j.py) && is_pow2(j.px);
@@ -1519,7 +1534,10 @@ to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
   const int64_t fields = j.batch * j.ncomp;
   const bool dbl = sizeof(T) == 8;
   const ElementParams<T> el = make_element<T>(j, j.el_flags);
-  for (int64_t b = 0; b < fields; ++b) {
+  // fields stored to `out` go through the mixed-radix sequence in batches
+  const int64_t step = (w.fast && !jones && j.out) ? w.chunk : 1;
+  for (int64_t b = 0; b < fields; b += step) {
+    const int64_t nb = std::min(step, fields - b);
     if (jones && b % 3 == 0) {
       // the element of the three components of field b / 3 (M J E) into tmp
       hipError_t e = Launch<T>::modulate(3, (const cx<T>*)j.in + b * nf, w.tmp, 3 * nf, nf, j.ny, j.nx, 1, 0, el,
@@ -1542,19 +1560,24 @@ to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
     pj.fy = w.fy;
     pj.tr = w.tr;
     pj.ht = w.fast ? 1 : 0;
+    pj.nbatch = nb;
     hipError_t e = timed("plain.propagate", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain propagation");
-    if (intensity) {
-      // epi_out[b / ncomp] += epi_scale |field|^2, the components in order
-      e = Plain<T>::intensity(pj.out, (T*)j.epi_out + (b / j.ncomp) * nf, nf, (T)j.epi_scale, s);
-      if (e != hipSuccess) return hip_fail(e, "plain intensity");
-    } else if (j.epi != TO_EPI_NONE) {
-      int nb = 0;
-      e = Plain<T>::loss(pj.out, (const T*)j.epi_ref, (cx<T>*)j.epi_grad + b * nf, w.partial, nf, j.epi,
-                         (T)j.epi_scale, &nb, s);
-      if (e != hipSuccess) return hip_fail(e, "plain loss");
-      if ((e = launch_reduce_add(w.partial, nb, j.epi_scale, j.epi_loss, s)) != hipSuccess)
-        return hip_fail(e, "plain loss reduction");
+    for (int64_t k = 0; k < nb; ++k) {
+      const int64_t fb = b + k;
+      const cx<T>* field = pj.out + k * nf;
+      if (intensity) {
+        // epi_out[fb / ncomp] += epi_scale |field|^2, the components in order
+        e = Plain<T>::intensity(field, (T*)j.epi_out + (fb / j.ncomp) * nf, nf, (T)j.epi_scale, s);
+        if (e != hipSuccess) return hip_fail(e, "plain intensity");
+      } else if (j.epi != TO_EPI_NONE) {
+        int nblk = 0;
+        e = Plain<T>::loss(field, (const T*)j.epi_ref, (cx<T>*)j.epi_grad + fb * nf, w.partial, nf, j.epi,
+                           (T)j.epi_scale, &nblk, s);
+        if (e != hipSuccess) return hip_fail(e, "plain loss");
+        if ((e = launch_reduce_add(w.partial, nblk, j.epi_scale, j.epi_loss, s)) != hipSuccess)
+          return hip_fail(e, "plain loss reduction");
+      }
     }
   }
   return TO_OK;
@@ -1697,7 +1720,8 @@ to_status run_batch_plain(const to_job& j, DeviceCtx* c, bool conj_h, const cx<T
   PlainWork<T> w;
   to_status st = plain_setup<T>(j, c, conj_h, s, &w);
   if (st != TO_OK) return st;
-  for (int64_t b = 0; b < j.batch; ++b) {
+  const int64_t step = w.fast ? w.chunk : 1;
+  for (int64_t b = 0; b < j.batch; b += step) {
     PlainJob<T> pj;
     pj.ny = j.ny;
     pj.nx = j.nx;
@@ -1714,6 +1738,7 @@ to_status run_batch_plain(const to_job& j, DeviceCtx* c, bool conj_h, const cx<T
     pj.fy = w.fy;
     pj.tr = w.tr;
     pj.ht = w.fast ? 1 : 0;
+    pj.nbatch = std::min(step, j.batch - b);
     e = timed("plain.coh_batch", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain propagation");
   }

@@ -13,6 +13,8 @@
 // L <= 16 TL, so each thread owns at most 16 points of a pass.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mixed.hpp"
 
 namespace toprop {
@@ -143,7 +145,7 @@ __device__ __forceinline__ void mixed_pass(cx<T>* ll, const LineIo<T>& io, const
       if constexpr (IN_G) {
         const bool valid = ok && q < a.nin;
         cx<T> x = io.in[(valid ? q : 0) * io.in_es];
-        if constexpr (EL) x = cmul(scalar_modulation(a.el, a.nlines, a.nin, io.line, valid ? q : 0), x);
+        if constexpr (EL) x = cmul(scalar_modulation(a.el, a.field_rows, a.nin, io.line, valid ? q : 0), x);
         v[t][r] = valid ? x : cx<T>{T(0), T(0)};
       } else {
         v[t][r] = ll[pidx(q)];
@@ -232,8 +234,8 @@ __global__ void __launch_bounds__(256) mixed_lines_kernel(MixedArgs<T> a) {
   const int line = blockIdx.x * G + g;
   const bool ok = line < a.nlines;
   const int64_t li = ok ? line : 0;
-  const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + li * a.h_ls : nullptr, (int)a.in_es,
-                     (int)a.out_es, (int)li};
+  const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + (li % a.h_lines) * a.h_ls : nullptr,
+                     (int)a.in_es, (int)a.out_es, (int)(li % a.field_rows)};
   cx<T>* ll = lds + g * (pidx(a.L - 1) + 1);
   if constexpr (MODE == 0) {
     mixed_transform<T, -1, true, false, true>(ll, io, a, ok, j, TL);
@@ -297,7 +299,7 @@ __device__ __forceinline__ void fixed_pass(cx<T>* ll, const LineIo<T>& io, const
       if constexpr (IN_G) {
         const bool valid = ok && q < a.nin;
         cx<T> x = io.in[valid ? q : 0];
-        if constexpr (EL) x = cmul(scalar_modulation(a.el, a.nlines, a.nin, io.line, valid ? q : 0), x);
+        if constexpr (EL) x = cmul(scalar_modulation(a.el, a.field_rows, a.nin, io.line, valid ? q : 0), x);
         v[t][r] = valid ? x : cx<T>{T(0), T(0)};
       } else if constexpr (IN_T) {
         v[t][r] = ll[(q % R1) * nb1 + q / R1];
@@ -366,7 +368,8 @@ __global__ void __launch_bounds__(256, (MODE == 0 && sizeof(T) == 4) ? 4 : 1) mi
   const int line = blockIdx.x * G + g;
   const bool ok = line < a.nlines;
   const int64_t li = ok ? line : 0;
-  const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + li * a.h_ls : nullptr, 1, 1, (int)li};
+  const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + (li % a.h_lines) * a.h_ls : nullptr, 1,
+                     1, (int)(li % a.field_rows)};
   cx<T>* ll = lds + g * L;
   if constexpr (MODE == 0) {
     fixed_passes<T, L, -1, 0, 1, true, false, true>(ll, io, a, ok, j);
@@ -402,6 +405,30 @@ __global__ void __launch_bounds__(256) mixed_twiddle_kernel(cx<T>* tw, int L) {
   tw[m] = cx<T>{(T)c, (T)(-s)};
 }
 
+// 32 x 32 tiles through LDS (one padding column), blockIdx.z = array of
+// the batch (offset by z0).
+template <typename T>
+__global__ void __launch_bounds__(256) mixed_transpose_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                              int rows, int cols, int64_t z0) {
+  __shared__ cx<T> tile[32][33];
+  const int64_t off = (z0 + blockIdx.z) * (int64_t)rows * cols;
+  in += off;
+  out += off;
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) {
+    const int r = r0 + ty + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[ty + k][tx] = in[(int64_t)r * cols + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 32; k += 8) {
+    const int c = c0 + ty + k, r = r0 + tx;
+    if (r < rows && c < cols) out[(int64_t)c * rows + r] = tile[tx][ty + k];
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -427,6 +454,8 @@ hipError_t Mixed<T>::launch(MixedArgs<T> a, int mode, hipStream_t s) {
   if ((mode == 0 && !a.h) || (mode > 0 && a.el.flags)) return hipErrorInvalidValue;
   if (a.el.flags & ~(uint32_t)(EL_PHASE | EL_COMPLEX | EL_LENS)) return hipErrorInvalidValue;
   if (a.nlines <= 0) return hipSuccess;
+  if (a.h_lines <= 0) a.h_lines = a.nlines;
+  if (a.field_rows <= 0) a.field_rows = a.nlines;
   if (a.in_es == 1 && a.out_es == 1) {
     switch (a.L) {
       case 2000: return launch_fixed<T, 2000>(a, mode, s);
@@ -467,6 +496,19 @@ hipError_t Mixed<T>::lines(int L, const MixedPlan& p, const cx<T>* tw, cx<T>* a,
   m.plan = p;
   m.tw = tw;
   return launch(m, dir < 0 ? -1 : 1, s);
+}
+
+template <typename T>
+hipError_t Mixed<T>::transpose(const cx<T>* in, cx<T>* out, int rows, int cols, int64_t batch, hipStream_t s) {
+  if (rows <= 0 || cols <= 0 || batch <= 0) return hipSuccess;
+  for (int64_t z0 = 0; z0 < batch; z0 += 65535) {
+    const unsigned nz = (unsigned)std::min<int64_t>(65535, batch - z0);
+    hipLaunchKernelGGL((mixed_transpose_kernel<T>), dim3((cols + 31) / 32, (rows + 31) / 32, nz), dim3(256), 0, s,
+                       in, out, rows, cols, z0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template struct Mixed<float>;

@@ -31,17 +31,19 @@ bool mixed_plan(int L, MixedPlan* p, bool pow2 = false);
 // padding) and written, elements q < nout times `scale` (the crop), to
 // out + i * out_ls (out[q * out_es]); in == out with equal strides is in
 // place.  With a transfer table h (the convolution mode), the forward
-// transform of line i is multiplied by h[i * h_ls + k] (conjugated if
-// `conj`) and transformed back.  A forward launch applies the element `el`
-// (phase mask, complex mask, lens; flags 0: none) to the field it reads,
-// taking line i as field row i of an nlines x nin field.
+// transform of line i is multiplied by h[(i mod h_lines) * h_ls + k]
+// (conjugated if `conj`) and transformed back.  A forward launch applies the
+// element `el` (phase mask, complex mask, lens; flags 0: none) to the field
+// it reads, taking line i as row i mod field_rows of a field_rows x nin
+// field (batches of fields are consecutive lines).  h_lines and field_rows
+// of 0 mean nlines.
 template <typename T>
 struct MixedArgs {
   const cx<T>* in;
   cx<T>* out;
   const cx<T>* h;
   int64_t in_ls, in_es, out_ls, out_es, h_ls;
-  int nin, nout, conj, nlines, L, tl_shift;
+  int nin, nout, conj, nlines, L, tl_shift, h_lines, field_rows;
   T scale;
   MixedPlan plan;
   const cx<T>* tw;  // exp(-2 pi i m / L), m < L
@@ -59,6 +61,8 @@ struct Mixed {
                           int64_t estride, int dir, hipStream_t s);
   // mode -1 / +1: forward / inverse transforms; 0: the convolution mode.
   static hipError_t launch(MixedArgs<T> a, int mode, hipStream_t s);
+  // out[b][c][r] = in[b][r][c] for `batch` row-major rows x cols arrays.
+  static hipError_t transpose(const cx<T>* in, cx<T>* out, int rows, int cols, int64_t batch, hipStream_t s);
 };
 
 }  // namespace toprop

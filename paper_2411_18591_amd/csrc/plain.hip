@@ -196,8 +196,10 @@ int grid_for(int64_t n) {
 template <typename T>
 hipError_t Plain<T>::run_mixed(const PlainJob<T>& pj, hipStream_t s) {
   const int ny = pj.ny, nx = pj.nx, py = pj.py, px = pj.px;
+  const int64_t nb = pj.nbatch;
   MixedPlan qx = pj.fx.mp, qy = pj.fy.mp;  // power-of-two extents: plans of radix 16, 8, 4, 2
-  if ((!qx.np && !mixed_plan(px, &qx, true)) || (!qy.np && !mixed_plan(py, &qy, true)) || !pj.tr)
+  if ((!qx.np && !mixed_plan(px, &qx, true)) || (!qy.np && !mixed_plan(py, &qy, true)) || !pj.tr || nb < 1 ||
+      nb * ny > INT32_MAX || nb * px > INT32_MAX)
     return hipErrorInvalidValue;
   hipError_t e;
   // rows: the ny field rows, modulated by the element and zero-extended to
@@ -214,14 +216,15 @@ hipError_t Plain<T>::run_mixed(const PlainJob<T>& pj, hipStream_t s) {
   r.out_es = 1;
   r.nout = px;
   r.scale = T(1);
-  r.nlines = ny;
+  r.nlines = (int)(nb * ny);
+  r.field_rows = ny;
   r.L = px;
   r.plan = qx;
   r.tw = pj.fx.tw;
   if ((e = Mixed<T>::launch(r, -1, s)) != hipSuccess) return e;
   // columns as rows of tr [px][ny]: zero-extended to py, forward, times the
   // transposed table, inverse, cropped to ny, in place
-  if ((e = Bluestein<T>::transpose(pj.pad, pj.tr, ny, px, s)) != hipSuccess) return e;
+  if ((e = Mixed<T>::transpose(pj.pad, pj.tr, ny, px, nb, s)) != hipSuccess) return e;
   MixedArgs<T> c{};
   c.in = pj.tr;
   c.out = pj.tr;
@@ -232,12 +235,13 @@ hipError_t Plain<T>::run_mixed(const PlainJob<T>& pj, hipStream_t s) {
   c.h_ls = py;
   c.conj = pj.conj;
   c.scale = T(1);
-  c.nlines = px;
+  c.nlines = (int)(nb * px);
+  c.h_lines = px;
   c.L = py;
   c.plan = qy;
   c.tw = pj.fy.tw;
   if ((e = Mixed<T>::launch(c, 0, s)) != hipSuccess) return e;
-  if ((e = Bluestein<T>::transpose(pj.tr, pj.pad, px, ny, s)) != hipSuccess) return e;
+  if ((e = Mixed<T>::transpose(pj.tr, pj.pad, px, ny, nb, s)) != hipSuccess) return e;
   // inverse rows, cropped to nx and scaled, into the output
   r.el.flags = 0;
   r.in = pj.pad;

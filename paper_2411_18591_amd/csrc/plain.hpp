@@ -22,6 +22,7 @@ struct PlainJob {
   LineFft<T> fy;        // transforms of length py
   cx<T>* tr;            // [px][py] workspace for Bluestein columns, or null
   int ht;               // 1: H is stored transposed ([px][py]) and the job takes run_mixed
+  int64_t nbatch = 1;   // run_mixed: consecutive fields of in / out in one pass (pad and tr hold as many)
 };
 
 template <typename T>
@@ -31,7 +32,9 @@ struct Plain {
   // form 2^a 3^b 5^c 7^d (<= 4096): zero padding, crop, the transfer
   // function and both column transforms fused into three mixed-radix
   // launches around two transposes, and only the ny rows that are not zero
-  // transformed.  Needs H transposed (pj.ht) and tr of px * ny elements.
+  // transformed.  Needs H transposed (pj.ht); pad and tr hold pj.nbatch *
+  // ny * px elements, and the pj.nbatch fields go through each launch
+  // together.
   static hipError_t run_mixed(const PlainJob<T>& pj, hipStream_t s);
   // The table of every bin, [py][px], or [px][py] with `transposed`.
   static hipError_t table(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s, bool transposed = false);
