@@ -1653,14 +1653,20 @@ to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, h
   const bool dbl = sizeof(T) == 8;
   const ElementParams<T> el = make_element<T>(j, j.el_flags);
   if (has_jones(j)) return run_backward_plain_jones<T>(j, gr, w, el, s);
-  for (int64_t b = 0; b < fields; ++b) {
+  // with grad_in given, g_mod = P^H grad_out goes there (in batches through
+  // the mixed-radix sequence) and is modulated in place; else into tmp2
+  const bool direct = gr.grad_in != nullptr;
+  const int64_t step = (w.fast && direct) ? w.chunk : 1;
+  const bool has_el = (j.el_flags & (TO_EL_PHASE | TO_EL_COMPLEX | TO_EL_LENS)) != 0;
+  for (int64_t b = 0; b < fields; b += step) {
+    const int64_t nb = std::min(step, fields - b);
     PlainJob<T> pj;
     pj.ny = j.ny;
     pj.nx = j.nx;
     pj.py = j.py;
     pj.px = j.px;
     pj.in = (const cx<T>*)gr.grad_out + b * nf;
-    pj.out = w.tmp2;  // g_mod = P^H grad_out
+    pj.out = direct ? (cx<T>*)gr.grad_in + b * nf : w.tmp2;  // g_mod = P^H grad_out
     pj.tmp = w.tmp;
     pj.pad = w.pad;
     pj.H = w.H;
@@ -1670,27 +1676,27 @@ to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, h
     pj.fy = w.fy;
     pj.tr = w.tr;
     pj.ht = w.fast ? 1 : 0;
+    pj.nbatch = nb;
     hipError_t e = timed("plain.adjoint", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain adjoint");
-    if (gr.grad_phase && (j.el_flags & TO_EL_PHASE) && gr.saved_in) {
-      e = Plain<T>::phase_grad(w.tmp2, (const cx<T>*)gr.saved_in + b * nf, (T*)gr.grad_phase, j.ny, j.nx,
-                               el, s);
-      if (e != hipSuccess) return hip_fail(e, "plain phase gradient");
-    }
-    if (gr.grad_f && (j.el_flags & TO_EL_LENS) && gr.saved_in) {
-      int nb = 0;
-      e = Plain<T>::lens_grad(w.tmp2, (const cx<T>*)gr.saved_in + b * nf, w.partial, j.ny, j.nx, el, j.el_f, &nb,
-                              s);
-      if (e == hipSuccess) e = launch_reduce_add(w.partial, nb, 1.0, gr.grad_f, s);
-      if (e != hipSuccess) return hip_fail(e, "plain lens gradient");
-    }
-    if (gr.grad_in) {
-      if (j.el_flags & (TO_EL_PHASE | TO_EL_COMPLEX | TO_EL_LENS))
-        e = Plain<T>::modulate(w.tmp2, (cx<T>*)gr.grad_in + b * nf, j.ny, j.nx, el, 1, s);
-      else
-        e = hipMemcpyAsync((cx<T>*)gr.grad_in + b * nf, w.tmp2, nf * sizeof(cx<T>),
-                           hipMemcpyDeviceToDevice, s);
-      if (e != hipSuccess) return hip_fail(e, "plain input gradient");
+    for (int64_t k = 0; k < nb; ++k) {
+      const int64_t fb = b + k;
+      cx<T>* gm = pj.out + k * nf;
+      if (gr.grad_phase && (j.el_flags & TO_EL_PHASE) && gr.saved_in) {
+        e = Plain<T>::phase_grad(gm, (const cx<T>*)gr.saved_in + fb * nf, (T*)gr.grad_phase, j.ny, j.nx, el, s);
+        if (e != hipSuccess) return hip_fail(e, "plain phase gradient");
+      }
+      if (gr.grad_f && (j.el_flags & TO_EL_LENS) && gr.saved_in) {
+        int nblk = 0;
+        e = Plain<T>::lens_grad(gm, (const cx<T>*)gr.saved_in + fb * nf, w.partial, j.ny, j.nx, el, j.el_f, &nblk,
+                                s);
+        if (e == hipSuccess) e = launch_reduce_add(w.partial, nblk, 1.0, gr.grad_f, s);
+        if (e != hipSuccess) return hip_fail(e, "plain lens gradient");
+      }
+      if (direct && has_el) {
+        e = Plain<T>::modulate(gm, gm, j.ny, j.nx, el, 1, s);  // grad_in = conj(M) g_mod, in place
+        if (e != hipSuccess) return hip_fail(e, "plain input gradient");
+      }
     }
   }
   return TO_OK;
