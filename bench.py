@@ -556,12 +556,32 @@ def run_resample(args):
     return 0
 
 
+def _event_ms(fn, steps, warmup):
+    """Mean milliseconds of fn() between two events on the current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
 def run_anylength(args):
     """Padding that is not a power of two: 16 complex64 fields of 1000^2
     (8 um, 700 nm, AS 10 cm, phase mask) padded 2x to 2000^2 (the unfused
     path with mixed-radix line transforms), forward and adjoint, beside the
     same fields padded to 2002^2 (2 * 7 * 11 * 13: Bluestein line transforms)
-    and to 2048^2 (the fused path)."""
+    and to 2048^2 (the fused path).  Beside it, the paper's own examples at
+    their native 2x padding against the power-of-two rounding: a Gaussian
+    Schell-model coherence propagation on a 50^2 grid (100^2 / 128^2), and
+    the 4f image of a 1000^2 field per wavelength (2000^2 / 2048^2, 25
+    wavelengths per call)."""
     import numpy as np
     import torch
 
@@ -596,6 +616,21 @@ def run_anylength(args):
         ms = ev0.elapsed_time(ev1) / args.steps
         res[name] = {"ms_per_step": round(ms, 3), "propagations_per_s": round(2 * B / (ms / 1000.0), 1),
                      "padded": opt.padded_shape(n, n)}
+    # the paper's own small-grid and 4f examples at their native 2x padding
+    native = {}
+    g = 50
+    G = torch.randn((g, g, g, g), dtype=torch.complex64, device=dev, generator=gen)
+    for name, rp in (("gsm_coherence_50_pad100", False), ("gsm_coherence_50_pad128", True)):
+        opt = tp.Optics(dy=10e-6, dx=10e-6, wavelength=0.7e-6, z=0.02, pad=2, round_pow2=rp)
+        native[name] = {"ms": round(_event_ms(lambda: tp.coherence_propagate(G, opt), args.steps, args.warmup), 4),
+                        "padded": opt.padded_shape(g, g)}
+    from paper_2411_18591_amd.fourf import FourF
+    lams = [650e-9 + 100e-9 * k / 24 for k in range(25)]
+    wts = [1.0 / 25] * 25
+    for name, P in (("fourf_1000_pad2000_per_wavelength", 2000), ("fourf_1000_pad2048_per_wavelength", 2048)):
+        sys4f = FourF(0.2, 10e-6, 10e-6, method="asm", padded=(P, P))
+        ms = _event_ms(lambda: sys4f.image(u[0], lams, wts), max(1, args.steps // 2), 1)
+        native[name] = {"ms": round(ms / 25, 4), "padded": [P, P]}
     ms = res["2000"]["ms_per_step"]
     step_bytes = 2 * B * n * n * 16
     print(json.dumps({
@@ -608,7 +643,8 @@ def run_anylength(args):
                                "2002^2 (Bluestein line transforms) and 2048^2 (fused path) for comparison"},
         "hbm_roofline_step": {"algorithmic_bytes": step_bytes,
                               "frac": round(step_bytes / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9), 5)},
-        "bluestein_2002": res["2002"], "pow2_2048": res["2048"], "roofline": None, "cpu_baseline": None}))
+        "bluestein_2002": res["2002"], "pow2_2048": res["2048"], "paper_examples_native_padding": native,
+        "roofline": None, "cpu_baseline": None}))
     return 0
 
 
