@@ -1445,6 +1445,8 @@ struct PlainWork {
   cx<T>* tr;  // transpose buffer of the column passes of non-power-of-two grids, or null
   bool fast;  // Plain::run_mixed applies (the table is stored transposed)
   int64_t chunk;  // fields per batched run_mixed pass (pad and tr hold that many)
+  bool hcalc;     // run_mixed forms the transfer function in its column launch (no table built)
+  TransferParams tp;
 };
 
 // Fields that go through one pass of the mixed-radix sequence together
@@ -1506,6 +1508,10 @@ to_status plain_setup(const to_job& j, DeviceCtx* c, bool conj, hipStream_t s, P
   w->fast = !pow2 && mixed_plan(j.py, &qy, true) && mixed_plan(j.px, &qx, true);
   TransferParams h = make_transfer(j, conj);
   hipError_t e;
+  // one or two fields: AS / Fresnel formed where it is used, no table per call
+  w->hcalc = w->fast && !h.table && j.batch * j.ncomp <= 2;
+  w->tp = h;
+  if (w->hcalc) return TO_OK;
   if (h.table) {  // direct integration: the call's (or the caller's) table
     if (!w->fast) {
       w->H = (cx<T>*)h.table;
@@ -1560,6 +1566,8 @@ to_status run_forward_plain(const to_job& j, DeviceCtx* c, hipStream_t s) {
     pj.fy = w.fy;
     pj.tr = w.tr;
     pj.ht = w.fast ? 1 : 0;
+    pj.hcalc = w.hcalc ? 1 : 0;
+    pj.tp = w.tp;
     pj.nbatch = nb;
     hipError_t e = timed("plain.propagate", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain propagation");
@@ -1616,6 +1624,8 @@ to_status run_backward_plain_jones(const to_job& j, const to_grad& gr, const Pla
       pj.fy = w.fy;
       pj.tr = w.tr;
       pj.ht = w.fast ? 1 : 0;
+      pj.hcalc = w.hcalc ? 1 : 0;
+      pj.tp = w.tp;
       e = timed("plain.adjoint", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     }
     if (e != hipSuccess) return hip_fail(e, "plain adjoint");
@@ -1676,6 +1686,8 @@ to_status run_backward_plain(const to_job& j, const to_grad& gr, DeviceCtx* c, h
     pj.fy = w.fy;
     pj.tr = w.tr;
     pj.ht = w.fast ? 1 : 0;
+    pj.hcalc = w.hcalc ? 1 : 0;
+    pj.tp = w.tp;
     pj.nbatch = nb;
     hipError_t e = timed("plain.adjoint", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain adjoint");
@@ -1744,6 +1756,8 @@ to_status run_batch_plain(const to_job& j, DeviceCtx* c, bool conj_h, const cx<T
     pj.fy = w.fy;
     pj.tr = w.tr;
     pj.ht = w.fast ? 1 : 0;
+    pj.hcalc = w.hcalc ? 1 : 0;
+    pj.tp = w.tp;
     pj.nbatch = std::min(step, j.batch - b);
     e = timed("plain.coh_batch", j.px, dbl, s, [&] { return Plain<T>::run(pj, s); });
     if (e != hipSuccess) return hip_fail(e, "plain propagation");

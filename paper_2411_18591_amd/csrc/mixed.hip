@@ -110,7 +110,8 @@ struct LineIo {
   cx<T>* out;
   const cx<T>* h;
   int in_es, out_es;  // q * es < 2^31: checked on the host
-  int line;
+  int line;           // row of the field (element modulation)
+  int hline;          // row of the transfer table (line mod h_lines)
 };
 
 // b mod ns for b, ns <= 4096 from a float reciprocal of ns (uniform), with
@@ -121,7 +122,7 @@ __device__ __forceinline__ int mod_small(int b, int ns, float inv_ns) {
   return k >= ns ? k - ns : k;
 }
 
-template <typename T, int R, int D, bool IN_G, bool OUT_G, bool MULH, bool EL>
+template <typename T, int R, int D, bool IN_G, bool OUT_G, bool MULH, bool EL, bool HC = false>
 __device__ __forceinline__ void mixed_pass(cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok, int NS,
                                            int j, int TL) {
   constexpr int NB = (kLinePoints + R - 1) / R;  // butterflies per thread
@@ -175,7 +176,9 @@ __device__ __forceinline__ void mixed_pass(cx<T>* ll, const LineIo<T>& io, const
     for (int r = 0; r < R; ++r) {
       const int q = base + r * NS;
       cx<T> y = v[t][r];
-      if constexpr (MULH) {
+      if constexpr (MULH && HC) {
+        y = cmul(y, transfer_at<T>(io.hline, q, a.h_lines, L, a.tp));
+      } else if constexpr (MULH) {
         cx<T> h = io.h[q];
         if (a.conj) h.y = -h.y;
         y = cmul(y, h);
@@ -190,28 +193,28 @@ __device__ __forceinline__ void mixed_pass(cx<T>* ll, const LineIo<T>& io, const
   if constexpr (!OUT_G) __syncthreads();
 }
 
-template <typename T, int D, bool IN_G, bool OUT_G, bool MULH, bool EL = false>
+template <typename T, int D, bool IN_G, bool OUT_G, bool MULH, bool EL = false, bool HC = false>
 __device__ __forceinline__ void mixed_pass_r(int R, cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok,
                                              int NS, int j, int TL) {
   switch (R) {
-    case 2: mixed_pass<T, 2, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
-    case 3: mixed_pass<T, 3, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
-    case 4: mixed_pass<T, 4, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
-    case 5: mixed_pass<T, 5, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
-    case 7: mixed_pass<T, 7, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
-    case 8: mixed_pass<T, 8, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
-    default: mixed_pass<T, 16, D, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, NS, j, TL); break;
+    case 2: mixed_pass<T, 2, D, IN_G, OUT_G, MULH, EL, HC>(ll, io, a, ok, NS, j, TL); break;
+    case 3: mixed_pass<T, 3, D, IN_G, OUT_G, MULH, EL, HC>(ll, io, a, ok, NS, j, TL); break;
+    case 4: mixed_pass<T, 4, D, IN_G, OUT_G, MULH, EL, HC>(ll, io, a, ok, NS, j, TL); break;
+    case 5: mixed_pass<T, 5, D, IN_G, OUT_G, MULH, EL, HC>(ll, io, a, ok, NS, j, TL); break;
+    case 7: mixed_pass<T, 7, D, IN_G, OUT_G, MULH, EL, HC>(ll, io, a, ok, NS, j, TL); break;
+    case 8: mixed_pass<T, 8, D, IN_G, OUT_G, MULH, EL, HC>(ll, io, a, ok, NS, j, TL); break;
+    default: mixed_pass<T, 16, D, IN_G, OUT_G, MULH, EL, HC>(ll, io, a, ok, NS, j, TL); break;
   }
 }
 
 // The passes of one transform: the first reads global memory (IN_G), the
 // last writes it (OUT_G) and/or multiplies by h (MULH).
-template <typename T, int D, bool IN_G, bool OUT_G, bool MULH, bool EL = false>
+template <typename T, int D, bool IN_G, bool OUT_G, bool MULH, bool EL = false, bool HC = false>
 __device__ __forceinline__ void mixed_transform(cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok,
                                                 int j, int TL) {
   const MixedPlan& p = a.plan;
   if (p.np == 1) {
-    mixed_pass_r<T, D, IN_G, OUT_G, MULH, EL>(p.r[0], ll, io, a, ok, 1, j, TL);
+    mixed_pass_r<T, D, IN_G, OUT_G, MULH, EL, HC>(p.r[0], ll, io, a, ok, 1, j, TL);
     return;
   }
   mixed_pass_r<T, D, IN_G, false, false, EL>(p.r[0], ll, io, a, ok, 1, j, TL);
@@ -220,13 +223,13 @@ __device__ __forceinline__ void mixed_transform(cx<T>* ll, const LineIo<T>& io, 
     mixed_pass_r<T, D, false, false, false>(p.r[i], ll, io, a, ok, ns, j, TL);
     ns *= p.r[i];
   }
-  mixed_pass_r<T, D, false, OUT_G, MULH>(p.r[p.np - 1], ll, io, a, ok, ns, j, TL);
+  mixed_pass_r<T, D, false, OUT_G, MULH, false, HC>(p.r[p.np - 1], ll, io, a, ok, ns, j, TL);
 }
 
 // MODE -1 / +1: one forward / inverse transform per line; MODE 0: forward
 // transform, multiplication by the line's h, inverse transform.  EL: the
 // forward transform applies a.el to what it reads.
-template <typename T, int MODE, bool EL>
+template <typename T, int MODE, bool EL, bool HC = false>
 __global__ void __launch_bounds__(256) mixed_lines_kernel(MixedArgs<T> a) {
   __shared__ cx<T> lds[kMixedLds];
   const int TL = 1 << a.tl_shift, G = 256 >> a.tl_shift;
@@ -235,10 +238,10 @@ __global__ void __launch_bounds__(256) mixed_lines_kernel(MixedArgs<T> a) {
   const bool ok = line < a.nlines;
   const int64_t li = ok ? line : 0;
   const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + (li % a.h_lines) * a.h_ls : nullptr,
-                     (int)a.in_es, (int)a.out_es, (int)(li % a.field_rows)};
+                     (int)a.in_es, (int)a.out_es, (int)(li % a.field_rows), (int)(li % a.h_lines)};
   cx<T>* ll = lds + g * (pidx(a.L - 1) + 1);
   if constexpr (MODE == 0) {
-    mixed_transform<T, -1, true, false, true>(ll, io, a, ok, j, TL);
+    mixed_transform<T, -1, true, false, true, false, HC>(ll, io, a, ok, j, TL);
     mixed_transform<T, +1, false, true, false>(ll, io, a, ok, j, TL);
   } else {
     mixed_transform<T, MODE, true, true, false, EL>(ll, io, a, ok, j, TL);
@@ -278,7 +281,7 @@ constexpr int threads_per_line(int L) {
 }
 
 template <typename T, int L, int R, int NS, int D, int R1, bool IN_G, bool OUT_G, bool MULH, bool IN_T, bool OUT_T,
-          bool EL>
+          bool EL, bool HC>
 __device__ __forceinline__ void fixed_pass(cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok, int j) {
   constexpr int TL = threads_per_line(L);
   constexpr int NB = (kLinePoints + R - 1) / R;
@@ -332,7 +335,9 @@ __device__ __forceinline__ void fixed_pass(cx<T>* ll, const LineIo<T>& io, const
         ll[b + r * nb] = y;
       } else {
         const int q = base + r * NS;
-        if constexpr (MULH) {
+        if constexpr (MULH && HC) {
+          y = cmul(y, transfer_at<T>(io.hline, q, a.h_lines, L, a.tp));
+        } else if constexpr (MULH) {
           cx<T> h = io.h[q];
           if (a.conj) h.y = -h.y;
           y = cmul(y, h);
@@ -348,20 +353,21 @@ __device__ __forceinline__ void fixed_pass(cx<T>* ll, const LineIo<T>& io, const
   if constexpr (!OUT_G) __syncthreads();
 }
 
-template <typename T, int L, int D, int P, int NS, bool IN_G, bool OUT_G, bool MULH, bool EL = false>
+template <typename T, int L, int D, int P, int NS, bool IN_G, bool OUT_G, bool MULH, bool EL = false, bool HC = false>
 __device__ __forceinline__ void fixed_passes(cx<T>* ll, const LineIo<T>& io, const MixedArgs<T>& a, bool ok,
                                              int j) {
   constexpr CPlan pl = cplan(L);
   constexpr int R = pl.r[P];
   constexpr bool first = P == 0, last = P == pl.np - 1;
   fixed_pass<T, L, R, NS, D, pl.r[0], first && IN_G, last && OUT_G, last && MULH, P == 1, first && !last,
-             first && EL>(ll, io, a, ok, j);
-  if constexpr (!last) fixed_passes<T, L, D, P + 1, NS * R, IN_G, OUT_G, MULH, EL>(ll, io, a, ok, j);
+             first && EL, HC>(ll, io, a, ok, j);
+  if constexpr (!last) fixed_passes<T, L, D, P + 1, NS * R, IN_G, OUT_G, MULH, EL, HC>(ll, io, a, ok, j);
 }
 
 // The column launch of complex64 holds 128 registers (four waves per SIMD).
-template <typename T, int L, int MODE, bool EL>
-__global__ void __launch_bounds__(256, (MODE == 0 && sizeof(T) == 4) ? 4 : 1) mixed_fixed_kernel(MixedArgs<T> a) {
+template <typename T, int L, int MODE, bool EL, bool HC = false>
+__global__ void __launch_bounds__(256, (MODE == 0 && !HC && sizeof(T) == 4) ? 4 : 1)
+    mixed_fixed_kernel(MixedArgs<T> a) {
   constexpr int TL = threads_per_line(L), G = 256 / TL;
   __shared__ cx<T> lds[G * L];
   const int g = threadIdx.x / TL, j = threadIdx.x % TL;
@@ -369,10 +375,10 @@ __global__ void __launch_bounds__(256, (MODE == 0 && sizeof(T) == 4) ? 4 : 1) mi
   const bool ok = line < a.nlines;
   const int64_t li = ok ? line : 0;
   const LineIo<T> io{a.in + li * a.in_ls, a.out + li * a.out_ls, a.h ? a.h + (li % a.h_lines) * a.h_ls : nullptr, 1,
-                     1, (int)(li % a.field_rows)};
+                     1, (int)(li % a.field_rows), (int)(li % a.h_lines)};
   cx<T>* ll = lds + g * L;
   if constexpr (MODE == 0) {
-    fixed_passes<T, L, -1, 0, 1, true, false, true>(ll, io, a, ok, j);
+    fixed_passes<T, L, -1, 0, 1, true, false, true, false, HC>(ll, io, a, ok, j);
     fixed_passes<T, L, +1, 0, 1, false, true, false>(ll, io, a, ok, j);
   } else {
     fixed_passes<T, L, MODE, 0, 1, true, true, false, EL>(ll, io, a, ok, j);
@@ -389,6 +395,8 @@ hipError_t launch_fixed(const MixedArgs<T>& a, int mode, hipStream_t s) {
     hipLaunchKernelGGL((mixed_fixed_kernel<T, L, -1, false>), grid, dim3(256), 0, s, a);
   else if (mode > 0)
     hipLaunchKernelGGL((mixed_fixed_kernel<T, L, +1, false>), grid, dim3(256), 0, s, a);
+  else if (a.hcalc)
+    hipLaunchKernelGGL((mixed_fixed_kernel<T, L, 0, false, true>), grid, dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((mixed_fixed_kernel<T, L, 0, false>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
@@ -451,7 +459,8 @@ hipError_t Mixed<T>::launch(MixedArgs<T> a, int mode, hipStream_t s) {
   if (a.nin < 1 || a.nout < 1) return hipErrorInvalidValue;
   if (a.in_es < 1 || a.out_es < 1 || a.in_es * a.L >= (int64_t(1) << 31) || a.out_es * a.L >= (int64_t(1) << 31))
     return hipErrorInvalidValue;  // element offsets are 32-bit in the kernel
-  if ((mode == 0 && !a.h) || (mode > 0 && a.el.flags)) return hipErrorInvalidValue;
+  if ((mode == 0 && !a.h && !a.hcalc) || (mode > 0 && a.el.flags)) return hipErrorInvalidValue;
+  if (a.hcalc && (mode != 0 || (a.tp.method != 0 && a.tp.method != 1))) return hipErrorInvalidValue;
   if (a.el.flags & ~(uint32_t)(EL_PHASE | EL_COMPLEX | EL_LENS)) return hipErrorInvalidValue;
   if (a.nlines <= 0) return hipSuccess;
   if (a.h_lines <= 0) a.h_lines = a.nlines;
@@ -476,6 +485,8 @@ hipError_t Mixed<T>::launch(MixedArgs<T> a, int mode, hipStream_t s) {
     hipLaunchKernelGGL((mixed_lines_kernel<T, -1, false>), grid, dim3(256), 0, s, a);
   else if (mode > 0)
     hipLaunchKernelGGL((mixed_lines_kernel<T, +1, false>), grid, dim3(256), 0, s, a);
+  else if (a.hcalc)
+    hipLaunchKernelGGL((mixed_lines_kernel<T, 0, false, true>), grid, dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((mixed_lines_kernel<T, 0, false>), grid, dim3(256), 0, s, a);
   return hipGetLastError();

@@ -48,6 +48,11 @@ struct MixedArgs {
   MixedPlan plan;
   const cx<T>* tw;  // exp(-2 pi i m / L), m < L
   ElementParams<T> el;
+  // hcalc: the convolution mode forms the transfer function itself,
+  // transfer_at(line mod h_lines, k, h_lines, L, tp) (conjugated by tp.conj),
+  // instead of reading h
+  int hcalc;
+  TransferParams tp;
 };
 
 template <typename T>

@@ -231,9 +231,11 @@ hipError_t Plain<T>::run_mixed(const PlainJob<T>& pj, hipStream_t s) {
   c.in_ls = c.out_ls = ny;
   c.in_es = c.out_es = 1;
   c.nin = c.nout = ny;
-  c.h = pj.H;
+  c.h = pj.hcalc ? nullptr : pj.H;
   c.h_ls = py;
   c.conj = pj.conj;
+  c.hcalc = pj.hcalc;
+  c.tp = pj.tp;
   c.scale = T(1);
   c.nlines = (int)(nb * px);
   c.h_lines = px;

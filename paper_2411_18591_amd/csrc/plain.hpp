@@ -23,6 +23,8 @@ struct PlainJob {
   cx<T>* tr;            // [px][py] workspace for Bluestein columns, or null
   int ht;               // 1: H is stored transposed ([px][py]) and the job takes run_mixed
   int64_t nbatch = 1;   // run_mixed: consecutive fields of in / out in one pass (pad and tr hold as many)
+  int hcalc = 0;        // run_mixed: form the transfer function from tp in the column launch (no table)
+  TransferParams tp{};  // AS or Fresnel parameters, tp.conj for the adjoint
 };
 
 template <typename T>
