@@ -103,7 +103,8 @@ __device__ __forceinline__ void small_dft(cx<T>* v) {
 // a.nin at in[q * in_es], zeros beyond), else from the LDS line `ll`.
 // OUT_G: it writes elements q < a.nout, times a.scale, to out[q * out_es],
 // else the whole line to `ll`.  MULH (a last forward pass, natural order):
-// output q is multiplied by h[q] (conjugated if a.conj) before it is stored.
+// output q is multiplied by h[q] (conjugated if a.conj) before it is stored,
+// or with HC by transfer_at(hline, q, h_lines, L, a.tp), formed in place.
 template <typename T>
 struct LineIo {
   const cx<T>* in;
@@ -227,8 +228,9 @@ __device__ __forceinline__ void mixed_transform(cx<T>* ll, const LineIo<T>& io, 
 }
 
 // MODE -1 / +1: one forward / inverse transform per line; MODE 0: forward
-// transform, multiplication by the line's h, inverse transform.  EL: the
-// forward transform applies a.el to what it reads.
+// transform, multiplication by the line's h (HC: the transfer function
+// formed in place), inverse transform.  EL: the forward transform applies
+// a.el to what it reads.
 template <typename T, int MODE, bool EL, bool HC = false>
 __global__ void __launch_bounds__(256) mixed_lines_kernel(MixedArgs<T> a) {
   __shared__ cx<T> lds[kMixedLds];
@@ -364,7 +366,8 @@ __device__ __forceinline__ void fixed_passes(cx<T>* ll, const LineIo<T>& io, con
   if constexpr (!last) fixed_passes<T, L, D, P + 1, NS * R, IN_G, OUT_G, MULH, EL, HC>(ll, io, a, ok, j);
 }
 
-// The column launch of complex64 holds 128 registers (four waves per SIMD).
+// The column launch of complex64 that reads a table holds 128 registers
+// (four waves per SIMD; forming H in place needs a few more).
 template <typename T, int L, int MODE, bool EL, bool HC = false>
 __global__ void __launch_bounds__(256, (MODE == 0 && !HC && sizeof(T) == 4) ? 4 : 1)
     mixed_fixed_kernel(MixedArgs<T> a) {
