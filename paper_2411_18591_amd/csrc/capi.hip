@@ -1899,8 +1899,14 @@ to_status prepare_jobs(const to_job* jobs, int n, DeviceCtx* c, hipStream_t s, s
     table_of[i] = k;
   }
   if (first.empty()) return TO_OK;
-  to_status st = ensure_di(c, total);
+  // scratch after the tables for the transposed column transforms of
+  // tables whose column length is not a power of two
+  size_t scratch = 0;
+  for (int k : first)
+    if (!is_pow2((*out)[k].py)) scratch = std::max(scratch, (size_t)(*out)[k].py * (*out)[k].px * sizeof(cx<T>));
+  to_status st = ensure_di(c, total + scratch);
   if (st != TO_OK) return st;
+  cx<T>* tr = scratch ? (cx<T>*)((char*)c->di + total) : nullptr;
   for (size_t k = 0; k < first.size(); ++k) {
     const to_job& j = (*out)[first[k]];
     cx<T>* H = (cx<T>*)((char*)c->di + offset[k]);
@@ -1908,7 +1914,7 @@ to_status prepare_jobs(const to_job* jobs, int n, DeviceCtx* c, hipStream_t s, s
     if ((st = line_fft<T>(c, j.px, s, &fx)) != TO_OK) return st;
     if ((st = line_fft<T>(c, j.py, s, &fy)) != TO_OK) return st;
     hipError_t e = timed("di_table", j.px, sizeof(T) == 8, s, [&] {
-      return TransferTable<T>::direct_integration(H, di_params(j), fx, fy, s);
+      return TransferTable<T>::direct_integration(H, di_params(j), fx, fy, s, tr);
     });
     if (e != hipSuccess) return hip_fail(e, "direct-integration table");
   }

@@ -60,12 +60,12 @@ int table_grid(int64_t n) {
 
 template <typename T>
 hipError_t TransferTable<T>::direct_integration(cx<T>* H, const DiParams& p, const LineFft<T>& fx,
-                                                const LineFft<T>& fy, hipStream_t s) {
+                                                const LineFft<T>& fy, hipStream_t s, cx<T>* tr) {
   hipLaunchKernelGGL((di_sample_kernel<T>), dim3(table_grid((int64_t)p.py * p.px)), dim3(256), 0, s, H, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = Plain<T>::rows_any(fx, H, p.py, -1, s)) != hipSuccess) return e;
-  return Plain<T>::cols_any(fy, H, p.px, -1, s);
+  return Plain<T>::cols_any(fy, H, p.px, -1, s, tr);
 }
 
 template <typename T>

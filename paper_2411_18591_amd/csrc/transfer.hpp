@@ -37,9 +37,11 @@ hipError_t separable_tables(const SepTableBatch& b, hipStream_t s);
 template <typename T>
 struct TransferTable {
   // DI: H = FFT2(sampled impulse response * dx dy), [py][px] row-major,
-  // built in place in H.
+  // built in place in H.  With `tr` (py * px elements of scratch), columns
+  // whose length is not a power of two are transformed as rows of the
+  // transposed table; without it, in place with strided access.
   static hipError_t direct_integration(cx<T>* H, const DiParams& p, const LineFft<T>& fx, const LineFft<T>& fy,
-                                       hipStream_t s);
+                                       hipStream_t s, cx<T>* tr = nullptr);
   // AS / Fresnel: H at every bin of the padded grid.
   static hipError_t analytic(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s);
 };
