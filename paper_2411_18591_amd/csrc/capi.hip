@@ -3,6 +3,8 @@
 // operations are documented in include/toprop.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -102,6 +104,7 @@ struct DeviceCtx {
   size_t coh_bytes = 0;
   void* di = nullptr;     // direct-integration tables built within a call
   size_t di_bytes = 0;
+  std::vector<const void*> di_t;  // those of the current call stored transposed ([px][py])
   void* sep = nullptr;    // separable complex64 transfer-function tables of a call
   size_t sep_bytes = 0;
   void* rs = nullptr;     // per-axis tables of a resampling call
@@ -1513,7 +1516,8 @@ to_status plain_setup(const to_job& j, DeviceCtx* c, bool conj, hipStream_t s, P
   w->tp = h;
   if (w->hcalc) return TO_OK;
   if (h.table) {  // direct integration: the call's (or the caller's) table
-    if (!w->fast) {
+    const bool built_t = std::find(c->di_t.begin(), c->di_t.end(), h.table) != c->di_t.end();
+    if (!w->fast || built_t) {  // the table as it is, or built transposed by this call
       w->H = (cx<T>*)h.table;
       return TO_OK;
     }
@@ -1898,12 +1902,20 @@ to_status prepare_jobs(const to_job* jobs, int n, DeviceCtx* c, hipStream_t s, s
     }
     table_of[i] = k;
   }
+  c->di_t.clear();
   if (first.empty()) return TO_OK;
-  // scratch after the tables for the transposed column transforms of
-  // tables whose column length is not a power of two
+  // Tables of grids that take the any-length mixed-radix sequence are built
+  // transposed, the layout its column launch reads; others with a column
+  // length that is not a power of two transform their columns as rows of
+  // the transposed table.  Both use scratch after the tables.
+  auto transposed = [](const to_job& j) {
+    MixedPlan a, b;
+    return !(is_pow2(j.py) && is_pow2(j.px)) && mixed_plan(j.py, &a, true) && mixed_plan(j.px, &b, true);
+  };
   size_t scratch = 0;
   for (int k : first)
-    if (!is_pow2((*out)[k].py)) scratch = std::max(scratch, (size_t)(*out)[k].py * (*out)[k].px * sizeof(cx<T>));
+    if (!is_pow2((*out)[k].py) || transposed((*out)[k]))
+      scratch = std::max(scratch, (size_t)(*out)[k].py * (*out)[k].px * sizeof(cx<T>));
   to_status st = ensure_di(c, total + scratch);
   if (st != TO_OK) return st;
   cx<T>* tr = scratch ? (cx<T>*)((char*)c->di + total) : nullptr;
@@ -1913,8 +1925,11 @@ to_status prepare_jobs(const to_job* jobs, int n, DeviceCtx* c, hipStream_t s, s
     LineFft<T> fx, fy;
     if ((st = line_fft<T>(c, j.px, s, &fx)) != TO_OK) return st;
     if ((st = line_fft<T>(c, j.py, s, &fy)) != TO_OK) return st;
+    const bool t = transposed(j);
+    if (t) c->di_t.push_back(H);
     hipError_t e = timed("di_table", j.px, sizeof(T) == 8, s, [&] {
-      return TransferTable<T>::direct_integration(H, di_params(j), fx, fy, s, tr);
+      return t ? TransferTable<T>::direct_integration_t(H, tr, di_params(j), fx, fy, s)
+               : TransferTable<T>::direct_integration(H, di_params(j), fx, fy, s, tr);
     });
     if (e != hipSuccess) return hip_fail(e, "direct-integration table");
   }

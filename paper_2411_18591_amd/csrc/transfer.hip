@@ -69,6 +69,17 @@ hipError_t TransferTable<T>::direct_integration(cx<T>* H, const DiParams& p, con
 }
 
 template <typename T>
+hipError_t TransferTable<T>::direct_integration_t(cx<T>* HT, cx<T>* tmp, const DiParams& p, const LineFft<T>& fx,
+                                                  const LineFft<T>& fy, hipStream_t s) {
+  hipLaunchKernelGGL((di_sample_kernel<T>), dim3(table_grid((int64_t)p.py * p.px)), dim3(256), 0, s, tmp, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = Plain<T>::rows_any(fx, tmp, p.py, -1, s)) != hipSuccess) return e;
+  if ((e = Mixed<T>::transpose(tmp, HT, p.py, p.px, 1, s)) != hipSuccess) return e;
+  return Plain<T>::rows_any(fy, HT, p.px, -1, s);
+}
+
+template <typename T>
 hipError_t TransferTable<T>::analytic(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s) {
   return Plain<T>::table(H, py, px, p, s);
 }

@@ -42,6 +42,10 @@ struct TransferTable {
   // transposed table; without it, in place with strided access.
   static hipError_t direct_integration(cx<T>* H, const DiParams& p, const LineFft<T>& fx, const LineFft<T>& fy,
                                        hipStream_t s, cx<T>* tr = nullptr);
+  // The same table stored transposed, HT[kx][ky] ([px][py]), as the
+  // any-length column launch reads it; `tmp` holds py * px elements.
+  static hipError_t direct_integration_t(cx<T>* HT, cx<T>* tmp, const DiParams& p, const LineFft<T>& fx,
+                                         const LineFft<T>& fy, hipStream_t s);
   // AS / Fresnel: H at every bin of the padded grid.
   static hipError_t analytic(cx<T>* H, int py, int px, const TransferParams& p, hipStream_t s);
 };

@@ -152,19 +152,22 @@ def test_4f_at_padding_that_is_not_a_power_of_two(method):
     assert rel(to_np(I), exp) <= 4e-5
 
 
-def test_cached_di_tables_give_the_same_image():
+@pytest.mark.parametrize("padded", [None, (96, 80)])
+def test_cached_di_tables_give_the_same_image(padded):
     """With the DI tables kept by the system (built once by
-    to_transfer_table), images equal the per-call-table images bitwise."""
+    to_transfer_table), images equal the per-call-table images bitwise; on
+    the 96 x 80 grid the per-call tables are built transposed for the
+    any-length sequence and the kept ones are transposed per job."""
     FourF = _fourf()
-    announce("4f cached DI tables")
+    announce(f"4f cached DI tables {padded}")
     rng = np.random.default_rng(992)
     ny, nx, d = 48, 40, 10e-6
     wl = workloads.Polychromatic4fWorkload(count=7, fwhm=40e-9)
     lams, wts = wl.wavelengths(), wl.weights()
     f = 2.0 * max(oracle.critical_distance(ny, nx, d, d, lam) for lam in lams)
     u = to_gpu(crandn(rng, 2, ny, nx, dtype=np.complex64), torch)
-    a = FourF(f, d, d, method="auto").image(u, lams, wts)
-    cached = FourF(f, d, d, method="auto", cache_tables=True)
+    a = FourF(f, d, d, method="auto", padded=padded).image(u, lams, wts)
+    cached = FourF(f, d, d, method="auto", cache_tables=True, padded=padded)
     b = cached.image(u, lams, wts)
     c = cached.image(u, lams, wts)
     torch.cuda.synchronize()
