@@ -251,8 +251,8 @@ __global__ void __launch_bounds__(256) mixed_lines_kernel(MixedArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// Lengths fixed at compile time (the paper's padded extents 2000, 500, 100
-// and 1000): the plan, strides and divisors are constants, every LDS and
+// Lengths fixed at compile time (the paper's grids 1000, 250, 50 and their
+// 2x padding 2000, 500, 100): the plan, strides and divisors are constants, every LDS and
 // global offset of a pass is an immediate from one per-butterfly base, and
 // the line needs no LDS padding: the first pass, whose natural stores
 // (position b R1 + r) would stride across the banks, stores output r of
@@ -473,7 +473,9 @@ hipError_t Mixed<T>::launch(MixedArgs<T> a, int mode, hipStream_t s) {
       case 2000: return launch_fixed<T, 2000>(a, mode, s);
       case 1000: return launch_fixed<T, 1000>(a, mode, s);
       case 500: return launch_fixed<T, 500>(a, mode, s);
+      case 250: return launch_fixed<T, 250>(a, mode, s);
       case 100: return launch_fixed<T, 100>(a, mode, s);
+      case 50: return launch_fixed<T, 50>(a, mode, s);
       default: break;
     }
   }

@@ -6,7 +6,7 @@ method on its power-of-two FFTs (any other length).  Against the FP64 oracle
 (whose transform of such lengths is the naive DFT, pinned on the CPU): even
 and odd lengths, every radix (2, 3, 4, 5, 7, 8, 16), both line methods in
 one job, a line of 2100 points (256 threads per line), the lengths with
-compile-time kernels (100, 500, 1000, 2000), AS / Fresnel / DI (at
+compile-time kernels (50, 100, 250, 500, 1000, 2000), AS / Fresnel / DI (at
 the smallest admissible DI padding, 2n - 1), forward and adjoint, elements,
 the MSE epilogue and the mask gradient, mixed with power-of-two jobs in one
 call; at the paper's 1000^2 -> 2000^2 scale (and 2002^2, a Bluestein
@@ -53,6 +53,8 @@ CASES = [
     (2, 1050, 3, 2100, "asm"),    # long mixed-radix rows, 256 threads per line (M 3, M 4*5*5*3*7)
     (250, 7, 500, 14, "asm"),     # compile-time length 500 in the column launch (the paper's 250^2 padded)
     (3, 500, 6, 1000, "fresnel"), # compile-time length 1000 in the row launches
+    (125, 7, 250, 14, "asm"),     # compile-time length 250 (the paper's 250^2 grid without padding)
+    (7, 25, 14, 50, "fresnel"),   # compile-time length 50 (the paper's 50^2 grid without padding)
 ]
 
 
