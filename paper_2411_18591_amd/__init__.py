@@ -116,6 +116,19 @@ def next_pow2(n: int) -> int:
     return p
 
 
+def next_smooth(n: int) -> int:
+    """The least m >= max(n, 3) whose prime factors are all at most 7."""
+    m = max(int(n), 3)
+    while True:
+        r = m
+        for q in (2, 3, 5, 7):
+            while r % q == 0:
+                r //= q
+        if r == 1:
+            return m
+        m += 1
+
+
 @dataclass
 class Optics:
     """Geometry and free-space parameters of one propagation.
@@ -123,7 +136,10 @@ class Optics:
     The padded grid is ``padded`` = (py, px) if given, else each extent is
     ``pad`` times the field, rounded up to a power of two unless
     ``round_pow2`` is False (extents that are not powers of two, up to 4096,
-    run through the unfused path with mixed-radix or Bluestein transforms).  ``method`` is
+    run through the unfused path with mixed-radix or Bluestein transforms);
+    with ``round_pow2=False`` and ``round_smooth=True`` it is rounded up to
+    the next length of the form 2^a 3^b 5^c 7^d instead (2002 -> 2016), which
+    keeps it on the mixed-radix transforms.  ``method`` is
     "asm", "fresnel", "di" (direct integration; needs pad >= 2 and z > 0) or
     "auto" (DI at or beyond the critical distance, AS below it)."""
     dy: float
@@ -136,11 +152,14 @@ class Optics:
     x0: float = 0.0
     padded: Optional[tuple] = None
     round_pow2: bool = True
+    round_smooth: bool = False
 
     def padded_shape(self, ny: int, nx: int):
         if self.padded is not None:
             return int(self.padded[0]), int(self.padded[1])
         if not self.round_pow2:
+            if self.round_smooth:
+                return next_smooth(self.pad * ny), next_smooth(self.pad * nx)
             return self.pad * ny, self.pad * nx
         return next_pow2(self.pad * ny), next_pow2(self.pad * nx)
 

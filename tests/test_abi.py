@@ -243,3 +243,22 @@ def test_transfer_table_validation(capi):
     j.method = capi.TO_DI
     j.py = 16
     assert lib.to_transfer_table(ctypes.byref(j), capi.TO_C64, 0x1000, None) == capi.TO_E_UNSUPPORTED
+
+
+def test_next_smooth_padding():
+    """round_smooth padding: the least length >= max(n, 3) with no prime
+    factor above 7, checked by brute force up to 5000."""
+    import paper_2411_18591_amd as tp
+
+    def smooth(m):
+        for q in (2, 3, 5, 7):
+            while m % q == 0:
+                m //= q
+        return m == 1
+
+    for n in range(1, 5001):
+        m = tp.next_smooth(n)
+        assert m >= max(n, 3) and smooth(m)
+        assert not any(smooth(k) for k in range(max(n, 3), m))
+    o = tp.Optics(dy=1e-5, dx=1e-5, wavelength=7e-7, z=0.1, pad=2, round_pow2=False, round_smooth=True)
+    assert o.padded_shape(1001, 1000) == (2016, 2000)

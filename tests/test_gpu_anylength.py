@@ -300,3 +300,18 @@ def test_transfer_formed_in_launch_equals_table(dtype, method):
             assert rel(to_np(adj1[0]), to_np(adj[k])) <= ulps, (ny, k)
         torch.cuda.synchronize()
         assert rel(to_np(big), _oracle(to_np(u), opt)) <= TOL[dtype]
+
+
+def test_round_smooth_padding():
+    """round_smooth rounds 2n up to the next 2/3/5/7-smooth length (11 x 13
+    -> 24 x 27, instead of the Bluestein lengths 22 x 26): against the oracle
+    on the same padded grid."""
+    tp = _tp()
+    announce("any-length round_smooth padding")
+    rng = np.random.default_rng(1270)
+    u = crandn(rng, 2, 11, 13, dtype=np.complex128)
+    opt = tp.Optics(dy=4e-6, dx=4e-6, wavelength=0.6e-6, z=3e-4, pad=2, round_pow2=False, round_smooth=True)
+    assert opt.padded_shape(11, 13) == (24, 27)
+    out = tp.propagate(to_gpu(u, torch), opt)
+    torch.cuda.synchronize()
+    assert rel(to_np(out), _oracle(u, opt)) <= 1e-12
