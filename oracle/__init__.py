@@ -360,7 +360,14 @@ def cis_cycles(c) -> np.ndarray:
 
 
 def phase_mask(phi) -> np.ndarray:
-    """Modulation profile of a phase modulator: ``exp(i phi)``."""
+    """Modulation profile of a phase modulator: ``exp(i phi)``.
+
+    The paper names phase modulators without a formula; the sign follows
+    the ``exp(+i k z)`` convention of Eq. (transfer_function).  Pinned by:
+    the thin-lens phase through this function is the lens that the
+    Gaussian-beam closed form pins, and a phase ramp 2 pi g x moves the
+    beam to +lambda z g (exact shift identity of the Fresnel transfer
+    function on the padded grid)."""
     return np.exp(1j * np.asarray(phi, dtype=np.float64))
 
 
@@ -455,7 +462,11 @@ def incoherent_sum(fields, weights, ncomp: int = 1) -> np.ndarray:
 
 
 def inner(u, v, dy: float, dx: float) -> complex:
-    """Inner product ``sum u conj(v) dx dy``, as in Eq. (loss_func)."""
+    """Inner product ``sum u conj(v) dx dy``, as in Eq. (loss_func).
+
+    Pinned by the closed-form overlap of two displaced, tilted Gaussians
+    (conjugated operand, area element, normalisation) and by
+    ``inner(u, u) = power(u)``."""
     return complex(np.sum(np.asarray(u) * np.conj(np.asarray(v))) * dx * dy)
 
 

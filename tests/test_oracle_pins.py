@@ -762,3 +762,80 @@ def test_incoherent_sum_equals_coherence_diagonal():
     w = [0.5, 1.5, 0.25]
     G = sum(wk * np.einsum("ab,cd->abcd", u, np.conj(u)) for wk, u in zip(w, modes))
     assert np.allclose(oracle.coherence_intensity(G), oracle.incoherent_sum(modes, w), atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Overlap integral of Eq. (loss_func) and the sign of a phase modulator
+# --------------------------------------------------------------------------
+
+def test_inner_gaussian_overlap_closed_form():
+    """Eq. (loss_func)'s overlap integral of two Gaussians of amplitude
+    exp(-r^2/w0^2), the second displaced by a and tilted by exp(i k0 x):
+
+        int u conj(v) dA = (pi w0^2 / 2) exp(-|a|^2 / (2 w0^2))
+                           exp(-k0^2 w0^2 / 8) exp(-i k0 a_x / 2)
+
+    (complete the square: r^2 + |r - a|^2 = 2 |r - a/2|^2 + |a|^2 / 2).  The
+    Riemann sum of a well-sampled Gaussian equals its integral far below
+    rounding, so this fixes the conjugated operand (the sign of the
+    imaginary part), the area element and the normalisation."""
+    n, d, w0 = 160, 10e-6, 150e-6
+    ax, ay, k0 = 30e-6, -20e-6, 2 * math.pi / 400e-6
+    x = oracle.coords(n, d)[None, :]
+    y = oracle.coords(n, d)[:, None]
+    u = np.exp(-(x ** 2 + y ** 2) / w0 ** 2)
+    v = np.exp(-((x - ax) ** 2 + (y - ay) ** 2) / w0 ** 2) * np.exp(1j * k0 * x)
+    expect = (math.pi * w0 ** 2 / 2) * math.exp(-(ax ** 2 + ay ** 2) / (2 * w0 ** 2)) \
+        * math.exp(-k0 ** 2 * w0 ** 2 / 8) * np.exp(-1j * k0 * ax / 2)
+    got = oracle.inner(u, v, d, d)
+    assert abs(got - expect) < 1e-12 * abs(expect)
+    assert got.imag < 0  # k0 ax > 0
+    # Hermitian symmetry, and the self-overlap is the power
+    assert abs(oracle.inner(v, u, d, d) - np.conj(got)) < 1e-15 * abs(got)
+    assert abs(oracle.inner(u, u, d, d) - oracle.power(u, d, d)) < 1e-15 * oracle.power(u, d, d)
+    assert abs(oracle.power(u, d, d) - math.pi * w0 ** 2 / 2) < 1e-12 * math.pi * w0 ** 2
+    # Eq. (loss_func) for normalised fields: 1 - |<u, v>|^2 / (|u|^2 |v|^2)
+    loss = 1 - abs(got) ** 2 / (oracle.power(u, d, d) * oracle.power(v, d, d))
+    assert abs(loss - (1 - math.exp(-(ax ** 2 + ay ** 2) / w0 ** 2) * math.exp(-k0 ** 2 * w0 ** 2 / 4))) < 1e-12
+
+
+def test_phase_mask_equals_pinned_lens():
+    """A phase modulator with the thin-lens phase -pi r^2 / (lambda f) is the
+    thin lens, whose sign the Gaussian-beam closed form pins (f > 0
+    converges to the q-parameter waist).  exp(-i phi) would give the
+    diverging lens."""
+    ny, nx, d, lam, f = 48, 40, 7e-6, 0.6e-6, 0.03
+    phi = 2 * math.pi * oracle.lens_phase_cycles(ny, nx, d, d, lam, f)
+    assert rel(oracle.phase_mask(phi), oracle.lens(ny, nx, d, d, lam, f)) < 1e-12
+
+
+def test_phase_ramp_steers_towards_positive_x():
+    """A phase ramp phi = 2 pi g x tilts the beam toward +x under the
+    exp(+i k z) convention of Eq. (transfer_function): after Fresnel
+    propagation over z the field is, exactly on the padded grid,
+
+        P[e^{2 pi i g x} u](x) = e^{2 pi i g x} e^{-i pi lambda z g^2} (P u)(x - lambda z g)
+
+    for g a frequency of the padded grid and lambda z g a whole number s of
+    samples (the spectrum of the beam vanishes at the wrap).  A modulator
+    applying exp(-i phi) would move the beam to -s.  Tolerance: z / lambda
+    is 1e5 cycles here, so the two propagations' FP64 phase rounding
+    reaches ~1e-11 relative (the wrong sign is an O(1) error)."""
+    n, d, lam, w0 = 256, 5e-6, 0.5e-6, 100e-6
+    k0, s = 10, 20
+    g = k0 / (2 * n * d)
+    z = s * d / (lam * g)
+    x = oracle.coords(n, d)[None, :]
+    y = oracle.coords(n, d)[:, None]
+    u = np.exp(-(x ** 2 + y ** 2) / w0 ** 2) * np.ones((n, n))
+    ramp = 2 * math.pi * g * x * np.ones((n, 1))
+    tilted = oracle.propagate(oracle.modulate(u, oracle.phase_mask(ramp)), d, d, lam, z, oracle.FRESNEL, pad=2)
+    plain = oracle.propagate(u, d, d, lam, z, oracle.FRESNEL, pad=2)
+    shifted = np.zeros_like(plain)
+    shifted[:, s:] = plain[:, :-s]
+    expect = np.exp(2j * math.pi * g * x) * np.exp(-1j * math.pi * lam * z * g * g) * shifted
+    assert rel(tilted, expect) < 1e-10
+    # the intensity centroid sits at +lambda z g
+    I = np.abs(tilted) ** 2
+    cx_ = float(np.sum(I * x) / np.sum(I))
+    assert abs(cx_ - lam * z * g) < 1e-6 * d
