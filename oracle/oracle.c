@@ -32,6 +32,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -158,6 +159,28 @@ int orc_dft2_any(cplx *a, long ny, long nx, int sign)
     return 0;
 }
 
+/* The same 2-D transform with its lines shared among the threads of the
+ * enclosing OpenMP team (call from inside a parallel region, by every
+ * thread): each row and each column is transformed exactly as above, only
+ * by whichever thread takes it.  Used when a call has fewer fields than
+ * threads, so that one large field still occupies every core. */
+static void dft2_any_team(cplx *a, long ny, long nx, int sign)
+{
+    long m = ny > nx ? ny : nx;
+    cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)m);
+    cplx *col = (cplx *)malloc(sizeof(cplx) * (size_t)ny);
+#pragma omp for schedule(static)
+    for (long r = 0; r < ny; ++r) dft_any(a + r * nx, nx, sign, tmp);
+#pragma omp for schedule(static)
+    for (long c = 0; c < nx; ++c) {
+        for (long r = 0; r < ny; ++r) col[r] = a[r * nx + c];
+        dft_any(col, ny, sign, tmp);
+        for (long r = 0; r < ny; ++r) a[r * nx + c] = col[r];
+    }
+    free(col);
+    free(tmp);
+}
+
 /* ---------------------------------------------------------------------- */
 /* Transfer functions                                                      */
 /* ---------------------------------------------------------------------- */
@@ -200,6 +223,7 @@ static long double tf_phase_cycles(long double fx, long double fy, double lam, d
 void orc_transfer(cplx *H, long py, long px, double dy, double dx, double lam, double z,
                   int method)
 {
+#pragma omp parallel for schedule(static)
     for (long ky = 0; ky < py; ++ky) {
         long double fy = freq_of_bin(ky, py, dy);
         for (long kx = 0; kx < px; ++kx) {
@@ -296,6 +320,29 @@ static void propagate_one(const cplx *in, cplx *out, cplx *work, const cplx *H, 
         for (long c = 0; c < nx; ++c) out[r * nx + c] = work[(r + oy) * px + c + ox] * scale;
 }
 
+/* propagate_one with every step shared among the threads of the enclosing
+ * team (call from inside a parallel region, by every thread); `work` is
+ * shared.  Same arithmetic per element and per line as propagate_one. */
+static void propagate_one_team(const cplx *in, cplx *out, cplx *work, const cplx *H, long ny,
+                               long nx, long py, long px, int adjoint)
+{
+    long oy = (py - ny) / 2, ox = (px - nx) / 2;
+#pragma omp for schedule(static)
+    for (long r = 0; r < py; ++r) {
+        memset(work + r * px, 0, sizeof(cplx) * (size_t)px);
+        if (r >= oy && r < oy + ny)
+            memcpy(work + r * px + ox, in + (r - oy) * nx, sizeof(cplx) * (size_t)nx);
+    }
+    dft2_any_team(work, py, px, -1);
+#pragma omp for schedule(static)
+    for (long i = 0; i < py * px; ++i) work[i] *= adjoint ? conj(H[i]) : H[i];
+    dft2_any_team(work, py, px, +1);
+    double scale = 1.0 / ((double)py * (double)px);
+#pragma omp for schedule(static)
+    for (long r = 0; r < ny; ++r)
+        for (long c = 0; c < nx; ++c) out[r * nx + c] = work[(r + oy) * px + c + ox] * scale;
+}
+
 /* Batched propagation of `batch` contiguous ny x nx fields on a py x px
  * padded grid.  Returns -1 for an unsupported size (padded extents no
  * smaller than the field; extents that are not powers of two use the naive
@@ -309,12 +356,22 @@ int orc_propagate(const cplx *in, cplx *out, long batch, long ny, long nx, long 
         free(H);
         return -1;
     }
+    if (batch >= omp_get_max_threads()) {
+        /* one field per thread at a time */
 #pragma omp parallel
-    {
-        cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
+        {
+            cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
 #pragma omp for schedule(dynamic, 1)
+            for (long b = 0; b < batch; ++b)
+                propagate_one(in + b * ny * nx, out + b * ny * nx, work, H, ny, nx, py, px, adjoint);
+            free(work);
+        }
+    } else {
+        /* fewer fields than threads: the threads share each field's lines */
+        cplx *work = (cplx *)malloc(sizeof(cplx) * (size_t)(py * px));
+#pragma omp parallel
         for (long b = 0; b < batch; ++b)
-            propagate_one(in + b * ny * nx, out + b * ny * nx, work, H, ny, nx, py, px, adjoint);
+            propagate_one_team(in + b * ny * nx, out + b * ny * nx, work, H, ny, nx, py, px, adjoint);
         free(work);
     }
     free(H);
