@@ -513,8 +513,31 @@ hipError_t prepare_transfer(const to_job& j, Lane* c, hipStream_t s, TransferPar
 // Fields per row block: a block pipelines the loads of its next field behind
 // the transform of the current one (and evaluates the element's modulation
 // once for all of them), while the launch keeps >= ~2048 blocks.
-int fields_per_block_rows(int row_blocks, int nfields) {
-  int fpb = (int)((int64_t)row_blocks * nfields / 2048);
+// Target block count of a row-pass launch: as many blocks as fit on the
+// device at once (one round of workgroups, each taking its share of the
+// fields), or TOPROP_ROW_BLOCKS.
+int device_cus() {
+  static int n = [] {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      return 256;
+    return cus;
+  }();
+  return n;
+}
+
+int row_blocks_target(int lx, bool dbl, bool heavy) {
+  static int env = [] {
+    const char* s = getenv("TOPROP_ROW_BLOCKS");
+    const int x = s ? atoi(s) : 0;
+    return x >= 64 ? x : 0;
+  }();
+  return env ? env : device_cus() * row_blocks_per_cu(lx, dbl, heavy);
+}
+
+int fields_per_block_rows(int row_blocks, int nfields, int target) {
+  int fpb = (int)((int64_t)row_blocks * nfields / std::max(1, target));
   if (fpb < 1) fpb = 1;
   if (fpb > 8) fpb = 8;
   if (fpb > nfields) fpb = nfields;
@@ -713,7 +736,8 @@ RowFwdArgs<T> row_fwd_args(const to_job& j, const Geometry& g, DeviceCtx* c, cx<
                            int64_t f0) {
   RowFwdArgs<T> ra;
   memset(&ra, 0, sizeof(ra));
-  ra.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block, nf);
+  ra.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block, nf,
+                                  row_blocks_target(g.lx, sizeof(T) == 8, g.nc_kernel == 3));
   ra.coh_m = coh_m;
   ra.f_off = f0;
   ra.in = in;
@@ -793,7 +817,8 @@ to_status finish_forward_chunk(const to_job& j, const Geometry& g, DeviceCtx* c,
   ia.epi_grad = j.epi_grad ? (cx<T>*)j.epi_grad + f0 * g.in_stride : nullptr;
   ia.row_partial = ln->partial;
   ia.backward = 0;
-  ia.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block, nf);
+  ia.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block, nf,
+                                  row_blocks_target(g.lx, sizeof(T) == 8, g.nc_kernel == 3));
   const int inv_blocks_y = (nf + ia.fpb - 1) / ia.fpb;
   ia.el = make_element<T>(j, 0);
   const bool dbl = sizeof(T) == 8;
@@ -1008,7 +1033,7 @@ to_status run_forward_chain(const to_job* jobs, int n, DeviceCtx* c, Lane* ln, h
       ma.nx = j0.nx;
       ma.tc_shift = g.tc_shift;
       ma.nfields = nf;
-      ma.fpb = fields_per_block_rows(row_blocks, nf);
+      ma.fpb = fields_per_block_rows(row_blocks, nf, row_blocks_target(g.lx, sizeof(T) == 8, false));
       ma.scale = (T)(1.0 / ((double)g.lx * (double)g.ly));
       ma.el = el[l + 1];
       ma.tw = twiddles<T>(c, g.lx);
@@ -1026,8 +1051,9 @@ to_status run_forward_chain(const to_job* jobs, int n, DeviceCtx* c, Lane* ln, h
 
 // Field groups of the fused backward boundary: each block takes `fpb`
 // fields, and the groups' gradient partials are combined in order.
-int mid_bwd_fields_per_block(int row_blocks, int nf) {
-  return fields_per_block_rows(row_blocks, nf);
+template <typename T>
+int mid_bwd_fields_per_block(int row_blocks, int nf, const Geometry& g) {
+  return fields_per_block_rows(row_blocks, nf, row_blocks_target(g.lx, sizeof(T) == 8, false));
 }
 
 // Reduction partials (doubles) of a backward chain's fused boundaries: lens
@@ -1037,7 +1063,7 @@ template <typename T>
 size_t chain_bwd_partial_count(const to_job& j, const Geometry& g) {
   const int row_blocks = (j.ny + g.rows_per_block - 1) / g.rows_per_block;
   const int nf = (int)g.chunk;
-  const int fpb = mid_bwd_fields_per_block(row_blocks, nf);
+  const int fpb = mid_bwd_fields_per_block<T>(row_blocks, nf, g);
   const int groups = (nf + fpb - 1) / fpb;
   size_t n = (size_t)groups * j.ny;
   if (groups > 1) n += ((size_t)groups * j.ny * j.nx * sizeof(T) + sizeof(double) - 1) / sizeof(double);
@@ -1087,7 +1113,7 @@ to_status run_backward_chain(const to_job* jobs, const to_grad* grads, int n, De
       mb.nx = j.nx;
       mb.tc_shift = g.tc_shift;
       mb.nfields = nf;
-      mb.fpb = mid_bwd_fields_per_block(row_blocks, nf);
+      mb.fpb = mid_bwd_fields_per_block<T>(row_blocks, nf, g);
       const int groups = (nf + mb.fpb - 1) / mb.fpb;
       mb.scale = (T)(1.0 / ((double)g.lx * (double)g.ly));
       mb.el = make_element<T>(j, j.el_flags);

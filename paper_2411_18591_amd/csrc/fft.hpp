@@ -157,6 +157,54 @@ struct DftHalfZero {
 };
 
 // ---------------------------------------------------------------------------
+// Raw buffer access.  A buffer resource holds a wave-uniform base address
+// and size in scalar registers; each access adds a per-lane byte offset
+// (voff) and a wave-uniform byte offset (soff).  Strided register sets
+// (element m at soff = m * stride) then cost no vector instructions for
+// their addresses.  Word 3 is the gfx9 descriptor word for untyped access
+// (32-bit data format).  The base must be wave-uniform and both offsets
+// must stay below 2^32 and within `bytes`.
+// ---------------------------------------------------------------------------
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ cx<float> buf_ld(rsrc_t r, uint32_t voff, uint32_t soff, float) {
+  return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ cx<double> buf_ld(rsrc_t r, uint32_t voff, uint32_t soff, double) {
+  return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> buf_ld(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return buf_ld(r, voff, soff, T());
+}
+__device__ __forceinline__ void buf_st(rsrc_t r, uint32_t voff, uint32_t soff, cx<float> v) {
+  using V = unsigned int __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_st(rsrc_t r, uint32_t voff, uint32_t soff, cx<double> v) {
+  using V = unsigned int __attribute__((ext_vector_type(4)));
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, v), r, voff, soff, 0);
+}
+// Real scalars (masks, targets, weights, gradients).
+__device__ __forceinline__ void buf_str(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_str(rsrc_t r, uint32_t voff, uint32_t soff, double v) {
+  using V = unsigned int __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ float buf_ldr(rsrc_t r, uint32_t voff, uint32_t soff, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ double buf_ldr(rsrc_t r, uint32_t voff, uint32_t soff, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// ---------------------------------------------------------------------------
 // Pass schedule.  A length-L transform with R points per thread runs passes
 // of radix R while they fit, and one final pass of the remaining radix.
 // ---------------------------------------------------------------------------
@@ -186,6 +234,7 @@ template <typename T, int L, int R, int RP, int NS, int D, bool FIRST_HALF_ZERO>
 __device__ __forceinline__ void stockham_butterflies(cx<T>* v, int j, const cx<T>* __restrict__ tw) {
   constexpr int TT = L / R;
   constexpr int NB = R / RP;
+  const rsrc_t twr = buf_rsrc(tw, (uint32_t)(L * sizeof(cx<T>)));
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
     cx<T> u[RP];
@@ -197,7 +246,9 @@ __device__ __forceinline__ void stockham_butterflies(cx<T>* v, int j, const cx<T
       constexpr int step = L / (NS * RP);
 #pragma unroll
       for (int i = 1; i < RP; ++i) {
-        cx<T> w = tw[(uint32_t)(i * k * step)];
+        // twiddle index i k step < L; byte offset k * (i step size), both
+        // factors below 2^24 (one full-rate 24-bit multiply)
+        cx<T> w = buf_ld<T>(twr, __umul24((uint32_t)k, (uint32_t)(i * step * sizeof(cx<T>))), 0u);
         if (D > 0) w.y = -w.y;
         u[i] = cmul(u[i], w);
       }

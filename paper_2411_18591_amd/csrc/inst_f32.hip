@@ -1,4 +1,6 @@
 // Propagation kernels instantiated for complex64 fields.
+#include <algorithm>
+
 #include "launch_impl.hpp"
 
 namespace toprop {
@@ -18,6 +20,8 @@ int col_tile_width(int ly, bool is_double, int variant) {
       tc = is_double ? ColCfg<double, L, 1>::TC : ColCfg<float, L, 1>::TC;
     else if (variant == 2)
       tc = is_double ? ColCfg<double, L, 2>::TC : ColCfg<float, L, 2>::TC;
+    else if (variant == 3)
+      tc = is_double ? ColCfg<double, L, 3>::TC : ColCfg<float, L, 3>::TC;
     else
       tc = is_double ? ColCfg<double, L, 0>::TC : ColCfg<float, L, 0>::TC;
     return hipSuccess;
@@ -51,6 +55,27 @@ int row_rows_per_block(int lx, bool is_double, bool heavy) {
   };
   if (dispatch_len(lx, q) != hipSuccess) return 1;
   return g;
+}
+
+int row_blocks_per_cu(int lx, bool is_double, bool heavy) {
+  int n = 1;
+  auto q = [&](auto Lc) -> hipError_t {
+    auto per = [&](auto cfg) {
+      using C = decltype(cfg);
+      using T = typename C::Real;
+      const int by_lds = 163840 / row_lds_bytes<T, C::Len, C::R, C::G, true>();
+      const int by_threads = 2048 / C::threads;
+      n = std::max(1, std::min(by_lds, by_threads));
+    };
+    constexpr int L = decltype(Lc)::value;
+    if (is_double)
+      heavy ? per(RowCfg<double, L, true>()) : per(RowCfg<double, L>());
+    else
+      heavy ? per(RowCfg<float, L, true>()) : per(RowCfg<float, L>());
+    return hipSuccess;
+  };
+  if (dispatch_len(lx, q) != hipSuccess) return 1;
+  return n;
 }
 }  // namespace toprop
 

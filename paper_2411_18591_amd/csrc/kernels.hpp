@@ -305,33 +305,25 @@ __device__ __forceinline__ void fft_wg(cx<T>* v, int j, cx<T>* lds, const cx<T>*
     constexpr int NB = R / RP;
     stockham_butterflies<T, L, R, RP, NS, D, HALF_IN && P == 0>(v, j, tw);
     if constexpr (P + 1 < S::npass) {
-      // The padding is periodic (period 128 positions for rows, 16 for
-      // column tiles), so lds_pos(p + k*step) = lds_pos(p) + k*lds_pos(step)
-      // whenever step is a multiple of the period: the per-element offsets
-      // then become compile-time immediates on a per-thread base.
-      constexpr int PER = STRIDE == 1 ? 128 : 16;
+      // The padding adds floor(p/32)*2 + floor(p/128) (rows) or floor(p/16)
+      // (column tiles) slots.  Output i of a butterfly sits at p0 + i NS with
+      // p0 = Q + r, Q a multiple of NS RP and r < NS, and no carry out of the
+      // low bits can occur in that sum, so lds_pos(p0 + i NS) =
+      // lds_pos(p0) + lds_pos(i NS); likewise lds_pos(j + m TT) =
+      // lds_pos(j) + lds_pos(m TT) for j < TT.  Every element offset is
+      // therefore a compile-time immediate on one per-thread base.
       __syncthreads();
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
         const int p0 = stockham_out_pos<L, R, RP, NS>(j, t, 0);
         const int b0 = lds_pos<STRIDE>(p0) * STRIDE;
 #pragma unroll
-        for (int i = 0; i < RP; ++i) {
-          if constexpr (NS % PER == 0)
-            lds[b0 + i * lds_pos<STRIDE>(NS) * STRIDE] = v[t + i * NB];
-          else
-            lds[lds_pos<STRIDE>(p0 + i * NS) * STRIDE] = v[t + i * NB];
-        }
+        for (int i = 0; i < RP; ++i) lds[b0 + lds_pos<STRIDE>(i * NS) * STRIDE] = v[t + i * NB];
       }
       __syncthreads();
       const int r0 = lds_pos<STRIDE>(j) * STRIDE;
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        if constexpr (TT % PER == 0)
-          v[m] = lds[r0 + m * lds_pos<STRIDE>(TT) * STRIDE];
-        else
-          v[m] = lds[lds_pos<STRIDE>(j + m * TT) * STRIDE];
-      }
+      for (int m = 0; m < R; ++m) v[m] = lds[r0 + lds_pos<STRIDE>(m * TT) * STRIDE];
     }
   });
 }
@@ -401,22 +393,99 @@ struct RowInvArgs {
   double* lens_partial;   // per row partial sums of dL/df
 };
 
+// Waves per SIMD that fit on a CU given a workgroup's LDS footprint (160 KiB
+// of LDS per CU, 4 SIMDs): the register budget the compiler may assume.
+constexpr int waves_per_simd(int threads, int lds_bytes) {
+  const int wg = lds_bytes > 0 ? 163840 / lds_bytes : 8;
+  const int w = (wg < 1 ? 1 : wg) * threads / 256;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
+// ---------------------------------------------------------------------------
+// Addressing shared by the row passes.
+//
+// A row pass owns rows of the padded grid: thread j of a row holds the
+// elements x = j + m TT, m < R.  Threads of one row are whole waves when
+// TT >= 64, so the row index is then wave-uniform (readfirstlane), and so is
+// every branch on it.  Field rows ([..][ny][nx], x fastest) put element m at
+// lane offset (y nx + j) plus a uniform m TT; scratch rows in the
+// column-tile layout [LX/tm][ny][tm] put element kx = j + m TT at
+// ((kx / tm) ny + y) tm + kx % tm, which with TT a multiple of tm (TT >= 16
+// >= tm) is a lane offset plus a uniform m TT ny.  Both go to buffer
+// accesses whose uniform part sits in a scalar register.
+//
+// EX ("exact width"): the field fills exactly the registers that can hold
+// it (nx == RI TT, RI = R/2 on a half-padded row, else R), so the test
+// x < nx reduces to the compile-time m < RI.
+// ---------------------------------------------------------------------------
+// LDS bytes of a row-pass workgroup: G padded rows (+ a double per thread
+// for the reductions of the kernels that have them).
+template <typename T, int L, int R, int G, bool RED>
+constexpr int row_lds_bytes() {
+  return G * lds_len<1>(L) * (int)sizeof(cx<T>) + (RED ? G * (L / R) * 8 : 0);
+}
+
+// Occupancy the row passes ask the compiler to keep: the waves per SIMD
+// their LDS allows, at most four (128 registers).  Three-component passes,
+// which hold three rows of registers, are left to the compiler.
+constexpr int row_min_waves(int nc, int w) { return nc == 1 ? (w < 4 ? w : 4) : 1; }
+
+template <int TT>
+__device__ __forceinline__ int row_group() {
+  const int g = (int)threadIdx.x / TT;
+  if constexpr (TT >= 64) return __builtin_amdgcn_readfirstlane(g);
+  return g;
+}
+
+template <typename T, int TT>
+struct TileRow {
+  uint32_t vo;  // lane part (bytes)
+  int j, y, ny, shift;
+  __device__ __forceinline__ TileRow(int j_, int y_, int ny_, int shift_) : j(j_), y(y_), ny(ny_), shift(shift_) {
+    if constexpr (TT >= 16)
+      vo = (uint32_t)(((((j >> shift) * ny + y) << shift) + (j & ((1 << shift) - 1))) * (int)sizeof(cx<T>));
+    else
+      vo = 0;
+  }
+  // lane and uniform byte offsets of register m
+  __device__ __forceinline__ uint32_t v(int m) const {
+    if constexpr (TT >= 16) {
+      return vo;
+    } else {
+      const int kx = j + m * TT;
+      return (uint32_t)(((((kx >> shift) * ny + y) << shift) + (kx & ((1 << shift) - 1))) * (int)sizeof(cx<T>));
+    }
+  }
+  __device__ __forceinline__ uint32_t s(int m) const {
+    if constexpr (TT >= 16)
+      return (uint32_t)m * (uint32_t)(TT * ny) * (uint32_t)sizeof(cx<T>);
+    else
+      return 0u;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // row_fwd
 // ---------------------------------------------------------------------------
-template <typename T, int L, int R, int G, bool HALF, int NC>
-__global__ void __launch_bounds__(G * (L / R)) row_fwd_kernel(RowFwdArgs<T> a) {
+template <typename T, int L, int R, int G, bool HALF, int NC, bool EX>
+__global__ void __launch_bounds__(G * (L / R))
+    __attribute__((amdgpu_waves_per_eu(row_min_waves(NC, waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, false>())),
+                                       waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, false>()))))
+    row_fwd_kernel(RowFwdArgs<T> a) {
   constexpr int TT = L / R;
   __shared__ cx<T> lds[G * lds_len<1>(L)];
   constexpr int RI = HALF ? R / 2 : R;  // registers that can hold a sample x < nx
-  const int g = threadIdx.x / TT;
+  const int g = row_group<TT>();
   const int j = threadIdx.x % TT;
   const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
   const bool rowok = y < a.ny;
   const int ny = a.ny, nx = a.nx;
   const int f0 = blockIdx.y * a.fpb;
   const int f1 = min(f0 + a.fpb, a.nfields);
-  const int tcm = (1 << a.tc_shift) - 1;
+  const TileRow<T, TT> tr(j, y, ny, a.tc_shift);
+  const uint32_t row_vo = (uint32_t)((y * nx + j) * (int)sizeof(cx<T>));
+  const uint32_t in_bytes = (uint32_t)(((int64_t)(NC - 1) * a.comp_stride + (int64_t)ny * nx) * sizeof(cx<T>));
+  const uint32_t s_bytes = (uint32_t)(a.s_stride * sizeof(cx<T>));
 
   // Scalar modulation of this thread's pixels, shared by every field.
   const bool scalar_el = (a.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) != 0 || a.coh_m;
@@ -426,55 +495,53 @@ __global__ void __launch_bounds__(G * (L / R)) row_fwd_kernel(RowFwdArgs<T> a) {
     const int x = j + m * TT;
     mod[m] = {T(1), T(0)};
     if (a.coh_m) {
-      if (rowok && x < nx) mod[m] = cconj(a.coh_m[y * nx + x]);
-    } else if (scalar_el && rowok && x < nx) {
+      if (rowok && (EX || x < nx)) mod[m] = cconj(a.coh_m[y * nx + x]);
+    } else if (scalar_el && rowok && (EX || x < nx)) {
       mod[m] = scalar_modulation(a.el, ny, nx, y, x);
     }
     // one pixel at a time: interleaving the sincos chains only costs registers
     __builtin_amdgcn_sched_barrier(0);
   }
 
-  // Loads of one field's row samples (zero outside the field).
-  auto load_row = [&](int f, int jv, int yv, cx<T> (&dst)[NC][RI]) {
-    const cx<T>* in_f = a.in + (int64_t)f * a.in_stride;
+  // Loads of one field's row samples (zero outside the field).  Rows past
+  // the field (ny not a multiple of G) still run the transforms, whose
+  // barriers every wave must reach, on zeros, and store nothing.
+  auto load_row = [&](int f, cx<T> (&dst)[NC][RI]) {
+    const rsrc_t in_r = buf_rsrc(a.in + (int64_t)f * a.in_stride, in_bytes);
 #pragma unroll
     for (int m = 0; m < RI; ++m) {
-      const int xv = jv + m * TT;
-      const bool inside = rowok && xv < nx;
+      const bool inside = rowok && (EX || j + m * TT < nx);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         cx<T> val = {T(0), T(0)};
-        if (inside) val = in_f[(uint32_t)(c * a.comp_stride + yv * nx + xv)];
+        if (inside)
+          val = buf_ld<T>(in_r, row_vo,
+                          (uint32_t)((c * a.comp_stride + m * TT) * (int64_t)sizeof(cx<T>)));
         dst[c][m] = val;
       }
     }
   };
   // Software pipeline over the block's fields: the next field's loads are
   // issued before the current field's transform, so their latency overlaps
-  // the FFT passes (measured faster than loading at the top of each
-  // iteration at both 8 and 16 points per thread).
-  constexpr bool kPipe = true;
+  // the FFT passes.
   cx<T> cur[NC][RI];
-  if (kPipe && f0 < f1) load_row(f0, j, y, cur);
+  if (f0 < f1) load_row(f0, cur);
 
 #pragma unroll 1
   for (int f = f0; f < f1; ++f) {
-    // Opaque copies of the thread's indices: the addresses below are then
-    // recomputed per field instead of being hoisted and kept live.
-    int jv = j, yv = y;
-    asm volatile("" : "+v"(jv), "+v"(yv));
-    cx<T> nxt[NC][kPipe ? RI : 1];
-    if constexpr (kPipe) {
-      if (f + 1 < f1) {
-        load_row(f + 1, jv, yv, nxt);
-      } else {
-#pragma unroll
-        for (int m = 0; m < RI; ++m)
-#pragma unroll
-          for (int c = 0; c < NC; ++c) nxt[c][m] = {T(0), T(0)};
-      }
+    // Opaque copy of the thread index for the transforms: their twiddle
+    // addresses are recomputed per field instead of being hoisted and kept
+    // live across the loop.
+    int jv = j;
+    asm volatile("" : "+v"(jv));
+    cx<T> nxt[NC][RI];
+    if (f + 1 < f1) {
+      load_row(f + 1, nxt);
     } else {
-      load_row(f, jv, yv, cur);
+#pragma unroll
+      for (int m = 0; m < RI; ++m)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) nxt[c][m] = {T(0), T(0)};
     }
     cx<T> v[NC][R];
     const cx<T> fmod = a.coh_m ? a.coh_m[a.f_off + f] : cx<T>{T(1), T(0)};
@@ -488,9 +555,9 @@ __global__ void __launch_bounds__(G * (L / R)) row_fwd_kernel(RowFwdArgs<T> a) {
       }
       if (m < RI) {
         if constexpr (NC == 3) {
-          if ((a.el.flags & (EL_JONES | EL_JONES_MAP)) && rowok && jv + m * TT < nx) {
+          if ((a.el.flags & (EL_JONES | EL_JONES_MAP)) && (EX || j + m * TT < nx)) {
             cx<T> w[3] = {v[0][m], v[1][m], v[2][m]};
-            apply_jones(a.el, (int64_t)yv * nx + (jv + m * TT), w);
+            apply_jones(a.el, (int64_t)y * nx + (j + m * TT), w);
 #pragma unroll
             for (int r = 0; r < 3; ++r) v[r][m] = w[r];
           }
@@ -505,37 +572,30 @@ __global__ void __launch_bounds__(G * (L / R)) row_fwd_kernel(RowFwdArgs<T> a) {
     for (int c = 0; c < NC; ++c) {
       fft_wg<T, L, R, -1, HALF, 1>(v[c], jv, lds + g * lds_len<1>(L), a.tw);
       if (rowok) {
-        cx<T>* dst = a.scratch + (int64_t)(f * NC + c) * a.s_stride;
+        const rsrc_t sr = buf_rsrc(a.scratch + (int64_t)(f * NC + c) * a.s_stride, s_bytes);
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-          const int kx = jv + m * TT;
-          dst[(uint32_t)((((kx >> a.tc_shift) * ny + yv) << a.tc_shift) + (kx & tcm))] = v[c][m];
-        }
+        for (int m = 0; m < R; ++m) buf_st(sr, tr.v(m), tr.s(m), v[c][m]);
       }
     }
-    if constexpr (kPipe) {
 #pragma unroll
-      for (int m = 0; m < RI; ++m)
+    for (int m = 0; m < RI; ++m)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) cur[c][m] = nxt[c][m];
-    }
+      for (int c = 0; c < NC; ++c) cur[c][m] = nxt[c][m];
   }
 }
 
 // ---------------------------------------------------------------------------
 // col: forward FFT along y, transfer function, inverse FFT, crop rows.
 // ---------------------------------------------------------------------------
-// Waves per SIMD that fit on a CU given a workgroup's LDS footprint (160 KiB
-// of LDS per CU, 4 SIMDs): the register budget the compiler may assume.
-constexpr int waves_per_simd(int threads, int lds_bytes) {
-  const int wg = lds_bytes > 0 ? 163840 / lds_bytes : 8;
-  const int w = (wg < 1 ? 1 : wg) * threads / 256;
-  return w < 1 ? 1 : (w > 8 ? 8 : w);
-}
-
-template <typename T, int L, int R, int TC, bool HALF>
+// EX: the field's rows fill exactly the registers that can hold them
+// (ny == R/2 TT on a half-padded column, ny == L otherwise), so y < ny is the
+// compile-time m < R/2 (or always true).
+// PF: the next field's column segment is loaded while the current one is
+// transformed (software pipeline over the block's fields).
+template <typename T, int L, int R, int TC, bool HALF, bool EX, bool PF>
 __global__ void __launch_bounds__(TC * (L / R))
-    __attribute__((amdgpu_waves_per_eu(1, waves_per_simd(TC * (L / R), lds_len<TC>(L) * TC * (int)sizeof(cx<T>)))))
+    __attribute__((amdgpu_waves_per_eu(PF ? waves_per_simd(TC * (L / R), lds_len<TC>(L) * TC * (int)sizeof(cx<T>)) : 1,
+                                       waves_per_simd(TC * (L / R), lds_len<TC>(L) * TC * (int)sizeof(cx<T>)))))
     col_kernel(ColArgs<T> a) {
   constexpr int TT = L / R;
   __shared__ cx<T> lds[lds_len<TC>(L) * TC];
@@ -586,20 +646,44 @@ __global__ void __launch_bounds__(TC * (L / R))
     for (int m = 0; m < R; ++m) hv[m] = transfer_at<T>(kx, j + m * TT, a.lx, L, a.h);
   }
 
+  // Element (y, c) of the block's columns: lane part (j tm + c), uniform
+  // part (tile ny tm + h cpb + m TT tm), in bytes from the field's scratch.
+  const uint32_t s_bytes = (uint32_t)(a.s_stride * sizeof(cx<T>));
+  const uint32_t col_vo = (uint32_t)((j * tm + c) * (int)sizeof(cx<T>));
+  const uint32_t col_so = (uint32_t)(((int64_t)tile * ny * tm + h * cpb) * sizeof(cx<T>));
+  const uint32_t m_so = (uint32_t)(TT * tm * (int)sizeof(cx<T>));
+  auto kept = [&](int m) { return active && (EX ? (!HALF || m < R / 2) : ((!HALF || m < R / 2) && j + m * TT < ny)); };
+  constexpr int RL = HALF ? R / 2 : R;  // registers that can hold a row y < ny
+  auto load_col = [&](int f, cx<T> (&dst)[RL]) {
+    const rsrc_t fr = buf_rsrc(a.scratch + (int64_t)f * a.s_stride, s_bytes);
+#pragma unroll
+    for (int m = 0; m < RL; ++m) {
+      cx<T> val = {T(0), T(0)};
+      if (kept(m)) val = buf_ld<T>(fr, col_vo, col_so + (uint32_t)m * m_so);
+      dst[m] = val;
+    }
+  };
+  cx<T> pre[PF ? RL : 1];
+  if constexpr (PF) {
+    if (f_begin < f_end) load_col(f_begin, pre);
+  }
   for (int f = f_begin; f < f_end; ++f) {
     // Opaque per-field copy of j: the twiddle loads (addresses depend on j
     // only) are not hoisted out of the field loop, which would hold every
     // twiddle of both transforms in registers.
     int j1 = j;
     asm volatile("" : "+v"(j1));
-    cx<T>* base = a.scratch + (int64_t)f * a.s_stride + (int64_t)tile * ny * tm + h * cpb;
+    const rsrc_t fr = buf_rsrc(a.scratch + (int64_t)f * a.s_stride, s_bytes);
     cx<T> v[R];
+    if constexpr (PF) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-      const int y = j + m * TT;
-      cx<T> val = {T(0), T(0)};
-      if (active && y < ny && (!HALF || m < R / 2)) val = base[(uint32_t)(y * tm + c)];
-      v[m] = val;
+      for (int m = 0; m < R; ++m) v[m] = m < RL ? pre[m < RL ? m : 0] : cx<T>{T(0), T(0)};
+      if (f + 1 < f_end) load_col(f + 1, pre);
+    } else {
+      cx<T> cur[RL];
+      load_col(f, cur);
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[m] = m < RL ? cur[m < RL ? m : 0] : cx<T>{T(0), T(0)};
     }
     fft_wg<T, L, R, -1, HALF, TC>(v, j1, lds + c, a.tw);
 #pragma unroll
@@ -610,13 +694,9 @@ __global__ void __launch_bounds__(TC * (L / R))
     int j2 = j;
     asm volatile("" : "+v"(j2));
     fft_wg<T, L, R, +1, false, TC>(v, j2, lds + c, a.tw);
-    if (active) {
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const int y = j + m * TT;
-        if ((!HALF || m < R / 2) && y < ny) base[(uint32_t)(y * tm + c)] = v[m];
-      }
-    }
+    for (int m = 0; m < R; ++m)
+      if (kept(m)) buf_st(fr, col_vo, col_so + (uint32_t)m * m_so, v[m]);
   }
 }
 
@@ -661,41 +741,53 @@ __device__ __forceinline__ double group_sum(double v, double* red) {
 //     Fields are looped inside the block so each pixel's gradient is summed
 //     by one thread in a fixed order.
 // ---------------------------------------------------------------------------
-template <typename T, int L, int R, int G, bool HALF, int NC, bool BWD>
-__global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
+template <typename T, int L, int R, int G, bool HALF, int NC, bool BWD, bool EX>
+__global__ void __launch_bounds__(G * (L / R))
+    __attribute__((amdgpu_waves_per_eu(row_min_waves(NC, waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, true>())),
+                                       waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, true>()))))
+    row_inv_kernel(RowInvArgs<T> a) {
   constexpr bool kBwd = BWD;
   constexpr int TT = L / R;
   constexpr int NT = G * TT;
   constexpr int RO = HALF ? R / 2 : R;  // output registers that can hold x < nx
+  constexpr uint32_t CB = sizeof(cx<T>), RB = sizeof(T);
   __shared__ cx<T> lds[G * lds_len<1>(L)];
   __shared__ double red[NT];
-  const int g = threadIdx.x / TT;
+  const int g = row_group<TT>();
   const int j = threadIdx.x % TT;
   const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
   const int ny = a.ny, nx = a.nx;
   const bool rowok = y < ny;
-  const int tcm = (1 << a.tc_shift) - 1;
+  const TileRow<T, TT> tr(j, y, ny, a.tc_shift);
+  const uint32_t s_bytes = (uint32_t)(a.s_stride * CB);
+  const int64_t npix = (int64_t)ny * nx;
+  // field-layout arrays: element m of this thread at lane offset (y nx + j)
+  // plus the uniform m TT (+ c comp_stride)
+  const uint32_t pix0 = (uint32_t)(y * nx + j);
+  const uint32_t f_bytes = (uint32_t)(((int64_t)(NC - 1) * a.comp_stride + npix) * CB);
+  const rsrc_t ref_r = buf_rsrc(a.epi_ref, (uint32_t)(npix * RB));
+  auto xin = [&](int m) { return EX || j + m * TT < nx; };
   // Backward: one block owns its rows' parameter gradients, so it loops over
   // every field of the chunk; forward: `fpb` fields per block.
   const int f_begin = kBwd ? 0 : (int)blockIdx.y * a.fpb;
   const int f_end = kBwd ? a.nfields : min(f_begin + a.fpb, a.nfields);
-  // Gather of one field's scratch row (tile layout).
-  auto load_row = [&](int f, int jv, int yv, int c, cx<T> (&dst)[R]) {
-    const cx<T>* src = a.scratch + (int64_t)(f * NC + c) * a.s_stride;
+  // One field component's scratch row (tile layout); zeros past the field.
+  auto load_row = [&](int f, int c, cx<T> (&dst)[R]) {
+    const rsrc_t sr = buf_rsrc(a.scratch + (int64_t)(f * NC + c) * a.s_stride, s_bytes);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const int kx = jv + m * TT;
       cx<T> val = {T(0), T(0)};
-      if (rowok) val = src[(uint32_t)((((kx >> a.tc_shift) * ny + yv) << a.tc_shift) + (kx & tcm))];
+      if (rowok) val = buf_ld<T>(sr, tr.v(m), tr.s(m));
       dst[m] = val;
     }
   };
-  // Scalar rows with 8 points per thread are software-pipelined: the next
-  // field's row is loaded while the current one is transformed (with 16 the
-  // registers are worth more as occupancy).
-  constexpr bool kPipe = NC == 1 && R <= 8;
-  cx<T> pre[R];
-  if (kPipe && f_begin < f_end) load_row(f_begin, j, y, 0, pre);
+  // Scalar rows are software-pipelined: the next field's row is loaded
+  // while the current one is transformed.
+  constexpr bool kPipe = NC == 1;
+  cx<T> pre[kPipe ? R : 1];
+  if constexpr (kPipe) {
+    if (f_begin < f_end) load_row(f_begin, 0, pre);
+  }
 
   T gphase[RO];
   cx<T> modr[RO];  // backward: scalar modulation of this thread's pixels (all fields)
@@ -706,7 +798,7 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
     modr[m] = {T(1), T(0)};
     dpsi[m] = 0.0;
     const int x = j + m * TT;
-    if (kBwd && rowok && x < nx) {
+    if (kBwd && rowok && xin(m)) {
       if (a.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) modr[m] = scalar_modulation(a.el, ny, nx, y, x);
       if (a.el.flags & EL_LENS) dpsi[m] = lens_dphase_df(a.el, ny, nx, y, x, a.lens_f);
       __builtin_amdgcn_sched_barrier(0);
@@ -716,43 +808,44 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
 
 #pragma unroll 1
   for (int f = f_begin; f < f_end; ++f) {
-    const bool active = rowok;
-    // Opaque copies of the thread's indices (see row_fwd_kernel).
-    int jv = j, yv = y;
-    asm volatile("" : "+v"(jv), "+v"(yv));
+    // Opaque copy of the thread index for the transforms (twiddle addresses
+    // recomputed per field rather than hoisted).
+    int jv = j;
+    asm volatile("" : "+v"(jv));
+    const rsrc_t out_r = buf_rsrc(a.out + (int64_t)f * a.out_stride, a.out ? f_bytes : 0u);
+    const rsrc_t in_r = buf_rsrc(a.saved_in + (int64_t)f * a.out_stride, a.saved_in ? f_bytes : 0u);
     cx<T> v[NC][R];
     // backward, scalar rows: this field's layer input, loaded before the
     // transform so its latency overlaps it
     cx<T> uin[kBwd && kPipe ? RO : 1];
     if constexpr (kBwd && kPipe) {
-      const bool want = (a.el.flags & (EL_PHASE | EL_LENS)) && a.saved_in;
+      const bool want = (a.el.flags & (EL_PHASE | EL_LENS)) && a.saved_in && rowok;
 #pragma unroll
       for (int m = 0; m < RO; ++m) {
-        const int x = jv + m * TT;
         uin[m] = {T(0), T(0)};
-        if (want && rowok && x < nx) uin[m] = a.saved_in[(int64_t)f * a.out_stride + (uint32_t)(yv * nx + x)];
+        if (want && xin(m)) uin[m] = buf_ld<T>(in_r, pix0 * CB, (uint32_t)(m * TT) * CB);
       }
     }
     if constexpr (kPipe) {
 #pragma unroll
       for (int m = 0; m < R; ++m) v[0][m] = pre[m];
-      if (f + 1 < f_end) load_row(f + 1, jv, yv, 0, pre);
+      if (f + 1 < f_end) load_row(f + 1, 0, pre);
       fft_wg<T, L, R, +1, false, 1>(v[0], jv, lds + g * lds_len<1>(L), a.tw);
     } else {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        load_row(f, jv, yv, c, v[c]);
+        load_row(f, c, v[c]);
         fft_wg<T, L, R, +1, false, 1>(v[c], jv, lds + g * lds_len<1>(L), a.tw);
       }
     }
     double loss_acc = 0.0;
-    if (active) {
+    if (rowok) {
+      const rsrc_t grad_r = buf_rsrc(a.epi_grad + (int64_t)f * a.out_stride, a.epi_grad ? f_bytes : 0u);
+      const rsrc_t eo_r = buf_rsrc(a.epi_out + (int64_t)f * npix, a.epi_out ? (uint32_t)(npix * RB) : 0u);
 #pragma unroll
       for (int m = 0; m < RO; ++m) {
-        const int x = jv + m * TT;
-        if (x >= nx) continue;
-        const uint32_t pix = (uint32_t)(yv * nx + x);
-        const int64_t fbase = (int64_t)f * a.out_stride;
+        if (!xin(m)) continue;
+        const uint32_t so = (uint32_t)(m * TT);  // elements
 #pragma unroll
         for (int c = 0; c < NC; ++c) v[c][m] = cscale(v[c][m], a.scale);
         if constexpr (!kBwd) {
@@ -760,35 +853,37 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
             T I = T(0);
 #pragma unroll
             for (int c = 0; c < NC; ++c) I += v[c][m].x * v[c][m].x + v[c][m].y * v[c][m].y;
-            a.epi_out[(int64_t)f * ny * nx + pix] += a.epi_scale * I;
+            const T prev = buf_ldr(eo_r, pix0 * RB, so * RB, T());
+            buf_str(eo_r, pix0 * RB, so * RB, prev + a.epi_scale * I);
           }
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            const uint32_t o = (uint32_t)(c * a.comp_stride) + pix;
-            if (a.out) a.out[fbase + o] = v[c][m];
+            const uint32_t oc = (uint32_t)((c * a.comp_stride + so) * CB);
+            if (a.out) buf_st(out_r, pix0 * CB, oc, v[c][m]);
             if (a.epi == EPI_MSE) {
               const T I = v[c][m].x * v[c][m].x + v[c][m].y * v[c][m].y;
-              const T d = I - a.epi_ref[pix];
+              const T d = I - buf_ldr(ref_r, pix0 * RB, so * RB, T());
               loss_acc += (double)d * (double)d;
-              a.epi_grad[fbase + o] = cscale(v[c][m], T(4) * a.epi_scale * d);
+              buf_st(grad_r, pix0 * CB, oc, cscale(v[c][m], T(4) * a.epi_scale * d));
             } else if (a.epi == EPI_WEIGHTED) {
               const T I = v[c][m].x * v[c][m].x + v[c][m].y * v[c][m].y;
-              const T w = a.epi_ref[pix];
+              const T w = buf_ldr(ref_r, pix0 * RB, so * RB, T());
               loss_acc += (double)w * (double)I;
-              a.epi_grad[fbase + o] = cscale(v[c][m], T(2) * a.epi_scale * w);
+              buf_st(grad_r, pix0 * CB, oc, cscale(v[c][m], T(2) * a.epi_scale * w));
             }
           }
         } else {
           // g_mod is v; the modulated forward field is M u_in.
           const cx<T> mod = modr[m];
           const uint32_t fl = a.el.flags;
+          const uint32_t pix = pix0 + so;
           if ((fl & (EL_PHASE | EL_LENS)) && a.saved_in) {
             cx<T> u[NC];
             if constexpr (kPipe) {
               u[0] = uin[m];
             } else {
 #pragma unroll
-              for (int c = 0; c < NC; ++c) u[c] = a.saved_in[fbase + (uint32_t)(c * a.comp_stride) + pix];
+              for (int c = 0; c < NC; ++c) u[c] = buf_ld<T>(in_r, pix0 * CB, (uint32_t)((c * a.comp_stride + so) * CB));
             }
             if constexpr (NC == 3) {
               if (fl & (EL_JONES | EL_JONES_MAP)) apply_jones(a.el, (int64_t)pix, u);
@@ -810,14 +905,14 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
               if (fl & (EL_JONES | EL_JONES_MAP)) apply_jones_adjoint(a.el, (int64_t)pix, gi);  // J^H g
             }
 #pragma unroll
-            for (int c = 0; c < NC; ++c) a.out[fbase + (uint32_t)(c * a.comp_stride) + pix] = gi[c];
+            for (int c = 0; c < NC; ++c) buf_st(out_r, pix0 * CB, (uint32_t)((c * a.comp_stride + so) * CB), gi[c]);
           }
         }
       }
     }
     if (!kBwd && (a.epi == EPI_MSE || a.epi == EPI_WEIGHTED)) {
       const double s = group_sum<TT, G>(loss_acc, red);
-      if (active && j == 0) a.row_partial[(int64_t)f * ny + y] = s;
+      if (rowok && j == 0) a.row_partial[(int64_t)f * ny + y] = s;
     }
   }
   if constexpr (kBwd) {
@@ -825,7 +920,7 @@ __global__ void __launch_bounds__(G * (L / R)) row_inv_kernel(RowInvArgs<T> a) {
 #pragma unroll
       for (int m = 0; m < RO; ++m) {
         const int x = j + m * TT;
-        if (x < nx) a.grad_phase[(int64_t)y * nx + x] += gphase[m];
+        if (xin(m)) a.grad_phase[(int64_t)y * nx + x] += gphase[m];
       }
     }
     if ((a.el.flags & EL_LENS) && a.lens_partial) {
@@ -857,19 +952,27 @@ struct RowMidArgs {
   const cx<T>* tw;
 };
 
-template <typename T, int L, int R, int G, bool HALF>
-__global__ void __launch_bounds__(G * (L / R)) row_mid_kernel(RowMidArgs<T> a) {
+template <typename T, int L, int R, int G, bool HALF, bool EX>
+__global__ void __launch_bounds__(G * (L / R))
+    __attribute__((amdgpu_waves_per_eu(row_min_waves(1, waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, false>())),
+                                       waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, false>()))))
+    row_mid_kernel(RowMidArgs<T> a) {
   constexpr int TT = L / R;
   constexpr int RO = HALF ? R / 2 : R;  // registers that can hold x < nx
+  constexpr uint32_t CB = sizeof(cx<T>);
   __shared__ cx<T> lds[G * lds_len<1>(L)];
-  const int g = threadIdx.x / TT;
+  const int g = row_group<TT>();
   const int j = threadIdx.x % TT;
   const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
   const int ny = a.ny, nx = a.nx;
   const bool rowok = y < ny;
-  const int tcm = (1 << a.tc_shift) - 1;
   const int f_begin = (int)blockIdx.y * a.fpb;
   const int f_end = min(f_begin + a.fpb, a.nfields);
+  const TileRow<T, TT> tr(j, y, ny, a.tc_shift);
+  const uint32_t s_bytes = (uint32_t)(a.s_stride * CB);
+  const uint32_t o_bytes = (uint32_t)((int64_t)ny * nx * CB);
+  const uint32_t pix0 = (uint32_t)(y * nx + j);
+  auto xin = [&](int m) { return EX || j + m * TT < nx; };
 
   const bool scalar_el = (a.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) != 0;
   cx<T> mod[RO];
@@ -877,48 +980,37 @@ __global__ void __launch_bounds__(G * (L / R)) row_mid_kernel(RowMidArgs<T> a) {
   for (int m = 0; m < RO; ++m) {
     const int x = j + m * TT;
     mod[m] = {T(1), T(0)};
-    if (scalar_el && rowok && x < nx) mod[m] = scalar_modulation(a.el, ny, nx, y, x);
+    if (scalar_el && rowok && xin(m)) mod[m] = scalar_modulation(a.el, ny, nx, y, x);
     __builtin_amdgcn_sched_barrier(0);
   }
-  auto load_row = [&](int f, int jv, int yv, cx<T> (&dst)[R]) {
-    const cx<T>* src = a.scratch + (int64_t)f * a.s_stride;
+  auto load_row = [&](int f, cx<T> (&dst)[R]) {
+    const rsrc_t sr = buf_rsrc(a.scratch + (int64_t)f * a.s_stride, s_bytes);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const int kx = jv + m * TT;
       cx<T> val = {T(0), T(0)};
-      if (rowok) val = src[(uint32_t)((((kx >> a.tc_shift) * ny + yv) << a.tc_shift) + (kx & tcm))];
+      if (rowok) val = buf_ld<T>(sr, tr.v(m), tr.s(m));
       dst[m] = val;
     }
   };
-  // With 8 points per thread the next field's row is loaded while the
-  // current one is transformed; with 16 the registers that costs are worth
-  // more as occupancy, and the row is loaded at the top of its iteration.
-  constexpr bool kPipe = R <= 8;
-  cx<T> pre[kPipe ? R : 1];
-  if constexpr (kPipe) {
-    if (f_begin < f_end) load_row(f_begin, j, y, pre);
-  }
+  // The next field's row is loaded while the current one is transformed.
+  cx<T> pre[R];
+  if (f_begin < f_end) load_row(f_begin, pre);
 
 #pragma unroll 1
   for (int f = f_begin; f < f_end; ++f) {
-    int jv = j, yv = y;
-    asm volatile("" : "+v"(jv), "+v"(yv));
+    int jv = j;
+    asm volatile("" : "+v"(jv));
     cx<T> v[R];
-    if constexpr (kPipe) {
 #pragma unroll
-      for (int m = 0; m < R; ++m) v[m] = pre[m];
-      if (f + 1 < f_end) load_row(f + 1, jv, yv, pre);
-    } else {
-      load_row(f, jv, yv, v);
-    }
+    for (int m = 0; m < R; ++m) v[m] = pre[m];
+    if (f + 1 < f_end) load_row(f + 1, pre);
     fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
-    cx<T>* out_f = a.out + (int64_t)f * a.out_stride;
+    const rsrc_t out_r = buf_rsrc(a.out + (int64_t)f * a.out_stride, o_bytes);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const int x = jv + m * TT;
-      if (m < RO && rowok && x < nx) {
+      if (m < RO && rowok && xin(m)) {
         v[m] = cscale(v[m], a.scale);
-        out_f[(uint32_t)(yv * nx + x)] = v[m];
+        buf_st(out_r, pix0 * CB, (uint32_t)(m * TT) * CB, v[m]);
         if (scalar_el) v[m] = cmul(mod[m], v[m]);
       } else {
         v[m] = {T(0), T(0)};
@@ -926,16 +1018,13 @@ __global__ void __launch_bounds__(G * (L / R)) row_mid_kernel(RowMidArgs<T> a) {
     }
     // fresh opaque index: the forward transform reloads its twiddles rather
     // than keeping the inverse transform's (same addresses) live
-    int jw = jv, yw = yv;
-    asm volatile("" : "+v"(jw), "+v"(yw));
+    int jw = jv;
+    asm volatile("" : "+v"(jw));
     fft_wg<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
     if (rowok) {
-      cx<T>* dst = a.scratch + (int64_t)f * a.s_stride;
+      const rsrc_t sr = buf_rsrc(a.scratch + (int64_t)f * a.s_stride, s_bytes);
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const int kx = jw + m * TT;
-        dst[(uint32_t)((((kx >> a.tc_shift) * ny + yw) << a.tc_shift) + (kx & tcm))] = v[m];
-      }
+      for (int m = 0; m < R; ++m) buf_st(sr, tr.v(m), tr.s(m), v[m]);
     }
   }
 }
@@ -969,25 +1058,29 @@ struct RowMidBwdArgs {
   const cx<T>* tw;
 };
 
-// Four waves per SIMD are requested for the half-padded case (a few
-// spilled dwords are cheaper than a fourth of the occupancy); the unpadded
-// case, with more live registers, is left to the compiler.
-template <typename T, int L, int R, int G, bool HALF>
-__global__ void __launch_bounds__(G * (L / R)) __attribute__((amdgpu_waves_per_eu(HALF ? 4 : 1, 8)))
+template <typename T, int L, int R, int G, bool HALF, bool EX>
+__global__ void __launch_bounds__(G * (L / R))
+    __attribute__((amdgpu_waves_per_eu(row_min_waves(1, waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, true>())),
+                                       waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, true>()))))
     row_mid_bwd_kernel(RowMidBwdArgs<T> a) {
   constexpr int TT = L / R;
   constexpr int NT = G * TT;
   constexpr int RO = HALF ? R / 2 : R;
+  constexpr uint32_t CB = sizeof(cx<T>);
   __shared__ cx<T> lds[G * lds_len<1>(L)];
   __shared__ double red[NT];
-  const int g = threadIdx.x / TT;
+  const int g = row_group<TT>();
   const int j = threadIdx.x % TT;
   const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
   const int ny = a.ny, nx = a.nx;
   const bool rowok = y < ny;
-  const int tcm = (1 << a.tc_shift) - 1;
   const uint32_t fl = a.el.flags;
   const bool want_param = (fl & (EL_PHASE | EL_LENS)) && a.saved_in;
+  const TileRow<T, TT> tr(j, y, ny, a.tc_shift);
+  const uint32_t s_bytes = (uint32_t)(a.s_stride * CB);
+  const uint32_t f_bytes = (uint32_t)((int64_t)ny * nx * CB);
+  const uint32_t pix0 = (uint32_t)(y * nx + j);
+  auto xin = [&](int m) { return EX || j + m * TT < nx; };
 
   T gphase[RO];
   cx<T> modr[RO];
@@ -996,63 +1089,60 @@ __global__ void __launch_bounds__(G * (L / R)) __attribute__((amdgpu_waves_per_e
     gphase[m] = T(0);
     modr[m] = {T(1), T(0)};
     const int x = j + m * TT;
-    if (rowok && x < nx) {
+    if (rowok && xin(m)) {
       if (fl & (EL_PHASE | EL_COMPLEX | EL_LENS)) modr[m] = scalar_modulation(a.el, ny, nx, y, x);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
   double lens_acc = 0.0;
-  auto load_row = [&](int f, int jv, int yv, cx<T> (&dst)[R]) {
-    const cx<T>* src = a.scratch + (int64_t)f * a.s_stride;
+  auto load_row = [&](int f, cx<T> (&dst)[R]) {
+    const rsrc_t sr = buf_rsrc(a.scratch + (int64_t)f * a.s_stride, s_bytes);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const int kx = jv + m * TT;
       cx<T> val = {T(0), T(0)};
-      if (rowok) val = src[(uint32_t)((((kx >> a.tc_shift) * ny + yv) << a.tc_shift) + (kx & tcm))];
+      if (rowok) val = buf_ld<T>(sr, tr.v(m), tr.s(m));
       dst[m] = val;
     }
   };
   const int f_begin = (int)blockIdx.y * a.fpb;
   const int f_end = min(f_begin + a.fpb, a.nfields);
+  // With 8 points per thread the next field's row is loaded while the
+  // current one is transformed; with 16 (and the layer input, modulation
+  // and gradient registers this pass holds) the row is loaded at the top of
+  // its iteration, which keeps the kernel within 128 registers.
   constexpr bool kPipe = R <= 8;
   cx<T> pre[kPipe ? R : 1];
   if constexpr (kPipe) {
-    if (f_begin < f_end) load_row(f_begin, j, y, pre);
+    if (f_begin < f_end) load_row(f_begin, pre);
   }
 
 #pragma unroll 1
   for (int f = f_begin; f < f_end; ++f) {
-    int jv = j, yv = y;
-    asm volatile("" : "+v"(jv), "+v"(yv));
+    int jv = j;
+    asm volatile("" : "+v"(jv));
     cx<T> v[R];
     if constexpr (kPipe) {
 #pragma unroll
       for (int m = 0; m < R; ++m) v[m] = pre[m];
-      if (f + 1 < f_end) load_row(f + 1, jv, yv, pre);
+      if (f + 1 < f_end) load_row(f + 1, pre);
     } else {
-      load_row(f, jv, yv, v);
+      load_row(f, v);
     }
-    // the layer input of this field's row; with 8 points per thread it is
-    // loaded before the transform so its latency overlaps it, with 16 after
-    // it (registers)
-    const int64_t fbase = (int64_t)f * a.stride;
+    // the layer input of this field's row, loaded before the transform so
+    // its latency overlaps it
+    const rsrc_t in_r = buf_rsrc(a.saved_in + (int64_t)f * a.stride, a.saved_in ? f_bytes : 0u);
+    const rsrc_t gi_r = buf_rsrc(a.grad_in + (int64_t)f * a.stride, a.grad_in ? f_bytes : 0u);
     cx<T> uin[RO];
-    auto load_in = [&]() {
 #pragma unroll
-      for (int m = 0; m < RO; ++m) {
-        const int x = jv + m * TT;
-        uin[m] = {T(0), T(0)};
-        if (want_param && rowok && x < nx) uin[m] = a.saved_in[fbase + (uint32_t)(yv * nx + x)];
-      }
-    };
-    if constexpr (kPipe) load_in();
+    for (int m = 0; m < RO; ++m) {
+      uin[m] = {T(0), T(0)};
+      if (want_param && rowok && xin(m)) uin[m] = buf_ld<T>(in_r, pix0 * CB, (uint32_t)(m * TT) * CB);
+    }
     fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
-    if constexpr (!kPipe) load_in();
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const int x = jv + m * TT;
-      if (m < RO && rowok && x < nx) {
-        const uint32_t pix = (uint32_t)(yv * nx + x);
+      const int x = j + m * TT;
+      if (m < RO && rowok && xin(m)) {
         v[m] = cscale(v[m], a.scale);  // g_mod
         const cx<T> mod = modr[m];
         if (want_param) {
@@ -1060,33 +1150,30 @@ __global__ void __launch_bounds__(G * (L / R)) __attribute__((amdgpu_waves_per_e
           const T im = v[m].y * um.x - v[m].x * um.y;  // Im(g conj(M u))
           if (fl & EL_PHASE) gphase[m] += im;
           // d(lens phase)/df, formed where needed (lens layers are rare)
-          if (fl & EL_LENS) lens_acc += (double)im * lens_dphase_df(a.el, ny, nx, yv, x, a.lens_f);
+          if (fl & EL_LENS) lens_acc += (double)im * lens_dphase_df(a.el, ny, nx, y, x, a.lens_f);
         }
         v[m] = cmulc(v[m], mod);  // g_l = conj(M) g_mod
-        if (a.grad_in) a.grad_in[fbase + pix] = v[m];
+        if (a.grad_in) buf_st(gi_r, pix0 * CB, (uint32_t)(m * TT) * CB, v[m]);
       } else {
         v[m] = {T(0), T(0)};
       }
     }
     // fresh opaque index: the forward transform reloads its twiddles rather
     // than keeping the inverse transform's (same addresses) live
-    int jw = jv, yw = yv;
-    asm volatile("" : "+v"(jw), "+v"(yw));
+    int jw = jv;
+    asm volatile("" : "+v"(jw));
     fft_wg<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
     if (rowok) {
-      cx<T>* dst = a.scratch + (int64_t)f * a.s_stride;
+      const rsrc_t sr = buf_rsrc(a.scratch + (int64_t)f * a.s_stride, s_bytes);
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const int kx = jw + m * TT;
-        dst[(uint32_t)((((kx >> a.tc_shift) * ny + yw) << a.tc_shift) + (kx & tcm))] = v[m];
-      }
+      for (int m = 0; m < R; ++m) buf_st(sr, tr.v(m), tr.s(m), v[m]);
     }
   }
   if (rowok && (fl & EL_PHASE) && a.grad_phase && a.saved_in) {
 #pragma unroll
     for (int m = 0; m < RO; ++m) {
       const int x = j + m * TT;
-      if (x < nx) {
+      if (xin(m)) {
         if (a.gphase_part)
           a.gphase_part[((int64_t)blockIdx.y * ny + y) * nx + x] = gphase[m];
         else

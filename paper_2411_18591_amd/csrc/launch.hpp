@@ -16,6 +16,8 @@ constexpr int kMaxLen = 8192;
 // length 2048, where R = 16 would cost them occupancy; so does complex128.
 template <typename T, int L, bool Heavy = false>
 struct RowCfg {
+  using Real = T;
+  static constexpr int Len = L;
   static constexpr int R =
       L <= 16 ? L : (L <= 1024 ? 8 : ((L == 2048 && (Heavy || sizeof(T) == 8)) ? 8 : 16));
   static constexpr int TT = L / R;
@@ -26,13 +28,16 @@ struct RowCfg {
 // Column pass: R points per thread, TC columns per workgroup, sized so that
 // the LDS exchange buffer (L * TC complex values) stays within the variant's
 // budget: V = 0: 128 KiB, R = 16; V = 1: 64 KiB, R = 16 (two workgroups per
-// CU); V = 2: 64 KiB, R = 8.
-constexpr int kColVariants = 3;
+// CU); V = 2: 64 KiB, R = 8; V = 3: as V = 1, with the next field's column
+// segment loaded during the current field's transforms.
+constexpr int kColVariants = 4;
+constexpr bool col_prefetch(int V) { return V == 3; }
 template <typename T, int L, int V = 0>
 struct ColCfg {
   static constexpr int R = L <= 16 ? L : (L <= 256 ? 8 : (V == 2 ? 8 : 16));
   static constexpr int TT = L / R;
   static constexpr int lds_elems = (int)((V == 0 ? 131072 : 65536) / sizeof(cx<T>));
+  static constexpr bool PF = col_prefetch(V);
   static constexpr int tc0 = lds_elems / L > 16 ? 16 : lds_elems / L;
   static constexpr int tc1 = tc0 < 1 ? 1 : tc0;
   static constexpr int TC = tc1 * TT > 1024 ? 1024 / TT : tc1;
@@ -43,6 +48,8 @@ struct ColCfg {
 int col_tile_width(int ly, bool is_double, int variant);
 // Rows per workgroup of the row passes for a given row length.
 int row_rows_per_block(int lx, bool is_double, bool heavy);
+// Row-pass workgroups that fit on one CU at once (LDS and thread limits).
+int row_blocks_per_cu(int lx, bool is_double, bool heavy);
 
 template <typename T>
 struct Launch {

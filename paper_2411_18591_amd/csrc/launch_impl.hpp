@@ -24,27 +24,44 @@ static hipError_t dispatch_len(int L, F&& f) {
   }
 }
 
+// Calls f(std::bool_constant<EX>) with EX = `exact` where exact-width
+// kernels are instantiated (transforms of 256 points and more), else false.
+template <int L, typename F>
+static void dispatch_exact(bool exact, F&& f) {
+  if constexpr (L >= 256) {
+    if (exact) {
+      f(std::true_type());
+      return;
+    }
+  }
+  f(std::false_type());
+}
+
 template <typename T>
 hipError_t Launch<T>::row_fwd(int lx, bool half, int nc, int ny, int nfields, const RowFwdArgs<T>& a,
                               hipStream_t s) {
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
     const int fpb = a.fpb > 0 ? a.fpb : 1;
-    if (nc == 3) {
-      using C = RowCfg<T, L, true>;
-      dim3 grid((ny + C::G - 1) / C::G, (nfields + fpb - 1) / fpb);
-      if (half)
-        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, true, 3>), grid, dim3(C::threads), 0, s, a);
-      else
-        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, false, 3>), grid, dim3(C::threads), 0, s, a);
-    } else {
-      using C = RowCfg<T, L>;
-      dim3 grid((ny + C::G - 1) / C::G, (nfields + fpb - 1) / fpb);
-      if (half)
-        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, true, 1>), grid, dim3(C::threads), 0, s, a);
-      else
-        hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, false, 1>), grid, dim3(C::threads), 0, s, a);
-    }
+    const bool exact = a.nx == (half ? L / 2 : L);
+    dispatch_exact<L>(exact, [&](auto ex) {
+      constexpr bool EX = decltype(ex)::value;
+      if (nc == 3) {
+        using C = RowCfg<T, L, true>;
+        dim3 grid((ny + C::G - 1) / C::G, (nfields + fpb - 1) / fpb);
+        if (half)
+          hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, true, 3, EX>), grid, dim3(C::threads), 0, s, a);
+        else
+          hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, false, 3, EX>), grid, dim3(C::threads), 0, s, a);
+      } else {
+        using C = RowCfg<T, L>;
+        dim3 grid((ny + C::G - 1) / C::G, (nfields + fpb - 1) / fpb);
+        if (half)
+          hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, true, 1, EX>), grid, dim3(C::threads), 0, s, a);
+        else
+          hipLaunchKernelGGL((row_fwd_kernel<T, L, C::R, C::G, false, 1, EX>), grid, dim3(C::threads), 0, s, a);
+      }
+    });
     return hipGetLastError();
   });
 }
@@ -54,19 +71,25 @@ hipError_t Launch<T>::col(int ly, bool half, int ntiles, int nfields, int varian
                           const ColArgs<T>& a, hipStream_t s) {
   return dispatch_len(ly, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
+    const bool exact = a.ny == (half ? L / 2 : L);
     auto go = [&](auto vc) {
       using C = ColCfg<T, L, decltype(vc)::value>;
       dim3 grid(ntiles, (nfields + a.fpc - 1) / a.fpc);
       dim3 block(C::threads);
-      if (half)
-        hipLaunchKernelGGL((col_kernel<T, L, C::R, C::TC, true>), grid, block, 0, s, a);
-      else
-        hipLaunchKernelGGL((col_kernel<T, L, C::R, C::TC, false>), grid, block, 0, s, a);
+      dispatch_exact<L>(exact, [&](auto ex) {
+        constexpr bool EX = decltype(ex)::value;
+        if (half)
+          hipLaunchKernelGGL((col_kernel<T, L, C::R, C::TC, true, EX, C::PF>), grid, block, 0, s, a);
+        else
+          hipLaunchKernelGGL((col_kernel<T, L, C::R, C::TC, false, EX, C::PF>), grid, block, 0, s, a);
+      });
     };
     if (variant == 1)
       go(std::integral_constant<int, 1>());
     else if (variant == 2)
       go(std::integral_constant<int, 2>());
+    else if (variant == 3)
+      go(std::integral_constant<int, 3>());
     else
       go(std::integral_constant<int, 0>());
     return hipGetLastError();
@@ -81,10 +104,13 @@ hipError_t Launch<T>::row_mid(int lx, bool half, int ny, int nblocks_y, const Ro
     using C = RowCfg<T, L>;
     dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
     dim3 block(C::threads);
-    if (half)
-      hipLaunchKernelGGL((row_mid_kernel<T, L, C::R, C::G, true>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((row_mid_kernel<T, L, C::R, C::G, false>), grid, block, 0, s, a);
+    dispatch_exact<L>(a.nx == (half ? L / 2 : L), [&](auto ex) {
+      constexpr bool EX = decltype(ex)::value;
+      if (half)
+        hipLaunchKernelGGL((row_mid_kernel<T, L, C::R, C::G, true, EX>), grid, block, 0, s, a);
+      else
+        hipLaunchKernelGGL((row_mid_kernel<T, L, C::R, C::G, false, EX>), grid, block, 0, s, a);
+    });
     return hipGetLastError();
   });
 }
@@ -97,10 +123,13 @@ hipError_t Launch<T>::row_mid_bwd(int lx, bool half, int ny, int nblocks_y, cons
     using C = RowCfg<T, L>;
     dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
     dim3 block(C::threads);
-    if (half)
-      hipLaunchKernelGGL((row_mid_bwd_kernel<T, L, C::R, C::G, true>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((row_mid_bwd_kernel<T, L, C::R, C::G, false>), grid, block, 0, s, a);
+    dispatch_exact<L>(a.nx == (half ? L / 2 : L), [&](auto ex) {
+      constexpr bool EX = decltype(ex)::value;
+      if (half)
+        hipLaunchKernelGGL((row_mid_bwd_kernel<T, L, C::R, C::G, true, EX>), grid, block, 0, s, a);
+      else
+        hipLaunchKernelGGL((row_mid_bwd_kernel<T, L, C::R, C::G, false, EX>), grid, block, 0, s, a);
+    });
     return hipGetLastError();
   });
 }
@@ -110,23 +139,27 @@ hipError_t Launch<T>::row_inv(int lx, bool half, int nc, int ny, int nblocks_y,
                               const RowInvArgs<T>& a, hipStream_t s) {
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
+    const bool exact = a.nx == (half ? L / 2 : L);
     auto go = [&](auto bwd) {
       constexpr bool B = decltype(bwd)::value;
-      if (nc == 3) {
-        using C = RowCfg<T, L, true>;
-        dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
-        if (half)
-          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 3, B>), grid, dim3(C::threads), 0, s, a);
-        else
-          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 3, B>), grid, dim3(C::threads), 0, s, a);
-      } else {
-        using C = RowCfg<T, L, B>;
-        dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
-        if (half)
-          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 1, B>), grid, dim3(C::threads), 0, s, a);
-        else
-          hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 1, B>), grid, dim3(C::threads), 0, s, a);
-      }
+      dispatch_exact<L>(exact, [&](auto ex) {
+        constexpr bool EX = decltype(ex)::value;
+        if (nc == 3) {
+          using C = RowCfg<T, L, true>;
+          dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
+          if (half)
+            hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 3, B, EX>), grid, dim3(C::threads), 0, s, a);
+          else
+            hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 3, B, EX>), grid, dim3(C::threads), 0, s, a);
+        } else {
+          using C = RowCfg<T, L, B>;
+          dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
+          if (half)
+            hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 1, B, EX>), grid, dim3(C::threads), 0, s, a);
+          else
+            hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 1, B, EX>), grid, dim3(C::threads), 0, s, a);
+        }
+      });
     };
     if (a.backward)
       go(std::true_type());
