@@ -216,6 +216,32 @@ typedef struct to_grad {
  * workspaces and must be serialised by the caller.                           */
 to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * operation, arguments and results (to rounding) as to_propagate, with no
+ * allocation of any kind: every workspace (the padded intermediate of a
+ * chunk of fields, loss partial sums, transfer-function and twiddle tables)
+ * lives in one static device array of TO_NOALLOC_SCRATCH_BYTES that each
+ * GPU the library runs on holds from the library's first use on it until
+ * the process ends.  Differences from to_propagate:
+ *   - all work runs on `stream`, jobs in call order, one chunk of fields at
+ *     a time (no library streams, no fused layer chains);
+ *   - padded extents must be powers of two, direct integration (TO_DI, or
+ *     TO_AUTO resolving to it) needs the job's tf_table, and one field's
+ *     intermediate (ny x px complex values, times 3 for a Jones element or a
+ *     three-component intensity epilogue) must fit the array less its
+ *     tables (about 62 MiB: a 1024 x 1024 complex64 field padded to
+ *     2048 x 2048 needs 16 MiB); otherwise TO_E_UNSUPPORTED with the sizes
+ *     in to_last_error(), before anything is enqueued;
+ *   - launches are not timed by to_profile_begin.
+ * Every call on a GPU uses that GPU's one array: calls that overlap in time
+ * on one GPU (different streams, or host threads) race and must be
+ * serialised by the caller.  A call rebuilds the tables it reads and writes
+ * every intermediate before reading it, so nothing carries over between
+ * calls.  The call may itself be captured into a HIP graph.              */
+#define TO_NOALLOC_SCRATCH_BYTES (64u << 20)
+to_status to_propagate_noalloc(const to_job* jobs, int32_t njobs, to_dtype dtype, void* stream);
+
 /* Modulation only (Eq. (field_modulation) / the Jones product):
  * out = M in, or out = M^H in when adjoint != 0.  The propagation fields of
  * the job (py, px, method, z) are ignored.   */

@@ -41,6 +41,7 @@ TO_EPI_INTENSITY = 3
 
 EXPORTED = (
     "to_propagate",
+    "to_propagate_noalloc",
     "to_resample",
     "to_transfer_table",
     "to_resolve_method",
@@ -151,6 +152,8 @@ def lib() -> ctypes.CDLL:
         GP = ctypes.POINTER(Grad)
         L.to_propagate.argtypes = [JP, c_int, c_int, ctypes.c_void_p]
         L.to_propagate.restype = c_int
+        L.to_propagate_noalloc.argtypes = [JP, c_int, c_int, ctypes.c_void_p]
+        L.to_propagate_noalloc.restype = c_int
         L.to_modulate.argtypes = [JP, c_int, c_int, c_int, ctypes.c_void_p]
         L.to_modulate.restype = c_int
         L.to_propagate_backward.argtypes = [JP, GP, c_int, c_int, ctypes.c_void_p]
@@ -219,6 +222,10 @@ def propagate(jobs, dtype: int, stream: int, plain: bool = False) -> None:
     arr = jobs_array(jobs)
     fn = lib().to_propagate_plain if plain else lib().to_propagate
     check(fn(arr, len(jobs), dtype, ctypes.c_void_p(stream)))
+
+
+def propagate_noalloc(jobs, dtype: int, stream: int) -> None:
+    check(lib().to_propagate_noalloc(jobs_array(jobs), len(jobs), dtype, ctypes.c_void_p(stream)))
 
 
 def modulate(jobs, dtype: int, adjoint: bool, stream: int) -> None:

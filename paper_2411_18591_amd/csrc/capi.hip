@@ -18,6 +18,7 @@
 #include "accum.hpp"
 #include "coherence.hpp"
 #include "launch.hpp"
+#include "noalloc.hpp"
 #include "plain.hpp"
 #include "plan.hpp"
 #include "resample.hpp"
@@ -90,6 +91,9 @@ struct Lane {
   // separable transfer-function tables: ex, ey (complex64) and sx, sy
   // (float), kMaxLen entries each, one slot per layer of a chain
   void* tf = nullptr;
+  // fixed: scratch and partials are a caller-provided area that is never
+  // grown (the no-allocation entry point); jobs are chunked to fit it
+  bool fixed = false;
 };
 
 struct DeviceCtx {
@@ -170,6 +174,9 @@ to_status get_ctx(DeviceCtx** out) {
 // when it has to reallocate, since queued work may still use the old buffer).
 to_status ensure_scratch(Lane* c, size_t bytes) {
   if (c->scratch_bytes >= bytes) return TO_OK;
+  if (c->fixed)
+    return fail(TO_E_UNSUPPORTED, "the job needs %zu bytes of scratch, more than the %zu of the static area", bytes,
+                c->scratch_bytes);
   hipError_t e;
   if (c->scratch) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
@@ -222,6 +229,9 @@ to_status ensure_di(DeviceCtx* c, size_t bytes) {
 
 to_status ensure_partial(Lane* c, size_t count) {
   if (c->partial_count >= count) return TO_OK;
+  if (c->fixed)
+    return fail(TO_E_UNSUPPORTED, "the job needs %zu partial sums, more than the %zu of the static area", count,
+                c->partial_count);
   hipError_t e;
   if (c->partial) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
@@ -314,8 +324,12 @@ hipEvent_t prof_event() {
   return g_prof_pool[g_prof_pool_used++];
 }
 
+// Set while a call must not create HIP objects (the no-allocation entry
+// point): its launches are not timed.
+thread_local bool g_prof_suspended = false;
+
 int prof_start(const char* name, int L, bool dbl, hipStream_t s) {
-  if (!g_prof_on) return -1;
+  if (!g_prof_on || g_prof_suspended) return -1;
   std::lock_guard<std::mutex> lk(g_prof_mutex);
   ProfRec r;
   char buf[96];
@@ -862,6 +876,17 @@ to_status finish_backward_chunk(const to_job& j, const to_grad& gr, const Geomet
   return TO_OK;
 }
 
+// A fixed-area lane: fewer fields per chunk, so that a chunk's scratch and
+// loss partials fit the area (at least one field must).
+template <typename T>
+void fit_chunk(const to_job& j, const Lane* ln, Geometry* g) {
+  if (!ln->fixed) return;
+  const size_t per = (size_t)g->s_stride * g->nc_kernel * sizeof(cx<T>);
+  int64_t ch = std::min<int64_t>(g->chunk, (int64_t)(ln->scratch_bytes / per));
+  if (has_loss(j)) ch = std::min<int64_t>(ch, (int64_t)(ln->partial_count / (size_t)j.ny));
+  g->chunk = std::max<int64_t>(1, ch);
+}
+
 template <typename T>
 to_status run_forward(const to_job& j, DeviceCtx* c, Lane* ln, hipStream_t s, bool conj_h = false,
                       const cx<T>* coh_m = nullptr) {
@@ -869,6 +894,7 @@ to_status run_forward(const to_job& j, DeviceCtx* c, Lane* ln, hipStream_t s, bo
   Geometry g;
   to_status st = make_geometry<T>(j, coupled(j), &g);
   if (st != TO_OK) return st;
+  fit_chunk<T>(j, ln, &g);
   st = ensure_scratch(ln, (size_t)g.s_stride * g.nc_kernel * g.chunk * sizeof(cx<T>));
   if (st != TO_OK) return st;
   if (has_loss(j)) {
@@ -1984,6 +2010,76 @@ to_status plan_args(int32_t py, int32_t px, to_dtype dtype) {
 }
 
 }  // namespace
+
+namespace toprop {
+
+to_status set_error(to_status st, const char* msg) { return fail(st, "%s", msg); }
+
+to_status hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+
+// to_propagate's work with every workspace carved from `ws` and everything
+// on `stream`: no allocation, no library streams or events, no profiling.
+// `tw` holds the twiddle tables in the packed layout of build_twiddles
+// (complex64 tables first, then complex128).
+// Layout of a fixed area: one transfer-function table slot, the loss
+// partial sums, then the chunk scratch.
+constexpr size_t kFixedPartialBytes = (size_t)1 << 20;
+size_t fixed_scratch_bytes(size_t ws_bytes) {
+  const size_t head = kTableSlotBytes + kFixedPartialBytes;
+  return ws_bytes > head ? ws_bytes - head : 0;
+}
+
+to_status validate_forward(const to_job* jobs, int32_t njobs, to_dtype dtype, size_t ws_bytes) {
+  const size_t avail = fixed_scratch_bytes(ws_bytes);
+  for (int i = 0; i < njobs; ++i) {
+    to_status st = validate(jobs[i], i, dtype, MODE_FWD);
+    if (st != TO_OK) return st;
+    const to_job& j = jobs[i];
+    if (j.batch == 0) continue;
+    if (!pow2_grid(j))
+      return fail(TO_E_UNSUPPORTED, "job %d: padded grid %dx%d: the no-allocation entry point needs powers of two",
+                  i, j.py, j.px);
+    if (resolved_method(j) == TO_DI && !j.tf_table)
+      return fail(TO_E_UNSUPPORTED,
+                  "job %d: direct integration without a caller table (to_transfer_table) needs workspace", i);
+    const size_t per = (size_t)j.px * j.ny * (coupled(j) ? 3 : 1) *
+                       (dtype == TO_C64 ? sizeof(cx<float>) : sizeof(cx<double>));
+    if (per > avail)
+      return fail(TO_E_UNSUPPORTED,
+                  "job %d: one field needs %zu bytes of scratch (ny x px x coupled components), more than the %zu "
+                  "bytes of the static area",
+                  i, per, avail);
+    if (has_loss(j) && (size_t)j.ny * sizeof(double) > kFixedPartialBytes)
+      return fail(TO_E_UNSUPPORTED, "job %d: %d rows exceed the static partial sums", i, j.ny);
+  }
+  return TO_OK;
+}
+
+to_status propagate_fixed(const to_job* jobs, int32_t njobs, to_dtype dtype, hipStream_t s, const void* tw,
+                          void* ws, size_t ws_bytes) {
+  static_assert(kTwTotal == kTwPacked, "packed twiddle layout");
+  DeviceCtx c;
+  c.tw32 = (cx<float>*)tw;
+  c.tw64 = (cx<double>*)((char*)tw + sizeof(cx<float>) * kTwTotal);
+  Lane ln;
+  ln.fixed = true;
+  char* p = (char*)ws;
+  ln.tf = p;
+  p += kTableSlotBytes;
+  ln.partial = (double*)p;
+  ln.partial_count = kFixedPartialBytes / sizeof(double);
+  p += kFixedPartialBytes;
+  ln.scratch = p;
+  ln.scratch_bytes = fixed_scratch_bytes(ws_bytes);
+  g_prof_suspended = true;
+  to_status st = TO_OK;
+  for (int i = 0; i < njobs && st == TO_OK; ++i)
+    st = dtype == TO_C64 ? run_forward<float>(jobs[i], &c, &ln, s) : run_forward<double>(jobs[i], &c, &ln, s);
+  g_prof_suspended = false;
+  return st;
+}
+
+}  // namespace toprop
 
 extern "C" {
 

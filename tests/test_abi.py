@@ -262,3 +262,23 @@ def test_next_smooth_padding():
         assert not any(smooth(k) for k in range(max(n, 3), m))
     o = tp.Optics(dy=1e-5, dx=1e-5, wavelength=7e-7, z=0.1, pad=2, round_pow2=False, round_smooth=True)
     assert o.padded_shape(1001, 1000) == (2016, 2000)
+
+
+@pytest.mark.parametrize("mutate,status,words", [
+    (lambda j: setattr(j, "ny", 0), "TO_E_INVAL", ">= 1"),            # the checks of to_propagate
+    (lambda j: (setattr(j, "nx", 20), setattr(j, "px", 48)), "TO_E_UNSUPPORTED", "powers of two"),
+    (lambda j: (setattr(j, "ny", 4096), setattr(j, "nx", 4096), setattr(j, "py", 8192), setattr(j, "px", 8192)),
+     "TO_E_UNSUPPORTED", "static area"),                               # 256 MiB for one field
+    (lambda j: setattr(j, "method", 2), "TO_E_UNSUPPORTED", "direct integration"),  # DI without a table
+])
+def test_noalloc_rejects_before_any_gpu_work(capi, mutate, status, words):
+    """The entry point that allocates nothing rejects jobs beyond its static
+    area (and everything to_propagate rejects) on the host, before it looks
+    up the array or enqueues anything, so these run without a GPU."""
+    j = good_job(capi)
+    mutate(j)
+    rc = capi.lib().to_propagate_noalloc(capi.jobs_array([j]), 1, capi.TO_C64, None)
+    assert rc == getattr(capi, status)
+    assert words in capi.lib().to_last_error().decode()
+    assert capi.lib().to_propagate_noalloc(None, -1, capi.TO_C64, None) == capi.TO_E_INVAL
+    assert capi.lib().to_propagate_noalloc(None, 0, capi.TO_C64, None) == capi.TO_OK
