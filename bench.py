@@ -47,12 +47,16 @@ def parse():
     p.add_argument("--layers", type=int, default=5)
     p.add_argument("--method", choices=["asm", "di", "auto"], default="asm",
                    help="propagation method of the network's layers (the headline figure is asm)")
-    p.add_argument("--workload", choices=["diffnet", "poly4f", "resample", "anylength", "suite"],
+    p.add_argument("--workload", choices=["diffnet", "poly4f", "resample", "anylength", "suite", "uneven"],
                    default="diffnet")
     p.add_argument("--fwhm-nm", type=float, default=10.0, help="poly4f: spectral FWHM")
     p.add_argument("--cache-tables", action="store_true",
                    help="poly4f: build the DI tables once, before the timed region (reported separately)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--uneven-sizes", default="",
+                   help="uneven: keep only the jobs of these field sizes (comma-separated)")
+    p.add_argument("--uneven-count", type=int, default=0,
+                   help="uneven: keep at most this many of the selected jobs (0: all)")
     p.add_argument("--cpu-sample-fields", type=int, default=0,
                    help="fields in the CPU oracle sample (0 = one per host thread)")
     p.add_argument("--cpu-child", default="", help=argparse.SUPPRESS)
@@ -194,6 +198,15 @@ def main():
         return run_anylength(args)
     if args.workload == "suite":
         return run_suite(args)
+    if args.workload == "uneven":
+        import torch
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        res = run_uneven(args, dev)
+        print(json.dumps({"metric": "uneven batch: time per forward + adjoint step", "unit": "ms", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "data": "synthetic (seeded, as in workloads/)", "configs": {"uneven_c64": res}}))
+        return 0
     import workloads
     wl_def = workloads.DiffractiveNetWorkload(batch=args.batch, n=args.n, layers=args.layers)
     B, N, L = wl_def.batch, wl_def.n, wl_def.layers
@@ -770,7 +783,27 @@ def run_suite(args):
                                         "kernels": top}
     del G0
 
+    res["uneven_128_jobs_c64"] = run_uneven(args, dev)
+    print(json.dumps({"metric": "other workloads: time per step", "unit": "ms", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "data": "synthetic (seeded, as in workloads/)", "configs": res}))
+    return 0
+
+
+def run_uneven(args, dev):
+    """The uneven batch: 128 independent jobs (256^2 .. 4096^2, random
+    wavelength, distance and spacing, ASM, 2x padding, complex64), one
+    forward call and one backward call over all of them per step
+    (`--uneven-sizes` / `--uneven-count` select a subset)."""
+    import torch
+
+    import paper_2411_18591_amd as tp
+    import workloads
     jobs = workloads.uneven_jobs()
+    if args.uneven_sizes:
+        keep = {int(x) for x in args.uneven_sizes.split(",") if x}
+        jobs = [j for j in jobs if j.n in keep]
+    if args.uneven_count > 0:
+        jobs = jobs[:args.uneven_count]
     us, gs, ops = [], [], []
     gen = torch.Generator(device=dev).manual_seed(5301)
     for j in jobs:
@@ -785,12 +818,53 @@ def run_suite(args):
         tp.propagate_backward_jobs(gs, ops, grad_ins=gi)
     ms, top = _timed(uneven, args.steps, args.warmup)
     elems = sum(j.n * j.n for j in jobs)
-    res["uneven_128_jobs_c64"] = {"ms_per_step": round(ms, 3), "propagations_per_step": 2 * len(jobs),
-                                  "propagations_per_s": round(2 * len(jobs) / (ms / 1000.0), 1),
-                                  "field_elements_per_job_sum": elems, "kernels": top}
-    print(json.dumps({"metric": "other workloads: time per step", "unit": "ms", "n_gpus": 1, "steps": args.steps,
-                      "warmup": args.warmup, "data": "synthetic (seeded, as in workloads/)", "configs": res}))
-    return 0
+    res = {"jobs": len(jobs), "ms_per_step": round(ms, 3), "propagations_per_step": 2 * len(jobs),
+           "propagations_per_s": round(2 * len(jobs) / (ms / 1000.0), 1),
+           "field_elements_per_job_sum": elems, "kernels": top}
+    if not args.no_cpu_baseline:
+        uneven()
+        torch.cuda.synchronize()
+        res.update(uneven_cpu_leg(jobs, us, gs, uo, gi))
+    return res
+
+
+def uneven_cpu_leg(jobs, us, gs, uo, gi):
+    """CPU-baseline leg of the uneven workload: the FP64 oracle on every job
+    (the same inputs, copied to the host), timed on the host cores, and each
+    job's relative L2 error of the library's output field and input gradient
+    against it."""
+    import numpy as np
+
+    import oracle
+    oracle.build()
+    threads = host_threads()
+    per_job, secs = [], 0.0
+    print(f"[bench] uneven: FP64 oracle on {len(jobs)} jobs, {threads} threads", file=sys.stderr, flush=True)
+    for k, j in enumerate(jobs):
+        u = us[k].cpu().numpy().astype(np.complex128)
+        g = gs[k].cpu().numpy().astype(np.complex128)
+        t0 = time.perf_counter()
+        eu = oracle.propagate(u, j.d, j.d, j.wavelength, j.z, oracle.ASM, 2)
+        eg = oracle.propagate(g, j.d, j.d, j.wavelength, j.z, oracle.ASM, 2, adjoint=True)
+        secs += time.perf_counter() - t0
+        ru = float(np.linalg.norm(uo[k].cpu().numpy() - eu) / np.linalg.norm(eu))
+        rg = float(np.linalg.norm(gi[k].cpu().numpy() - eg) / np.linalg.norm(eg))
+        per_job.append({"job": k, "n": j.n, "u_out_rel_l2": float(f"{ru:.3e}"), "g_in_rel_l2": float(f"{rg:.3e}")})
+        if k % 16 == 15:
+            print(f"[bench] uneven: oracle {k + 1}/{len(jobs)} jobs, {secs:.1f} s", file=sys.stderr, flush=True)
+    worst = {}
+    for r in per_job:
+        w = worst.setdefault(r["n"], [0.0, 0.0])
+        w[0], w[1] = max(w[0], r["u_out_rel_l2"]), max(w[1], r["g_in_rel_l2"])
+    return {"error_vs_oracle": {"bar": "c64 field <= 2e-5", "all_within_bar": all(
+                max(r["u_out_rel_l2"], r["g_in_rel_l2"]) <= 2e-5 for r in per_job),
+                                "worst_by_n": {str(n): {"u_out": w[0], "g_in": w[1]} for n, w in sorted(worst.items())},
+                                "per_job": per_job},
+            "cpu_baseline": {"value": round(2 * len(jobs) / secs, 3), "unit": "propagations/s", "cores": threads,
+                             "kind": "oracle", "host_cpu": host_cpu_model(),
+                             "sample": f"all {len(jobs)} jobs, forward and adjoint ({2 * len(jobs)} FP64 "
+                                       f"propagations, {secs:.1f} s; lines of each transform shared among "
+                                       f"the threads)"}}
 
 
 def host_threads() -> int:

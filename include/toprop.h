@@ -298,8 +298,9 @@ to_status to_propagate_backward_plain(const to_job* jobs, const to_grad* grads, 
                                       to_dtype dtype, void* stream);
 
 /* Launch schedule of one padded grid and dtype: the column-pass
- * configuration (0 .. 2: LDS budget and points per thread of the column
- * FFT) and the budget of padded intermediate per chunk of fields [MiB].    */
+ * configuration (0 .. 3: LDS budget, points per thread and prefetch of the
+ * column FFT) and the budget of padded intermediate per chunk of fields
+ * [MiB].                                                                   */
 typedef struct to_plan {
   int32_t col_variant;
   int32_t chunk_mb;
@@ -318,13 +319,14 @@ typedef struct to_plan {
  * checks of to_plan_load is ignored) and written back after each tuning.
  * `result` (may be NULL) receives the chosen plan.
  * Precedence when a job runs: TOPROP_COL_VARIANT / TOPROP_CHUNK_MB (tuning
- * overrides) > plan table > built-in defaults (variant 1, 128 MiB).        */
+ * overrides) > plan table > built-in defaults (variant 1; variant 0 for
+ * complex64 columns of 4096 points and more; 128 MiB).                     */
 to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* result);
 
 /* Plan table access (host only, no device work).  to_plan_get sets *found
  * to 1 and fills *plan when (py, px, dtype) has a plan, else *found = 0.
  * to_plan_set validates (py, px powers of two in [8, 8192], col_variant in
- * [0, 3), chunk_mb in [1, 65536], us >= 0) and stores.                     */
+ * [0, 4), chunk_mb in [1, 65536], us >= 0) and stores.                     */
 to_status to_plan_get(int32_t py, int32_t px, to_dtype dtype, to_plan* plan, int32_t* found);
 to_status to_plan_set(int32_t py, int32_t px, to_dtype dtype, const to_plan* plan);
 to_status to_plan_clear(void);
@@ -383,6 +385,22 @@ to_status to_resample(const void* src, void* dst, const to_grid* grid_in, const 
 /* The method a job runs with: job->method, or for TO_AUTO the choice by the
  * critical distance described with the transfer functions.  Host only.      */
 to_status to_resolve_method(const to_job* job, int32_t* method);
+
+/* Jones matrices of standard elements (section "Polarization"), host only,
+ * written to out[18] in the layout of to_job.el_jones (row-major 3x3,
+ * (re, im) pairs), the 2x2 Jones matrix acting on (Ex, Ey) embedded with
+ * J_zz = 1 and no coupling to Ez.
+ *   to_jones_linear_polarizer: transmission axis at theta [rad] from x, the
+ *     projector [[c^2, c s], [c s, s^2]] (c = cos theta, s = sin theta);
+ *   to_jones_waveplate: fast axis at theta, retardance Gamma [rad] of the
+ *     slow axis, R(theta) diag(1, exp(i Gamma)) R(-theta) (Gamma = pi/2: a
+ *     quarter-wave plate), no global phase;
+ *   to_jones_compose: out = then * first (first acts first); out may alias
+ *     either input.
+ * TO_E_INVAL for a NULL pointer or a non-finite angle.                      */
+to_status to_jones_linear_polarizer(double theta, double* out);
+to_status to_jones_waveplate(double theta, double retardance, double* out);
+to_status to_jones_compose(const double* first, const double* then, double* out);
 
 /* Library version, e.g. "toprop 0.1.0 gfx950".                              */
 const char* to_version(void);

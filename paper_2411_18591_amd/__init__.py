@@ -16,7 +16,6 @@ complex128 tensors of shape ``[..., ny, nx]`` (scalar) or ``[..., 3, ny, nx]``
 """
 from __future__ import annotations
 
-import math
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -81,28 +80,25 @@ def _stream(t: torch.Tensor) -> int:
 # ---------------------------------------------------------------------------
 
 def linear_polarizer(theta: float):
-    """2x2 Jones matrix of a linear polarizer whose axis is at angle theta
-    from x: the projector onto (cos theta, sin theta)."""
-    c, s = math.cos(theta), math.sin(theta)
-    return [[complex(c * c), complex(c * s)], [complex(c * s), complex(s * s)]]
+    """3x3 Jones matrix (the 2x2 matrix on (Ex, Ey), J_zz = 1) of a linear
+    polarizer whose axis is at angle theta from x (to_jones_linear_polarizer)."""
+    return _capi.jones_linear_polarizer(theta)
 
 
 def waveplate(theta: float, retardance: float):
-    """2x2 Jones matrix of a waveplate (fast axis at theta, retardance
-    Gamma): R(theta) diag(1, exp(i Gamma)) R(-theta)."""
-    c, s = math.cos(theta), math.sin(theta)
-    e = complex(math.cos(retardance), math.sin(retardance))
-    # R diag(1, e) R^T with R = [[c, -s], [s, c]]
-    return [[c * c + e * s * s, c * s - e * c * s], [s * c - e * s * c, s * s + e * c * c]]
+    """3x3 Jones matrix of a waveplate, fast axis at theta, retardance Gamma
+    (to_jones_waveplate)."""
+    return _capi.jones_waveplate(theta, retardance)
 
 
-def jones3(*mats2x2):
-    """Product of 2x2 Jones matrices (applied left to right: the first
-    argument acts first), embedded in 3x3 with J[2][2] = 1."""
-    J = [[1 + 0j, 0j], [0j, 1 + 0j]]
-    for M in mats2x2:
-        J = [[sum(M[r][k] * J[k][c] for k in range(2)) for c in range(2)] for r in range(2)]
-    return [[J[0][0], J[0][1], 0j], [J[1][0], J[1][1], 0j], [0j, 0j, 1 + 0j]]
+def jones3(*mats):
+    """Product of 3x3 Jones matrices applied left to right (the first
+    argument acts first), composed by to_jones_compose; no argument gives
+    the identity."""
+    J = [[1 + 0j if r == c else 0j for c in range(3)] for r in range(3)]
+    for M in mats:
+        J = _capi.jones_compose(J, M)
+    return J
 
 
 # ---------------------------------------------------------------------------

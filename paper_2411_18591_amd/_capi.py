@@ -40,6 +40,9 @@ TO_EPI_WEIGHTED = 2
 TO_EPI_INTENSITY = 3
 
 EXPORTED = (
+    "to_jones_linear_polarizer",
+    "to_jones_waveplate",
+    "to_jones_compose",
     "to_propagate",
     "to_propagate_noalloc",
     "to_resample",
@@ -200,6 +203,13 @@ def lib() -> ctypes.CDLL:
         L.to_resample.argtypes = [ctypes.c_void_p, ctypes.c_void_p, GR, GR, ctypes.c_int64, c_int, c_int, c_int,
                                   ctypes.c_void_p]
         L.to_resample.restype = c_int
+        DP = ctypes.POINTER(ctypes.c_double)
+        L.to_jones_linear_polarizer.argtypes = [ctypes.c_double, DP]
+        L.to_jones_linear_polarizer.restype = c_int
+        L.to_jones_waveplate.argtypes = [ctypes.c_double, ctypes.c_double, DP]
+        L.to_jones_waveplate.restype = c_int
+        L.to_jones_compose.argtypes = [DP, DP, DP]
+        L.to_jones_compose.restype = c_int
         _lib = L
     return _lib
 
@@ -207,6 +217,41 @@ def lib() -> ctypes.CDLL:
 def check(status: int) -> None:
     if status != TO_OK:
         raise ToError(status, lib().to_last_error().decode())
+
+
+def _jones_out():
+    return (ctypes.c_double * 18)()
+
+
+def _jones_list(buf):
+    return [[complex(buf[6 * r + 2 * c], buf[6 * r + 2 * c + 1]) for c in range(3)] for r in range(3)]
+
+
+def _jones_buf(J):
+    buf = _jones_out()
+    for r in range(3):
+        for c in range(3):
+            buf[6 * r + 2 * c] = complex(J[r][c]).real
+            buf[6 * r + 2 * c + 1] = complex(J[r][c]).imag
+    return buf
+
+
+def jones_linear_polarizer(theta: float):
+    out = _jones_out()
+    check(lib().to_jones_linear_polarizer(float(theta), out))
+    return _jones_list(out)
+
+
+def jones_waveplate(theta: float, retardance: float):
+    out = _jones_out()
+    check(lib().to_jones_waveplate(float(theta), float(retardance), out))
+    return _jones_list(out)
+
+
+def jones_compose(first, then):
+    out = _jones_out()
+    check(lib().to_jones_compose(_jones_buf(first), _jones_buf(then), out))
+    return _jones_list(out)
 
 
 def jobs_array(jobs):

@@ -16,14 +16,16 @@ int col_tile_width(int ly, bool is_double, int variant) {
   int tc = 0;
   auto q = [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    if (variant == 1)
-      tc = is_double ? ColCfg<double, L, 1>::TC : ColCfg<float, L, 1>::TC;
-    else if (variant == 2)
-      tc = is_double ? ColCfg<double, L, 2>::TC : ColCfg<float, L, 2>::TC;
-    else if (variant == 3)
-      tc = is_double ? ColCfg<double, L, 3>::TC : ColCfg<float, L, 3>::TC;
-    else
-      tc = is_double ? ColCfg<double, L, 0>::TC : ColCfg<float, L, 0>::TC;
+    auto w = [&](auto vc) {
+      constexpr int V = decltype(vc)::value;
+      tc = is_double ? ColCfg<double, L, V>::TC : ColCfg<float, L, V>::TC;
+    };
+    switch (variant) {
+      case 1: w(std::integral_constant<int, 1>()); break;
+      case 2: w(std::integral_constant<int, 2>()); break;
+      case 3: w(std::integral_constant<int, 3>()); break;
+      default: w(std::integral_constant<int, 0>()); break;
+    }
     return hipSuccess;
   };
   if (dispatch_len(ly, q) != hipSuccess) return 0;

@@ -84,14 +84,12 @@ hipError_t Launch<T>::col(int ly, bool half, int ntiles, int nfields, int varian
           hipLaunchKernelGGL((col_kernel<T, L, C::R, C::TC, false, EX, C::PF>), grid, block, 0, s, a);
       });
     };
-    if (variant == 1)
-      go(std::integral_constant<int, 1>());
-    else if (variant == 2)
-      go(std::integral_constant<int, 2>());
-    else if (variant == 3)
-      go(std::integral_constant<int, 3>());
-    else
-      go(std::integral_constant<int, 0>());
+    switch (variant) {
+      case 1: go(std::integral_constant<int, 1>()); break;
+      case 2: go(std::integral_constant<int, 2>()); break;
+      case 3: go(std::integral_constant<int, 3>()); break;
+      default: go(std::integral_constant<int, 0>()); break;
+    }
     return hipGetLastError();
   });
 }

@@ -282,3 +282,27 @@ def test_noalloc_rejects_before_any_gpu_work(capi, mutate, status, words):
     assert words in capi.lib().to_last_error().decode()
     assert capi.lib().to_propagate_noalloc(None, -1, capi.TO_C64, None) == capi.TO_E_INVAL
     assert capi.lib().to_propagate_noalloc(None, 0, capi.TO_C64, None) == capi.TO_OK
+
+
+def test_jones_elements_match_the_oracle(capi):
+    """The library's element matrices (host-only entry points) against the
+    oracle's, whose polarizer and waveplate are pinned by the paper's
+    transmitted powers and Malus's law; composition order: the first
+    argument acts first."""
+    import math
+
+    import numpy as np
+
+    import oracle
+    for th in (0.0, 0.3, math.pi / 6, math.pi / 4, 2.0):
+        got = np.array(capi.jones_linear_polarizer(th))
+        assert np.abs(got - oracle.embed_jones(oracle.linear_polarizer(th))).max() <= 1e-15
+        for gam in (math.pi / 2, math.pi, 1.1):
+            got = np.array(capi.jones_waveplate(th, gam))
+            assert np.abs(got - oracle.embed_jones(oracle.waveplate(th, gam))).max() <= 1e-15
+    qwp, lp = capi.jones_waveplate(math.pi / 4, math.pi / 2), capi.jones_linear_polarizer(math.pi / 6)
+    got = np.array(capi.jones_compose(qwp, lp))
+    exp = oracle.embed_jones(oracle.linear_polarizer(math.pi / 6) @ oracle.waveplate(math.pi / 4, math.pi / 2))
+    assert np.abs(got - exp).max() <= 1e-15
+    with pytest.raises(capi.ToError):
+        capi.jones_linear_polarizer(float("nan"))

@@ -106,9 +106,16 @@ def test_elements_loss_and_mask_gradient(dtype, shape):
     Ie = np.abs(v) ** 2 - T
     assert abs(float(loss.item()) - 0.5 * float((Ie ** 2).sum())) <= 1e-4 * 0.5 * float((Ie ** 2).sum())
     g = 4 * 0.5 * Ie * v
+    # the loss gradient 2 (|v|^2 - T) v is a derived quantity: the error of
+    # v enters |v|^2 - T relative to that difference, not to |v|^2, so its
+    # bar carries the factor 4 (measured and justified with the other
+    # derived bars); the input gradient is one adjoint propagation of the
+    # library's own loss gradient and takes the field bar
     assert rel(to_np(grad), g) <= 4 * TOL[dtype]
     gmod = _oracle(to_np(grad).astype(np.complex128), opt, adjoint=True)
-    assert rel(to_np(gin), oracle.modulate(gmod, M, conj=True)) <= 4 * TOL[dtype]
+    e_in = rel(to_np(gin), oracle.modulate(gmod, M, conj=True))
+    announce(f"any-length loss chain: input-gradient error {e_in:.2e}")
+    assert e_in <= TOL[dtype], e_in
     assert rel(to_np(gphi), oracle.grad_phase(gmod, um)) <= (1e-4 if dtype == np.complex64 else 1e-10)
 
 

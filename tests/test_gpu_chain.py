@@ -97,7 +97,9 @@ def test_forward_backward_chain_matches_layers_and_oracle(shape, dtype):
         grads[l] = oracle.grad_phase(gm, oracle.modulate(ref[l], m))
         g = oracle.modulate(gm, m, conj=True)
     for l in range(1, L + 1):
-        assert rel(uf[l], ref[l]) <= ORACLE_TOL[dtype] * l, l
+        e = rel(uf[l], ref[l])
+        announce(f"chain layer {l}: field error vs oracle {e:.2e}")
+        assert e <= ORACLE_TOL[dtype], (l, e)
     assert abs(lf - loss) <= 4 * ORACLE_TOL[dtype] * loss
     for l in range(L):
         assert rel(gf[l], grads[l]) <= GRAD_TOL[dtype], l

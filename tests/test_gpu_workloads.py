@@ -84,8 +84,10 @@ def test_diffractive_network_full_size():
     announce("diffractive network: oracle on field 0 through 5 layers")
     us = oracle.stack_forward(u0[:1].astype(np.complex128), [m.astype(np.float64) for m in masks],
                               wl.d, wl.d, wl.wavelength, wl.z, oracle.ASM, wl.pad)
-    assert rel(out0_128, us[-1][0]) <= 5e-12
-    assert rel(out0_64, us[-1][0]) <= 2e-5
+    e128, e64 = rel(out0_128, us[-1][0]), rel(out0_64, us[-1][0])
+    announce(f"diffractive network: field 0 after 5 layers, error c128 {e128:.2e}, c64 {e64:.2e}")
+    assert e128 <= 1e-12, e128
+    assert e64 <= 2e-5, e64
 
 
 def _prop1d(v, h):
