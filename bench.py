@@ -63,6 +63,8 @@ def parse():
     p.add_argument("--cpu-sample-layers", type=int, default=3,
                    help="layers (of the workload's masks) in the CPU oracle sample")
     p.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="run with the built-in schedule instead of tuning one before the timed region")
     p.add_argument("--plain-steps", type=int, default=1,
                    help="timed steps of the unfused plain form (0 = skip the comparison)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -234,6 +236,16 @@ def main():
                          torch.from_numpy(target_np).to(dev), opt)
     loss = net.loss
     step = net.step
+    # The launch schedule of the padded grid (column configuration, chunk,
+    # fields per row-pass workgroup), tuned by the library's autotuner on one
+    # layer's forward propagation of the whole batch before anything is timed.
+    plan = None
+    if not args.no_autotune:
+        print("[bench] autotune", file=sys.stderr, flush=True)
+        tuned, plan = tp.autotune(net.u[0], opt, phase=net.masks[0])
+        del tuned
+        torch.cuda.synchronize()
+        print(f"[bench] plan {plan}", file=sys.stderr, flush=True)
 
     print("[bench] warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -367,6 +379,7 @@ def main():
             "propagations_per_step": props,
         },
         "hbm_roofline_step": {"algorithmic_bytes": step_bytes, "frac": round(hbm_frac_step, 4)},
+        "schedule": {"tuned": plan is not None, "plan": plan},
         "profiled_pass_ms_per_step": None if prof_ms_step is None else round(prof_ms_step, 4),
         "plain_form": plain,
         "roofline": roofline,
@@ -821,6 +834,27 @@ def run_uneven(args, dev):
     res = {"jobs": len(jobs), "ms_per_step": round(ms, 3), "propagations_per_step": 2 * len(jobs),
            "propagations_per_s": round(2 * len(jobs) / (ms / 1000.0), 1),
            "field_elements_per_job_sum": elems, "kernels": top}
+    # The same step captured once into a HIP graph (both calls, every lane)
+    # and replayed: no host launch work per kernel.  The replay's outputs
+    # must equal the eager step's bit for bit.
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in uo + gi]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        uneven()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        uneven()
+    for t in uo + gi:
+        t.zero_()
+    ms_g, _ = _timed(graph.replay, args.steps, 1)
+    same = all(torch.equal(a, b) for a, b in zip(uo + gi, ref))
+    res["graph"] = {"ms_per_step": round(ms_g, 3), "propagations_per_s": round(2 * len(jobs) / (ms_g / 1000.0), 1),
+                    "outputs_equal_eager": same}
+    del graph, ref
     if not args.no_cpu_baseline:
         uneven()
         torch.cuda.synchronize()

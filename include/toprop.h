@@ -304,11 +304,14 @@ to_status to_propagate_backward_plain(const to_job* jobs, const to_grad* grads, 
 typedef struct to_plan {
   int32_t col_variant;
   int32_t chunk_mb;
+  int32_t row_fpb;  /* fields per row-pass workgroup, 1 .. 8; 0: as many as
+                       keep one round of resident workgroups per launch     */
   double us;  /* measured time of the tuned forward propagation [us]       */
 } to_plan;
 
 /* Autotuner (the schedules of the batch/schedule layer): times every column
- * configuration for several chunk sizes on this job (forward propagation,
+ * configuration for several chunk sizes on this job, then the fields per
+ * row-pass workgroup with the fastest of those (forward propagation,
  * element included, epilogue left out, into a temporary output), stores the
  * fastest in the plan table under (job->py, job->px, dtype), then runs the
  * job once with it (so job->out and the epilogue are as after
@@ -318,22 +321,23 @@ typedef struct to_plan {
  * the table is read from it on first use (a file that fails the format
  * checks of to_plan_load is ignored) and written back after each tuning.
  * `result` (may be NULL) receives the chosen plan.
- * Precedence when a job runs: TOPROP_COL_VARIANT / TOPROP_CHUNK_MB (tuning
- * overrides) > plan table > built-in defaults (variant 1; variant 0 for
+ * Precedence when a job runs: TOPROP_COL_VARIANT / TOPROP_CHUNK_MB /
+ * TOPROP_ROW_FPB (tuning overrides) > plan table > built-in defaults (variant 1; variant 0 for
  * complex64 columns of 4096 points and more; 128 MiB).                     */
 to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* result);
 
 /* Plan table access (host only, no device work).  to_plan_get sets *found
  * to 1 and fills *plan when (py, px, dtype) has a plan, else *found = 0.
  * to_plan_set validates (py, px powers of two in [8, 8192], col_variant in
- * [0, 4), chunk_mb in [1, 65536], us >= 0) and stores.                     */
+ * [0, 4), chunk_mb in [1, 65536], row_fpb in [0, 8], us >= 0) and stores.  */
 to_status to_plan_get(int32_t py, int32_t px, to_dtype dtype, to_plan* plan, int32_t* found);
 to_status to_plan_set(int32_t py, int32_t px, to_dtype dtype, const to_plan* plan);
 to_status to_plan_clear(void);
 
-/* Plan files: text, first line "toprop-plan 1", then one record per line
- * "<c64|c128> <py> <px> <col_variant> <chunk_mb> <us>" ('#' lines are
- * comments).  to_plan_load merges a file into the table only if every line
+/* Plan files: text, first line "toprop-plan 2", then one record per line
+ * "<c64|c128> <py> <px> <col_variant> <chunk_mb> <row_fpb> <us>" ('#' lines
+ * are comments); files headed "toprop-plan 1" hold the same records without
+ * row_fpb (read as 0).  to_plan_load merges a file into the table only if every line
  * passes the checks of to_plan_set (and no key repeats); otherwise it
  * returns TO_E_INVAL naming the line and leaves the table unchanged.
  * to_plan_save writes the table atomically (temporary file + rename).     */

@@ -514,8 +514,9 @@ def plan_get(py: int, px: int, dtype=torch.complex64):
     return _capi.plan_get(py, px, _dtype_of(dtype))
 
 
-def plan_set(py: int, px: int, col_variant: int, chunk_mb: int, dtype=torch.complex64, us: float = 0.0):
-    _capi.plan_set(py, px, _dtype_of(dtype), col_variant, chunk_mb, us)
+def plan_set(py: int, px: int, col_variant: int, chunk_mb: int, dtype=torch.complex64, us: float = 0.0,
+             row_fpb: int = 0):
+    _capi.plan_set(py, px, _dtype_of(dtype), col_variant, chunk_mb, us, row_fpb)
 
 
 def plan_clear():

@@ -128,8 +128,13 @@ class Plan(ctypes.Structure):
     _fields_ = [
         ("col_variant", ctypes.c_int32),
         ("chunk_mb", ctypes.c_int32),
+        ("row_fpb", ctypes.c_int32),
         ("us", ctypes.c_double),
     ]
+
+
+def _plan_dict(p) -> dict:
+    return {"col_variant": p.col_variant, "chunk_mb": p.chunk_mb, "row_fpb": p.row_fpb, "us": p.us}
 
 
 class ToError(RuntimeError):
@@ -292,7 +297,7 @@ def coherence_propagate(job, dtype: int, adjoint: bool, grad, stream: int) -> No
 def autotune(job, dtype: int, stream: int) -> dict:
     p = Plan()
     check(lib().to_autotune(ctypes.byref(job), dtype, ctypes.c_void_p(stream), ctypes.byref(p)))
-    return {"col_variant": p.col_variant, "chunk_mb": p.chunk_mb, "us": p.us}
+    return _plan_dict(p)
 
 
 def transfer_table(job, dtype: int, table: int, stream: int) -> None:
@@ -316,11 +321,12 @@ def plan_get(py: int, px: int, dtype: int):
     p = Plan()
     found = ctypes.c_int32()
     check(lib().to_plan_get(py, px, dtype, ctypes.byref(p), ctypes.byref(found)))
-    return {"col_variant": p.col_variant, "chunk_mb": p.chunk_mb, "us": p.us} if found.value else None
+    return _plan_dict(p) if found.value else None
 
 
-def plan_set(py: int, px: int, dtype: int, col_variant: int, chunk_mb: int, us: float = 0.0) -> None:
-    p = Plan(col_variant, chunk_mb, us)
+def plan_set(py: int, px: int, dtype: int, col_variant: int, chunk_mb: int, us: float = 0.0,
+             row_fpb: int = 0) -> None:
+    p = Plan(col_variant, chunk_mb, row_fpb, us)
     check(lib().to_plan_set(py, px, dtype, ctypes.byref(p)))
 
 

@@ -274,9 +274,19 @@ long env_chunk_mb() {  // -1: not set
   return mb;
 }
 
+int env_row_fpb() {  // 0: not set
+  static int v = [] {
+    const char* s = getenv("TOPROP_ROW_FPB");
+    const int x = s ? atoi(s) : 0;
+    return (x >= 1 && x <= kPlanMaxRowFpb) ? x : 0;
+  }();
+  return v;
+}
+
 struct Schedule {
   int col_variant;
   size_t chunk_bytes;
+  int row_fpb;  // fields per row-pass workgroup, 0: from the occupancy target
 };
 
 // Built-in column configuration: complex64 columns of 4096 points and more
@@ -287,8 +297,9 @@ struct Schedule {
 int default_col_variant(int dtype, int ly) { return (dtype == 0 && ly >= 4096) ? 0 : kDefaultColVariant; }
 
 Schedule schedule_for(int dtype, int ly, int lx) {
-  if (t_force_plan) return {t_force_plan->col_variant, (size_t)t_force_plan->chunk_mb << 20};
-  Schedule sc{default_col_variant(dtype, ly), (size_t)kDefaultChunkMb << 20};
+  if (t_force_plan)
+    return {t_force_plan->col_variant, (size_t)t_force_plan->chunk_mb << 20, t_force_plan->row_fpb};
+  Schedule sc{default_col_variant(dtype, ly), (size_t)kDefaultChunkMb << 20, 0};
   PlanEntry pe;
   const bool have = plan_lookup(dtype, ly, lx, &pe);
   if (env_col_variant() >= 0)
@@ -299,6 +310,10 @@ Schedule schedule_for(int dtype, int ly, int lx) {
     sc.chunk_bytes = (size_t)env_chunk_mb() << 20;
   else if (have)
     sc.chunk_bytes = (size_t)pe.chunk_mb << 20;
+  if (env_row_fpb() >= 1)
+    sc.row_fpb = env_row_fpb();
+  else if (have)
+    sc.row_fpb = pe.row_fpb;
   return sc;
 }
 
@@ -666,7 +681,16 @@ struct Geometry {
   int64_t chunk;          // field groups per chunk
   int rows_per_block;     // rows handled by one row-pass workgroup
   int col_variant;        // column-pass configuration (see ColCfg)
+  int row_fpb = 0;        // fields per row-pass workgroup from the schedule (0: automatic)
 };
+
+// Fields per row-pass workgroup: the schedule's value (at most the chunk's
+// fields) or, when it leaves the choice open, as many as keep the launch at
+// one round of resident workgroups.
+int row_fields_per_block(const Geometry& g, int row_blocks, int nf, bool heavy, bool dbl) {
+  if (g.row_fpb > 0) return std::max(1, std::min(g.row_fpb, nf));
+  return fields_per_block_rows(row_blocks, nf, row_blocks_target(g.lx, dbl, heavy));
+}
 
 // Components of a field processed together by one workgroup: a Jones
 // element mixes them, and the intensity epilogue sums over them.
@@ -699,6 +723,7 @@ to_status make_geometry(const to_job& j, bool jones, Geometry* g) {
   g->half_y = 2 * j.ny <= g->ly;
   const Schedule sc = schedule_for(sizeof(T) == 8 ? 1 : 0, g->ly, g->lx);
   g->col_variant = sc.col_variant;
+  g->row_fpb = sc.row_fpb;
   // columns per column-pass block (cpb) and the scratch tile width (tm):
   // a tile row segment is one 128-byte cache line when the rows allow it
   g->tc = col_tile_width(g->ly, sizeof(T) == 8, g->col_variant);
@@ -759,8 +784,8 @@ RowFwdArgs<T> row_fwd_args(const to_job& j, const Geometry& g, DeviceCtx* c, cx<
                            int64_t f0) {
   RowFwdArgs<T> ra;
   memset(&ra, 0, sizeof(ra));
-  ra.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block, nf,
-                                  row_blocks_target(g.lx, sizeof(T) == 8, g.nc_kernel == 3));
+  ra.fpb = row_fields_per_block(g, (j.ny + g.rows_per_block - 1) / g.rows_per_block, nf, g.nc_kernel == 3,
+                                sizeof(T) == 8);
   ra.coh_m = coh_m;
   ra.f_off = f0;
   ra.in = in;
@@ -840,8 +865,8 @@ to_status finish_forward_chunk(const to_job& j, const Geometry& g, DeviceCtx* c,
   ia.epi_grad = j.epi_grad ? (cx<T>*)j.epi_grad + f0 * g.in_stride : nullptr;
   ia.row_partial = ln->partial;
   ia.backward = 0;
-  ia.fpb = fields_per_block_rows((j.ny + g.rows_per_block - 1) / g.rows_per_block, nf,
-                                  row_blocks_target(g.lx, sizeof(T) == 8, g.nc_kernel == 3));
+  ia.fpb = row_fields_per_block(g, (j.ny + g.rows_per_block - 1) / g.rows_per_block, nf, g.nc_kernel == 3,
+                                sizeof(T) == 8);
   const int inv_blocks_y = (nf + ia.fpb - 1) / ia.fpb;
   ia.el = make_element<T>(j, 0);
   const bool dbl = sizeof(T) == 8;
@@ -1068,7 +1093,7 @@ to_status run_forward_chain(const to_job* jobs, int n, DeviceCtx* c, Lane* ln, h
       ma.nx = j0.nx;
       ma.tc_shift = g.tc_shift;
       ma.nfields = nf;
-      ma.fpb = fields_per_block_rows(row_blocks, nf, row_blocks_target(g.lx, sizeof(T) == 8, false));
+      ma.fpb = row_fields_per_block(g, row_blocks, nf, false, sizeof(T) == 8);
       ma.scale = (T)(1.0 / ((double)g.lx * (double)g.ly));
       ma.el = el[l + 1];
       ma.tw = twiddles<T>(c, g.lx);
@@ -1088,7 +1113,7 @@ to_status run_forward_chain(const to_job* jobs, int n, DeviceCtx* c, Lane* ln, h
 // fields, and the groups' gradient partials are combined in order.
 template <typename T>
 int mid_bwd_fields_per_block(int row_blocks, int nf, const Geometry& g) {
-  return fields_per_block_rows(row_blocks, nf, row_blocks_target(g.lx, sizeof(T) == 8, false));
+  return row_fields_per_block(g, row_blocks, nf, false, sizeof(T) == 8);
 }
 
 // Reduction partials (doubles) of a backward chain's fused boundaries: lens
@@ -2406,6 +2431,22 @@ to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* 
       }
     }
   }
+  // then the fields per row-pass workgroup, with the best column
+  // configuration and chunk (0: the occupancy rule)
+  static const int kRowFpb[] = {1, 2, 4, 8};
+  for (int fpb : kRowFpb) {
+    if (st != TO_OK) break;
+    const int64_t nf = (int64_t)tj.batch * (coupled(tj) ? 1 : tj.ncomp);
+    if (fpb > 1 && fpb > nf) continue;  // the same as the largest already timed
+    PlanEntry pe{best.col_variant, best.chunk_mb, 0.0, fpb};
+    double us = 0.0;
+    st = dtype == TO_C64 ? time_candidate<float>(tj, c, s, pe, 3, ea, eb, &us)
+                         : time_candidate<double>(tj, c, s, pe, 3, ea, eb, &us);
+    if (st == TO_OK && us < best.us) {
+      best = pe;
+      best.us = us;
+    }
+  }
   (void)hipEventDestroy(ea);
   (void)hipEventDestroy(eb);
   (void)hipFree(tmp);  // the timed runs were synchronized above
@@ -2415,7 +2456,7 @@ to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* 
     std::string err;
     plan_save_file(plan_env_path().c_str(), &err);  // best effort: the table holds the plan
   }
-  if (result) *result = {best.col_variant, best.chunk_mb, best.us};
+  if (result) *result = {best.col_variant, best.chunk_mb, best.row_fpb, best.us};
   // the job itself, once, under the stored plan
   return to_propagate(job, 1, dtype, stream);
 }
@@ -2426,7 +2467,7 @@ to_status to_plan_get(int32_t py, int32_t px, to_dtype dtype, to_plan* plan, int
   if (!plan || !found) return fail(TO_E_INVAL, "plan or found is NULL");
   PlanEntry pe;
   *found = plan_lookup(dtype == TO_C64 ? 0 : 1, py, px, &pe) ? 1 : 0;
-  if (*found) *plan = {pe.col_variant, pe.chunk_mb, pe.us};
+  if (*found) *plan = {pe.col_variant, pe.chunk_mb, pe.row_fpb, pe.us};
   return TO_OK;
 }
 
@@ -2434,7 +2475,7 @@ to_status to_plan_set(int32_t py, int32_t px, to_dtype dtype, const to_plan* pla
   to_status st = plan_args(py, px, dtype);
   if (st != TO_OK) return st;
   if (!plan) return fail(TO_E_INVAL, "plan is NULL");
-  const PlanEntry pe{plan->col_variant, plan->chunk_mb, plan->us};
+  const PlanEntry pe{plan->col_variant, plan->chunk_mb, plan->us, plan->row_fpb};
   std::string err;
   const int dt = dtype == TO_C64 ? 0 : 1;
   if (!plan_entry_valid(dt, py, px, pe, &err)) return fail(TO_E_INVAL, "%s", err.c_str());

@@ -1,10 +1,12 @@
 // Plan table and its file format (host code).
 //
 // File format, one record per line, '#' starts a comment line:
-//   toprop-plan 1                                   (first line, exactly)
-//   <c64|c128> <ly> <lx> <col_variant> <chunk_mb> <us>
+//   toprop-plan 2                                   (first line, exactly)
+//   <c64|c128> <ly> <lx> <col_variant> <chunk_mb> <row_fpb> <us>
 // ly, lx: powers of two in [8, 8192]; col_variant in [0, kColVariants);
-// chunk_mb in [1, 65536]; us finite and >= 0.  Duplicate keys are an error.
+// chunk_mb in [1, 65536]; row_fpb in [0, 8] (0: automatic); us finite and
+// >= 0.  Duplicate keys are an error.  Files of version 1 (the same records
+// without row_fpb) are read with row_fpb = 0; files are written as version 2.
 #include <cerrno>
 #include <cmath>
 #include <cstdio>
@@ -28,7 +30,8 @@ std::mutex g_plan_mutex;
 std::map<Key, PlanEntry> g_plans;
 bool g_env_loaded = false;
 
-const char* kHeader = "toprop-plan 1";
+const char* kHeader = "toprop-plan 2";
+const char* kHeaderV1 = "toprop-plan 1";
 
 bool pow2_len(int n) { return n >= kMinLen && n <= kMaxLen && (n & (n - 1)) == 0; }
 
@@ -57,12 +60,15 @@ bool parse_double(const std::string& t, double* v) {
 bool parse_plan(std::istream& in, const char* name, std::map<Key, PlanEntry>* out, std::string* err) {
   std::string line;
   int ln = 0;
+  int fields = 7;  // per record: 7 in version 2, 6 in version 1
   char buf[256];
   while (std::getline(in, line)) {
     ++ln;
     if (ln == 1) {
-      if (line != kHeader) {
-        snprintf(buf, sizeof buf, "%s: line 1 is not the header '%s'", name, kHeader);
+      if (line == kHeaderV1) {
+        fields = 6;
+      } else if (line != kHeader) {
+        snprintf(buf, sizeof buf, "%s: line 1 is not the header '%s' (or '%s')", name, kHeader, kHeaderV1);
         *err = buf;
         return false;
       }
@@ -70,19 +76,22 @@ bool parse_plan(std::istream& in, const char* name, std::map<Key, PlanEntry>* ou
     }
     if (line.empty() || line[0] == '#') continue;
     std::istringstream ls(line);
-    std::string tok[7];
+    std::string tok[8];
     int n = 0;
-    while (n < 7 && (ls >> tok[n])) ++n;
-    if (n != 6) {
-      snprintf(buf, sizeof buf, "%s: line %d has %s 6 fields", name, ln, n < 6 ? "fewer than" : "more than");
+    while (n < 8 && (ls >> tok[n])) ++n;
+    if (n != fields) {
+      snprintf(buf, sizeof buf, "%s: line %d has %s %d fields", name, ln, n < fields ? "fewer than" : "more than",
+               fields);
       *err = buf;
       return false;
     }
     const int dt = tok[0] == "c64" ? 0 : (tok[0] == "c128" ? 1 : -1);
     PlanEntry e;
     int ly, lx;
+    e.row_fpb = 0;
+    const bool fpb_ok = fields == 6 || parse_int(tok[5], &e.row_fpb);
     if (dt < 0 || !parse_int(tok[1], &ly) || !parse_int(tok[2], &lx) || !parse_int(tok[3], &e.col_variant) ||
-        !parse_int(tok[4], &e.chunk_mb) || !parse_double(tok[5], &e.us)) {
+        !parse_int(tok[4], &e.chunk_mb) || !fpb_ok || !parse_double(tok[fields - 1], &e.us)) {
       snprintf(buf, sizeof buf, "%s: line %d: malformed record", name, ln);
       *err = buf;
       return false;
@@ -138,6 +147,8 @@ bool plan_entry_valid(int dtype, int ly, int lx, const PlanEntry& e, std::string
     snprintf(buf, sizeof buf, "column variant %d is outside [0, %d)", e.col_variant, kColVariants);
   } else if (e.chunk_mb < 1 || e.chunk_mb > kPlanMaxChunkMb) {
     snprintf(buf, sizeof buf, "chunk size %d MiB is outside [1, %d]", e.chunk_mb, kPlanMaxChunkMb);
+  } else if (e.row_fpb < 0 || e.row_fpb > kPlanMaxRowFpb) {
+    snprintf(buf, sizeof buf, "row fields per workgroup %d is outside [0, %d]", e.row_fpb, kPlanMaxRowFpb);
   } else if (!std::isfinite(e.us) || e.us < 0) {
     snprintf(buf, sizeof buf, "time %g is not a finite non-negative number", e.us);
   } else {
@@ -202,10 +213,10 @@ int plan_save_file(const char* path, std::string* err) {
     *err = std::string("cannot write plan file ") + tmp;
     return -1;
   }
-  fprintf(f, "%s\n# dtype ly lx col_variant chunk_mb us\n", kHeader);
+  fprintf(f, "%s\n# dtype ly lx col_variant chunk_mb row_fpb us\n", kHeader);
   for (auto& kv : snap)
-    fprintf(f, "%s %d %d %d %d %.3f\n", std::get<0>(kv.first) ? "c128" : "c64", std::get<1>(kv.first),
-            std::get<2>(kv.first), kv.second.col_variant, kv.second.chunk_mb, kv.second.us);
+    fprintf(f, "%s %d %d %d %d %d %.3f\n", std::get<0>(kv.first) ? "c128" : "c64", std::get<1>(kv.first),
+            std::get<2>(kv.first), kv.second.col_variant, kv.second.chunk_mb, kv.second.row_fpb, kv.second.us);
   const bool bad = ferror(f) != 0;
   if (fclose(f) != 0 || bad) {
     remove(tmp.c_str());

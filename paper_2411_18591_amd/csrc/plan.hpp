@@ -1,5 +1,6 @@
 // Plan table: per (dtype, padded ly, padded lx) launch schedule chosen by the
-// autotuner (column-pass configuration and chunk size), with a strict text
+// autotuner (column-pass configuration, chunk size, fields per row-pass
+// workgroup), with a strict text
 // file format for persisting it.  Host code only.
 #pragma once
 
@@ -11,6 +12,7 @@ struct PlanEntry {
   int col_variant;  // ColCfg variant of the column pass
   int chunk_mb;     // budget of padded intermediate per chunk [MiB]
   double us;        // measured time of the tuned forward propagation [us]
+  int row_fpb = 0;  // fields per row-pass workgroup (0: chosen from the device's occupancy)
 };
 
 // dtype: 0 = complex64, 1 = complex128.
@@ -33,5 +35,6 @@ bool plan_entry_valid(int dtype, int ly, int lx, const PlanEntry& e, std::string
 const std::string& plan_env_path();
 
 constexpr int kPlanMaxChunkMb = 65536;
+constexpr int kPlanMaxRowFpb = 8;
 
 }  // namespace toprop

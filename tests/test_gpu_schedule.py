@@ -292,8 +292,10 @@ def test_autotune_stores_a_plan_and_keeps_parity():
     out, plan = tp.autotune(ug, opt, phase=pg)
     torch.cuda.synchronize()
     assert 0 <= plan["col_variant"] < 4 and plan["chunk_mb"] in (32, 64, 128, 256) and plan["us"] > 0
+    assert plan["row_fpb"] in (0, 1, 2, 4)
     stored = tp.plan_get(2 * n, 2 * n)
-    assert (stored["col_variant"], stored["chunk_mb"]) == (plan["col_variant"], plan["chunk_mb"])
+    assert (stored["col_variant"], stored["chunk_mb"], stored["row_fpb"]) == (
+        plan["col_variant"], plan["chunk_mb"], plan["row_fpb"])
     exp = oracle.propagate(oracle.modulate(u, oracle.phase_mask(phi)), d, d, lam, z, oracle.ASM, 2)
     assert rel(to_np(out), exp) <= TOL
     again = tp.propagate(ug, opt, phase=pg)  # uses the stored plan
