@@ -833,7 +833,7 @@ def run_uneven(args, dev):
     elems = sum(j.n * j.n for j in jobs)
     res = {"jobs": len(jobs), "ms_per_step": round(ms, 3), "propagations_per_step": 2 * len(jobs),
            "propagations_per_s": round(2 * len(jobs) / (ms / 1000.0), 1),
-           "field_elements_per_job_sum": elems, "kernels": top}
+           "field_elements_per_job_sum": elems, "kernels": top, "roofline": uneven_roofline(top)}
     # The same step captured once into a HIP graph (both calls, every lane)
     # and replayed: no host launch work per kernel.  The replay's outputs
     # must equal the eager step's bit for bit.
@@ -860,6 +860,30 @@ def run_uneven(args, dev):
         torch.cuda.synchronize()
         res.update(uneven_cpu_leg(jobs, us, gs, uo, gi))
     return res
+
+
+def uneven_roofline(top):
+    """Roofline entry of the uneven batch's dominant kernel (largest total
+    GPU time): one launch covers one field of a square job padded to L x L
+    (N = L / 2), whose nominal flops and algorithmic bytes `kernel_model`
+    gives; launches on the four lanes overlap, so the per-launch time (and
+    the fraction) is a lower bound on what the kernel reaches alone."""
+    if not top:
+        return None
+    name, rec = next(iter(top.items()))
+    try:
+        L = int(name.rsplit("_L", 1)[1])
+    except (IndexError, ValueError):
+        return None
+    m = kernel_model(name, {"n": L // 2, "padded": L}, 1)
+    if not m:
+        return None
+    by, fl = m
+    avg_s = rec["avg_us"] * 1e-6
+    tfs, gbs = fl / avg_s / 1e12, by / avg_s / 1e9
+    return {"bound": "alu", "achieved": round(tfs, 3), "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tfs / VALU_FP32_PEAK_TFLOPS, 4), "traffic": None, "kernel": name,
+            "avg_us": rec["avg_us"], "hbm_view": {"achieved_GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}}
 
 
 def uneven_cpu_leg(jobs, us, gs, uo, gi):
