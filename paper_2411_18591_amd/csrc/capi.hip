@@ -23,6 +23,7 @@
 #include "noalloc.hpp"
 #include "plain.hpp"
 #include "plan.hpp"
+#include "queue.hpp"
 #include "resample.hpp"
 #include "transfer.hpp"
 
@@ -2036,6 +2037,219 @@ to_status prepare_jobs_dt(const to_job* jobs, int n, to_dtype dt, DeviceCtx* c, 
   return dt == TO_C64 ? prepare_all<float>(jobs, n, c, s, out) : prepare_all<double>(jobs, n, c, s, out);
 }
 
+// ---------------------------------------------------------------------------
+// Job-queue groups: independent propagations of one shape class, each too
+// small to fill the device with its own launches, run as one launch per pass
+// over all of them (QueueLaunch) instead of three launches per job.  A group
+// is one scheduling unit on the lanes.  Every eligible job runs through the
+// queue kernels, alone or not, so its result does not depend on the other
+// jobs of the call.
+// ---------------------------------------------------------------------------
+// Upper bound of a group's summed intermediates: a group's passes then
+// hand their intermediate to the next pass through the last-level cache
+// (256 MiB, shared by the lanes) instead of HBM.
+constexpr size_t kQueueScratchCap = (size_t)64 << 20;
+
+bool env_no_queue() { return getenv("TOPROP_NO_QUEUE") != nullptr; }  // read per call
+
+struct QueueKey {
+  int lx, ly, variant, tc, tm;
+  bool half_x, half_y, ex_x, ex_y;
+  bool operator==(const QueueKey& o) const {
+    return lx == o.lx && ly == o.ly && variant == o.variant && tc == o.tc && tm == o.tm && half_x == o.half_x &&
+           half_y == o.half_y && ex_x == o.ex_x && ex_y == o.ex_y;
+  }
+};
+
+// Shape class of job j for a job-queue launch and the size of its padded
+// intermediate; false where the job runs on its own: grids beyond the
+// queue's lengths, coupled components, elements, epilogues, more fields
+// than one chunk, or a transfer function whose tables would be built in the
+// lane (one slot, not one per job).
+template <typename T>
+bool queue_class(const to_job& j, bool backward, QueueKey* key, size_t* scratch_bytes) {
+  if (j.batch == 0 || !pow2_grid(j) || !queue_len_ok(j.px) || !queue_len_ok(j.py)) return false;
+  if (j.el_flags != 0 || coupled(j) || has_jones(j)) return false;
+  if (!backward && j.epi != TO_EPI_NONE) return false;
+  Geometry g;
+  if (make_geometry<T>(j, false, &g) != TO_OK || g.nc_kernel != 1 || g.chunk < g.nfields) return false;
+  if (sizeof(T) == 4) {
+    const TransferParams h = make_transfer(j, backward);
+    const bool exact_phase = h.method == TO_ASM && !(asm_remainder_cycles(j) <= kFastRemainderCycles);
+    if (!h.table && !exact_phase && !j.tf_table) return false;
+  }
+  key->lx = g.lx;
+  key->ly = g.ly;
+  key->variant = g.col_variant;
+  key->tc = g.tc;
+  key->tm = g.tm;
+  key->half_x = g.half_x;
+  key->half_y = g.half_y;
+  key->ex_x = j.nx == (g.half_x ? g.lx / 2 : g.lx);
+  key->ex_y = j.ny == (g.half_y ? g.ly / 2 : g.ly);
+  *scratch_bytes = ((size_t)g.s_stride * g.nfields * sizeof(cx<T>) + 255) & ~(size_t)255;
+  return true;
+}
+
+// Scheduling units of a call: a chain of `len` jobs from `beg` (len 1: one
+// job), or a job-queue group (`group` >= 0, an index into the call's groups).
+struct Unit {
+  int beg, len, group;
+};
+
+// Groups the single-job units whose jobs share a class and touch no range
+// any other job of the call touches (so they may run in any order, in one
+// launch); a job joins the first open group of its class.  An eligible job
+// that conflicts with another job forms a group of its own.  `jrd` / `jwr`:
+// each job's read and written ranges.
+template <typename T>
+std::vector<Unit> group_units(const to_job* jobs, const std::vector<Unit>& units, bool backward,
+                              const std::vector<std::vector<Span>>& jrd, const std::vector<std::vector<Span>>& jwr,
+                              std::vector<std::vector<int>>* groups) {
+  groups->clear();
+  const int n = (int)jrd.size();
+  auto touches = [&](int a, int b) {  // a writes what b reads or writes, or the reverse
+    for (const Span& w : jwr[a]) {
+      for (const Span& r : jrd[b]) if (overlaps(w, r)) return true;
+      for (const Span& r : jwr[b]) if (overlaps(w, r)) return true;
+    }
+    for (const Span& w : jwr[b])
+      for (const Span& r : jrd[a]) if (overlaps(w, r)) return true;
+    return false;
+  };
+  std::vector<QueueKey> gkey;
+  std::vector<size_t> gbytes;
+  std::vector<bool> gopen;  // whether other jobs may join
+  std::vector<int> group_of(units.size(), -1);
+  for (size_t u = 0; u < units.size(); ++u) {
+    if (units[u].len != 1) continue;
+    const int i = units[u].beg;
+    QueueKey key;
+    size_t bytes = 0;
+    if (!queue_class<T>(jobs[i], backward, &key, &bytes)) continue;
+    bool alone = true;
+    for (int k = 0; k < n && alone; ++k) alone = k == i || !touches(i, k);
+    int gi = 0;
+    while (alone && gi < (int)groups->size() &&
+           !(gkey[gi] == key && gopen[gi] && (int)(*groups)[gi].size() < kQueueJobs &&
+             gbytes[gi] + bytes <= kQueueScratchCap))
+      ++gi;
+    if (!alone) gi = (int)groups->size();
+    if (gi == (int)groups->size()) {
+      groups->emplace_back();
+      gkey.push_back(key);
+      gbytes.push_back(0);
+      gopen.push_back(alone);
+    }
+    (*groups)[gi].push_back((int)u);
+    gbytes[gi] += bytes;
+    group_of[u] = gi;
+  }
+  // a group takes the place of its first unit
+  std::vector<int> renum(groups->size(), -1);
+  std::vector<std::vector<int>> kept;
+  std::vector<Unit> out;
+  for (size_t u = 0; u < units.size(); ++u) {
+    const int gi = group_of[u];
+    if (gi < 0) {
+      out.push_back(units[u]);
+      continue;
+    }
+    if ((*groups)[gi].front() != (int)u) continue;
+    renum[gi] = (int)kept.size();
+    std::vector<int> members;
+    for (int v : (*groups)[gi]) members.push_back(units[v].beg);
+    kept.push_back(members);
+    out.push_back(Unit{units[u].beg, 1, renum[gi]});
+  }
+  *groups = kept;
+  return out;
+}
+
+// Scratch of a group: each member's intermediate at its own offset.
+template <typename T>
+size_t queue_scratch(const to_job* jobs, const std::vector<int>& members, bool backward,
+                     std::vector<size_t>* offsets) {
+  size_t total = 0;
+  for (int i : members) {
+    QueueKey key;
+    size_t bytes = 0;
+    queue_class<T>(jobs[i], backward, &key, &bytes);
+    if (offsets) offsets->push_back(total);
+    total += bytes;
+  }
+  return total;
+}
+
+// Forward (grads == nullptr) or adjoint propagation of a job-queue group.
+template <typename T>
+to_status run_queue(const to_job* jobs, const to_grad* grads, const std::vector<int>& members, DeviceCtx* c,
+                    Lane* ln, hipStream_t s) {
+  const bool bwd = grads != nullptr;
+  const bool dbl = sizeof(T) == 8;
+  std::vector<size_t> off;
+  const size_t total = queue_scratch<T>(jobs, members, bwd, &off);
+  to_status st = ensure_scratch(ln, total);
+  if (st != TO_OK) return st;
+  Geometry g0;
+  if ((st = make_geometry<T>(jobs[members[0]], false, &g0)) != TO_OK) return st;
+  QueueArgs<T> rf, ri;
+  ColQueueArgs<T> cq;
+  memset(&rf, 0, sizeof(rf));
+  memset(&ri, 0, sizeof(ri));
+  memset(&cq, 0, sizeof(cq));
+  rf.njobs = ri.njobs = cq.q.njobs = (int)members.size();
+  rf.lx = ri.lx = cq.q.lx = g0.lx;
+  rf.tc_shift = ri.tc_shift = cq.q.tc_shift = g0.tc_shift;
+  cq.q.tm = g0.tm;
+  cq.q.cpb = g0.tc;
+  ri.scale = (T)(1.0 / ((double)g0.lx * (double)g0.ly));
+  rf.tw = ri.tw = twiddles<T>(c, g0.lx);
+  cq.q.tw = twiddles<T>(c, g0.ly);
+  for (size_t k = 0; k < members.size(); ++k) {
+    const to_job& j = jobs[members[k]];
+    Geometry g;
+    if ((st = make_geometry<T>(j, false, &g)) != TO_OK) return st;
+    const int nf = (int)g.nfields;
+    cx<T>* scratch = (cx<T>*)((char*)ln->scratch + off[k]);
+    const int row_blocks = (j.ny + g.rows_per_block - 1) / g.rows_per_block;
+    TransferParams h = make_transfer(j, bwd);
+    hipError_t e = prepare_transfer<T>(j, ln, s, &h);  // takes the call's table; launches nothing here
+    if (e != hipSuccess) return hip_fail(e, "transfer table");
+    QueueJob<T> base;
+    memset(&base, 0, sizeof(base));
+    base.scratch = scratch;
+    base.ny = j.ny;
+    base.nx = j.nx;
+    base.nfields = nf;
+    rf.job[k] = base;
+    rf.job[k].in = (const cx<T>*)(bwd ? grads[members[k]].grad_out : j.in);
+    rf.job[k].fpb = row_fields_per_block(g, row_blocks, nf, false, dbl);
+    cq.q.job[k] = base;
+    cq.q.job[k].fpb = col_fields_per_block(g.lx / g.tc, nf, g.ly);
+    cq.h[k] = h;
+    ri.job[k] = base;
+    ri.job[k].out = (cx<T>*)(bwd ? grads[members[k]].grad_in : j.out);
+    ri.job[k].fpb = bwd ? nf : row_fields_per_block(g, row_blocks, nf, false, dbl);
+  }
+  const int cus = device_cus();
+  const QueueKey* kp = nullptr;
+  QueueKey key;
+  size_t bytes;
+  if (queue_class<T>(jobs[members[0]], bwd, &key, &bytes)) kp = &key;
+  if (!kp) return fail(TO_E_INVAL, "job-queue group of an ineligible job");
+  hipError_t e = timed(bwd ? "bwd.queue_row_fwd" : "fwd.queue_row_fwd", g0.lx, dbl, s,
+                       [&] { return QueueLaunch<T>::row_fwd(g0.lx, key.half_x, key.ex_x, rf, cus, s); });
+  if (e != hipSuccess) return hip_fail(e, "queue row_fwd launch");
+  e = timed(bwd ? "bwd.queue_col" : "fwd.queue_col", g0.ly, dbl, s,
+            [&] { return QueueLaunch<T>::col(g0.ly, key.half_y, key.ex_y, key.variant, cq, cus, s); });
+  if (e != hipSuccess) return hip_fail(e, "queue col launch");
+  e = timed(bwd ? "bwd.queue_row_inv" : "fwd.queue_row_inv", g0.lx, dbl, s,
+            [&] { return QueueLaunch<T>::row_inv(g0.lx, key.half_x, key.ex_x, bwd, ri, cus, s); });
+  if (e != hipSuccess) return hip_fail(e, "queue row_inv launch");
+  return TO_OK;
+}
+
 to_status plan_args(int32_t py, int32_t px, to_dtype dtype) {
   if (dtype != TO_C64 && dtype != TO_C128) return fail(TO_E_INVAL, "dtype must be TO_C64 or TO_C128");
   (void)py;
@@ -2183,49 +2397,79 @@ to_status to_propagate(const to_job* jobs, int32_t njobs, to_dtype dtype, void* 
   jobs = prepared.data();
   st = dtype == TO_C64 ? prepare_plain_jobs<float>(jobs, njobs, c, s) : prepare_plain_jobs<double>(jobs, njobs, c, s);
   if (st != TO_OK) return st;
-  // scheduling units: single jobs and chains of layers
-  std::vector<int> ubeg, ulen;
+  // scheduling units: single jobs, chains of layers, job-queue groups
+  std::vector<Unit> units;
   for (int i = 0; i < njobs;) {
     const int len = forward_chain_len(jobs, njobs, i, dtype);
-    ubeg.push_back(i);
-    ulen.push_back(len);
+    units.push_back(Unit{i, len, -1});
     i += len;
   }
-  const int nu = (int)ubeg.size();
+  const size_t relt = dtype == TO_C64 ? sizeof(float) : sizeof(double);
+  std::vector<std::vector<Span>> jrd(njobs), jwr(njobs);
+  for (int i = 0; i < njobs; ++i) {
+    const to_job& j = jobs[i];
+    const size_t fb = field_bytes(j, dtype);
+    jrd[i].push_back(span(j.in, fb));
+    jwr[i].push_back(span(j.out, fb));
+    element_spans(j, dtype, &jrd[i]);
+    if (has_loss(j)) {
+      jwr[i].push_back(span(j.epi_grad, fb));
+      jwr[i].push_back(span(j.epi_loss, sizeof(double)));
+    }
+    if (!pow2_grid(j)) jwr[i].push_back(Span{1, 2});  // the plain path's one workspace
+  }
+  std::vector<std::vector<int>> groups;
+  if (!env_no_queue()) {
+    // for grouping, an intensity accumulation counts as a write
+    std::vector<std::vector<Span>> jw = jwr;
+    for (int i = 0; i < njobs; ++i)
+      if (jobs[i].epi == TO_EPI_INTENSITY && jobs[i].batch > 0)
+        jw[i].push_back(span(jobs[i].epi_out, (size_t)jobs[i].batch * jobs[i].ny * jobs[i].nx * relt));
+    units = dtype == TO_C64 ? group_units<float>(jobs, units, false, jrd, jw, &groups)
+                            : group_units<double>(jobs, units, false, jrd, jw, &groups);
+  }
+  auto members = [&](int u) {
+    std::vector<int> m;
+    if (units[u].group >= 0) return groups[units[u].group];
+    for (int i = units[u].beg; i < units[u].beg + units[u].len; ++i) m.push_back(i);
+    return m;
+  };
+  const int nu = (int)units.size();
   std::vector<std::vector<Span>> rd(nu), wr(nu);
   std::vector<double> cost(nu, 0.0);
   std::vector<AccUse> acc;
-  const size_t relt = dtype == TO_C64 ? sizeof(float) : sizeof(double);
   for (int u = 0; u < nu; ++u) {
-    for (int i = ubeg[u]; i < ubeg[u] + ulen[u]; ++i) {
+    for (int i : members(u)) {
       const to_job& j = jobs[i];
-      const size_t fb = field_bytes(j, dtype);
-      rd[u].push_back(span(j.in, fb));
-      wr[u].push_back(span(j.out, fb));
-      element_spans(j, dtype, &rd[u]);
-      if (has_loss(j)) {
-        wr[u].push_back(span(j.epi_grad, fb));
-        wr[u].push_back(span(j.epi_loss, sizeof(double)));
-      }
+      rd[u].insert(rd[u].end(), jrd[i].begin(), jrd[i].end());
+      wr[u].insert(wr[u].end(), jwr[i].begin(), jwr[i].end());
       if (j.epi == TO_EPI_INTENSITY && j.batch > 0)
         acc.push_back({u, i, span(j.epi_out, (size_t)j.batch * j.ny * j.nx * relt)});
-      if (!pow2_grid(j)) wr[u].push_back(Span{1, 2});  // the plain path's one workspace
       cost[u] += job_cost(j);
     }
   }
   auto run = [&](int u, Lane* ln, hipStream_t ls) {
-    const to_job* js = jobs + ubeg[u];
+    const Unit& un = units[u];
+    if (un.group >= 0)
+      return dtype == TO_C64 ? run_queue<float>(jobs, nullptr, groups[un.group], c, ln, ls)
+                             : run_queue<double>(jobs, nullptr, groups[un.group], c, ln, ls);
+    const to_job* js = jobs + un.beg;
     if (!pow2_grid(*js))
       return dtype == TO_C64 ? run_forward_plain<float>(*js, c, ls) : run_forward_plain<double>(*js, c, ls);
-    if (ulen[u] > 1)
-      return dtype == TO_C64 ? run_forward_chain<float>(js, ulen[u], c, ln, ls)
-                             : run_forward_chain<double>(js, ulen[u], c, ln, ls);
+    if (un.len > 1)
+      return dtype == TO_C64 ? run_forward_chain<float>(js, un.len, c, ln, ls)
+                             : run_forward_chain<double>(js, un.len, c, ln, ls);
     return dtype == TO_C64 ? run_forward<float>(*js, c, ln, ls) : run_forward<double>(*js, c, ln, ls);
   };
   auto need = [&](int u, size_t* sb, size_t* pc) {
     *sb = 0;
     *pc = 0;
-    for (int i = ubeg[u]; i < ubeg[u] + ulen[u]; ++i) {
+    if (units[u].group >= 0) {
+      *sb = dtype == TO_C64 ? queue_scratch<float>(jobs, groups[units[u].group], false, nullptr)
+                            : queue_scratch<double>(jobs, groups[units[u].group], false, nullptr);
+      return;
+    }
+    for (int i : members(u)) {
       size_t a = 0, b = 0;
       if (dtype == TO_C64)
         workspace_need<float>(jobs[i], false, &a, &b);
@@ -2282,47 +2526,70 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
   jobs = prepared.data();
   st = dtype == TO_C64 ? prepare_plain_jobs<float>(jobs, njobs, c, s) : prepare_plain_jobs<double>(jobs, njobs, c, s);
   if (st != TO_OK) return st;
-  std::vector<int> ubeg, ulen;
+  std::vector<Unit> units;
   for (int i = 0; i < njobs;) {
     const int len = backward_chain_len(jobs, grads, njobs, i, dtype);
-    ubeg.push_back(i);
-    ulen.push_back(len);
+    units.push_back(Unit{i, len, -1});
     i += len;
   }
-  const int nu = (int)ubeg.size();
+  std::vector<std::vector<Span>> jrd(njobs), jwr(njobs);
+  for (int i = 0; i < njobs; ++i) {
+    const to_job& j = jobs[i];
+    const to_grad& g = grads[i];
+    const size_t fb = field_bytes(j, dtype);
+    const size_t rb = (size_t)j.ny * j.nx * (dtype == TO_C64 ? sizeof(float) : sizeof(double));
+    jrd[i].push_back(span(g.grad_out, fb));
+    jrd[i].push_back(span(g.saved_in, fb));
+    element_spans(j, dtype, &jrd[i]);
+    jwr[i].push_back(span(g.grad_in, fb));
+    jwr[i].push_back(span(g.grad_phase, rb));
+    jwr[i].push_back(span(g.grad_f, sizeof(double)));
+    if (!pow2_grid(j)) jwr[i].push_back(Span{1, 2});  // the plain path's one workspace
+  }
+  std::vector<std::vector<int>> groups;
+  if (!env_no_queue())
+    units = dtype == TO_C64 ? group_units<float>(jobs, units, true, jrd, jwr, &groups)
+                            : group_units<double>(jobs, units, true, jrd, jwr, &groups);
+  auto members = [&](int u) {
+    std::vector<int> m;
+    if (units[u].group >= 0) return groups[units[u].group];
+    for (int i = units[u].beg; i < units[u].beg + units[u].len; ++i) m.push_back(i);
+    return m;
+  };
+  const int nu = (int)units.size();
   std::vector<std::vector<Span>> rd(nu), wr(nu);
   std::vector<double> cost(nu, 0.0);
   for (int u = 0; u < nu; ++u) {
-    for (int i = ubeg[u]; i < ubeg[u] + ulen[u]; ++i) {
-      const to_job& j = jobs[i];
-      const to_grad& g = grads[i];
-      const size_t fb = field_bytes(j, dtype);
-      const size_t rb = (size_t)j.ny * j.nx * (dtype == TO_C64 ? sizeof(float) : sizeof(double));
-      rd[u].push_back(span(g.grad_out, fb));
-      rd[u].push_back(span(g.saved_in, fb));
-      element_spans(j, dtype, &rd[u]);
-      wr[u].push_back(span(g.grad_in, fb));
-      wr[u].push_back(span(g.grad_phase, rb));
-      wr[u].push_back(span(g.grad_f, sizeof(double)));
-      if (!pow2_grid(j)) wr[u].push_back(Span{1, 2});  // the plain path's one workspace
-      cost[u] += job_cost(j);
+    for (int i : members(u)) {
+      rd[u].insert(rd[u].end(), jrd[i].begin(), jrd[i].end());
+      wr[u].insert(wr[u].end(), jwr[i].begin(), jwr[i].end());
+      cost[u] += job_cost(jobs[i]);
     }
   }
   auto run = [&](int u, Lane* ln, hipStream_t ls) {
-    const int i = ubeg[u];
+    const Unit& un = units[u];
+    if (un.group >= 0)
+      return dtype == TO_C64 ? run_queue<float>(jobs, grads, groups[un.group], c, ln, ls)
+                             : run_queue<double>(jobs, grads, groups[un.group], c, ln, ls);
+    const int i = un.beg;
     if (!pow2_grid(jobs[i]))
       return dtype == TO_C64 ? run_backward_plain<float>(jobs[i], grads[i], c, ls)
                              : run_backward_plain<double>(jobs[i], grads[i], c, ls);
-    if (ulen[u] > 1)
-      return dtype == TO_C64 ? run_backward_chain<float>(jobs + i, grads + i, ulen[u], c, ln, ls)
-                             : run_backward_chain<double>(jobs + i, grads + i, ulen[u], c, ln, ls);
+    if (un.len > 1)
+      return dtype == TO_C64 ? run_backward_chain<float>(jobs + i, grads + i, un.len, c, ln, ls)
+                             : run_backward_chain<double>(jobs + i, grads + i, un.len, c, ln, ls);
     return dtype == TO_C64 ? run_backward<float>(jobs[i], grads[i], c, ln, ls)
                            : run_backward<double>(jobs[i], grads[i], c, ln, ls);
   };
   auto need = [&](int u, size_t* sb, size_t* pc) {
     *sb = 0;
     *pc = 0;
-    for (int i = ubeg[u]; i < ubeg[u] + ulen[u]; ++i) {
+    if (units[u].group >= 0) {
+      *sb = dtype == TO_C64 ? queue_scratch<float>(jobs, groups[units[u].group], true, nullptr)
+                            : queue_scratch<double>(jobs, groups[units[u].group], true, nullptr);
+      return;
+    }
+    for (int i : members(u)) {
       size_t a = 0, b = 0;
       if (dtype == TO_C64)
         workspace_need<float>(jobs[i], true, &a, &b);
@@ -2331,9 +2598,9 @@ to_status to_propagate_backward(const to_job* jobs, const to_grad* grads, int32_
       *sb = std::max(*sb, a);
       *pc = std::max(*pc, b);
     }
-    if (ulen[u] > 1) {
+    if (units[u].len > 1) {
       Geometry g;
-      const to_job& j0 = jobs[ubeg[u]];
+      const to_job& j0 = jobs[units[u].beg];
       if (dtype == TO_C64 && make_geometry<float>(j0, false, &g) == TO_OK)
         *pc = std::max(*pc, chain_bwd_partial_count<float>(j0, g));
       if (dtype == TO_C128 && make_geometry<double>(j0, false, &g) == TO_OK)

@@ -469,8 +469,8 @@ constexpr int row_lds_bytes() {
 constexpr int row_min_waves(int nc, int w) { return nc == 1 ? (w < 4 ? w : 4) : 1; }
 
 template <int TT>
-__device__ __forceinline__ int row_group() {
-  const int g = (int)threadIdx.x / TT;
+__device__ __forceinline__ int row_group(int tid = (int)threadIdx.x) {
+  const int g = tid / TT;
   if constexpr (TT >= 64) return __builtin_amdgcn_readfirstlane(g);
   return g;
 }
@@ -505,20 +505,22 @@ struct TileRow {
 // ---------------------------------------------------------------------------
 // row_fwd
 // ---------------------------------------------------------------------------
+// The body of a workgroup of the pass, at block (bx, by) of a grid gx
+// blocks wide, for thread `tid` of the workgroup: the kernel below runs it at
+// its own block index, the job-queue kernel at the index of each item it
+// takes (with an opaque copy of the thread index, so that nothing derived
+// from it is hoisted out of the item loop and held in registers).
 template <typename T, int L, int R, int G, bool HALF, int NC, bool EX>
-__global__ void __launch_bounds__(G * (L / R))
-    __attribute__((amdgpu_waves_per_eu(row_min_waves(NC, waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, false>())),
-                                       waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, false>()))))
-    row_fwd_kernel(RowFwdArgs<T> a) {
+__device__ __forceinline__ void row_fwd_body(RowFwdArgs<T> a, int bx, int by, int gx, int tid) {
   constexpr int TT = L / R;
   __shared__ cx<T> lds[G * lds_len<1>(L)];
   constexpr int RI = HALF ? R / 2 : R;  // registers that can hold a sample x < nx
-  const int g = row_group<TT>();
-  const int j = threadIdx.x % TT;
-  const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
+  const int g = row_group<TT>(tid);
+  const int j = tid % TT;
+  const int y = xcd_remap(bx, gx) * G + g;
   const bool rowok = y < a.ny;
   const int ny = a.ny, nx = a.nx;
-  const int f0 = blockIdx.y * a.fpb;
+  const int f0 = by * a.fpb;
   const int f1 = min(f0 + a.fpb, a.nfields);
   const TileRow<T, TT> tr(j, y, ny, a.tc_shift);
   const uint32_t row_vo = (uint32_t)((y * nx + j) * (int)sizeof(cx<T>));
@@ -622,6 +624,14 @@ __global__ void __launch_bounds__(G * (L / R))
   }
 }
 
+template <typename T, int L, int R, int G, bool HALF, int NC, bool EX>
+__global__ void __launch_bounds__(G * (L / R))
+    __attribute__((amdgpu_waves_per_eu(row_min_waves(NC, waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, false>())),
+                                       waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, false>()))))
+    row_fwd_kernel(RowFwdArgs<T> a) {
+  row_fwd_body<T, L, R, G, HALF, NC, EX>(a, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // col: forward FFT along y, transfer function, inverse FFT, crop rows.
 // ---------------------------------------------------------------------------
@@ -631,23 +641,20 @@ __global__ void __launch_bounds__(G * (L / R))
 // PF: the next field's column segment is loaded while the current one is
 // transformed (software pipeline over the block's fields).
 template <typename T, int L, int R, int TC, bool HALF, bool EX, bool PF>
-__global__ void __launch_bounds__(TC * (L / R))
-    __attribute__((amdgpu_waves_per_eu(PF ? waves_per_simd(TC * (L / R), lds_len<TC>(L) * TC * (int)sizeof(cx<T>)) : 1,
-                                       waves_per_simd(TC * (L / R), lds_len<TC>(L) * TC * (int)sizeof(cx<T>)))))
-    col_kernel(ColArgs<T> a) {
+__device__ __forceinline__ void col_body(ColArgs<T> a, int bx, int by, int gx, int tid) {
   constexpr int TT = L / R;
   __shared__ cx<T> lds[lds_len<TC>(L) * TC];
-  const int c = threadIdx.x % TC;
-  const int j = threadIdx.x / TC;
+  const int c = tid % TC;
+  const int j = tid / TC;
   // The scratch layout stores column tiles `tm` bins wide (a full cache line
   // per row segment); a block transforms `cpb` (<= TC) of them.  Blocks that
   // share a tile get consecutive logical indices, hence the same XCD and L2.
-  const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int lb = xcd_remap(bx, gx);
   const int tm = a.tm, cpb = a.cpb;
   const int per = tm / cpb;
   const int tile = lb / per, h = lb - tile * per;
   const int ny = a.ny;
-  const int f_begin = (int)blockIdx.y * a.fpc;
+  const int f_begin = by * a.fpc;
   const int f_end = min(f_begin + a.fpc, a.nfields);
   const bool active = c < cpb;
 
@@ -738,6 +745,14 @@ __global__ void __launch_bounds__(TC * (L / R))
   }
 }
 
+template <typename T, int L, int R, int TC, bool HALF, bool EX, bool PF>
+__global__ void __launch_bounds__(TC * (L / R))
+    __attribute__((amdgpu_waves_per_eu(PF ? waves_per_simd(TC * (L / R), lds_len<TC>(L) * TC * (int)sizeof(cx<T>)) : 1,
+                                       waves_per_simd(TC * (L / R), lds_len<TC>(L) * TC * (int)sizeof(cx<T>)))))
+    col_kernel(ColArgs<T> a) {
+  col_body<T, L, R, TC, HALF, EX, PF>(a, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Block reduction of one double per thread (fixed order: deterministic).
 // ---------------------------------------------------------------------------
@@ -780,10 +795,7 @@ __device__ __forceinline__ double group_sum(double v, double* red) {
 //     by one thread in a fixed order.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int R, int G, bool HALF, int NC, bool BWD, bool EX>
-__global__ void __launch_bounds__(G * (L / R))
-    __attribute__((amdgpu_waves_per_eu(row_min_waves(NC, waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, true>())),
-                                       waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, true>()))))
-    row_inv_kernel(RowInvArgs<T> a) {
+__device__ __forceinline__ void row_inv_body(RowInvArgs<T> a, int bx, int by, int gx, int tid) {
   constexpr bool kBwd = BWD;
   constexpr int TT = L / R;
   constexpr int NT = G * TT;
@@ -791,9 +803,9 @@ __global__ void __launch_bounds__(G * (L / R))
   constexpr uint32_t CB = sizeof(cx<T>), RB = sizeof(T);
   __shared__ cx<T> lds[G * lds_len<1>(L)];
   __shared__ double red[NT];
-  const int g = row_group<TT>();
-  const int j = threadIdx.x % TT;
-  const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
+  const int g = row_group<TT>(tid);
+  const int j = tid % TT;
+  const int y = xcd_remap(bx, gx) * G + g;
   const int ny = a.ny, nx = a.nx;
   const bool rowok = y < ny;
   const TileRow<T, TT> tr(j, y, ny, a.tc_shift);
@@ -807,7 +819,7 @@ __global__ void __launch_bounds__(G * (L / R))
   auto xin = [&](int m) { return EX || j + m * TT < nx; };
   // Backward: one block owns its rows' parameter gradients, so it loops over
   // every field of the chunk; forward: `fpb` fields per block.
-  const int f_begin = kBwd ? 0 : (int)blockIdx.y * a.fpb;
+  const int f_begin = kBwd ? 0 : by * a.fpb;
   const int f_end = kBwd ? a.nfields : min(f_begin + a.fpb, a.nfields);
   // One field component's scratch row (tile layout); zeros past the field.
   auto load_row = [&](int f, int c, cx<T> (&dst)[R]) {
@@ -966,6 +978,152 @@ __global__ void __launch_bounds__(G * (L / R))
       if (rowok && j == 0) a.lens_partial[y] = s;
     }
   }
+}
+
+template <typename T, int L, int R, int G, bool HALF, int NC, bool BWD, bool EX>
+__global__ void __launch_bounds__(G * (L / R))
+    __attribute__((amdgpu_waves_per_eu(row_min_waves(NC, waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, true>())),
+                                       waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, true>()))))
+    row_inv_kernel(RowInvArgs<T> a) {
+  row_inv_body<T, L, R, G, HALF, NC, BWD, EX>(a, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Job-queue launches.  One launch of a pass serves up to kQueueJobs
+// independent propagations of one shape class (same padded lengths, pruning
+// and kernel configuration; scalar fields, no element, no epilogue).  Each
+// job contributes the workgroups of its own grid as items, numbered job
+// after job; the launch holds at most as many workgroups as are resident at
+// once, and each walks the items in strides of the grid size.  An item runs
+// exactly the workgroup of the job's own launch at that block index, so the
+// results equal those of the per-job launches bit for bit.  The job records
+// travel in the kernel arguments: nothing is uploaded, and a launch captured
+// in a graph carries its own copy.
+// ---------------------------------------------------------------------------
+constexpr int kQueueJobs = 16;
+
+template <typename T>
+struct QueueJob {
+  const cx<T>* in;   // row_fwd: the field (or gradient) read
+  cx<T>* out;        // row_inv: the field written (null: not formed)
+  cx<T>* scratch;    // the job's padded intermediate, [field][LX/tm][ny][tm]
+  int ny, nx;
+  int nfields;
+  int fpb;           // fields per workgroup of this pass (col: per column block)
+  int first;         // first item; the job owns items first .. first + gx gy - 1
+  int gx, gy;        // the job's grid of this pass
+};
+
+template <typename T>
+struct QueueArgs {
+  int njobs;
+  int items;         // one past the last job's last item
+  int lx;            // padded row length
+  int tc_shift;      // log2 of the scratch tile width
+  int tm, cpb;       // column pass: scratch tile width, columns per workgroup
+  T scale;           // row_inv: 1 / (LX LY)
+  const cx<T>* tw;   // twiddles of this pass's transform length
+  QueueJob<T> job[kQueueJobs];
+};
+
+template <typename T>
+struct ColQueueArgs {
+  QueueArgs<T> q;
+  TransferParams h[kQueueJobs];  // per job (adjoint: conj set)
+};
+
+// Runs body(k, bx, by, tid) for the items of this workgroup: blockIdx.x,
+// blockIdx.x + gridDim.x, ...  Items in the alignment gap after a job's grid
+// are skipped.  Every value involved is uniform over the workgroup.
+template <typename T, typename F>
+__device__ __forceinline__ void queue_walk(const QueueArgs<T>& q, F&& body) {
+  int k = 0;
+#pragma unroll 1
+  for (int it = (int)blockIdx.x; it < q.items; it += (int)gridDim.x) {
+    while (k + 1 < q.njobs && it >= q.job[k + 1].first) ++k;
+    const int local = it - q.job[k].first;
+    const int by = local / q.job[k].gx;
+    if (by >= q.job[k].gy) continue;
+    __syncthreads();  // the previous item's LDS reads are complete
+    // The item's thread index, opaque to the compiler: what the body derives
+    // from it is recomputed per item instead of being hoisted out of the
+    // item loop and held in registers across it.
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    body(k, local - by * q.job[k].gx, by, tid);
+  }
+}
+
+template <typename T, int L, int R, int G, bool HALF, bool EX>
+__global__ void __launch_bounds__(G * (L / R))
+    __attribute__((amdgpu_waves_per_eu(row_min_waves(1, waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, false>())),
+                                       waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, false>()))))
+    row_fwd_queue_kernel(QueueArgs<T> q) {
+  queue_walk(q, [&](int k, int bx, int by, int tid) {
+    const QueueJob<T>& jb = q.job[k];
+    RowFwdArgs<T> a{};
+    a.in = jb.in;
+    a.scratch = jb.scratch;
+    a.in_stride = (int64_t)jb.ny * jb.nx;
+    a.comp_stride = a.in_stride;
+    a.s_stride = (int64_t)q.lx * jb.ny;
+    a.ny = jb.ny;
+    a.nx = jb.nx;
+    a.tc_shift = q.tc_shift;
+    a.nfields = jb.nfields;
+    a.fpb = jb.fpb;
+    a.tw = q.tw;
+    row_fwd_body<T, L, R, G, HALF, 1, EX>(a, bx, by, jb.gx, tid);
+  });
+}
+
+template <typename T, int L, int R, int TC, bool HALF, bool EX, bool PF>
+__global__ void __launch_bounds__(TC * (L / R))
+    __attribute__((amdgpu_waves_per_eu(PF ? waves_per_simd(TC * (L / R), lds_len<TC>(L) * TC * (int)sizeof(cx<T>)) : 1,
+                                       waves_per_simd(TC * (L / R), lds_len<TC>(L) * TC * (int)sizeof(cx<T>)))))
+    col_queue_kernel(ColQueueArgs<T> cq) {
+  const QueueArgs<T>& q = cq.q;
+  queue_walk(q, [&](int k, int bx, int by, int tid) {
+    const QueueJob<T>& jb = q.job[k];
+    ColArgs<T> a;
+    a.scratch = jb.scratch;
+    a.s_stride = (int64_t)q.lx * jb.ny;
+    a.ny = jb.ny;
+    a.lx = q.lx;
+    a.tm = q.tm;
+    a.cpb = q.cpb;
+    a.nfields = jb.nfields;
+    a.fpc = jb.fpb;
+    a.h = cq.h[k];
+    a.tw = q.tw;
+    col_body<T, L, R, TC, HALF, EX, PF>(a, bx, by, jb.gx, tid);
+  });
+}
+
+template <typename T, int L, int R, int G, bool HALF, bool BWD, bool EX>
+__global__ void __launch_bounds__(G * (L / R))
+    __attribute__((amdgpu_waves_per_eu(row_min_waves(1, waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, true>())),
+                                       waves_per_simd(G * (L / R), row_lds_bytes<T, L, R, G, true>()))))
+    row_inv_queue_kernel(QueueArgs<T> q) {
+  queue_walk(q, [&](int k, int bx, int by, int tid) {
+    const QueueJob<T>& jb = q.job[k];
+    RowInvArgs<T> a{};
+    a.scratch = jb.scratch;
+    a.s_stride = (int64_t)q.lx * jb.ny;
+    a.comp_stride = (int64_t)jb.ny * jb.nx;
+    a.out = jb.out;
+    a.out_stride = a.comp_stride;
+    a.ny = jb.ny;
+    a.nx = jb.nx;
+    a.tc_shift = q.tc_shift;
+    a.nfields = jb.nfields;
+    a.scale = q.scale;
+    a.tw = q.tw;
+    a.epi = EPI_NONE;
+    a.backward = BWD ? 1 : 0;
+    a.fpb = jb.fpb;
+    row_inv_body<T, L, R, G, HALF, 1, BWD, EX>(a, bx, by, jb.gx, tid);
+  });
 }
 
 // ---------------------------------------------------------------------------
