@@ -35,6 +35,7 @@ VALU_FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published (packed FP32 FMA)
 # The library is built without packed FP32 instructions: each lane retires
 # one FP32 FMA per cycle, 256 CU x 64 lanes x 2 flop x 2.4 GHz.
 VALU_FP32_NONPACKED_TFLOPS = 78.6
+VALU_FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector, published
 
 
 def parse():
@@ -124,15 +125,14 @@ def fft_flops(L: int) -> float:
     return 5.0 * L * math.log2(L)
 
 
-def kernel_model(name: str, wl, chunk_fields: int):
+def kernel_model(name: str, wl, chunk_fields: int, c: int = 8):
     """Algorithmic bytes and flops of ONE launch of a propagation kernel for
-    this workload (c64, N x N field, P x P padded, `chunk_fields` fields per
-    launch).  Bytes are what the kernel must read and write in the 3-pass
+    this workload (N x N field, P x P padded, `chunk_fields` fields per
+    launch, `c` bytes per complex value: 8 for c64, 16 for c128).  Bytes are what the kernel must read and write in the 3-pass
     decomposition (field in/out, the N x P intermediate in/out, masks and
     gradients); flops count 5 L log2 L per length-L FFT plus 6 per complex
     multiply."""
     N, P = wl["n"], wl["padded"]
-    c = 8  # bytes per complex64
     f = chunk_fields
     if ".row_fwd_" in name:
         by = f * (N * N * c + N * P * c) + (N * N * 4 if name.startswith("fwd") else 0)
@@ -694,7 +694,10 @@ def run_anylength(args):
         "hbm_roofline_step": {"algorithmic_bytes": step_bytes,
                               "frac": round(step_bytes / (ms / 1000.0) / (HBM_PEAK_GBS * 1e9), 5)},
         "bluestein_2002": res["2002"], "pow2_2048": res["2048"], "paper_examples_native_padding": native,
-        "roofline": None, "cpu_baseline": None}))
+        "roofline": None, "cpu_baseline": None,
+        "not_measured": "roofline: the unfused mixed-radix passes have no per-launch model here; cpu_baseline: "
+                        "the oracle transforms extents that are not powers of two with its O(n^2) DFT, meant "
+                        "for small grids"}))
     return 0
 
 
@@ -720,7 +723,46 @@ def _timed(step, steps, warmup):
     torch.cuda.synchronize()
     prof = _capi.profile_end()
     top = sorted(prof.items(), key=lambda kv: -kv[1][1])[:3]
+    _timed.last_profile = prof
     return ms, {k: {"launches": n, "avg_us": round(1000.0 * t / n, 2)} for k, (n, t) in top}
+
+
+def model_roofline(prof, n, padded, fields_per_launch, c=8):
+    """Roofline entry of the kernel with the largest GPU time in `prof` (one
+    profiled step: name -> (launches, total ms)) among those `kernel_model`
+    covers: N x N fields padded to P x P, `fields_per_launch(name, launches)`
+    fields per launch, `c` bytes per complex value.  complex128 kernels are
+    priced against the FP64 vector peak, complex64 ones against FP32."""
+    best = None
+    for name, (cnt, ms) in prof.items():
+        if cnt <= 0:
+            continue
+        f = fields_per_launch(name, cnt)
+        m = kernel_model(name, {"n": n, "padded": padded}, f, c) if f else None
+        if m and (best is None or ms > best[0]):
+            best = (ms, name, cnt, f, m)
+    if best is None:
+        return None
+    ms, name, cnt, f, (by, fl) = best
+    avg_s = ms / cnt / 1000.0
+    gbs, tfs = by / avg_s / 1e9, fl / avg_s / 1e12
+    peak = VALU_FP64_PEAK_TFLOPS if c == 16 else VALU_FP32_PEAK_TFLOPS
+    return {"bound": "alu", "achieved": round(tfs, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(tfs / peak, 4), "traffic": None, "kernel": name, "avg_us": round(avg_s * 1e6, 2),
+            "fields_per_launch": f, "algorithmic_bytes_per_launch": int(by), "flops_per_launch": int(fl),
+            "hbm_view": {"achieved_GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+
+
+def _oracle_rate(fn, units, budget_s):
+    """Runs fn() (one unit of `units` propagations) until `budget_s` of wall
+    time have passed (at least once); returns (units / s, runs, seconds)."""
+    runs, t0 = 0, time.perf_counter()
+    while True:
+        fn()
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            return units * runs / el, runs, el
 
 
 def run_suite(args):
@@ -750,7 +792,27 @@ def run_suite(args):
     def gauss():
         tp.propagate_jobs([u, mid], [o1, o2], outs=[mid, out], elements=[{}, {"lens_f": g.f}])
     ms, top = _timed(gauss, max(args.steps, 20), args.warmup)
-    res["gaussian_lens_256_c128"] = {"ms_per_step": round(ms, 4), "propagations_per_step": 2, "kernels": top}
+    res["gaussian_lens_256_c128"] = {
+        "ms_per_step": round(ms, 4), "propagations_per_step": 2, "propagations_per_s": round(2 / (ms / 1000.0), 1),
+        "kernels": top,
+        "roofline": model_roofline(_timed.last_profile, g.n, 2 * g.n, lambda name, cnt: 1, c=16)}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        u_h = g.field()
+        lens = oracle.lens(g.n, g.n, g.d, g.d, g.wavelength, g.f)
+
+        def gauss_oracle():
+            a = oracle.propagate(u_h, g.d, g.d, g.wavelength, g.z1, oracle.ASM, g.pad)
+            return oracle.propagate(a * lens, g.d, g.d, g.wavelength, g.z2, oracle.ASM, g.pad)
+        rate, runs, secs = _oracle_rate(gauss_oracle, 2, 2.0)
+        got = out.cpu().numpy()
+        exp = gauss_oracle()
+        res["gaussian_lens_256_c128"]["error_vs_oracle"] = float(
+            f"{np.linalg.norm(got - exp) / np.linalg.norm(exp):.3e}")
+        res["gaussian_lens_256_c128"]["cpu_baseline"] = {
+            "value": round(rate, 2), "unit": "propagations/s", "cores": host_threads(), "kind": "oracle",
+            "sample": f"the whole step (z1, lens, z2) in FP64, {runs} runs in {secs:.1f} s"}
 
     w = workloads.PolarizedWorkload()
     E = torch.from_numpy(w.field()).to(dev)
@@ -772,8 +834,32 @@ def run_suite(args):
         tp.propagate_backward_jobs(list(grads), opts, saved_ins=list(E), grad_ins=[None] * K, grad_fs=list(gfs),
                                    elements=[dict(jones=J, lens_f=w.f)] * K, ncomp=3)
     ms, top = _timed(polarized, args.steps, args.warmup)
-    res["polarized_8x3x2048_c64"] = {"ms_per_step": round(ms, 3), "propagations_per_step": 2 * 3 * K,
-                                     "propagations_per_s": round(2 * 3 * K / (ms / 1000.0), 1), "kernels": top}
+    res["polarized_8x3x2048_c64"] = {
+        "ms_per_step": round(ms, 3), "propagations_per_step": 2 * 3 * K,
+        "propagations_per_s": round(2 * 3 * K / (ms / 1000.0), 1), "kernels": top,
+        # every launch of a job covers its three components
+        "roofline": model_roofline(_timed.last_profile, w.n, 2 * w.n, lambda name, cnt: 3)}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        J_h = np.array(J, dtype=np.complex128)
+        E0 = E[0].cpu().numpy().astype(np.complex128)
+        lam0 = float(w.wavelengths[0])
+        lens0 = oracle.lens(w.n, w.n, w.d, w.d, lam0, w.f)
+
+        def pol_oracle():
+            m = oracle.jones_apply(E0, J_h) * lens0
+            return oracle.propagate(m, w.d, w.d, lam0, w.z, oracle.FRESNEL, w.pad)
+        print("[bench] polarized: FP64 oracle on one wavelength", file=sys.stderr, flush=True)
+        rate, runs, secs = _oracle_rate(pol_oracle, 3, 3.0)
+        exp = pol_oracle()
+        got = outs[0].cpu().numpy()
+        res["polarized_8x3x2048_c64"]["error_vs_oracle"] = {
+            "wavelength_0_field": float(f"{np.linalg.norm(got - exp) / np.linalg.norm(exp):.3e}")}
+        res["polarized_8x3x2048_c64"]["cpu_baseline"] = {
+            "value": round(rate, 3), "unit": "propagations/s", "cores": host_threads(), "kind": "oracle",
+            "sample": f"one wavelength forward (Jones, lens, three Fresnel component propagations of "
+                      f"{w.n}^2 on {2 * w.n}^2) in FP64, {runs} runs in {secs:.1f} s"}
     del E, outs, grads
 
     c = workloads.CoherenceWorkload()
@@ -791,9 +877,27 @@ def run_suite(args):
         tp.coherence_propagate(gG, oc, adjoint=True, saved_in=G0, grad_phase=gphi, phase=pg, lens_f=c.f)
     ms, top = _timed(coherence, args.steps, args.warmup)
     slices = 4 * n * n
+    prof = _timed.last_profile
+    # the step's slice propagations split evenly over the launches of a pass
+    col_launches = sum(cnt for name, (cnt, _) in prof.items() if ".col_" in name)
+
+    def coh_fields(name, cnt):
+        return slices // col_launches if col_launches and slices % col_launches == 0 else None
     res["gaussian_schell_64^4_c64"] = {"ms_per_step": round(ms, 3), "slice_propagations_per_step": slices,
                                         "slice_propagations_per_s": round(slices / (ms / 1000.0), 1),
-                                        "kernels": top}
+                                        "kernels": top,
+                                        "roofline": model_roofline(prof, n, 2 * n, coh_fields)}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        G_h = c.gamma().astype(np.complex128)
+        print("[bench] coherence: FP64 oracle on the 64^4 forward propagation", file=sys.stderr, flush=True)
+        rate, runs, secs = _oracle_rate(
+            lambda: oracle.coherence_propagate(G_h, c.d, c.d, c.wavelength, c.z, oracle.ASM, c.pad), 2 * n * n, 2.0)
+        res["gaussian_schell_64^4_c64"]["cpu_baseline"] = {
+            "value": round(rate, 1), "unit": "slice propagations/s", "cores": host_threads(), "kind": "oracle",
+            "sample": f"the unmodulated forward 4-D propagation ({2 * n * n} slice propagations of {n}^2 on "
+                      f"{2 * n}^2) in FP64, {runs} runs in {secs:.1f} s"}
     del G0
 
     res["uneven_128_jobs_c64"] = run_uneven(args, dev)
