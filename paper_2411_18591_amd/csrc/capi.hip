@@ -853,6 +853,69 @@ hipError_t launch_col(const char* phase, const Geometry& g, const ColArgs<T>& ca
   });
 }
 
+// Row passes of a job without element (forward row_inv: nor epilogue)
+// through the job-queue kernels, with one job and one workgroup per block:
+// the per-job passes with the element and epilogue branches folded away
+// (fewer registers; no spills at 4096 and 8192 points).  The records must
+// have the scalar-field layout those kernels assume.
+template <typename T>
+bool row_fwd_plain(const Geometry& g, int nc, const RowFwdArgs<T>& ra) {
+  const int64_t npix = (int64_t)ra.ny * ra.nx;
+  return nc == 1 && ra.el.flags == 0 && !ra.coh_m && ra.in_stride == npix && ra.comp_stride == npix &&
+         ra.s_stride == (int64_t)g.lx * ra.ny && queue_row_len_ok(g.lx);
+}
+
+template <typename T>
+bool row_inv_plain(const Geometry& g, int nc, const RowInvArgs<T>& ia) {
+  const int64_t npix = (int64_t)ia.ny * ia.nx;
+  return nc == 1 && ia.el.flags == 0 && ia.epi == TO_EPI_NONE && !ia.lens_partial && ia.out_stride == npix &&
+         ia.comp_stride == npix && ia.s_stride == (int64_t)g.lx * ia.ny && queue_row_len_ok(g.lx);
+}
+
+template <typename T>
+QueueArgs<T> plain_args(const Geometry& g, const cx<T>* tw, const cx<T>* in, cx<T>* out, const cx<T>* scratch,
+                        int ny, int nx, int nf, int fpb) {
+  QueueArgs<T> q;
+  memset(&q, 0, sizeof(q));
+  q.njobs = 1;
+  q.lx = g.lx;
+  q.tc_shift = g.tc_shift;
+  q.scale = (T)(1.0 / ((double)g.lx * (double)g.ly));
+  q.tw = tw;
+  q.job[0].in = in;
+  q.job[0].out = out;
+  q.job[0].scratch = const_cast<cx<T>*>(scratch);
+  q.job[0].ny = ny;
+  q.job[0].nx = nx;
+  q.job[0].nfields = nf;
+  q.job[0].fpb = fpb > 0 ? fpb : 1;
+  return q;
+}
+
+template <typename T>
+hipError_t launch_row_fwd_any(const char* phase, const Geometry& g, int ny, int nf, int nc, const RowFwdArgs<T>& ra,
+                              hipStream_t s) {
+  if (!row_fwd_plain<T>(g, nc, ra)) return launch_row_fwd<T>(phase, g, ny, nf, nc, ra, s);
+  QueueArgs<T> q = plain_args<T>(g, ra.tw, ra.in, nullptr, ra.scratch, ra.ny, ra.nx, nf, ra.fpb);
+  const bool exact = ra.nx == (g.half_x ? g.lx / 2 : g.lx);
+  return timed(phase, g.lx, sizeof(T) == 8, s,
+               [&] { return QueueLaunch<T>::row_fwd(g.lx, g.half_x, exact, q, 0, s); });
+}
+
+template <typename T>
+hipError_t launch_row_inv_any(const char* phase, const Geometry& g, int nc, int nblocks_y, const RowInvArgs<T>& ia,
+                              hipStream_t s) {
+  const bool dbl = sizeof(T) == 8;
+  if (!row_inv_plain<T>(g, nc, ia))
+    return timed(phase, g.lx, dbl, s,
+                 [&] { return Launch<T>::row_inv(g.lx, g.half_x, nc, ia.ny, nblocks_y, ia, s); });
+  QueueArgs<T> q = plain_args<T>(g, ia.tw, nullptr, ia.out, ia.scratch, ia.ny, ia.nx, ia.nfields, ia.fpb);
+  q.scale = ia.scale;
+  const bool exact = ia.nx == (g.half_x ? g.lx / 2 : g.lx);
+  return timed(phase, g.lx, dbl, s,
+               [&] { return QueueLaunch<T>::row_inv(g.lx, g.half_x, exact, ia.backward != 0, q, 0, s); });
+}
+
 // Forward row_inv with the job's epilogue, then the loss reduction.
 template <typename T>
 to_status finish_forward_chunk(const to_job& j, const Geometry& g, DeviceCtx* c, Lane* ln, cx<T>* scratch,
@@ -871,9 +934,7 @@ to_status finish_forward_chunk(const to_job& j, const Geometry& g, DeviceCtx* c,
   const int inv_blocks_y = (nf + ia.fpb - 1) / ia.fpb;
   ia.el = make_element<T>(j, 0);
   const bool dbl = sizeof(T) == 8;
-  hipError_t e = timed("fwd.row_inv", g.lx, dbl, s, [&] {
-    return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, inv_blocks_y, ia, s);
-  });
+  hipError_t e = launch_row_inv_any<T>("fwd.row_inv", g, g.nc_kernel, inv_blocks_y, ia, s);
   if (e != hipSuccess) return hip_fail(e, "row_inv launch");
   if (has_loss(j)) {
     e = timed("fwd.loss_reduce", 0, dbl, s, [&] {
@@ -900,8 +961,7 @@ to_status finish_backward_chunk(const to_job& j, const to_grad& gr, const Geomet
   ia.lens_f = j.el_f;
   ia.lens_partial = want_f ? ln->partial : nullptr;
   const bool dbl = sizeof(T) == 8;
-  hipError_t e = timed("bwd.row_inv", g.lx, dbl, s,
-                       [&] { return Launch<T>::row_inv(g.lx, g.half_x, g.nc_kernel, j.ny, 1, ia, s); });
+  hipError_t e = launch_row_inv_any<T>("bwd.row_inv", g, g.nc_kernel, 1, ia, s);
   if (e != hipSuccess) return hip_fail(e, "row_inv launch");
   if (want_f) {
     e = timed("bwd.lens_reduce", 0, dbl, s,
@@ -945,7 +1005,7 @@ to_status run_forward(const to_job& j, DeviceCtx* c, Lane* ln, hipStream_t s, bo
     const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
     RowFwdArgs<T> ra = row_fwd_args<T>(j, g, c, scratch, (const cx<T>*)j.in + f0 * g.in_stride, g.in_stride, nf,
                                        el, coh_m, f0);
-    if ((e = launch_row_fwd<T>("fwd.row_fwd", g, j.ny, nf, g.nc_kernel, ra, s)) != hipSuccess)
+    if ((e = launch_row_fwd_any<T>("fwd.row_fwd", g, j.ny, nf, g.nc_kernel, ra, s)) != hipSuccess)
       return hip_fail(e, "row_fwd launch");
     if ((e = launch_col<T>("fwd.col", g, col_args<T>(j, g, c, scratch, nf * g.nc_kernel, h), s)) != hipSuccess)
       return hip_fail(e, "col launch");
@@ -978,7 +1038,7 @@ to_status run_backward(const to_job& j, const to_grad& gr, DeviceCtx* c, Lane* l
     const int flat = nf * g.nc_kernel;
     RowFwdArgs<T> ra = row_fwd_args<T>(j, g, c, scratch, (const cx<T>*)gr.grad_out + f0 * g.in_stride,
                                        g.comp_stride, flat, none, nullptr, 0);
-    if ((e = launch_row_fwd<T>("bwd.row_fwd", g, j.ny, flat, 1, ra, s)) != hipSuccess)
+    if ((e = launch_row_fwd_any<T>("bwd.row_fwd", g, j.ny, flat, 1, ra, s)) != hipSuccess)
       return hip_fail(e, "row_fwd launch");
     if ((e = launch_col<T>("bwd.col", g, col_args<T>(j, g, c, scratch, flat, h), s)) != hipSuccess)
       return hip_fail(e, "col launch");
@@ -1080,7 +1140,7 @@ to_status run_forward_chain(const to_job* jobs, int n, DeviceCtx* c, Lane* ln, h
     const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
     RowFwdArgs<T> ra = row_fwd_args<T>(j0, g, c, scratch, (const cx<T>*)j0.in + f0 * g.in_stride, g.in_stride,
                                        nf, el[0], nullptr, f0);
-    if ((e = launch_row_fwd<T>("fwd.row_fwd", g, j0.ny, nf, 1, ra, s)) != hipSuccess)
+    if ((e = launch_row_fwd_any<T>("fwd.row_fwd", g, j0.ny, nf, 1, ra, s)) != hipSuccess)
       return hip_fail(e, "row_fwd launch");
     if ((e = launch_col<T>("fwd.col", g, col_args<T>(j0, g, c, scratch, nf, h[0]), s)) != hipSuccess)
       return hip_fail(e, "col launch");
@@ -1155,7 +1215,7 @@ to_status run_backward_chain(const to_job* jobs, const to_grad* grads, int n, De
     const int nf = (int)std::min<int64_t>(g.chunk, g.nfields - f0);
     RowFwdArgs<T> ra = row_fwd_args<T>(j0, g, c, scratch, (const cx<T>*)grads[0].grad_out + f0 * g.in_stride,
                                        g.comp_stride, nf, none, nullptr, 0);
-    if ((e = launch_row_fwd<T>("bwd.row_fwd", g, j0.ny, nf, 1, ra, s)) != hipSuccess)
+    if ((e = launch_row_fwd_any<T>("bwd.row_fwd", g, j0.ny, nf, 1, ra, s)) != hipSuccess)
       return hip_fail(e, "row_fwd launch");
     if ((e = launch_col<T>("bwd.col", g, col_args<T>(j0, g, c, scratch, nf, h[0]), s)) != hipSuccess)
       return hip_fail(e, "col launch");

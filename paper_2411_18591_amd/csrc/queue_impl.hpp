@@ -39,18 +39,21 @@ static int queue_blocks_per_cu(const void* kernel, int threads) {
 template <typename A>
 static hipError_t queue_go(const void* kernel, A& args, int threads, int items, int cus, hipStream_t s) {
   if (items <= 0) return hipSuccess;
-  int grid = std::min(items, queue_blocks_per_cu(kernel, threads) * std::max(cus, 1));
-  if (grid > 8) grid &= ~7;
+  int grid = items;
+  if (cus > 0) {
+    grid = std::min(items, queue_blocks_per_cu(kernel, threads) * cus);
+    if (grid > 8) grid &= ~7;
+  }
   void* kargs[] = {&args};
   return hipLaunchKernel(kernel, dim3(grid), dim3(threads), kargs, 0, s);
 }
 
 template <typename T>
 hipError_t QueueLaunch<T>::row_fwd(int lx, bool half, bool exact, QueueArgs<T>& q, int cus, hipStream_t s) {
-  if (!queue_len_ok(lx)) return hipErrorInvalidValue;
+  if (!queue_row_len_ok(lx)) return hipErrorInvalidValue;
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    if constexpr (L < kQueueMinLen || L > kQueueMaxLen) {
+    if constexpr (L < kQueueMinLen || L > kQueueRowMaxLen) {
       return hipErrorInvalidValue;
     } else {
       using C = RowCfg<T, L>;
@@ -112,10 +115,10 @@ hipError_t QueueLaunch<T>::col(int ly, bool half, bool exact, int variant, ColQu
 template <typename T>
 hipError_t QueueLaunch<T>::row_inv(int lx, bool half, bool exact, bool bwd, QueueArgs<T>& q, int cus,
                                    hipStream_t s) {
-  if (!queue_len_ok(lx)) return hipErrorInvalidValue;
+  if (!queue_row_len_ok(lx)) return hipErrorInvalidValue;
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    if constexpr (L < kQueueMinLen || L > kQueueMaxLen) {
+    if constexpr (L < kQueueMinLen || L > kQueueRowMaxLen) {
       return hipErrorInvalidValue;
     } else {
       hipError_t e = hipSuccess;
