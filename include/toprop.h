@@ -298,7 +298,7 @@ to_status to_propagate_backward_plain(const to_job* jobs, const to_grad* grads, 
                                       to_dtype dtype, void* stream);
 
 /* Launch schedule of one padded grid and dtype: the column-pass
- * configuration (0 .. 3: LDS budget, points per thread and prefetch of the
+ * configuration (0 .. 4: LDS budget, points per thread and prefetch of the
  * column FFT) and the budget of padded intermediate per chunk of fields
  * [MiB].                                                                   */
 typedef struct to_plan {
@@ -323,13 +323,13 @@ typedef struct to_plan {
  * `result` (may be NULL) receives the chosen plan.
  * Precedence when a job runs: TOPROP_COL_VARIANT / TOPROP_CHUNK_MB /
  * TOPROP_ROW_FPB (tuning overrides) > plan table > built-in defaults (variant 1; variant 0 for
- * complex64 columns of 4096 points and more; 128 MiB).                     */
+ * complex64 columns of 4096 points, variant 4 for those of 8192; 128 MiB).                     */
 to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* result);
 
 /* Plan table access (host only, no device work).  to_plan_get sets *found
  * to 1 and fills *plan when (py, px, dtype) has a plan, else *found = 0.
  * to_plan_set validates (py, px powers of two in [8, 8192], col_variant in
- * [0, 4), chunk_mb in [1, 65536], row_fpb in [0, 8], us >= 0) and stores.  */
+ * [0, 5), chunk_mb in [1, 65536], row_fpb in [0, 8], us >= 0) and stores.  */
 to_status to_plan_get(int32_t py, int32_t px, to_dtype dtype, to_plan* plan, int32_t* found);
 to_status to_plan_set(int32_t py, int32_t px, to_dtype dtype, const to_plan* plan);
 to_status to_plan_clear(void);

@@ -295,7 +295,10 @@ struct Schedule {
 // twice the columns per cache-line segment of variant 1; measured 95 against
 // 107 us at 4096 points and 540 against 675 us at 8192 on one 2048^2 and
 // one 4096^2 field), everything else variant 1.
-int default_col_variant(int dtype, int ly) { return (dtype == 0 && ly >= 4096) ? 0 : kDefaultColVariant; }
+int default_col_variant(int dtype, int ly) {
+  if (dtype == 0 && ly >= 8192) return 4;
+  return (dtype == 0 && ly >= 4096) ? 0 : kDefaultColVariant;
+}
 
 Schedule schedule_for(int dtype, int ly, int lx) {
   if (t_force_plan)
@@ -2735,6 +2738,7 @@ to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* 
   PlanEntry best{kDefaultColVariant, kDefaultChunkMb, -1.0};
   std::vector<std::pair<int, int64_t>> seen;  // (variant, chunk fields) already timed
   for (int v = 0; v < kColVariants && st == TO_OK; ++v) {
+    if (v == 4 && tj.py < 8192) continue;  // the same kernels as variant 0 below 8192 points
     for (int mb : kChunkMb) {
       PlanEntry pe{v, mb, 0.0};
       Geometry g;

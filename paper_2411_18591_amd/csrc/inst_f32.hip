@@ -24,6 +24,7 @@ int col_tile_width(int ly, bool is_double, int variant) {
       case 1: w(std::integral_constant<int, 1>()); break;
       case 2: w(std::integral_constant<int, 2>()); break;
       case 3: w(std::integral_constant<int, 3>()); break;
+      case 4: w(std::integral_constant<int, 4>()); break;
       default: w(std::integral_constant<int, 0>()); break;
     }
     return hipSuccess;

@@ -29,14 +29,17 @@ struct RowCfg {
 // the LDS exchange buffer (L * TC complex values) stays within the variant's
 // budget: V = 0: 128 KiB, R = 16; V = 1: 64 KiB, R = 16 (two workgroups per
 // CU); V = 2: 64 KiB, R = 8; V = 3: as V = 1, with the next field's column
-// segment loaded during the current field's transforms.
-constexpr int kColVariants = 4;
+// segment loaded during the current field's transforms; V = 4: as V = 0,
+// with R = 32 for columns of 8192 points (three passes of radix 32/32/8
+// instead of 16/16/16/2, two LDS exchanges per transform instead of three,
+// at half the waves per CU; at 4096 points it measured slower than V = 0).
+constexpr int kColVariants = 5;
 constexpr bool col_prefetch(int V) { return V == 3; }
 template <typename T, int L, int V = 0>
 struct ColCfg {
-  static constexpr int R = L <= 16 ? L : (L <= 256 ? 8 : (V == 2 ? 8 : 16));
+  static constexpr int R = L <= 16 ? L : (L <= 256 ? 8 : (V == 2 ? 8 : ((V == 4 && L >= 8192) ? 32 : 16)));
   static constexpr int TT = L / R;
-  static constexpr int lds_elems = (int)((V == 0 ? 131072 : 65536) / sizeof(cx<T>));
+  static constexpr int lds_elems = (int)((V == 0 || V == 4 ? 131072 : 65536) / sizeof(cx<T>));
   static constexpr bool PF = col_prefetch(V);
   static constexpr int tc0 = lds_elems / L > 16 ? 16 : lds_elems / L;
   static constexpr int tc1 = tc0 < 1 ? 1 : tc0;

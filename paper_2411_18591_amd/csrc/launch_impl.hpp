@@ -88,6 +88,7 @@ hipError_t Launch<T>::col(int ly, bool half, int ntiles, int nfields, int varian
       case 1: go(std::integral_constant<int, 1>()); break;
       case 2: go(std::integral_constant<int, 2>()); break;
       case 3: go(std::integral_constant<int, 3>()); break;
+      case 4: go(std::integral_constant<int, 4>()); break;
       default: go(std::integral_constant<int, 0>()); break;
     }
     return hipGetLastError();

@@ -291,7 +291,7 @@ def test_autotune_stores_a_plan_and_keeps_parity():
     ug, pg, Tg = to_gpu(u, torch), to_gpu(phi, torch), to_gpu(T, torch)
     out, plan = tp.autotune(ug, opt, phase=pg)
     torch.cuda.synchronize()
-    assert 0 <= plan["col_variant"] < 4 and plan["chunk_mb"] in (32, 64, 128, 256) and plan["us"] > 0
+    assert 0 <= plan["col_variant"] < 5 and plan["chunk_mb"] in (32, 64, 128, 256) and plan["us"] > 0
     assert plan["row_fpb"] in (0, 1, 2, 4)
     stored = tp.plan_get(2 * n, 2 * n)
     assert (stored["col_variant"], stored["chunk_mb"], stored["row_fpb"]) == (

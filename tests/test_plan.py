@@ -34,7 +34,7 @@ def test_set_get_clear(capi):
 
 @pytest.mark.parametrize("py,px,variant,chunk,us,fpb", [
     (2048, 2047, 1, 128, 0.0, 0), (4, 2048, 1, 128, 0.0, 0), (16384, 16, 1, 128, 0.0, 0),
-    (2048, 2048, 4, 128, 0.0, 0), (2048, 2048, -1, 128, 0.0, 0), (2048, 2048, 1, 0, 0.0, 0),
+    (2048, 2048, 5, 128, 0.0, 0), (2048, 2048, -1, 128, 0.0, 0), (2048, 2048, 1, 0, 0.0, 0),
     (2048, 2048, 1, 65537, 0.0, 0), (2048, 2048, 1, 64, -1.0, 0), (2048, 2048, 1, 64, float("nan"), 0),
     (2048, 2048, 1, 64, 1.0, -1), (2048, 2048, 1, 64, 1.0, 9),
 ])
