@@ -88,7 +88,8 @@ def copy_calibration():
 
 
 # Files that hold the propagation kernels' device code and launch shapes.
-KERNEL_SOURCES = ("fft.hpp", "kernels.hpp", "launch.hpp", "launch_impl.hpp", "inst_f32.hip", "inst_f64.hip")
+KERNEL_SOURCES = ("fft.hpp", "kernels.hpp", "launch.hpp", "launch_impl.hpp", "inst_f32.hip", "inst_f64.hip",
+                  "queue.hpp", "queue_impl.hpp", "queue_f32.hip", "queue_f64.hip")
 
 
 def kernel_source_digest() -> str:
