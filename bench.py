@@ -121,6 +121,27 @@ def measured_traffic(kernel_label: str, launch_fields: int):
     return None if ent is None else int(ent["bytes"])
 
 
+def counted_valu(kernel_label: str, launch_fields: int):
+    """VALU issue of a kernel from the committed SQ counter runs
+    (`profiles/diffnet_1024_c64_counters.json`), or None when they were not
+    taken for it, the kernel sources changed since, or a launch covers a
+    different number of fields."""
+    path = os.path.join(ROOT, "profiles", "diffnet_1024_c64_counters.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_digest() or rec.get("launch_fields") != launch_fields:
+        return None
+    ent = rec.get("per_launch", {}).get(kernel_label.split(".", 1)[-1])
+    if ent is None:
+        return None
+    return {"frac": ent["valu_busy_frac"], "frac_at_2p4GHz": ent["valu_busy_frac_at_2p4GHz"],
+            "lane_instr_per_point_transform": ent["lane_instr_per_point_transform"],
+            "source": "SQ_INSTS_VALU / (256 CUs x cycles), profiles/diffnet_1024_c64_counters.json"}
+
+
 def fft_flops(L: int) -> float:
     """Conventional flop count of one complex FFT of length L."""
     return 5.0 * L * math.log2(L)
@@ -320,6 +341,7 @@ def main():
         f_h = gbs / HBM_PEAK_GBS
         f_a = tfs / VALU_FP32_PEAK_TFLOPS
         traffic = measured_traffic(name, chunk) if (N, B, L, method) == (1024, 64, 5, "ASM") else None
+        valu = counted_valu(name, chunk) if (N, B, L, method) == (1024, 64, 5, "ASM") else None
         # bound: the resource closer to saturation, the ALU side taken at the
         # rate this build can reach (no packed FP32); reported against the
         # published peak, with the non-packed view beside it
@@ -329,7 +351,8 @@ def main():
                         "kernel": name, "avg_us": round(avg_s * 1e6, 2),
                         "nonpacked_view": {"peak": VALU_FP32_NONPACKED_TFLOPS,
                                            "frac": round(tfs / VALU_FP32_NONPACKED_TFLOPS, 4)},
-                        "hbm_view": {"achieved_GB_s": round(gbs, 1), "frac": round(f_h, 4)}}
+                        "hbm_view": {"achieved_GB_s": round(gbs, 1), "frac": round(f_h, 4)},
+                        "valu_issue_counted": valu}
         else:
             roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(f_h, 4), "traffic": traffic,
