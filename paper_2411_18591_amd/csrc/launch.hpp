@@ -12,14 +12,16 @@ constexpr int kMinLen = 8;
 constexpr int kMaxLen = 8192;
 
 // Row passes: R points per thread, G rows per workgroup.  Heavy kernels
-// (the backward row_inv epilogue, three coupled components) keep R = 8 at
-// length 2048, where R = 16 would cost them occupancy; so does complex128.
+// (the backward row_inv epilogue, three coupled components) keep R = 8 from
+// length 2048 on, where R = 16 would cost them occupancy (three coupled
+// components at 4096 points: 344 and 408 VGPRs, one wave per SIMD, against
+// 187 and 212); so does complex128 at 2048.
 template <typename T, int L, bool Heavy = false>
 struct RowCfg {
   using Real = T;
   static constexpr int Len = L;
   static constexpr int R =
-      L <= 16 ? L : (L <= 1024 ? 8 : ((L == 2048 && (Heavy || sizeof(T) == 8)) ? 8 : 16));
+      L <= 16 ? L : (L <= 1024 ? 8 : (((L >= 2048 && Heavy) || (L == 2048 && sizeof(T) == 8)) ? 8 : 16));
   static constexpr int TT = L / R;
   static constexpr int G = TT >= 256 ? 1 : 256 / TT;
   static constexpr int threads = G * TT;
