@@ -962,27 +962,28 @@ def run_uneven(args, dev):
     res = {"jobs": len(jobs), "ms_per_step": round(ms, 3), "propagations_per_step": 2 * len(jobs),
            "propagations_per_s": round(2 * len(jobs) / (ms / 1000.0), 1),
            "field_elements_per_job_sum": elems, "kernels": top, "roofline": uneven_roofline(top)}
-    # The same step captured once into a HIP graph (both calls, every lane)
-    # and replayed: no host launch work per kernel.  The replay's outputs
-    # must equal the eager step's bit for bit.
+    # The same step captured by the library into two HIP graphs that it owns
+    # (the forward call and the adjoint call, every lane and job-queue launch
+    # included; `to_graph_create`) and replayed: no host launch work per
+    # kernel.  The replays' outputs must equal the eager step's bit for bit.
     torch.cuda.synchronize()
     ref = [t.clone() for t in uo + gi]
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        uneven()
-    torch.cuda.current_stream().wait_stream(side)
+    _, g_fwd = tp.propagate_jobs(us, ops, outs=uo, graph=True)
+    _, g_bwd = tp.propagate_backward_jobs(gs, ops, grad_ins=gi, graph=True)
+
+    def replay():
+        g_fwd.launch()
+        g_bwd.launch()
     torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        uneven()
     for t in uo + gi:
         t.zero_()
-    ms_g, _ = _timed(graph.replay, args.steps, 1)
+    ms_g, _ = _timed(replay, args.steps, 1)
     same = all(torch.equal(a, b) for a, b in zip(uo + gi, ref))
     res["graph"] = {"ms_per_step": round(ms_g, 3), "propagations_per_s": round(2 * len(jobs) / (ms_g / 1000.0), 1),
-                    "outputs_equal_eager": same}
-    del graph, ref
+                    "outputs_equal_eager": same, "captured_by": "library (to_graph_create)"}
+    g_fwd.close()
+    g_bwd.close()
+    del ref
     if not args.no_cpu_baseline:
         uneven()
         torch.cuda.synchronize()

@@ -406,6 +406,28 @@ to_status to_jones_linear_polarizer(double theta, double* out);
 to_status to_jones_waveplate(double theta, double retardance, double* out);
 to_status to_jones_compose(const double* first, const double* then, double* out);
 
+/* Captured calls (the batch dimension of the paper's Overview, §2, run as
+ * one HIP graph).  to_graph_create runs one to_propagate call (grads ==
+ * NULL) or one to_propagate_backward call (grads != NULL) over `jobs` on
+ * `stream` — its results are those of that call, and it sizes every
+ * workspace — then synchronizes `stream` and captures the same call, all
+ * lanes and job-queue launches included, into a HIP graph that the library
+ * instantiates and owns.  to_graph_launch replays it on `stream`: the same
+ * kernels with the same arguments, reading and writing the buffers the
+ * records named at creation, so a replay equals the call on the buffers'
+ * contents at replay time.  The caller keeps those buffers alive (and at
+ * the same addresses) until to_graph_destroy, and does not let a replay
+ * overlap another call of this library on the device (they share the
+ * workspaces).  Allocates (the first call, the graph): not for use under
+ * another capture.  Errors: TO_E_INVAL (NULL out, njobs < 1, invalid
+ * jobs as in the call), TO_E_HIP (capture or instantiation failed; nothing
+ * is created).                                                               */
+typedef struct to_graph_s* to_graph;
+to_status to_graph_create(const to_job* jobs, const to_grad* grads, int32_t njobs, to_dtype dtype,
+                          void* stream, to_graph* out);
+to_status to_graph_launch(to_graph graph, void* stream);
+to_status to_graph_destroy(to_graph graph);
+
 /* Library version, e.g. "toprop 0.1.0 gfx950".                              */
 const char* to_version(void);
 

@@ -427,12 +427,45 @@ def _common_dtype(tensors) -> int:
     return codes.pop()
 
 
+class Graph:
+    """A library call captured into a HIP graph owned by the library
+    (`to_graph_create`): :meth:`launch` replays it on a stream, reading and
+    writing the tensors the call named (keep them alive; refill them in
+    place).  Returned by ``propagate_jobs(..., graph=True)`` and
+    ``propagate_backward_jobs(..., graph=True)``."""
+
+    def __init__(self, handle: int, tensors, device):
+        self._h = handle
+        self._keep = list(tensors)  # the captured addresses stay valid
+        self._device = device
+
+    def launch(self, stream: Optional[torch.cuda.Stream] = None) -> None:
+        if self._h is None:
+            raise RuntimeError("graph was closed")
+        s = stream if stream is not None else torch.cuda.current_stream(self._device)
+        _capi.graph_launch(self._h, s.cuda_stream)
+
+    def close(self) -> None:
+        if self._h is not None:
+            _capi.graph_destroy(self._h)
+            self._h = None
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def propagate_jobs(fields: Sequence[torch.Tensor], opts: Sequence[Optics], *, outs=None, elements=None,
-                   ncomp: int = 1, plain: bool = False):
+                   ncomp: int = 1, plain: bool = False, graph: bool = False):
     """One library call over several independent propagations, each with its
     own grid, optics and element (the uneven batch).  Independent jobs run
     concurrently on the library's lanes; a job that reads what an earlier job
-    of the call writes runs after it.  Returns the output tensors."""
+    of the call writes runs after it.  Returns the output tensors; with
+    ``graph=True`` the call also is captured (after running once) and
+    ``(outs, Graph)`` is returned."""
     n = len(fields)
     if len(opts) != n:
         raise ValueError("one Optics per field")
@@ -442,13 +475,19 @@ def propagate_jobs(fields: Sequence[torch.Tensor], opts: Sequence[Optics], *, ou
         return outs
     dt = _common_dtype(fields)
     jobs = [make_job(u, o, out=y, ncomp=ncomp, **el) for u, o, y, el in zip(fields, opts, outs, elements)]
+    if graph:
+        if plain:
+            raise ValueError("graph=True captures the fused call")
+        h = _capi.graph_create(jobs, None, dt, _stream(fields[0]))
+        kept = list(fields) + list(outs) + [v for el in elements for v in el.values() if isinstance(v, torch.Tensor)]
+        return outs, Graph(h, kept, fields[0].device)
     _capi.propagate(jobs, dt, _stream(fields[0]), plain=plain)
     return outs
 
 
 def propagate_backward_jobs(grads_out: Sequence[torch.Tensor], opts: Sequence[Optics], *, saved_ins=None,
                             grad_ins=None, grad_phases=None, grad_fs=None, elements=None, ncomp: int = 1,
-                            plain: bool = False, transient=None):
+                            plain: bool = False, transient=None, graph: bool = False):
     """Backward of :func:`propagate_jobs` in one call: returns dL/d(in) per
     job (``grad_ins[i]`` None: not formed); element gradients accumulate
     into ``grad_phases[i]`` / ``grad_fs[i]`` (jobs that share a gradient
@@ -485,6 +524,13 @@ def propagate_backward_jobs(grads_out: Sequence[torch.Tensor], opts: Sequence[Op
         g.flags = _capi.TO_GRAD_IN_TRANSIENT if tr else 0
         jobs.append(j)
         grs.append(g)
+    if graph:
+        if plain:
+            raise ValueError("graph=True captures the fused call")
+        h = _capi.graph_create(jobs, grs, dt, _stream(grads_out[0]))
+        kept = [t for t in list(grads_out) + grad_ins + saved_ins + grad_phases + grad_fs if isinstance(t, torch.Tensor)]
+        kept += [v for el in elements for v in el.values() if isinstance(v, torch.Tensor)]
+        return grad_ins, Graph(h, kept, grads_out[0].device)
     _capi.propagate_backward(jobs, grs, dt, _stream(grads_out[0]), plain=plain)
     return grad_ins
 

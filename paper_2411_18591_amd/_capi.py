@@ -45,6 +45,9 @@ EXPORTED = (
     "to_jones_compose",
     "to_propagate",
     "to_propagate_noalloc",
+    "to_graph_create",
+    "to_graph_launch",
+    "to_graph_destroy",
     "to_resample",
     "to_transfer_table",
     "to_resolve_method",
@@ -162,6 +165,12 @@ def lib() -> ctypes.CDLL:
         L.to_propagate.restype = c_int
         L.to_propagate_noalloc.argtypes = [JP, c_int, c_int, ctypes.c_void_p]
         L.to_propagate_noalloc.restype = c_int
+        L.to_graph_create.argtypes = [JP, GP, c_int, c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+        L.to_graph_create.restype = c_int
+        L.to_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.to_graph_launch.restype = c_int
+        L.to_graph_destroy.argtypes = [ctypes.c_void_p]
+        L.to_graph_destroy.restype = c_int
         L.to_modulate.argtypes = [JP, c_int, c_int, c_int, ctypes.c_void_p]
         L.to_modulate.restype = c_int
         L.to_propagate_backward.argtypes = [JP, GP, c_int, c_int, ctypes.c_void_p]
@@ -281,6 +290,22 @@ def propagate_noalloc(jobs, dtype: int, stream: int) -> None:
 def modulate(jobs, dtype: int, adjoint: bool, stream: int) -> None:
     arr = jobs_array(jobs)
     check(lib().to_modulate(arr, len(jobs), dtype, 1 if adjoint else 0, ctypes.c_void_p(stream)))
+
+
+def graph_create(jobs, grads, dtype: int, stream: int) -> int:
+    """to_graph_create: run the call once, capture it; returns the handle."""
+    h = ctypes.c_void_p()
+    g = grads_array(grads) if grads is not None else None
+    check(lib().to_graph_create(jobs_array(jobs), g, len(jobs), dtype, ctypes.c_void_p(stream), ctypes.byref(h)))
+    return h.value
+
+
+def graph_launch(handle: int, stream: int) -> None:
+    check(lib().to_graph_launch(ctypes.c_void_p(handle), ctypes.c_void_p(stream)))
+
+
+def graph_destroy(handle: int) -> None:
+    check(lib().to_graph_destroy(ctypes.c_void_p(handle)))
 
 
 def propagate_backward(jobs, grads, dtype: int, stream: int, plain: bool = False) -> None:

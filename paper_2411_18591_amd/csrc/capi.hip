@@ -173,6 +173,25 @@ to_status get_ctx(DeviceCtx** out) {
   return TO_OK;
 }
 
+// Captured calls (to_graph_create) hold the addresses of the workspaces they
+// were captured with.  While any is alive, a workspace that grows is not
+// freed but retired, and retired buffers are freed when the last graph is
+// destroyed.
+int g_live_graphs = 0;                            // under g_mutex
+std::vector<std::pair<int, void*>> g_retired;     // (device, buffer), under g_mutex
+
+void free_workspace(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_mutex);
+  if (g_live_graphs > 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    g_retired.emplace_back(dev, p);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
 // Grow a lane's scratch buffer to at least `bytes` (synchronizes the device
 // when it has to reallocate, since queued work may still use the old buffer).
 to_status ensure_scratch(Lane* c, size_t bytes) {
@@ -183,7 +202,7 @@ to_status ensure_scratch(Lane* c, size_t bytes) {
   hipError_t e;
   if (c->scratch) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    (void)hipFree(c->scratch);
+    free_workspace(c->scratch);
     c->scratch = nullptr;
     c->scratch_bytes = 0;
   }
@@ -199,7 +218,7 @@ to_status ensure_plain(DeviceCtx* c, size_t bytes) {
   hipError_t e;
   if (c->plain) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    (void)hipFree(c->plain);
+    free_workspace(c->plain);
     c->plain = nullptr;
     c->plain_bytes = 0;
   }
@@ -216,7 +235,7 @@ to_status ensure_area(void** area, size_t* have, size_t bytes, const char* what)
   hipError_t e;
   if (*area) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    (void)hipFree(*area);
+    free_workspace(*area);
     *area = nullptr;
     *have = 0;
   }
@@ -238,7 +257,7 @@ to_status ensure_partial(Lane* c, size_t count) {
   hipError_t e;
   if (c->partial) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    (void)hipFree(c->partial);
+    free_workspace(c->partial);
     c->partial = nullptr;
     c->partial_count = 0;
   }
@@ -1492,7 +1511,7 @@ to_status ensure_coh(DeviceCtx* c, size_t bytes) {
   hipError_t e;
   if (c->coh) {
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    (void)hipFree(c->coh);
+    free_workspace(c->coh);
     c->coh = nullptr;
     c->coh_bytes = 0;
   }
@@ -2837,6 +2856,7 @@ const char* to_last_error(void) { return g_last_error.c_str(); }
 
 to_status to_release(void) {
   std::lock_guard<std::mutex> lk(g_mutex);
+  if (g_live_graphs > 0) return fail(TO_E_INVAL, "%d captured call(s) still hold the workspaces", g_live_graphs);
   // release everything even after an error; report the first one
   hipError_t first = hipSuccess;
   auto note = [&](hipError_t e) {
@@ -3073,6 +3093,95 @@ to_status to_profile_entry(int32_t i, char* name, int32_t name_len, int64_t* lau
   snprintf(name, (size_t)name_len, "%s", g_prof_agg[i].name.c_str());
   *launches = g_prof_agg[i].launches;
   *total_ms = g_prof_agg[i].ms;
+  return TO_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Captured calls.
+// ---------------------------------------------------------------------------
+struct to_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;  // the private stream the call was captured on
+};
+
+void graph_free(to_graph g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+  delete g;
+}
+
+to_status to_graph_destroy(to_graph g) {
+  if (!g) return fail(TO_E_INVAL, "graph is NULL");
+  graph_free(g);
+  std::lock_guard<std::mutex> lk(g_mutex);
+  if (--g_live_graphs == 0 && !g_retired.empty()) {
+    // replays may still be queued: wait for the devices before freeing
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& r : g_retired) {
+      (void)hipSetDevice(r.first);
+      (void)hipDeviceSynchronize();
+      (void)hipFree(r.second);
+    }
+    g_retired.clear();
+    (void)hipSetDevice(cur);
+  }
+  return TO_OK;
+}
+
+to_status to_graph_create(const to_job* jobs, const to_grad* grads, int32_t njobs, to_dtype dtype,
+                          void* stream, to_graph* out) {
+  if (!out) return fail(TO_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (njobs < 1 || !jobs) return fail(TO_E_INVAL, "a captured call needs at least one job");
+  auto call = [&](void* s) {
+    return grads ? to_propagate_backward(jobs, grads, njobs, dtype, s) : to_propagate(jobs, njobs, dtype, s);
+  };
+  // the eager call: results, workspaces, tables
+  to_status st = call(stream);
+  if (st != TO_OK) return st;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  to_graph g = new to_graph_s;
+  if ((e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking)) != hipSuccess) {
+    delete g;
+    return hip_fail(e, "hipStreamCreate");
+  }
+  if ((e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    graph_free(g);
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  st = call(g->stream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(g->stream, &graph);
+  g->graph = graph;
+  if (st != TO_OK) {
+    graph_free(g);
+    return st;
+  }
+  if (e != hipSuccess) {
+    graph_free(g);
+    return hip_fail(e, "hipStreamEndCapture");
+  }
+  if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess) {
+    graph_free(g);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mutex);
+    ++g_live_graphs;
+  }
+  *out = g;
+  return TO_OK;
+}
+
+to_status to_graph_launch(to_graph g, void* stream) {
+  if (!g || !g->exec) return fail(TO_E_INVAL, "graph is NULL");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return TO_OK;
 }
 
