@@ -16,14 +16,19 @@ constexpr int kMaxLen = 8192;
 // length 2048 on, where R = 16 would cost them occupancy (three coupled
 // components at 4096 points: 344 and 408 VGPRs, one wave per SIMD, against
 // 187 and 212); so does complex128 at 2048.
-template <typename T, int L, bool Heavy = false>
+// OneRow: one row per workgroup at 2048 points (half the threads, a barrier
+// over two waves instead of four); measured faster for the fused forward
+// boundary (89.5 -> 84.9 us per launch of 8 fields) and the forward
+// row_inv (65.4 -> 63.5 us), slower for row_fwd and the fused backward
+// boundary, which keep two rows.
+template <typename T, int L, bool Heavy = false, bool OneRow = false>
 struct RowCfg {
   using Real = T;
   static constexpr int Len = L;
   static constexpr int R =
       L <= 16 ? L : (L <= 1024 ? 8 : (((L >= 2048 && Heavy) || (L == 2048 && sizeof(T) == 8)) ? 8 : 16));
   static constexpr int TT = L / R;
-  static constexpr int G = TT >= 256 ? 1 : 256 / TT;
+  static constexpr int G = (OneRow && L == 2048 && R == 16) ? 1 : (TT >= 256 ? 1 : 256 / TT);
   static constexpr int threads = G * TT;
 };
 

@@ -100,7 +100,7 @@ hipError_t Launch<T>::row_mid(int lx, bool half, int ny, int nblocks_y, const Ro
                               hipStream_t s) {
   return dispatch_len(lx, [&](auto Lc) -> hipError_t {
     constexpr int L = decltype(Lc)::value;
-    using C = RowCfg<T, L>;
+    using C = RowCfg<T, L, false, true>;
     dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
     dim3 block(C::threads);
     dispatch_exact<L>(a.nx == (half ? L / 2 : L), [&](auto ex) {
@@ -151,7 +151,7 @@ hipError_t Launch<T>::row_inv(int lx, bool half, int nc, int ny, int nblocks_y,
           else
             hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, false, 3, B, EX>), grid, dim3(C::threads), 0, s, a);
         } else {
-          using C = RowCfg<T, L, B>;
+          using C = RowCfg<T, L, B, !B>;
           dim3 grid((ny + C::G - 1) / C::G, nblocks_y);
           if (half)
             hipLaunchKernelGGL((row_inv_kernel<T, L, C::R, C::G, true, 1, B, EX>), grid, dim3(C::threads), 0, s, a);
