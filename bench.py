@@ -262,12 +262,36 @@ def main():
     # fields per row-pass workgroup), tuned by the library's autotuner on one
     # layer's forward propagation of the whole batch before anything is timed.
     plan = None
+    schedule = {"tuned": False, "plan": None}
     if not args.no_autotune:
         print("[bench] autotune", file=sys.stderr, flush=True)
         tuned, plan = tp.autotune(net.u[0], opt, phase=net.masks[0])
         del tuned
         torch.cuda.synchronize()
         print(f"[bench] plan {plan}", file=sys.stderr, flush=True)
+        # The autotuner times one layer's forward propagation; the step is a
+        # chained forward + backward.  The tuned plan is checked on the step
+        # itself against the built-in schedule (a few untimed steps each) and
+        # the faster one is kept.
+        def step_ms(n=3):
+            step()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(n):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / n
+        t_tuned = step_ms()
+        tp.plan_clear()
+        t_builtin = step_ms()
+        keep = "tuned" if t_tuned < t_builtin else "built-in"
+        if keep == "tuned":
+            tp.plan_set(P, P, plan["col_variant"], plan["chunk_mb"], us=plan["us"], row_fpb=plan["row_fpb"])
+        schedule = {"tuned": True, "plan": plan if keep == "tuned" else None, "autotuner_plan": plan,
+                    "kept": keep, "step_ms": {"tuned": round(t_tuned, 3), "built_in": round(t_builtin, 3)}}
+        print(f"[bench] schedule {schedule}", file=sys.stderr, flush=True)
 
     print("[bench] warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -340,8 +364,10 @@ def main():
         tfs = fl / avg_s / 1e12
         f_h = gbs / HBM_PEAK_GBS
         f_a = tfs / VALU_FP32_PEAK_TFLOPS
-        traffic = measured_traffic(name, chunk) if (N, B, L, method) == (1024, 64, 5, "ASM") else None
-        valu = counted_valu(name, chunk) if (N, B, L, method) == (1024, 64, 5, "ASM") else None
+        # the committed counter records were taken with the built-in schedule
+        same_run = (N, B, L, method) == (1024, 64, 5, "ASM") and schedule["plan"] is None
+        traffic = measured_traffic(name, chunk) if same_run else None
+        valu = counted_valu(name, chunk) if same_run else None
         # bound: the resource closer to saturation, the ALU side taken at the
         # rate this build can reach (no packed FP32); reported against the
         # published peak, with the non-packed view beside it
@@ -403,7 +429,7 @@ def main():
             "propagations_per_step": props,
         },
         "hbm_roofline_step": {"algorithmic_bytes": step_bytes, "frac": round(hbm_frac_step, 4)},
-        "schedule": {"tuned": plan is not None, "plan": plan},
+        "schedule": schedule,
         "profiled_pass_ms_per_step": None if prof_ms_step is None else round(prof_ms_step, 4),
         "plain_form": plain,
         "roofline": roofline,
