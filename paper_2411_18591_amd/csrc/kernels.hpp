@@ -332,10 +332,27 @@ constexpr int lds_len(int L) {  // elements (per column) of a padded exchange bu
   return STRIDE == 1 ? L + 2 * (L >> 5) + (L >> 7) : L + (L >> 4);
 }
 
-template <typename T, int L, int R, int D, bool HALF_IN, int STRIDE>
+// Orders this wavefront's LDS accesses before and after it without a
+// workgroup barrier: the LDS unit executes one wave's instructions in issue
+// order, so only the compiler's reordering has to be stopped.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// WAVE: every thread of the transform sits in the calling thread's
+// wavefront, so the exchanges between passes need no workgroup barrier.
+template <typename T, int L, int R, int D, bool HALF_IN, int STRIDE, bool WAVE = false>
 __device__ __forceinline__ void fft_wg(cx<T>* v, int j, cx<T>* lds, const cx<T>* __restrict__ tw) {
   using S = Schedule<L, R>;
   constexpr int TT = S::T;
+  auto sync = [] {
+    if constexpr (WAVE)
+      wave_sync();
+    else
+      __syncthreads();
+  };
   static_for<0, S::npass>([&](auto pc) {
     constexpr int P = decltype(pc)::value;
     constexpr int RP = S::radix(P);
@@ -350,7 +367,7 @@ __device__ __forceinline__ void fft_wg(cx<T>* v, int j, cx<T>* lds, const cx<T>*
       // lds_pos(p0) + lds_pos(i NS); likewise lds_pos(j + m TT) =
       // lds_pos(j) + lds_pos(m TT) for j < TT.  Every element offset is
       // therefore a compile-time immediate on one per-thread base.
-      __syncthreads();
+      sync();
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
         const int p0 = stockham_out_pos<L, R, RP, NS>(j, t, 0);
@@ -358,12 +375,99 @@ __device__ __forceinline__ void fft_wg(cx<T>* v, int j, cx<T>* lds, const cx<T>*
 #pragma unroll
         for (int i = 0; i < RP; ++i) lds[b0 + lds_pos<STRIDE>(i * NS) * STRIDE] = v[t + i * NB];
       }
-      __syncthreads();
+      sync();
       const int r0 = lds_pos<STRIDE>(j) * STRIDE;
 #pragma unroll
       for (int m = 0; m < R; ++m) v[m] = lds[r0 + lds_pos<STRIDE>(m * TT) * STRIDE];
     }
   });
+}
+
+// ---------------------------------------------------------------------------
+// Split transform for column tiles: a length-L transform as one radix-R pass
+// across the whole transform followed by R sub-transforms of M = L/R points,
+// each held by TS = M/R consecutive threads (decimation in frequency:
+// X[R k + g] = sum_a w_M^{a k} w_L^{a g} sum_b x[a + M b] w_R^{b g}).  When a
+// sub-transform's threads share one wavefront, its exchanges need no
+// workgroup barrier: three barriers per forward + inverse pair instead of
+// 4 (npass - 1).  The forward transform leaves thread j = g TS + s holding
+// X[R (s + m TS) + g] in register m (frequency row R s + g + m M); the
+// inverse takes that order and returns natural order, x[j + m M] in
+// register m, like fft_wg.
+// ---------------------------------------------------------------------------
+template <int L, int R, int TC>
+struct ColSplit {
+  static constexpr int M = L / R;
+  static constexpr int TS = M / R;
+  // threads of one sub-transform (all TC columns) within one wavefront
+  static constexpr bool ok = L >= R * R && R >= 4 && TS * TC <= 64 && (64 % (TS * TC)) == 0 && M % 16 == 0;
+  __device__ __forceinline__ static int freq_row(int j) { return R * (j % TS) + j / TS; }
+};
+
+// Radix-R pass over registers m (elements j + m M), then the twiddles
+// w_L^{D j g} on output g.
+template <typename T, int L, int R, int D, bool HALF_IN>
+__device__ __forceinline__ void split_outer(cx<T>* v, int j, const cx<T>* __restrict__ tw) {
+  const rsrc_t twr = buf_rsrc(tw, (uint32_t)(L * sizeof(cx<T>)));
+  if constexpr (HALF_IN)
+    DftHalfZero<R, D, T>::run(v);
+  else
+    Dft<R, D, T>::run(v);
+#pragma unroll
+  for (int g = 1; g < R; ++g) {
+    cx<T> w = buf_ld<T>(twr, __umul24((uint32_t)j, (uint32_t)(g * sizeof(cx<T>))), 0u);
+    if (D > 0) w.y = -w.y;
+    v[g] = cmul(v[g], w);
+  }
+}
+
+template <typename T, int L, int R, bool HALF_IN, int STRIDE>
+__device__ __forceinline__ void split_fwd(cx<T>* v, int j, cx<T>* lds, const cx<T>* __restrict__ tw) {
+  using SP = ColSplit<L, R, STRIDE>;
+  constexpr int M = SP::M, TS = SP::TS;
+  split_outer<T, L, R, -1, HALF_IN>(v, j, tw);
+  // Positions g M + j (j < M, M a multiple of 16) and s + m TS (s < TS, TS
+  // and 16 powers of two) add without a carry out of the low four bits, so
+  // lds_pos splits into a per-thread base plus a compile-time offset.
+  const int wb = lds_pos<STRIDE>(j) * STRIDE;
+  __syncthreads();  // earlier readers of the buffer are done
+#pragma unroll
+  for (int g = 0; g < R; ++g) lds[wb + lds_pos<STRIDE>(g * M) * STRIDE] = v[g];
+  __syncthreads();
+  const int g = j / TS, s = j % TS;
+  cx<T>* sub = lds + lds_pos<STRIDE>(g * M) * STRIDE;
+  const int rb = lds_pos<STRIDE>(s) * STRIDE;
+#pragma unroll
+  for (int m = 0; m < R; ++m) v[m] = sub[rb + lds_pos<STRIDE>(m * TS) * STRIDE];
+  // the sub-transform's twiddles: the length-M table (packed before L's)
+  fft_wg<T, M, R, -1, false, STRIDE, true>(v, s, sub, tw - (L - M));
+}
+
+template <typename T, int L, int R, int STRIDE>
+__device__ __forceinline__ void split_inv(cx<T>* v, int j, cx<T>* lds, const cx<T>* __restrict__ tw) {
+  using SP = ColSplit<L, R, STRIDE>;
+  constexpr int M = SP::M, TS = SP::TS;
+  const int g = j / TS, s = j % TS;
+  cx<T>* sub = lds + lds_pos<STRIDE>(g * M) * STRIDE;
+  fft_wg<T, M, R, +1, false, STRIDE, true>(v, s, sub, tw - (L - M));
+  // since the last workgroup barrier only this wavefront has read `sub`
+  wave_sync();
+  const int rb = lds_pos<STRIDE>(s) * STRIDE;
+#pragma unroll
+  for (int m = 0; m < R; ++m) sub[rb + lds_pos<STRIDE>(m * TS) * STRIDE] = v[m];
+  __syncthreads();
+  const int wb = lds_pos<STRIDE>(j) * STRIDE;
+#pragma unroll
+  for (int q = 0; q < R; ++q) v[q] = lds[wb + lds_pos<STRIDE>(q * M) * STRIDE];
+  // w_L^{+j g} on input g, then the radix-R pass over g
+  const rsrc_t twr = buf_rsrc(tw, (uint32_t)(L * sizeof(cx<T>)));
+#pragma unroll
+  for (int q = 1; q < R; ++q) {
+    cx<T> w = buf_ld<T>(twr, __umul24((uint32_t)j, (uint32_t)(q * sizeof(cx<T>))), 0u);
+    w.y = -w.y;
+    v[q] = cmul(v[q], w);
+  }
+  Dft<R, +1, T>::run(v);
 }
 
 // ---------------------------------------------------------------------------
@@ -659,7 +763,13 @@ __device__ __forceinline__ void col_body(ColArgs<T> a, int bx, int by, int gx, i
   const bool active = c < cpb;
 
   // Transfer function at this thread's bins, formed once and applied to
-  // every field of the block.
+  // every field of the block.  The split transform leaves frequency row
+  // jf + m TT in register m.
+  // (complex64 only, and not with the prefetching variant: there the extra
+  // registers spill or halve the waves per SIMD)
+  constexpr bool SPLIT = ColSplit<L, R, TC>::ok && !PF && sizeof(T) == 4;
+  const int jf = SPLIT ? ColSplit<L, R, TC>::freq_row(j) : j;
+  __builtin_assume(jf >= 0 && jf < TT);
   const int kx = tile * tm + h * cpb + c;
   cx<T> hv[R];
   bool done = false;
@@ -670,7 +780,7 @@ __device__ __forceinline__ void col_body(ColArgs<T> a, int bx, int by, int gx, i
       const float sxk = a.h.sx[kxc];
       const float lam_fy_unit = (float)(sqrt(a.h.lam2) * a.h.inv_lydy);
 #pragma unroll
-      for (int m = 0; m < R; ++m) hv[m] = transfer_fast(exk, sxk, j + m * TT, L, lam_fy_unit, a.h);
+      for (int m = 0; m < R; ++m) hv[m] = transfer_fast(exk, sxk, jf + m * TT, L, lam_fy_unit, a.h);
       done = true;
     }
   }
@@ -680,7 +790,7 @@ __device__ __forceinline__ void col_body(ColArgs<T> a, int bx, int by, int gx, i
     const cx<T>* tab = static_cast<const cx<T>*>(a.h.table) + (active ? kx : 0);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      cx<T> t = tab[(int64_t)(j + m * TT) * a.lx];
+      cx<T> t = tab[(int64_t)(jf + m * TT) * a.lx];
       if (a.h.conj) t.y = -t.y;
       hv[m] = t;
     }
@@ -688,7 +798,7 @@ __device__ __forceinline__ void col_body(ColArgs<T> a, int bx, int by, int gx, i
   }
   if (!done) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) hv[m] = transfer_at<T>(kx, j + m * TT, a.lx, L, a.h);
+    for (int m = 0; m < R; ++m) hv[m] = transfer_at<T>(kx, jf + m * TT, a.lx, L, a.h);
   }
 
   // Element (y, c) of the block's columns: lane part (j tm + c), uniform
@@ -730,7 +840,10 @@ __device__ __forceinline__ void col_body(ColArgs<T> a, int bx, int by, int gx, i
 #pragma unroll
       for (int m = 0; m < R; ++m) v[m] = m < RL ? cur[m < RL ? m : 0] : cx<T>{T(0), T(0)};
     }
-    fft_wg<T, L, R, -1, HALF, TC>(v, j1, lds + c, a.tw);
+    if constexpr (SPLIT)
+      split_fwd<T, L, R, HALF, TC>(v, j1, lds + c, a.tw);
+    else
+      fft_wg<T, L, R, -1, HALF, TC>(v, j1, lds + c, a.tw);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = cmul(v[m], hv[m]);
     // Opaque copy of j: the inverse transform reloads its twiddles instead
@@ -738,7 +851,10 @@ __device__ __forceinline__ void col_body(ColArgs<T> a, int bx, int by, int gx, i
     // multiply.
     int j2 = j;
     asm volatile("" : "+v"(j2));
-    fft_wg<T, L, R, +1, false, TC>(v, j2, lds + c, a.tw);
+    if constexpr (SPLIT)
+      split_inv<T, L, R, TC>(v, j2, lds + c, a.tw);
+    else
+      fft_wg<T, L, R, +1, false, TC>(v, j2, lds + c, a.tw);
 #pragma unroll
     for (int m = 0; m < R; ++m)
       if (kept(m)) buf_st(fr, col_vo, col_so + (uint32_t)m * m_so, v[m]);
