@@ -384,25 +384,35 @@ __device__ __forceinline__ void fft_wg(cx<T>* v, int j, cx<T>* lds, const cx<T>*
 }
 
 // ---------------------------------------------------------------------------
-// Split transform for column tiles: a length-L transform as one radix-R pass
-// across the whole transform followed by R sub-transforms of M = L/R points,
-// each held by TS = M/R consecutive threads (decimation in frequency:
-// X[R k + g] = sum_a w_M^{a k} w_L^{a g} sum_b x[a + M b] w_R^{b g}).  When a
-// sub-transform's threads share one wavefront, its exchanges need no
-// workgroup barrier: three barriers per forward + inverse pair instead of
-// 4 (npass - 1).  The forward transform leaves thread j = g TS + s holding
-// X[R (s + m TS) + g] in register m (frequency row R s + g + m M); the
-// inverse takes that order and returns natural order, x[j + m M] in
-// register m, like fft_wg.
+// Split transform: a length-L transform as one radix-R pass across the whole
+// transform and R sub-transforms of M = L/R points, each held by TS = M/R
+// consecutive threads (X[R k + g] = sum_a w_M^{a k} w_L^{a g} sum_b
+// x[a + M b] w_R^{b g}).  When a sub-transform's threads share one
+// wavefront, its exchanges need no workgroup barrier.  Two orders:
+//  natural: thread j holds element j + m M in register m (as fft_wg);
+//  split:   thread j = g TS + s holds element R (s + m TS) + g, i.e.
+//           split_base(j) + m M.
+// split_dif takes natural order to split order (the radix-R pass first);
+// split_dit takes split order to natural order (the sub-transforms first).
+// A forward split_dif + inverse split_dit pair (or inverse + forward) costs
+// three workgroup barriers instead of 4 (npass - 1).
 // ---------------------------------------------------------------------------
-template <int L, int R, int TC>
-struct ColSplit {
+template <int L, int R, int STRIDE, int WAVE_THREADS>
+struct Split {
   static constexpr int M = L / R;
   static constexpr int TS = M / R;
-  // threads of one sub-transform (all TC columns) within one wavefront
-  static constexpr bool ok = L >= R * R && R >= 4 && TS * TC <= 64 && (64 % (TS * TC)) == 0 && M % 16 == 0;
-  __device__ __forceinline__ static int freq_row(int j) { return R * (j % TS) + j / TS; }
+  // WAVE_THREADS: threads of one sub-transform (with all STRIDE columns of a
+  // column tile) that must fit one wavefront; lds_pos splits over g M + p
+  // when M is a multiple of the padding period (16 for column tiles, 128
+  // for rows)
+  static constexpr bool ok = L >= R * R && R >= 4 && WAVE_THREADS <= 64 && (64 % WAVE_THREADS) == 0 &&
+                             M % (STRIDE == 1 ? 128 : 16) == 0;
+  __device__ __forceinline__ static int base(int j) { return R * (j % TS) + j / TS; }
 };
+template <int L, int R, int TC>
+using ColSplit = Split<L, R, TC, (L / R / R) * TC>;
+template <int L, int R>
+using RowSplit = Split<L, R, 1, L / R / R>;
 
 // Radix-R pass over registers m (elements j + m M), then the twiddles
 // w_L^{D j g} on output g.
@@ -421,14 +431,14 @@ __device__ __forceinline__ void split_outer(cx<T>* v, int j, const cx<T>* __rest
   }
 }
 
-template <typename T, int L, int R, bool HALF_IN, int STRIDE>
-__device__ __forceinline__ void split_fwd(cx<T>* v, int j, cx<T>* lds, const cx<T>* __restrict__ tw) {
-  using SP = ColSplit<L, R, STRIDE>;
+// Positions g M + j (j < M) and s + m TS (s < TS; TS, 32 and 128 powers of
+// two) add without a carry into the padding bits, so lds_pos splits into a
+// per-thread base plus a compile-time offset.
+template <typename T, int L, int R, int D, bool HALF_IN, int STRIDE>
+__device__ __forceinline__ void split_dif(cx<T>* v, int j, cx<T>* lds, const cx<T>* __restrict__ tw) {
+  using SP = Split<L, R, STRIDE, 1>;
   constexpr int M = SP::M, TS = SP::TS;
-  split_outer<T, L, R, -1, HALF_IN>(v, j, tw);
-  // Positions g M + j (j < M, M a multiple of 16) and s + m TS (s < TS, TS
-  // and 16 powers of two) add without a carry out of the low four bits, so
-  // lds_pos splits into a per-thread base plus a compile-time offset.
+  split_outer<T, L, R, D, HALF_IN>(v, j, tw);
   const int wb = lds_pos<STRIDE>(j) * STRIDE;
   __syncthreads();  // earlier readers of the buffer are done
 #pragma unroll
@@ -440,17 +450,20 @@ __device__ __forceinline__ void split_fwd(cx<T>* v, int j, cx<T>* lds, const cx<
 #pragma unroll
   for (int m = 0; m < R; ++m) v[m] = sub[rb + lds_pos<STRIDE>(m * TS) * STRIDE];
   // the sub-transform's twiddles: the length-M table (packed before L's)
-  fft_wg<T, M, R, -1, false, STRIDE, true>(v, s, sub, tw - (L - M));
+  fft_wg<T, M, R, D, false, STRIDE, true>(v, s, sub, tw - (L - M));
 }
 
-template <typename T, int L, int R, int STRIDE>
-__device__ __forceinline__ void split_inv(cx<T>* v, int j, cx<T>* lds, const cx<T>* __restrict__ tw) {
-  using SP = ColSplit<L, R, STRIDE>;
+// HALF_IN: registers m >= R/2 are zero (elements from L/2 on, in split order
+// as in natural order).  Since the last workgroup barrier only this
+// wavefront may have touched its sub-transform's region.
+template <typename T, int L, int R, int D, bool HALF_IN, int STRIDE>
+__device__ __forceinline__ void split_dit(cx<T>* v, int j, cx<T>* lds, const cx<T>* __restrict__ tw) {
+  using SP = Split<L, R, STRIDE, 1>;
   constexpr int M = SP::M, TS = SP::TS;
   const int g = j / TS, s = j % TS;
   cx<T>* sub = lds + lds_pos<STRIDE>(g * M) * STRIDE;
-  fft_wg<T, M, R, +1, false, STRIDE, true>(v, s, sub, tw - (L - M));
-  // since the last workgroup barrier only this wavefront has read `sub`
+  wave_sync();
+  fft_wg<T, M, R, D, HALF_IN, STRIDE, true>(v, s, sub, tw - (L - M));
   wave_sync();
   const int rb = lds_pos<STRIDE>(s) * STRIDE;
 #pragma unroll
@@ -459,15 +472,15 @@ __device__ __forceinline__ void split_inv(cx<T>* v, int j, cx<T>* lds, const cx<
   const int wb = lds_pos<STRIDE>(j) * STRIDE;
 #pragma unroll
   for (int q = 0; q < R; ++q) v[q] = lds[wb + lds_pos<STRIDE>(q * M) * STRIDE];
-  // w_L^{+j g} on input g, then the radix-R pass over g
+  // w_L^{D j g} on input g, then the radix-R pass over g
   const rsrc_t twr = buf_rsrc(tw, (uint32_t)(L * sizeof(cx<T>)));
 #pragma unroll
   for (int q = 1; q < R; ++q) {
     cx<T> w = buf_ld<T>(twr, __umul24((uint32_t)j, (uint32_t)(q * sizeof(cx<T>))), 0u);
-    w.y = -w.y;
+    if (D > 0) w.y = -w.y;
     v[q] = cmul(v[q], w);
   }
-  Dft<R, +1, T>::run(v);
+  Dft<R, D, T>::run(v);
 }
 
 // ---------------------------------------------------------------------------
@@ -768,7 +781,7 @@ __device__ __forceinline__ void col_body(ColArgs<T> a, int bx, int by, int gx, i
   // (complex64 only, and not with the prefetching variant: there the extra
   // registers spill or halve the waves per SIMD)
   constexpr bool SPLIT = ColSplit<L, R, TC>::ok && !PF && sizeof(T) == 4;
-  const int jf = SPLIT ? ColSplit<L, R, TC>::freq_row(j) : j;
+  const int jf = SPLIT ? ColSplit<L, R, TC>::base(j) : j;
   __builtin_assume(jf >= 0 && jf < TT);
   const int kx = tile * tm + h * cpb + c;
   cx<T> hv[R];
@@ -841,7 +854,7 @@ __device__ __forceinline__ void col_body(ColArgs<T> a, int bx, int by, int gx, i
       for (int m = 0; m < R; ++m) v[m] = m < RL ? cur[m < RL ? m : 0] : cx<T>{T(0), T(0)};
     }
     if constexpr (SPLIT)
-      split_fwd<T, L, R, HALF, TC>(v, j1, lds + c, a.tw);
+      split_dif<T, L, R, -1, HALF, TC>(v, j1, lds + c, a.tw);
     else
       fft_wg<T, L, R, -1, HALF, TC>(v, j1, lds + c, a.tw);
 #pragma unroll
@@ -852,7 +865,7 @@ __device__ __forceinline__ void col_body(ColArgs<T> a, int bx, int by, int gx, i
     int j2 = j;
     asm volatile("" : "+v"(j2));
     if constexpr (SPLIT)
-      split_inv<T, L, R, TC>(v, j2, lds + c, a.tw);
+      split_dit<T, L, R, +1, false, TC>(v, j2, lds + c, a.tw);
     else
       fft_wg<T, L, R, +1, false, TC>(v, j2, lds + c, a.tw);
 #pragma unroll
@@ -1247,7 +1260,9 @@ __global__ void __launch_bounds__(G * (L / R))
 // one layer is the input of the next), fused: per row, the inverse FFT of
 // the finished layer, crop and 1/(LX LY) scale, store of that layer's
 // output, the next layer's element, the forward FFT of the next layer, back
-// into the same scratch row.  Bit-identical to row_inv followed by row_fwd.
+// into the same scratch row.  Equal to row_inv followed by row_fwd (bit for
+// bit where both take the same factorisation: not for complex64 rows that
+// take the split transforms here).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct RowMidArgs {
@@ -1275,6 +1290,10 @@ __global__ void __launch_bounds__(G * (L / R))
   __shared__ cx<T> lds[G * lds_len<1>(L)];
   const int g = row_group<TT>();
   const int j = threadIdx.x % TT;
+  // Split transforms (complex64): the inverse leaves pixel xj + m TT in
+  // register m and the forward takes that order back to natural order.
+  constexpr bool SPLIT = RowSplit<L, R>::ok && sizeof(T) == 4;
+  const int xj = SPLIT ? RowSplit<L, R>::base(j) : j;
   const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
   const int ny = a.ny, nx = a.nx;
   const bool rowok = y < ny;
@@ -1283,14 +1302,14 @@ __global__ void __launch_bounds__(G * (L / R))
   const TileRow<T, TT> tr(j, y, ny, a.tc_shift);
   const uint32_t s_bytes = (uint32_t)(a.s_stride * CB);
   const uint32_t o_bytes = (uint32_t)((int64_t)ny * nx * CB);
-  const uint32_t pix0 = (uint32_t)(y * nx + j);
-  auto xin = [&](int m) { return EX || j + m * TT < nx; };
+  const uint32_t pix0 = (uint32_t)(y * nx + xj);
+  auto xin = [&](int m) { return EX || xj + m * TT < nx; };
 
   const bool scalar_el = (a.el.flags & (EL_PHASE | EL_COMPLEX | EL_LENS)) != 0;
   cx<T> mod[RO];
 #pragma unroll
   for (int m = 0; m < RO; ++m) {
-    const int x = j + m * TT;
+    const int x = xj + m * TT;
     mod[m] = {T(1), T(0)};
     if (scalar_el && rowok && xin(m)) mod[m] = scalar_modulation(a.el, ny, nx, y, x);
     __builtin_amdgcn_sched_barrier(0);
@@ -1304,19 +1323,30 @@ __global__ void __launch_bounds__(G * (L / R))
       dst[m] = val;
     }
   };
-  // The next field's row is loaded while the current one is transformed.
-  cx<T> pre[R];
-  if (f_begin < f_end) load_row(f_begin, pre);
+  // The next field's row is loaded while the current one is transformed
+  // (not with the split transforms: their registers leave no room for it).
+  constexpr bool kPipe = !SPLIT;
+  cx<T> pre[kPipe ? R : 1];
+  if constexpr (kPipe) {
+    if (f_begin < f_end) load_row(f_begin, pre);
+  }
 
 #pragma unroll 1
   for (int f = f_begin; f < f_end; ++f) {
     int jv = j;
     asm volatile("" : "+v"(jv));
     cx<T> v[R];
+    if constexpr (kPipe) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = pre[m];
-    if (f + 1 < f_end) load_row(f + 1, pre);
-    fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
+      for (int m = 0; m < R; ++m) v[m] = pre[m];
+      if (f + 1 < f_end) load_row(f + 1, pre);
+    } else {
+      load_row(f, v);
+    }
+    if constexpr (SPLIT)
+      split_dif<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
+    else
+      fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
     const rsrc_t out_r = buf_rsrc(a.out + (int64_t)f * a.out_stride, o_bytes);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
@@ -1332,7 +1362,10 @@ __global__ void __launch_bounds__(G * (L / R))
     // than keeping the inverse transform's (same addresses) live
     int jw = jv;
     asm volatile("" : "+v"(jw));
-    fft_wg<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
+    if constexpr (SPLIT)
+      split_dit<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
+    else
+      fft_wg<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
     if (rowok) {
       const rsrc_t sr = buf_rsrc(a.scratch + (int64_t)f * a.s_stride, s_bytes);
 #pragma unroll
@@ -1383,6 +1416,11 @@ __global__ void __launch_bounds__(G * (L / R))
   __shared__ double red[NT];
   const int g = row_group<TT>();
   const int j = threadIdx.x % TT;
+  // Split transforms (complex64): the inverse leaves pixel xj + m TT in
+  // register m and the forward takes that order back to natural order.
+  // (not at 8192 points, where the split's registers spill)
+  constexpr bool SPLIT = RowSplit<L, R>::ok && sizeof(T) == 4 && L <= 4096;
+  const int xj = SPLIT ? RowSplit<L, R>::base(j) : j;
   const int y = xcd_remap((int)blockIdx.x, (int)gridDim.x) * G + g;
   const int ny = a.ny, nx = a.nx;
   const bool rowok = y < ny;
@@ -1391,8 +1429,8 @@ __global__ void __launch_bounds__(G * (L / R))
   const TileRow<T, TT> tr(j, y, ny, a.tc_shift);
   const uint32_t s_bytes = (uint32_t)(a.s_stride * CB);
   const uint32_t f_bytes = (uint32_t)((int64_t)ny * nx * CB);
-  const uint32_t pix0 = (uint32_t)(y * nx + j);
-  auto xin = [&](int m) { return EX || j + m * TT < nx; };
+  const uint32_t pix0 = (uint32_t)(y * nx + xj);
+  auto xin = [&](int m) { return EX || xj + m * TT < nx; };
 
   T gphase[RO];
   cx<T> modr[RO];
@@ -1400,7 +1438,7 @@ __global__ void __launch_bounds__(G * (L / R))
   for (int m = 0; m < RO; ++m) {
     gphase[m] = T(0);
     modr[m] = {T(1), T(0)};
-    const int x = j + m * TT;
+    const int x = xj + m * TT;
     if (rowok && xin(m)) {
       if (fl & (EL_PHASE | EL_COMPLEX | EL_LENS)) modr[m] = scalar_modulation(a.el, ny, nx, y, x);
       __builtin_amdgcn_sched_barrier(0);
@@ -1450,10 +1488,13 @@ __global__ void __launch_bounds__(G * (L / R))
       uin[m] = {T(0), T(0)};
       if (want_param && rowok && xin(m)) uin[m] = buf_ld<T>(in_r, pix0 * CB, (uint32_t)(m * TT) * CB);
     }
-    fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
+    if constexpr (SPLIT)
+      split_dif<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
+    else
+      fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      const int x = j + m * TT;
+      const int x = xj + m * TT;
       if (m < RO && rowok && xin(m)) {
         v[m] = cscale(v[m], a.scale);  // g_mod
         const cx<T> mod = modr[m];
@@ -1474,7 +1515,10 @@ __global__ void __launch_bounds__(G * (L / R))
     // than keeping the inverse transform's (same addresses) live
     int jw = jv;
     asm volatile("" : "+v"(jw));
-    fft_wg<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
+    if constexpr (SPLIT)
+      split_dit<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
+    else
+      fft_wg<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
     if (rowok) {
       const rsrc_t sr = buf_rsrc(a.scratch + (int64_t)f * a.s_stride, s_bytes);
 #pragma unroll
@@ -1484,7 +1528,7 @@ __global__ void __launch_bounds__(G * (L / R))
   if (rowok && (fl & EL_PHASE) && a.grad_phase && a.saved_in) {
 #pragma unroll
     for (int m = 0; m < RO; ++m) {
-      const int x = j + m * TT;
+      const int x = xj + m * TT;
       if (xin(m)) {
         if (a.gphase_part)
           a.gphase_part[((int64_t)blockIdx.y * ny + y) * nx + x] = gphase[m];
