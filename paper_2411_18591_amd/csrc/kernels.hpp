@@ -327,6 +327,13 @@ __device__ __forceinline__ constexpr int lds_pos(int pos) {
   else
     return pos + (pos >> 4);
 }
+// STRIDE = -1: a single transform (stride 1) with the column-tile padding,
+// which the split row transforms use (their exchange patterns are
+// conflict-free or nearly so under it, not under the row padding).
+template <int STRIDE>
+__device__ __forceinline__ constexpr int lds_mul() {
+  return STRIDE < 0 ? 1 : STRIDE;
+}
 template <int STRIDE>
 constexpr int lds_len(int L) {  // elements (per column) of a padded exchange buffer
   return STRIDE == 1 ? L + 2 * (L >> 5) + (L >> 7) : L + (L >> 4);
@@ -371,14 +378,14 @@ __device__ __forceinline__ void fft_wg(cx<T>* v, int j, cx<T>* lds, const cx<T>*
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
         const int p0 = stockham_out_pos<L, R, RP, NS>(j, t, 0);
-        const int b0 = lds_pos<STRIDE>(p0) * STRIDE;
+        const int b0 = lds_pos<STRIDE>(p0) * lds_mul<STRIDE>();
 #pragma unroll
-        for (int i = 0; i < RP; ++i) lds[b0 + lds_pos<STRIDE>(i * NS) * STRIDE] = v[t + i * NB];
+        for (int i = 0; i < RP; ++i) lds[b0 + lds_pos<STRIDE>(i * NS) * lds_mul<STRIDE>()] = v[t + i * NB];
       }
       sync();
-      const int r0 = lds_pos<STRIDE>(j) * STRIDE;
+      const int r0 = lds_pos<STRIDE>(j) * lds_mul<STRIDE>();
 #pragma unroll
-      for (int m = 0; m < R; ++m) v[m] = lds[r0 + lds_pos<STRIDE>(m * TT) * STRIDE];
+      for (int m = 0; m < R; ++m) v[m] = lds[r0 + lds_pos<STRIDE>(m * TT) * lds_mul<STRIDE>()];
     }
   });
 }
@@ -412,7 +419,7 @@ struct Split {
 template <int L, int R, int TC>
 using ColSplit = Split<L, R, TC, (L / R / R) * TC>;
 template <int L, int R>
-using RowSplit = Split<L, R, 1, L / R / R>;
+using RowSplit = Split<L, R, -1, L / R / R>;
 
 // Radix-R pass over registers m (elements j + m M), then the twiddles
 // w_L^{D j g} on output g.
@@ -439,16 +446,16 @@ __device__ __forceinline__ void split_dif(cx<T>* v, int j, cx<T>* lds, const cx<
   using SP = Split<L, R, STRIDE, 1>;
   constexpr int M = SP::M, TS = SP::TS;
   split_outer<T, L, R, D, HALF_IN>(v, j, tw);
-  const int wb = lds_pos<STRIDE>(j) * STRIDE;
+  const int wb = lds_pos<STRIDE>(j) * lds_mul<STRIDE>();
   __syncthreads();  // earlier readers of the buffer are done
 #pragma unroll
-  for (int g = 0; g < R; ++g) lds[wb + lds_pos<STRIDE>(g * M) * STRIDE] = v[g];
+  for (int g = 0; g < R; ++g) lds[wb + lds_pos<STRIDE>(g * M) * lds_mul<STRIDE>()] = v[g];
   __syncthreads();
   const int g = j / TS, s = j % TS;
-  cx<T>* sub = lds + lds_pos<STRIDE>(g * M) * STRIDE;
-  const int rb = lds_pos<STRIDE>(s) * STRIDE;
+  cx<T>* sub = lds + lds_pos<STRIDE>(g * M) * lds_mul<STRIDE>();
+  const int rb = lds_pos<STRIDE>(s) * lds_mul<STRIDE>();
 #pragma unroll
-  for (int m = 0; m < R; ++m) v[m] = sub[rb + lds_pos<STRIDE>(m * TS) * STRIDE];
+  for (int m = 0; m < R; ++m) v[m] = sub[rb + lds_pos<STRIDE>(m * TS) * lds_mul<STRIDE>()];
   // the sub-transform's twiddles: the length-M table (packed before L's)
   fft_wg<T, M, R, D, false, STRIDE, true>(v, s, sub, tw - (L - M));
 }
@@ -461,17 +468,17 @@ __device__ __forceinline__ void split_dit(cx<T>* v, int j, cx<T>* lds, const cx<
   using SP = Split<L, R, STRIDE, 1>;
   constexpr int M = SP::M, TS = SP::TS;
   const int g = j / TS, s = j % TS;
-  cx<T>* sub = lds + lds_pos<STRIDE>(g * M) * STRIDE;
+  cx<T>* sub = lds + lds_pos<STRIDE>(g * M) * lds_mul<STRIDE>();
   wave_sync();
   fft_wg<T, M, R, D, HALF_IN, STRIDE, true>(v, s, sub, tw - (L - M));
   wave_sync();
-  const int rb = lds_pos<STRIDE>(s) * STRIDE;
+  const int rb = lds_pos<STRIDE>(s) * lds_mul<STRIDE>();
 #pragma unroll
-  for (int m = 0; m < R; ++m) sub[rb + lds_pos<STRIDE>(m * TS) * STRIDE] = v[m];
+  for (int m = 0; m < R; ++m) sub[rb + lds_pos<STRIDE>(m * TS) * lds_mul<STRIDE>()] = v[m];
   __syncthreads();
-  const int wb = lds_pos<STRIDE>(j) * STRIDE;
+  const int wb = lds_pos<STRIDE>(j) * lds_mul<STRIDE>();
 #pragma unroll
-  for (int q = 0; q < R; ++q) v[q] = lds[wb + lds_pos<STRIDE>(q * M) * STRIDE];
+  for (int q = 0; q < R; ++q) v[q] = lds[wb + lds_pos<STRIDE>(q * M) * lds_mul<STRIDE>()];
   // w_L^{D j g} on input g, then the radix-R pass over g
   const rsrc_t twr = buf_rsrc(tw, (uint32_t)(L * sizeof(cx<T>)));
 #pragma unroll
@@ -1344,7 +1351,7 @@ __global__ void __launch_bounds__(G * (L / R))
       load_row(f, v);
     }
     if constexpr (SPLIT)
-      split_dif<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
+      split_dif<T, L, R, +1, false, -1>(v, jv, lds + g * lds_len<1>(L), a.tw);
     else
       fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
     const rsrc_t out_r = buf_rsrc(a.out + (int64_t)f * a.out_stride, o_bytes);
@@ -1363,7 +1370,7 @@ __global__ void __launch_bounds__(G * (L / R))
     int jw = jv;
     asm volatile("" : "+v"(jw));
     if constexpr (SPLIT)
-      split_dit<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
+      split_dit<T, L, R, -1, HALF, -1>(v, jw, lds + g * lds_len<1>(L), a.tw);
     else
       fft_wg<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
     if (rowok) {
@@ -1489,7 +1496,7 @@ __global__ void __launch_bounds__(G * (L / R))
       if (want_param && rowok && xin(m)) uin[m] = buf_ld<T>(in_r, pix0 * CB, (uint32_t)(m * TT) * CB);
     }
     if constexpr (SPLIT)
-      split_dif<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
+      split_dif<T, L, R, +1, false, -1>(v, jv, lds + g * lds_len<1>(L), a.tw);
     else
       fft_wg<T, L, R, +1, false, 1>(v, jv, lds + g * lds_len<1>(L), a.tw);
 #pragma unroll
@@ -1516,7 +1523,7 @@ __global__ void __launch_bounds__(G * (L / R))
     int jw = jv;
     asm volatile("" : "+v"(jw));
     if constexpr (SPLIT)
-      split_dit<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
+      split_dit<T, L, R, -1, HALF, -1>(v, jw, lds + g * lds_len<1>(L), a.tw);
     else
       fft_wg<T, L, R, -1, HALF, 1>(v, jw, lds + g * lds_len<1>(L), a.tw);
     if (rowok) {
