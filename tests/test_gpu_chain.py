@@ -6,8 +6,10 @@ a time, and the FP64 oracle's stack.
 
 Bars: complex64 relative L2 <= 2e-5 against the oracle (fields), <= 2e-4
 (mask gradients); fused against one-by-one <= 1e-6 (complex64) / 1e-13
-(complex128): the same arithmetic in the same order, up to the compiler's
-choice of fused multiply-adds in the fused kernels."""
+(complex128): for complex128 the same arithmetic in the same order, up to
+the compiler's choice of fused multiply-adds in the fused kernels; for
+complex64 the fused boundaries take the split transforms, another FP32
+factorisation of the same propagation (larger grids: test_gpu_split.py)."""
 import numpy as np
 import pytest
 
