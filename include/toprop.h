@@ -323,7 +323,7 @@ typedef struct to_plan {
  * `result` (may be NULL) receives the chosen plan.
  * Precedence when a job runs: TOPROP_COL_VARIANT / TOPROP_CHUNK_MB /
  * TOPROP_ROW_FPB (tuning overrides) > plan table > built-in defaults (variant 1; variant 0 for
- * complex64 columns of 4096 points, variant 4 for those of 8192; 128 MiB).                     */
+ * complex64 columns of 4096 points and more; 128 MiB).                                         */
 to_status to_autotune(const to_job* job, to_dtype dtype, void* stream, to_plan* result);
 
 /* Plan table access (host only, no device work).  to_plan_get sets *found

@@ -313,9 +313,10 @@ struct Schedule {
 // take variant 0 (one 1024-thread workgroup per CU holding 4 or 2 columns,
 // twice the columns per cache-line segment of variant 1; measured 95 against
 // 107 us at 4096 points and 540 against 675 us at 8192 on one 2048^2 and
-// one 4096^2 field), everything else variant 1.
+// one 4096^2 field; with the split transforms also ahead of variant 4 at
+// 8192: 1569 against 1722 us per launch in the uneven batch), everything
+// else variant 1.
 int default_col_variant(int dtype, int ly) {
-  if (dtype == 0 && ly >= 8192) return 4;
   return (dtype == 0 && ly >= 4096) ? 0 : kDefaultColVariant;
 }
 
