@@ -298,9 +298,11 @@ to_status to_propagate_backward_plain(const to_job* jobs, const to_grad* grads, 
                                       to_dtype dtype, void* stream);
 
 /* Launch schedule of one padded grid and dtype: the column-pass
- * configuration (0 .. 4: LDS budget, points per thread and prefetch of the
- * column FFT) and the budget of padded intermediate per chunk of fields
- * [MiB].                                                                   */
+ * configuration (0 .. 4: LDS budget, points per thread, prefetch and, for
+ * complex64, the factorisation of the column FFT: 0, 1 and 4 take the split
+ * transform (a radix pass across the column, sub-transforms inside one
+ * wavefront), 2 and 3 the Stockham passes) and the budget of padded
+ * intermediate per chunk of fields [MiB].                                  */
 typedef struct to_plan {
   int32_t col_variant;
   int32_t chunk_mb;
