@@ -92,15 +92,26 @@ KERNEL_SOURCES = ("fft.hpp", "kernels.hpp", "launch.hpp", "launch_impl.hpp", "in
                   "queue.hpp", "queue_impl.hpp", "queue_f32.hip", "queue_f64.hip")
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank lines, each line stripped (the
+    kernel files hold no string literal with a comment marker)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*", "", ln).strip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_source_digest() -> str:
-    """SHA-256 over the propagation kernels' sources (name + bytes)."""
+    """SHA-256 over the propagation kernels' code (file names + the sources
+    without comments), so that records taken on the kernels stay valid
+    across comment-only edits and lapse on any change to the code."""
     import hashlib
     d = os.path.join(ROOT, "paper_2411_18591_amd", "csrc")
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(f.encode())
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(d, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()
 
 

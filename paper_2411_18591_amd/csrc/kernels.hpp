@@ -398,7 +398,7 @@ __device__ __forceinline__ void fft_wg(cx<T>* v, int j, cx<T>* lds, const cx<T>*
 // wavefront, its exchanges need no workgroup barrier.  Two orders:
 //  natural: thread j holds element j + m M in register m (as fft_wg);
 //  split:   thread j = g TS + s holds element R (s + m TS) + g, i.e.
-//           split_base(j) + m M.
+//           base(j) + m M.
 // split_dif takes natural order to split order (the radix-R pass first);
 // split_dit takes split order to natural order (the sub-transforms first).
 // A forward split_dif + inverse split_dit pair (or inverse + forward) costs
@@ -410,8 +410,9 @@ struct Split {
   static constexpr int TS = M / R;
   // WAVE_THREADS: threads of one sub-transform (with all STRIDE columns of a
   // column tile) that must fit one wavefront; lds_pos splits over g M + p
-  // when M is a multiple of the padding period (16 for column tiles, 128
-  // for rows)
+  // when M is a multiple of the padding period (16 for the column-tile
+  // padding, which the split rows use too (STRIDE = -1); 128 for the row
+  // padding)
   static constexpr bool ok = L >= R * R && R >= 4 && WAVE_THREADS <= 64 && (64 % WAVE_THREADS) == 0 &&
                              M % (STRIDE == 1 ? 128 : 16) == 0;
   __device__ __forceinline__ static int base(int j) { return R * (j % TS) + j / TS; }
